@@ -1,0 +1,685 @@
+/*
+ * rsz_oracle.c -- plain, slow, single-threaded CPU oracle for the ROIBIN-SZ
+ * per-frame compression path (arXiv 2206.11297).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path (the
+ * HIP library) never calls it, links it or shares code, headers or tables with
+ * it.
+ *
+ * What the paper fixes and what is a stated reading:
+ *   - ROI windows around each Bragg peak are kept without error, with a
+ *     constant fill outside the panel (Sec. IV, Sec. IV-A).
+ *   - The background is binned as a b x b mean (Sec. VI) and compressed with an
+ *     absolute error bound that holds on the *binned* values (Sec. V-C, "Our
+ *     Approach", and the footnote of Sec. VI).
+ *   - The SZ stage is a black box in the paper (Sec. V-C names Lorenzo +
+ *     regression + linear quantization).  Here it is the dual-quantisation
+ *     recipe: prequantise to integers at step 2*eb, 2D Lorenzo on the integer
+ *     field, outliers for residuals outside the radius, Huffman over 1024
+ *     symbols.  Every constant the paper leaves open is a reading listed in the
+ *     design notes (radius 512, chunk 4096, tie-breaks, container layout).
+ *   - Compression ratio is relative to raw uint16 detector bytes (Sec. IV).
+ *
+ * Arithmetic: fp64 sums in raster order, a correctly rounded divide and
+ * rint() (round half to even).  Build with -ffp-contract=off and without
+ * fast-math so that nothing is contracted or reordered.
+ *
+ * Parity pins (tests): brute-force masks, numpy sums, the closed-form
+ * reconstruction, prefix-sum inverse of the Lorenzo step, an independent heap
+ * Huffman cost, Kraft sums, brute-force optimality on tiny alphabets and a
+ * hand-derived stream fixture.  Nothing here is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define RO_OK 0
+#define RO_ERR_ARG (-1)
+#define RO_ERR_PEAK (-2)
+#define RO_ERR_RANGE (-3)
+#define RO_ERR_CAPACITY (-4)
+#define RO_ERR_CORRUPT (-5)
+
+#define RO_RADIUS 512
+#define RO_NSYM 1024
+#define RO_MAXLEN 32
+#define RO_CHUNK 4096
+#define RO_QMAX 268435455.0 /* 2^28 - 1 */
+#define RO_HEADER 80
+
+typedef struct {
+  uint32_t panels, height, width; /* frame is panels x height x width f32 */
+  uint32_t window;                /* ROI window edge w                     */
+  uint32_t bin;                   /* bin factor b                          */
+  uint32_t bin_mode;              /* 0 = background pixels only, 1 = all   */
+  double eb;                      /* absolute bound on binned values       */
+} ro_params;
+
+/* ------------------------------------------------------------------ sizes */
+
+static uint64_t ro_hb(const ro_params *p) { return (p->height + p->bin - 1) / p->bin; }
+static uint64_t ro_wb(const ro_params *p) { return (p->width + p->bin - 1) / p->bin; }
+static uint64_t ro_nbins(const ro_params *p) { return (uint64_t)p->panels * ro_hb(p) * ro_wb(p); }
+static uint64_t ro_align4(uint64_t x) { return (x + 3u) & ~(uint64_t)3u; }
+
+/* Argument validation.  Limits: each dimension 1..65535, window 1..1023,
+ * bin 1..8, bin_mode 0/1, eb finite and > 0, pixels < 2^31, bins < 2^27,
+ * npeaks * w * w <= 2^28 payload words. */
+int ro_check_params(const ro_params *p, uint32_t npeaks) {
+  if (!p) return RO_ERR_ARG;
+  if (p->panels < 1 || p->panels > 65535 || p->height < 1 || p->height > 65535 ||
+      p->width < 1 || p->width > 65535)
+    return RO_ERR_ARG;
+  if (p->window < 1 || p->window > 1023) return RO_ERR_ARG;
+  if (p->bin < 1 || p->bin > 8) return RO_ERR_ARG;
+  if (p->bin_mode > 1) return RO_ERR_ARG;
+  if (!(p->eb > 0.0) || !isfinite(p->eb)) return RO_ERR_ARG;
+  if ((uint64_t)p->panels * p->height * p->width >= (1ull << 31)) return RO_ERR_ARG;
+  if (ro_nbins(p) >= (1ull << 27)) return RO_ERR_ARG;
+  if ((uint64_t)npeaks * p->window * p->window > (1ull << 28)) return RO_ERR_ARG;
+  return RO_OK;
+}
+
+/* Every peak must name a pixel of the frame (panel, row, col). */
+int ro_check_peaks(const ro_params *p, const int32_t *peaks, uint32_t npeaks) {
+  for (uint32_t k = 0; k < npeaks; ++k) {
+    int32_t pa = peaks[3 * k], r = peaks[3 * k + 1], c = peaks[3 * k + 2];
+    if (pa < 0 || (uint32_t)pa >= p->panels || r < 0 || (uint32_t)r >= p->height || c < 0 ||
+        (uint32_t)c >= p->width)
+      return RO_ERR_PEAK;
+  }
+  return RO_OK;
+}
+
+/* ------------------------------------------------------- region of interest */
+
+/* ROI mask (Sec. IV: the stream is split into the regions around each peak and
+ * the background).  Window rows r-h .. r-h+w-1 and cols c-h .. c-h+w-1 with
+ * h = floor(w/2), clipped to the panel; the mask is the union over peaks.
+ * Bitmap: one u32 word per 32 columns of each (panel,row), LSB = lowest col. */
+void ro_mask(const ro_params *p, const int32_t *peaks, uint32_t npeaks, uint32_t *bitmap) {
+  const uint64_t wpr = (p->width + 31u) / 32u;
+  memset(bitmap, 0, sizeof(uint32_t) * (size_t)(p->panels * (uint64_t)p->height * wpr));
+  const int64_t h = p->window / 2;
+  for (uint32_t k = 0; k < npeaks; ++k) {
+    const int64_t pa = peaks[3 * k], r0 = peaks[3 * k + 1] - h, c0 = peaks[3 * k + 2] - h;
+    for (int64_t i = r0; i < r0 + (int64_t)p->window; ++i) {
+      if (i < 0 || i >= (int64_t)p->height) continue;
+      for (int64_t j = c0; j < c0 + (int64_t)p->window; ++j) {
+        if (j < 0 || j >= (int64_t)p->width) continue;
+        bitmap[((uint64_t)pa * p->height + (uint64_t)i) * wpr + (uint64_t)j / 32u] |=
+            1u << (j % 32);
+      }
+    }
+  }
+}
+
+static int ro_mask_bit(const ro_params *p, const uint32_t *bitmap, uint64_t pa, uint64_t i,
+                       uint64_t j) {
+  const uint64_t wpr = (p->width + 31u) / 32u;
+  return (bitmap[(pa * p->height + i) * wpr + j / 32u] >> (j % 32u)) & 1u;
+}
+
+/* ROI payload (Sec. IV-A: npeaks x window buffer, constant fill outside the
+ * panel).  Entries are the raw 32-bit patterns of the frame, never touched as
+ * floats, so the window round-trips bit-exactly; the fill is 0x00000000. */
+void ro_roi(const ro_params *p, const float *frame, const int32_t *peaks, uint32_t npeaks,
+            uint32_t *payload) {
+  const int64_t h = p->window / 2, w = p->window;
+  for (uint32_t k = 0; k < npeaks; ++k) {
+    const int64_t pa = peaks[3 * k], r0 = peaks[3 * k + 1] - h, c0 = peaks[3 * k + 2] - h;
+    for (int64_t u = 0; u < w; ++u)
+      for (int64_t v = 0; v < w; ++v) {
+        const int64_t i = r0 + u, j = c0 + v;
+        uint32_t bits = 0u;
+        if (i >= 0 && i < (int64_t)p->height && j >= 0 && j < (int64_t)p->width)
+          memcpy(&bits, &frame[((uint64_t)pa * p->height + (uint64_t)i) * p->width + (uint64_t)j],
+                 4);
+        payload[((uint64_t)k * w + (uint64_t)u) * w + (uint64_t)v] = bits;
+      }
+  }
+}
+
+/* ---------------------------------------------------------------- binning */
+
+/* b x b binning (Sec. VI: a bin combines b*b values into their mean).  Bin
+ * (pa,I,J) covers rows [I*b, min(I*b+b,H)) and cols [J*b, min(J*b+b,W)).  The
+ * included pixels are all of them (bin_mode 1) or those outside the ROI mask
+ * (bin_mode 0).  S is the fp64 sum in raster order starting from +0.0, n the
+ * number of included pixels; the mean is S/n. */
+void ro_bin(const ro_params *p, const float *frame, const uint32_t *bitmap, double *S,
+            uint32_t *n) {
+  const uint64_t Hb = ro_hb(p), Wb = ro_wb(p), b = p->bin;
+  for (uint64_t pa = 0; pa < p->panels; ++pa)
+    for (uint64_t I = 0; I < Hb; ++I)
+      for (uint64_t J = 0; J < Wb; ++J) {
+        double s = 0.0;
+        uint32_t cnt = 0;
+        for (uint64_t i = I * b; i < I * b + b && i < p->height; ++i)
+          for (uint64_t j = J * b; j < J * b + b && j < p->width; ++j) {
+            if (p->bin_mode == 0 && ro_mask_bit(p, bitmap, pa, i, j)) continue;
+            s = s + (double)frame[(pa * p->height + i) * p->width + j];
+            cnt++;
+          }
+        const uint64_t g = (pa * Hb + I) * Wb + J;
+        S[g] = s;
+        n[g] = cnt;
+      }
+}
+
+/* ------------------------------------------------------- error-bounded part */
+
+/* Prequantisation at step 2*eb so that |q*2eb - S/n| <= eb (the absolute bound
+ * on binned values, Sec. V-C "Our Approach").  q = rint(S / (n*2eb)), q = 0 for
+ * an empty bin.  |q| must stay below 2^28 (this also rejects NaN/Inf). */
+int ro_prequant(const ro_params *p, const double *S, const uint32_t *n, int32_t *q) {
+  const uint64_t nb = ro_nbins(p);
+  const double step = 2.0 * p->eb;
+  int status = RO_OK;
+  for (uint64_t g = 0; g < nb; ++g) {
+    if (n[g] == 0) {
+      q[g] = 0;
+      continue;
+    }
+    const double den = (double)n[g] * step;
+    const double t = rint(S[g] / den);
+    if (!(fabs(t) <= RO_QMAX)) {
+      status = RO_ERR_RANGE;
+      q[g] = 0;
+      continue;
+    }
+    q[g] = (int32_t)t;
+  }
+  return status;
+}
+
+/* 2D Lorenzo predictor over each panel of the integer field (the SZ predictor
+ * of Sec. V-C, dimension 2 of Sec. VI): r = q - q_up - q_left + q_upleft with
+ * zeros outside the panel. */
+void ro_lorenzo(const ro_params *p, const int32_t *q, int32_t *r) {
+  const uint64_t Hb = ro_hb(p), Wb = ro_wb(p);
+  for (uint64_t pa = 0; pa < p->panels; ++pa)
+    for (uint64_t I = 0; I < Hb; ++I)
+      for (uint64_t J = 0; J < Wb; ++J) {
+        const uint64_t g = (pa * Hb + I) * Wb + J;
+        const int64_t up = I > 0 ? q[g - Wb] : 0;
+        const int64_t left = J > 0 ? q[g - 1] : 0;
+        const int64_t ul = (I > 0 && J > 0) ? q[g - Wb - 1] : 0;
+        r[g] = (int32_t)((int64_t)q[g] - up - left + ul);
+      }
+}
+
+/* Quantisation codes: code = r + 512 when |r| < 512, else code 0 and the pair
+ * (bin index, r) goes to the outlier list in ascending bin order. */
+uint32_t ro_codes(uint64_t nbins, const int32_t *r, uint16_t *codes, uint32_t *out_idx,
+                  int32_t *out_res) {
+  uint32_t n_out = 0;
+  for (uint64_t g = 0; g < nbins; ++g) {
+    if (r[g] > -RO_RADIUS && r[g] < RO_RADIUS) {
+      codes[g] = (uint16_t)(r[g] + RO_RADIUS);
+    } else {
+      codes[g] = 0;
+      if (out_idx) out_idx[n_out] = (uint32_t)g;
+      if (out_res) out_res[n_out] = r[g];
+      n_out++;
+    }
+  }
+  return n_out;
+}
+
+void ro_histogram(uint64_t nbins, const uint16_t *codes, uint32_t *hist) {
+  memset(hist, 0, sizeof(uint32_t) * RO_NSYM);
+  for (uint64_t g = 0; g < nbins; ++g) hist[codes[g]]++;
+}
+
+/* ------------------------------------------------------------------ Huffman */
+
+typedef struct {
+  uint64_t w;
+  uint32_t sym;
+} ro_leaf;
+
+static int ro_leaf_cmp(const void *a, const void *b) {
+  const ro_leaf *x = (const ro_leaf *)a, *y = (const ro_leaf *)b;
+  if (x->w != y->w) return x->w < y->w ? -1 : 1;
+  return x->sym < y->sym ? -1 : (x->sym > y->sym ? 1 : 0);
+}
+
+/* One Huffman build with the two-queue method: leaves sorted by (weight,
+ * symbol); internal nodes in a FIFO; each pick takes the leaf when the leaf
+ * weight is <= the front internal weight.  Returns the longest length. */
+static int ro_huffman_once(const uint64_t *weight, uint8_t *len) {
+  ro_leaf leaf[RO_NSYM];
+  int nl = 0;
+  memset(len, 0, RO_NSYM);
+  for (int s = 0; s < RO_NSYM; ++s)
+    if (weight[s] > 0) {
+      leaf[nl].w = weight[s];
+      leaf[nl].sym = (uint32_t)s;
+      nl++;
+    }
+  if (nl == 0) return 0;
+  if (nl == 1) {
+    len[leaf[0].sym] = 1;
+    return 1;
+  }
+  qsort(leaf, (size_t)nl, sizeof(ro_leaf), ro_leaf_cmp);
+  /* node ids: 0..nl-1 leaves (sorted order), nl..2nl-2 internal in creation order */
+  uint64_t nw[2 * RO_NSYM];
+  int parent[2 * RO_NSYM];
+  for (int i = 0; i < nl; ++i) nw[i] = leaf[i].w;
+  int lf = 0, nf = nl, nend = nl; /* leaf front, internal front, next internal id */
+  for (int m = 0; m < nl - 1; ++m) {
+    int pick[2];
+    for (int t = 0; t < 2; ++t) {
+      if (nf == nend || (lf < nl && nw[lf] <= nw[nf]))
+        pick[t] = lf++;
+      else
+        pick[t] = nf++;
+    }
+    nw[nend] = nw[pick[0]] + nw[pick[1]];
+    parent[pick[0]] = nend;
+    parent[pick[1]] = nend;
+    nend++;
+  }
+  int depth[2 * RO_NSYM];
+  const int root = nend - 1;
+  depth[root] = 0;
+  for (int v = root - 1; v >= 0; --v) depth[v] = depth[parent[v]] + 1;
+  int maxlen = 0;
+  for (int i = 0; i < nl; ++i) {
+    len[leaf[i].sym] = (uint8_t)(depth[i] > 255 ? 255 : depth[i]);
+    if (depth[i] > maxlen) maxlen = depth[i];
+  }
+  return maxlen;
+}
+
+/* Huffman code lengths for the 1024-symbol histogram.  A single used symbol
+ * gets length 1.  If a length exceeds 32 the weights are halved (kept >= 1)
+ * and the build repeats. */
+void ro_huffman_lengths(const uint32_t *hist, uint8_t *len) {
+  uint64_t w[RO_NSYM];
+  for (int s = 0; s < RO_NSYM; ++s) w[s] = hist[s];
+  for (;;) {
+    if (ro_huffman_once(w, len) <= RO_MAXLEN) return;
+    for (int s = 0; s < RO_NSYM; ++s)
+      if (w[s] > 0) w[s] = (w[s] >> 1) > 0 ? (w[s] >> 1) : 1;
+  }
+}
+
+/* Canonical codes: symbols ordered by (length, symbol); the first gets 0, each
+ * next one (previous + 1) shifted left by the length increase (the canonical
+ * assignment of RFC 1951 sec. 3.2.2). */
+void ro_canonical(const uint8_t *len, uint32_t *code) {
+  memset(code, 0, sizeof(uint32_t) * RO_NSYM);
+  uint64_t c = 0;
+  int prev = 0, first = 1;
+  for (int L = 1; L <= RO_MAXLEN; ++L)
+    for (int s = 0; s < RO_NSYM; ++s) {
+      if (len[s] != L) continue;
+      if (first) {
+        c = 0;
+        first = 0;
+      } else {
+        c = (c + 1) << (L - prev);
+      }
+      code[s] = (uint32_t)c;
+      prev = L;
+    }
+}
+
+/* Bitstream: codewords of code[0..nbins) concatenated MSB-first; stream bit k
+ * is bit 31-(k%32) of word k/32; trailing bits of the last word are zero.
+ * chunk_off[c] = bit offset of symbol c*4096.  Returns the total bit count T.
+ * words may be NULL to only count. */
+uint64_t ro_bitstream(uint64_t nbins, const uint16_t *codes, const uint8_t *len,
+                      const uint32_t *cw, uint32_t *words, uint32_t *chunk_off) {
+  uint64_t T = 0;
+  for (uint64_t g = 0; g < nbins; ++g) {
+    if (g % RO_CHUNK == 0 && chunk_off) chunk_off[g / RO_CHUNK] = (uint32_t)T;
+    const unsigned L = len[codes[g]];
+    const uint32_t c = cw[codes[g]];
+    if (words)
+      for (unsigned t = 0; t < L; ++t) {
+        const uint64_t k = T + t;
+        const uint32_t bit = (c >> (L - 1 - t)) & 1u;
+        if (k % 32 == 0) words[k / 32] = 0;
+        words[k / 32] |= bit << (31 - k % 32);
+      }
+    T += L;
+  }
+  return T;
+}
+
+/* ---------------------------------------------------------------- container */
+
+typedef struct {
+  uint64_t peaks, roi, lens, oidx, ores, chunks, bits, total;
+} ro_layout;
+
+static ro_layout ro_sections(const ro_params *p, uint32_t npeaks, uint64_t n_out,
+                             uint64_t n_chunks, uint64_t T) {
+  ro_layout L;
+  L.peaks = RO_HEADER;
+  L.roi = L.peaks + ro_align4(6ull * npeaks);
+  L.lens = L.roi + 4ull * npeaks * p->window * p->window;
+  L.oidx = L.lens + RO_NSYM;
+  L.ores = L.oidx + 4ull * n_out;
+  L.chunks = L.ores + 4ull * n_out;
+  L.bits = L.chunks + 4ull * n_chunks;
+  L.total = L.bits + 4ull * ((T + 31) / 32);
+  return L;
+}
+
+static void put16(uint8_t *b, uint64_t o, uint16_t v) { memcpy(b + o, &v, 2); }
+static void put32(uint8_t *b, uint64_t o, uint32_t v) { memcpy(b + o, &v, 4); }
+static void put64(uint8_t *b, uint64_t o, uint64_t v) { memcpy(b + o, &v, 8); }
+static uint16_t get16(const uint8_t *b, uint64_t o) { uint16_t v; memcpy(&v, b + o, 2); return v; }
+static uint32_t get32(const uint8_t *b, uint64_t o) { uint32_t v; memcpy(&v, b + o, 4); return v; }
+static uint64_t get64(const uint8_t *b, uint64_t o) { uint64_t v; memcpy(&v, b + o, 8); return v; }
+
+/* Worst-case stream size: every bin an outlier and every codeword 32 bits. */
+int ro_max_bytes(const ro_params *p, uint32_t npeaks, uint64_t *bytes) {
+  int st = ro_check_params(p, npeaks);
+  if (st) return st;
+  const uint64_t nb = ro_nbins(p), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
+  *bytes = ro_sections(p, npeaks, nb, nc, 32ull * nb).total;
+  return RO_OK;
+}
+
+/* Everything the compressor computes, for parity tests.  Any pointer may be
+ * NULL.  Returns the status of compression (OK / ARG / PEAK / RANGE). */
+int ro_intermediates(const ro_params *p, const float *frame, const int32_t *peaks,
+                     uint32_t npeaks, uint32_t *mask, uint32_t *payload, double *S, uint32_t *n,
+                     int32_t *q, int32_t *r, uint16_t *codes, uint32_t *out_idx, int32_t *out_res,
+                     uint32_t *n_out_p, uint32_t *hist, uint8_t *lens, uint32_t *cw,
+                     uint32_t *chunk_off, uint64_t *T_p) {
+  int st = ro_check_params(p, npeaks);
+  if (st) return st;
+  st = ro_check_peaks(p, peaks, npeaks);
+  if (st) return st;
+  const uint64_t nb = ro_nbins(p), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
+  const uint64_t wpr = (p->width + 31u) / 32u;
+  uint32_t *m = (uint32_t *)malloc(4 * (size_t)(p->panels * (uint64_t)p->height * wpr));
+  double *s = (double *)malloc(8 * (size_t)nb);
+  uint32_t *cnt = (uint32_t *)malloc(4 * (size_t)nb);
+  int32_t *qq = (int32_t *)malloc(4 * (size_t)nb);
+  int32_t *rr = (int32_t *)malloc(4 * (size_t)nb);
+  uint16_t *cd = (uint16_t *)malloc(2 * (size_t)nb);
+  ro_mask(p, peaks, npeaks, m);
+  if (payload) ro_roi(p, frame, peaks, npeaks, payload);
+  ro_bin(p, frame, m, s, cnt);
+  st = ro_prequant(p, s, cnt, qq);
+  ro_lorenzo(p, qq, rr);
+  const uint32_t n_out = ro_codes(nb, rr, cd, out_idx, out_res);
+  uint32_t h[RO_NSYM];
+  uint8_t l[RO_NSYM];
+  uint32_t c[RO_NSYM];
+  ro_histogram(nb, cd, h);
+  ro_huffman_lengths(h, l);
+  ro_canonical(l, c);
+  uint32_t *co = (uint32_t *)malloc(4 * (size_t)nc);
+  const uint64_t T = ro_bitstream(nb, cd, l, c, NULL, co);
+  if (mask) memcpy(mask, m, 4 * (size_t)(p->panels * (uint64_t)p->height * wpr));
+  if (S) memcpy(S, s, 8 * (size_t)nb);
+  if (n) memcpy(n, cnt, 4 * (size_t)nb);
+  if (q) memcpy(q, qq, 4 * (size_t)nb);
+  if (r) memcpy(r, rr, 4 * (size_t)nb);
+  if (codes) memcpy(codes, cd, 2 * (size_t)nb);
+  if (n_out_p) *n_out_p = n_out;
+  if (hist) memcpy(hist, h, sizeof h);
+  if (lens) memcpy(lens, l, sizeof l);
+  if (cw) memcpy(cw, c, sizeof c);
+  if (chunk_off) memcpy(chunk_off, co, 4 * (size_t)nc);
+  if (T_p) *T_p = T;
+  free(m); free(s); free(cnt); free(qq); free(rr); free(cd); free(co);
+  return st;
+}
+
+/* Compress one frame into the self-contained stream (header, peaks, ROI
+ * payload, code lengths, outliers, chunk offsets, bitstream).  On
+ * RO_ERR_CAPACITY *out_bytes holds the required size. */
+int ro_compress(const ro_params *p, const float *frame, const int32_t *peaks, uint32_t npeaks,
+                uint8_t *out, uint64_t out_cap, uint64_t *out_bytes) {
+  int st = ro_check_params(p, npeaks);
+  if (st) return st;
+  st = ro_check_peaks(p, peaks, npeaks);
+  if (st) return st;
+  const uint64_t nb = ro_nbins(p), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
+  const uint64_t wpr = (p->width + 31u) / 32u;
+  uint32_t *m = (uint32_t *)malloc(4 * (size_t)(p->panels * (uint64_t)p->height * wpr));
+  double *s = (double *)malloc(8 * (size_t)nb);
+  uint32_t *cnt = (uint32_t *)malloc(4 * (size_t)nb);
+  int32_t *qq = (int32_t *)malloc(4 * (size_t)nb);
+  int32_t *rr = (int32_t *)malloc(4 * (size_t)nb);
+  uint16_t *cd = (uint16_t *)malloc(2 * (size_t)nb);
+  uint32_t *oi = (uint32_t *)malloc(4 * (size_t)nb);
+  int32_t *orr = (int32_t *)malloc(4 * (size_t)nb);
+  uint32_t *co = (uint32_t *)malloc(4 * (size_t)nc);
+  ro_mask(p, peaks, npeaks, m);
+  ro_bin(p, frame, m, s, cnt);
+  st = ro_prequant(p, s, cnt, qq);
+  if (st == RO_OK) {
+    ro_lorenzo(p, qq, rr);
+    const uint32_t n_out = ro_codes(nb, rr, cd, oi, orr);
+    uint32_t h[RO_NSYM];
+    uint8_t l[RO_NSYM];
+    uint32_t c[RO_NSYM];
+    ro_histogram(nb, cd, h);
+    ro_huffman_lengths(h, l);
+    ro_canonical(l, c);
+    const uint64_t T = ro_bitstream(nb, cd, l, c, NULL, co);
+    const ro_layout L = ro_sections(p, npeaks, n_out, nc, T);
+    *out_bytes = L.total;
+    if (L.total > out_cap) {
+      st = RO_ERR_CAPACITY;
+    } else {
+      memset(out, 0, (size_t)L.total);
+      memcpy(out, "RSZ1", 4);
+      put16(out, 4, 1);
+      put16(out, 6, (uint16_t)(p->bin_mode & 1u));
+      put32(out, 8, p->panels);
+      put32(out, 12, p->height);
+      put32(out, 16, p->width);
+      put32(out, 20, p->window);
+      put32(out, 24, p->bin);
+      put32(out, 28, RO_RADIUS);
+      memcpy(out + 32, &p->eb, 8);
+      put32(out, 40, npeaks);
+      put32(out, 44, n_out);
+      put32(out, 48, RO_CHUNK);
+      put32(out, 52, (uint32_t)nc);
+      put64(out, 56, T);
+      put64(out, 64, L.total);
+      put64(out, 72, 0);
+      for (uint32_t k = 0; k < npeaks; ++k)
+        for (int t = 0; t < 3; ++t) put16(out, L.peaks + 6ull * k + 2 * t, (uint16_t)peaks[3 * k + t]);
+      ro_roi(p, frame, peaks, npeaks, (uint32_t *)(out + L.roi));
+      memcpy(out + L.lens, l, RO_NSYM);
+      for (uint32_t k = 0; k < n_out; ++k) {
+        put32(out, L.oidx + 4ull * k, oi[k]);
+        put32(out, L.ores + 4ull * k, (uint32_t)orr[k]);
+      }
+      for (uint64_t k = 0; k < nc; ++k) put32(out, L.chunks + 4 * k, co[k]);
+      ro_bitstream(nb, cd, l, c, (uint32_t *)(out + L.bits), NULL);
+    }
+  }
+  free(m); free(s); free(cnt); free(qq); free(rr); free(cd); free(oi); free(orr); free(co);
+  return st;
+}
+
+/* ---------------------------------------------------------------- decoding */
+
+/* Parse the header of a stream and check it against the buffer size. */
+int ro_stream_info(const uint8_t *in, uint64_t in_bytes, ro_params *p, uint32_t *npeaks,
+                   uint64_t *stream_bytes) {
+  if (in_bytes < RO_HEADER || memcmp(in, "RSZ1", 4) != 0 || get16(in, 4) != 1)
+    return RO_ERR_CORRUPT;
+  ro_params q;
+  q.bin_mode = get16(in, 6);
+  q.panels = get32(in, 8);
+  q.height = get32(in, 12);
+  q.width = get32(in, 16);
+  q.window = get32(in, 20);
+  q.bin = get32(in, 24);
+  memcpy(&q.eb, in + 32, 8);
+  const uint32_t np = get32(in, 40);
+  if (ro_check_params(&q, np) != RO_OK) return RO_ERR_CORRUPT;
+  if (get32(in, 28) != RO_RADIUS || get32(in, 48) != RO_CHUNK || get64(in, 72) != 0)
+    return RO_ERR_CORRUPT;
+  const uint64_t nb = ro_nbins(&q), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
+  const uint64_t n_out = get32(in, 44), T = get64(in, 56), total = get64(in, 64);
+  if (get32(in, 52) != nc || n_out > nb || T > 32ull * nb) return RO_ERR_CORRUPT;
+  if (ro_sections(&q, np, n_out, nc, T).total != total || total > in_bytes) return RO_ERR_CORRUPT;
+  if (p) *p = q;
+  if (npeaks) *npeaks = np;
+  if (stream_bytes) *stream_bytes = total;
+  return RO_OK;
+}
+
+/* Decompress a stream into a panels x height x width float frame.
+ * Structural validation first (any failure -> RO_ERR_CORRUPT); then
+ * codes -> residuals -> q by 2D prefix sums -> bin value q*2eb replicated over
+ * the bin -> ROI windows restored bit-exactly from the payload.  Where windows
+ * overlap, the later peak in list order is written last. */
+int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t frame_elems) {
+  ro_params p;
+  uint32_t np;
+  uint64_t total;
+  int st = ro_stream_info(in, in_bytes, &p, &np, &total);
+  if (st) return st;
+  const uint64_t pix = (uint64_t)p.panels * p.height * p.width;
+  if (frame_elems < pix) return RO_ERR_ARG;
+  const uint64_t nb = ro_nbins(&p), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
+  const uint64_t n_out = get32(in, 44), T = get64(in, 56);
+  const ro_layout L = ro_sections(&p, np, n_out, nc, T);
+  /* peaks */
+  int32_t *pk = (int32_t *)malloc(12 * (size_t)(np ? np : 1));
+  for (uint32_t k = 0; k < np; ++k)
+    for (int t = 0; t < 3; ++t) pk[3 * k + t] = get16(in, L.peaks + 6ull * k + 2 * t);
+  if (ro_check_peaks(&p, pk, np) != RO_OK) {
+    free(pk);
+    return RO_ERR_CORRUPT;
+  }
+  /* code lengths: each <= 32 and a complete prefix code (Kraft sum 1), or one
+   * symbol of length 1 */
+  uint8_t len[RO_NSYM];
+  memcpy(len, in + L.lens, RO_NSYM);
+  uint64_t kraft = 0;
+  int used = 0;
+  for (int s = 0; s < RO_NSYM; ++s) {
+    if (len[s] > RO_MAXLEN) { free(pk); return RO_ERR_CORRUPT; }
+    if (len[s]) { kraft += 1ull << (RO_MAXLEN - len[s]); used++; }
+  }
+  if (!(kraft == (1ull << RO_MAXLEN) || (used == 1 && kraft == (1ull << (RO_MAXLEN - 1))))) {
+    free(pk);
+    return RO_ERR_CORRUPT;
+  }
+  /* canonical decoding tables: per length, first code, count and offset into
+   * the (length, symbol)-ordered symbol list */
+  uint32_t cw[RO_NSYM];
+  ro_canonical(len, cw);
+  uint64_t first[RO_MAXLEN + 2];
+  uint32_t count[RO_MAXLEN + 2], offs[RO_MAXLEN + 2], sorted[RO_NSYM];
+  uint32_t ns = 0;
+  for (int Lx = 1; Lx <= RO_MAXLEN; ++Lx) {
+    count[Lx] = 0;
+    offs[Lx] = ns;
+    first[Lx] = 0;
+    for (int s = 0; s < RO_NSYM; ++s)
+      if (len[s] == Lx) {
+        if (count[Lx] == 0) first[Lx] = cw[s];
+        sorted[ns++] = (uint32_t)s;
+        count[Lx]++;
+      }
+  }
+  /* decode every symbol sequentially, checking the chunk offsets */
+  int32_t *res = (int32_t *)malloc(4 * (size_t)nb);
+  uint16_t *cd = (uint16_t *)malloc(2 * (size_t)nb);
+  const uint8_t *bits = in + L.bits;
+  uint64_t pos = 0, prev_off = 0;
+  int bad = 0;
+  for (uint64_t g = 0; g < nb && !bad; ++g) {
+    if (g % RO_CHUNK == 0) {
+      const uint64_t off = get32(in, L.chunks + 4 * (g / RO_CHUNK));
+      if (off != pos || off < prev_off || off > T) { bad = 1; break; }
+      prev_off = off;
+    }
+    uint64_t c = 0;
+    int Lx = 0, found = -1;
+    while (Lx < RO_MAXLEN) {
+      if (pos >= T) { bad = 1; break; }
+      const uint32_t word = get32(bits, 4 * (pos / 32));
+      c = (c << 1) | ((word >> (31 - pos % 32)) & 1u);
+      pos++;
+      Lx++;
+      if (count[Lx] && c >= first[Lx] && c - first[Lx] < count[Lx]) {
+        found = (int)sorted[offs[Lx] + (uint32_t)(c - first[Lx])];
+        break;
+      }
+    }
+    if (found < 0) { bad = 1; break; }
+    cd[g] = (uint16_t)found;
+  }
+  if (!bad && pos != T) bad = 1;
+  /* outliers: strictly increasing indices at the code-0 positions, |r| >= 512 */
+  if (!bad) {
+    uint64_t k = 0;
+    for (uint64_t g = 0; g < nb && !bad; ++g) {
+      if (cd[g] != 0) {
+        res[g] = (int32_t)cd[g] - RO_RADIUS;
+        continue;
+      }
+      if (k >= n_out) { bad = 1; break; }
+      const uint32_t idx = get32(in, L.oidx + 4 * k);
+      const int32_t rv = (int32_t)get32(in, L.ores + 4 * k);
+      if (idx != g || (rv > -RO_RADIUS && rv < RO_RADIUS)) { bad = 1; break; }
+      res[g] = rv;
+      k++;
+    }
+    if (k != n_out) bad = 1;
+  }
+  if (bad) {
+    free(pk); free(res); free(cd);
+    return RO_ERR_CORRUPT;
+  }
+  /* inverse Lorenzo: q is the 2D inclusive prefix sum of r over each panel
+   * (two's-complement wrap-around, as int32) */
+  const uint64_t Hb = ro_hb(&p), Wb = ro_wb(&p), b = p.bin;
+  for (uint64_t pa = 0; pa < p.panels; ++pa) {
+    for (uint64_t I = 0; I < Hb; ++I)
+      for (uint64_t J = 1; J < Wb; ++J) {
+        const uint64_t g = (pa * Hb + I) * Wb + J;
+        res[g] = (int32_t)((uint32_t)res[g] + (uint32_t)res[g - 1]);
+      }
+    for (uint64_t I = 1; I < Hb; ++I)
+      for (uint64_t J = 0; J < Wb; ++J) {
+        const uint64_t g = (pa * Hb + I) * Wb + J;
+        res[g] = (int32_t)((uint32_t)res[g] + (uint32_t)res[g - Wb]);
+      }
+  }
+  /* background: the bin value replicated over the bin */
+  const double step = 2.0 * p.eb;
+  for (uint64_t pa = 0; pa < p.panels; ++pa)
+    for (uint64_t i = 0; i < p.height; ++i)
+      for (uint64_t j = 0; j < p.width; ++j) {
+        const uint64_t g = (pa * Hb + i / b) * Wb + j / b;
+        frame[(pa * p.height + i) * p.width + j] = (float)((double)res[g] * step);
+      }
+  /* ROI windows, bit-exact from the payload */
+  const int64_t h = p.window / 2, w = p.window;
+  for (uint32_t k = 0; k < np; ++k) {
+    const int64_t pa = pk[3 * k], r0 = pk[3 * k + 1] - h, c0 = pk[3 * k + 2] - h;
+    for (int64_t u = 0; u < w; ++u)
+      for (int64_t v = 0; v < w; ++v) {
+        const int64_t i = r0 + u, j = c0 + v;
+        if (i < 0 || i >= (int64_t)p.height || j < 0 || j >= (int64_t)p.width) continue;
+        memcpy(&frame[((uint64_t)pa * p.height + (uint64_t)i) * p.width + (uint64_t)j],
+               in + L.roi + 4 * (((uint64_t)k * w + (uint64_t)u) * w + (uint64_t)v), 4);
+      }
+  }
+  free(pk); free(res); free(cd);
+  return RO_OK;
+}

@@ -1,0 +1,158 @@
+"""Independent reader/builder of the compressed stream layout, and brute-force
+definitions used as pins.  Test code only: written from the stated format and
+the paper's definitions, sharing nothing with the oracle or the HIP library.
+
+Layout (little-endian, sections 4-byte aligned):
+  header 80 B: magic 'RSZ1', u16 version 1, u16 flags (bit0 bin_mode),
+  u32 P, H, W, window, bin, radius(512), f64 eb, u32 npeaks, n_out, chunk(4096),
+  n_chunks, u64 T (bits), u64 stream_bytes, u64 reserved 0;
+  then peaks (npeaks x 3 u16, padded to 4), ROI payload (npeaks*w*w u32),
+  code lengths (1024 u8), outlier indices (n_out u32), outlier residuals
+  (n_out i32), chunk bit offsets (n_chunks u32), bitstream (ceil(T/32) u32,
+  codewords MSB-first within each word).
+"""
+import struct
+
+import numpy as np
+
+HDR = struct.Struct("<4sHHIIIIIIdIIIIQQQ")
+assert HDR.size == 80
+
+
+def align4(x):
+    return (x + 3) & ~3
+
+
+def sections(npeaks, window, n_out, n_chunks, T):
+    off = {}
+    off["peaks"] = 80
+    off["roi"] = 80 + align4(6 * npeaks)
+    off["lens"] = off["roi"] + 4 * npeaks * window * window
+    off["oidx"] = off["lens"] + 1024
+    off["ores"] = off["oidx"] + 4 * n_out
+    off["chunks"] = off["ores"] + 4 * n_out
+    off["bits"] = off["chunks"] + 4 * n_chunks
+    off["total"] = off["bits"] + 4 * ((T + 31) // 32)
+    return off
+
+
+def parse(buf):
+    buf = bytes(np.asarray(buf, dtype=np.uint8).tobytes())
+    (magic, ver, flags, P, H, W, w, b, R, eb, npk, n_out, ch, nch, T, total, res) = \
+        HDR.unpack_from(buf, 0)
+    off = sections(npk, w, n_out, nch, T)
+    d = dict(magic=magic, version=ver, flags=flags, P=P, H=H, W=W, window=w, bin=b, radius=R,
+             eb=eb, npeaks=npk, n_out=n_out, chunk=ch, n_chunks=nch, T=T, stream_bytes=total,
+             reserved=res, off=off)
+    d["peaks"] = np.frombuffer(buf, np.uint16, 3 * npk, off["peaks"]).reshape(-1, 3)
+    d["roi"] = np.frombuffer(buf, np.uint32, npk * w * w, off["roi"])
+    d["lens"] = np.frombuffer(buf, np.uint8, 1024, off["lens"])
+    d["oidx"] = np.frombuffer(buf, np.uint32, n_out, off["oidx"])
+    d["ores"] = np.frombuffer(buf, np.int32, n_out, off["ores"])
+    d["chunk_offsets"] = np.frombuffer(buf, np.uint32, nch, off["chunks"])
+    d["bit_words"] = np.frombuffer(buf, np.uint32, (T + 31) // 32, off["bits"])
+    return d
+
+
+def bits_of(words, T):
+    """Stream bits as a list of 0/1, bit k = bit 31-(k%32) of word k//32."""
+    out = []
+    for k in range(T):
+        out.append((int(words[k // 32]) >> (31 - k % 32)) & 1)
+    return out
+
+
+def decode_symbols(lens, words, T, nsym):
+    """Bit-by-bit prefix decode with a dictionary of codewords rebuilt from the
+    lengths by sorting (length, symbol) -- written independently."""
+    syms = sorted((int(lens[s]), s) for s in range(1024) if lens[s] > 0)
+    table = {}
+    code = -1
+    prev = 0
+    for L, s in syms:
+        code = 0 if code < 0 else (code + 1) << (L - prev)
+        prev = L
+        table[(L, code)] = s
+    bits = bits_of(words, T)
+    out, pos = [], 0
+    offsets = []
+    for g in range(nsym):
+        if g % 4096 == 0:
+            offsets.append(pos)
+        c, L = 0, 0
+        while True:
+            c = (c << 1) | bits[pos]
+            pos += 1
+            L += 1
+            if (L, c) in table:
+                out.append(table[(L, c)])
+                break
+            assert L < 32
+    assert pos == T
+    return np.array(out, np.int64), offsets
+
+
+def mask_bruteforce(shape, peaks, window):
+    """Per pixel: inside the window of any peak on the same panel."""
+    P, H, W = shape
+    h = window // 2
+    M = np.zeros(shape, bool)
+    for p in range(P):
+        for i in range(H):
+            for j in range(W):
+                for (pk, r, c) in peaks:
+                    if pk == p and r - h <= i <= r - h + window - 1 and c - h <= j <= c - h + window - 1:
+                        M[p, i, j] = True
+                        break
+    return M
+
+
+def mask_slices(shape, peaks, window):
+    """Same mask by numpy slice assignment."""
+    P, H, W = shape
+    h = window // 2
+    M = np.zeros(shape, bool)
+    for (pk, r, c) in peaks:
+        M[pk, max(0, r - h):max(0, r - h + window), max(0, c - h):max(0, c - h + window)] = True
+    return M
+
+
+def unpack_bitmap(bitmap, W):
+    bitmap = np.asarray(bitmap, np.uint32)
+    P, H, wpr = bitmap.shape
+    bits = ((bitmap[..., None] >> np.arange(32, dtype=np.uint32)) & 1).astype(bool)
+    return bits.reshape(P, H, wpr * 32)[:, :, :W]
+
+
+def bin_sums(frame, M, b, include_all):
+    """S (fp64, raster-order accumulation) and n per bin by explicit loops
+    over the b x b offsets; partial bins at the edges."""
+    P, H, W = frame.shape
+    Hb, Wb = -(-H // b), -(-W // b)
+    S = np.zeros((P, Hb, Wb), np.float64)
+    n = np.zeros((P, Hb, Wb), np.int64)
+    x64 = frame.astype(np.float64)
+    for di in range(b):
+        for dj in range(b):
+            sub = x64[:, di::b, dj::b]
+            inc = np.ones(sub.shape, bool) if include_all else ~M[:, di::b, dj::b]
+            hs, ws = sub.shape[1], sub.shape[2]
+            S[:, :hs, :ws] = np.where(inc, S[:, :hs, :ws] + sub, S[:, :hs, :ws])
+            n[:, :hs, :ws] += inc
+    return S, n
+
+
+def closed_form_reconstruction(frame, peaks, window, b, eb, bin_mode):
+    """y = x on ROI pixels (bit-exact), else float32(rint(S/(n*2eb)) * 2eb)
+    replicated over the bin, with q = 0 for an empty bin."""
+    P, H, W = frame.shape
+    M = mask_slices(frame.shape, peaks, window)
+    S, n = bin_sums(frame, M, b, bin_mode == 1)
+    den = n.astype(np.float64) * (2.0 * eb)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        q = np.where(n > 0, np.rint(S / np.where(n > 0, den, 1.0)), 0.0)
+    q = q.astype(np.int64)             # q is an integer: rint(-0.3) is the integer 0
+    val = (q.astype(np.float64) * (2.0 * eb)).astype(np.float32)
+    y = np.repeat(np.repeat(val, b, axis=1), b, axis=2)[:, :H, :W].copy()
+    y[M] = frame[M]
+    return y, M, S, n, q

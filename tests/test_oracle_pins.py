@@ -1,0 +1,422 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each check is independent of the oracle's own code: hand-derived streams
+(tests/golden), brute-force masks, explicit-loop bin sums, the closed-form
+reconstruction, prefix-sum inversion of the Lorenzo step, an independent heap
+Huffman cost, brute-force optimal codes on tiny alphabets, Kraft sums and an
+independent bit-level stream reader.
+"""
+import glob
+import heapq
+import itertools
+import json
+import os
+import struct
+
+import numpy as np
+import pytest
+
+from oracle import rsz_oracle as O
+from paper_2206_11297_amd import synth
+from tests import streamfmt as F
+
+GOLDEN = sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden", "*.json")))
+
+
+def _params(d):
+    return O.params(d["panels"], d["height"], d["width"], d["window"], d["bin"], d["eb"],
+                    d["bin_mode"])
+
+
+def _build_expected_stream(g):
+    """Byte stream assembled from the hand-derived fixture with struct."""
+    p, e = g["params"], g["expect"]
+    peaks = g["peaks"]
+    off = F.sections(len(peaks), p["window"], e["n_out"], e["n_chunks"], e["T"])
+    buf = bytearray(off["total"])
+    F.HDR.pack_into(buf, 0, b"RSZ1", 1, p["bin_mode"], p["panels"], p["height"], p["width"],
+                    p["window"], p["bin"], 512, p["eb"], len(peaks), e["n_out"], 4096,
+                    e["n_chunks"], e["T"], e["stream_bytes"], 0)
+    for k, pk in enumerate(peaks):
+        struct.pack_into("<3H", buf, off["peaks"] + 6 * k, *pk)
+    for k, wd in enumerate(e["roi_words"]):
+        struct.pack_into("<I", buf, off["roi"] + 4 * k, wd)
+    for s, L in e["lens"].items():
+        buf[off["lens"] + int(s)] = L
+    for k, (gi, rv) in enumerate(e["outliers"]):
+        struct.pack_into("<I", buf, off["oidx"] + 4 * k, gi)
+        struct.pack_into("<i", buf, off["ores"] + 4 * k, rv)
+    for k, c in enumerate(e["chunk_offsets"]):
+        struct.pack_into("<I", buf, off["chunks"] + 4 * k, c)
+    for k, wd in enumerate(e["bit_words"]):
+        struct.pack_into("<I", buf, off["bits"] + 4 * k, wd)
+    assert off["total"] == e["stream_bytes"]
+    return np.frombuffer(bytes(buf), np.uint8)
+
+
+@pytest.mark.parametrize("path", GOLDEN, ids=[os.path.basename(p) for p in GOLDEN])
+def test_golden_stream_hand_derived(path):
+    g = json.load(open(path))
+    p = _params(g["params"])
+    frame = np.array(g["frame"], np.float32)
+    peaks = np.array(g["peaks"], np.int32).reshape(-1, 3)
+    st, stream, nbytes = O.compress(p, frame, peaks)
+    assert st == O.OK
+    expected = _build_expected_stream(g)
+    assert nbytes == expected.size
+    np.testing.assert_array_equal(stream, expected)
+    d = O.intermediates(p, frame, peaks)
+    for s, c in g["expect"]["codewords"].items():
+        assert d["cw"][int(s)] == c
+    st, y = O.decompress(stream)
+    assert st == O.OK
+    np.testing.assert_array_equal(y, np.array(g["expect"]["reconstruction"], np.float32))
+
+
+TINY = [
+    # (seed, shape, npeaks, window, bin, eb, kind)
+    (1, (1, 5, 7), 2, 3, 2, 1.0, "normal"),
+    (2, (2, 9, 9), 3, 5, 3, 0.5, "int"),
+    (3, (2, 6, 8), 0, 1, 1, 1.0, "int"),
+    (4, (1, 9, 4), 3, 1, 2, 10.0, "normal"),
+    (5, (2, 7, 9), 2, 9, 2, 1.0, "special"),
+    (6, (1, 8, 8), 3, 3, 4, 0.25, "const"),
+    (7, (3, 4, 5), 3, 2, 2, 1.0, "normal"),
+    (8, (1, 1, 1), 1, 1, 1, 1.0, "normal"),
+    (9, (2, 3, 9), 3, 4, 3, 5.0, "int"),
+    (10, (1, 9, 9), 2, 17, 2, 1.0, "normal"),
+]
+
+
+@pytest.mark.parametrize("case", TINY, ids=[f"seed{c[0]}" for c in TINY])
+@pytest.mark.parametrize("bin_mode", [0, 1])
+def test_tiny_bruteforce(case, bin_mode):
+    seed, shape, npk, w, b, eb, kind = case
+    frame, peaks = synth.tiny_case(seed, shape, npk, kind)
+    p = O.params(*shape, w, b, eb, bin_mode)
+    d = O.intermediates(p, frame, peaks)
+    assert d["status"] == O.OK
+    # mask: brute force per pixel, and numpy slices
+    Mb = F.mask_bruteforce(shape, [tuple(x) for x in peaks], w)
+    np.testing.assert_array_equal(Mb, F.mask_slices(shape, [tuple(x) for x in peaks], w))
+    np.testing.assert_array_equal(F.unpack_bitmap(d["mask"], shape[2]), Mb)
+    # ROI payload: bits of the window, zero outside the panel
+    xb = frame.view(np.uint32)
+    h = w // 2
+    for k, (pk, r, c) in enumerate(peaks):
+        for u in range(w):
+            for v in range(w):
+                i, j = r - h + u, c - h + v
+                ok = 0 <= i < shape[1] and 0 <= j < shape[2]
+                assert d["roi"][k, u, v] == (xb[pk, i, j] if ok else 0)
+    # bin sums and counts
+    S, n = F.bin_sums(frame, Mb, b, bin_mode == 1)
+    np.testing.assert_array_equal(d["n"], n.ravel())
+    np.testing.assert_array_equal(d["S"].view(np.uint64), S.ravel().view(np.uint64))
+    # prequantisation
+    den = n.ravel().astype(np.float64) * (2.0 * eb)
+    q = np.where(n.ravel() > 0, np.rint(S.ravel() / np.where(den > 0, den, 1)), 0)
+    np.testing.assert_array_equal(d["q"], q.astype(np.int32))
+    # Lorenzo: the 2D prefix sum of r over each panel gives q back
+    Hb, Wb = -(-shape[1] // b), -(-shape[2] // b)
+    r3 = d["r"].reshape(shape[0], Hb, Wb).astype(np.int64)
+    np.testing.assert_array_equal(np.cumsum(np.cumsum(r3, 1), 2).ravel(), d["q"])
+    # codes and outliers
+    codes = d["codes"].astype(np.int64)
+    small = np.abs(d["r"]) < 512
+    np.testing.assert_array_equal(codes[small], d["r"][small] + 512)
+    assert np.all(codes[~small] == 0)
+    np.testing.assert_array_equal(d["out_idx"], np.nonzero(~small)[0])
+    np.testing.assert_array_equal(d["out_res"], d["r"][~small])
+    np.testing.assert_array_equal(d["hist"], np.bincount(codes, minlength=1024))
+    # whole stream: decompress == closed form; ROI bit-exact; bound
+    st, stream, _ = O.compress(p, frame, peaks)
+    assert st == O.OK
+    st, y = O.decompress(stream)
+    assert st == O.OK
+    yc, M, S, n, qc = F.closed_form_reconstruction(frame, peaks, w, b, eb, bin_mode)
+    np.testing.assert_array_equal(y.view(np.uint32), yc.view(np.uint32))
+    np.testing.assert_array_equal(y.view(np.uint32)[M], frame.view(np.uint32)[M])
+
+
+def _bound_check(frame, peaks, y, w, b, eb, bin_mode):
+    """Every reconstructed background value is within eb of its bin mean
+    (Sec. V-C: the bound holds on the binned values).  The slack covers the
+    final float32 rounding of q*2eb and the rounding of the mean itself."""
+    P, H, W = frame.shape
+    M = F.mask_slices(frame.shape, [tuple(x) for x in peaks], w)
+    S, n = F.bin_sums(frame, M, b, bin_mode == 1)
+    mean = np.where(n > 0, S / np.maximum(n, 1), 0.0)
+    mean_px = np.repeat(np.repeat(mean, b, 1), b, 2)[:, :H, :W]
+    n_px = np.repeat(np.repeat(n, b, 1), b, 2)[:, :H, :W]
+    sel = (~M) & (n_px > 0)
+    yv = y.astype(np.float64)[sel]
+    err = np.abs(yv - mean_px[sel])
+    slack = np.spacing(np.abs(y[sel]).astype(np.float32)).astype(np.float64) + \
+        2.0 ** -50 * np.abs(mean_px[sel])
+    assert np.all(err <= eb + slack), float(np.max(err - eb - slack))
+
+
+@pytest.mark.parametrize("eb", [1.0, 5.0, 10.0, 20.0])
+def test_cspad_frame_round_trip_and_bound(eb):
+    frame, peaks = synth.cspad_frame(0)
+    p = O.params(32, 185, 388, 17, 2, eb, 0)
+    st, stream, nbytes = O.compress(p, frame, peaks)
+    assert st == O.OK
+    st, y = O.decompress(stream)
+    assert st == O.OK
+    M = F.mask_slices(frame.shape, [tuple(x) for x in peaks], 17)
+    # ROI pixels round-trip bit-exactly (Sec. IV)
+    np.testing.assert_array_equal(y.view(np.uint32)[M], frame.view(np.uint32)[M])
+    _bound_check(frame, peaks, y, 17, 2, eb, 0)
+    yc, *_ = F.closed_form_reconstruction(frame, peaks, 17, 2, eb, 0)
+    np.testing.assert_array_equal(y.view(np.uint32), yc.view(np.uint32))
+    # independent stream reader: layout, sizes, symbol decode, chunk offsets
+    s = F.parse(stream)
+    assert s["magic"] == b"RSZ1" and s["stream_bytes"] == nbytes == s["off"]["total"]
+    d = O.intermediates(p, frame, peaks)
+    nb = 32 * 93 * 194
+    syms, offs = F.decode_symbols(s["lens"], s["bit_words"], s["T"], nb)
+    np.testing.assert_array_equal(syms, d["codes"])
+    np.testing.assert_array_equal(np.array(offs, np.uint32), s["chunk_offsets"])
+    np.testing.assert_array_equal(s["peaks"].astype(np.int32), peaks)
+    # compression ratio from the exact size, relative to uint16 raw (Sec. IV)
+    cr_u16 = frame.size * 2 / nbytes
+    assert 1.0 < cr_u16 < 32.5
+
+
+def test_bound_on_jungfrau_frame():
+    frame, peaks = synth.jungfrau_frame(3)
+    for eb, b, w in [(1.0, 2, 11), (10.0, 4, 25)]:
+        p = O.params(8, 512, 1024, w, b, eb, 0)
+        st, stream, _ = O.compress(p, frame, peaks)
+        assert st == O.OK
+        st, y = O.decompress(stream)
+        assert st == O.OK
+        _bound_check(frame, peaks, y, w, b, eb, 0)
+
+
+# ------------------------------------------------------------------ Huffman
+
+
+def _heap_cost(counts):
+    """Optimal prefix-code cost = sum of internal node weights (tie-break free)."""
+    h = [int(c) for c in counts if c > 0]
+    if len(h) == 1:
+        return h[0]
+    heapq.heapify(h)
+    cost = 0
+    while len(h) > 1:
+        a, b = heapq.heappop(h), heapq.heappop(h)
+        cost += a + b
+        heapq.heappush(h, a + b)
+    return cost
+
+
+def _check_code(hist, lens):
+    used = hist > 0
+    assert np.all((lens > 0) == used)
+    assert lens.max() <= 32
+    kraft = sum(2.0 ** -int(L) for L in lens[used])
+    if used.sum() == 1:
+        assert lens[used][0] == 1
+    else:
+        assert kraft == 1.0
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_huffman_optimal_and_complete(seed):
+    rng = np.random.default_rng([2206, 11297, 7, seed])
+    k = int(rng.integers(1, 300))
+    hist = np.zeros(1024, np.uint32)
+    syms = rng.choice(1024, k, replace=False)
+    if seed % 3 == 0:
+        hist[syms] = rng.integers(1, 5, k)          # many ties
+    elif seed % 3 == 1:
+        hist[syms] = (rng.pareto(1.0, k) * 10 + 1).astype(np.uint32)
+    else:
+        hist[syms] = rng.integers(1, 1 << 20, k)
+    lens = O.huffman_lengths(hist)
+    _check_code(hist, lens)
+    assert int(np.dot(hist.astype(np.int64), lens.astype(np.int64))) == _heap_cost(hist)
+    cw = O.canonical(lens)
+    # prefix-free: no codeword is a prefix of another
+    items = [(int(lens[s]), int(cw[s])) for s in range(1024) if lens[s]]
+    strs = sorted(format(c, f"0{L}b") for L, c in items)
+    for a, b in zip(strs, strs[1:]):
+        assert not b.startswith(a)
+    # canonical: ordered by (length, symbol), codes increase, first is zero
+    order = sorted((int(lens[s]), s) for s in range(1024) if lens[s])
+    vals = [int(cw[s]) << (32 - L) for L, s in order]
+    assert vals == sorted(vals) and vals[0] == 0 and len(set(vals)) == len(vals)
+
+
+def test_huffman_bruteforce_small_alphabets():
+    """Optimal lengths by exhaustive search over complete codes (<= 6 symbols)."""
+    rng = np.random.default_rng([2206, 11297, 8])
+    for trial in range(60):
+        k = int(rng.integers(2, 7))
+        w = rng.integers(1, 30, k)
+        best = None
+        for Ls in itertools.product(range(1, k), repeat=k):
+            if sum(2.0 ** -L for L in Ls) == 1.0:
+                c = int(np.dot(w, Ls))
+                best = c if best is None else min(best, c)
+        hist = np.zeros(1024, np.uint32)
+        syms = rng.choice(1024, k, replace=False)
+        hist[syms] = w
+        lens = O.huffman_lengths(hist)
+        assert int(np.dot(w, lens[syms].astype(np.int64))) == best
+
+
+def test_huffman_single_symbol_and_length_limit():
+    hist = np.zeros(1024, np.uint32)
+    hist[512] = 12345
+    lens = O.huffman_lengths(hist)
+    assert lens[512] == 1 and lens.sum() == 1
+    # Fibonacci weights force depth > 32 without the limit; lengths stay <= 32
+    fib = [1, 1]
+    while len(fib) < 40:
+        fib.append(fib[-1] + fib[-2])
+    hist = np.zeros(1024, np.uint32)
+    hist[:40] = np.array(fib, np.uint64).astype(np.uint32)
+    lens = O.huffman_lengths(hist)
+    _check_code(hist, lens)
+    assert lens.max() <= 32
+
+
+# ------------------------------------------------------------ special cases
+
+
+def test_constant_frame_closed_form():
+    """Constant frame, no peaks: one bin value, residual q at (0,0) only (plus
+    the first row/column of the Lorenzo step), exact reconstruction when the
+    value is a multiple of 2eb."""
+    frame = np.full((2, 16, 24), 40.0, np.float32)
+    p = O.params(2, 16, 24, 17, 2, 10.0, 0)
+    d = O.intermediates(p, frame, np.zeros((0, 3), np.int32))
+    assert np.all(d["q"] == 2)
+    S = d["S"].reshape(2, 8, 12)
+    assert np.all(S == 160.0) and np.all(d["n"] == 4)
+    r = d["r"].reshape(2, 8, 12)
+    assert np.all(r[:, 0, 0] == 2) and np.all(r[:, 1:, 1:] == 0)
+    assert np.all(r[:, 0, 1:] == 0) and np.all(r[:, 1:, 0] == 0)
+    st, stream, _ = O.compress(p, frame, np.zeros((0, 3), np.int32))
+    st, y = O.decompress(stream)
+    np.testing.assert_array_equal(y, frame)
+
+
+def test_bilinear_field_has_zero_residuals():
+    """q = a + b*I + c*J gives r = 0 for I, J >= 1 (the 2D Lorenzo predictor is
+    exact on bilinear data)."""
+    I, J = np.meshgrid(np.arange(12), np.arange(20), indexing="ij")
+    val = 2.0 * (3 + 2 * I - 5 * J)            # exact multiples of 2eb=2
+    frame = val[None].astype(np.float32)
+    p = O.params(1, 12, 20, 1, 1, 1.0, 0)
+    d = O.intermediates(p, frame, np.zeros((0, 3), np.int32))
+    r = d["r"].reshape(12, 20)
+    assert np.all(r[1:, 1:] == 0)
+
+
+def test_rounding_ties_go_to_even():
+    """Bin means at exact half steps round to the even integer."""
+    k = np.arange(-6, 6)
+    vals = (k + 0.5) * 2.0                   # eb = 1 -> t = k + 0.5
+    frame = vals[None, None, :].astype(np.float32)
+    p = O.params(1, 1, k.size, 1, 1, 1.0, 0)
+    d = O.intermediates(p, frame, np.zeros((0, 3), np.int32))
+    expect = np.array([x + 1 if (x % 2) else x for x in k])  # even of k, k+1
+    np.testing.assert_array_equal(d["q"], expect)
+
+
+def test_window_covering_panel_and_empty_bins():
+    """A window larger than the panel makes every pixel ROI: all bins empty,
+    q = 0, and the frame round-trips bit-exactly."""
+    frame, _ = synth.tiny_case(11, (1, 6, 7), 0, "normal")
+    peaks = np.array([[0, 3, 3]], np.int32)
+    p = O.params(1, 6, 7, 31, 2, 1.0, 0)
+    d = O.intermediates(p, frame, peaks)
+    assert np.all(d["n"] == 0) and np.all(d["q"] == 0)
+    st, stream, _ = O.compress(p, frame, peaks)
+    st, y = O.decompress(stream)
+    np.testing.assert_array_equal(y.view(np.uint32), frame.view(np.uint32))
+
+
+def test_huge_eb_gives_zero_field():
+    frame, peaks = synth.tiny_case(12, (2, 8, 8), 2, "normal")
+    p = O.params(2, 8, 8, 3, 2, 1e12, 0)
+    d = O.intermediates(p, frame, peaks)
+    assert np.all(d["q"] == 0) and np.all(d["codes"] == 512)
+    assert d["lens"][512] == 1 and d["T"] == d["codes"].size
+
+
+def test_errors():
+    frame, peaks = synth.tiny_case(13, (1, 8, 8), 2, "normal")
+    p = O.params(1, 8, 8, 3, 2, 1.0, 0)
+    assert O.compress(p, frame, np.array([[1, 0, 0]], np.int32))[0] == O.ERR_PEAK
+    assert O.compress(p, frame, np.array([[0, 8, 0]], np.int32))[0] == O.ERR_PEAK
+    assert O.compress(p, frame, np.array([[0, 0, -1]], np.int32))[0] == O.ERR_PEAK
+    for bad in [O.params(0, 8, 8, 3, 2, 1.0), O.params(1, 8, 8, 0, 2, 1.0),
+                O.params(1, 8, 8, 3, 9, 1.0), O.params(1, 8, 8, 3, 2, 0.0),
+                O.params(1, 8, 8, 3, 2, float("nan")), O.params(1, 8, 8, 3, 2, 1.0, 2)]:
+        assert O.compress(bad, frame, peaks)[0] == O.ERR_ARG
+    f2 = frame.copy()
+    f2[0, 5, 5] = np.inf
+    assert O.compress(p, f2, np.zeros((0, 3), np.int32))[0] == O.ERR_RANGE
+    # NaN inside a ROI window is kept verbatim in background mode
+    f3 = frame.copy()
+    f3[0, 4, 4] = np.nan
+    st, stream, _ = O.compress(p, f3, np.array([[0, 4, 4]], np.int32))
+    assert st == O.OK
+    st, y = O.decompress(stream)
+    assert st == O.OK and y.view(np.uint32)[0, 4, 4] == f3.view(np.uint32)[0, 4, 4]
+    # capacity: too small reports the required size
+    st, s_ok, need = O.compress(p, frame, peaks)
+    st, _, need2 = O.compress(p, frame, peaks, cap=need - 1)
+    assert st == O.ERR_CAPACITY and need2 == need
+
+
+def test_corrupt_streams_are_rejected_or_decoded_safely():
+    frame, peaks = synth.tiny_case(14, (2, 12, 16), 3, "normal", scale=200.0)
+    p = O.params(2, 12, 16, 3, 2, 1.0, 0)
+    st, stream, _ = O.compress(p, frame, peaks)
+    assert st == O.OK
+    assert O.decompress(stream[:-1])[0] == O.ERR_CORRUPT
+    assert O.decompress(stream[:79])[0] == O.ERR_CORRUPT
+    rng = np.random.default_rng(5)
+    rejected = 0
+    for t in range(300):
+        s2 = stream.copy()
+        pos = int(rng.integers(0, s2.size))
+        s2[pos] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        st, _ = O.decompress(s2)
+        assert st in (O.OK, O.ERR_CORRUPT)
+        rejected += st == O.ERR_CORRUPT
+    assert rejected > 0
+
+
+def test_trend_cr_rises_with_bin_and_bound():
+    """Direction of the paper's hyper-parameter table (Sec. VI): compression
+    ratio grows with bin size and with tolerance.  The paper's values are
+    not targets (different data and entropy stage)."""
+    frame, peaks = synth.cspad_frame(5)
+    def size(b, eb):
+        st, s, n = O.compress(O.params(32, 185, 388, 17, b, eb, 0), frame, peaks)
+        assert st == O.OK
+        return n
+    assert size(1, 10.0) > size(2, 10.0) > size(3, 10.0)
+    assert size(2, 1.0) > size(2, 5.0) > size(2, 10.0)
+
+
+def test_generators_are_reproducible():
+    a, pa = synth.cspad_frame(3)
+    b, pb = synth.cspad_frame(3)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(pa, pb)
+    c, _ = synth.cspad_frame(4)
+    assert not np.array_equal(a, c)
+    counts = synth.batch_peak_counts(1000)
+    assert (counts == 0).sum() >= 200 and abs(counts[counts > 0].mean() - 60) < 2
+    f, pk = synth.jungfrau_frame(1)
+    assert f.shape == (8, 512, 1024) and 20 <= pk.shape[0] <= 800
+    assert pk[:, 0].max() < 8 and pk[:, 1].max() < 512 and pk[:, 2].max() < 1024
