@@ -1,0 +1,189 @@
+/*
+ * rsz.h -- C ABI of librsz: ROIBIN-SZ per-frame compression of serial
+ * crystallography detector frames on an AMD MI355X (gfx950) GPU.
+ *
+ * Method (arXiv 2206.11297): each frame is split into the regions of interest
+ * around its Bragg peaks, kept without error, and the background (Sec. IV).
+ * The background is binned b x b by its mean (Sec. VI) and compressed with an
+ * absolute error bound that holds on the binned values (Sec. V-C, "Our
+ * Approach").  Here the background compressor is prequantisation at step 2*eb,
+ * a 2D Lorenzo predictor over the integer field of each panel, outlier capture
+ * outside a radius of 512, and Huffman coding over 1024 symbols.
+ *
+ * Conventions for every entry point:
+ *   - Pointers prefixed d_ are device memory (e.g. torch tensors on the GPU),
+ *     h_ are host memory.  The caller owns every buffer; the library allocates
+ *     no device memory and keeps no pointer after a call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Functions return an rsz_status value and never throw.  After an error
+ *     the contents of output buffers are unspecified.
+ *   - Calls on different streams with different workspaces may run
+ *     concurrently; calls sharing a workspace must be ordered by the caller.
+ *   - Device buffers must be 16-byte aligned (frames, outputs, workspaces).
+ *
+ * Frame layout: panels x height x width float32, C-contiguous.  Stream
+ * layout (little-endian, sections 4-byte aligned): 80-byte header, peaks
+ * (u16 panel,row,col), ROI payload (npeaks*w*w u32 bit patterns, 0 outside
+ * the panel), code lengths (1024 u8), outlier bin indices (u32), outlier
+ * residuals (i32), chunk bit offsets (u32, one per 4096 symbols), bitstream
+ * (u32 words, codewords MSB-first).
+ */
+#ifndef RSZ_H
+#define RSZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A Bragg peak: integer pixel position (Sec. IV-B: the peak list is an array
+ * of coordinates). */
+typedef struct {
+  int32_t panel, row, col;
+} rsz_peak;
+
+/* Compression parameters.
+ *   panels, height, width: frame shape, each 1..65535, pixels < 2^31, and
+ *     panels*ceil(height/bin)*ceil(width/bin) < 2^27 bins.
+ *   window: ROI edge w in pixels, 1..1023 (17 in the paper, Sec. IV); the
+ *     window of a peak at (r,c) covers rows r-w/2 .. r-w/2+w-1 (integer
+ *     division), same for columns, clipped to the panel.
+ *   bin: bin factor b, 1..8 (2 in the paper's chosen setting, Sec. VI).
+ *   bin_mode: RSZ_BIN_BACKGROUND averages only pixels outside every ROI
+ *     window; RSZ_BIN_ALL averages every pixel of the bin.
+ *   eb: absolute error bound on binned values, finite and > 0. */
+typedef struct {
+  uint32_t panels, height, width;
+  uint32_t window;
+  uint32_t bin;
+  uint32_t bin_mode;
+  double eb;
+} rsz_params;
+
+enum { RSZ_BIN_BACKGROUND = 0, RSZ_BIN_ALL = 1 };
+
+typedef enum {
+  RSZ_OK = 0,
+  RSZ_ERR_ARG = -1,       /* invalid parameter, pointer, size or alignment */
+  RSZ_ERR_PEAK = -2,      /* a peak lies outside the frame                 */
+  RSZ_ERR_RANGE = -3,     /* a background bin is non-finite or |q| >= 2^28 */
+  RSZ_ERR_CAPACITY = -4,  /* output buffer too small (size reported)       */
+  RSZ_ERR_CORRUPT = -5,   /* malformed compressed stream                   */
+  RSZ_ERR_WORKSPACE = -6, /* workspace too small                           */
+  RSZ_ERR_HIP = -7        /* HIP runtime error                             */
+} rsz_status;
+
+/* Human-readable name of a status value (static string). */
+const char *rsz_status_string(int status);
+
+/* Upper bound of the compressed size of one frame with npeaks peaks (every
+ * bin an outlier and every codeword 32 bits).  Host-only. */
+int rsz_max_compressed_bytes(const rsz_params *p, uint32_t npeaks, uint64_t *bytes);
+
+/* Device workspace needed by rsz_compress for one frame.  Host-only. */
+int rsz_workspace_bytes(const rsz_params *p, uint32_t npeaks, uint64_t *bytes);
+
+/* Compress one device-resident frame (Sec. IV: ROI extraction, binning,
+ * error-bounded compression of the binned background).
+ *   d_frame: panels*height*width float32.  d_peaks: npeaks peaks (may be NULL
+ *   when npeaks is 0).  d_out/out_cap: output buffer.  h_out_bytes: receives
+ *   the stream size (also on RSZ_ERR_CAPACITY, where it is the size needed).
+ *   d_ws/ws_bytes: workspace of at least rsz_workspace_bytes().
+ * Work is queued on `stream`; the call returns after the stream has finished
+ * it (it reads back the size).  Peaks outside the frame give RSZ_ERR_PEAK,
+ * a non-finite or out-of-range background bin RSZ_ERR_RANGE. */
+int rsz_compress(const rsz_params *p, const float *d_frame, const rsz_peak *d_peaks,
+                 uint32_t npeaks, void *d_out, uint64_t out_cap, uint64_t *h_out_bytes,
+                 void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* One frame of a batch.  out/out_cap: that frame's own output buffer
+ * (device); the frames of a batch may have different shapes, parameters and
+ * peak counts. */
+typedef struct {
+  rsz_params params;
+  const float *frame;
+  const rsz_peak *peaks;
+  uint32_t npeaks;
+  uint32_t reserved; /* must be 0 */
+  void *out;
+  uint64_t out_cap;
+} rsz_frame_desc;
+
+/* Device workspace for rsz_compress_batch over these descriptors.  Host-only.
+ * Descriptors with invalid parameters are sized as empty. */
+int rsz_batch_workspace_bytes(uint32_t nframes, const rsz_frame_desc *h_descs,
+                              uint64_t *bytes);
+
+/* Compress nframes frames in one batched launch sequence (every step of the
+ * path is one kernel launch over all frames).  h_descs is host memory and may
+ * be reused once the call returns.  Per-frame results go to device arrays:
+ * d_out_bytes[i] (stream size, or the size needed on RSZ_ERR_CAPACITY) and
+ * d_status[i] (an rsz_status).  Asynchronous: returns after queueing; the
+ * results are valid once `stream` has finished.  The return value reports only
+ * errors of the call itself (ARG, WORKSPACE, HIP); a frame with invalid
+ * parameters reports RSZ_ERR_ARG in d_status. */
+int rsz_compress_batch(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t *d_out_bytes,
+                       int32_t *d_status, void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* Parse and check the 80-byte header of a stream held in host memory
+ * (h_stream, n >= 80 bytes).  Fills *p, *npeaks and *stream_bytes.
+ * Returns RSZ_ERR_CORRUPT for a malformed header.  Host-only. */
+int rsz_stream_info(const void *h_stream, uint64_t n, rsz_params *p, uint32_t *npeaks,
+                    uint64_t *stream_bytes);
+
+/* Device workspace for rsz_decompress of the stream whose header is given
+ * (host copy of at least its first 80 bytes).  Host-only. */
+int rsz_decompress_workspace_bytes(const void *h_header, uint64_t n, uint64_t *bytes);
+
+/* Decompress one device-resident stream into d_frame (panels*height*width
+ * float32, frame_elems >= that).  Background pixels get their bin value
+ * q*2*eb (Sec. VI "binning", bound of Sec. V-C); ROI pixels get their exact
+ * bits back (Sec. IV).  Structurally invalid streams give RSZ_ERR_CORRUPT.
+ * Synchronous with respect to `stream` (reads the header and the status). */
+int rsz_decompress(const void *d_in, uint64_t in_bytes, float *d_frame, uint64_t frame_elems,
+                   void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* Intermediates of compressing one frame, for parity checks.  Every pointer
+ * is device memory and may be NULL to skip that output.
+ *   mask: panels*height*ceil(width/32) u32, bit j%32 of word j/32 = ROI pixel.
+ *   S: nbins f64 sums, n: nbins u32 counts, q: nbins i32 quantised bins,
+ *   codes: nbins u16, hist: 1024 u32, lens: 1024 u8, cw: 1024 u32 canonical
+ *   codewords.  Bins are ordered (panel, bin row, bin column). */
+typedef struct {
+  uint32_t *mask;
+  double *S;
+  uint32_t *n;
+  int32_t *q;
+  uint16_t *codes;
+  uint32_t *hist;
+  uint8_t *lens;
+  uint32_t *cw;
+} rsz_debug_bufs;
+
+/* Runs the compression kernels of one frame up to the codebook and copies the
+ * intermediates out.  Same workspace as rsz_compress.  Synchronous. */
+int rsz_debug_intermediates(const rsz_params *p, const float *d_frame, const rsz_peak *d_peaks,
+                            uint32_t npeaks, const rsz_debug_bufs *bufs, void *d_ws,
+                            uint64_t ws_bytes, void *stream);
+
+/* Kernel timing with HIP events recorded around every launch, on the stream
+ * the kernel runs on.  rsz_profile_enable(1) clears and starts recording;
+ * rsz_profile_read waits for the recorded events and returns, per kernel
+ * name, the number of launches and the summed milliseconds (up to max
+ * entries; *n receives the count). */
+typedef struct {
+  char name[48];
+  uint32_t launches;
+  double total_ms;
+} rsz_kernel_time;
+
+int rsz_profile_enable(int enable);
+int rsz_profile_read(rsz_kernel_time *h_out, int max, int *n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSZ_H */

@@ -542,8 +542,8 @@ int ro_stream_info(const uint8_t *in, uint64_t in_bytes, ro_params *p, uint32_t 
 /* Decompress a stream into a panels x height x width float frame.
  * Structural validation first (any failure -> RO_ERR_CORRUPT); then
  * codes -> residuals -> q by 2D prefix sums -> bin value q*2eb replicated over
- * the bin -> ROI windows restored bit-exactly from the payload.  Where windows
- * overlap, the later peak in list order is written last. */
+ * the bin -> ROI windows restored bit-exactly from the payload.  Overlapping
+ * windows must carry identical bits for their shared pixels. */
 int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t frame_elems) {
   ro_params p;
   uint32_t np;
@@ -635,7 +635,11 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
       if (k >= n_out) { bad = 1; break; }
       const uint32_t idx = get32(in, L.oidx + 4 * k);
       const int32_t rv = (int32_t)get32(in, L.ores + 4 * k);
-      if (idx != g || (rv > -RO_RADIUS && rv < RO_RADIUS)) { bad = 1; break; }
+      /* |q| < 2^28 bounds every residual below 2^30 in magnitude */
+      if (idx != g || (rv > -RO_RADIUS && rv < RO_RADIUS) || rv <= -(1 << 30) || rv >= (1 << 30)) {
+        bad = 1;
+        break;
+      }
       res[g] = rv;
       k++;
     }
@@ -680,6 +684,22 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
                in + L.roi + 4 * (((uint64_t)k * w + (uint64_t)u) * w + (uint64_t)v), 4);
       }
   }
+  /* windows that overlap copy the same frame pixel, so every payload entry
+   * must agree with what was restored there; a stream where they differ is
+   * malformed */
+  for (uint32_t k = 0; k < np && !bad; ++k) {
+    const int64_t pa = pk[3 * k], r0 = pk[3 * k + 1] - h, c0 = pk[3 * k + 2] - h;
+    for (int64_t u = 0; u < w && !bad; ++u)
+      for (int64_t v = 0; v < w; ++v) {
+        const int64_t i = r0 + u, j = c0 + v;
+        if (i < 0 || i >= (int64_t)p.height || j < 0 || j >= (int64_t)p.width) continue;
+        if (memcmp(&frame[((uint64_t)pa * p.height + (uint64_t)i) * p.width + (uint64_t)j],
+                   in + L.roi + 4 * (((uint64_t)k * w + (uint64_t)u) * w + (uint64_t)v), 4) != 0) {
+          bad = 1;
+          break;
+        }
+      }
+  }
   free(pk); free(res); free(cd);
-  return RO_OK;
+  return bad ? RO_ERR_CORRUPT : RO_OK;
 }

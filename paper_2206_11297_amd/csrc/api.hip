@@ -1,0 +1,597 @@
+// api.hip -- host side of librsz: argument checks, batch planning, workspace
+// layout, the exported C ABI, and kernel timing.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rsz_internal.h"
+
+namespace rsz {
+
+// ----------------------------------------------------------------- timing
+
+namespace {
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+thread_local ProfRec *g_open = nullptr;
+}  // namespace
+
+void prof_begin(const char *name, hipStream_t s) {
+  if (!g_prof_on) return;
+  ProfRec r;
+  r.name = name;
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+  (void)hipEventRecord(r.a, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(r);
+  g_open = &g_prof.back();
+}
+
+void prof_end(hipStream_t s) {
+  if (!g_prof_on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (g_open) (void)hipEventRecord(g_open->b, s);
+  g_open = nullptr;
+}
+
+// --------------------------------------------------------------- planning
+
+static uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+static int check_params(const rsz_params *p, uint32_t npeaks) {
+  if (!p) return RSZ_ERR_ARG;
+  if (p->panels < 1 || p->panels > 65535 || p->height < 1 || p->height > 65535 ||
+      p->width < 1 || p->width > 65535)
+    return RSZ_ERR_ARG;
+  if (p->window < 1 || p->window > 1023 || p->bin < 1 || p->bin > 8 || p->bin_mode > 1)
+    return RSZ_ERR_ARG;
+  if (!(p->eb > 0.0) || !std::isfinite(p->eb)) return RSZ_ERR_ARG;
+  const uint64_t pix = (uint64_t)p->panels * p->height * p->width;
+  const uint64_t nb = (uint64_t)p->panels * div_up(p->height, p->bin) * div_up(p->width, p->bin);
+  if (pix >= (1ull << 31) || nb >= (1ull << 27)) return RSZ_ERR_ARG;
+  if ((uint64_t)npeaks * p->window * p->window > (1ull << 28)) return RSZ_ERR_ARG;
+  return RSZ_OK;
+}
+
+struct Geom {
+  uint32_t Hb, Wb, nbins, nchunks, TH, segs, groups, nstrips;
+  uint64_t off_roi, off_lens, off_oidx;
+  uint64_t max_bytes;
+};
+
+// Segment height: at most kMaxTH bin rows and a mask of at most kMaskRowsMax
+// raw rows per wave; segments are balanced in groups of kWaves per workgroup.
+static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap) {
+  Geom g;
+  g.Hb = (uint32_t)div_up(p->height, p->bin);
+  g.Wb = (uint32_t)div_up(p->width, p->bin);
+  g.nbins = p->panels * g.Hb * g.Wb;
+  g.nchunks = (uint32_t)div_up(g.nbins, kChunk);
+  uint32_t thmax = std::min<uint32_t>(kMaxTH, kMaskRowsMax / p->bin - 1);
+  thmax = std::max<uint32_t>(1, std::min(thmax, th_cap));
+  const uint32_t nseg = kWaves * (uint32_t)div_up(g.Hb, (uint64_t)kWaves * thmax);
+  g.TH = (uint32_t)div_up(g.Hb, nseg);
+  g.segs = (uint32_t)div_up(g.Hb, g.TH);
+  g.groups = (uint32_t)div_up(g.segs, kWaves);
+  g.nstrips = (uint32_t)div_up(g.Wb, 64);
+  g.off_roi = kHeader + align_up(6ull * npeaks, 4);
+  g.off_lens = g.off_roi + 4ull * npeaks * p->window * p->window;
+  g.off_oidx = g.off_lens + kNumSym;
+  // worst case: every bin an outlier, every codeword 32 bits
+  g.max_bytes = g.off_oidx + 8ull * g.nbins + 4ull * g.nchunks + 4ull * g.nbins;
+  return g;
+}
+
+struct Layout {
+  uint64_t plans, prefix, states, frames_begin, total;
+  std::vector<uint64_t> frame_off;  // per frame start of its private region
+};
+
+static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const Geom &g) {
+  uint64_t b = 0;
+  b += align_up(4ull * (p->panels + 1), 256);  // pstart
+  b += align_up(4ull * p->panels, 256);        // pcursor
+  b += align_up(12ull * npeaks, 256);          // bucket
+  b += align_up(2ull * g.nbins, 256);          // codes
+  b += align_up(4ull * g.nbins, 256);          // rbuf
+  b += 2 * align_up(4ull * g.nchunks, 256);    // chunk bits / nout
+  return b;
+}
+
+static Layout layout(uint32_t nframes, const std::vector<const rsz_params *> &ps,
+                     const std::vector<uint32_t> &np, const std::vector<Geom> &gs,
+                     const std::vector<int> &valid) {
+  Layout L;
+  L.plans = 0;
+  L.prefix = align_up(sizeof(FramePlan) * nframes, 256);
+  L.states = L.prefix + align_up(3 * 4ull * (nframes + 1), 256);
+  L.frames_begin = L.states + align_up(sizeof(FrameState) * nframes, 256);
+  uint64_t off = L.frames_begin;
+  L.frame_off.resize(nframes);
+  for (uint32_t f = 0; f < nframes; ++f) {
+    L.frame_off[f] = off;
+    if (valid[f]) off += frame_region_bytes(ps[f], np[f], gs[f]);
+  }
+  L.total = off;
+  return L;
+}
+
+// Host image of the plan, copied to the head of the workspace.
+struct HostPlan {
+  std::vector<uint8_t> bytes;
+  BatchPlan bp;
+  uint32_t common_b;
+};
+
+static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_bytes,
+                      int32_t *res_status, uint8_t *ws, uint64_t ws_bytes, uint32_t th_cap,
+                      HostPlan &hp, uint64_t *need, const rsz_debug_bufs *dbg) {
+  std::vector<const rsz_params *> ps(nframes);
+  std::vector<uint32_t> np(nframes);
+  std::vector<Geom> gs(nframes);
+  std::vector<int> valid(nframes);
+  for (uint32_t f = 0; f < nframes; ++f) {
+    ps[f] = &d[f].params;
+    np[f] = d[f].npeaks;
+    valid[f] = check_params(ps[f], np[f]) == RSZ_OK && d[f].reserved == 0 && d[f].frame &&
+               d[f].out && (np[f] == 0 || d[f].peaks) &&
+               ((uintptr_t)d[f].frame % 16 == 0) && ((uintptr_t)d[f].out % 16 == 0);
+    if (valid[f]) gs[f] = geometry(ps[f], np[f], th_cap);
+  }
+  Layout L = layout(nframes, ps, np, gs, valid);
+  if (need) *need = L.total;
+  if (!ws) return RSZ_OK;
+  if (ws_bytes < L.total) return RSZ_ERR_WORKSPACE;
+  hp.bytes.assign(L.states, 0);
+  FramePlan *fpl = (FramePlan *)hp.bytes.data();
+  uint32_t *tp = (uint32_t *)(hp.bytes.data() + L.prefix);
+  uint32_t *cp = tp + (nframes + 1);
+  uint32_t *rp = cp + (nframes + 1);
+  uint64_t tiles = 0, chunks = 0, roi = 0;
+  hp.common_b = 0;
+  bool first = true;
+  for (uint32_t f = 0; f < nframes; ++f) {
+    FramePlan &fp = fpl[f];
+    memset(&fp, 0, sizeof fp);
+    tp[f] = (uint32_t)tiles;
+    cp[f] = (uint32_t)chunks;
+    rp[f] = (uint32_t)roi;
+    fp.st = (FrameState *)(ws + L.states) + f;
+    fp.res_bytes = res_bytes + f;
+    fp.res_status = res_status + f;
+    if (!valid[f]) {
+      fp.init_status = RSZ_ERR_ARG;
+      continue;
+    }
+    const rsz_params *p = ps[f];
+    const Geom &g = gs[f];
+    fp.P = p->panels;
+    fp.H = p->height;
+    fp.W = p->width;
+    fp.w = p->window;
+    fp.b = p->bin;
+    fp.mode = p->bin_mode;
+    fp.eb = p->eb;
+    fp.step = 2.0 * p->eb;
+    fp.Hb = g.Hb;
+    fp.Wb = g.Wb;
+    fp.nbins = g.nbins;
+    fp.nchunks = g.nchunks;
+    fp.npeaks = np[f];
+    fp.TH = g.TH;
+    fp.segs = g.segs;
+    fp.groups = g.groups;
+    fp.nstrips = g.nstrips;
+    fp.init_status = RSZ_OK;
+    fp.frame = d[f].frame;
+    fp.peaks = (const int32_t *)d[f].peaks;
+    fp.out = (uint8_t *)d[f].out;
+    fp.out_cap = d[f].out_cap;
+    fp.off_roi = g.off_roi;
+    fp.off_lens = g.off_lens;
+    fp.off_oidx = g.off_oidx;
+    uint8_t *base = ws + L.frame_off[f];
+    fp.pstart = (uint32_t *)base;
+    base += align_up(4ull * (p->panels + 1), 256);
+    fp.pcursor = (uint32_t *)base;
+    base += align_up(4ull * p->panels, 256);
+    fp.bucket = (int32_t *)base;
+    base += align_up(12ull * np[f], 256);
+    fp.codes = (uint16_t *)base;
+    base += align_up(2ull * g.nbins, 256);
+    fp.rbuf = (int32_t *)base;
+    base += align_up(4ull * g.nbins, 256);
+    fp.chunk_bits = (uint32_t *)base;
+    base += align_up(4ull * g.nchunks, 256);
+    fp.chunk_nout = (uint32_t *)base;
+    if (dbg) {
+      fp.dbg_mask = dbg->mask;
+      fp.dbg_S = dbg->S;
+      fp.dbg_n = dbg->n;
+      fp.dbg_q = dbg->q;
+    }
+    tiles += (uint64_t)p->panels * g.groups;
+    chunks += g.nchunks;
+    roi += (uint64_t)np[f] * p->window * p->window;
+    if (first) {
+      hp.common_b = p->bin;
+      first = false;
+    } else if (hp.common_b != p->bin) {
+      hp.common_b = 0;
+    }
+  }
+  if (tiles >= (1ull << 31) || chunks >= (1ull << 31) || roi >= (1ull << 32)) return RSZ_ERR_ARG;
+  tp[nframes] = (uint32_t)tiles;
+  cp[nframes] = (uint32_t)chunks;
+  rp[nframes] = (uint32_t)roi;
+  hp.bp.nframes = nframes;
+  hp.bp.total_tiles = (uint32_t)tiles;
+  hp.bp.total_chunks = (uint32_t)chunks;
+  hp.bp.total_roi = (uint32_t)roi;
+  hp.bp.frames = (const FramePlan *)(ws + L.plans);
+  hp.bp.tile_prefix = (const uint32_t *)(ws + L.prefix);
+  hp.bp.chunk_prefix = hp.bp.tile_prefix + (nframes + 1);
+  hp.bp.roi_prefix = hp.bp.chunk_prefix + (nframes + 1);
+  return RSZ_OK;
+}
+
+static uint32_t default_th_cap(uint32_t nframes) { return nframes >= 16 ? kMaxTH : 8; }
+
+// Plans reach the device through a ring of pinned host buffers: a slot is
+// reused only after the event recorded behind its previous copy has fired, so
+// an asynchronous call never reads host memory that has been overwritten.
+namespace {
+struct StageSlot {
+  void *ptr = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+};
+std::mutex g_stage_mu;
+StageSlot g_stage[8];
+unsigned g_stage_next = 0;
+}  // namespace
+
+static int stage_to_device(void *dst, const void *src, size_t n, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  StageSlot &sl = g_stage[g_stage_next++ % 8];
+  if (sl.ev && hipEventSynchronize(sl.ev) != hipSuccess) return RSZ_ERR_HIP;
+  if (sl.cap < n) {
+    if (sl.ptr) (void)hipHostFree(sl.ptr);
+    sl.ptr = nullptr;
+    sl.cap = 0;
+    const size_t cap = std::max<size_t>(align_up(n, 1 << 16), 1 << 16);
+    if (hipHostMalloc(&sl.ptr, cap, hipHostMallocDefault) != hipSuccess) return RSZ_ERR_HIP;
+    sl.cap = cap;
+  }
+  memcpy(sl.ptr, src, n);
+  if (hipMemcpyAsync(dst, sl.ptr, n, hipMemcpyHostToDevice, s) != hipSuccess) return RSZ_ERR_HIP;
+  if (!sl.ev && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess)
+    return RSZ_ERR_HIP;
+  if (hipEventRecord(sl.ev, s) != hipSuccess) return RSZ_ERR_HIP;
+  return RSZ_OK;
+}
+
+// Queue the whole path for a batch; results land in res_bytes/res_status.
+static int enqueue(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_bytes,
+                   int32_t *res_status, void *ws, uint64_t ws_bytes, hipStream_t s,
+                   const rsz_debug_bufs *dbg, bool front_only, HostPlan &hp) {
+  const int st = build_plan(nframes, d, res_bytes, res_status, (uint8_t *)ws, ws_bytes,
+                            default_th_cap(nframes), hp, nullptr, dbg);
+  if (st) return st;
+  if (stage_to_device(ws, hp.bytes.data(), hp.bytes.size(), s) != RSZ_OK) return RSZ_ERR_HIP;
+  if (launch_compress_front_b(hp.bp, hp.common_b, s, dbg != nullptr) != hipSuccess)
+    return RSZ_ERR_HIP;
+  if (!front_only && launch_compress_back(hp.bp, s) != hipSuccess) return RSZ_ERR_HIP;
+  return RSZ_OK;
+}
+
+uint64_t decode_tables_bytes();
+
+// Host parse of a stream header; fills the decode plan geometry.
+static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_params *p,
+                        uint32_t *npeaks, DecodePlan *dp) {
+  if (!h || n < kHeader) return RSZ_ERR_CORRUPT;
+  uint32_t u[20];
+  memcpy(u, h, 80);
+  if (memcmp(h, "RSZ1", 4) != 0 || (u[1] & 0xFFFFu) != 1u) return RSZ_ERR_CORRUPT;
+  rsz_params q;
+  q.bin_mode = u[1] >> 16;
+  q.panels = u[2];
+  q.height = u[3];
+  q.width = u[4];
+  q.window = u[5];
+  q.bin = u[6];
+  memcpy(&q.eb, h + 32, 8);
+  const uint32_t np = u[10];
+  if (check_params(&q, np) != RSZ_OK) return RSZ_ERR_CORRUPT;
+  uint64_t T, total, reserved;
+  memcpy(&T, h + 56, 8);
+  memcpy(&total, h + 64, 8);
+  memcpy(&reserved, h + 72, 8);
+  if (u[7] != (uint32_t)kRadius || u[12] != kChunk || reserved != 0) return RSZ_ERR_CORRUPT;
+  const Geom g = geometry(&q, np, kMaxTH);
+  const uint64_t n_out = u[11];
+  if (u[13] != g.nchunks || n_out > g.nbins || T > 32ull * g.nbins) return RSZ_ERR_CORRUPT;
+  const uint64_t off_ores = g.off_oidx + 4 * n_out;
+  const uint64_t off_chunks = off_ores + 4 * n_out;
+  const uint64_t off_bits = off_chunks + 4ull * g.nchunks;
+  if (off_bits + 4 * ((T + 31) / 32) != total || total > in_bytes) return RSZ_ERR_CORRUPT;
+  if (p) *p = q;
+  if (npeaks) *npeaks = np;
+  if (dp) {
+    memset(dp, 0, sizeof *dp);
+    dp->P = q.panels;
+    dp->H = q.height;
+    dp->W = q.width;
+    dp->w = q.window;
+    dp->b = q.bin;
+    dp->npeaks = np;
+    dp->step = 2.0 * q.eb;
+    dp->Hb = g.Hb;
+    dp->Wb = g.Wb;
+    dp->nbins = g.nbins;
+    dp->nchunks = g.nchunks;
+    dp->n_out = (uint32_t)n_out;
+    dp->T = T;
+    dp->total = total;
+    dp->off_peaks = kHeader;
+    dp->off_roi = g.off_roi;
+    dp->off_lens = g.off_lens;
+    dp->off_oidx = g.off_oidx;
+    dp->off_ores = off_ores;
+    dp->off_chunks = off_chunks;
+    dp->off_bits = off_bits;
+  }
+  return RSZ_OK;
+}
+
+static uint64_t decode_ws_bytes(const DecodePlan &dp) {
+  return align_up(4ull * dp.nbins, 256) + align_up(4ull * dp.nchunks, 256) + 256 +
+         align_up(decode_tables_bytes(), 256);
+}
+
+// Results of a single-frame call live in the workspace tail.
+static uint64_t single_extra() { return 256; }
+
+}  // namespace rsz
+
+using namespace rsz;
+
+extern "C" {
+
+const char *rsz_status_string(int s) {
+  switch (s) {
+    case RSZ_OK: return "ok";
+    case RSZ_ERR_ARG: return "invalid argument";
+    case RSZ_ERR_PEAK: return "peak outside the frame";
+    case RSZ_ERR_RANGE: return "background value out of range";
+    case RSZ_ERR_CAPACITY: return "output buffer too small";
+    case RSZ_ERR_CORRUPT: return "corrupt stream";
+    case RSZ_ERR_WORKSPACE: return "workspace too small";
+    case RSZ_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int rsz_max_compressed_bytes(const rsz_params *p, uint32_t npeaks, uint64_t *bytes) {
+  const int st = check_params(p, npeaks);
+  if (st) return st;
+  if (!bytes) return RSZ_ERR_ARG;
+  *bytes = geometry(p, npeaks, kMaxTH).max_bytes;
+  return RSZ_OK;
+}
+
+static rsz_frame_desc one_desc(const rsz_params *p, const float *frame, const rsz_peak *peaks,
+                               uint32_t npeaks, void *out, uint64_t cap) {
+  rsz_frame_desc d;
+  memset(&d, 0, sizeof d);
+  d.params = *p;
+  d.frame = frame;
+  d.peaks = peaks;
+  d.npeaks = npeaks;
+  d.out = out;
+  d.out_cap = cap;
+  return d;
+}
+
+int rsz_workspace_bytes(const rsz_params *p, uint32_t npeaks, uint64_t *bytes) {
+  const int st = check_params(p, npeaks);
+  if (st) return st;
+  if (!bytes) return RSZ_ERR_ARG;
+  // shapes only: use aligned placeholder pointers
+  rsz_frame_desc d = one_desc(p, (const float *)256, npeaks ? (const rsz_peak *)256 : nullptr,
+                              npeaks, (void *)256, 0);
+  HostPlan hp;
+  uint64_t need = 0;
+  build_plan(1, &d, nullptr, nullptr, nullptr, 0, default_th_cap(1), hp, &need, nullptr);
+  *bytes = need + single_extra();
+  return RSZ_OK;
+}
+
+int rsz_batch_workspace_bytes(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t *bytes) {
+  if (!bytes || nframes == 0 || !h_descs) return RSZ_ERR_ARG;
+  HostPlan hp;
+  uint64_t need = 0;
+  build_plan(nframes, h_descs, nullptr, nullptr, nullptr, 0, default_th_cap(nframes), hp, &need,
+             nullptr);
+  *bytes = need;
+  return RSZ_OK;
+}
+
+static int single_frame(const rsz_params *p, const float *d_frame, const rsz_peak *d_peaks,
+                        uint32_t npeaks, void *d_out, uint64_t out_cap, uint64_t *h_out_bytes,
+                        void *d_ws, uint64_t ws_bytes, hipStream_t s, const rsz_debug_bufs *dbg) {
+  int st = check_params(p, npeaks);
+  if (st) return st;
+  if (!d_frame || !d_ws || (npeaks && !d_peaks) || (!dbg && (!d_out || !h_out_bytes)))
+    return RSZ_ERR_ARG;
+  if ((uintptr_t)d_frame % 16 || (uintptr_t)d_ws % 256 || (d_out && (uintptr_t)d_out % 16))
+    return RSZ_ERR_ARG;
+  uint64_t need = 0;
+  rsz_workspace_bytes(p, npeaks, &need);
+  if (ws_bytes < need) return RSZ_ERR_WORKSPACE;
+  // result slots at the workspace tail
+  uint8_t *tail = (uint8_t *)d_ws + (need - single_extra());
+  uint64_t *res_bytes = (uint64_t *)tail;
+  int32_t *res_status = (int32_t *)(tail + 8);
+  rsz_frame_desc d = one_desc(p, d_frame, d_peaks, npeaks, d_out ? d_out : (void *)d_ws, out_cap);
+  HostPlan hp;
+  st = enqueue(1, &d, res_bytes, res_status, d_ws, need - single_extra(), s, dbg, dbg != nullptr,
+               hp);
+  if (st) return st;
+  if (dbg) {
+    // the codebook intermediates sit in the frame's state and region
+    const FramePlan *fp = (const FramePlan *)hp.bytes.data();
+    const FrameState *fs = fp->st;
+    if (dbg->codes &&
+        hipMemcpyAsync(dbg->codes, fp->codes, 2ull * fp->nbins, hipMemcpyDeviceToDevice, s))
+      return RSZ_ERR_HIP;
+    if (dbg->hist && hipMemcpyAsync(dbg->hist, fs->hist, 4 * kNumSym, hipMemcpyDeviceToDevice, s))
+      return RSZ_ERR_HIP;
+    if (dbg->lens && hipMemcpyAsync(dbg->lens, fs->lens, kNumSym, hipMemcpyDeviceToDevice, s))
+      return RSZ_ERR_HIP;
+    if (dbg->cw && hipMemcpyAsync(dbg->cw, fs->cw, 4 * kNumSym, hipMemcpyDeviceToDevice, s))
+      return RSZ_ERR_HIP;
+    int32_t status = 0;
+    if (hipMemcpyAsync(&status, &fs->status, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return RSZ_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return RSZ_ERR_HIP;
+    return status;
+  }
+  uint64_t res[2] = {0, 0};
+  if (hipMemcpyAsync(res, tail, 16, hipMemcpyDeviceToHost, s) != hipSuccess) return RSZ_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return RSZ_ERR_HIP;
+  const int32_t status = (int32_t)(uint32_t)res[1];
+  if (status == RSZ_OK || status == RSZ_ERR_CAPACITY) *h_out_bytes = res[0];
+  return status;
+}
+
+int rsz_compress(const rsz_params *p, const float *d_frame, const rsz_peak *d_peaks,
+                 uint32_t npeaks, void *d_out, uint64_t out_cap, uint64_t *h_out_bytes,
+                 void *d_ws, uint64_t ws_bytes, void *stream) {
+  return single_frame(p, d_frame, d_peaks, npeaks, d_out, out_cap, h_out_bytes, d_ws, ws_bytes,
+                      (hipStream_t)stream, nullptr);
+}
+
+int rsz_debug_intermediates(const rsz_params *p, const float *d_frame, const rsz_peak *d_peaks,
+                            uint32_t npeaks, const rsz_debug_bufs *bufs, void *d_ws,
+                            uint64_t ws_bytes, void *stream) {
+  if (!bufs) return RSZ_ERR_ARG;
+  return single_frame(p, d_frame, d_peaks, npeaks, nullptr, 0, nullptr, d_ws, ws_bytes,
+                      (hipStream_t)stream, bufs);
+}
+
+int rsz_compress_batch(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t *d_out_bytes,
+                       int32_t *d_status, void *d_ws, uint64_t ws_bytes, void *stream) {
+  if (nframes == 0 || !h_descs || !d_out_bytes || !d_status || !d_ws) return RSZ_ERR_ARG;
+  if ((uintptr_t)d_ws % 256) return RSZ_ERR_ARG;
+  HostPlan hp;
+  return enqueue(nframes, h_descs, d_out_bytes, d_status, d_ws, ws_bytes, (hipStream_t)stream,
+                 nullptr, false, hp);
+}
+
+int rsz_stream_info(const void *h_stream, uint64_t n, rsz_params *p, uint32_t *npeaks,
+                    uint64_t *stream_bytes) {
+  DecodePlan dp;
+  const int st = parse_header((const uint8_t *)h_stream, n, ~0ull, p, npeaks, &dp);
+  if (st) return st;
+  if (dp.total > n && n > kHeader) {
+    // a caller that passes more than the header must pass the whole stream
+    return RSZ_ERR_CORRUPT;
+  }
+  if (stream_bytes) *stream_bytes = dp.total;
+  return RSZ_OK;
+}
+
+int rsz_decompress_workspace_bytes(const void *h_header, uint64_t n, uint64_t *bytes) {
+  DecodePlan dp;
+  const int st = parse_header((const uint8_t *)h_header, n, ~0ull, nullptr, nullptr, &dp);
+  if (st) return st;
+  if (!bytes) return RSZ_ERR_ARG;
+  *bytes = decode_ws_bytes(dp);
+  return RSZ_OK;
+}
+
+int rsz_decompress(const void *d_in, uint64_t in_bytes, float *d_frame, uint64_t frame_elems,
+                   void *d_ws, uint64_t ws_bytes, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (!d_in || !d_frame || !d_ws || (uintptr_t)d_in % 16 || (uintptr_t)d_frame % 16 ||
+      (uintptr_t)d_ws % 256)
+    return RSZ_ERR_ARG;
+  if (in_bytes < kHeader) return RSZ_ERR_CORRUPT;
+  uint8_t hdr[80];
+  if (hipMemcpyAsync(hdr, d_in, 80, hipMemcpyDeviceToHost, s) != hipSuccess) return RSZ_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return RSZ_ERR_HIP;
+  DecodePlan dp;
+  int st = parse_header(hdr, 80, in_bytes, nullptr, nullptr, &dp);
+  if (st) return st;
+  if (frame_elems < (uint64_t)dp.P * dp.H * dp.W) return RSZ_ERR_ARG;
+  if (ws_bytes < decode_ws_bytes(dp)) return RSZ_ERR_WORKSPACE;
+  uint8_t *w = (uint8_t *)d_ws;
+  dp.in = (const uint8_t *)d_in;
+  dp.frame = d_frame;
+  dp.res = (int32_t *)w;
+  w += align_up(4ull * dp.nbins, 256);
+  dp.zcount = (uint32_t *)w;
+  w += align_up(4ull * dp.nchunks, 256);
+  dp.status = (int32_t *)w;
+  w += 256;
+  dp.tables = (uint32_t *)w;
+  if (launch_decompress(dp, s) != hipSuccess) return RSZ_ERR_HIP;
+  int32_t status = 0;
+  if (hipMemcpyAsync(&status, dp.status, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return RSZ_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return RSZ_ERR_HIP;
+  return status;
+}
+
+int rsz_profile_enable(int enable) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto &r : g_prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  g_prof.reserve(1 << 16);
+  g_prof_on = enable != 0;
+  return RSZ_OK;
+}
+
+int rsz_profile_read(rsz_kernel_time *out, int max, int *n) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  std::vector<rsz_kernel_time> acc;
+  for (auto &r : g_prof) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return RSZ_ERR_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return RSZ_ERR_HIP;
+    auto it = std::find_if(acc.begin(), acc.end(),
+                           [&](const rsz_kernel_time &k) { return r.name == k.name; });
+    if (it == acc.end()) {
+      rsz_kernel_time k;
+      memset(&k, 0, sizeof k);
+      strncpy(k.name, r.name.c_str(), sizeof k.name - 1);
+      acc.push_back(k);
+      it = acc.end() - 1;
+    }
+    it->launches++;
+    it->total_ms += ms;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  const int m = std::min<int>((int)acc.size(), max);
+  for (int i = 0; i < m; ++i) out[i] = acc[i];
+  if (n) *n = (int)acc.size();
+  return RSZ_OK;
+}
+
+}  // extern "C"

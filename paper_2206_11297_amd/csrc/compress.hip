@@ -1,0 +1,686 @@
+// compress.hip -- HIP kernels of the ROIBIN-SZ compression path for gfx950.
+//
+// Launch sequence over a batch of frames (one launch per step for the whole
+// batch; every kernel maps its flat work index to a frame with the prefix
+// sums of the batch plan):
+//   k_prep      one workgroup per frame: clear the histogram, check the peaks,
+//               bucket them by panel.
+//   k_bin       fused ROI mask + b x b background binning + prequantisation +
+//               2D Lorenzo + code/outlier + histogram; one wave per segment
+//               of bin rows of a panel, walking it in 64-column strips.
+//   k_codebook  one workgroup per frame: Huffman lengths and canonical codes.
+//   k_chunkbits one workgroup per 4096-symbol chunk: bits and outlier count.
+//   k_scan      one workgroup per frame: chunk offsets, sizes, header.
+//   k_encode    one workgroup per chunk: bit-packing and outlier lists.
+//   k_roi       ROI window payload, bit copies.
+#include <algorithm>
+
+#include "rsz_internal.h"
+
+namespace rsz {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Frame owning flat work item `item`: the largest f with prefix[f] <= item.
+__device__ __forceinline__ uint32_t find_frame(const uint32_t *prefix, uint32_t nframes,
+                                               uint32_t item) {
+  uint32_t lo = 0, hi = nframes;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (prefix[mid] <= item) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int32_t load_status(const FrameState *st) {
+  return __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void set_status(FrameState *st, int32_t code) {
+  atomicCAS(&st->status, (int32_t)RSZ_OK, code);
+}
+
+// Exclusive scan over the 256 threads of a workgroup; `total` gets the sum.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *s_tmp, T &total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_tmp[wave] = x;
+  __syncthreads();
+  T off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const T t = s_tmp[i];
+    if (i < wave) off += t;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return off + x - v;
+}
+
+// ----------------------------------------------------------------- k_prep
+
+__global__ __launch_bounds__(256) void k_prep(BatchPlan bp) {
+  const FramePlan &fp = bp.frames[blockIdx.x];
+  FrameState *st = fp.st;
+  __shared__ int s_bad;
+  __shared__ uint32_t s_tmp[4];
+  for (int i = threadIdx.x; i < kNumSym; i += 256) st->hist[i] = 0;
+  if (threadIdx.x == 0) {
+    s_bad = 0;
+    st->status = fp.init_status;
+    st->n_out = 0;
+    st->T = 0;
+    st->total = 0;
+  }
+  if (fp.init_status != RSZ_OK) return;
+  for (uint32_t p = threadIdx.x; p <= fp.P; p += 256) fp.pstart[p] = 0;
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) {
+    const int32_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
+    if (pa < 0 || (uint32_t)pa >= fp.P || r < 0 || (uint32_t)r >= fp.H || c < 0 ||
+        (uint32_t)c >= fp.W)
+      s_bad = 1;
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (threadIdx.x == 0) st->status = RSZ_ERR_PEAK;
+    return;
+  }
+  for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) atomicAdd(&fp.pstart[fp.peaks[3 * k] + 1], 1u);
+  __threadfence();
+  __syncthreads();
+  // inclusive scan of pstart[1..P] (counts) -> bucket starts
+  uint32_t carry = 0;
+  for (uint32_t base = 1; base <= fp.P; base += 256) {
+    const uint32_t p = base + threadIdx.x;
+    const uint32_t v = p <= fp.P ? __hip_atomic_load(&fp.pstart[p], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<uint32_t>(v, s_tmp, tot);
+    if (p <= fp.P) {
+      fp.pstart[p] = carry + ex + v;
+      fp.pcursor[p - 1] = carry + ex;
+    }
+    carry += tot;
+  }
+  __threadfence();
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) {
+    const int32_t pa = fp.peaks[3 * k];
+    const uint32_t pos = atomicAdd(&fp.pcursor[pa], 1u);
+    fp.bucket[3 * pos] = pa;
+    fp.bucket[3 * pos + 1] = fp.peaks[3 * k + 1];
+    fp.bucket[3 * pos + 2] = fp.peaks[3 * k + 2];
+  }
+}
+
+// ------------------------------------------------------------------ k_bin
+
+// Histogram update with one LDS atomic per distinct code in the wave.
+__device__ __forceinline__ void wave_histogram(uint32_t code, bool valid, uint32_t *hist) {
+  const int lane = threadIdx.x & 63;
+  uint64_t pending = __ballot(valid);
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const uint32_t lc = __builtin_amdgcn_readlane(code, leader);
+    const uint64_t same = __ballot(code == lc) & pending;
+    if (lane == leader) atomicAdd(&hist[lc], (uint32_t)__builtin_popcountll(same));
+    pending &= ~same;
+  }
+}
+
+// Sum, count and quantise one bin.  Pixels are added in raster order to an
+// fp64 accumulator starting at +0.0; masked pixels are skipped in background
+// mode.  q = rint(S / (n * 2eb)); an empty bin gives q = 0.
+template <int BB>
+__device__ __forceinline__ int32_t quant_bin(const float *__restrict__ fr, uint32_t H, uint32_t W,
+                                             int bdyn, uint32_t I, uint32_t J, bool bg,
+                                             const uint32_t *mask, int64_t R0, int64_t C0,
+                                             int wpr, double step, bool &range_err, double &S_out,
+                                             uint32_t &n_out) {
+  const int b = BB ? BB : bdyn;
+  double S = 0.0;
+  uint32_t n = 0;
+#pragma unroll
+  for (int di = 0; di < (BB ? BB : 8); ++di) {
+    if (!BB && di >= b) break;
+    const uint32_t i = I * b + di;
+    if (i >= H) break;
+    const float *row = fr + (size_t)i * W;
+    const uint32_t *mrow = mask + (int64_t)(i - R0) * wpr;
+#pragma unroll
+    for (int dj = 0; dj < (BB ? BB : 8); ++dj) {
+      if (!BB && dj >= b) break;
+      const uint32_t j = J * b + dj;
+      if (j >= W) break;
+      const float x = row[j];
+      if (bg) {
+        const int bit = (int)((int64_t)j - C0);
+        if ((mrow[bit >> 5] >> (bit & 31)) & 1u) continue;
+      }
+      S = S + (double)x;
+      n++;
+    }
+  }
+  S_out = S;
+  n_out = n;
+  if (n == 0) return 0;
+  const double den = (double)n * step;
+  const double t = rint(S / den);
+  if (!(fabs(t) <= kQMax)) {
+    range_err = true;
+    return 0;
+  }
+  return (int32_t)t;
+}
+
+template <int BB, bool DEBUG>
+__device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint32_t *hist,
+                            uint32_t *mask, int32_t (*edge)[kMaxTH + 1]) {
+  const int lane = threadIdx.x & 63;
+  const int b = BB ? BB : (int)fp.b;
+  const uint32_t H = fp.H, W = fp.W, Hb = fp.Hb, Wb = fp.Wb;
+  const uint32_t I0 = seg * fp.TH, I1 = min(I0 + fp.TH, Hb);
+  const int64_t R0 = (int64_t)I0 * b - b;
+  const int mrows = (int)(I1 - I0 + 1) * b;
+  const int wpr = 2 * b;
+  const float *fr = fp.frame + (size_t)p * H * W;
+  const bool bg = fp.mode == RSZ_BIN_BACKGROUND;
+  const uint32_t pk0 = fp.pstart[p], pk1 = fp.pstart[p + 1];
+  const int64_t hw = fp.w / 2, wwin = fp.w;
+  const double step = fp.step;
+  const size_t gbase = (size_t)p * Hb * Wb;
+  uint16_t *codes = fp.codes + gbase;
+  int32_t *rbuf = fp.rbuf + gbase;
+  bool range_err = false;
+  double Sd;
+  uint32_t nd;
+
+  const bool build_mask = bg || (DEBUG && fp.dbg_mask);
+  for (uint32_t s = 0; s < fp.nstrips; ++s) {
+    const int64_t C0 = (int64_t)s * 64 * b;
+    if (build_mask) {
+      for (int i = lane; i < mrows * wpr; i += 64) mask[i] = 0u;
+      wave_sync();
+      for (uint32_t k = pk0 + lane; k < pk1; k += 64) {
+        const int64_t r = fp.bucket[3 * k + 1], c = fp.bucket[3 * k + 2];
+        const int64_t rlo = max(r - hw, max(R0, (int64_t)0));
+        const int64_t rhi = min(r - hw + wwin, min(R0 + mrows, (int64_t)H));
+        const int64_t clo = max(c - hw, max(C0, (int64_t)0));
+        const int64_t chi = min(c - hw + wwin, min(C0 + 64 * b, (int64_t)W));
+        if (rlo >= rhi || clo >= chi) continue;
+        const int b0 = (int)(clo - C0), b1 = (int)(chi - 1 - C0);
+        for (int64_t i = rlo; i < rhi; ++i) {
+          uint32_t *mr = mask + (i - R0) * wpr;
+          for (int wd = b0 >> 5; wd <= (b1 >> 5); ++wd) {
+            const int lo = max(b0 - wd * 32, 0), hi = min(b1 - wd * 32, 31);
+            const uint32_t m = (hi == 31 ? 0xFFFFFFFFu : ((1u << (hi + 1)) - 1u)) & ~((1u << lo) - 1u);
+            atomicOr(&mr[wd], m);
+          }
+        }
+      }
+      wave_sync();
+      if (DEBUG && fp.dbg_mask) {
+        const uint32_t wprg = (W + 31) / 32;
+        const int64_t rs = (int64_t)I0 * b, re = min((int64_t)I1 * b, (int64_t)H);
+        for (int64_t e = lane; e < (re - rs) * wpr; e += 64) {
+          const int64_t i = rs + e / wpr;
+          const int64_t wd = C0 / 32 + e % wpr;
+          if (wd < wprg)
+            fp.dbg_mask[((size_t)p * H + i) * wprg + wd] = mask[(i - R0) * wpr + e % wpr];
+        }
+      }
+    }
+    const uint32_t J = s * 64 + lane;
+    const bool colv = J < Wb;
+    const int cur = s & 1, prv = cur ^ 1;
+    int32_t q_up = 0;
+    if (I0 > 0 && colv)
+      q_up = quant_bin<BB>(fr, H, W, b, I0 - 1, J, bg, mask, R0, C0, wpr, step, range_err, Sd, nd);
+    int32_t e_up = (s > 0 && I0 > 0) ? edge[prv][0] : 0;
+    if (lane == 63) edge[cur][0] = q_up;
+    for (uint32_t I = I0; I < I1; ++I) {
+      int32_t q = 0;
+      if (colv) q = quant_bin<BB>(fr, H, W, b, I, J, bg, mask, R0, C0, wpr, step, range_err, Sd, nd);
+      int32_t ql = __shfl_up(q, 1), qul = __shfl_up(q_up, 1);
+      const int32_t e = (s > 0) ? edge[prv][I - I0 + 1] : 0;
+      if (lane == 0) {
+        ql = e;
+        qul = e_up;
+      }
+      e_up = e;
+      if (lane == 63) edge[cur][I - I0 + 1] = q;
+      const int32_t r = q - q_up - ql + qul;
+      uint32_t code = 0xFFFFu;
+      if (colv) {
+        const size_t g = (size_t)I * Wb + J;
+        code = (r > -kRadius && r < kRadius) ? (uint32_t)(r + kRadius) : 0u;
+        codes[g] = (uint16_t)code;
+        if (code == 0) rbuf[g] = r;
+        if (DEBUG) {
+          if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
+          if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
+          if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
+        }
+      }
+      wave_histogram(code, colv, hist);
+      q_up = q;
+    }
+    wave_sync();
+  }
+  if (range_err) set_status(fp.st, RSZ_ERR_RANGE);
+}
+
+template <int BB, bool DEBUG>
+__global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
+  __shared__ uint32_t s_hist[kNumSym];
+  __shared__ uint32_t s_mask[kWaves][kMaskWords];
+  __shared__ int32_t s_edge[kWaves][2][kMaxTH + 1];
+  const uint32_t f = find_frame(bp.tile_prefix, bp.nframes, blockIdx.x);
+  const FramePlan &fp = bp.frames[f];
+  for (int i = threadIdx.x; i < kNumSym; i += 256) s_hist[i] = 0u;
+  __syncthreads();
+  const int wv = threadIdx.x >> 6;
+  const uint32_t t = blockIdx.x - bp.tile_prefix[f];
+  const uint32_t panel = t / fp.groups, grp = t % fp.groups;
+  const uint32_t seg = grp * kWaves + wv;
+  const bool ok = load_status(fp.st) == RSZ_OK;
+  if (ok && seg < fp.segs) bin_segment<BB, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kNumSym; i += 256)
+    if (s_hist[i]) atomicAdd(&fp.st->hist[i], s_hist[i]);
+}
+
+// ------------------------------------------------------------- k_codebook
+
+__device__ void bitonic_sort_1024(uint64_t *key) {
+  for (uint32_t k = 2; k <= 1024; k <<= 1)
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t t = threadIdx.x; t < 512; t += 256) {
+        const uint32_t i = 2 * t - (t & (j - 1));
+        const uint32_t l = i + j;
+        const bool asc = (i & k) == 0;
+        const uint64_t a = key[i], c = key[l];
+        if ((a > c) == asc) {
+          key[i] = c;
+          key[l] = a;
+        }
+      }
+      __syncthreads();
+    }
+}
+
+// Huffman code lengths by the two-queue method over leaves sorted by
+// (count, symbol), internal nodes in creation order, a leaf taken first on
+// equal weights; lengths above 32 make the counts halve (kept >= 1) and the
+// build repeat.  Then canonical codewords in (length, symbol) order.
+__global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
+  const FramePlan &fp = bp.frames[blockIdx.x];
+  FrameState *st = fp.st;
+  __shared__ uint64_t s_key[kNumSym];
+  __shared__ uint64_t s_w[2 * kNumSym];
+  __shared__ uint64_t s_weight[kNumSym];
+  __shared__ uint16_t s_par[2 * kNumSym];
+  __shared__ uint16_t s_dep[2 * kNumSym];
+  __shared__ uint8_t s_len[kNumSym];
+  __shared__ uint32_t s_blc[kMaxLen + 1];
+  __shared__ uint64_t s_first[kMaxLen + 1];
+  __shared__ uint32_t s_start[kMaxLen + 1];
+  __shared__ int s_nl, s_maxlen, s_ok;
+  if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
+  __syncthreads();
+  if (!s_ok) return;
+  for (int s = threadIdx.x; s < kNumSym; s += 256) {
+    s_weight[s] = st->hist[s];
+    s_len[s] = 0;
+  }
+  __syncthreads();
+  for (;;) {
+    for (int s = threadIdx.x; s < kNumSym; s += 256)
+      s_key[s] = s_weight[s] ? ((s_weight[s] << 10) | (uint64_t)s) : ~0ull;
+    if (threadIdx.x == 0) s_nl = 0;
+    __syncthreads();
+    bitonic_sort_1024(s_key);
+    for (int i = threadIdx.x; i < kNumSym; i += 256)
+      if (s_key[i] != ~0ull && (i == kNumSym - 1 || s_key[i + 1] == ~0ull)) s_nl = i + 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int nl = s_nl;
+      int maxlen = 0;
+      if (nl == 1) {
+        s_dep[0] = 1;
+        maxlen = 1;
+      } else if (nl > 1) {
+        for (int i = 0; i < nl; ++i) s_w[i] = s_key[i] >> 10;
+        int lf = 0, nf = nl, ne = nl;
+        for (int m = 0; m < nl - 1; ++m) {
+          int a, c;
+          if (nf == ne || (lf < nl && s_w[lf] <= s_w[nf])) a = lf++; else a = nf++;
+          if (nf == ne || (lf < nl && s_w[lf] <= s_w[nf])) c = lf++; else c = nf++;
+          s_w[ne] = s_w[a] + s_w[c];
+          s_par[a] = (uint16_t)ne;
+          s_par[c] = (uint16_t)ne;
+          ne++;
+        }
+        s_dep[ne - 1] = 0;
+        for (int v = ne - 2; v >= 0; --v) s_dep[v] = s_dep[s_par[v]] + 1;
+        for (int i = 0; i < nl; ++i) maxlen = max(maxlen, (int)s_dep[i]);
+      }
+      s_maxlen = maxlen;
+    }
+    __syncthreads();
+    if (s_maxlen <= kMaxLen) break;
+    for (int s = threadIdx.x; s < kNumSym; s += 256)
+      if (s_weight[s]) s_weight[s] = (s_weight[s] >> 1) ? (s_weight[s] >> 1) : 1ull;
+    __syncthreads();
+  }
+  const int nl = s_nl;
+  for (int i = threadIdx.x; i < nl; i += 256) s_len[s_key[i] & 1023] = (uint8_t)s_dep[i];
+  if (threadIdx.x <= kMaxLen) s_blc[threadIdx.x] = 0;
+  __syncthreads();
+  for (int s = threadIdx.x; s < kNumSym; s += 256) {
+    const uint32_t L = s_len[s];
+    s_key[s] = L ? (((uint64_t)L << 10) | (uint64_t)s) : ~0ull;
+    if (L) atomicAdd(&s_blc[L], 1u);
+  }
+  __syncthreads();
+  bitonic_sort_1024(s_key);
+  if (threadIdx.x == 0) {
+    uint64_t code = 0;
+    uint32_t start = 0;
+    s_blc[0] = 0;
+    for (int L = 1; L <= kMaxLen; ++L) {
+      code = (code + s_blc[L - 1]) << 1;
+      s_first[L] = code;
+      s_start[L] = start;
+      start += s_blc[L];
+    }
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < kNumSym; s += 256) {
+    st->lens[s] = s_len[s];
+    st->cw[s] = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kNumSym; i += 256) {
+    const uint64_t k = s_key[i];
+    if (k == ~0ull) continue;
+    const uint32_t L = (uint32_t)(k >> 10), s = (uint32_t)(k & 1023);
+    st->cw[s] = (uint32_t)(s_first[L] + (uint64_t)(i - s_start[L]));
+  }
+}
+
+// ------------------------------------------------------------ k_chunkbits
+
+__global__ __launch_bounds__(256) void k_chunkbits(BatchPlan bp) {
+  const uint32_t c = blockIdx.x;
+  const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, c);
+  const FramePlan &fp = bp.frames[f];
+  const FrameState *st = fp.st;
+  __shared__ uint8_t s_len[kNumSym];
+  __shared__ uint64_t s_tmp[4];
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
+  for (int s = threadIdx.x; s < kNumSym; s += 256) s_len[s] = st->lens[s];
+  __syncthreads();
+  if (!s_ok) return;
+  const uint32_t lc = c - bp.chunk_prefix[f];
+  const uint32_t g0 = lc * kChunk + threadIdx.x * 16;
+  uint32_t bits = 0, nout = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t g = g0 + k;
+    if (g < fp.nbins) {
+      const uint32_t code = fp.codes[g];
+      bits += s_len[code];
+      nout += code == 0;
+    }
+  }
+  uint64_t tot;
+  block_exclusive_scan<uint64_t>(((uint64_t)nout << 32) | bits, s_tmp, tot);
+  if (threadIdx.x == 0) {
+    fp.chunk_bits[lc] = (uint32_t)tot;
+    fp.chunk_nout[lc] = (uint32_t)(tot >> 32);
+  }
+}
+
+// ----------------------------------------------------------------- k_scan
+
+__device__ __forceinline__ void put_u32(uint8_t *o, uint64_t off, uint32_t v) {
+  *(uint32_t *)(o + off) = v;
+}
+
+__global__ __launch_bounds__(256) void k_scan(BatchPlan bp) {
+  const FramePlan &fp = bp.frames[blockIdx.x];
+  FrameState *st = fp.st;
+  __shared__ uint64_t s_tmp[4];
+  __shared__ int32_t s_status;
+  if (threadIdx.x == 0) s_status = load_status(st);
+  __syncthreads();
+  if (s_status != RSZ_OK) {
+    if (threadIdx.x == 0) {
+      *fp.res_status = s_status;
+      *fp.res_bytes = 0;
+    }
+    return;
+  }
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < fp.nchunks; base += 256) {
+    const uint32_t c = base + threadIdx.x;
+    const uint64_t v = c < fp.nchunks ? (((uint64_t)fp.chunk_nout[c] << 32) | fp.chunk_bits[c]) : 0;
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan<uint64_t>(v, s_tmp, tot) + carry;
+    if (c < fp.nchunks) {
+      fp.chunk_bits[c] = (uint32_t)ex;
+      fp.chunk_nout[c] = (uint32_t)(ex >> 32);
+    }
+    carry += tot;
+  }
+  const uint64_t T = (uint32_t)carry;
+  const uint32_t n_out = (uint32_t)(carry >> 32);
+  const uint64_t off_ores = fp.off_oidx + 4ull * n_out;
+  const uint64_t off_chunks = off_ores + 4ull * n_out;
+  const uint64_t off_bits = off_chunks + 4ull * fp.nchunks;
+  const uint64_t nwords = (T + 31) / 32;
+  const uint64_t total = off_bits + 4 * nwords;
+  const bool fits = total <= fp.out_cap;
+  if (threadIdx.x == 0) {
+    st->T = T;
+    st->n_out = n_out;
+    st->total = total;
+    st->off_ores = off_ores;
+    st->off_chunks = off_chunks;
+    st->off_bits = off_bits;
+    if (!fits) st->status = RSZ_ERR_CAPACITY;
+    *fp.res_status = fits ? RSZ_OK : RSZ_ERR_CAPACITY;
+    *fp.res_bytes = total;
+  }
+  if (!fits) return;
+  uint8_t *o = fp.out;
+  if (threadIdx.x == 0) {
+    put_u32(o, 0, 0x315A5352u);  // "RSZ1"
+    put_u32(o, 4, 1u | ((fp.mode & 1u) << 16));
+    put_u32(o, 8, fp.P);
+    put_u32(o, 12, fp.H);
+    put_u32(o, 16, fp.W);
+    put_u32(o, 20, fp.w);
+    put_u32(o, 24, fp.b);
+    put_u32(o, 28, (uint32_t)kRadius);
+    const uint64_t ebits = __double_as_longlong(fp.eb);
+    put_u32(o, 32, (uint32_t)ebits);
+    put_u32(o, 36, (uint32_t)(ebits >> 32));
+    put_u32(o, 40, fp.npeaks);
+    put_u32(o, 44, n_out);
+    put_u32(o, 48, kChunk);
+    put_u32(o, 52, fp.nchunks);
+    put_u32(o, 56, (uint32_t)T);
+    put_u32(o, 60, (uint32_t)(T >> 32));
+    put_u32(o, 64, (uint32_t)total);
+    put_u32(o, 68, (uint32_t)(total >> 32));
+    put_u32(o, 72, 0u);
+    put_u32(o, 76, 0u);
+  }
+  // peaks as u16 triples, padded with zeros to 4 bytes
+  uint16_t *pk = (uint16_t *)(o + kHeader);
+  for (uint32_t e = threadIdx.x; e < 3 * fp.npeaks; e += 256) pk[e] = (uint16_t)fp.peaks[e];
+  if (threadIdx.x == 0 && (3 * fp.npeaks) % 2) pk[3 * fp.npeaks] = 0;
+  for (int s = threadIdx.x; s < kNumSym; s += 256) o[fp.off_lens + s] = st->lens[s];
+  uint32_t *co = (uint32_t *)(o + off_chunks);
+  uint32_t *bw = (uint32_t *)(o + off_bits);
+  for (uint32_t c = threadIdx.x; c < fp.nchunks; c += 256) {
+    const uint32_t off = fp.chunk_bits[c];
+    co[c] = off;
+    bw[off >> 5] = 0u;  // chunk boundary words are or-ed by two chunks
+  }
+  if (threadIdx.x == 0 && (T & 31)) bw[T >> 5] = 0u;
+}
+
+// --------------------------------------------------------------- k_encode
+
+__global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
+  const uint32_t c = blockIdx.x;
+  const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, c);
+  const FramePlan &fp = bp.frames[f];
+  const FrameState *st = fp.st;
+  __shared__ uint8_t s_len[kNumSym];
+  __shared__ uint32_t s_cw[kNumSym];
+  __shared__ uint32_t s_words[kChunk + 2];
+  __shared__ uint64_t s_tmp[4];
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
+  for (int s = threadIdx.x; s < kNumSym; s += 256) {
+    s_len[s] = st->lens[s];
+    s_cw[s] = st->cw[s];
+  }
+  __syncthreads();
+  if (!s_ok) return;
+  const uint32_t lc = c - bp.chunk_prefix[f];
+  const uint32_t S0 = fp.chunk_bits[lc];
+  const uint32_t O0 = fp.chunk_nout[lc];
+  const uint32_t g0 = lc * kChunk + threadIdx.x * 16;
+  uint32_t code[16];
+  uint32_t bits = 0, nout = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t g = g0 + k;
+    code[k] = g < fp.nbins ? fp.codes[g] : 0xFFFFu;
+    if (g < fp.nbins) {
+      bits += s_len[code[k]];
+      nout += code[k] == 0;
+    }
+  }
+  uint64_t tot;
+  const uint64_t ex = block_exclusive_scan<uint64_t>(((uint64_t)nout << 32) | bits, s_tmp, tot);
+  const uint32_t clen = (uint32_t)tot;
+  const uint32_t nwords = ((S0 & 31) + clen + 31) >> 5;
+  for (uint32_t k = threadIdx.x; k < nwords; k += 256) s_words[k] = 0u;
+  __syncthreads();
+  uint32_t pos = (S0 & 31) + (uint32_t)ex;
+  uint32_t oi = O0 + (uint32_t)(ex >> 32);
+  uint8_t *o = fp.out;
+  uint32_t *oidx = (uint32_t *)(o + fp.off_oidx);
+  int32_t *ores = (int32_t *)(o + st->off_ores);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (code[k] == 0xFFFFu) continue;
+    const uint32_t L = s_len[code[k]];
+    const uint64_t v = ((uint64_t)s_cw[code[k]] << (64 - L)) >> (pos & 31);
+    atomicOr(&s_words[pos >> 5], (uint32_t)(v >> 32));
+    if ((pos & 31) + L > 32) atomicOr(&s_words[(pos >> 5) + 1], (uint32_t)v);
+    pos += L;
+    if (code[k] == 0) {
+      const uint32_t g = g0 + k;
+      oidx[oi] = g;
+      ores[oi] = fp.rbuf[g];
+      oi++;
+    }
+  }
+  __syncthreads();
+  uint32_t *bw = (uint32_t *)(o + st->off_bits) + (S0 >> 5);
+  const bool part_lo = (S0 & 31) != 0, part_hi = ((S0 + clen) & 31) != 0;
+  for (uint32_t k = threadIdx.x; k < nwords; k += 256) {
+    const uint32_t v = s_words[k];
+    if ((k == 0 && part_lo) || (k == nwords - 1 && part_hi))
+      atomicOr(&bw[k], v);
+    else
+      bw[k] = v;
+  }
+}
+
+// ------------------------------------------------------------------ k_roi
+
+__global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
+  const uint32_t stride = gridDim.x * 256;
+  for (uint32_t e = blockIdx.x * 256 + threadIdx.x; e < bp.total_roi; e += stride) {
+    const uint32_t f = find_frame(bp.roi_prefix, bp.nframes, e);
+    const FramePlan &fp = bp.frames[f];
+    if (load_status(fp.st) != RSZ_OK) continue;
+    const uint32_t le = e - bp.roi_prefix[f];
+    const uint32_t ww = fp.w * fp.w;
+    const uint32_t k = le / ww, rem = le - k * ww;
+    const uint32_t u = rem / fp.w, v = rem - u * fp.w;
+    const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
+    const int64_t h = fp.w / 2;
+    const int64_t i = r - h + u, j = c - h + v;
+    uint32_t bits = 0u;
+    if (pa >= 0 && pa < fp.P && i >= 0 && i < fp.H && j >= 0 && j < fp.W)
+      bits = __float_as_uint(fp.frame[((size_t)pa * fp.H + (size_t)i) * fp.W + (size_t)j]);
+    ((uint32_t *)(fp.out + fp.off_roi))[le] = bits;
+  }
+}
+
+// -------------------------------------------------------------- launchers
+
+#define RSZ_LAUNCH(name, kern, grid, s, ...)                      \
+  do {                                                            \
+    prof_begin(name, s);                                          \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, __VA_ARGS__); \
+    prof_end(s);                                                  \
+    hipError_t e_ = hipGetLastError();                            \
+    if (e_ != hipSuccess) return e_;                              \
+  } while (0)
+
+template <bool DEBUG>
+static hipError_t launch_bin(const BatchPlan &bp, uint32_t b, hipStream_t s) {
+  if (bp.total_tiles == 0) return hipSuccess;
+  switch (b) {
+    case 1: RSZ_LAUNCH("k_bin", (k_bin<1, DEBUG>), bp.total_tiles, s, bp); break;
+    case 2: RSZ_LAUNCH("k_bin", (k_bin<2, DEBUG>), bp.total_tiles, s, bp); break;
+    case 4: RSZ_LAUNCH("k_bin", (k_bin<4, DEBUG>), bp.total_tiles, s, bp); break;
+    default: RSZ_LAUNCH("k_bin", (k_bin<0, DEBUG>), bp.total_tiles, s, bp); break;
+  }
+  return hipSuccess;
+}
+
+// prep + bin + codebook; `b` is the common bin factor of the batch or 0.
+hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t s, bool debug) {
+  RSZ_LAUNCH("k_prep", k_prep, bp.nframes, s, bp);
+  hipError_t e = debug ? launch_bin<true>(bp, b, s) : launch_bin<false>(bp, b, s);
+  if (e != hipSuccess) return e;
+  RSZ_LAUNCH("k_codebook", k_codebook, bp.nframes, s, bp);
+  return hipSuccess;
+}
+
+hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
+  if (bp.total_chunks) RSZ_LAUNCH("k_chunkbits", k_chunkbits, bp.total_chunks, s, bp);
+  RSZ_LAUNCH("k_scan", k_scan, bp.nframes, s, bp);
+  if (bp.total_chunks) RSZ_LAUNCH("k_encode", k_encode, bp.total_chunks, s, bp);
+  if (bp.total_roi) {
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((bp.total_roi + 255) / 256, 1u << 20);
+    RSZ_LAUNCH("k_roi", k_roi, blocks, s, bp);
+  }
+  return hipSuccess;
+}
+
+}  // namespace rsz

@@ -1,0 +1,107 @@
+// rsz_internal.h -- plan structures shared by the host side and the HIP
+// kernels of librsz.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rsz.h"
+
+namespace rsz {
+
+constexpr int kRadius = 512;          // residuals in (-512, 512) get a code
+constexpr int kNumSym = 1024;         // code alphabet; code 0 marks an outlier
+constexpr int kMaxLen = 32;           // longest Huffman codeword
+constexpr uint32_t kChunk = 4096;     // symbols between bitstream sync offsets
+constexpr double kQMax = 268435455.0; // |q| <= 2^28 - 1
+constexpr uint64_t kHeader = 80;
+
+// Binning kernel geometry: 4 independent waves per workgroup, each owning a
+// segment of up to kMaxTH bin rows of one panel and walking it in strips of
+// 64 bin columns.
+constexpr int kWaves = 4;
+constexpr int kMaxTH = 32;
+constexpr int kMaskRowsMax = 72;      // (TH+1)*b raw rows per segment
+constexpr int kMaskWords = 1152;      // per wave: rows * 2b words
+
+inline __host__ __device__ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// Per-frame mutable state in the workspace.
+struct FrameState {
+  int32_t status;
+  uint32_t n_out;
+  uint64_t T;          // bitstream bits
+  uint64_t total;      // stream bytes
+  uint64_t off_ores, off_chunks, off_bits;
+  uint32_t hist[kNumSym];
+  uint32_t cw[kNumSym];
+  uint8_t lens[kNumSym];
+};
+
+// Per-frame constant plan, built on the host and copied to the workspace.
+struct FramePlan {
+  uint32_t P, H, W, w, b, mode;
+  double eb, step;          // step = 2*eb
+  uint32_t Hb, Wb, nbins, nchunks;
+  uint32_t npeaks, TH, segs, groups;   // segments per panel, workgroups per panel
+  uint32_t nstrips;
+  int32_t init_status;      // RSZ_OK or RSZ_ERR_ARG
+  const float *frame;
+  const int32_t *peaks;     // npeaks x (panel,row,col)
+  uint8_t *out;
+  uint64_t out_cap;
+  uint64_t off_roi, off_lens, off_oidx;
+  uint16_t *codes;          // nbins
+  int32_t *rbuf;            // nbins, residual of outlier bins
+  uint32_t *chunk_bits;     // nchunks, then exclusive offsets
+  uint32_t *chunk_nout;     // nchunks, then exclusive offsets
+  uint32_t *pstart;         // P+1 bucket starts of peaks by panel
+  uint32_t *pcursor;        // P scatter cursors
+  int32_t *bucket;          // npeaks x 3, grouped by panel
+  FrameState *st;
+  uint64_t *res_bytes;      // where to report the size (device)
+  int32_t *res_status;      // where to report the status (device)
+  // debug outputs (device, may be null)
+  uint32_t *dbg_mask;
+  double *dbg_S;
+  uint32_t *dbg_n;
+  int32_t *dbg_q;
+};
+
+// Prefix sums over the frames of a batch, for mapping flat work items.
+struct BatchPlan {
+  uint32_t nframes;
+  uint32_t total_tiles, total_chunks, total_roi;
+  const FramePlan *frames;
+  const uint32_t *tile_prefix;   // nframes + 1
+  const uint32_t *chunk_prefix;  // nframes + 1
+  const uint32_t *roi_prefix;    // nframes + 1
+};
+
+// Launchers (compress.hip).
+// k_prep + k_bin + k_codebook; b = common bin factor of the batch, or 0.
+hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t s, bool debug);
+// k_chunkbits + k_scan + k_encode + k_roi.
+hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s);
+
+// Decompression plan and launchers (decompress.hip).
+struct DecodePlan {
+  uint32_t P, H, W, w, b, npeaks;
+  double step;
+  uint32_t Hb, Wb, nbins, nchunks, n_out;
+  uint64_t T, total;
+  uint64_t off_peaks, off_roi, off_lens, off_oidx, off_ores, off_chunks, off_bits;
+  const uint8_t *in;
+  float *frame;
+  int32_t *res;         // nbins
+  uint32_t *zcount;     // nchunks code-0 counts
+  int32_t *status;      // one word
+  uint32_t *tables;     // decode tables
+};
+hipError_t launch_decompress(const DecodePlan &dp, hipStream_t s);
+
+// Kernel timing hooks (api.hip).
+void prof_begin(const char *name, hipStream_t s);
+void prof_end(hipStream_t s);
+
+}  // namespace rsz

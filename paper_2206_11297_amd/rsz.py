@@ -1,0 +1,332 @@
+"""Python binding of librsz (ctypes).  Argument marshalling only: every step of
+the compression path runs in the HIP kernels of librsz.so.
+
+Low-level functions mirror the C ABI names (include/rsz.h) and take raw device
+pointers; the torch helpers below them allocate outputs and workspaces as
+torch tensors on the current device and pass the current HIP stream.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librsz.so")
+
+RSZ_OK, RSZ_ERR_ARG, RSZ_ERR_PEAK, RSZ_ERR_RANGE = 0, -1, -2, -3
+RSZ_ERR_CAPACITY, RSZ_ERR_CORRUPT, RSZ_ERR_WORKSPACE, RSZ_ERR_HIP = -4, -5, -6, -7
+RSZ_BIN_BACKGROUND, RSZ_BIN_ALL = 0, 1
+
+EXPORTS = ["rsz_status_string", "rsz_max_compressed_bytes", "rsz_workspace_bytes",
+           "rsz_compress", "rsz_batch_workspace_bytes", "rsz_compress_batch",
+           "rsz_stream_info", "rsz_decompress_workspace_bytes", "rsz_decompress",
+           "rsz_debug_intermediates", "rsz_profile_enable", "rsz_profile_read"]
+
+
+class RszError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class rsz_params(C.Structure):
+    _fields_ = [("panels", C.c_uint32), ("height", C.c_uint32), ("width", C.c_uint32),
+                ("window", C.c_uint32), ("bin", C.c_uint32), ("bin_mode", C.c_uint32),
+                ("eb", C.c_double)]
+
+
+class rsz_frame_desc(C.Structure):
+    _fields_ = [("params", rsz_params), ("frame", C.c_void_p), ("peaks", C.c_void_p),
+                ("npeaks", C.c_uint32), ("reserved", C.c_uint32), ("out", C.c_void_p),
+                ("out_cap", C.c_uint64)]
+
+
+class rsz_debug_bufs(C.Structure):
+    _fields_ = [("mask", C.c_void_p), ("S", C.c_void_p), ("n", C.c_void_p), ("q", C.c_void_p),
+                ("codes", C.c_void_p), ("hist", C.c_void_p), ("lens", C.c_void_p),
+                ("cw", C.c_void_p)]
+
+
+class rsz_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_uint32), ("total_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librsz.so; fails loudly when the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing: run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, vp, u32, u64 = C.POINTER, C.c_void_p, C.c_uint32, C.c_uint64
+        L.rsz_status_string.restype = C.c_char_p
+        L.rsz_status_string.argtypes = [C.c_int]
+        L.rsz_max_compressed_bytes.argtypes = [P(rsz_params), u32, P(u64)]
+        L.rsz_workspace_bytes.argtypes = [P(rsz_params), u32, P(u64)]
+        L.rsz_compress.argtypes = [P(rsz_params), vp, vp, u32, vp, u64, P(u64), vp, u64, vp]
+        L.rsz_batch_workspace_bytes.argtypes = [u32, P(rsz_frame_desc), P(u64)]
+        L.rsz_compress_batch.argtypes = [u32, P(rsz_frame_desc), vp, vp, vp, u64, vp]
+        L.rsz_stream_info.argtypes = [vp, u64, P(rsz_params), P(u32), P(u64)]
+        L.rsz_decompress_workspace_bytes.argtypes = [vp, u64, P(u64)]
+        L.rsz_decompress.argtypes = [vp, u64, vp, u64, vp, u64, vp]
+        L.rsz_debug_intermediates.argtypes = [P(rsz_params), vp, vp, u32, P(rsz_debug_bufs), vp,
+                                              u64, vp]
+        L.rsz_profile_enable.argtypes = [C.c_int]
+        L.rsz_profile_read.argtypes = [P(rsz_kernel_time), C.c_int, P(C.c_int)]
+        _lib = L
+    return _lib
+
+
+def status_string(status):
+    return lib().rsz_status_string(int(status)).decode()
+
+
+def params(panels, height, width, window, bin, eb, bin_mode=RSZ_BIN_BACKGROUND):
+    return rsz_params(panels, height, width, window, bin, bin_mode, float(eb))
+
+
+# ------------------------------------------------------------ C ABI mirrors
+
+
+def rsz_max_compressed_bytes(p, npeaks):
+    out = C.c_uint64(0)
+    st = lib().rsz_max_compressed_bytes(C.byref(p), npeaks, C.byref(out))
+    return st, out.value
+
+
+def rsz_workspace_bytes(p, npeaks):
+    out = C.c_uint64(0)
+    st = lib().rsz_workspace_bytes(C.byref(p), npeaks, C.byref(out))
+    return st, out.value
+
+
+def rsz_compress(p, d_frame, d_peaks, npeaks, d_out, out_cap, d_ws, ws_bytes, stream):
+    nbytes = C.c_uint64(0)
+    st = lib().rsz_compress(C.byref(p), d_frame, d_peaks, npeaks, d_out, out_cap,
+                            C.byref(nbytes), d_ws, ws_bytes, stream)
+    return st, nbytes.value
+
+
+def rsz_batch_workspace_bytes(descs):
+    arr = (rsz_frame_desc * len(descs))(*descs)
+    out = C.c_uint64(0)
+    st = lib().rsz_batch_workspace_bytes(len(descs), arr, C.byref(out))
+    return st, out.value
+
+
+def rsz_compress_batch(descs, d_out_bytes, d_status, d_ws, ws_bytes, stream):
+    arr = (rsz_frame_desc * len(descs))(*descs)
+    return lib().rsz_compress_batch(len(descs), arr, d_out_bytes, d_status, d_ws, ws_bytes,
+                                    stream)
+
+
+def rsz_stream_info(h_bytes):
+    buf = bytes(h_bytes)
+    p = rsz_params()
+    npk = C.c_uint32(0)
+    total = C.c_uint64(0)
+    st = lib().rsz_stream_info(buf, len(buf), C.byref(p), C.byref(npk), C.byref(total))
+    return st, p, npk.value, total.value
+
+
+def rsz_decompress_workspace_bytes(h_header):
+    buf = bytes(h_header)
+    out = C.c_uint64(0)
+    st = lib().rsz_decompress_workspace_bytes(buf, len(buf), C.byref(out))
+    return st, out.value
+
+
+def rsz_decompress(d_in, in_bytes, d_frame, frame_elems, d_ws, ws_bytes, stream):
+    return lib().rsz_decompress(d_in, in_bytes, d_frame, frame_elems, d_ws, ws_bytes, stream)
+
+
+def rsz_debug_intermediates(p, d_frame, d_peaks, npeaks, bufs, d_ws, ws_bytes, stream):
+    return lib().rsz_debug_intermediates(C.byref(p), d_frame, d_peaks, npeaks, C.byref(bufs),
+                                         d_ws, ws_bytes, stream)
+
+
+def rsz_profile_enable(on):
+    return lib().rsz_profile_enable(1 if on else 0)
+
+
+def rsz_profile_read(max_entries=64):
+    arr = (rsz_kernel_time * max_entries)()
+    n = C.c_int(0)
+    st = lib().rsz_profile_read(arr, max_entries, C.byref(n))
+    if st:
+        raise RszError(st, "rsz_profile_read")
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms)
+            for i in range(min(n.value, max_entries))}
+
+
+# ------------------------------------------------------------ torch helpers
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_frame(frame, peaks):
+    torch = _torch()
+    if not frame.is_cuda or frame.dtype != torch.float32 or frame.dim() != 3:
+        raise ValueError("frame must be a float32 [panels, height, width] GPU tensor")
+    frame = frame.contiguous()
+    if peaks is None:
+        peaks = torch.zeros((0, 3), dtype=torch.int32, device=frame.device)
+    peaks = peaks.to(device=frame.device, dtype=torch.int32).reshape(-1, 3).contiguous()
+    return frame, peaks
+
+
+def workspace(nbytes, device=None):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def compress(frame, peaks, window=17, bin=2, eb=10.0, bin_mode=RSZ_BIN_BACKGROUND, out=None,
+             ws=None):
+    """Compress one GPU frame; returns the stream as a uint8 GPU tensor."""
+    torch = _torch()
+    frame, peaks = _check_frame(frame, peaks)
+    P, H, W = frame.shape
+    p = params(P, H, W, window, bin, eb, bin_mode)
+    npk = peaks.shape[0]
+    st, cap = rsz_max_compressed_bytes(p, npk)
+    if st:
+        raise RszError(st, "rsz_max_compressed_bytes")
+    st, wsb = rsz_workspace_bytes(p, npk)
+    if st:
+        raise RszError(st, "rsz_workspace_bytes")
+    if out is None:
+        out = torch.empty(cap, dtype=torch.uint8, device=frame.device)
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, frame.device)
+    st, nbytes = rsz_compress(p, _ptr(frame), _ptr(peaks) if npk else None, npk, _ptr(out),
+                              out.numel(), _ptr(ws), ws.numel(), _stream())
+    if st:
+        raise RszError(st, "rsz_compress")
+    return out[:nbytes]
+
+
+def decompress(stream, ws=None):
+    """Decompress a uint8 GPU stream; returns the float32 [P,H,W] GPU frame."""
+    torch = _torch()
+    stream = stream.contiguous()
+    if stream.data_ptr() % 16:
+        stream = stream.clone()
+    head = stream[:80].cpu().numpy().tobytes()
+    st, p, _, total = rsz_stream_info(head)
+    if st:
+        raise RszError(st, "rsz_stream_info")
+    st, wsb = rsz_decompress_workspace_bytes(head)
+    if st:
+        raise RszError(st, "rsz_decompress_workspace_bytes")
+    frame = torch.empty((p.panels, p.height, p.width), dtype=torch.float32, device=stream.device)
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, stream.device)
+    st = rsz_decompress(_ptr(stream), stream.numel(), _ptr(frame), frame.numel(), _ptr(ws),
+                        ws.numel(), _stream())
+    if st:
+        raise RszError(st, "rsz_decompress")
+    return frame
+
+
+def debug_intermediates(frame, peaks, window=17, bin=2, eb=10.0, bin_mode=RSZ_BIN_BACKGROUND):
+    """All intermediates of compressing one frame as GPU tensors (dict)."""
+    torch = _torch()
+    frame, peaks = _check_frame(frame, peaks)
+    P, H, W = frame.shape
+    p = params(P, H, W, window, bin, eb, bin_mode)
+    npk = peaks.shape[0]
+    Hb, Wb = -(-H // bin), -(-W // bin)
+    nb = P * Hb * Wb
+    dev = frame.device
+    d = dict(mask=torch.zeros((P, H, -(-W // 32)), dtype=torch.int32, device=dev),
+             S=torch.zeros(nb, dtype=torch.float64, device=dev),
+             n=torch.zeros(nb, dtype=torch.int32, device=dev),
+             q=torch.zeros(nb, dtype=torch.int32, device=dev),
+             codes=torch.zeros(nb, dtype=torch.int16, device=dev),
+             hist=torch.zeros(1024, dtype=torch.int32, device=dev),
+             lens=torch.zeros(1024, dtype=torch.uint8, device=dev),
+             cw=torch.zeros(1024, dtype=torch.int32, device=dev))
+    bufs = rsz_debug_bufs(*[d[k].data_ptr() for k in
+                            ("mask", "S", "n", "q", "codes", "hist", "lens", "cw")])
+    st, wsb = rsz_workspace_bytes(p, npk)
+    if st:
+        raise RszError(st, "rsz_workspace_bytes")
+    ws = workspace(wsb, dev)
+    st = rsz_debug_intermediates(p, _ptr(frame), _ptr(peaks) if npk else None, npk, bufs,
+                                 _ptr(ws), ws.numel(), _stream())
+    d["status"] = st
+    return d
+
+
+class Batch:
+    """Descriptors, output buffers and workspace for one batched launch.
+
+    frames: list of float32 [P,H,W] GPU tensors; peaks: list of int32 [n,3]
+    GPU tensors; params: list of (window, bin, eb, bin_mode) per frame or one
+    tuple for all.  Output buffers are sized by rsz_max_compressed_bytes and
+    packed into one uint8 tensor."""
+
+    def __init__(self, frames, peaks, prm):
+        torch = _torch()
+        self.frames = [f.contiguous() for f in frames]
+        self.peaks = [pk.to(dtype=torch.int32).reshape(-1, 3).contiguous() for pk in peaks]
+        n = len(self.frames)
+        prm = prm if isinstance(prm, list) else [prm] * n
+        self.params = []
+        caps = []
+        for f, pk, (w, b, eb, mode) in zip(self.frames, self.peaks, prm):
+            P, H, W = f.shape
+            p = params(P, H, W, w, b, eb, mode)
+            st, cap = rsz_max_compressed_bytes(p, pk.shape[0])
+            if st:
+                raise RszError(st, "rsz_max_compressed_bytes")
+            self.params.append(p)
+            caps.append((cap + 255) // 256 * 256)
+        dev = self.frames[0].device
+        self.offsets = [0]
+        for c in caps:
+            self.offsets.append(self.offsets[-1] + c)
+        self.out = torch.empty(self.offsets[-1], dtype=torch.uint8, device=dev)
+        self.caps = caps
+        self.descs = []
+        for i in range(n):
+            d = rsz_frame_desc()
+            d.params = self.params[i]
+            d.frame = self.frames[i].data_ptr()
+            d.peaks = self.peaks[i].data_ptr() if self.peaks[i].shape[0] else None
+            d.npeaks = self.peaks[i].shape[0]
+            d.reserved = 0
+            d.out = self.out.data_ptr() + self.offsets[i]
+            d.out_cap = caps[i]
+            self.descs.append(d)
+        st, wsb = rsz_batch_workspace_bytes(self.descs)
+        if st:
+            raise RszError(st, "rsz_batch_workspace_bytes")
+        self.ws = workspace(wsb, dev)
+        self.sizes = torch.zeros(n, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(n, dtype=torch.int32, device=dev)
+
+    def run(self):
+        """Queue one batched compression on the current stream (asynchronous)."""
+        st = rsz_compress_batch(self.descs, _ptr(self.sizes), _ptr(self.status), _ptr(self.ws),
+                                self.ws.numel(), _stream())
+        if st:
+            raise RszError(st, "rsz_compress_batch")
+
+    def stream(self, i, sizes=None):
+        """Stream of frame i as a GPU uint8 view (after the stream finished)."""
+        n = int(self.sizes[i]) if sizes is None else int(sizes[i])
+        return self.out[self.offsets[i]:self.offsets[i] + n]

@@ -1,0 +1,99 @@
+"""The C-ABI library loads and exports every symbol include/rsz.h declares, and
+its host-only entry points (sizes, stream header checks, argument checks)
+behave as documented.  No GPU work is launched here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import rsz_oracle as O
+from paper_2206_11297_amd import rsz, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "rsz.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsz_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_names():
+    assert _declared_functions() == sorted(rsz.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.CDLL(rsz.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    for s in range(-7, 1):
+        assert rsz.status_string(s) != "unknown status"
+
+
+@pytest.mark.parametrize("shape,w,b,npk", [((32, 185, 388), 17, 2, 60), ((8, 512, 1024), 25, 4, 800),
+                                           ((1, 1, 1), 1, 1, 1), ((2, 9, 7), 3, 3, 5)])
+def test_max_bytes_matches_oracle(shape, w, b, npk):
+    p = rsz.params(*shape, w, b, 10.0)
+    st, n = rsz.rsz_max_compressed_bytes(p, npk)
+    sto, no = O.max_bytes(O.params(*shape, w, b, 10.0), npk)
+    assert st == 0 and sto == 0 and n == no
+    st, ws = rsz.rsz_workspace_bytes(p, npk)
+    assert st == 0 and ws > 0
+
+
+@pytest.mark.parametrize("bad", [dict(panels=0), dict(height=70000), dict(window=0),
+                                 dict(window=1024), dict(bin=0), dict(bin=9), dict(eb=0.0),
+                                 dict(eb=float("inf")), dict(eb=float("nan")), dict(bin_mode=2),
+                                 dict(panels=65535, height=65535, width=2)])
+def test_bad_params_rejected(bad):
+    kw = dict(panels=2, height=8, width=8, window=3, bin=2, eb=1.0, bin_mode=0)
+    kw.update(bad)
+    p = rsz.params(**kw)
+    assert rsz.rsz_max_compressed_bytes(p, 1)[0] == rsz.RSZ_ERR_ARG
+    assert rsz.rsz_workspace_bytes(p, 1)[0] == rsz.RSZ_ERR_ARG
+    assert rsz.rsz_compress(p, None, None, 0, None, 0, None, 0, None)[0] == rsz.RSZ_ERR_ARG
+
+
+def test_compress_rejects_null_and_misaligned_pointers_before_any_gpu_work():
+    p = rsz.params(2, 8, 8, 3, 2, 1.0)
+    st, _ = rsz.rsz_compress(p, None, None, 0, C.c_void_p(4096), 1 << 20, C.c_void_p(4096),
+                             1 << 20, None)
+    assert st == rsz.RSZ_ERR_ARG
+    st, _ = rsz.rsz_compress(p, C.c_void_p(4100), None, 0, C.c_void_p(4096), 1 << 20,
+                             C.c_void_p(4096), 1 << 20, None)
+    assert st == rsz.RSZ_ERR_ARG
+    st, _ = rsz.rsz_compress(p, C.c_void_p(4096), None, 0, C.c_void_p(4096), 1 << 20,
+                             C.c_void_p(4096), 16, None)
+    assert st == rsz.RSZ_ERR_WORKSPACE
+
+
+def test_stream_info_agrees_with_oracle_streams():
+    for eb in (1.0, 10.0):
+        f, pk = synth.cspad_frame(2)
+        st, s, n = O.compress(O.params(32, 185, 388, 17, 2, eb), f, pk)
+        st, p, npk, total = rsz.rsz_stream_info(s.tobytes()[:80])
+        assert st == 0 and total == n and npk == pk.shape[0]
+        assert (p.panels, p.height, p.width, p.window, p.bin, p.bin_mode, p.eb) == \
+            (32, 185, 388, 17, 2, 0, eb)
+        assert rsz.rsz_stream_info(s.tobytes())[0] == 0
+        assert rsz.rsz_stream_info(s.tobytes()[:-4])[0] == rsz.RSZ_ERR_CORRUPT
+        st, wsb = rsz.rsz_decompress_workspace_bytes(s.tobytes()[:80])
+        assert st == 0 and wsb >= 4 * 32 * 93 * 194
+
+
+def test_stream_info_rejects_bad_headers_like_the_oracle():
+    f, pk = synth.tiny_case(21, (2, 9, 11), 3, "normal", scale=100.0)
+    st, s, n = O.compress(O.params(2, 9, 11, 3, 2, 1.0), f, pk)
+    rng = np.random.default_rng(3)
+    for t in range(400):
+        s2 = s.copy()
+        pos = int(rng.integers(0, 80))
+        s2[pos] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        a = rsz.rsz_stream_info(s2.tobytes())[0]
+        b = O.stream_info(s2)[0]
+        assert (a == 0) == (b == 0), pos

@@ -420,3 +420,25 @@ def test_generators_are_reproducible():
     f, pk = synth.jungfrau_frame(1)
     assert f.shape == (8, 512, 1024) and 20 <= pk.shape[0] <= 800
     assert pk[:, 0].max() < 8 and pk[:, 1].max() < 512 and pk[:, 2].max() < 1024
+
+
+def test_overlapping_windows_must_agree():
+    """Two windows sharing a pixel copy the same frame value (Sec. IV): a
+    stream whose payloads disagree there is malformed."""
+    frame, _ = synth.tiny_case(15, (1, 12, 12), 0, "normal")
+    peaks = np.array([[0, 5, 5], [0, 6, 6]], np.int32)   # 3x3 windows overlap
+    p = O.params(1, 12, 12, 3, 2, 1.0, 0)
+    st, s, _ = O.compress(p, frame, peaks)
+    assert O.decompress(s)[0] == O.OK
+    hdr = F.parse(s)
+    roi = hdr["off"]["roi"]
+    # window 0 entry (u=2, v=2) is pixel (6,6), also window 1 entry (1,1)
+    k0 = roi + 4 * (0 * 9 + 2 * 3 + 2)
+    s2 = s.copy()
+    s2[k0] ^= 1
+    assert O.decompress(s2)[0] == O.ERR_CORRUPT
+    # a non-shared entry may change freely: pixel (4,4) is only in window 0
+    s3 = s.copy()
+    s3[roi] ^= 1
+    st, y = O.decompress(s3)
+    assert st == O.OK and y.view(np.uint32)[0, 4, 4] == frame.view(np.uint32)[0, 4, 4] ^ 1
