@@ -1,0 +1,185 @@
+"""Benchmark of the ROIBIN-SZ compression path on one MI355X.
+
+Workload: a batch of 1000 CSPAD-geometry frames (32 x 185 x 388 float32,
+seeded synthetic: Gaussian noise, water ring, Bragg peaks with Poisson(60)
+counts and 20% non-hit frames), ROI window 17, 2x2 binning, absolute error
+bound 10 ADU.  One step = one batched compression of all 1000 frames (every
+kernel of the path, one launch each); frames are resident in HBM before the
+timed region.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "cspad-batch"
+NFRAMES = 1000
+SHAPE = (32, 185, 388)
+WINDOW, BIN, EB = 17, 2, 10.0
+
+
+def _gen(i):
+    from paper_2206_11297_amd import synth
+    counts = synth.batch_peak_counts(NFRAMES)
+    return synth.batch_frame(i, counts)
+
+
+def generate(n, workers):
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    if workers <= 1:
+        for i in range(n):
+            yield _gen(i)
+        return
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+        for item in ex.map(_gen, range(n), chunksize=4):
+            yield item
+
+
+def traffic_record(kernel):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{WORKLOAD}_traffic.json")
+    src = os.path.join(ROOT, "paper_2206_11297_amd", "csrc", "compress.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("compress_hip_sha256") != sha:
+        return None
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=NFRAMES)
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--latency-frames", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the compression path is not sharded "
+              "across GPUs (frames are independent; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    # frames are drawn before the GPU is touched (fork-safe worker pool)
+    t0 = time.time()
+    host = list(generate(args.frames, args.workers))
+    gen_s = time.time() - t0
+    print(f"[bench] generated {len(host)} frames in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_2206_11297_amd import rsz
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    frames = [torch.from_numpy(f).to(dev) for f, _ in host]
+    peaks = [torch.from_numpy(p).to(dev) for _, p in host]
+    torch.cuda.synchronize()
+    B = rsz.Batch(frames, peaks, (WINDOW, BIN, EB, rsz.RSZ_BIN_BACKGROUND))
+    raw_bytes = sum(f.numel() * 4 for f in frames)
+    npix = raw_bytes // 4
+
+    for _ in range(args.warmup):
+        B.run()
+    torch.cuda.synchronize()
+    st = B.status.cpu().numpy()
+    assert (st == 0).all(), f"compression failed: statuses {set(st.tolist())}"
+
+    rsz.rsz_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = rsz.rsz_profile_read()
+    rsz.rsz_profile_enable(False)
+    ms_step = elapsed * 1e3 / args.steps
+    gbps = raw_bytes / (elapsed / args.steps) / 1e9
+
+    sizes = B.sizes.cpu().numpy().astype(np.int64)
+    cr_u16 = (npix // len(frames)) * 2 / sizes
+    kernel_ms = {k: v[1] / v[0] for k, v in prof.items()}
+    kb_ms = kernel_ms["k_bin"]
+    achieved = raw_bytes / (kb_ms * 1e-3) / 1e9
+    tr = traffic_record("k_bin")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 4),
+            "traffic": None if tr is None else tr["hbm_bytes_per_launch"],
+            "kernel": "k_bin", "algorithmic_bytes_per_launch": raw_bytes,
+            "avg_launch_ms": round(kb_ms, 4)}
+
+    # one-frame-per-launch latency at the same bound (synchronous calls)
+    lat = []
+    p1 = rsz.params(*SHAPE, WINDOW, BIN, EB)
+    stc, cap = rsz.rsz_max_compressed_bytes(p1, 1000)
+    out1 = torch.empty(cap, dtype=torch.uint8, device=dev)
+    ws1 = rsz.workspace(rsz.rsz_workspace_bytes(p1, 1000)[1], dev)
+    s = rsz._stream()
+    for i in range(min(args.latency_frames, len(frames))):
+        pk = peaks[i]
+        npk = pk.shape[0]
+        a = time.perf_counter()
+        st1, n1 = rsz.rsz_compress(p1, rsz._ptr(frames[i]), rsz._ptr(pk) if npk else None, npk,
+                                   rsz._ptr(out1), cap, rsz._ptr(ws1), ws1.numel(), s)
+        lat.append(time.perf_counter() - a)
+        assert st1 == 0 and n1 == sizes[i]
+    lat_ms = np.array(lat) * 1e3
+
+    # CPU baseline: the oracle, single-threaded, on the first frames for a
+    # bounded time; its streams must equal the GPU streams byte for byte
+    from oracle import rsz_oracle as O
+    po = O.params(*SHAPE, WINDOW, BIN, EB, 0)
+    out_host = B.out.cpu().numpy()
+    n_cpu, cpu_t, parity = 0, 0.0, True
+    while n_cpu < len(host) and cpu_t < args.cpu_seconds:
+        f, pk = host[n_cpu]
+        a = time.perf_counter()
+        sto, ref, nb = O.compress(po, f, pk)
+        cpu_t += time.perf_counter() - a
+        got = out_host[B.offsets[n_cpu]:B.offsets[n_cpu] + int(sizes[n_cpu])]
+        parity &= sto == 0 and np.array_equal(got, ref)
+        n_cpu += 1
+    cpu_gbps = n_cpu * SHAPE[0] * SHAPE[1] * SHAPE[2] * 4 / cpu_t / 1e9
+
+    line = {
+        "metric": "raw-frame GB/s compressed (1 GPU) at eb=10 ADU; compression ratio; "
+                  "p99 frame latency",
+        "value": round(gbps, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD}-{len(frames)}: {len(frames)} frames "
+                               f"{SHAPE[0]}x{SHAPE[1]}x{SHAPE[2]} f32, Poisson(60) peaks, "
+                               "20% non-hit, window 17, bin 2x2, eb 10 ADU, one batched launch",
+                   "frames": len(frames), "raw_bytes": raw_bytes},
+        "roofline": roof,
+        "cpu_baseline": {"value": round(cpu_gbps, 4), "unit": "GB/s", "cores": 1,
+                         "kind": "oracle",
+                         "sample": f"first {n_cpu} frames of the batch, single thread, "
+                                   f"{cpu_t:.1f}s", "streams_equal_gpu": bool(parity)},
+        "compression_ratio_u16": {"mean": round(float(cr_u16.mean()), 3),
+                                  "min": round(float(cr_u16.min()), 3),
+                                  "max": round(float(cr_u16.max()), 3),
+                                  "aggregate": round(float(npix * 2 / sizes.sum()), 3)},
+        "compression_ratio_f32_aggregate": round(float(npix * 4 / sizes.sum()), 3),
+        "latency_ms": {"one_frame_per_launch_p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "one_frame_per_launch_p99": round(float(np.percentile(lat_ms, 99)), 4),
+                       "batched_all_frames": round(ms_step, 4)},
+        "kernel_ms": {k: round(v, 4) for k, v in kernel_ms.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
