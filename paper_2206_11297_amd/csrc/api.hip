@@ -192,6 +192,10 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.groups = g.groups;
     fp.nstrips = g.nstrips;
     fp.init_status = RSZ_OK;
+    fp.vec = (p->bin == 2 || p->bin == 4) && p->width % p->bin == 0 &&
+             (uintptr_t)d[f].frame % (4 * p->bin) == 0;
+    fp.inv[0] = 0.0;
+    for (uint32_t n = 1; n <= 64; ++n) fp.inv[n] = 1.0 / ((double)n * fp.step);
     fp.frame = d[f].frame;
     fp.peaks = (const int32_t *)d[f].peaks;
     fp.out = (uint8_t *)d[f].out;

@@ -127,10 +127,13 @@ __global__ __launch_bounds__(256) void k_prep(BatchPlan bp) {
 
 // ------------------------------------------------------------------ k_bin
 
-// Histogram update with one LDS atomic per distinct code in the wave.
-__device__ __forceinline__ void wave_histogram(uint32_t code, bool valid, uint32_t *hist) {
+// Histogram update with one LDS atomic per distinct code in the wave; the
+// zero-residual code 512 is counted per lane and added once at the end.
+__device__ __forceinline__ void wave_histogram(uint32_t code, bool valid, uint32_t *hist,
+                                               uint32_t &c512) {
   const int lane = threadIdx.x & 63;
-  uint64_t pending = __ballot(valid);
+  c512 += (valid && code == (uint32_t)kRadius) ? 1u : 0u;
+  uint64_t pending = __ballot(valid && code != (uint32_t)kRadius);
   while (pending) {
     const int leader = __builtin_ctzll(pending);
     const uint32_t lc = __builtin_amdgcn_readlane(code, leader);
@@ -140,44 +143,29 @@ __device__ __forceinline__ void wave_histogram(uint32_t code, bool valid, uint32
   }
 }
 
-// Sum, count and quantise one bin.  Pixels are added in raster order to an
-// fp64 accumulator starting at +0.0; masked pixels are skipped in background
-// mode.  q = rint(S / (n * 2eb)); an empty bin gives q = 0.
-template <int BB>
-__device__ __forceinline__ int32_t quant_bin(const float *__restrict__ fr, uint32_t H, uint32_t W,
-                                             int bdyn, uint32_t I, uint32_t J, bool bg,
-                                             const uint32_t *mask, int64_t R0, int64_t C0,
-                                             int wpr, double step, bool &range_err, double &S_out,
-                                             uint32_t &n_out) {
-  const int b = BB ? BB : bdyn;
-  double S = 0.0;
-  uint32_t n = 0;
-#pragma unroll
-  for (int di = 0; di < (BB ? BB : 8); ++di) {
-    if (!BB && di >= b) break;
-    const uint32_t i = I * b + di;
-    if (i >= H) break;
-    const float *row = fr + (size_t)i * W;
-    const uint32_t *mrow = mask + (int64_t)(i - R0) * wpr;
-#pragma unroll
-    for (int dj = 0; dj < (BB ? BB : 8); ++dj) {
-      if (!BB && dj >= b) break;
-      const uint32_t j = J * b + dj;
-      if (j >= W) break;
-      const float x = row[j];
-      if (bg) {
-        const int bit = (int)((int64_t)j - C0);
-        if ((mrow[bit >> 5] >> (bit & 31)) & 1u) continue;
-      }
-      S = S + (double)x;
-      n++;
-    }
-  }
-  S_out = S;
-  n_out = n;
+// Value of lane-1 (lane 0 gets `first`): the left neighbour along a row.
+__device__ __forceinline__ int32_t from_left(int32_t v, int32_t first) {
+  return __builtin_amdgcn_update_dpp(first, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+}
+
+// q = rint(S / den) with den = n*2eb, S/den correctly rounded.  Fast path:
+// t1 = S * inv with inv = 1/den (correctly rounded) is within 3 ulp-relative
+// of the exact quotient; when |t1| < 2^28 and t1 is more than 2^-20 away from
+// a half-integer, no half-integer lies between t1 and the correctly rounded
+// quotient (their distance is below 2^28 * 3 * 2^-53 < 2^-23), so rint of
+// both is the same integer.  Otherwise the exact division is taken.
+__device__ __forceinline__ int32_t quantize(double S, uint32_t n, double step, double inv,
+                                            bool &range_err) {
   if (n == 0) return 0;
-  const double den = (double)n * step;
-  const double t = rint(S / den);
+  const double t1 = S * inv;
+  const double d = t1 - floor(t1) - 0.5;
+  double t;
+  if (fabs(t1) < 268435456.0 && fabs(d) > 0x1p-20) {
+    t = rint(t1);
+  } else {
+    const double den = (double)n * step;
+    t = rint(S / den);
+  }
   if (!(fabs(t) <= kQMax)) {
     range_err = true;
     return 0;
@@ -185,9 +173,99 @@ __device__ __forceinline__ int32_t quant_bin(const float *__restrict__ fr, uint3
   return (int32_t)t;
 }
 
-template <int BB, bool DEBUG>
+// Raw pixels of one bin, loaded with clamped (always valid) addresses; the
+// inclusion of each pixel is decided after the load.
+template <int BB>
+struct BinPix {
+  float v[BB ? BB : 8][BB ? BB : 8];
+  uint32_t m[BB ? BB : 8];   // mask bits of each raw row, bit dj = column J*b+dj
+};
+
+template <int BB, bool VEC>
+__device__ __forceinline__ void load_bin(BinPix<BB> &px, const float *__restrict__ fr, uint32_t H,
+                                         uint32_t W, int b, uint32_t I, uint32_t Jc, bool bg,
+                                         const uint32_t *mask, int64_t R0, int64_t C0, int wpr) {
+  constexpr int NB = BB ? BB : 8;
+#pragma unroll
+  for (int di = 0; di < NB; ++di) {
+    if (!BB && di >= b) break;
+    const uint32_t i = min(I * b + di, H - 1);
+    const float *row = fr + (size_t)i * W;
+    const uint32_t j0 = Jc * b;
+    if constexpr (VEC && BB == 2) {
+      const float2 x = *(const float2 *)(row + j0);
+      px.v[di][0] = x.x;
+      px.v[di][1] = x.y;
+    } else if constexpr (VEC && BB == 4) {
+      const float4 x = *(const float4 *)(row + j0);
+      px.v[di][0] = x.x;
+      px.v[di][1] = x.y;
+      px.v[di][2] = x.z;
+      px.v[di][3] = x.w;
+    } else {
+#pragma unroll
+      for (int dj = 0; dj < NB; ++dj) {
+        if (!BB && dj >= b) break;
+        px.v[di][dj] = row[min(j0 + dj, W - 1)];
+      }
+    }
+    px.m[di] = 0u;
+    if (bg) {
+      const uint32_t *mrow = mask + (int64_t)(i - R0) * wpr;
+      const int bit = (int)((int64_t)j0 - C0);
+      if constexpr (BB == 1 || BB == 2 || BB == 4 || BB == 8) {
+        // b divides 32: the bits of one bin row share one word
+        px.m[di] = mrow[bit >> 5] >> (bit & 31);
+      } else {
+        uint32_t m = 0;
+        for (int dj = 0; dj < b; ++dj) {
+          const int bj = bit + dj;
+          m |= ((mrow[bj >> 5] >> (bj & 31)) & 1u) << dj;
+        }
+        px.m[di] = m;
+      }
+    }
+  }
+}
+
+// Sum in raster order over the included pixels (fp64, from +0.0), count, and
+// quantise.
+template <int BB>
+__device__ __forceinline__ int32_t reduce_bin(const BinPix<BB> &px, uint32_t H, uint32_t W, int b,
+                                              uint32_t I, uint32_t J, double step,
+                                              const double *inv, bool &range_err, double &S_out,
+                                              uint32_t &n_out) {
+  constexpr int NB = BB ? BB : 8;
+  double S = 0.0;
+  uint32_t n = 0;
+#pragma unroll
+  for (int di = 0; di < NB; ++di) {
+    if (!BB && di >= b) break;
+    const bool rowv = I * b + di < H;
+#pragma unroll
+    for (int dj = 0; dj < NB; ++dj) {
+      if (!BB && dj >= b) break;
+      const bool inc = rowv && (J * b + dj < W) && !((px.m[di] >> dj) & 1u);
+      const double y = S + (double)px.v[di][dj];
+      S = inc ? y : S;
+      n += inc ? 1u : 0u;
+    }
+  }
+  S_out = S;
+  n_out = n;
+  return quantize(S, n, step, inv[n], range_err);
+}
+
+// Rows of bins whose loads are issued together.
+template <int BB>
+constexpr int rows_in_flight() {
+  return BB == 1 ? 8 : (BB == 2 ? 4 : (BB == 4 ? 2 : 1));
+}
+
+template <int BB, bool VEC, bool DEBUG>
 __device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint32_t *hist,
-                            uint32_t *mask, int32_t (*edge)[kMaxTH + 1]) {
+                            uint32_t *mask, int32_t (*edge)[kMaxTH + 1], const double *inv) {
+  constexpr int RB = rows_in_flight<BB>();
   const int lane = threadIdx.x & 63;
   const int b = BB ? BB : (int)fp.b;
   const uint32_t H = fp.H, W = fp.W, Hb = fp.Hb, Wb = fp.Wb;
@@ -204,6 +282,7 @@ __device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint3
   uint16_t *codes = fp.codes + gbase;
   int32_t *rbuf = fp.rbuf + gbase;
   bool range_err = false;
+  uint32_t c512 = 0;
   double Sd;
   uint32_t nd;
 
@@ -244,41 +323,56 @@ __device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint3
     }
     const uint32_t J = s * 64 + lane;
     const bool colv = J < Wb;
+    const uint32_t Jc = colv ? J : Wb - 1;   // loads of idle lanes stay inside the frame
     const int cur = s & 1, prv = cur ^ 1;
     int32_t q_up = 0;
-    if (I0 > 0 && colv)
-      q_up = quant_bin<BB>(fr, H, W, b, I0 - 1, J, bg, mask, R0, C0, wpr, step, range_err, Sd, nd);
+    if (I0 > 0) {
+      BinPix<BB> px;
+      load_bin<BB, VEC>(px, fr, H, W, b, I0 - 1, Jc, bg, mask, R0, C0, wpr);
+      const int32_t qh = reduce_bin<BB>(px, H, W, b, I0 - 1, J, step, inv, range_err, Sd, nd);
+      q_up = colv ? qh : 0;
+    }
     int32_t e_up = (s > 0 && I0 > 0) ? edge[prv][0] : 0;
     if (lane == 63) edge[cur][0] = q_up;
-    for (uint32_t I = I0; I < I1; ++I) {
-      int32_t q = 0;
-      if (colv) q = quant_bin<BB>(fr, H, W, b, I, J, bg, mask, R0, C0, wpr, step, range_err, Sd, nd);
-      int32_t ql = __shfl_up(q, 1), qul = __shfl_up(q_up, 1);
-      const int32_t e = (s > 0) ? edge[prv][I - I0 + 1] : 0;
-      if (lane == 0) {
-        ql = e;
-        qul = e_up;
-      }
-      e_up = e;
-      if (lane == 63) edge[cur][I - I0 + 1] = q;
-      const int32_t r = q - q_up - ql + qul;
-      uint32_t code = 0xFFFFu;
-      if (colv) {
-        const size_t g = (size_t)I * Wb + J;
-        code = (r > -kRadius && r < kRadius) ? (uint32_t)(r + kRadius) : 0u;
-        codes[g] = (uint16_t)code;
-        if (code == 0) rbuf[g] = r;
-        if (DEBUG) {
-          if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
-          if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
-          if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
+    for (uint32_t Ib = I0; Ib < I1; Ib += RB) {
+      BinPix<BB> px[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (Ib + r < I1) load_bin<BB, VEC>(px[r], fr, H, W, b, Ib + r, Jc, bg, mask, R0, C0, wpr);
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const uint32_t I = Ib + r;
+        if (I >= I1) break;
+        const int32_t qv = reduce_bin<BB>(px[r], H, W, b, I, J, step, inv, range_err, Sd, nd);
+        const int32_t q = colv ? qv : 0;
+        const int32_t e = (s > 0) ? edge[prv][I - I0 + 1] : 0;
+        const int32_t ql = from_left(q, e);
+        const int32_t qul = from_left(q_up, e_up);
+        e_up = e;
+        if (lane == 63) edge[cur][I - I0 + 1] = q;
+        const int32_t rres = q - q_up - ql + qul;
+        uint32_t code = 0xFFFFu;
+        if (colv) {
+          const size_t g = (size_t)I * Wb + J;
+          code = (rres > -kRadius && rres < kRadius) ? (uint32_t)(rres + kRadius) : 0u;
+          codes[g] = (uint16_t)code;
+          if (code == 0) rbuf[g] = rres;
+          if (DEBUG) {
+            if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
+            if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
+            if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
+          }
         }
+        wave_histogram(code, colv, hist, c512);
+        q_up = q;
       }
-      wave_histogram(code, colv, hist);
-      q_up = q;
     }
     wave_sync();
   }
+  // per-lane counts of code 512
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) c512 += __shfl_xor(c512, d);
+  if (lane == 0 && c512) atomicAdd(&hist[kRadius], c512);
   if (range_err) set_status(fp.st, RSZ_ERR_RANGE);
 }
 
@@ -287,16 +381,23 @@ __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
   __shared__ uint32_t s_hist[kNumSym];
   __shared__ uint32_t s_mask[kWaves][kMaskWords];
   __shared__ int32_t s_edge[kWaves][2][kMaxTH + 1];
+  __shared__ double s_inv[65];
   const uint32_t f = find_frame(bp.tile_prefix, bp.nframes, blockIdx.x);
   const FramePlan &fp = bp.frames[f];
   for (int i = threadIdx.x; i < kNumSym; i += 256) s_hist[i] = 0u;
+  if (threadIdx.x < 65) s_inv[threadIdx.x] = fp.inv[threadIdx.x];
   __syncthreads();
   const int wv = threadIdx.x >> 6;
   const uint32_t t = blockIdx.x - bp.tile_prefix[f];
   const uint32_t panel = t / fp.groups, grp = t % fp.groups;
   const uint32_t seg = grp * kWaves + wv;
   const bool ok = load_status(fp.st) == RSZ_OK;
-  if (ok && seg < fp.segs) bin_segment<BB, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv]);
+  if (ok && seg < fp.segs) {
+    if ((BB == 2 || BB == 4) && fp.vec)
+      bin_segment<BB, true, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+    else
+      bin_segment<BB, false, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < kNumSym; i += 256)
     if (s_hist[i]) atomicAdd(&fp.st->hist[i], s_hist[i]);

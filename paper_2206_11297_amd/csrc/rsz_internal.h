@@ -46,6 +46,8 @@ struct FramePlan {
   uint32_t npeaks, TH, segs, groups;   // segments per panel, workgroups per panel
   uint32_t nstrips;
   int32_t init_status;      // RSZ_OK or RSZ_ERR_ARG
+  uint32_t vec;             // rows load as float2/float4 (W % b == 0, aligned)
+  double inv[65];           // inv[n] = 1 / (n * 2eb), correctly rounded
   const float *frame;
   const int32_t *peaks;     // npeaks x (panel,row,col)
   uint8_t *out;
