@@ -355,8 +355,10 @@ uint64_t ro_bitstream(uint64_t nbins, const uint16_t *codes, const uint8_t *len,
 
 /* ---------------------------------------------------------------- container */
 
+/* Section order: header, peaks, ROI payload, code lengths, chunk offsets,
+ * bitstream, outlier indices, outlier residuals. */
 typedef struct {
-  uint64_t peaks, roi, lens, oidx, ores, chunks, bits, total;
+  uint64_t peaks, roi, lens, chunks, bits, oidx, ores, total;
 } ro_layout;
 
 static ro_layout ro_sections(const ro_params *p, uint32_t npeaks, uint64_t n_out,
@@ -365,11 +367,11 @@ static ro_layout ro_sections(const ro_params *p, uint32_t npeaks, uint64_t n_out
   L.peaks = RO_HEADER;
   L.roi = L.peaks + ro_align4(6ull * npeaks);
   L.lens = L.roi + 4ull * npeaks * p->window * p->window;
-  L.oidx = L.lens + RO_NSYM;
-  L.ores = L.oidx + 4ull * n_out;
-  L.chunks = L.ores + 4ull * n_out;
+  L.chunks = L.lens + RO_NSYM;
   L.bits = L.chunks + 4ull * n_chunks;
-  L.total = L.bits + 4ull * ((T + 31) / 32);
+  L.oidx = L.bits + 4ull * ((T + 31) / 32);
+  L.ores = L.oidx + 4ull * n_out;
+  L.total = L.ores + 4ull * n_out;
   return L;
 }
 
@@ -439,7 +441,7 @@ int ro_intermediates(const ro_params *p, const float *frame, const int32_t *peak
 }
 
 /* Compress one frame into the self-contained stream (header, peaks, ROI
- * payload, code lengths, outliers, chunk offsets, bitstream).  On
+ * payload, code lengths, chunk offsets, bitstream, outliers).  On
  * RO_ERR_CAPACITY *out_bytes holds the required size. */
 int ro_compress(const ro_params *p, const float *frame, const int32_t *peaks, uint32_t npeaks,
                 uint8_t *out, uint64_t out_cap, uint64_t *out_bytes) {

@@ -64,7 +64,7 @@ static int check_params(const rsz_params *p, uint32_t npeaks) {
 
 struct Geom {
   uint32_t Hb, Wb, nbins, nchunks, TH, segs, groups, nstrips;
-  uint64_t off_roi, off_lens, off_oidx;
+  uint64_t off_roi, off_lens, off_chunks, off_bits;
   uint64_t max_bytes;
 };
 
@@ -85,9 +85,10 @@ static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap) {
   g.nstrips = (uint32_t)div_up(g.Wb, 64);
   g.off_roi = kHeader + align_up(6ull * npeaks, 4);
   g.off_lens = g.off_roi + 4ull * npeaks * p->window * p->window;
-  g.off_oidx = g.off_lens + kNumSym;
-  // worst case: every bin an outlier, every codeword 32 bits
-  g.max_bytes = g.off_oidx + 8ull * g.nbins + 4ull * g.nchunks + 4ull * g.nbins;
+  g.off_chunks = g.off_lens + kNumSym;
+  g.off_bits = g.off_chunks + 4ull * g.nchunks;
+  // worst case: every codeword 32 bits and every bin an outlier
+  g.max_bytes = g.off_bits + 4ull * g.nbins + 8ull * g.nbins;
   return g;
 }
 
@@ -101,9 +102,11 @@ static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const G
   b += align_up(4ull * (p->panels + 1), 256);  // pstart
   b += align_up(4ull * p->panels, 256);        // pcursor
   b += align_up(12ull * npeaks, 256);          // bucket
-  b += align_up(2ull * g.nbins, 256);          // codes
+  b += align_up(2ull * kChunk * g.nchunks, 256);  // codes, padded to whole chunks
   b += align_up(4ull * g.nbins, 256);          // rbuf
-  b += 2 * align_up(4ull * g.nchunks, 256);    // chunk bits / nout
+  b += align_up(4ull * g.nbins, 256);          // obuf
+  b += align_up(8ull * g.nchunks, 256);        // chunk_desc
+  b += 2 * align_up(4ull * g.nchunks, 256);    // chunk_off, head
   return b;
 }
 
@@ -113,7 +116,7 @@ static Layout layout(uint32_t nframes, const std::vector<const rsz_params *> &ps
   Layout L;
   L.plans = 0;
   L.prefix = align_up(sizeof(FramePlan) * nframes, 256);
-  L.states = L.prefix + align_up(3 * 4ull * (nframes + 1), 256);
+  L.states = L.prefix + align_up(3 * 4ull * (nframes + 1) + 4, 256);
   L.frames_begin = L.states + align_up(sizeof(FrameState) * nframes, 256);
   uint64_t off = L.frames_begin;
   L.frame_off.resize(nframes);
@@ -156,7 +159,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   uint32_t *tp = (uint32_t *)(hp.bytes.data() + L.prefix);
   uint32_t *cp = tp + (nframes + 1);
   uint32_t *rp = cp + (nframes + 1);
-  uint64_t tiles = 0, chunks = 0, roi = 0;
+  uint64_t tiles = 0, chunks = 0, npk_total = 0;
   hp.common_b = 0;
   bool first = true;
   for (uint32_t f = 0; f < nframes; ++f) {
@@ -164,7 +167,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     memset(&fp, 0, sizeof fp);
     tp[f] = (uint32_t)tiles;
     cp[f] = (uint32_t)chunks;
-    rp[f] = (uint32_t)roi;
+    rp[f] = (uint32_t)npk_total;
     fp.st = (FrameState *)(ws + L.states) + f;
     fp.res_bytes = res_bytes + f;
     fp.res_status = res_status + f;
@@ -202,7 +205,8 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.out_cap = d[f].out_cap;
     fp.off_roi = g.off_roi;
     fp.off_lens = g.off_lens;
-    fp.off_oidx = g.off_oidx;
+    fp.off_chunks = g.off_chunks;
+    fp.off_bits = g.off_bits;
     uint8_t *base = ws + L.frame_off[f];
     fp.pstart = (uint32_t *)base;
     base += align_up(4ull * (p->panels + 1), 256);
@@ -211,12 +215,16 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.bucket = (int32_t *)base;
     base += align_up(12ull * np[f], 256);
     fp.codes = (uint16_t *)base;
-    base += align_up(2ull * g.nbins, 256);
+    base += align_up(2ull * kChunk * g.nchunks, 256);
     fp.rbuf = (int32_t *)base;
     base += align_up(4ull * g.nbins, 256);
-    fp.chunk_bits = (uint32_t *)base;
+    fp.obuf = (uint32_t *)base;
+    base += align_up(4ull * g.nbins, 256);
+    fp.chunk_desc = (uint64_t *)base;
+    base += align_up(8ull * g.nchunks, 256);
+    fp.chunk_off = (uint32_t *)base;
     base += align_up(4ull * g.nchunks, 256);
-    fp.chunk_nout = (uint32_t *)base;
+    fp.head = (uint32_t *)base;
     if (dbg) {
       fp.dbg_mask = dbg->mask;
       fp.dbg_S = dbg->S;
@@ -225,7 +233,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     }
     tiles += (uint64_t)p->panels * g.groups;
     chunks += g.nchunks;
-    roi += (uint64_t)np[f] * p->window * p->window;
+    npk_total += np[f];
     if (first) {
       hp.common_b = p->bin;
       first = false;
@@ -233,18 +241,19 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
       hp.common_b = 0;
     }
   }
-  if (tiles >= (1ull << 31) || chunks >= (1ull << 31) || roi >= (1ull << 32)) return RSZ_ERR_ARG;
+  if (tiles >= (1ull << 31) || chunks >= (1ull << 31) || npk_total >= (1ull << 31))
+    return RSZ_ERR_ARG;
   tp[nframes] = (uint32_t)tiles;
   cp[nframes] = (uint32_t)chunks;
-  rp[nframes] = (uint32_t)roi;
+  rp[nframes] = (uint32_t)npk_total;
   hp.bp.nframes = nframes;
   hp.bp.total_tiles = (uint32_t)tiles;
   hp.bp.total_chunks = (uint32_t)chunks;
-  hp.bp.total_roi = (uint32_t)roi;
+  hp.bp.total_peaks = (uint32_t)npk_total;
   hp.bp.frames = (const FramePlan *)(ws + L.plans);
   hp.bp.tile_prefix = (const uint32_t *)(ws + L.prefix);
   hp.bp.chunk_prefix = hp.bp.tile_prefix + (nframes + 1);
-  hp.bp.roi_prefix = hp.bp.chunk_prefix + (nframes + 1);
+  hp.bp.peak_prefix = hp.bp.chunk_prefix + (nframes + 1);
   return RSZ_OK;
 }
 
@@ -325,10 +334,9 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
   const Geom g = geometry(&q, np, kMaxTH);
   const uint64_t n_out = u[11];
   if (u[13] != g.nchunks || n_out > g.nbins || T > 32ull * g.nbins) return RSZ_ERR_CORRUPT;
-  const uint64_t off_ores = g.off_oidx + 4 * n_out;
-  const uint64_t off_chunks = off_ores + 4 * n_out;
-  const uint64_t off_bits = off_chunks + 4ull * g.nchunks;
-  if (off_bits + 4 * ((T + 31) / 32) != total || total > in_bytes) return RSZ_ERR_CORRUPT;
+  const uint64_t off_oidx = g.off_bits + 4 * ((T + 31) / 32);
+  const uint64_t off_ores = off_oidx + 4 * n_out;
+  if (off_ores + 4 * n_out != total || total > in_bytes) return RSZ_ERR_CORRUPT;
   if (p) *p = q;
   if (npeaks) *npeaks = np;
   if (dp) {
@@ -350,10 +358,10 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
     dp->off_peaks = kHeader;
     dp->off_roi = g.off_roi;
     dp->off_lens = g.off_lens;
-    dp->off_oidx = g.off_oidx;
+    dp->off_chunks = g.off_chunks;
+    dp->off_bits = g.off_bits;
+    dp->off_oidx = off_oidx;
     dp->off_ores = off_ores;
-    dp->off_chunks = off_chunks;
-    dp->off_bits = off_bits;
   }
   return RSZ_OK;
 }

@@ -9,10 +9,12 @@
 //               2D Lorenzo + code/outlier + histogram; one wave per segment
 //               of bin rows of a panel, walking it in 64-column strips.
 //   k_codebook  one workgroup per frame: Huffman lengths and canonical codes.
-//   k_chunkbits one workgroup per 4096-symbol chunk: bits and outlier count.
-//   k_scan      one workgroup per frame: chunk offsets, sizes, header.
-//   k_encode    one workgroup per chunk: bit-packing and outlier lists.
-//   k_roi       ROI window payload, bit copies.
+//   k_encode    one workgroup per 4096-symbol chunk, single pass: chunk bit
+//               and outlier offsets by a decoupled look-back scan over the
+//               chunks of the frame, then bit-packing and outlier indices.
+//   k_tail      one workgroup per frame: sizes, capacity, header, chunk
+//               boundary words, outlier sections.
+//   k_roi       one workgroup per peak: ROI window payload, bit copies.
 #include <algorithm>
 
 #include "rsz_internal.h"
@@ -79,11 +81,13 @@ __global__ __launch_bounds__(256) void k_prep(BatchPlan bp) {
   if (threadIdx.x == 0) {
     s_bad = 0;
     st->status = fp.init_status;
+    st->ticket = 0;
     st->n_out = 0;
     st->T = 0;
     st->total = 0;
   }
   if (fp.init_status != RSZ_OK) return;
+  for (uint32_t c = threadIdx.x; c < fp.nchunks; c += 256) fp.chunk_desc[c] = 0ull;
   for (uint32_t p = threadIdx.x; p <= fp.P; p += 256) fp.pstart[p] = 0;
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) {
@@ -522,50 +526,165 @@ __global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
   }
 }
 
-// ------------------------------------------------------------ k_chunkbits
+// --------------------------------------------------------------- k_encode
 
-__global__ __launch_bounds__(256) void k_chunkbits(BatchPlan bp) {
-  const uint32_t c = blockIdx.x;
-  const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, c);
-  const FramePlan &fp = bp.frames[f];
-  const FrameState *st = fp.st;
+// Look-back descriptor of a chunk: flag (bits 62-63: 1 = this chunk's own
+// totals, 2 = totals of all chunks up to and including it), outlier count
+// (bits 32-58) and bit count (bits 0-31).  Frame totals stay below 2^32 bits
+// and 2^27 outliers, so packed values add without carries between fields.
+constexpr uint64_t kDescAgg = 1ull << 62, kDescInc = 2ull << 62;
+constexpr uint64_t kDescVal = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+// A descriptor carries everything a later chunk needs from it, so relaxed
+// agent-scope atomics suffice: no other memory is published through it, and
+// release/acquire ordering here would write back and invalidate the L2 on
+// every publish and poll.
+__device__ __forceinline__ void put_desc(uint64_t *d, uint64_t v) {
+  __hip_atomic_store(d, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t get_desc(const uint64_t *d) {
+  return __hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The chunks of a frame are taken in the order of a per-frame ticket, so every
+// chunk a workgroup looks back at belongs to a workgroup that started earlier
+// and publishes its own totals before it waits for anything: the wait always
+// ends.  A spin limit bounds it
+// anyway and turns a stall into an error status.
+__global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
   __shared__ uint8_t s_len[kNumSym];
+  __shared__ uint32_t s_cw[kNumSym];
+  __shared__ uint32_t s_words[kChunk + 2];
   __shared__ uint64_t s_tmp[4];
+  __shared__ uint64_t s_prefix;
+  __shared__ uint32_t s_lc;
   __shared__ int s_ok;
-  if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
-  for (int s = threadIdx.x; s < kNumSym; s += 256) s_len[s] = st->lens[s];
+  const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, blockIdx.x);
+  const FramePlan &fp = bp.frames[f];
+  FrameState *st = fp.st;
+  if (threadIdx.x == 0) {
+    s_ok = load_status(st) == RSZ_OK;
+    if (s_ok) s_lc = atomicAdd(&st->ticket, 1u);
+  }
   __syncthreads();
-  if (!s_ok) return;
-  const uint32_t lc = c - bp.chunk_prefix[f];
+  if (!s_ok) return;  // every chunk of the frame skips: nobody waits on it
+  for (int s = threadIdx.x; s < kNumSym; s += 256) {
+    s_len[s] = st->lens[s];
+    s_cw[s] = st->cw[s];
+  }
+  __syncthreads();
+  const uint32_t lc = s_lc;
   const uint32_t g0 = lc * kChunk + threadIdx.x * 16;
+  // the codes region is padded to whole chunks: both 16-byte loads stay inside
+  const uint4 *cv = (const uint4 *)(fp.codes + g0);
+  const uint4 c0 = cv[0], c1 = cv[1];
+  const uint32_t w8[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+  uint32_t code[16];
   uint32_t bits = 0, nout = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const uint32_t g = g0 + k;
+    code[k] = g < fp.nbins ? ((w8[k >> 1] >> (16 * (k & 1))) & 0xFFFFu) : 0xFFFFu;
     if (g < fp.nbins) {
-      const uint32_t code = fp.codes[g];
-      bits += s_len[code];
-      nout += code == 0;
+      bits += s_len[code[k]];
+      nout += code[k] == 0;
     }
   }
   uint64_t tot;
-  block_exclusive_scan<uint64_t>(((uint64_t)nout << 32) | bits, s_tmp, tot);
+  const uint64_t ex = block_exclusive_scan<uint64_t>(((uint64_t)nout << 32) | bits, s_tmp, tot);
+  if (threadIdx.x < 64) {
+    // wave 0 looks back over windows of 64 preceding chunks: the chunks up
+    // to the nearest one with an inclusive total must all have published
+    const int lane = threadIdx.x;
+    uint64_t prefix = 0;
+    if (lc == 0) {
+      if (lane == 0) put_desc(&fp.chunk_desc[0], kDescInc | tot);
+    } else {
+      if (lane == 0) put_desc(&fp.chunk_desc[lc], kDescAgg | tot);
+      int64_t base = (int64_t)lc - 1;
+      uint32_t spins = 0;
+      for (;;) {
+        const int64_t k = base - lane;
+        const uint64_t v = k >= 0 ? get_desc(&fp.chunk_desc[k]) : kDescInc;
+        const uint64_t flag = v & ~kDescVal;
+        const uint64_t inc = __ballot(flag == kDescInc);
+        const uint64_t notyet = __ballot(flag == 0);
+        const int first = inc ? __builtin_ctzll(inc) : 64;
+        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+        if (notyet & need) {
+          if (++spins > kSpinLimit) {
+            if (lane == 0) set_status(st, RSZ_ERR_HIP);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        uint64_t x = ((need >> lane) & 1ull) ? (v & kDescVal) : 0ull;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d);
+        prefix += x;
+        if (first < 64) break;
+        base -= 64;
+      }
+      if (lane == 0) put_desc(&fp.chunk_desc[lc], kDescInc | (prefix + tot));
+    }
+    if (lane == 0) s_prefix = prefix;
+  }
+  __syncthreads();
+  const uint32_t S0 = (uint32_t)s_prefix;
+  const uint32_t O0 = (uint32_t)(s_prefix >> 32);
+  const uint32_t clen = (uint32_t)tot;
+  const uint32_t nwords = ((S0 & 31) + clen + 31) >> 5;
+  for (uint32_t k = threadIdx.x; k < nwords; k += 256) s_words[k] = 0u;
+  __syncthreads();
+  uint32_t pos = (S0 & 31) + (uint32_t)ex;
+  uint32_t oi = O0 + (uint32_t)(ex >> 32);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (code[k] == 0xFFFFu) continue;
+    const uint32_t L = s_len[code[k]];
+    const uint64_t v = ((uint64_t)s_cw[code[k]] << (64 - L)) >> (pos & 31);
+    atomicOr(&s_words[pos >> 5], (uint32_t)(v >> 32));
+    if ((pos & 31) + L > 32) atomicOr(&s_words[(pos >> 5) + 1], (uint32_t)v);
+    pos += L;
+    if (code[k] == 0) {
+      if (oi < fp.nbins) fp.obuf[oi] = g0 + k;
+      oi++;
+    }
+  }
+  __syncthreads();
+  uint8_t *o = fp.out;
+  const uint64_t cap = fp.out_cap;
   if (threadIdx.x == 0) {
-    fp.chunk_bits[lc] = (uint32_t)tot;
-    fp.chunk_nout[lc] = (uint32_t)(tot >> 32);
+    fp.chunk_off[lc] = S0;
+    if (fp.off_chunks + 4ull * lc + 4 <= cap) *(uint32_t *)(o + fp.off_chunks + 4ull * lc) = S0;
+  }
+  // A partial first word is shared with the previous chunk: its bits go to
+  // head[] and k_tail merges them.  Every other word belongs to this chunk.
+  uint32_t *bw = (uint32_t *)(o + fp.off_bits);
+  const uint32_t wlo = S0 >> 5;
+  for (uint32_t k = threadIdx.x; k < nwords; k += 256) {
+    const uint32_t v = s_words[k];
+    if (k == 0 && (S0 & 31)) {
+      fp.head[lc] = v;
+      continue;
+    }
+    const uint64_t widx = (uint64_t)wlo + k;
+    if (fp.off_bits + 4 * widx + 4 <= cap) bw[widx] = v;
   }
 }
 
-// ----------------------------------------------------------------- k_scan
+// ----------------------------------------------------------------- k_tail
 
 __device__ __forceinline__ void put_u32(uint8_t *o, uint64_t off, uint32_t v) {
   *(uint32_t *)(o + off) = v;
 }
 
-__global__ __launch_bounds__(256) void k_scan(BatchPlan bp) {
+__global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
   const FramePlan &fp = bp.frames[blockIdx.x];
   FrameState *st = fp.st;
-  __shared__ uint64_t s_tmp[4];
   __shared__ int32_t s_status;
   if (threadIdx.x == 0) s_status = load_status(st);
   __syncthreads();
@@ -576,33 +695,19 @@ __global__ __launch_bounds__(256) void k_scan(BatchPlan bp) {
     }
     return;
   }
-  uint64_t carry = 0;
-  for (uint32_t base = 0; base < fp.nchunks; base += 256) {
-    const uint32_t c = base + threadIdx.x;
-    const uint64_t v = c < fp.nchunks ? (((uint64_t)fp.chunk_nout[c] << 32) | fp.chunk_bits[c]) : 0;
-    uint64_t tot;
-    const uint64_t ex = block_exclusive_scan<uint64_t>(v, s_tmp, tot) + carry;
-    if (c < fp.nchunks) {
-      fp.chunk_bits[c] = (uint32_t)ex;
-      fp.chunk_nout[c] = (uint32_t)(ex >> 32);
-    }
-    carry += tot;
-  }
-  const uint64_t T = (uint32_t)carry;
-  const uint32_t n_out = (uint32_t)(carry >> 32);
-  const uint64_t off_ores = fp.off_oidx + 4ull * n_out;
-  const uint64_t off_chunks = off_ores + 4ull * n_out;
-  const uint64_t off_bits = off_chunks + 4ull * fp.nchunks;
+  const uint64_t last = get_desc(&fp.chunk_desc[fp.nchunks - 1]) & kDescVal;
+  const uint64_t T = (uint32_t)last;
+  const uint32_t n_out = (uint32_t)(last >> 32);
   const uint64_t nwords = (T + 31) / 32;
-  const uint64_t total = off_bits + 4 * nwords;
+  const uint64_t off_oidx = fp.off_bits + 4 * nwords;
+  const uint64_t off_ores = off_oidx + 4ull * n_out;
+  const uint64_t total = off_ores + 4ull * n_out;
   const bool fits = total <= fp.out_cap;
+  __syncthreads();
   if (threadIdx.x == 0) {
     st->T = T;
     st->n_out = n_out;
     st->total = total;
-    st->off_ores = off_ores;
-    st->off_chunks = off_chunks;
-    st->off_bits = off_bits;
     if (!fits) st->status = RSZ_ERR_CAPACITY;
     *fp.res_status = fits ? RSZ_OK : RSZ_ERR_CAPACITY;
     *fp.res_bytes = total;
@@ -637,107 +742,41 @@ __global__ __launch_bounds__(256) void k_scan(BatchPlan bp) {
   for (uint32_t e = threadIdx.x; e < 3 * fp.npeaks; e += 256) pk[e] = (uint16_t)fp.peaks[e];
   if (threadIdx.x == 0 && (3 * fp.npeaks) % 2) pk[3 * fp.npeaks] = 0;
   for (int s = threadIdx.x; s < kNumSym; s += 256) o[fp.off_lens + s] = st->lens[s];
-  uint32_t *co = (uint32_t *)(o + off_chunks);
-  uint32_t *bw = (uint32_t *)(o + off_bits);
+  // chunk boundary words: previous chunk's bits (stored by it) | this chunk's
+  uint32_t *bw = (uint32_t *)(o + fp.off_bits);
   for (uint32_t c = threadIdx.x; c < fp.nchunks; c += 256) {
-    const uint32_t off = fp.chunk_bits[c];
-    co[c] = off;
-    bw[off >> 5] = 0u;  // chunk boundary words are or-ed by two chunks
+    const uint32_t S0 = fp.chunk_off[c];
+    if (S0 & 31) bw[S0 >> 5] |= fp.head[c];
   }
-  if (threadIdx.x == 0 && (T & 31)) bw[T >> 5] = 0u;
-}
-
-// --------------------------------------------------------------- k_encode
-
-__global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
-  const uint32_t c = blockIdx.x;
-  const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, c);
-  const FramePlan &fp = bp.frames[f];
-  const FrameState *st = fp.st;
-  __shared__ uint8_t s_len[kNumSym];
-  __shared__ uint32_t s_cw[kNumSym];
-  __shared__ uint32_t s_words[kChunk + 2];
-  __shared__ uint64_t s_tmp[4];
-  __shared__ int s_ok;
-  if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
-  for (int s = threadIdx.x; s < kNumSym; s += 256) {
-    s_len[s] = st->lens[s];
-    s_cw[s] = st->cw[s];
-  }
-  __syncthreads();
-  if (!s_ok) return;
-  const uint32_t lc = c - bp.chunk_prefix[f];
-  const uint32_t S0 = fp.chunk_bits[lc];
-  const uint32_t O0 = fp.chunk_nout[lc];
-  const uint32_t g0 = lc * kChunk + threadIdx.x * 16;
-  uint32_t code[16];
-  uint32_t bits = 0, nout = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const uint32_t g = g0 + k;
-    code[k] = g < fp.nbins ? fp.codes[g] : 0xFFFFu;
-    if (g < fp.nbins) {
-      bits += s_len[code[k]];
-      nout += code[k] == 0;
-    }
-  }
-  uint64_t tot;
-  const uint64_t ex = block_exclusive_scan<uint64_t>(((uint64_t)nout << 32) | bits, s_tmp, tot);
-  const uint32_t clen = (uint32_t)tot;
-  const uint32_t nwords = ((S0 & 31) + clen + 31) >> 5;
-  for (uint32_t k = threadIdx.x; k < nwords; k += 256) s_words[k] = 0u;
-  __syncthreads();
-  uint32_t pos = (S0 & 31) + (uint32_t)ex;
-  uint32_t oi = O0 + (uint32_t)(ex >> 32);
-  uint8_t *o = fp.out;
-  uint32_t *oidx = (uint32_t *)(o + fp.off_oidx);
-  int32_t *ores = (int32_t *)(o + st->off_ores);
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    if (code[k] == 0xFFFFu) continue;
-    const uint32_t L = s_len[code[k]];
-    const uint64_t v = ((uint64_t)s_cw[code[k]] << (64 - L)) >> (pos & 31);
-    atomicOr(&s_words[pos >> 5], (uint32_t)(v >> 32));
-    if ((pos & 31) + L > 32) atomicOr(&s_words[(pos >> 5) + 1], (uint32_t)v);
-    pos += L;
-    if (code[k] == 0) {
-      const uint32_t g = g0 + k;
-      oidx[oi] = g;
-      ores[oi] = fp.rbuf[g];
-      oi++;
-    }
-  }
-  __syncthreads();
-  uint32_t *bw = (uint32_t *)(o + st->off_bits) + (S0 >> 5);
-  const bool part_lo = (S0 & 31) != 0, part_hi = ((S0 + clen) & 31) != 0;
-  for (uint32_t k = threadIdx.x; k < nwords; k += 256) {
-    const uint32_t v = s_words[k];
-    if ((k == 0 && part_lo) || (k == nwords - 1 && part_hi))
-      atomicOr(&bw[k], v);
-    else
-      bw[k] = v;
+  uint32_t *oidx = (uint32_t *)(o + off_oidx);
+  int32_t *ores = (int32_t *)(o + off_ores);
+  for (uint32_t k = threadIdx.x; k < n_out; k += 256) {
+    const uint32_t g = fp.obuf[k];
+    oidx[k] = g;
+    ores[k] = fp.rbuf[g];
   }
 }
 
 // ------------------------------------------------------------------ k_roi
 
 __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
-  const uint32_t stride = gridDim.x * 256;
-  for (uint32_t e = blockIdx.x * 256 + threadIdx.x; e < bp.total_roi; e += stride) {
-    const uint32_t f = find_frame(bp.roi_prefix, bp.nframes, e);
-    const FramePlan &fp = bp.frames[f];
-    if (load_status(fp.st) != RSZ_OK) continue;
-    const uint32_t le = e - bp.roi_prefix[f];
-    const uint32_t ww = fp.w * fp.w;
-    const uint32_t k = le / ww, rem = le - k * ww;
-    const uint32_t u = rem / fp.w, v = rem - u * fp.w;
-    const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
-    const int64_t h = fp.w / 2;
+  const uint32_t kg = blockIdx.x;
+  const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
+  const FramePlan &fp = bp.frames[f];
+  if (load_status(fp.st) != RSZ_OK) return;
+  const uint32_t k = kg - bp.peak_prefix[f];
+  const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
+  if (pa < 0 || pa >= fp.P) return;
+  const int64_t h = fp.w / 2;
+  const uint32_t ww = fp.w * fp.w;
+  uint32_t *dst = (uint32_t *)(fp.out + fp.off_roi) + (size_t)k * ww;
+  const float *src = fp.frame + (size_t)pa * fp.H * fp.W;
+  for (uint32_t e = threadIdx.x; e < ww; e += 256) {
+    const uint32_t u = e / fp.w, v = e - u * fp.w;
     const int64_t i = r - h + u, j = c - h + v;
     uint32_t bits = 0u;
-    if (pa >= 0 && pa < fp.P && i >= 0 && i < fp.H && j >= 0 && j < fp.W)
-      bits = __float_as_uint(fp.frame[((size_t)pa * fp.H + (size_t)i) * fp.W + (size_t)j]);
-    ((uint32_t *)(fp.out + fp.off_roi))[le] = bits;
+    if (i >= 0 && i < fp.H && j >= 0 && j < fp.W) bits = __float_as_uint(src[i * fp.W + j]);
+    dst[e] = bits;
   }
 }
 
@@ -774,13 +813,9 @@ hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t 
 }
 
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
-  if (bp.total_chunks) RSZ_LAUNCH("k_chunkbits", k_chunkbits, bp.total_chunks, s, bp);
-  RSZ_LAUNCH("k_scan", k_scan, bp.nframes, s, bp);
   if (bp.total_chunks) RSZ_LAUNCH("k_encode", k_encode, bp.total_chunks, s, bp);
-  if (bp.total_roi) {
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((bp.total_roi + 255) / 256, 1u << 20);
-    RSZ_LAUNCH("k_roi", k_roi, blocks, s, bp);
-  }
+  RSZ_LAUNCH("k_tail", k_tail, bp.nframes, s, bp);
+  if (bp.total_peaks) RSZ_LAUNCH("k_roi", k_roi, bp.total_peaks, s, bp);
   return hipSuccess;
 }
 

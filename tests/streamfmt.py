@@ -7,9 +7,9 @@ Layout (little-endian, sections 4-byte aligned):
   u32 P, H, W, window, bin, radius(512), f64 eb, u32 npeaks, n_out, chunk(4096),
   n_chunks, u64 T (bits), u64 stream_bytes, u64 reserved 0;
   then peaks (npeaks x 3 u16, padded to 4), ROI payload (npeaks*w*w u32),
-  code lengths (1024 u8), outlier indices (n_out u32), outlier residuals
-  (n_out i32), chunk bit offsets (n_chunks u32), bitstream (ceil(T/32) u32,
-  codewords MSB-first within each word).
+  code lengths (1024 u8), chunk bit offsets (n_chunks u32), bitstream
+  (ceil(T/32) u32, codewords MSB-first within each word), outlier indices
+  (n_out u32), outlier residuals (n_out i32).
 """
 import struct
 
@@ -28,11 +28,11 @@ def sections(npeaks, window, n_out, n_chunks, T):
     off["peaks"] = 80
     off["roi"] = 80 + align4(6 * npeaks)
     off["lens"] = off["roi"] + 4 * npeaks * window * window
-    off["oidx"] = off["lens"] + 1024
-    off["ores"] = off["oidx"] + 4 * n_out
-    off["chunks"] = off["ores"] + 4 * n_out
+    off["chunks"] = off["lens"] + 1024
     off["bits"] = off["chunks"] + 4 * n_chunks
-    off["total"] = off["bits"] + 4 * ((T + 31) // 32)
+    off["oidx"] = off["bits"] + 4 * ((T + 31) // 32)
+    off["ores"] = off["oidx"] + 4 * n_out
+    off["total"] = off["ores"] + 4 * n_out
     return off
 
 
