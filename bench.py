@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--latency-frames", type=int, default=200)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the compression path is not sharded "
@@ -89,6 +91,15 @@ def main():
     B = rsz.Batch(frames, peaks, (WINDOW, BIN, EB, rsz.RSZ_BIN_BACKGROUND))
     raw_bytes = sum(f.numel() * 4 for f in frames)
     npix = raw_bytes // 4
+
+    if args.copy_calibration:
+        # plain copy of a known size: 1 GiB read + 1 GiB written
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         B.run()
@@ -135,7 +146,7 @@ def main():
                                    rsz._ptr(out1), cap, rsz._ptr(ws1), ws1.numel(), s)
         lat.append(time.perf_counter() - a)
         assert st1 == 0 and n1 == sizes[i]
-    lat_ms = np.array(lat) * 1e3
+    lat_ms = np.array(lat if lat else [float("nan")]) * 1e3
 
     # CPU baseline: the oracle, single-threaded, on the first frames for a
     # bounded time; its streams must equal the GPU streams byte for byte
@@ -151,7 +162,7 @@ def main():
         got = out_host[B.offsets[n_cpu]:B.offsets[n_cpu] + int(sizes[n_cpu])]
         parity &= sto == 0 and np.array_equal(got, ref)
         n_cpu += 1
-    cpu_gbps = n_cpu * SHAPE[0] * SHAPE[1] * SHAPE[2] * 4 / cpu_t / 1e9
+    cpu_gbps = n_cpu * SHAPE[0] * SHAPE[1] * SHAPE[2] * 4 / cpu_t / 1e9 if n_cpu else None
 
     line = {
         "metric": "raw-frame GB/s compressed (1 GPU) at eb=10 ADU; compression ratio; "
@@ -164,7 +175,8 @@ def main():
                                "20% non-hit, window 17, bin 2x2, eb 10 ADU, one batched launch",
                    "frames": len(frames), "raw_bytes": raw_bytes},
         "roofline": roof,
-        "cpu_baseline": {"value": round(cpu_gbps, 4), "unit": "GB/s", "cores": 1,
+        "cpu_baseline": {"value": None if cpu_gbps is None else round(cpu_gbps, 4),
+                         "unit": "GB/s", "cores": 1,
                          "kind": "oracle",
                          "sample": f"first {n_cpu} frames of the batch, single thread, "
                                    f"{cpu_t:.1f}s", "streams_equal_gpu": bool(parity)},

@@ -182,13 +182,13 @@ __device__ __forceinline__ int32_t quantize(double S, uint32_t n, double step, d
 template <int BB>
 struct BinPix {
   float v[BB ? BB : 8][BB ? BB : 8];
-  uint32_t m[BB ? BB : 8];   // mask bits of each raw row, bit dj = column J*b+dj
+  uint32_t m[BB ? BB : 8];   // mask word(s) of each raw row (shifted in reduce)
 };
 
-template <int BB, bool VEC>
+template <int BB, bool VEC, bool BG>
 __device__ __forceinline__ void load_bin(BinPix<BB> &px, const float *__restrict__ fr, uint32_t H,
-                                         uint32_t W, int b, uint32_t I, uint32_t Jc, bool bg,
-                                         const uint32_t *mask, int64_t R0, int64_t C0, int wpr) {
+                                         uint32_t W, int b, uint32_t I, uint32_t Jc,
+                                         const uint32_t *mask, int64_t R0, int wpr, int mword) {
   constexpr int NB = BB ? BB : 8;
 #pragma unroll
   for (int di = 0; di < NB; ++di) {
@@ -213,32 +213,40 @@ __device__ __forceinline__ void load_bin(BinPix<BB> &px, const float *__restrict
         px.v[di][dj] = row[min(j0 + dj, W - 1)];
       }
     }
-    px.m[di] = 0u;
-    if (bg) {
-      const uint32_t *mrow = mask + (int64_t)(i - R0) * wpr;
-      const int bit = (int)((int64_t)j0 - C0);
-      if constexpr (BB == 1 || BB == 2 || BB == 4 || BB == 8) {
-        // b divides 32: the bits of one bin row share one word
-        px.m[di] = mrow[bit >> 5] >> (bit & 31);
-      } else {
-        uint32_t m = 0;
-        for (int dj = 0; dj < b; ++dj) {
-          const int bj = bit + dj;
-          m |= ((mrow[bj >> 5] >> (bj & 31)) & 1u) << dj;
-        }
-        px.m[di] = m;
-      }
+    if constexpr (BG) {
+      // the word holding this lane's first bit; for b not dividing 32 the
+      // row's bits may continue in the next word (read in row_bits)
+      px.m[di] = mask[(int64_t)(i - R0) * wpr + mword];
+    } else {
+      px.m[di] = 0u;
     }
+  }
+}
+
+// Mask bits of bin row di: bit dj = pixel J*b+dj is inside a window.
+template <int BB, bool BG>
+__device__ __forceinline__ uint32_t row_bits(const BinPix<BB> &px, int di, int b, int mshift,
+                                             const uint32_t *mask, int64_t rowoff, int mword) {
+  if constexpr (!BG) {
+    return 0u;
+  } else if constexpr (BB == 1 || BB == 2 || BB == 4 || BB == 8) {
+    return px.m[di] >> mshift;
+  } else {
+    // straddling case: combine with the next word when the bits cross it
+    const uint32_t lo = px.m[di] >> mshift;
+    const uint32_t hi = (mshift + b > 32) ? (mask[rowoff + mword + 1] << (32 - mshift)) : 0u;
+    return lo | hi;
   }
 }
 
 // Sum in raster order over the included pixels (fp64, from +0.0), count, and
 // quantise.
-template <int BB>
+template <int BB, bool BG>
 __device__ __forceinline__ int32_t reduce_bin(const BinPix<BB> &px, uint32_t H, uint32_t W, int b,
                                               uint32_t I, uint32_t J, double step,
                                               const double *inv, bool &range_err, double &S_out,
-                                              uint32_t &n_out) {
+                                              uint32_t &n_out, int mshift, const uint32_t *mask,
+                                              int64_t R0, int wpr, int mword) {
   constexpr int NB = BB ? BB : 8;
   double S = 0.0;
   uint32_t n = 0;
@@ -246,10 +254,12 @@ __device__ __forceinline__ int32_t reduce_bin(const BinPix<BB> &px, uint32_t H, 
   for (int di = 0; di < NB; ++di) {
     if (!BB && di >= b) break;
     const bool rowv = I * b + di < H;
+    const int64_t rowoff = (int64_t)(min(I * b + di, H - 1) - R0) * wpr;
+    const uint32_t mb = row_bits<BB, BG>(px, di, b, mshift, mask, rowoff, mword);
 #pragma unroll
     for (int dj = 0; dj < NB; ++dj) {
       if (!BB && dj >= b) break;
-      const bool inc = rowv && (J * b + dj < W) && !((px.m[di] >> dj) & 1u);
+      const bool inc = rowv && (J * b + dj < W) && !((mb >> dj) & 1u);
       const double y = S + (double)px.v[di][dj];
       S = inc ? y : S;
       n += inc ? 1u : 0u;
@@ -263,10 +273,10 @@ __device__ __forceinline__ int32_t reduce_bin(const BinPix<BB> &px, uint32_t H, 
 // Rows of bins whose loads are issued together.
 template <int BB>
 constexpr int rows_in_flight() {
-  return BB == 1 ? 8 : (BB == 2 ? 4 : (BB == 4 ? 2 : 1));
+  return BB == 1 ? 8 : (BB == 2 ? 8 : (BB == 4 ? 2 : 1));
 }
 
-template <int BB, bool VEC, bool DEBUG>
+template <int BB, bool VEC, bool BG, bool DEBUG>
 __device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint32_t *hist,
                             uint32_t *mask, int32_t (*edge)[kMaxTH + 1], const double *inv) {
   constexpr int RB = rows_in_flight<BB>();
@@ -278,7 +288,6 @@ __device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint3
   const int mrows = (int)(I1 - I0 + 1) * b;
   const int wpr = 2 * b;
   const float *fr = fp.frame + (size_t)p * H * W;
-  const bool bg = fp.mode == RSZ_BIN_BACKGROUND;
   const uint32_t pk0 = fp.pstart[p], pk1 = fp.pstart[p + 1];
   const int64_t hw = fp.w / 2, wwin = fp.w;
   const double step = fp.step;
@@ -289,8 +298,10 @@ __device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint3
   uint32_t c512 = 0;
   double Sd;
   uint32_t nd;
+  // this lane's bits in a strip's mask rows: bit lane*b of the strip
+  const int mword = (lane * b) >> 5, mshift = (lane * b) & 31;
 
-  const bool build_mask = bg || (DEBUG && fp.dbg_mask);
+  const bool build_mask = BG || (DEBUG && fp.dbg_mask);
   for (uint32_t s = 0; s < fp.nstrips; ++s) {
     const int64_t C0 = (int64_t)s * 64 * b;
     if (build_mask) {
@@ -328,12 +339,16 @@ __device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint3
     const uint32_t J = s * 64 + lane;
     const bool colv = J < Wb;
     const uint32_t Jc = colv ? J : Wb - 1;   // loads of idle lanes stay inside the frame
+    // idle lanes read the mask bits of the last column too (in range)
+    const int mw = colv ? mword : (int)(((Jc - s * 64) * b) >> 5);
+    const int ms = colv ? mshift : (int)(((Jc - s * 64) * b) & 31);
     const int cur = s & 1, prv = cur ^ 1;
     int32_t q_up = 0;
     if (I0 > 0) {
       BinPix<BB> px;
-      load_bin<BB, VEC>(px, fr, H, W, b, I0 - 1, Jc, bg, mask, R0, C0, wpr);
-      const int32_t qh = reduce_bin<BB>(px, H, W, b, I0 - 1, J, step, inv, range_err, Sd, nd);
+      load_bin<BB, VEC, BG>(px, fr, H, W, b, I0 - 1, Jc, mask, R0, wpr, mw);
+      const int32_t qh = reduce_bin<BB, BG>(px, H, W, b, I0 - 1, J, step, inv, range_err, Sd, nd,
+                                            ms, mask, R0, wpr, mw);
       q_up = colv ? qh : 0;
     }
     int32_t e_up = (s > 0 && I0 > 0) ? edge[prv][0] : 0;
@@ -342,12 +357,13 @@ __device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint3
       BinPix<BB> px[RB];
 #pragma unroll
       for (int r = 0; r < RB; ++r)
-        if (Ib + r < I1) load_bin<BB, VEC>(px[r], fr, H, W, b, Ib + r, Jc, bg, mask, R0, C0, wpr);
+        if (Ib + r < I1) load_bin<BB, VEC, BG>(px[r], fr, H, W, b, Ib + r, Jc, mask, R0, wpr, mw);
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const uint32_t I = Ib + r;
         if (I >= I1) break;
-        const int32_t qv = reduce_bin<BB>(px[r], H, W, b, I, J, step, inv, range_err, Sd, nd);
+        const int32_t qv = reduce_bin<BB, BG>(px[r], H, W, b, I, J, step, inv, range_err, Sd, nd,
+                                              ms, mask, R0, wpr, mw);
         const int32_t q = colv ? qv : 0;
         const int32_t e = (s > 0) ? edge[prv][I - I0 + 1] : 0;
         const int32_t ql = from_left(q, e);
@@ -391,16 +407,26 @@ __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
   for (int i = threadIdx.x; i < kNumSym; i += 256) s_hist[i] = 0u;
   if (threadIdx.x < 65) s_inv[threadIdx.x] = fp.inv[threadIdx.x];
   __syncthreads();
-  const int wv = threadIdx.x >> 6;
+  // wave index as a wave-uniform (scalar) value: everything per segment and
+  // per row below stays in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t t = blockIdx.x - bp.tile_prefix[f];
   const uint32_t panel = t / fp.groups, grp = t % fp.groups;
   const uint32_t seg = grp * kWaves + wv;
   const bool ok = load_status(fp.st) == RSZ_OK;
   if (ok && seg < fp.segs) {
-    if ((BB == 2 || BB == 4) && fp.vec)
-      bin_segment<BB, true, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
-    else
-      bin_segment<BB, false, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+    const bool bg = fp.mode == RSZ_BIN_BACKGROUND;
+    if ((BB == 2 || BB == 4) && fp.vec) {
+      if (bg)
+        bin_segment<BB, true, true, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+      else
+        bin_segment<BB, true, false, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+    } else {
+      if (bg)
+        bin_segment<BB, false, true, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+      else
+        bin_segment<BB, false, false, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kNumSym; i += 256)
