@@ -63,7 +63,7 @@ static int check_params(const rsz_params *p, uint32_t npeaks) {
 }
 
 struct Geom {
-  uint32_t Hb, Wb, nbins, nchunks, TH, segs, groups, nstrips;
+  uint32_t Hb, Wb, nbins, nchunks, TH, segs, groups, nstrips, rowmajor;
   uint64_t off_roi, off_lens, off_chunks, off_bits;
   uint64_t max_bytes;
 };
@@ -76,13 +76,19 @@ static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap) {
   g.Wb = (uint32_t)div_up(p->width, p->bin);
   g.nbins = p->panels * g.Hb * g.Wb;
   g.nchunks = (uint32_t)div_up(g.nbins, kChunk);
-  uint32_t thmax = std::min<uint32_t>(kMaxTH, kMaskRowsMax / p->bin - 1);
-  thmax = std::max<uint32_t>(1, std::min(thmax, th_cap));
+  g.nstrips = (uint32_t)div_up(g.Wb, 64);
+  g.rowmajor = g.nstrips <= (uint32_t)kRowMajorStrips;
+  // the wave's LDS mask covers (TH+1)*b raw rows of one strip (2b words per
+  // row) or, row-major, of the whole panel row (2b*nstrips words per row)
+  uint32_t thmax = g.rowmajor
+                       ? (uint32_t)kMaskWords / (2 * p->bin * p->bin * g.nstrips)
+                       : (uint32_t)kMaskRowsMax / p->bin;
+  thmax = thmax > 1 ? thmax - 1 : 1;
+  thmax = std::max<uint32_t>(1, std::min({thmax, (uint32_t)kMaxTH, th_cap}));
   const uint32_t nseg = kWaves * (uint32_t)div_up(g.Hb, (uint64_t)kWaves * thmax);
   g.TH = (uint32_t)div_up(g.Hb, nseg);
   g.segs = (uint32_t)div_up(g.Hb, g.TH);
   g.groups = (uint32_t)div_up(g.segs, kWaves);
-  g.nstrips = (uint32_t)div_up(g.Wb, 64);
   g.off_roi = kHeader + align_up(6ull * npeaks, 4);
   g.off_lens = g.off_roi + 4ull * npeaks * p->window * p->window;
   g.off_chunks = g.off_lens + kNumSym;
@@ -133,6 +139,7 @@ struct HostPlan {
   std::vector<uint8_t> bytes;
   BatchPlan bp;
   uint32_t common_b;
+  uint32_t nsmax = 0;   // strips per row of the widest row-major frame
 };
 
 static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_bytes,
@@ -194,6 +201,8 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.segs = g.segs;
     fp.groups = g.groups;
     fp.nstrips = g.nstrips;
+    fp.rowmajor = g.rowmajor;
+    if (g.rowmajor) hp.nsmax = std::max(hp.nsmax, g.nstrips);
     fp.init_status = RSZ_OK;
     fp.vec = (p->bin == 2 || p->bin == 4) && p->width % p->bin == 0 &&
              (uintptr_t)d[f].frame % (4 * p->bin) == 0;
@@ -301,7 +310,7 @@ static int enqueue(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_byte
                             default_th_cap(nframes), hp, nullptr, dbg);
   if (st) return st;
   if (stage_to_device(ws, hp.bytes.data(), hp.bytes.size(), s) != RSZ_OK) return RSZ_ERR_HIP;
-  if (launch_compress_front_b(hp.bp, hp.common_b, s, dbg != nullptr) != hipSuccess)
+  if (launch_compress_front_b(hp.bp, hp.common_b, hp.nsmax, s, dbg != nullptr) != hipSuccess)
     return RSZ_ERR_HIP;
   if (!front_only && launch_compress_back(hp.bp, s) != hipSuccess) return RSZ_ERR_HIP;
   return RSZ_OK;

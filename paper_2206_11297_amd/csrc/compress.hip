@@ -273,11 +273,11 @@ __device__ __forceinline__ int32_t reduce_bin(const BinPix<BB> &px, uint32_t H, 
 // Rows of bins whose loads are issued together.
 template <int BB>
 constexpr int rows_in_flight() {
-  return BB == 1 ? 8 : (BB == 2 ? 8 : (BB == 4 ? 2 : 1));
+  return BB == 1 ? 8 : (BB == 2 ? 4 : (BB == 4 ? 2 : 1));
 }
 
 template <int BB, bool VEC, bool BG, bool DEBUG>
-__device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint32_t *hist,
+__device__ __forceinline__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint32_t *hist,
                             uint32_t *mask, int32_t (*edge)[kMaxTH + 1], const double *inv) {
   constexpr int RB = rows_in_flight<BB>();
   const int lane = threadIdx.x & 63;
@@ -396,7 +396,158 @@ __device__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint3
   if (range_err) set_status(fp.st, RSZ_ERR_RANGE);
 }
 
-template <int BB, bool DEBUG>
+// Wave mask of one segment: raw rows [R0, R0 + mrows) x columns [C0, C0 +
+// 32*wpr) of panel p, bit set where a pixel lies in some peak's window.
+__device__ __forceinline__ void build_mask(const FramePlan &fp, uint32_t p, uint32_t *mask,
+                                           int64_t R0, int mrows, int64_t C0, int wpr) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t pk0 = fp.pstart[p], pk1 = fp.pstart[p + 1];
+  const int64_t hw = fp.w / 2, wwin = fp.w;
+  for (int i = lane; i < mrows * wpr; i += 64) mask[i] = 0u;
+  wave_sync();
+  for (uint32_t k = pk0 + lane; k < pk1; k += 64) {
+    const int64_t r = fp.bucket[3 * k + 1], c = fp.bucket[3 * k + 2];
+    const int64_t rlo = max(r - hw, max(R0, (int64_t)0));
+    const int64_t rhi = min(r - hw + wwin, min(R0 + mrows, (int64_t)fp.H));
+    const int64_t clo = max(c - hw, max(C0, (int64_t)0));
+    const int64_t chi = min(c - hw + wwin, min(C0 + 32 * (int64_t)wpr, (int64_t)fp.W));
+    if (rlo >= rhi || clo >= chi) continue;
+    const int b0 = (int)(clo - C0), b1 = (int)(chi - 1 - C0);
+    for (int64_t i = rlo; i < rhi; ++i) {
+      uint32_t *mr = mask + (i - R0) * wpr;
+      for (int wd = b0 >> 5; wd <= (b1 >> 5); ++wd) {
+        const int lo = max(b0 - wd * 32, 0), hi = min(b1 - wd * 32, 31);
+        const uint32_t m = (hi == 31 ? 0xFFFFFFFFu : ((1u << (hi + 1)) - 1u)) & ~((1u << lo) - 1u);
+        atomicOr(&mr[wd], m);
+      }
+    }
+  }
+  wave_sync();
+}
+
+// Strips of a row whose loads are issued together in the row-major walk.
+template <int BB>
+constexpr int strips_in_flight() {
+  return BB == 1 || BB == 2 ? 4 : (BB == 4 ? 2 : 1);
+}
+
+template <int BB, bool VEC, bool BG, bool DEBUG, int NSMAX>
+__device__ __forceinline__ void bin_segment_rows(const FramePlan &fp, uint32_t p, uint32_t seg, uint32_t *hist,
+                                 uint32_t *mask, const double *inv) {
+  constexpr int G = strips_in_flight<BB>();
+  const int lane = threadIdx.x & 63;
+  const int b = BB ? BB : (int)fp.b;
+  const uint32_t H = fp.H, W = fp.W, Hb = fp.Hb, Wb = fp.Wb;
+  const int ns = (int)fp.nstrips;
+  const uint32_t I0 = seg * fp.TH, I1 = min(I0 + fp.TH, Hb);
+  const int64_t R0 = (int64_t)I0 * b - b;
+  const int mrows = (int)(I1 - I0 + 1) * b;
+  const int wpr = 2 * b * ns;
+  const float *fr = fp.frame + (size_t)p * H * W;
+  const double step = fp.step;
+  const size_t gbase = (size_t)p * Hb * Wb;
+  uint16_t *codes = fp.codes + gbase;
+  int32_t *rbuf = fp.rbuf + gbase;
+  bool range_err = false;
+  uint32_t c512 = 0;
+  double Sd;
+  uint32_t nd;
+  if (BG || (DEBUG && fp.dbg_mask)) {
+    build_mask(fp, p, mask, R0, mrows, 0, wpr);
+    if (DEBUG && fp.dbg_mask) {
+      const uint32_t wprg = (W + 31) / 32;
+      const int64_t rs = (int64_t)I0 * b, re = min((int64_t)I1 * b, (int64_t)H);
+      for (int64_t e = lane; e < (re - rs) * (int64_t)wprg; e += 64) {
+        const int64_t i = rs + e / wprg, wd = e % wprg;
+        fp.dbg_mask[((size_t)p * H + i) * wprg + wd] = mask[(i - R0) * wpr + wd];
+      }
+    }
+  }
+  // column of strip s for this lane; idle lanes (past the panel) load the
+  // last column, which stays inside the frame
+#define RSZ_JC(s) (((s) * 64 + lane) < Wb ? ((s) * 64 + lane) : Wb - 1)
+  int32_t q_up[NSMAX];
+#pragma unroll
+  for (int s = 0; s < NSMAX; ++s) {
+    q_up[s] = 0;
+    if (I0 > 0 && s < ns) {
+      const uint32_t jc = RSZ_JC(s);
+      BinPix<BB> px;
+      load_bin<BB, VEC, BG>(px, fr, H, W, b, I0 - 1, jc, mask, R0, wpr, (int)((jc * b) >> 5));
+      const int32_t qh = reduce_bin<BB, BG>(px, H, W, b, I0 - 1, s * 64 + lane, step, inv,
+                                            range_err, Sd, nd, (int)((jc * b) & 31), mask, R0,
+                                            wpr, (int)((jc * b) >> 5));
+      q_up[s] = (uint32_t)(s * 64 + lane) < Wb ? qh : 0;
+    }
+  }
+  for (uint32_t I = I0; I < I1; ++I) {
+    int32_t left = 0, upleft = 0;   // last lane of the previous strip, this row / row above
+#pragma unroll
+    for (int s0 = 0; s0 < NSMAX; s0 += G) {
+      if (s0 >= ns) break;
+      BinPix<BB> px[G];
+#pragma unroll
+      for (int gi = 0; gi < G; ++gi)
+        if (s0 + gi < ns) {
+          const uint32_t jc = RSZ_JC(s0 + gi);
+          load_bin<BB, VEC, BG>(px[gi], fr, H, W, b, I, jc, mask, R0, wpr, (int)((jc * b) >> 5));
+        }
+#pragma unroll
+      for (int gi = 0; gi < G; ++gi) {
+        const int s = s0 + gi;
+        if (s >= ns) break;
+        const uint32_t J = s * 64 + lane;
+        const bool colv = J < Wb;
+        const uint32_t jc = RSZ_JC(s);
+        const int32_t qv = reduce_bin<BB, BG>(px[gi], H, W, b, I, J, step, inv, range_err, Sd,
+                                              nd, (int)((jc * b) & 31), mask, R0, wpr,
+                                              (int)((jc * b) >> 5));
+        const int32_t q = colv ? qv : 0;
+        const int32_t ql = from_left(q, left);
+        const int32_t qul = from_left(q_up[s], upleft);
+        left = __builtin_amdgcn_readlane(q, 63);
+        upleft = __builtin_amdgcn_readlane(q_up[s], 63);
+        const int32_t rres = q - q_up[s] - ql + qul;
+        uint32_t code = 0xFFFFu;
+        if (colv) {
+          const size_t g = (size_t)I * Wb + J;
+          code = (rres > -kRadius && rres < kRadius) ? (uint32_t)(rres + kRadius) : 0u;
+          codes[g] = (uint16_t)code;
+          if (code == 0) rbuf[g] = rres;
+          if (DEBUG) {
+            if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
+            if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
+            if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
+          }
+        }
+        wave_histogram(code, colv, hist, c512);
+        q_up[s] = q;
+      }
+    }
+  }
+#undef RSZ_JC
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) c512 += __shfl_xor(c512, d);
+  if (lane == 0 && c512) atomicAdd(&hist[kRadius], c512);
+  if (range_err) set_status(fp.st, RSZ_ERR_RANGE);
+}
+
+template <int BB, bool VEC, bool BG, bool DEBUG, int NSMAX>
+__device__ __forceinline__ void bin_dispatch(const FramePlan &fp, uint32_t panel, uint32_t seg,
+                                             uint32_t *hist, uint32_t *mask,
+                                             int32_t (*edge)[kMaxTH + 1], const double *inv) {
+  if constexpr (NSMAX > 0) {
+    if (fp.rowmajor) {
+      bin_segment_rows<BB, VEC, BG, DEBUG, NSMAX>(fp, panel, seg, hist, mask, inv);
+      return;
+    }
+  }
+  bin_segment<BB, VEC, BG, DEBUG>(fp, panel, seg, hist, mask, edge, inv);
+}
+
+// NSMAX: most strips per panel row handled by the row-major walk in this
+// instantiation (frames with more strips, or 0 here, use the strip walk).
+template <int BB, int NSMAX, bool DEBUG>
 __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
   __shared__ uint32_t s_hist[kNumSym];
   __shared__ uint32_t s_mask[kWaves][kMaskWords];
@@ -416,16 +567,17 @@ __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
   const bool ok = load_status(fp.st) == RSZ_OK;
   if (ok && seg < fp.segs) {
     const bool bg = fp.mode == RSZ_BIN_BACKGROUND;
+    uint32_t *mask = s_mask[wv];
     if ((BB == 2 || BB == 4) && fp.vec) {
       if (bg)
-        bin_segment<BB, true, true, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+        bin_dispatch<BB, true, true, DEBUG, NSMAX>(fp, panel, seg, s_hist, mask, s_edge[wv], s_inv);
       else
-        bin_segment<BB, true, false, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+        bin_dispatch<BB, true, false, DEBUG, NSMAX>(fp, panel, seg, s_hist, mask, s_edge[wv], s_inv);
     } else {
       if (bg)
-        bin_segment<BB, false, true, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+        bin_dispatch<BB, false, true, DEBUG, NSMAX>(fp, panel, seg, s_hist, mask, s_edge[wv], s_inv);
       else
-        bin_segment<BB, false, false, DEBUG>(fp, panel, seg, s_hist, s_mask[wv], s_edge[wv], s_inv);
+        bin_dispatch<BB, false, false, DEBUG, NSMAX>(fp, panel, seg, s_hist, mask, s_edge[wv], s_inv);
     }
   }
   __syncthreads();
@@ -817,22 +969,40 @@ __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
     if (e_ != hipSuccess) return e_;                              \
   } while (0)
 
-template <bool DEBUG>
-static hipError_t launch_bin(const BatchPlan &bp, uint32_t b, hipStream_t s) {
-  if (bp.total_tiles == 0) return hipSuccess;
-  switch (b) {
-    case 1: RSZ_LAUNCH("k_bin", (k_bin<1, DEBUG>), bp.total_tiles, s, bp); break;
-    case 2: RSZ_LAUNCH("k_bin", (k_bin<2, DEBUG>), bp.total_tiles, s, bp); break;
-    case 4: RSZ_LAUNCH("k_bin", (k_bin<4, DEBUG>), bp.total_tiles, s, bp); break;
-    default: RSZ_LAUNCH("k_bin", (k_bin<0, DEBUG>), bp.total_tiles, s, bp); break;
+template <int NSMAX, bool DEBUG>
+static hipError_t launch_bin_ns(const BatchPlan &bp, uint32_t b, hipStream_t s) {
+  constexpr bool kSpecial = NSMAX == 4;  // only b in {1,2,4}, no debug
+  if constexpr (kSpecial && DEBUG) {
+    return hipErrorInvalidValue;
+  } else {
+    switch (b) {
+      case 1: RSZ_LAUNCH("k_bin", (k_bin<1, NSMAX, DEBUG>), bp.total_tiles, s, bp); break;
+      case 2: RSZ_LAUNCH("k_bin", (k_bin<2, NSMAX, DEBUG>), bp.total_tiles, s, bp); break;
+      case 4: RSZ_LAUNCH("k_bin", (k_bin<4, NSMAX, DEBUG>), bp.total_tiles, s, bp); break;
+      default:
+        if constexpr (kSpecial) return hipErrorInvalidValue;
+        else RSZ_LAUNCH("k_bin", (k_bin<0, NSMAX, DEBUG>), bp.total_tiles, s, bp);
+        break;
+    }
+    return hipSuccess;
   }
-  return hipSuccess;
+}
+
+// nsmax: strips per row of the widest row-major frame (0: none).  The debug
+// build and the generic bin factor use the widest row-major instantiation.
+template <bool DEBUG>
+static hipError_t launch_bin(const BatchPlan &bp, uint32_t b, uint32_t nsmax, hipStream_t s) {
+  if (bp.total_tiles == 0) return hipSuccess;
+  if (nsmax == 0) return launch_bin_ns<0, DEBUG>(bp, b, s);
+  if (DEBUG || (b != 1 && b != 2 && b != 4) || nsmax > 4) return launch_bin_ns<8, DEBUG>(bp, b, s);
+  return launch_bin_ns<4, DEBUG>(bp, b, s);
 }
 
 // prep + bin + codebook; `b` is the common bin factor of the batch or 0.
-hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t s, bool debug) {
+hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t nsmax, hipStream_t s,
+                                   bool debug) {
   RSZ_LAUNCH("k_prep", k_prep, bp.nframes, s, bp);
-  hipError_t e = debug ? launch_bin<true>(bp, b, s) : launch_bin<false>(bp, b, s);
+  hipError_t e = debug ? launch_bin<true>(bp, b, nsmax, s) : launch_bin<false>(bp, b, nsmax, s);
   if (e != hipSuccess) return e;
   RSZ_LAUNCH("k_codebook", k_codebook, bp.nframes, s, bp);
   return hipSuccess;

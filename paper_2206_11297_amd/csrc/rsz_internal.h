@@ -22,7 +22,8 @@ constexpr uint64_t kHeader = 80;
 constexpr int kWaves = 4;
 constexpr int kMaxTH = 32;
 constexpr int kMaskRowsMax = 72;      // (TH+1)*b raw rows per segment
-constexpr int kMaskWords = 1152;      // per wave: rows * 2b words
+constexpr int kMaskWords = 1152;      // per wave: rows * 2b words (per strip)
+constexpr int kRowMajorStrips = 8;   // widest panel row (in 64-bin strips) walked row-major
 
 inline __host__ __device__ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -47,6 +48,7 @@ struct FramePlan {
   uint32_t nstrips;
   int32_t init_status;      // RSZ_OK or RSZ_ERR_ARG
   uint32_t vec;             // rows load as float2/float4 (W % b == 0, aligned)
+  uint32_t rowmajor;        // k_bin walks whole rows (nstrips <= kRowMajorStrips)
   double inv[65];           // inv[n] = 1 / (n * 2eb), correctly rounded
   const float *frame;
   const int32_t *peaks;     // npeaks x (panel,row,col)
@@ -85,7 +87,8 @@ struct BatchPlan {
 
 // Launchers (compress.hip).
 // k_prep + k_bin + k_codebook; b = common bin factor of the batch, or 0.
-hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t s, bool debug);
+hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t nsmax, hipStream_t s,
+                                   bool debug);
 // k_encode + k_tail + k_roi.
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s);
 
