@@ -152,24 +152,20 @@ __device__ __forceinline__ int32_t from_left(int32_t v, int32_t first) {
   return __builtin_amdgcn_update_dpp(first, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
 
-// q = rint(S / den) with den = n*2eb, S/den correctly rounded.  Fast path:
-// t1 = S * inv with inv = 1/den (correctly rounded) is within 3 ulp-relative
-// of the exact quotient; when |t1| < 2^28 and t1 is more than 2^-20 away from
-// a half-integer, no half-integer lies between t1 and the correctly rounded
-// quotient (their distance is below 2^28 * 3 * 2^-53 < 2^-23), so rint of
-// both is the same integer.  Otherwise the exact division is taken.
+// q = rint(S / den) with den = n*2eb and S/den correctly rounded.  Fast path:
+// t1 = S * inv with inv = 1/den correctly rounded differs from the exact
+// quotient x by at most (2u + u^2)|x| and from the rounded quotient by at
+// most 3.01u|x| (u = 2^-53).  When |t1 - rint(t1)| < 0.5 - 2^-20, t1 lies
+// more than 2^-20 from the half-integers around rint(t1); for |x| < 2^31 the
+// rounded quotient is then within 2^-22 of t1, on the same side, and rounds
+// to the same integer.  Larger |x| make both results exceed 2^28 - 1 (a range
+// error either way), and NaN/Inf fail the test.  Otherwise: the divide.
 __device__ __forceinline__ int32_t quantize(double S, uint32_t n, double step, double inv,
                                             bool &range_err) {
   if (n == 0) return 0;
   const double t1 = S * inv;
-  const double d = t1 - floor(t1) - 0.5;
-  double t;
-  if (fabs(t1) < 268435456.0 && fabs(d) > 0x1p-20) {
-    t = rint(t1);
-  } else {
-    const double den = (double)n * step;
-    t = rint(S / den);
-  }
+  double t = rint(t1);
+  if (!(fabs(t1 - t) < 0.5 - 0x1p-20)) t = rint(S / ((double)n * step));
   if (!(fabs(t) <= kQMax)) {
     range_err = true;
     return 0;
