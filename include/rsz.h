@@ -24,9 +24,9 @@
  * Frame layout: panels x height x width float32, C-contiguous.  Stream
  * layout (little-endian, sections 4-byte aligned): 80-byte header, peaks
  * (u16 panel,row,col), ROI payload (npeaks*w*w u32 bit patterns, 0 outside
- * the panel), code lengths (1024 u8), outlier bin indices (u32), outlier
- * residuals (i32), chunk bit offsets (u32, one per 4096 symbols), bitstream
- * (u32 words, codewords MSB-first).
+ * the panel), code lengths (1024 u8), chunk bit offsets (u32, one per 4096
+ * symbols), bitstream (u32 words, codewords MSB-first), outlier bin indices
+ * (u32), outlier residuals (i32).
  */
 #ifndef RSZ_H
 #define RSZ_H
@@ -100,13 +100,15 @@ int rsz_compress(const rsz_params *p, const float *d_frame, const rsz_peak *d_pe
 
 /* One frame of a batch.  out/out_cap: that frame's own output buffer
  * (device); the frames of a batch may have different shapes, parameters and
- * peak counts. */
+ * peak counts.  tile_rows: tuning knob, the most bin rows one wave of the
+ * binning kernel walks (0 = library default; clamped to what its LDS holds).
+ * It changes speed only: the output bytes never depend on it. */
 typedef struct {
   rsz_params params;
   const float *frame;
   const rsz_peak *peaks;
   uint32_t npeaks;
-  uint32_t reserved; /* must be 0 */
+  uint32_t tile_rows;
   void *out;
   uint64_t out_cap;
 } rsz_frame_desc;
@@ -126,6 +128,30 @@ int rsz_batch_workspace_bytes(uint32_t nframes, const rsz_frame_desc *h_descs,
  * parameters reports RSZ_ERR_ARG in d_status. */
 int rsz_compress_batch(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t *d_out_bytes,
                        int32_t *d_status, void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* The same batch split in two, for callers that replay it (e.g. from a HIP
+ * graph): rsz_batch_prepare copies the plan of the batch into d_ws (queued on
+ * `stream`) and fills *h_plan, a caller-owned host record; rsz_batch_launch
+ * queues only the kernels of the path, reading the plan from d_ws, and makes
+ * no copy, memset or allocation, so it can be captured and replayed.  Every
+ * replay recomputes all outputs from the frames' current contents; the
+ * descriptors (pointers, shapes, peak counts) are fixed at prepare time. */
+typedef struct {
+  uint64_t opaque[8];
+} rsz_batch_plan;
+
+int rsz_batch_prepare(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t *d_out_bytes,
+                      int32_t *d_status, void *d_ws, uint64_t ws_bytes, void *stream,
+                      rsz_batch_plan *h_plan);
+int rsz_batch_launch(const rsz_batch_plan *h_plan, void *stream);
+
+/* Captures rsz_batch_launch of a prepared plan into a HIP graph on `stream`
+ * (which must not be capturing already) and instantiates it: *h_graph_exec
+ * receives a hipGraphExec_t (as void*).  rsz_graph_launch replays it on a
+ * stream; rsz_graph_destroy frees it. */
+int rsz_batch_graph_create(const rsz_batch_plan *h_plan, void *stream, void **h_graph_exec);
+int rsz_graph_launch(void *graph_exec, void *stream);
+int rsz_graph_destroy(void *graph_exec);
 
 /* Parse and check the 80-byte header of a stream held in host memory
  * (h_stream, n >= 80 bytes).  Fills *p, *npeaks and *stream_bytes.

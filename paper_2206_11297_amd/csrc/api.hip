@@ -152,10 +152,10 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   for (uint32_t f = 0; f < nframes; ++f) {
     ps[f] = &d[f].params;
     np[f] = d[f].npeaks;
-    valid[f] = check_params(ps[f], np[f]) == RSZ_OK && d[f].reserved == 0 && d[f].frame &&
-               d[f].out && (np[f] == 0 || d[f].peaks) &&
-               ((uintptr_t)d[f].frame % 16 == 0) && ((uintptr_t)d[f].out % 16 == 0);
-    if (valid[f]) gs[f] = geometry(ps[f], np[f], th_cap);
+    valid[f] = check_params(ps[f], np[f]) == RSZ_OK && d[f].frame && d[f].out &&
+               (np[f] == 0 || d[f].peaks) && ((uintptr_t)d[f].frame % 16 == 0) &&
+               ((uintptr_t)d[f].out % 16 == 0);
+    if (valid[f]) gs[f] = geometry(ps[f], np[f], d[f].tile_rows ? d[f].tile_rows : th_cap);
   }
   Layout L = layout(nframes, ps, np, gs, valid);
   if (need) *need = L.total;
@@ -301,6 +301,13 @@ static int stage_to_device(void *dst, const void *src, size_t n, hipStream_t s) 
   if (hipEventRecord(sl.ev, s) != hipSuccess) return RSZ_ERR_HIP;
   return RSZ_OK;
 }
+
+// Host record of a prepared batch (the public rsz_batch_plan is its storage).
+struct PlanRecord {
+  BatchPlan bp;
+  uint32_t common_b, nsmax;
+};
+static_assert(sizeof(PlanRecord) <= sizeof(rsz_batch_plan), "plan record too large");
 
 // Queue the whole path for a batch; results land in res_bytes/res_status.
 static int enqueue(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_bytes,
@@ -573,6 +580,76 @@ int rsz_decompress(const void *d_in, uint64_t in_bytes, float *d_frame, uint64_t
     return RSZ_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return RSZ_ERR_HIP;
   return status;
+}
+
+int rsz_batch_prepare(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t *d_out_bytes,
+                      int32_t *d_status, void *d_ws, uint64_t ws_bytes, void *stream,
+                      rsz_batch_plan *h_plan) {
+  if (nframes == 0 || !h_descs || !d_out_bytes || !d_status || !d_ws || !h_plan) return RSZ_ERR_ARG;
+  if ((uintptr_t)d_ws % 256) return RSZ_ERR_ARG;
+  HostPlan hp;
+  const int st = build_plan(nframes, h_descs, d_out_bytes, d_status, (uint8_t *)d_ws, ws_bytes,
+                            default_th_cap(nframes), hp, nullptr, nullptr);
+  if (st) return st;
+  if (stage_to_device(d_ws, hp.bytes.data(), hp.bytes.size(), (hipStream_t)stream) != RSZ_OK)
+    return RSZ_ERR_HIP;
+  PlanRecord rec;
+  rec.bp = hp.bp;
+  rec.common_b = hp.common_b;
+  rec.nsmax = hp.nsmax;
+  memset(h_plan, 0, sizeof *h_plan);
+  memcpy(h_plan, &rec, sizeof rec);
+  return RSZ_OK;
+}
+
+int rsz_batch_launch(const rsz_batch_plan *h_plan, void *stream) {
+  if (!h_plan) return RSZ_ERR_ARG;
+  PlanRecord rec;
+  memcpy(&rec, h_plan, sizeof rec);
+  if (rec.bp.nframes == 0 || !rec.bp.frames) return RSZ_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_compress_front_b(rec.bp, rec.common_b, rec.nsmax, s, false) != hipSuccess)
+    return RSZ_ERR_HIP;
+  if (launch_compress_back(rec.bp, s) != hipSuccess) return RSZ_ERR_HIP;
+  return RSZ_OK;
+}
+
+int rsz_batch_graph_create(const rsz_batch_plan *h_plan, void *stream, void **h_graph_exec) {
+  if (!h_plan || !h_graph_exec) return RSZ_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipGraph_t g = nullptr;
+  // timing events are not recorded into graphs
+  const bool prof = g_prof_on;
+  g_prof_on = false;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    g_prof_on = prof;
+    return RSZ_ERR_HIP;
+  }
+  const int st = rsz_batch_launch(h_plan, stream);
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  g_prof_on = prof;
+  if (st != RSZ_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != RSZ_OK ? st : RSZ_ERR_HIP;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return RSZ_ERR_HIP;
+  *h_graph_exec = (void *)ex;
+  return RSZ_OK;
+}
+
+int rsz_graph_launch(void *graph_exec, void *stream) {
+  if (!graph_exec) return RSZ_ERR_ARG;
+  return hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream) == hipSuccess
+             ? RSZ_OK
+             : RSZ_ERR_HIP;
+}
+
+int rsz_graph_destroy(void *graph_exec) {
+  if (!graph_exec) return RSZ_ERR_ARG;
+  return hipGraphExecDestroy((hipGraphExec_t)graph_exec) == hipSuccess ? RSZ_OK : RSZ_ERR_HIP;
 }
 
 int rsz_profile_enable(int enable) {

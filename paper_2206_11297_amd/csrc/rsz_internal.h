@@ -22,7 +22,7 @@ constexpr uint64_t kHeader = 80;
 constexpr int kWaves = 4;
 constexpr int kMaxTH = 32;
 constexpr int kMaskRowsMax = 72;      // (TH+1)*b raw rows per segment
-constexpr int kMaskWords = 1152;      // per wave: rows * 2b words (per strip)
+constexpr int kMaskWords = 896;       // per wave: rows * 2b words (per strip)
 constexpr int kRowMajorStrips = 8;   // widest panel row (in 64-bin strips) walked row-major
 
 inline __host__ __device__ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }

@@ -17,6 +17,8 @@ RSZ_BIN_BACKGROUND, RSZ_BIN_ALL = 0, 1
 
 EXPORTS = ["rsz_status_string", "rsz_max_compressed_bytes", "rsz_workspace_bytes",
            "rsz_compress", "rsz_batch_workspace_bytes", "rsz_compress_batch",
+           "rsz_batch_prepare", "rsz_batch_launch", "rsz_batch_graph_create",
+           "rsz_graph_launch", "rsz_graph_destroy",
            "rsz_stream_info", "rsz_decompress_workspace_bytes", "rsz_decompress",
            "rsz_debug_intermediates", "rsz_profile_enable", "rsz_profile_read"]
 
@@ -35,8 +37,12 @@ class rsz_params(C.Structure):
 
 class rsz_frame_desc(C.Structure):
     _fields_ = [("params", rsz_params), ("frame", C.c_void_p), ("peaks", C.c_void_p),
-                ("npeaks", C.c_uint32), ("reserved", C.c_uint32), ("out", C.c_void_p),
+                ("npeaks", C.c_uint32), ("tile_rows", C.c_uint32), ("out", C.c_void_p),
                 ("out_cap", C.c_uint64)]
+
+
+class rsz_batch_plan(C.Structure):
+    _fields_ = [("opaque", C.c_uint64 * 8)]
 
 
 class rsz_debug_bufs(C.Structure):
@@ -67,6 +73,12 @@ def lib():
         L.rsz_compress.argtypes = [P(rsz_params), vp, vp, u32, vp, u64, P(u64), vp, u64, vp]
         L.rsz_batch_workspace_bytes.argtypes = [u32, P(rsz_frame_desc), P(u64)]
         L.rsz_compress_batch.argtypes = [u32, P(rsz_frame_desc), vp, vp, vp, u64, vp]
+        L.rsz_batch_prepare.argtypes = [u32, P(rsz_frame_desc), vp, vp, vp, u64, vp,
+                                        P(rsz_batch_plan)]
+        L.rsz_batch_launch.argtypes = [P(rsz_batch_plan), vp]
+        L.rsz_batch_graph_create.argtypes = [P(rsz_batch_plan), vp, P(vp)]
+        L.rsz_graph_launch.argtypes = [vp, vp]
+        L.rsz_graph_destroy.argtypes = [vp]
         L.rsz_stream_info.argtypes = [vp, u64, P(rsz_params), P(u32), P(u64)]
         L.rsz_decompress_workspace_bytes.argtypes = [vp, u64, P(u64)]
         L.rsz_decompress.argtypes = [vp, u64, vp, u64, vp, u64, vp]
@@ -119,6 +131,32 @@ def rsz_compress_batch(descs, d_out_bytes, d_status, d_ws, ws_bytes, stream):
     arr = (rsz_frame_desc * len(descs))(*descs)
     return lib().rsz_compress_batch(len(descs), arr, d_out_bytes, d_status, d_ws, ws_bytes,
                                     stream)
+
+
+def rsz_batch_prepare(descs, d_out_bytes, d_status, d_ws, ws_bytes, stream):
+    arr = (rsz_frame_desc * len(descs))(*descs)
+    plan = rsz_batch_plan()
+    st = lib().rsz_batch_prepare(len(descs), arr, d_out_bytes, d_status, d_ws, ws_bytes, stream,
+                                 C.byref(plan))
+    return st, plan
+
+
+def rsz_batch_launch(plan, stream):
+    return lib().rsz_batch_launch(C.byref(plan), stream)
+
+
+def rsz_batch_graph_create(plan, stream):
+    ex = C.c_void_p()
+    st = lib().rsz_batch_graph_create(C.byref(plan), stream, C.byref(ex))
+    return st, ex
+
+
+def rsz_graph_launch(graph_exec, stream):
+    return lib().rsz_graph_launch(graph_exec, stream)
+
+
+def rsz_graph_destroy(graph_exec):
+    return lib().rsz_graph_destroy(graph_exec)
 
 
 def rsz_stream_info(h_bytes):
@@ -279,7 +317,7 @@ class Batch:
     tuple for all.  Output buffers are sized by rsz_max_compressed_bytes and
     packed into one uint8 tensor."""
 
-    def __init__(self, frames, peaks, prm):
+    def __init__(self, frames, peaks, prm, tile_rows=0):
         torch = _torch()
         self.frames = [f.contiguous() for f in frames]
         self.peaks = [pk.to(dtype=torch.int32).reshape(-1, 3).contiguous() for pk in peaks]
@@ -308,7 +346,7 @@ class Batch:
             d.frame = self.frames[i].data_ptr()
             d.peaks = self.peaks[i].data_ptr() if self.peaks[i].shape[0] else None
             d.npeaks = self.peaks[i].shape[0]
-            d.reserved = 0
+            d.tile_rows = int(tile_rows)
             d.out = self.out.data_ptr() + self.offsets[i]
             d.out_cap = caps[i]
             self.descs.append(d)
@@ -325,6 +363,41 @@ class Batch:
                                 self.ws.numel(), _stream())
         if st:
             raise RszError(st, "rsz_compress_batch")
+
+    def prepare(self):
+        """Upload the plan once; launch() / graph() then replay only kernels."""
+        st, self.plan = rsz_batch_prepare(self.descs, _ptr(self.sizes), _ptr(self.status),
+                                          _ptr(self.ws), self.ws.numel(), _stream())
+        if st:
+            raise RszError(st, "rsz_batch_prepare")
+
+    def launch(self):
+        st = rsz_batch_launch(self.plan, _stream())
+        if st:
+            raise RszError(st, "rsz_batch_launch")
+
+    def graph(self):
+        """Capture the prepared batch into a HIP graph (replay with replay())."""
+        torch = _torch()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        st, self.graph_exec = rsz_batch_graph_create(self.plan, C.c_void_p(side.cuda_stream))
+        if st:
+            raise RszError(st, "rsz_batch_graph_create")
+        torch.cuda.current_stream().wait_stream(side)
+
+    def replay(self):
+        st = rsz_graph_launch(self.graph_exec, _stream())
+        if st:
+            raise RszError(st, "rsz_graph_launch")
+
+    def __del__(self):
+        ex = getattr(self, "graph_exec", None)
+        if ex is not None and ex.value:
+            try:
+                rsz_graph_destroy(ex)
+            except Exception:
+                pass
 
     def stream(self, i, sizes=None):
         """Stream of frame i as a GPU uint8 view (after the stream finished)."""

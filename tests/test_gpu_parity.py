@@ -211,3 +211,57 @@ def test_batch_reports_per_frame_errors(torch):
     assert B.status.cpu().tolist() == [0, rsz.RSZ_ERR_PEAK, rsz.RSZ_ERR_ARG]
     st, ref, _ = O.compress(O.params(2, 20, 20, 3, 2, 1.0), good, gp)
     np.testing.assert_array_equal(B.stream(0).cpu().numpy(), ref)
+
+
+def _oracle_streams(cases, prm):
+    out = []
+    for (f, pk), (w, b, eb, mode) in zip(cases, prm):
+        st, ref, _ = O.compress(O.params(*f.shape, w, b, eb, mode), f, pk)
+        assert st == O.OK
+        out.append(ref)
+    return out
+
+
+def test_batch_prepare_launch_and_graph_replays(torch):
+    """The prepared plan replays (eagerly and from a HIP graph) with the frames
+    changed in between: every replay matches the oracle on the current
+    contents."""
+    cases = [synth.cspad_frame(9), synth.jungfrau_frame(4), synth.tiny_case(43, (2, 33, 70), 3,
+                                                                            "normal")]
+    prm = [(17, 2, 10.0, 0), (25, 4, 10.0, 0), (3, 3, 1.0, 1)]
+    frames = [_gpu(torch, f) for f, _ in cases]
+    peaks = [_gpu(torch, p) for _, p in cases]
+    B = rsz.Batch(frames, peaks, prm)
+    B.prepare()
+    B.launch()
+    torch.cuda.synchronize()
+    for i, ref in enumerate(_oracle_streams(cases, prm)):
+        np.testing.assert_array_equal(B.stream(i).cpu().numpy(), ref)
+    B.graph()
+    rng = np.random.default_rng(77)
+    for rep in range(3):
+        # eager work between replays: new frame contents, written in place
+        cur = []
+        for (f, pk), g in zip(cases, frames):
+            f2 = (f + rng.normal(0, 3, f.shape)).astype(np.float32)
+            g.copy_(torch.from_numpy(f2))
+            cur.append((f2, pk))
+        torch.cuda.synchronize()
+        B.replay()
+        torch.cuda.synchronize()
+        assert B.status.cpu().tolist() == [0, 0, 0]
+        for i, ref in enumerate(_oracle_streams(cur, prm)):
+            np.testing.assert_array_equal(B.stream(i).cpu().numpy(), ref)
+
+
+def test_tile_rows_never_change_bytes(torch):
+    frame, peaks = synth.cspad_frame(10)
+    ref = None
+    for tr in (0, 1, 3, 8, 17, 32, 100):
+        B = rsz.Batch([_gpu(torch, frame)], [_gpu(torch, peaks)], (17, 2, 10.0, 0), tile_rows=tr)
+        B.run()
+        torch.cuda.synchronize()
+        got = B.stream(0).cpu().numpy()
+        if ref is None:
+            st, ref, _ = O.compress(O.params(32, 185, 388, 17, 2, 10.0, 0), frame, peaks)
+        np.testing.assert_array_equal(got, ref)
