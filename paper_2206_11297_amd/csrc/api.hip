@@ -111,8 +111,7 @@ static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const G
   b += align_up(2ull * kChunk * g.nchunks, 256);  // codes, padded to whole chunks
   b += align_up(4ull * g.nbins, 256);          // rbuf
   b += align_up(4ull * g.nbins, 256);          // obuf
-  b += align_up(8ull * g.nchunks, 256);        // chunk_desc
-  b += 2 * align_up(4ull * g.nchunks, 256);    // chunk_off, head
+  b += 3 * align_up(4ull * g.nchunks, 256);    // chunk_off, chunk_oo, head
   return b;
 }
 
@@ -122,7 +121,7 @@ static Layout layout(uint32_t nframes, const std::vector<const rsz_params *> &ps
   Layout L;
   L.plans = 0;
   L.prefix = align_up(sizeof(FramePlan) * nframes, 256);
-  L.states = L.prefix + align_up(3 * 4ull * (nframes + 1) + 4, 256);
+  L.states = L.prefix + align_up(4 * 4ull * (nframes + 1), 256);
   L.frames_begin = L.states + align_up(sizeof(FrameState) * nframes, 256);
   uint64_t off = L.frames_begin;
   L.frame_off.resize(nframes);
@@ -166,15 +165,21 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   uint32_t *tp = (uint32_t *)(hp.bytes.data() + L.prefix);
   uint32_t *cp = tp + (nframes + 1);
   uint32_t *rp = cp + (nframes + 1);
-  uint64_t tiles = 0, chunks = 0, npk_total = 0;
+  uint32_t *kp = rp + (nframes + 1);
+  uint64_t tiles = 0, units = 0, npk_total = 0, all_chunks = 0, chunks_done = 0;
+  for (uint32_t f = 0; f < nframes; ++f)
+    if (valid[f]) all_chunks += gs[f].nchunks;
+  // chunks per encode workgroup: about 8192 workgroups for large batches
+  const uint32_t cpw = (uint32_t)std::min<uint64_t>(32, std::max<uint64_t>(1, all_chunks / 8192));
   hp.common_b = 0;
   bool first = true;
   for (uint32_t f = 0; f < nframes; ++f) {
     FramePlan &fp = fpl[f];
     memset(&fp, 0, sizeof fp);
     tp[f] = (uint32_t)tiles;
-    cp[f] = (uint32_t)chunks;
+    cp[f] = (uint32_t)units;
     rp[f] = (uint32_t)npk_total;
+    kp[f] = (uint32_t)chunks_done;
     fp.st = (FrameState *)(ws + L.states) + f;
     fp.res_bytes = res_bytes + f;
     fp.res_status = res_status + f;
@@ -229,9 +234,9 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     base += align_up(4ull * g.nbins, 256);
     fp.obuf = (uint32_t *)base;
     base += align_up(4ull * g.nbins, 256);
-    fp.chunk_desc = (uint64_t *)base;
-    base += align_up(8ull * g.nchunks, 256);
     fp.chunk_off = (uint32_t *)base;
+    base += align_up(4ull * g.nchunks, 256);
+    fp.chunk_oo = (uint32_t *)base;
     base += align_up(4ull * g.nchunks, 256);
     fp.head = (uint32_t *)base;
     if (dbg) {
@@ -241,7 +246,8 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
       fp.dbg_q = dbg->q;
     }
     tiles += (uint64_t)p->panels * g.groups;
-    chunks += g.nchunks;
+    units += div_up(g.nchunks, cpw);
+    chunks_done += g.nchunks;
     npk_total += np[f];
     if (first) {
       hp.common_b = p->bin;
@@ -250,19 +256,24 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
       hp.common_b = 0;
     }
   }
-  if (tiles >= (1ull << 31) || chunks >= (1ull << 31) || npk_total >= (1ull << 31))
+  if (tiles >= (1ull << 31) || units >= (1ull << 31) || npk_total >= (1ull << 31) ||
+      chunks_done >= (1ull << 31))
     return RSZ_ERR_ARG;
   tp[nframes] = (uint32_t)tiles;
-  cp[nframes] = (uint32_t)chunks;
+  cp[nframes] = (uint32_t)units;
   rp[nframes] = (uint32_t)npk_total;
+  kp[nframes] = (uint32_t)chunks_done;
   hp.bp.nframes = nframes;
+  hp.bp.total_chunks = (uint32_t)chunks_done;
   hp.bp.total_tiles = (uint32_t)tiles;
-  hp.bp.total_chunks = (uint32_t)chunks;
+  hp.bp.total_units = (uint32_t)units;
   hp.bp.total_peaks = (uint32_t)npk_total;
+  hp.bp.cpw = cpw;
   hp.bp.frames = (const FramePlan *)(ws + L.plans);
   hp.bp.tile_prefix = (const uint32_t *)(ws + L.prefix);
-  hp.bp.chunk_prefix = hp.bp.tile_prefix + (nframes + 1);
-  hp.bp.peak_prefix = hp.bp.chunk_prefix + (nframes + 1);
+  hp.bp.unit_prefix = hp.bp.tile_prefix + (nframes + 1);
+  hp.bp.peak_prefix = hp.bp.unit_prefix + (nframes + 1);
+  hp.bp.chunk_prefix = hp.bp.peak_prefix + (nframes + 1);
   return RSZ_OK;
 }
 

@@ -9,9 +9,10 @@
 //               2D Lorenzo + code/outlier + histogram; one wave per segment
 //               of bin rows of a panel, walking it in 64-column strips.
 //   k_codebook  one workgroup per frame: Huffman lengths and canonical codes.
-//   k_encode    one workgroup per 4096-symbol chunk, single pass: chunk bit
-//               and outlier offsets by a decoupled look-back scan over the
-//               chunks of the frame, then bit-packing and outlier indices.
+//   k_count     one wave per 4096-symbol chunk: its bits and outliers.
+//   k_scan      one workgroup per frame: chunk bit and outlier offsets.
+//   k_encode    one workgroup per run of chunks: bit-packing and outlier
+//               indices at the offsets k_codebook computed.
 //   k_tail      one workgroup per frame: sizes, capacity, header, chunk
 //               boundary words, outlier sections.
 //   k_roi       one workgroup per peak: ROI window payload, bit copies.
@@ -81,13 +82,11 @@ __global__ __launch_bounds__(256) void k_prep(BatchPlan bp) {
   if (threadIdx.x == 0) {
     s_bad = 0;
     st->status = fp.init_status;
-    st->ticket = 0;
     st->n_out = 0;
     st->T = 0;
     st->total = 0;
   }
   if (fp.init_status != RSZ_OK) return;
-  for (uint32_t c = threadIdx.x; c < fp.nchunks; c += 256) fp.chunk_desc[c] = 0ull;
   for (uint32_t p = threadIdx.x; p <= fp.P; p += 256) fp.pstart[p] = 0;
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) {
@@ -700,153 +699,175 @@ __global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
   }
 }
 
+// ---------------------------------------------------------------- k_count
+
+// Bits and outliers of every 4096-symbol chunk: one wave per chunk, 64 codes
+// per lane (the codes region is padded to whole chunks, so the 16-byte loads
+// stay inside it).  Work item = (frame, chunk) through the chunk prefix, four
+// per workgroup.
+__global__ __launch_bounds__(256) void k_count(BatchPlan bp) {
+  __shared__ uint4 s_len4[4][kNumSym / 16];   // each wave's frame code lengths
+  // the four chunks of a workgroup may span frames: each wave finds its own
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t item = blockIdx.x * 4 + wv;
+  if (item >= bp.total_chunks) return;
+  const uint32_t fw = find_frame(bp.chunk_prefix, bp.nframes, item);
+  const FramePlan &fp = bp.frames[fw];
+  if (load_status(fp.st) != RSZ_OK) return;
+  const uint32_t c = item - bp.chunk_prefix[fw];
+  const uint32_t g0 = c * kChunk + lane * 64;
+  const uint4 *cv = (const uint4 *)(fp.codes + g0);
+  uint4 v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = cv[k];
+  s_len4[wv][lane] = ((const uint4 *)fp.st->lens)[lane];
+  wave_sync();
+  const uint8_t *lens = (const uint8_t *)s_len4[wv];
+  uint32_t bits = 0, nout = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t w4[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t code = (w4[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+      const bool in = g0 + k * 8 + e < fp.nbins;
+      bits += in ? lens[code & (kNumSym - 1)] : 0u;
+      nout += (in && code == 0) ? 1u : 0u;
+    }
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    bits += __shfl_xor(bits, d);
+    nout += __shfl_xor(nout, d);
+  }
+  if (lane == 0) {
+    fp.chunk_off[c] = bits;
+    fp.chunk_oo[c] = nout;
+  }
+}
+
+// ----------------------------------------------------------------- k_scan
+
+// Exclusive scans of the chunk counts of a frame: chunk bit offsets, chunk
+// outlier offsets, and the frame totals.
+__global__ __launch_bounds__(256) void k_scan(BatchPlan bp) {
+  const FramePlan &fp = bp.frames[blockIdx.x];
+  FrameState *st = fp.st;
+  __shared__ uint64_t s_tmp[4];
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
+  __syncthreads();
+  if (!s_ok) return;
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < fp.nchunks; base += 256) {
+    const uint32_t c = base + threadIdx.x;
+    const uint64_t v = c < fp.nchunks ? (((uint64_t)fp.chunk_oo[c] << 32) | fp.chunk_off[c]) : 0;
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan<uint64_t>(v, s_tmp, tot) + carry;
+    if (c < fp.nchunks) {
+      fp.chunk_off[c] = (uint32_t)ex;
+      fp.chunk_oo[c] = (uint32_t)(ex >> 32);
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    st->T = (uint32_t)carry;
+    st->n_out = (uint32_t)(carry >> 32);
+  }
+}
+
 // --------------------------------------------------------------- k_encode
 
-// Look-back descriptor of a chunk: flag (bits 62-63: 1 = this chunk's own
-// totals, 2 = totals of all chunks up to and including it), outlier count
-// (bits 32-58) and bit count (bits 0-31).  Frame totals stay below 2^32 bits
-// and 2^27 outliers, so packed values add without carries between fields.
-constexpr uint64_t kDescAgg = 1ull << 62, kDescInc = 2ull << 62;
-constexpr uint64_t kDescVal = (1ull << 62) - 1;
-constexpr uint32_t kSpinLimit = 1u << 24;
-
-// A descriptor carries everything a later chunk needs from it, so relaxed
-// agent-scope atomics suffice: no other memory is published through it, and
-// release/acquire ordering here would write back and invalidate the L2 on
-// every publish and poll.
-__device__ __forceinline__ void put_desc(uint64_t *d, uint64_t v) {
-  __hip_atomic_store(d, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t get_desc(const uint64_t *d) {
-  return __hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// The chunks of a frame are taken in the order of a per-frame ticket, so every
-// chunk a workgroup looks back at belongs to a workgroup that started earlier
-// and publishes its own totals before it waits for anything: the wait always
-// ends.  A spin limit bounds it
-// anyway and turns a stall into an error status.
+// One workgroup per run of bp.cpw consecutive chunks of a frame; each chunk's
+// bit and outlier offsets come from k_codebook, so no workgroup waits for
+// another.  Bits are packed in LDS and stored as whole words; a chunk's first
+// word, when it starts mid-word, is shared with the previous chunk and goes
+// to head[] for k_tail to merge.
 __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
   __shared__ uint8_t s_len[kNumSym];
   __shared__ uint32_t s_cw[kNumSym];
   __shared__ uint32_t s_words[kChunk + 2];
   __shared__ uint64_t s_tmp[4];
-  __shared__ uint64_t s_prefix;
-  __shared__ uint32_t s_lc;
   __shared__ int s_ok;
-  const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, blockIdx.x);
+  const uint32_t f = find_frame(bp.unit_prefix, bp.nframes, blockIdx.x);
   const FramePlan &fp = bp.frames[f];
-  FrameState *st = fp.st;
-  if (threadIdx.x == 0) {
-    s_ok = load_status(st) == RSZ_OK;
-    if (s_ok) s_lc = atomicAdd(&st->ticket, 1u);
-  }
+  const FrameState *st = fp.st;
+  if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
   __syncthreads();
-  if (!s_ok) return;  // every chunk of the frame skips: nobody waits on it
+  if (!s_ok) return;
   for (int s = threadIdx.x; s < kNumSym; s += 256) {
     s_len[s] = st->lens[s];
     s_cw[s] = st->cw[s];
   }
-  __syncthreads();
-  const uint32_t lc = s_lc;
-  const uint32_t g0 = lc * kChunk + threadIdx.x * 16;
-  // the codes region is padded to whole chunks: both 16-byte loads stay inside
-  const uint4 *cv = (const uint4 *)(fp.codes + g0);
-  const uint4 c0 = cv[0], c1 = cv[1];
-  const uint32_t w8[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-  uint32_t code[16];
-  uint32_t bits = 0, nout = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const uint32_t g = g0 + k;
-    code[k] = g < fp.nbins ? ((w8[k >> 1] >> (16 * (k & 1))) & 0xFFFFu) : 0xFFFFu;
-    if (g < fp.nbins) {
-      bits += s_len[code[k]];
-      nout += code[k] == 0;
-    }
-  }
-  uint64_t tot;
-  const uint64_t ex = block_exclusive_scan<uint64_t>(((uint64_t)nout << 32) | bits, s_tmp, tot);
-  if (threadIdx.x < 64) {
-    // wave 0 looks back over windows of 64 preceding chunks: the chunks up
-    // to the nearest one with an inclusive total must all have published
-    const int lane = threadIdx.x;
-    uint64_t prefix = 0;
-    if (lc == 0) {
-      if (lane == 0) put_desc(&fp.chunk_desc[0], kDescInc | tot);
-    } else {
-      if (lane == 0) put_desc(&fp.chunk_desc[lc], kDescAgg | tot);
-      int64_t base = (int64_t)lc - 1;
-      uint32_t spins = 0;
-      for (;;) {
-        const int64_t k = base - lane;
-        const uint64_t v = k >= 0 ? get_desc(&fp.chunk_desc[k]) : kDescInc;
-        const uint64_t flag = v & ~kDescVal;
-        const uint64_t inc = __ballot(flag == kDescInc);
-        const uint64_t notyet = __ballot(flag == 0);
-        const int first = inc ? __builtin_ctzll(inc) : 64;
-        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
-        if (notyet & need) {
-          if (++spins > kSpinLimit) {
-            if (lane == 0) set_status(st, RSZ_ERR_HIP);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        uint64_t x = ((need >> lane) & 1ull) ? (v & kDescVal) : 0ull;
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d);
-        prefix += x;
-        if (first < 64) break;
-        base -= 64;
-      }
-      if (lane == 0) put_desc(&fp.chunk_desc[lc], kDescInc | (prefix + tot));
-    }
-    if (lane == 0) s_prefix = prefix;
-  }
-  __syncthreads();
-  const uint32_t S0 = (uint32_t)s_prefix;
-  const uint32_t O0 = (uint32_t)(s_prefix >> 32);
-  const uint32_t clen = (uint32_t)tot;
-  const uint32_t nwords = ((S0 & 31) + clen + 31) >> 5;
-  for (uint32_t k = threadIdx.x; k < nwords; k += 256) s_words[k] = 0u;
-  __syncthreads();
-  uint32_t pos = (S0 & 31) + (uint32_t)ex;
-  uint32_t oi = O0 + (uint32_t)(ex >> 32);
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    if (code[k] == 0xFFFFu) continue;
-    const uint32_t L = s_len[code[k]];
-    const uint64_t v = ((uint64_t)s_cw[code[k]] << (64 - L)) >> (pos & 31);
-    atomicOr(&s_words[pos >> 5], (uint32_t)(v >> 32));
-    if ((pos & 31) + L > 32) atomicOr(&s_words[(pos >> 5) + 1], (uint32_t)v);
-    pos += L;
-    if (code[k] == 0) {
-      if (oi < fp.nbins) fp.obuf[oi] = g0 + k;
-      oi++;
-    }
-  }
-  __syncthreads();
+  const uint32_t c0 = (blockIdx.x - bp.unit_prefix[f]) * bp.cpw;
+  const uint32_t c1 = min(c0 + bp.cpw, fp.nchunks);
   uint8_t *o = fp.out;
   const uint64_t cap = fp.out_cap;
-  if (threadIdx.x == 0) {
-    fp.chunk_off[lc] = S0;
-    if (fp.off_chunks + 4ull * lc + 4 <= cap) *(uint32_t *)(o + fp.off_chunks + 4ull * lc) = S0;
-  }
-  // A partial first word is shared with the previous chunk: its bits go to
-  // head[] and k_tail merges them.  Every other word belongs to this chunk.
   uint32_t *bw = (uint32_t *)(o + fp.off_bits);
-  const uint32_t wlo = S0 >> 5;
-  for (uint32_t k = threadIdx.x; k < nwords; k += 256) {
-    const uint32_t v = s_words[k];
-    if (k == 0 && (S0 & 31)) {
-      fp.head[lc] = v;
-      continue;
+  // the codes region is padded to whole chunks: the 16-byte loads stay inside
+  uint4 n0 = make_uint4(0, 0, 0, 0), n1 = n0;
+  if (c0 < c1) {
+    const uint4 *cv = (const uint4 *)(fp.codes + c0 * kChunk + threadIdx.x * 16);
+    n0 = cv[0];
+    n1 = cv[1];
+  }
+  for (uint32_t lc = c0; lc < c1; ++lc) {
+    const uint32_t g0 = lc * kChunk + threadIdx.x * 16;
+    const uint32_t w8[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+    if (lc + 1 < c1) {   // next chunk's codes in flight while this one is packed
+      const uint4 *cv = (const uint4 *)(fp.codes + g0 + kChunk);
+      n0 = cv[0];
+      n1 = cv[1];
     }
-    const uint64_t widx = (uint64_t)wlo + k;
-    if (fp.off_bits + 4 * widx + 4 <= cap) bw[widx] = v;
+    __syncthreads();   // tables loaded / previous chunk's words written out
+    uint32_t code[16];
+    uint32_t bits = 0, nout = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t g = g0 + k;
+      code[k] = g < fp.nbins ? ((w8[k >> 1] >> (16 * (k & 1))) & 0xFFFFu) : 0xFFFFu;
+      if (g < fp.nbins) {
+        bits += s_len[code[k]];
+        nout += code[k] == 0;
+      }
+    }
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan<uint64_t>(((uint64_t)nout << 32) | bits, s_tmp, tot);
+    const uint32_t S0 = fp.chunk_off[lc];
+    const uint32_t O0 = fp.chunk_oo[lc];
+    const uint32_t clen = (uint32_t)tot;
+    const uint32_t nwords = ((S0 & 31) + clen + 31) >> 5;
+    for (uint32_t k = threadIdx.x; k < nwords; k += 256) s_words[k] = 0u;
+    __syncthreads();
+    uint32_t pos = (S0 & 31) + (uint32_t)ex;
+    uint32_t oi = O0 + (uint32_t)(ex >> 32);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (code[k] == 0xFFFFu) continue;
+      const uint32_t L = s_len[code[k]];
+      const uint64_t v = ((uint64_t)s_cw[code[k]] << (64 - L)) >> (pos & 31);
+      atomicOr(&s_words[pos >> 5], (uint32_t)(v >> 32));
+      if ((pos & 31) + L > 32) atomicOr(&s_words[(pos >> 5) + 1], (uint32_t)v);
+      pos += L;
+      if (code[k] == 0) {
+        if (oi < fp.nbins) fp.obuf[oi] = g0 + k;
+        oi++;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && fp.off_chunks + 4ull * lc + 4 <= cap)
+      *(uint32_t *)(o + fp.off_chunks + 4ull * lc) = S0;
+    const uint32_t wlo = S0 >> 5;
+    for (uint32_t k = threadIdx.x; k < nwords; k += 256) {
+      const uint32_t v = s_words[k];
+      if (k == 0 && (S0 & 31)) {
+        fp.head[lc] = v;
+        continue;
+      }
+      const uint64_t widx = (uint64_t)wlo + k;
+      if (fp.off_bits + 4 * widx + 4 <= cap) bw[widx] = v;
+    }
   }
 }
 
@@ -869,9 +890,8 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
     }
     return;
   }
-  const uint64_t last = get_desc(&fp.chunk_desc[fp.nchunks - 1]) & kDescVal;
-  const uint64_t T = (uint32_t)last;
-  const uint32_t n_out = (uint32_t)(last >> 32);
+  const uint64_t T = st->T;
+  const uint32_t n_out = st->n_out;
   const uint64_t nwords = (T + 31) / 32;
   const uint64_t off_oidx = fp.off_bits + 4 * nwords;
   const uint64_t off_ores = off_oidx + 4ull * n_out;
@@ -879,8 +899,6 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
   const bool fits = total <= fp.out_cap;
   __syncthreads();
   if (threadIdx.x == 0) {
-    st->T = T;
-    st->n_out = n_out;
     st->total = total;
     if (!fits) st->status = RSZ_ERR_CAPACITY;
     *fp.res_status = fits ? RSZ_OK : RSZ_ERR_CAPACITY;
@@ -1005,7 +1023,9 @@ hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t nsm
 }
 
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
-  if (bp.total_chunks) RSZ_LAUNCH("k_encode", k_encode, bp.total_chunks, s, bp);
+  if (bp.total_chunks) RSZ_LAUNCH("k_count", k_count, (bp.total_chunks + 3) / 4, s, bp);
+  RSZ_LAUNCH("k_scan", k_scan, bp.nframes, s, bp);
+  if (bp.total_units) RSZ_LAUNCH("k_encode", k_encode, bp.total_units, s, bp);
   RSZ_LAUNCH("k_tail", k_tail, bp.nframes, s, bp);
   if (bp.total_peaks) RSZ_LAUNCH("k_roi", k_roi, bp.total_peaks, s, bp);
   return hipSuccess;

@@ -30,7 +30,6 @@ inline __host__ __device__ uint64_t align_up(uint64_t x, uint64_t a) { return (x
 // Per-frame mutable state in the workspace.
 struct FrameState {
   int32_t status;
-  uint32_t ticket;     // next chunk of this frame for k_encode
   uint32_t n_out;
   uint64_t T;          // bitstream bits
   uint64_t total;      // stream bytes
@@ -59,8 +58,8 @@ struct FramePlan {
   uint16_t *codes;          // nbins
   int32_t *rbuf;            // nbins, residual of outlier bins
   uint32_t *obuf;           // nbins, outlier bin indices in stream order
-  uint64_t *chunk_desc;     // nchunks look-back descriptors (flag | nout | bits)
-  uint32_t *chunk_off;      // nchunks bit offsets
+  uint32_t *chunk_off;      // nchunks: bit count, then bit offset of each chunk
+  uint32_t *chunk_oo;       // nchunks: outlier count, then outlier offset
   uint32_t *head;           // nchunks: bits of a chunk in its shared first word
   uint32_t *pstart;         // P+1 bucket starts of peaks by panel
   uint32_t *pcursor;        // P scatter cursors
@@ -78,18 +77,20 @@ struct FramePlan {
 // Prefix sums over the frames of a batch, for mapping flat work items.
 struct BatchPlan {
   uint32_t nframes;
-  uint32_t total_tiles, total_chunks, total_peaks;
+  uint32_t total_tiles, total_units, total_peaks, total_chunks;
+  uint32_t cpw;                  // chunks encoded by one k_encode workgroup
   const FramePlan *frames;
   const uint32_t *tile_prefix;   // nframes + 1
-  const uint32_t *chunk_prefix;  // nframes + 1
+  const uint32_t *unit_prefix;   // nframes + 1 (units of cpw chunks)
   const uint32_t *peak_prefix;   // nframes + 1
+  const uint32_t *chunk_prefix;  // nframes + 1
 };
 
 // Launchers (compress.hip).
 // k_prep + k_bin + k_codebook; b = common bin factor of the batch, or 0.
 hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t nsmax, hipStream_t s,
                                    bool debug);
-// k_encode + k_tail + k_roi.
+// k_count + k_scan + k_encode + k_tail + k_roi.
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s);
 
 // Decompression plan and launchers (decompress.hip).
