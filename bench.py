@@ -41,6 +41,70 @@ def generate(n, workers):
             yield item
 
 
+def _gen_pool(k):
+    """Frame k of the serving pool: geometries cycle over CSPAD 32x185x388,
+    Jungfrau 8x512x1024 and a 1x2048x2048 panel; 0-1500 peaks each."""
+    from paper_2206_11297_amd import synth
+    import numpy as np
+    rng = np.random.default_rng([2206, 11297, synth.W_SERVE, k])
+    npk = int(rng.integers(0, 1501))
+    g = k % 3
+    if g == 0:
+        return synth.cspad_frame(k, npeaks=npk, workload=synth.W_SERVE)
+    shape = synth.JUNGFRAU4M if g == 1 else synth.SQUARE4M
+    return synth.jungfrau_frame(k, shape=shape, npeaks=npk, workload=synth.W_SERVE)
+
+
+def serving_section(args, torch, dev):
+    """Poisson-arrival serving of mixed geometries: continuous batching vs one
+    frame per launch at the same offered load, plus a backlogged run."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    from paper_2206_11297_amd import serve
+    npool = args.serve_pool
+    with ProcessPoolExecutor(min(args.workers, npool), mp_context=mp.get_context("fork")) as ex:
+        pool = list(ex.map(_gen_pool, range(npool)))
+    gpool = [(torch.from_numpy(f).to(dev), torch.from_numpy(p).to(dev)) for f, p in pool]
+    torch.cuda.synchronize()
+    out = {"workload": f"serving: Poisson arrivals, pool of {npool} resident frames cycling "
+                       "32x185x388 / 8x512x1024 / 1x2048x2048 f32, 0-1500 peaks, eb from "
+                       "{5,10,20} per request, window 17, bin 2x2",
+           "slots": args.serve_slots, "max_batch": args.serve_batch}
+    limits = serve.SlotLimits(max_frames=args.serve_batch,
+                              out_bytes=args.serve_batch * (14 << 20),
+                              ws_bytes=args.serve_batch * (12 << 20))
+    out["hbm_budget_gb"] = round(args.serve_slots * (limits.out_bytes + limits.ws_bytes) / 1e9, 2)
+    batched = serve.GpuExecutor(args.serve_slots, limits, dev)
+    single_lim = serve.SlotLimits(1, 14 << 20, 12 << 20)
+    single = serve.GpuExecutor(1, single_lim, dev)
+
+    def requests(rate, n, seed):
+        rng = np.random.default_rng([2206, 11297, 3, seed])
+        t = np.cumsum(rng.exponential(1.0 / rate, n)) if rate else np.zeros(n)
+        reqs = []
+        for i in range(n):
+            k = int(rng.integers(0, npool))
+            eb = float([5.0, 10.0, 20.0][int(rng.integers(0, 3))])
+            reqs.append(serve.Request(i, float(t[i]), gpool[k][0], gpool[k][1], (17, 2, eb, 0)))
+        return reqs
+
+    # warm-up of both paths
+    serve.Scheduler(batched, args.serve_slots, limits).run(requests(0, 16, 1))
+    serve.Scheduler(single, 1, single_lim).run(requests(0, 4, 2))
+    for rate in args.serve_rates:
+        reqs = requests(rate * 1e3, args.serve_frames, int(rate))
+        rb = serve.summarize(serve.Scheduler(batched, args.serve_slots, limits).run(reqs), reqs)
+        rs = serve.summarize(serve.Scheduler(single, 1, single_lim).run(reqs), reqs)
+        out[f"{rate:g}kHz"] = {"continuous_batching": rb, "one_frame_per_launch": rs}
+        print(f"[bench] serving {rate:g} kHz: batched p99 {rb['p99_ms']} ms, one-frame p99 "
+              f"{rs['p99_ms']} ms", file=sys.stderr, flush=True)
+    reqs = requests(0, args.serve_frames, 99)
+    out["backlogged"] = serve.summarize(serve.Scheduler(batched, args.serve_slots, limits).run(reqs),
+                                        reqs)
+    return out
+
+
 def traffic_record(kernel):
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source."""
@@ -66,6 +130,12 @@ def main():
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[1.0, 10.0],
+                    help="Poisson arrival rates in kHz for the serving section ([] skips it)")
+    ap.add_argument("--serve-frames", type=int, default=1500)
+    ap.add_argument("--serve-pool", type=int, default=24)
+    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-batch", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the compression path is not sharded "
@@ -164,6 +234,8 @@ def main():
         n_cpu += 1
     cpu_gbps = n_cpu * SHAPE[0] * SHAPE[1] * SHAPE[2] * 4 / cpu_t / 1e9 if n_cpu else None
 
+    serving = serving_section(args, torch, dev) if args.serve_rates else None
+
     line = {
         "metric": "raw-frame GB/s compressed (1 GPU) at eb=10 ADU; compression ratio; "
                   "p99 frame latency",
@@ -189,7 +261,14 @@ def main():
                        "one_frame_per_launch_p99": round(float(np.percentile(lat_ms, 99)), 4),
                        "batched_all_frames": round(ms_step, 4)},
         "kernel_ms": {k: round(v, 4) for k, v in kernel_ms.items()},
+        "serving": serving,
     }
+    if serving:
+        top = serving.get(f"{max(args.serve_rates):g}kHz")
+        if top:
+            line["latency_ms"]["serving_p50"] = top["continuous_batching"]["p50_ms"]
+            line["latency_ms"]["serving_p99"] = top["continuous_batching"]["p99_ms"]
+            line["latency_ms"]["serving_rate_khz"] = max(args.serve_rates)
     print(json.dumps(line), flush=True)
 
 

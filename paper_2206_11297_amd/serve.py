@@ -26,7 +26,7 @@ class Request:
     peaks: object           # int32 [n,3] device tensor
     params: tuple           # (window, bin, eb, bin_mode)
     out_cap: int = 0        # worst-case stream bytes (set by the executor)
-    ws_bytes: int = 0       # workspace bytes as a one-frame batch (upper bound share)
+    ws_bytes: int = 0       # workspace share (bound used by admission, set by the executor)
     raw_bytes: int = 0
 
 
@@ -70,12 +70,19 @@ class Scheduler:
         self.clock = clock
 
     def _form_batch(self, pending):
-        batch = []
-        while pending:
-            cand = batch + [pending[0]]
-            if len(cand) > self.limits.max_frames or not self.ex.fits(cand, self.limits):
+        # running sums of each request's own bound keep admission O(batch);
+        # one exact check of the formed batch follows
+        lim = self.limits
+        batch, out, ws = [], 0, 0
+        while pending and len(batch) < lim.max_frames:
+            r = pending[0]
+            if out + r.out_cap > lim.out_bytes or ws + r.ws_bytes > lim.ws_bytes:
                 break
+            out += r.out_cap
+            ws += r.ws_bytes
             batch.append(pending.popleft())
+        while batch and not self.ex.fits(batch, lim):
+            pending.appendleft(batch.pop())
         return batch
 
     def run(self, requests: Sequence[Request], keep_streams=False) -> List[Result]:
@@ -159,6 +166,14 @@ class GpuExecutor:
             raise rsz.RszError(st, "rsz_max_compressed_bytes")
         r.out_cap = (cap + 255) // 256 * 256
         r.raw_bytes = P * H * W * 4
+        # workspace share: the larger of the frame alone and its per-frame
+        # share in a large batch (the tiling, hence the layout, differs)
+        d1, _ = self._descs(0, [r])
+        st1, w1 = rsz.rsz_batch_workspace_bytes(d1)
+        st16, w16 = rsz.rsz_batch_workspace_bytes(d1 * 16)
+        if st1 or st16:
+            raise rsz.RszError(st1 or st16, "rsz_batch_workspace_bytes")
+        r.ws_bytes = max(w1, -(-w16 // 16)) + 4096
 
     def _descs(self, slot, batch):
         rsz = self.rsz
