@@ -63,26 +63,27 @@ static int check_params(const rsz_params *p, uint32_t npeaks) {
 }
 
 struct Geom {
-  uint32_t Hb, Wb, nbins, nchunks, TH, segs, groups, nstrips, rowmajor;
+  uint32_t Hb, Wb, nbins, nchunks, TH, segs, groups, nstrips, gstrips, cgs;
   uint64_t off_roi, off_lens, off_chunks, off_bits;
   uint64_t max_bytes;
 };
 
-// Segment height: at most kMaxTH bin rows and a mask of at most kMaskRowsMax
-// raw rows per wave; segments are balanced in groups of kWaves per workgroup.
-static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap) {
+// Binning tiles: column groups of at most `gs` strips (the kernel's compiled
+// width for this batch) and segments of at most kMaxTH bin rows whose LDS
+// mask, (TH+1)*b raw rows of wpr words, fits kMaskWords; segments are
+// balanced in groups of kWaves per workgroup.
+static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap, uint32_t gs) {
   Geom g;
   g.Hb = (uint32_t)div_up(p->height, p->bin);
   g.Wb = (uint32_t)div_up(p->width, p->bin);
   g.nbins = p->panels * g.Hb * g.Wb;
   g.nchunks = (uint32_t)div_up(g.nbins, kChunk);
   g.nstrips = (uint32_t)div_up(g.Wb, 64);
-  g.rowmajor = g.nstrips <= (uint32_t)kRowMajorStrips;
-  // the wave's LDS mask covers (TH+1)*b raw rows of one strip (2b words per
-  // row) or, row-major, of the whole panel row (2b*nstrips words per row)
-  uint32_t thmax = g.rowmajor
-                       ? (uint32_t)kMaskWords / (2 * p->bin * p->bin * g.nstrips)
-                       : (uint32_t)kMaskRowsMax / p->bin;
+  g.gstrips = std::max<uint32_t>(1, std::min(gs, g.nstrips));
+  g.cgs = (uint32_t)div_up(g.nstrips, g.gstrips);
+  // one extra word left of a group for its halo column
+  const uint32_t wpr = 2 * p->bin * g.gstrips + (g.cgs > 1 ? 1 : 0);
+  uint32_t thmax = (uint32_t)kMaskWords / (p->bin * wpr);
   thmax = thmax > 1 ? thmax - 1 : 1;
   thmax = std::max<uint32_t>(1, std::min({thmax, (uint32_t)kMaxTH, th_cap}));
   const uint32_t nseg = kWaves * (uint32_t)div_up(g.Hb, (uint64_t)kWaves * thmax);
@@ -105,9 +106,8 @@ struct Layout {
 
 static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const Geom &g) {
   uint64_t b = 0;
-  b += align_up(4ull * (p->panels + 1), 256);  // pstart
-  b += align_up(4ull * p->panels, 256);        // pcursor
-  b += align_up(12ull * npeaks, 256);          // bucket
+  b += align_up(4ull * ((uint64_t)p->panels * g.segs + 1), 256);  // bstart
+  b += align_up(4ull * npeaks, 256);                              // bucket
   b += align_up(2ull * kChunk * g.nchunks, 256);  // codes, padded to whole chunks
   b += align_up(4ull * g.nbins, 256);          // rbuf
   b += align_up(4ull * g.nbins, 256);          // obuf
@@ -137,8 +137,7 @@ static Layout layout(uint32_t nframes, const std::vector<const rsz_params *> &ps
 struct HostPlan {
   std::vector<uint8_t> bytes;
   BatchPlan bp;
-  uint32_t common_b;
-  uint32_t nsmax = 0;   // strips per row of the widest row-major frame
+  uint32_t common_b;    // bin factor of every valid frame, or 0 when they differ
 };
 
 static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_bytes,
@@ -154,8 +153,20 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     valid[f] = check_params(ps[f], np[f]) == RSZ_OK && d[f].frame && d[f].out &&
                (np[f] == 0 || d[f].peaks) && ((uintptr_t)d[f].frame % 16 == 0) &&
                ((uintptr_t)d[f].out % 16 == 0);
-    if (valid[f]) gs[f] = geometry(ps[f], np[f], d[f].tile_rows ? d[f].tile_rows : th_cap);
   }
+  // the binning kernel is compiled for the common bin factor of the batch
+  hp.common_b = 0;
+  bool first = true;
+  for (uint32_t f = 0; f < nframes; ++f) {
+    if (!valid[f]) continue;
+    if (first) hp.common_b = ps[f]->bin;
+    else if (hp.common_b != ps[f]->bin) hp.common_b = 0;
+    first = false;
+  }
+  const uint32_t gsw = (uint32_t)group_strips((int)hp.common_b);
+  for (uint32_t f = 0; f < nframes; ++f)
+    if (valid[f])
+      gs[f] = geometry(ps[f], np[f], d[f].tile_rows ? d[f].tile_rows : th_cap, gsw);
   Layout L = layout(nframes, ps, np, gs, valid);
   if (need) *need = L.total;
   if (!ws) return RSZ_OK;
@@ -171,8 +182,6 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     if (valid[f]) all_chunks += gs[f].nchunks;
   // chunks per encode workgroup: about 8192 workgroups for large batches
   const uint32_t cpw = (uint32_t)std::min<uint64_t>(32, std::max<uint64_t>(1, all_chunks / 8192));
-  hp.common_b = 0;
-  bool first = true;
   for (uint32_t f = 0; f < nframes; ++f) {
     FramePlan &fp = fpl[f];
     memset(&fp, 0, sizeof fp);
@@ -206,8 +215,8 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.segs = g.segs;
     fp.groups = g.groups;
     fp.nstrips = g.nstrips;
-    fp.rowmajor = g.rowmajor;
-    if (g.rowmajor) hp.nsmax = std::max(hp.nsmax, g.nstrips);
+    fp.gstrips = g.gstrips;
+    fp.cgs = g.cgs;
     fp.init_status = RSZ_OK;
     fp.vec = (p->bin == 2 || p->bin == 4) && p->width % p->bin == 0 &&
              (uintptr_t)d[f].frame % (4 * p->bin) == 0;
@@ -222,12 +231,10 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.off_chunks = g.off_chunks;
     fp.off_bits = g.off_bits;
     uint8_t *base = ws + L.frame_off[f];
-    fp.pstart = (uint32_t *)base;
-    base += align_up(4ull * (p->panels + 1), 256);
-    fp.pcursor = (uint32_t *)base;
-    base += align_up(4ull * p->panels, 256);
-    fp.bucket = (int32_t *)base;
-    base += align_up(12ull * np[f], 256);
+    fp.bstart = (uint32_t *)base;
+    base += align_up(4ull * ((uint64_t)p->panels * g.segs + 1), 256);
+    fp.bucket = (uint32_t *)base;
+    base += align_up(4ull * np[f], 256);
     fp.codes = (uint16_t *)base;
     base += align_up(2ull * kChunk * g.nchunks, 256);
     fp.rbuf = (int32_t *)base;
@@ -245,16 +252,10 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
       fp.dbg_n = dbg->n;
       fp.dbg_q = dbg->q;
     }
-    tiles += (uint64_t)p->panels * g.groups;
+    tiles += (uint64_t)p->panels * g.cgs * g.groups;
     units += div_up(g.nchunks, cpw);
     chunks_done += g.nchunks;
     npk_total += np[f];
-    if (first) {
-      hp.common_b = p->bin;
-      first = false;
-    } else if (hp.common_b != p->bin) {
-      hp.common_b = 0;
-    }
   }
   if (tiles >= (1ull << 31) || units >= (1ull << 31) || npk_total >= (1ull << 31) ||
       chunks_done >= (1ull << 31))
@@ -316,7 +317,7 @@ static int stage_to_device(void *dst, const void *src, size_t n, hipStream_t s) 
 // Host record of a prepared batch (the public rsz_batch_plan is its storage).
 struct PlanRecord {
   BatchPlan bp;
-  uint32_t common_b, nsmax;
+  uint32_t common_b;
 };
 static_assert(sizeof(PlanRecord) <= sizeof(rsz_batch_plan), "plan record too large");
 
@@ -328,7 +329,7 @@ static int enqueue(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_byte
                             default_th_cap(nframes), hp, nullptr, dbg);
   if (st) return st;
   if (stage_to_device(ws, hp.bytes.data(), hp.bytes.size(), s) != RSZ_OK) return RSZ_ERR_HIP;
-  if (launch_compress_front_b(hp.bp, hp.common_b, hp.nsmax, s, dbg != nullptr) != hipSuccess)
+  if (launch_compress_front_b(hp.bp, hp.common_b, s, dbg != nullptr) != hipSuccess)
     return RSZ_ERR_HIP;
   if (!front_only && launch_compress_back(hp.bp, s) != hipSuccess) return RSZ_ERR_HIP;
   return RSZ_OK;
@@ -358,7 +359,7 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
   memcpy(&total, h + 64, 8);
   memcpy(&reserved, h + 72, 8);
   if (u[7] != (uint32_t)kRadius || u[12] != kChunk || reserved != 0) return RSZ_ERR_CORRUPT;
-  const Geom g = geometry(&q, np, kMaxTH);
+  const Geom g = geometry(&q, np, kMaxTH, 1);
   const uint64_t n_out = u[11];
   if (u[13] != g.nchunks || n_out > g.nbins || T > 32ull * g.nbins) return RSZ_ERR_CORRUPT;
   const uint64_t off_oidx = g.off_bits + 4 * ((T + 31) / 32);
@@ -425,7 +426,7 @@ int rsz_max_compressed_bytes(const rsz_params *p, uint32_t npeaks, uint64_t *byt
   const int st = check_params(p, npeaks);
   if (st) return st;
   if (!bytes) return RSZ_ERR_ARG;
-  *bytes = geometry(p, npeaks, kMaxTH).max_bytes;
+  *bytes = geometry(p, npeaks, kMaxTH, 1).max_bytes;
   return RSZ_OK;
 }
 
@@ -607,7 +608,6 @@ int rsz_batch_prepare(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t 
   PlanRecord rec;
   rec.bp = hp.bp;
   rec.common_b = hp.common_b;
-  rec.nsmax = hp.nsmax;
   memset(h_plan, 0, sizeof *h_plan);
   memcpy(h_plan, &rec, sizeof rec);
   return RSZ_OK;
@@ -619,7 +619,7 @@ int rsz_batch_launch(const rsz_batch_plan *h_plan, void *stream) {
   memcpy(&rec, h_plan, sizeof rec);
   if (rec.bp.nframes == 0 || !rec.bp.frames) return RSZ_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
-  if (launch_compress_front_b(rec.bp, rec.common_b, rec.nsmax, s, false) != hipSuccess)
+  if (launch_compress_front_b(rec.bp, rec.common_b, s, false) != hipSuccess)
     return RSZ_ERR_HIP;
   if (launch_compress_back(rec.bp, s) != hipSuccess) return RSZ_ERR_HIP;
   return RSZ_OK;

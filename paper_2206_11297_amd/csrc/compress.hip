@@ -4,10 +4,11 @@
 // batch; every kernel maps its flat work index to a frame with the prefix
 // sums of the batch plan):
 //   k_prep      one workgroup per frame: clear the histogram, check the peaks,
-//               bucket them by panel.
+//               bucket them by band of segment rows.
 //   k_bin       fused ROI mask + b x b background binning + prequantisation +
-//               2D Lorenzo + code/outlier + histogram; one wave per segment
-//               of bin rows of a panel, walking it in 64-column strips.
+//               2D Lorenzo + code/outlier + histogram; one wave per tile
+//               (segment of bin rows x column group of 64-column strips of a
+//               panel), walking it row by row.
 //   k_codebook  one workgroup per frame: Huffman lengths and canonical codes.
 //   k_count     one wave per 4096-symbol chunk: its bits and outliers.
 //   k_scan      one workgroup per frame: chunk bit and outlier offsets.
@@ -73,11 +74,15 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *s_tmp, T &total) {
 
 // ----------------------------------------------------------------- k_prep
 
+// Keys of the band counting sort held in LDS per pass over the peaks.
+constexpr uint32_t kPrepKeys = 4096;
+
 __global__ __launch_bounds__(256) void k_prep(BatchPlan bp) {
   const FramePlan &fp = bp.frames[blockIdx.x];
   FrameState *st = fp.st;
   __shared__ int s_bad;
   __shared__ uint32_t s_tmp[4];
+  __shared__ uint32_t s_cnt[kPrepKeys];
   for (int i = threadIdx.x; i < kNumSym; i += 256) st->hist[i] = 0;
   if (threadIdx.x == 0) {
     s_bad = 0;
@@ -87,7 +92,6 @@ __global__ __launch_bounds__(256) void k_prep(BatchPlan bp) {
     st->total = 0;
   }
   if (fp.init_status != RSZ_OK) return;
-  for (uint32_t p = threadIdx.x; p <= fp.P; p += 256) fp.pstart[p] = 0;
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) {
     const int32_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
@@ -100,32 +104,64 @@ __global__ __launch_bounds__(256) void k_prep(BatchPlan bp) {
     if (threadIdx.x == 0) st->status = RSZ_ERR_PEAK;
     return;
   }
-  for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) atomicAdd(&fp.pstart[fp.peaks[3 * k] + 1], 1u);
-  __threadfence();
-  __syncthreads();
-  // inclusive scan of pstart[1..P] (counts) -> bucket starts
+  // Counting sort of the peaks by band (panel, segment of raw rows), so that
+  // a k_bin wave scans only the bands its rows can touch.  Keys are taken in
+  // passes of kPrepKeys; the order inside a band is irrelevant (the mask is
+  // a union).
+  const uint32_t nkeys = fp.P * fp.segs;
+  const uint32_t band = fp.TH * fp.b;
   uint32_t carry = 0;
-  for (uint32_t base = 1; base <= fp.P; base += 256) {
-    const uint32_t p = base + threadIdx.x;
-    const uint32_t v = p <= fp.P ? __hip_atomic_load(&fp.pstart[p], __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT) : 0u;
+  for (uint32_t k0 = 0; k0 < nkeys; k0 += kPrepKeys) {
+    const uint32_t kn = min(kPrepKeys, nkeys - k0);
+    for (uint32_t i = threadIdx.x; i < kPrepKeys; i += 256) s_cnt[i] = 0;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) {
+      const uint32_t key = (uint32_t)fp.peaks[3 * k] * fp.segs + (uint32_t)fp.peaks[3 * k + 1] / band;
+      if (key - k0 < kn) atomicAdd(&s_cnt[key - k0], 1u);
+    }
+    __syncthreads();
+    // exclusive scan, 16 consecutive keys per thread
+    constexpr int E = kPrepKeys / 256;
+    uint32_t v[E], sum = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      v[e] = s_cnt[threadIdx.x * E + e];
+      sum += v[e];
+    }
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<uint32_t>(v, s_tmp, tot);
-    if (p <= fp.P) {
-      fp.pstart[p] = carry + ex + v;
-      fp.pcursor[p - 1] = carry + ex;
+    uint32_t run = carry + block_exclusive_scan<uint32_t>(sum, s_tmp, tot);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t i = threadIdx.x * E + e;
+      s_cnt[i] = run;
+      if (i < kn) fp.bstart[k0 + i] = run;
+      run += v[e];
     }
     carry += tot;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) {
+      const uint32_t r = (uint32_t)fp.peaks[3 * k + 1], c = (uint32_t)fp.peaks[3 * k + 2];
+      const uint32_t key = (uint32_t)fp.peaks[3 * k] * fp.segs + r / band;
+      if (key - k0 < kn) fp.bucket[atomicAdd(&s_cnt[key - k0], 1u)] = r << 16 | c;
+    }
+    __syncthreads();
   }
-  __threadfence();
-  __syncthreads();
-  for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) {
-    const int32_t pa = fp.peaks[3 * k];
-    const uint32_t pos = atomicAdd(&fp.pcursor[pa], 1u);
-    fp.bucket[3 * pos] = pa;
-    fp.bucket[3 * pos + 1] = fp.peaks[3 * k + 1];
-    fp.bucket[3 * pos + 2] = fp.peaks[3 * k + 2];
-  }
+  if (threadIdx.x == 0) fp.bstart[nkeys] = fp.npeaks;
+}
+
+// Peaks whose window can touch raw rows [R0, R0 + mrows) of panel p: the
+// bucket range of the bands holding rows R0 + h - w + 1 .. R0 + mrows - 1 + h
+// (h = w/2), clipped to the panel.
+__device__ __forceinline__ void peak_range(const FramePlan &fp, uint32_t p, int64_t R0, int mrows,
+                                           uint32_t &k0, uint32_t &k1) {
+  const int64_t hw = fp.w / 2;
+  const int64_t lo = max(R0 + hw - (int64_t)fp.w + 1, (int64_t)0);
+  const int64_t hi = min(R0 + mrows - 1 + hw, (int64_t)fp.H - 1);
+  k0 = k1 = 0;
+  if (lo > hi) return;
+  const int64_t band = (int64_t)fp.TH * fp.b;
+  k0 = fp.bstart[(size_t)p * fp.segs + (uint32_t)(lo / band)];
+  k1 = fp.bstart[(size_t)p * fp.segs + (uint32_t)(hi / band) + 1];
 }
 
 // ------------------------------------------------------------------ k_bin
@@ -265,143 +301,19 @@ __device__ __forceinline__ int32_t reduce_bin(const BinPix<BB> &px, uint32_t H, 
   return quantize(S, n, step, inv[n], range_err);
 }
 
-// Rows of bins whose loads are issued together.
-template <int BB>
-constexpr int rows_in_flight() {
-  return BB == 1 ? 8 : (BB == 2 ? 4 : (BB == 4 ? 2 : 1));
-}
-
-template <int BB, bool VEC, bool BG, bool DEBUG>
-__device__ __forceinline__ void bin_segment(const FramePlan &fp, uint32_t p, uint32_t seg, uint32_t *hist,
-                            uint32_t *mask, int32_t (*edge)[kMaxTH + 1], const double *inv) {
-  constexpr int RB = rows_in_flight<BB>();
-  const int lane = threadIdx.x & 63;
-  const int b = BB ? BB : (int)fp.b;
-  const uint32_t H = fp.H, W = fp.W, Hb = fp.Hb, Wb = fp.Wb;
-  const uint32_t I0 = seg * fp.TH, I1 = min(I0 + fp.TH, Hb);
-  const int64_t R0 = (int64_t)I0 * b - b;
-  const int mrows = (int)(I1 - I0 + 1) * b;
-  const int wpr = 2 * b;
-  const float *fr = fp.frame + (size_t)p * H * W;
-  const uint32_t pk0 = fp.pstart[p], pk1 = fp.pstart[p + 1];
-  const int64_t hw = fp.w / 2, wwin = fp.w;
-  const double step = fp.step;
-  const size_t gbase = (size_t)p * Hb * Wb;
-  uint16_t *codes = fp.codes + gbase;
-  int32_t *rbuf = fp.rbuf + gbase;
-  bool range_err = false;
-  uint32_t c512 = 0;
-  double Sd;
-  uint32_t nd;
-  // this lane's bits in a strip's mask rows: bit lane*b of the strip
-  const int mword = (lane * b) >> 5, mshift = (lane * b) & 31;
-
-  const bool build_mask = BG || (DEBUG && fp.dbg_mask);
-  for (uint32_t s = 0; s < fp.nstrips; ++s) {
-    const int64_t C0 = (int64_t)s * 64 * b;
-    if (build_mask) {
-      for (int i = lane; i < mrows * wpr; i += 64) mask[i] = 0u;
-      wave_sync();
-      for (uint32_t k = pk0 + lane; k < pk1; k += 64) {
-        const int64_t r = fp.bucket[3 * k + 1], c = fp.bucket[3 * k + 2];
-        const int64_t rlo = max(r - hw, max(R0, (int64_t)0));
-        const int64_t rhi = min(r - hw + wwin, min(R0 + mrows, (int64_t)H));
-        const int64_t clo = max(c - hw, max(C0, (int64_t)0));
-        const int64_t chi = min(c - hw + wwin, min(C0 + 64 * b, (int64_t)W));
-        if (rlo >= rhi || clo >= chi) continue;
-        const int b0 = (int)(clo - C0), b1 = (int)(chi - 1 - C0);
-        for (int64_t i = rlo; i < rhi; ++i) {
-          uint32_t *mr = mask + (i - R0) * wpr;
-          for (int wd = b0 >> 5; wd <= (b1 >> 5); ++wd) {
-            const int lo = max(b0 - wd * 32, 0), hi = min(b1 - wd * 32, 31);
-            const uint32_t m = (hi == 31 ? 0xFFFFFFFFu : ((1u << (hi + 1)) - 1u)) & ~((1u << lo) - 1u);
-            atomicOr(&mr[wd], m);
-          }
-        }
-      }
-      wave_sync();
-      if (DEBUG && fp.dbg_mask) {
-        const uint32_t wprg = (W + 31) / 32;
-        const int64_t rs = (int64_t)I0 * b, re = min((int64_t)I1 * b, (int64_t)H);
-        for (int64_t e = lane; e < (re - rs) * wpr; e += 64) {
-          const int64_t i = rs + e / wpr;
-          const int64_t wd = C0 / 32 + e % wpr;
-          if (wd < wprg)
-            fp.dbg_mask[((size_t)p * H + i) * wprg + wd] = mask[(i - R0) * wpr + e % wpr];
-        }
-      }
-    }
-    const uint32_t J = s * 64 + lane;
-    const bool colv = J < Wb;
-    const uint32_t Jc = colv ? J : Wb - 1;   // loads of idle lanes stay inside the frame
-    // idle lanes read the mask bits of the last column too (in range)
-    const int mw = colv ? mword : (int)(((Jc - s * 64) * b) >> 5);
-    const int ms = colv ? mshift : (int)(((Jc - s * 64) * b) & 31);
-    const int cur = s & 1, prv = cur ^ 1;
-    int32_t q_up = 0;
-    if (I0 > 0) {
-      BinPix<BB> px;
-      load_bin<BB, VEC, BG>(px, fr, H, W, b, I0 - 1, Jc, mask, R0, wpr, mw);
-      const int32_t qh = reduce_bin<BB, BG>(px, H, W, b, I0 - 1, J, step, inv, range_err, Sd, nd,
-                                            ms, mask, R0, wpr, mw);
-      q_up = colv ? qh : 0;
-    }
-    int32_t e_up = (s > 0 && I0 > 0) ? edge[prv][0] : 0;
-    if (lane == 63) edge[cur][0] = q_up;
-    for (uint32_t Ib = I0; Ib < I1; Ib += RB) {
-      BinPix<BB> px[RB];
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-        if (Ib + r < I1) load_bin<BB, VEC, BG>(px[r], fr, H, W, b, Ib + r, Jc, mask, R0, wpr, mw);
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const uint32_t I = Ib + r;
-        if (I >= I1) break;
-        const int32_t qv = reduce_bin<BB, BG>(px[r], H, W, b, I, J, step, inv, range_err, Sd, nd,
-                                              ms, mask, R0, wpr, mw);
-        const int32_t q = colv ? qv : 0;
-        const int32_t e = (s > 0) ? edge[prv][I - I0 + 1] : 0;
-        const int32_t ql = from_left(q, e);
-        const int32_t qul = from_left(q_up, e_up);
-        e_up = e;
-        if (lane == 63) edge[cur][I - I0 + 1] = q;
-        const int32_t rres = q - q_up - ql + qul;
-        uint32_t code = 0xFFFFu;
-        if (colv) {
-          const size_t g = (size_t)I * Wb + J;
-          code = (rres > -kRadius && rres < kRadius) ? (uint32_t)(rres + kRadius) : 0u;
-          codes[g] = (uint16_t)code;
-          if (code == 0) rbuf[g] = rres;
-          if (DEBUG) {
-            if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
-            if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
-            if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
-          }
-        }
-        wave_histogram(code, colv, hist, c512);
-        q_up = q;
-      }
-    }
-    wave_sync();
-  }
-  // per-lane counts of code 512
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) c512 += __shfl_xor(c512, d);
-  if (lane == 0 && c512) atomicAdd(&hist[kRadius], c512);
-  if (range_err) set_status(fp.st, RSZ_ERR_RANGE);
-}
-
 // Wave mask of one segment: raw rows [R0, R0 + mrows) x columns [C0, C0 +
 // 32*wpr) of panel p, bit set where a pixel lies in some peak's window.
 __device__ __forceinline__ void build_mask(const FramePlan &fp, uint32_t p, uint32_t *mask,
                                            int64_t R0, int mrows, int64_t C0, int wpr) {
   const int lane = threadIdx.x & 63;
-  const uint32_t pk0 = fp.pstart[p], pk1 = fp.pstart[p + 1];
+  uint32_t pk0, pk1;
+  peak_range(fp, p, R0, mrows, pk0, pk1);
   const int64_t hw = fp.w / 2, wwin = fp.w;
   for (int i = lane; i < mrows * wpr; i += 64) mask[i] = 0u;
   wave_sync();
   for (uint32_t k = pk0 + lane; k < pk1; k += 64) {
-    const int64_t r = fp.bucket[3 * k + 1], c = fp.bucket[3 * k + 2];
+    const uint32_t rc = fp.bucket[k];
+    const int64_t r = rc >> 16, c = rc & 0xFFFFu;
     const int64_t rlo = max(r - hw, max(R0, (int64_t)0));
     const int64_t rhi = min(r - hw + wwin, min(R0 + mrows, (int64_t)fp.H));
     const int64_t clo = max(c - hw, max(C0, (int64_t)0));
@@ -420,24 +332,36 @@ __device__ __forceinline__ void build_mask(const FramePlan &fp, uint32_t p, uint
   wave_sync();
 }
 
-// Strips of a row whose loads are issued together in the row-major walk.
+// Strips of a row whose loads are issued together.
 template <int BB>
 constexpr int strips_in_flight() {
   return BB == 1 || BB == 2 ? 4 : (BB == 4 ? 2 : 1);
 }
 
-template <int BB, bool VEC, bool BG, bool DEBUG, int NSMAX>
-__device__ __forceinline__ void bin_segment_rows(const FramePlan &fp, uint32_t p, uint32_t seg, uint32_t *hist,
-                                 uint32_t *mask, const double *inv) {
+// One wave's tile: bin rows [I0, I1) of segment `seg` x the strips of 64 bin
+// columns [S0, S0 + ns) of column group `cg` of panel p, walked row by row.
+// The Lorenzo predictor of the tile's first row and first column reads the q
+// of bin row I0 - 1 and bin column J0 - 1, owned by neighbouring tiles: both
+// are recomputed here from the frame (same loads, same sums).
+template <int BB, bool VEC, bool BG, bool DEBUG>
+__device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32_t seg,
+                                         uint32_t cg, uint32_t *hist, uint32_t *mask,
+                                         const double *inv) {
   constexpr int G = strips_in_flight<BB>();
+  constexpr int NS = group_strips(BB);
   const int lane = threadIdx.x & 63;
   const int b = BB ? BB : (int)fp.b;
   const uint32_t H = fp.H, W = fp.W, Hb = fp.Hb, Wb = fp.Wb;
-  const int ns = (int)fp.nstrips;
+  const uint32_t S0 = cg * fp.gstrips;
+  const int ns = (int)min(fp.gstrips, fp.nstrips - S0);
+  const uint32_t J0 = S0 * 64;
+  // the mask starts one word left of the group when there is a halo column
+  const int lw = cg > 0 ? 1 : 0;
+  const int64_t Cm = (int64_t)J0 * b - 32 * lw;
+  const int wpr = 2 * b * ns + lw;
   const uint32_t I0 = seg * fp.TH, I1 = min(I0 + fp.TH, Hb);
   const int64_t R0 = (int64_t)I0 * b - b;
   const int mrows = (int)(I1 - I0 + 1) * b;
-  const int wpr = 2 * b * ns;
   const float *fr = fp.frame + (size_t)p * H * W;
   const double step = fp.step;
   const size_t gbase = (size_t)p * Hb * Wb;
@@ -448,55 +372,76 @@ __device__ __forceinline__ void bin_segment_rows(const FramePlan &fp, uint32_t p
   double Sd;
   uint32_t nd;
   if (BG || (DEBUG && fp.dbg_mask)) {
-    build_mask(fp, p, mask, R0, mrows, 0, wpr);
+    build_mask(fp, p, mask, R0, mrows, Cm, wpr);
     if (DEBUG && fp.dbg_mask) {
+      // this group's words of the full-width mask rows (J0*b is a multiple of 32)
       const uint32_t wprg = (W + 31) / 32;
+      const uint32_t wd0 = J0 * b / 32;
+      const int64_t nwd = min(2 * b * ns, (int)(wprg - wd0));
       const int64_t rs = (int64_t)I0 * b, re = min((int64_t)I1 * b, (int64_t)H);
-      for (int64_t e = lane; e < (re - rs) * (int64_t)wprg; e += 64) {
-        const int64_t i = rs + e / wprg, wd = e % wprg;
-        fp.dbg_mask[((size_t)p * H + i) * wprg + wd] = mask[(i - R0) * wpr + wd];
+      for (int64_t e = lane; e < (re - rs) * nwd; e += 64) {
+        const int64_t i = rs + e / nwd, wd = e % nwd;
+        fp.dbg_mask[((size_t)p * H + i) * wprg + wd0 + wd] = mask[(i - R0) * wpr + lw + wd];
       }
     }
   }
-  // column of strip s for this lane; idle lanes (past the panel) load the
-  // last column, which stays inside the frame
-#define RSZ_JC(s) (((s) * 64 + lane) < Wb ? ((s) * 64 + lane) : Wb - 1)
-  int32_t q_up[NSMAX];
+  // halo column: lane i holds q of bin (I0 - 1 + i, J0 - 1), 0 outside the
+  // panel; its pixels sit in the last b bits of mask word 0
+  int32_t q_left = 0;
+  if (cg > 0) {
+    const int64_t Ih = (int64_t)I0 - 1 + lane;
+    const bool hv = Ih >= 0 && Ih < (int64_t)I1;
+    const uint32_t Ic = (uint32_t)min(max(Ih, (int64_t)0), (int64_t)I1 - 1);
+    BinPix<BB> px;
+    load_bin<BB, VEC, BG>(px, fr, H, W, b, Ic, J0 - 1, mask, R0, wpr, 0);
+    bool herr = false;
+    const int32_t qh = reduce_bin<BB, BG>(px, H, W, b, Ic, J0 - 1, step, inv, herr, Sd, nd,
+                                          32 - b, mask, R0, wpr, 0);
+    q_left = hv ? qh : 0;
+    range_err |= hv && herr;
+  }
+  // column of strip s for this lane and its mask word; idle lanes (past the
+  // panel) load the last column, which stays inside the frame
+#define RSZ_JC(s) ((J0 + (s) * 64 + lane) < Wb ? (J0 + (s) * 64 + lane) : Wb - 1)
+#define RSZ_MW(jc) ((int)((((jc) - J0) * b + 32 * lw) >> 5))
+  int32_t q_up[NS];
 #pragma unroll
-  for (int s = 0; s < NSMAX; ++s) {
+  for (int s = 0; s < NS; ++s) {
     q_up[s] = 0;
     if (I0 > 0 && s < ns) {
       const uint32_t jc = RSZ_JC(s);
       BinPix<BB> px;
-      load_bin<BB, VEC, BG>(px, fr, H, W, b, I0 - 1, jc, mask, R0, wpr, (int)((jc * b) >> 5));
-      const int32_t qh = reduce_bin<BB, BG>(px, H, W, b, I0 - 1, s * 64 + lane, step, inv,
+      load_bin<BB, VEC, BG>(px, fr, H, W, b, I0 - 1, jc, mask, R0, wpr, RSZ_MW(jc));
+      const int32_t qh = reduce_bin<BB, BG>(px, H, W, b, I0 - 1, J0 + s * 64 + lane, step, inv,
                                             range_err, Sd, nd, (int)((jc * b) & 31), mask, R0,
-                                            wpr, (int)((jc * b) >> 5));
-      q_up[s] = (uint32_t)(s * 64 + lane) < Wb ? qh : 0;
+                                            wpr, RSZ_MW(jc));
+      q_up[s] = J0 + s * 64 + lane < Wb ? qh : 0;
     }
   }
   for (uint32_t I = I0; I < I1; ++I) {
-    int32_t left = 0, upleft = 0;   // last lane of the previous strip, this row / row above
+    // q left of the group on this row and on the row above
+    int32_t left = __builtin_amdgcn_readlane(q_left, I - I0 + 1);
+    int32_t upleft = __builtin_amdgcn_readlane(q_left, I - I0);
 #pragma unroll
-    for (int s0 = 0; s0 < NSMAX; s0 += G) {
+    for (int s0 = 0; s0 < NS; s0 += G) {
       if (s0 >= ns) break;
       BinPix<BB> px[G];
 #pragma unroll
       for (int gi = 0; gi < G; ++gi)
         if (s0 + gi < ns) {
           const uint32_t jc = RSZ_JC(s0 + gi);
-          load_bin<BB, VEC, BG>(px[gi], fr, H, W, b, I, jc, mask, R0, wpr, (int)((jc * b) >> 5));
+          load_bin<BB, VEC, BG>(px[gi], fr, H, W, b, I, jc, mask, R0, wpr, RSZ_MW(jc));
         }
 #pragma unroll
       for (int gi = 0; gi < G; ++gi) {
         const int s = s0 + gi;
         if (s >= ns) break;
-        const uint32_t J = s * 64 + lane;
+        const uint32_t J = J0 + s * 64 + lane;
         const bool colv = J < Wb;
         const uint32_t jc = RSZ_JC(s);
         const int32_t qv = reduce_bin<BB, BG>(px[gi], H, W, b, I, J, step, inv, range_err, Sd,
                                               nd, (int)((jc * b) & 31), mask, R0, wpr,
-                                              (int)((jc * b) >> 5));
+                                              RSZ_MW(jc));
         const int32_t q = colv ? qv : 0;
         const int32_t ql = from_left(q, left);
         const int32_t qul = from_left(q_up[s], upleft);
@@ -520,6 +465,7 @@ __device__ __forceinline__ void bin_segment_rows(const FramePlan &fp, uint32_t p
       }
     }
   }
+#undef RSZ_MW
 #undef RSZ_JC
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) c512 += __shfl_xor(c512, d);
@@ -527,52 +473,36 @@ __device__ __forceinline__ void bin_segment_rows(const FramePlan &fp, uint32_t p
   if (range_err) set_status(fp.st, RSZ_ERR_RANGE);
 }
 
-template <int BB, bool VEC, bool BG, bool DEBUG, int NSMAX>
-__device__ __forceinline__ void bin_dispatch(const FramePlan &fp, uint32_t panel, uint32_t seg,
-                                             uint32_t *hist, uint32_t *mask,
-                                             int32_t (*edge)[kMaxTH + 1], const double *inv) {
-  if constexpr (NSMAX > 0) {
-    if (fp.rowmajor) {
-      bin_segment_rows<BB, VEC, BG, DEBUG, NSMAX>(fp, panel, seg, hist, mask, inv);
-      return;
-    }
-  }
-  bin_segment<BB, VEC, BG, DEBUG>(fp, panel, seg, hist, mask, edge, inv);
-}
-
-// NSMAX: most strips per panel row handled by the row-major walk in this
-// instantiation (frames with more strips, or 0 here, use the strip walk).
-template <int BB, int NSMAX, bool DEBUG>
+// BB: the bin factor (1, 2, 4) compiled in, or 0 for any b (one strip per
+// column group).  Workgroup t of a frame: panel, column group, then a group
+// of kWaves consecutive segments, one per wave.
+template <int BB, bool DEBUG>
 __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
   __shared__ uint32_t s_hist[kNumSym];
   __shared__ uint32_t s_mask[kWaves][kMaskWords];
-  __shared__ int32_t s_edge[kWaves][2][kMaxTH + 1];
   __shared__ double s_inv[65];
   const uint32_t f = find_frame(bp.tile_prefix, bp.nframes, blockIdx.x);
   const FramePlan &fp = bp.frames[f];
   for (int i = threadIdx.x; i < kNumSym; i += 256) s_hist[i] = 0u;
   if (threadIdx.x < 65) s_inv[threadIdx.x] = fp.inv[threadIdx.x];
   __syncthreads();
-  // wave index as a wave-uniform (scalar) value: everything per segment and
+  // wave index as a wave-uniform (scalar) value: everything per tile and
   // per row below stays in scalar registers
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t t = blockIdx.x - bp.tile_prefix[f];
-  const uint32_t panel = t / fp.groups, grp = t % fp.groups;
-  const uint32_t seg = grp * kWaves + wv;
+  const uint32_t per_panel = fp.groups * fp.cgs;
+  const uint32_t panel = t / per_panel, rem = t % per_panel;
+  const uint32_t cg = rem / fp.groups, seg = (rem % fp.groups) * kWaves + wv;
   const bool ok = load_status(fp.st) == RSZ_OK;
   if (ok && seg < fp.segs) {
     const bool bg = fp.mode == RSZ_BIN_BACKGROUND;
     uint32_t *mask = s_mask[wv];
     if ((BB == 2 || BB == 4) && fp.vec) {
-      if (bg)
-        bin_dispatch<BB, true, true, DEBUG, NSMAX>(fp, panel, seg, s_hist, mask, s_edge[wv], s_inv);
-      else
-        bin_dispatch<BB, true, false, DEBUG, NSMAX>(fp, panel, seg, s_hist, mask, s_edge[wv], s_inv);
+      if (bg) bin_tile<BB, true, true, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
+      else bin_tile<BB, true, false, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
     } else {
-      if (bg)
-        bin_dispatch<BB, false, true, DEBUG, NSMAX>(fp, panel, seg, s_hist, mask, s_edge[wv], s_inv);
-      else
-        bin_dispatch<BB, false, false, DEBUG, NSMAX>(fp, panel, seg, s_hist, mask, s_edge[wv], s_inv);
+      if (bg) bin_tile<BB, false, true, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
+      else bin_tile<BB, false, false, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
     }
   }
   __syncthreads();
@@ -983,40 +913,23 @@ __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
     if (e_ != hipSuccess) return e_;                              \
   } while (0)
 
-template <int NSMAX, bool DEBUG>
-static hipError_t launch_bin_ns(const BatchPlan &bp, uint32_t b, hipStream_t s) {
-  constexpr bool kSpecial = NSMAX == 4;  // only b in {1,2,4}, no debug
-  if constexpr (kSpecial && DEBUG) {
-    return hipErrorInvalidValue;
-  } else {
-    switch (b) {
-      case 1: RSZ_LAUNCH("k_bin", (k_bin<1, NSMAX, DEBUG>), bp.total_tiles, s, bp); break;
-      case 2: RSZ_LAUNCH("k_bin", (k_bin<2, NSMAX, DEBUG>), bp.total_tiles, s, bp); break;
-      case 4: RSZ_LAUNCH("k_bin", (k_bin<4, NSMAX, DEBUG>), bp.total_tiles, s, bp); break;
-      default:
-        if constexpr (kSpecial) return hipErrorInvalidValue;
-        else RSZ_LAUNCH("k_bin", (k_bin<0, NSMAX, DEBUG>), bp.total_tiles, s, bp);
-        break;
-    }
-    return hipSuccess;
-  }
-}
-
-// nsmax: strips per row of the widest row-major frame (0: none).  The debug
-// build and the generic bin factor use the widest row-major instantiation.
+// `b`: the common bin factor of the batch, or 0 (mixed or not 1, 2, 4).
 template <bool DEBUG>
-static hipError_t launch_bin(const BatchPlan &bp, uint32_t b, uint32_t nsmax, hipStream_t s) {
+static hipError_t launch_bin(const BatchPlan &bp, uint32_t b, hipStream_t s) {
   if (bp.total_tiles == 0) return hipSuccess;
-  if (nsmax == 0) return launch_bin_ns<0, DEBUG>(bp, b, s);
-  if (DEBUG || (b != 1 && b != 2 && b != 4) || nsmax > 4) return launch_bin_ns<8, DEBUG>(bp, b, s);
-  return launch_bin_ns<4, DEBUG>(bp, b, s);
+  switch (b) {
+    case 1: RSZ_LAUNCH("k_bin", (k_bin<1, DEBUG>), bp.total_tiles, s, bp); break;
+    case 2: RSZ_LAUNCH("k_bin", (k_bin<2, DEBUG>), bp.total_tiles, s, bp); break;
+    case 4: RSZ_LAUNCH("k_bin", (k_bin<4, DEBUG>), bp.total_tiles, s, bp); break;
+    default: RSZ_LAUNCH("k_bin", (k_bin<0, DEBUG>), bp.total_tiles, s, bp); break;
+  }
+  return hipSuccess;
 }
 
 // prep + bin + codebook; `b` is the common bin factor of the batch or 0.
-hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t nsmax, hipStream_t s,
-                                   bool debug) {
+hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t s, bool debug) {
   RSZ_LAUNCH("k_prep", k_prep, bp.nframes, s, bp);
-  hipError_t e = debug ? launch_bin<true>(bp, b, nsmax, s) : launch_bin<false>(bp, b, nsmax, s);
+  hipError_t e = debug ? launch_bin<true>(bp, b, s) : launch_bin<false>(bp, b, s);
   if (e != hipSuccess) return e;
   RSZ_LAUNCH("k_codebook", k_codebook, bp.nframes, s, bp);
   return hipSuccess;

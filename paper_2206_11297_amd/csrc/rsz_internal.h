@@ -17,13 +17,17 @@ constexpr double kQMax = 268435455.0; // |q| <= 2^28 - 1
 constexpr uint64_t kHeader = 80;
 
 // Binning kernel geometry: 4 independent waves per workgroup, each owning a
-// segment of up to kMaxTH bin rows of one panel and walking it in strips of
-// 64 bin columns.
+// tile of one panel: a segment of up to kMaxTH bin rows x a column group of
+// up to group_strips(b) strips of 64 bin columns.
 constexpr int kWaves = 4;
 constexpr int kMaxTH = 32;
-constexpr int kMaskRowsMax = 72;      // (TH+1)*b raw rows per segment
-constexpr int kMaskWords = 896;       // per wave: rows * 2b words (per strip)
-constexpr int kRowMajorStrips = 8;   // widest panel row (in 64-bin strips) walked row-major
+constexpr int kMaskWords = 896;       // per wave: (TH+1)*b rows x (2b*strips+1) words
+
+// Strips per column group for bin factor b as compiled in the binning kernel
+// (0: any b, and batches mixing bin factors).
+__host__ __device__ constexpr int group_strips(int b) {
+  return b == 1 || b == 2 ? 4 : (b == 4 ? 2 : 1);
+}
 
 inline __host__ __device__ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -44,10 +48,9 @@ struct FramePlan {
   double eb, step;          // step = 2*eb
   uint32_t Hb, Wb, nbins, nchunks;
   uint32_t npeaks, TH, segs, groups;   // segments per panel, workgroups per panel
-  uint32_t nstrips;
+  uint32_t nstrips, gstrips, cgs;   // strips per panel row, per column group; groups
   int32_t init_status;      // RSZ_OK or RSZ_ERR_ARG
   uint32_t vec;             // rows load as float2/float4 (W % b == 0, aligned)
-  uint32_t rowmajor;        // k_bin walks whole rows (nstrips <= kRowMajorStrips)
   double inv[65];           // inv[n] = 1 / (n * 2eb), correctly rounded
   const float *frame;
   const int32_t *peaks;     // npeaks x (panel,row,col)
@@ -61,9 +64,9 @@ struct FramePlan {
   uint32_t *chunk_off;      // nchunks: bit count, then bit offset of each chunk
   uint32_t *chunk_oo;       // nchunks: outlier count, then outlier offset
   uint32_t *head;           // nchunks: bits of a chunk in its shared first word
-  uint32_t *pstart;         // P+1 bucket starts of peaks by panel
-  uint32_t *pcursor;        // P scatter cursors
-  int32_t *bucket;          // npeaks x 3, grouped by panel
+  uint32_t *bstart;         // P*segs+1 starts of the peak bands: band k =
+                            // (panel k / segs, raw rows [(k % segs)*TH*b, +TH*b))
+  uint32_t *bucket;         // npeaks peaks as (row << 16 | col), grouped by band
   FrameState *st;
   uint64_t *res_bytes;      // where to report the size (device)
   int32_t *res_status;      // where to report the status (device)
@@ -88,8 +91,7 @@ struct BatchPlan {
 
 // Launchers (compress.hip).
 // k_prep + k_bin + k_codebook; b = common bin factor of the batch, or 0.
-hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t nsmax, hipStream_t s,
-                                   bool debug);
+hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t s, bool debug);
 // k_count + k_scan + k_encode + k_tail + k_roi.
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s);
 

@@ -265,3 +265,22 @@ def test_tile_rows_never_change_bytes(torch):
         if ref is None:
             st, ref, _ = O.compress(O.params(32, 185, 388, 17, 2, 10.0, 0), frame, peaks)
         np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("shape,b,npk", [((1, 150, 1200), 1, 600), ((2, 130, 300), 2, 500),
+                                         ((3, 61, 700), 3, 350)])
+@pytest.mark.parametrize("w", [1, 17, 40])
+def test_dense_peaks_every_band_split(torch, shape, b, npk, w):
+    """Hundreds of peaks per panel, whose windows cross the row bands that
+    peaks are bucketed by, for segment heights from one bin row up: strip
+    walk (wide panel) and row walk."""
+    frame, peaks = synth.tiny_case(40 + w, shape, npk, "normal")
+    st, ref, _ = O.compress(O.params(*shape, w, b, 1.0, 0), frame, peaks)
+    assert st == O.OK
+    for tr in (1, 2, 5, 0):
+        print(f"dense shape={shape} b={b} w={w} tile_rows={tr}", flush=True)
+        B = rsz.Batch([_gpu(torch, frame)], [_gpu(torch, peaks)], (w, b, 1.0, 0), tile_rows=tr)
+        B.run()
+        torch.cuda.synchronize()
+        assert B.status.cpu().tolist() == [0]
+        np.testing.assert_array_equal(B.stream(0).cpu().numpy(), ref)
