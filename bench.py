@@ -90,8 +90,8 @@ def serving_section(args, torch, dev):
         return reqs
 
     # warm-up of both paths
-    serve.Scheduler(batched, args.serve_slots, limits).run(requests(0, 16, 1))
-    serve.Scheduler(single, 1, single_lim).run(requests(0, 4, 2))
+    serve.Scheduler(batched, args.serve_slots, limits).run(requests(0, 16, 1001))
+    serve.Scheduler(single, 1, single_lim).run(requests(0, 4, 1002))
     for rate in args.serve_rates:
         reqs = requests(rate * 1e3, args.serve_frames, int(rate))
         rb = serve.summarize(serve.Scheduler(batched, args.serve_slots, limits).run(reqs), reqs)
@@ -103,6 +103,113 @@ def serving_section(args, torch, dev):
     out["backlogged"] = serve.summarize(serve.Scheduler(batched, args.serve_slots, limits).run(reqs),
                                         reqs)
     return out
+
+
+def cpu_baseline(args, host, B, sizes):
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import rsz_oracle as O
+    po = O.params(*SHAPE, WINDOW, BIN, EB, 0)
+    out_host = B.out.cpu().numpy()
+    frame_bytes = SHAPE[0] * SHAPE[1] * SHAPE[2] * 4
+
+    def one(k):
+        i = k % len(host)   # the frame-parallel leg cycles over the frames
+        f, pk = host[i]
+        sto, ref, _ = O.compress(po, f, pk)
+        got = out_host[B.offsets[i]:B.offsets[i] + int(sizes[i])]
+        return sto == 0 and np.array_equal(got, ref)
+
+    budget = args.cpu_seconds
+    n1, t1, parity = 0, 0.0, True
+    while n1 < len(host) and t1 < budget / 2:
+        a = time.perf_counter()
+        parity &= one(n1)
+        t1 += time.perf_counter() - a
+        n1 += 1
+    if n1 == 0:
+        return None
+    single = n1 * frame_bytes / t1 / 1e9
+    threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+    # frames for about budget/2 of wall time at the single-thread rate x threads
+    nmt = int(max(threads, threads * (budget / 2) * n1 / t1))
+    a = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        oks = list(ex.map(one, range(nmt)))
+    tmt = time.perf_counter() - a
+    parity &= all(oks)
+    return {"value": round(nmt * frame_bytes / tmt / 1e9, 4), "unit": "GB/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{nmt} frame compressions cycling over the first {min(nmt, len(host))} "
+                      f"frames of the batch, one frame per thread on {threads} threads, "
+                      f"{tmt:.1f}s wall; single thread: first {n1} frames, {t1:.1f}s",
+            "single_thread_value": round(single, 4), "streams_equal_gpu": bool(parity)}
+
+
+def _counter_rows(root, counter):
+    """Per-dispatch values of one counter from rocprofv3 CSV output under root:
+    {kernel name: [(grid size, value in KiB)]}."""
+    import csv
+    import glob
+    rows = {}
+    for path in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != counter:
+                    continue
+                rows.setdefault(r["Kernel_Name"], []).append(
+                    (int(r.get("Grid_Size") or 0), float(r["Counter_Value"])))
+    return rows
+
+
+def traffic_summary(fetch_dir, write_dir, out_dir):
+    """Summary of two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, both with --copy-calibration): per-kernel HBM bytes per
+    dispatch, scaled by what the counters read for a 1 GiB device copy (reads
+    1 GiB) and a 1 GiB fill (writes 1 GiB).  Writes the JSON record read by
+    the roofline and a Markdown table."""
+    fetch = _counter_rows(fetch_dir, "FETCH_SIZE")
+    write = _counter_rows(write_dir, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+
+    def calib(rows, pick):
+        vals = [v for k, lst in rows.items() if pick(k) for _, v in lst if v > 0.5 * gib_kib]
+        if not vals:
+            raise SystemExit("calibration kernel not found in the counter output")
+        return gib_kib / max(vals)
+
+    fs = calib(fetch, lambda k: "copyBuffer" in k or "copy" in k.lower())
+    ws = calib(write, lambda k: "fill" in k.lower())
+    src = os.path.join(ROOT, "paper_2206_11297_amd", "csrc", "compress.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    table = []
+    for k in sorted(set(fetch) | set(write)):
+        if "rsz::" not in k:
+            continue
+        f = fetch.get(k, [])
+        w = write.get(k, [])
+        fk = sum(v for _, v in f) / max(1, len(f))
+        wk = sum(v for _, v in w) / max(1, len(w))
+        table.append((k, len(f), fk, fk * 1024 * fs, len(w), wk, wk * 1024 * ws))
+    kb = [t for t in table if "k_bin" in t[0]]
+    rec = {"kernel": "k_bin", "workload": WORKLOAD, "compress_hip_sha256": sha,
+           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+           "fetch_bytes_per_launch": round(kb[0][3]) if kb else None,
+           "write_bytes_per_launch": round(kb[0][6]) if kb else None,
+           "hbm_bytes_per_launch": round(kb[0][3] + kb[0][6]) if kb else None,
+           "algorithmic_bytes_per_launch": NFRAMES * SHAPE[0] * SHAPE[1] * SHAPE[2] * 4}
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, f"k_bin_{WORKLOAD}_traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    lines = [f"fetch scale {fs:.4f} (1 GiB copy), write scale {ws:.4f} (1 GiB fill)", "",
+             "| kernel | dispatches | FETCH_SIZE KiB/dispatch | read GB | WRITE_SIZE KiB/dispatch "
+             "| written GB |", "|---|---|---|---|---|---|"]
+    for k, nf, fk, fb, nw, wk, wb in sorted(table, key=lambda t: -t[3]):
+        lines.append(f"| `{k[:48]}` | {nf} | {fk:.0f} | {fb / 1e9:.3f} | {wk:.0f} | "
+                     f"{wb / 1e9:.3f} |")
+    with open(os.path.join(out_dir, f"{WORKLOAD}_traffic_table.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps(rec))
 
 
 def traffic_record(kernel):
@@ -126,20 +233,28 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=NFRAMES)
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="oracle time budget (half single-thread, half frame-parallel)")
+    ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_DIR"),
+                    help="summarize two rocprofv3 --pmc runs (CSV output) and exit")
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--serve-rates", type=float, nargs="*", default=[1.0, 10.0],
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[1.0, 2.0, 5.0, 10.0],
                     help="Poisson arrival rates in kHz for the serving section ([] skips it)")
-    ap.add_argument("--serve-frames", type=int, default=1500)
+    ap.add_argument("--serve-frames", type=int, default=10000)
     ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-batch", type=int, default=32)
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the compression path is not sharded "
-              "across GPUs (frames are independent; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the compression path is not sharded across "
+              "GPUs (frames are independent, so several GPUs would each run their own "
+              "batches).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -218,21 +333,11 @@ def main():
         assert st1 == 0 and n1 == sizes[i]
     lat_ms = np.array(lat if lat else [float("nan")]) * 1e3
 
-    # CPU baseline: the oracle, single-threaded, on the first frames for a
-    # bounded time; its streams must equal the GPU streams byte for byte
-    from oracle import rsz_oracle as O
-    po = O.params(*SHAPE, WINDOW, BIN, EB, 0)
-    out_host = B.out.cpu().numpy()
-    n_cpu, cpu_t, parity = 0, 0.0, True
-    while n_cpu < len(host) and cpu_t < args.cpu_seconds:
-        f, pk = host[n_cpu]
-        a = time.perf_counter()
-        sto, ref, nb = O.compress(po, f, pk)
-        cpu_t += time.perf_counter() - a
-        got = out_host[B.offsets[n_cpu]:B.offsets[n_cpu] + int(sizes[n_cpu])]
-        parity &= sto == 0 and np.array_equal(got, ref)
-        n_cpu += 1
-    cpu_gbps = n_cpu * SHAPE[0] * SHAPE[1] * SHAPE[2] * 4 / cpu_t / 1e9 if n_cpu else None
+    # CPU baseline: the oracle as it is, first on one thread, then one frame
+    # per thread on the host's cores (the C library runs without the GIL),
+    # each for a bounded time; its streams must equal the GPU streams byte
+    # for byte
+    cpu = cpu_baseline(args, host, B, sizes)
 
     serving = serving_section(args, torch, dev) if args.serve_rates else None
 
@@ -247,11 +352,7 @@ def main():
                                "20% non-hit, window 17, bin 2x2, eb 10 ADU, one batched launch",
                    "frames": len(frames), "raw_bytes": raw_bytes},
         "roofline": roof,
-        "cpu_baseline": {"value": None if cpu_gbps is None else round(cpu_gbps, 4),
-                         "unit": "GB/s", "cores": 1,
-                         "kind": "oracle",
-                         "sample": f"first {n_cpu} frames of the batch, single thread, "
-                                   f"{cpu_t:.1f}s", "streams_equal_gpu": bool(parity)},
+        "cpu_baseline": cpu,
         "compression_ratio_u16": {"mean": round(float(cr_u16.mean()), 3),
                                   "min": round(float(cr_u16.min()), 3),
                                   "max": round(float(cr_u16.max()), 3),
