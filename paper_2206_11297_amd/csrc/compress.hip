@@ -167,16 +167,18 @@ __device__ __forceinline__ void peak_range(const FramePlan &fp, uint32_t p, int6
 // ------------------------------------------------------------------ k_bin
 
 // Histogram update with one LDS atomic per distinct code in the wave; the
-// zero-residual code 512 is counted per lane and added once at the end.
-__device__ __forceinline__ void wave_histogram(uint32_t code, bool valid, uint32_t *hist,
+// zero-residual code 512 is counted from a lane mask into a wave-uniform
+// total that is added once at the end.  vmask: the lanes holding a bin.
+__device__ __forceinline__ void wave_histogram(uint32_t code, uint64_t vmask, uint32_t *hist,
                                                uint32_t &c512) {
   const int lane = threadIdx.x & 63;
-  c512 += (valid && code == (uint32_t)kRadius) ? 1u : 0u;
-  uint64_t pending = __ballot(valid && code != (uint32_t)kRadius);
+  c512 += (uint32_t)__builtin_popcountll(
+      __builtin_amdgcn_uicmp(code, (uint32_t)kRadius, 32 /* eq */) & vmask);
+  uint64_t pending = __builtin_amdgcn_uicmp(code, (uint32_t)kRadius, 33 /* ne */) & vmask;
   while (pending) {
     const int leader = __builtin_ctzll(pending);
     const uint32_t lc = __builtin_amdgcn_readlane(code, leader);
-    const uint64_t same = __ballot(code == lc) & pending;
+    const uint64_t same = __builtin_amdgcn_uicmp(code, lc, 32 /* eq */) & pending;
     if (lane == leader) atomicAdd(&hist[lc], (uint32_t)__builtin_popcountll(same));
     pending &= ~same;
   }
@@ -301,6 +303,75 @@ __device__ __forceinline__ int32_t reduce_bin(const BinPix<BB> &px, uint32_t H, 
   return quantize(S, n, step, inv[n], range_err);
 }
 
+// Vector path (b = 2 or 4 with W % b == 0, rows 8- or 16-byte aligned): a
+// lane's bin row is one float2/float4 load at a 32-bit byte offset from a
+// wave-uniform row pointer, and the b x b pixels reduce branch-free.
+template <int BB, bool BG>
+__device__ __forceinline__ void load_vec(BinPix<BB> &px, const float *__restrict__ fr, uint32_t H,
+                                         uint32_t W, uint32_t I, uint32_t lofs,
+                                         const uint32_t *mlane, int64_t R0, int wpr) {
+#pragma unroll
+  for (int di = 0; di < BB; ++di) {
+    const uint32_t i = min(I * BB + di, H - 1);
+    const char *row = (const char *)(fr + (size_t)i * W);
+    if constexpr (BB == 2) {
+      const float2 x = *(const float2 *)(row + lofs);
+      px.v[di][0] = x.x;
+      px.v[di][1] = x.y;
+    } else {
+      const float4 x = *(const float4 *)(row + lofs);
+      px.v[di][0] = x.x;
+      px.v[di][1] = x.y;
+      px.v[di][2] = x.z;
+      px.v[di][3] = x.w;
+    }
+    px.m[di] = BG ? mlane[(int)(i - R0) * wpr] : 0u;
+  }
+}
+
+// The fp64 raster-order sum of the included pixels, their count and q.  An
+// excluded pixel enters as -0.0, which leaves any sum unchanged (x + -0 = x
+// for every x, zeros included), and the sum starts from the first pixel
+// rather than from +0.0.  Both can change only the sign of a zero sum, never
+// q; with `exact_S` a final +0.0 restores the sum from +0.0 bit for bit (a
+// sum from +0.0 is never -0.0).  rowbits: the in-panel pixels of the bin,
+// raster bit order (wave-uniform).
+template <int BB, bool BG>
+__device__ __forceinline__ int32_t reduce_vec(const BinPix<BB> &px, uint32_t rowbits, int mshift,
+                                              const double *inv, double step, bool &range_err,
+                                              bool exact_S, double &S_out, uint32_t &n_out) {
+  uint32_t inc = rowbits;
+  if constexpr (BG) {
+    uint32_t mb = 0;
+#pragma unroll
+    for (int di = 0; di < BB; ++di) mb |= __builtin_amdgcn_ubfe(px.m[di], mshift, BB) << (di * BB);
+    inc &= ~mb;
+  }
+  double S = 0.0;
+#pragma unroll
+  for (int k = 0; k < BB * BB; ++k) {
+    // all ones for an included pixel, else zero: keep its bits or take -0.0
+    const uint32_t keep = (uint32_t)__builtin_amdgcn_sbfe((int)inc, k, 1);
+    const uint32_t xb = (__float_as_uint(px.v[k / BB][k % BB]) & keep) | (0x80000000u & ~keep);
+    const double x = (double)__uint_as_float(xb);
+    S = k == 0 ? x : S + x;
+  }
+  const uint32_t n = __builtin_popcount(inc);
+  if (exact_S) {
+    S_out = S + 0.0;
+    n_out = n;
+  }
+  // n == 0: inv[0] = 0 and S = -0.0, so t1 = 0 and q = 0 without a branch
+  const double t1 = S * inv[n];
+  double t = rint(t1);
+  if (!(fabs(t1 - t) < 0.5 - 0x1p-20)) t = rint(S / ((double)n * step));
+  if (!(fabs(t) <= kQMax)) {
+    range_err = true;
+    return 0;
+  }
+  return (int32_t)t;
+}
+
 // Wave mask of one segment: raw rows [R0, R0 + mrows) x columns [C0, C0 +
 // 32*wpr) of panel p, bit set where a pixel lies in some peak's window.
 __device__ __forceinline__ void build_mask(const FramePlan &fp, uint32_t p, uint32_t *mask,
@@ -418,10 +489,37 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
       q_up[s] = J0 + s * 64 + lane < Wb ? qh : 0;
     }
   }
+  // per strip, loop-invariant: the lane's load offset (vector path) and its
+  // mask word in LDS
+  uint32_t lofs[NS];
+  const uint32_t *mlane[NS];
+  uint64_t vmask[NS];   // lanes of strip s inside the panel
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const uint32_t jc = RSZ_JC(s < ns ? s : 0);
+    lofs[s] = jc * (uint32_t)b * 4u;
+    mlane[s] = mask + RSZ_MW(jc);
+    vmask[s] = __builtin_amdgcn_uicmp(J0 + s * 64 + lane, Wb, 36 /* ult */);
+  }
+  // ql_up[s]: left neighbours of the row above (row I0 - 1 to start)
+  int32_t ql_up[NS];
+  {
+    int32_t lft = __builtin_amdgcn_readlane(q_left, 0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      ql_up[s] = 0;
+      if (s < ns) {
+        ql_up[s] = from_left(q_up[s], lft);
+        lft = __builtin_amdgcn_readlane(q_up[s], 63);
+      }
+    }
+  }
   for (uint32_t I = I0; I < I1; ++I) {
-    // q left of the group on this row and on the row above
+    // q left of the group on this row
     int32_t left = __builtin_amdgcn_readlane(q_left, I - I0 + 1);
-    int32_t upleft = __builtin_amdgcn_readlane(q_left, I - I0);
+    // in-panel pixels of this bin row (vector path: every column is)
+    uint32_t rowbits = 0;
+    if constexpr (VEC) rowbits = (1u << (min((uint32_t)BB, H - I * BB) * BB)) - 1u;
 #pragma unroll
     for (int s0 = 0; s0 < NS; s0 += G) {
       if (s0 >= ns) break;
@@ -429,8 +527,12 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
 #pragma unroll
       for (int gi = 0; gi < G; ++gi)
         if (s0 + gi < ns) {
-          const uint32_t jc = RSZ_JC(s0 + gi);
-          load_bin<BB, VEC, BG>(px[gi], fr, H, W, b, I, jc, mask, R0, wpr, RSZ_MW(jc));
+          if constexpr (VEC) {
+            load_vec<BB, BG>(px[gi], fr, H, W, I, lofs[s0 + gi], mlane[s0 + gi], R0, wpr);
+          } else {
+            const uint32_t jc = RSZ_JC(s0 + gi);
+            load_bin<BB, VEC, BG>(px[gi], fr, H, W, b, I, jc, mask, R0, wpr, RSZ_MW(jc));
+          }
         }
 #pragma unroll
       for (int gi = 0; gi < G; ++gi) {
@@ -439,37 +541,40 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
         const uint32_t J = J0 + s * 64 + lane;
         const bool colv = J < Wb;
         const uint32_t jc = RSZ_JC(s);
-        const int32_t qv = reduce_bin<BB, BG>(px[gi], H, W, b, I, J, step, inv, range_err, Sd,
-                                              nd, (int)((jc * b) & 31), mask, R0, wpr,
-                                              RSZ_MW(jc));
+        int32_t qv;
+        if constexpr (VEC) {
+          qv = reduce_vec<BB, BG>(px[gi], rowbits, (int)((jc * b) & 31), inv, step, range_err,
+                                  DEBUG, Sd, nd);
+        } else {
+          qv = reduce_bin<BB, BG>(px[gi], H, W, b, I, J, step, inv, range_err, Sd, nd,
+                                  (int)((jc * b) & 31), mask, R0, wpr, RSZ_MW(jc));
+        }
         const int32_t q = colv ? qv : 0;
         const int32_t ql = from_left(q, left);
-        const int32_t qul = from_left(q_up[s], upleft);
         left = __builtin_amdgcn_readlane(q, 63);
-        upleft = __builtin_amdgcn_readlane(q_up[s], 63);
-        const int32_t rres = q - q_up[s] - ql + qul;
-        uint32_t code = 0xFFFFu;
+        // residual + radius; codes 1..1023 carry it, 0 marks an outlier
+        const int32_t c = q + ql_up[s] + kRadius - q_up[s] - ql;
+        const uint32_t code = (uint32_t)c < (uint32_t)kNumSym ? (uint32_t)c : 0u;
         if (colv) {
           const size_t g = (size_t)I * Wb + J;
-          code = (rres > -kRadius && rres < kRadius) ? (uint32_t)(rres + kRadius) : 0u;
-          codes[g] = (uint16_t)code;
-          if (code == 0) rbuf[g] = rres;
+          // row pointer (wave-uniform) + 32-bit lane offset
+          *(uint16_t *)((char *)(codes + (size_t)I * Wb) + J * 2u) = (uint16_t)code;
+          if (code == 0) *(int32_t *)((char *)(rbuf + (size_t)I * Wb) + J * 4u) = c - kRadius;
           if (DEBUG) {
             if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
             if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
             if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
           }
         }
-        wave_histogram(code, colv, hist, c512);
+        wave_histogram(code, vmask[s], hist, c512);
         q_up[s] = q;
+        ql_up[s] = ql;
       }
     }
   }
 #undef RSZ_MW
 #undef RSZ_JC
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) c512 += __shfl_xor(c512, d);
-  if (lane == 0 && c512) atomicAdd(&hist[kRadius], c512);
+  if (lane == 0 && c512) atomicAdd(&hist[kRadius], c512);   // c512 is a wave total
   if (range_err) set_status(fp.st, RSZ_ERR_RANGE);
 }
 
@@ -497,10 +602,15 @@ __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
   if (ok && seg < fp.segs) {
     const bool bg = fp.mode == RSZ_BIN_BACKGROUND;
     uint32_t *mask = s_mask[wv];
-    if ((BB == 2 || BB == 4) && fp.vec) {
-      if (bg) bin_tile<BB, true, true, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
-      else bin_tile<BB, true, false, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
-    } else {
+    bool vec = false;
+    if constexpr (BB == 2 || BB == 4) {
+      vec = fp.vec != 0;
+      if (vec) {
+        if (bg) bin_tile<BB, true, true, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
+        else bin_tile<BB, true, false, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
+      }
+    }
+    if (!vec) {
       if (bg) bin_tile<BB, false, true, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
       else bin_tile<BB, false, false, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
     }
