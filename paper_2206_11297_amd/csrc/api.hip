@@ -108,7 +108,7 @@ static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const G
   uint64_t b = 0;
   b += align_up(4ull * ((uint64_t)p->panels * g.segs + 1), 256);  // bstart
   b += align_up(4ull * npeaks, 256);                              // bucket
-  b += align_up(2ull * kChunk * g.nchunks, 256);  // codes, padded to whole chunks
+  b += align_up(1ull * kChunk * g.nchunks, 256);  // code bytes, padded to whole chunks
   b += align_up(4ull * g.nbins, 256);          // rbuf
   b += align_up(4ull * g.nbins, 256);          // obuf
   b += 3 * align_up(4ull * g.nchunks, 256);    // chunk_off, chunk_oo, head
@@ -235,8 +235,8 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     base += align_up(4ull * ((uint64_t)p->panels * g.segs + 1), 256);
     fp.bucket = (uint32_t *)base;
     base += align_up(4ull * np[f], 256);
-    fp.codes = (uint16_t *)base;
-    base += align_up(2ull * kChunk * g.nchunks, 256);
+    fp.codes = base;
+    base += align_up(1ull * kChunk * g.nchunks, 256);
     fp.rbuf = (int32_t *)base;
     base += align_up(4ull * g.nbins, 256);
     fp.obuf = (uint32_t *)base;
@@ -492,8 +492,7 @@ static int single_frame(const rsz_params *p, const float *d_frame, const rsz_pea
     // the codebook intermediates sit in the frame's state and region
     const FramePlan *fp = (const FramePlan *)hp.bytes.data();
     const FrameState *fs = fp->st;
-    if (dbg->codes &&
-        hipMemcpyAsync(dbg->codes, fp->codes, 2ull * fp->nbins, hipMemcpyDeviceToDevice, s))
+    if (dbg->codes && launch_debug_codes(hp.bp, fp->nbins, dbg->codes, s) != hipSuccess)
       return RSZ_ERR_HIP;
     if (dbg->hist && hipMemcpyAsync(dbg->hist, fs->hist, 4 * kNumSym, hipMemcpyDeviceToDevice, s))
       return RSZ_ERR_HIP;

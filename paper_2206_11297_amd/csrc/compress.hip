@@ -189,6 +189,16 @@ __device__ __forceinline__ int32_t from_left(int32_t v, int32_t first) {
   return __builtin_amdgcn_update_dpp(first, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
 
+// Codes travel from the binning kernel to the encoder as one byte per bin:
+// r + 128 for |r| <= 127, else 0 with the bin's residual in rbuf (codes
+// 1..384 and 640..1023, and the outliers).
+__device__ __forceinline__ uint32_t code_byte(int32_t r) {
+  return (uint32_t)(r + 127) < 255u ? (uint32_t)(r + 128) : 0u;
+}
+__device__ __forceinline__ uint32_t code_from_residual(int32_t r) {
+  return (r > -kRadius && r < kRadius) ? (uint32_t)(r + kRadius) : 0u;
+}
+
 // q = rint(S / den) with den = n*2eb and S/den correctly rounded.  Fast path:
 // t1 = S * inv with inv = 1/den correctly rounded differs from the exact
 // quotient x by at most (2u + u^2)|x| and from the rounded quotient by at
@@ -436,7 +446,7 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
   const float *fr = fp.frame + (size_t)p * H * W;
   const double step = fp.step;
   const size_t gbase = (size_t)p * Hb * Wb;
-  uint16_t *codes = fp.codes + gbase;
+  uint8_t *codes = fp.codes + gbase;
   int32_t *rbuf = fp.rbuf + gbase;
   bool range_err = false;
   uint32_t c512 = 0;
@@ -552,14 +562,15 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
         const int32_t q = colv ? qv : 0;
         const int32_t ql = from_left(q, left);
         left = __builtin_amdgcn_readlane(q, 63);
-        // residual + radius; codes 1..1023 carry it, 0 marks an outlier
-        const int32_t c = q + ql_up[s] + kRadius - q_up[s] - ql;
-        const uint32_t code = (uint32_t)c < (uint32_t)kNumSym ? (uint32_t)c : 0u;
+        // residual; codes 1..1023 carry r + 512, 0 marks an outlier
+        const int32_t r = q + ql_up[s] - q_up[s] - ql;
+        const uint32_t code = code_from_residual(r);
         if (colv) {
           const size_t g = (size_t)I * Wb + J;
+          const uint32_t cb = code_byte(r);
           // row pointer (wave-uniform) + 32-bit lane offset
-          *(uint16_t *)((char *)(codes + (size_t)I * Wb) + J * 2u) = (uint16_t)code;
-          if (code == 0) *(int32_t *)((char *)(rbuf + (size_t)I * Wb) + J * 4u) = c - kRadius;
+          codes[(size_t)I * Wb + J] = (uint8_t)cb;
+          if (cb == 0) *(int32_t *)((char *)(rbuf + (size_t)I * Wb) + J * 4u) = r;
           if (DEBUG) {
             if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
             if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
@@ -741,9 +752,9 @@ __global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
 
 // ---------------------------------------------------------------- k_count
 
-// Bits and outliers of every 4096-symbol chunk: one wave per chunk, 64 codes
-// per lane (the codes region is padded to whole chunks, so the 16-byte loads
-// stay inside it).  Work item = (frame, chunk) through the chunk prefix, four
+// Bits and outliers of every 4096-symbol chunk: one wave per chunk, 64 code
+// bytes per lane (the codes region is padded to whole chunks, so the 16-byte
+// loads stay inside it).  Work item = (frame, chunk) through the chunk prefix, four
 // per workgroup.
 __global__ __launch_bounds__(256) void k_count(BatchPlan bp) {
   __shared__ uint4 s_len4[4][kNumSym / 16];   // each wave's frame code lengths
@@ -758,23 +769,31 @@ __global__ __launch_bounds__(256) void k_count(BatchPlan bp) {
   const uint32_t c = item - bp.chunk_prefix[fw];
   const uint32_t g0 = c * kChunk + lane * 64;
   const uint4 *cv = (const uint4 *)(fp.codes + g0);
-  uint4 v[8];
+  uint4 v[4];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = cv[k];
+  for (int k = 0; k < 4; ++k) v[k] = cv[k];
   s_len4[wv][lane] = ((const uint4 *)fp.st->lens)[lane];
   wave_sync();
   const uint8_t *lens = (const uint8_t *)s_len4[wv];
   uint32_t bits = 0, nout = 0;
+  uint64_t esc = 0;   // this lane's bytes that defer to the residual
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < 4; ++k) {
     const uint32_t w4[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const uint32_t code = (w4[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-      const bool in = g0 + k * 8 + e < fp.nbins;
-      bits += in ? lens[code & (kNumSym - 1)] : 0u;
-      nout += (in && code == 0) ? 1u : 0u;
+    for (int e = 0; e < 16; ++e) {
+      const uint32_t b = (w4[e >> 2] >> (8 * (e & 3))) & 0xFFu;
+      const bool in = g0 + k * 16 + e < fp.nbins;
+      bits += (in && b) ? lens[b + (kRadius - 128)] : 0u;
+      esc |= (uint64_t)(in && !b) << (k * 16 + e);
     }
+  }
+  while (esc) {
+    const int e = __builtin_ctzll(esc);
+    esc &= esc - 1;
+    const uint32_t code = code_from_residual(fp.rbuf[g0 + e]);
+    bits += lens[code];
+    nout += code == 0;
   }
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
@@ -846,27 +865,22 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
   const uint64_t cap = fp.out_cap;
   uint32_t *bw = (uint32_t *)(o + fp.off_bits);
   // the codes region is padded to whole chunks: the 16-byte loads stay inside
-  uint4 n0 = make_uint4(0, 0, 0, 0), n1 = n0;
-  if (c0 < c1) {
-    const uint4 *cv = (const uint4 *)(fp.codes + c0 * kChunk + threadIdx.x * 16);
-    n0 = cv[0];
-    n1 = cv[1];
-  }
+  uint4 n0 = make_uint4(0, 0, 0, 0);
+  if (c0 < c1) n0 = *(const uint4 *)(fp.codes + c0 * kChunk + threadIdx.x * 16);
   for (uint32_t lc = c0; lc < c1; ++lc) {
     const uint32_t g0 = lc * kChunk + threadIdx.x * 16;
-    const uint32_t w8[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
-    if (lc + 1 < c1) {   // next chunk's codes in flight while this one is packed
-      const uint4 *cv = (const uint4 *)(fp.codes + g0 + kChunk);
-      n0 = cv[0];
-      n1 = cv[1];
-    }
+    const uint32_t w4[4] = {n0.x, n0.y, n0.z, n0.w};
+    if (lc + 1 < c1)   // next chunk's codes in flight while this one is packed
+      n0 = *(const uint4 *)(fp.codes + g0 + kChunk);
     __syncthreads();   // tables loaded / previous chunk's words written out
     uint32_t code[16];
     uint32_t bits = 0, nout = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const uint32_t g = g0 + k;
-      code[k] = g < fp.nbins ? ((w8[k >> 1] >> (16 * (k & 1))) & 0xFFFFu) : 0xFFFFu;
+      const uint32_t b = (w4[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+      code[k] = g < fp.nbins ? b + (kRadius - 128) : 0xFFFFu;
+      if (g < fp.nbins && b == 0) code[k] = code_from_residual(fp.rbuf[g]);
       if (g < fp.nbins) {
         bits += s_len[code[k]];
         nout += code[k] == 0;
@@ -1022,6 +1036,21 @@ __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
     hipError_t e_ = hipGetLastError();                            \
     if (e_ != hipSuccess) return e_;                              \
   } while (0)
+
+// Debug: the u16 codes of frame 0 of a plan, expanded from the code bytes.
+__global__ __launch_bounds__(256) void k_debug_codes(BatchPlan bp, uint16_t *out) {
+  const FramePlan &fp = bp.frames[0];
+  for (uint32_t g = blockIdx.x * 256 + threadIdx.x; g < fp.nbins; g += gridDim.x * 256) {
+    const uint32_t b = fp.codes[g];
+    out[g] = (uint16_t)(b ? b + (kRadius - 128) : code_from_residual(fp.rbuf[g]));
+  }
+}
+
+hipError_t launch_debug_codes(const BatchPlan &bp, uint32_t nbins, uint16_t *out, hipStream_t s) {
+  const uint32_t grid = std::max(1u, std::min(4096u, (nbins + 255) / 256));
+  hipLaunchKernelGGL(k_debug_codes, dim3(grid), dim3(256), 0, s, bp, out);
+  return hipGetLastError();
+}
 
 // `b`: the common bin factor of the batch, or 0 (mixed or not 1, 2, 4).
 template <bool DEBUG>

@@ -58,8 +58,8 @@ struct FramePlan {
   uint64_t out_cap;
   // stream sections before the bitstream have fixed offsets
   uint64_t off_roi, off_lens, off_chunks, off_bits;
-  uint16_t *codes;          // nbins
-  int32_t *rbuf;            // nbins, residual of outlier bins
+  uint8_t *codes;           // nbins code bytes (r + 128, or 0: see rbuf)
+  int32_t *rbuf;            // nbins, residual of bins whose code byte is 0
   uint32_t *obuf;           // nbins, outlier bin indices in stream order
   uint32_t *chunk_off;      // nchunks: bit count, then bit offset of each chunk
   uint32_t *chunk_oo;       // nchunks: outlier count, then outlier offset
@@ -92,6 +92,7 @@ struct BatchPlan {
 // Launchers (compress.hip).
 // k_prep + k_bin + k_codebook; b = common bin factor of the batch, or 0.
 hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t s, bool debug);
+hipError_t launch_debug_codes(const BatchPlan &bp, uint32_t nbins, uint16_t *out, hipStream_t s);
 // k_count + k_scan + k_encode + k_tail + k_roi.
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s);
 
