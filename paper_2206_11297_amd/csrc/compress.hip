@@ -838,16 +838,32 @@ __global__ __launch_bounds__(256) void k_scan(BatchPlan bp) {
 
 // --------------------------------------------------------------- k_encode
 
-// One workgroup per run of bp.cpw consecutive chunks of a frame; each chunk's
-// bit and outlier offsets come from k_codebook, so no workgroup waits for
-// another.  Bits are packed in LDS and stored as whole words; a chunk's first
-// word, when it starts mid-word, is shared with the previous chunk and goes
-// to head[] for k_tail to merge.
+// Exclusive prefix sum over the lanes of a wave, and the wave total.
+__device__ __forceinline__ uint64_t wave_exclusive_scan(uint64_t v, uint64_t &total) {
+  const int lane = threadIdx.x & 63;
+  uint64_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  total = __shfl(x, 63);
+  return x - v;
+}
+
+// One workgroup per run of bp.cpw consecutive chunks of a frame; its four
+// waves take every fourth chunk, each chunk's bit and outlier offsets come
+// from k_scan, so nothing waits across waves.  A wave packs its chunk in four
+// rounds of 1024 symbols (16 per lane): a wave scan places each lane's bits,
+// the codewords are ORed into the wave's LDS words, and the complete words
+// are stored whole; the round's last partial word carries into the next.  A
+// chunk's first word, when it starts mid-word, is shared with the previous
+// chunk and goes to head[] for k_tail to merge.
+constexpr int kRoundSyms = 1024;
 __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
   __shared__ uint8_t s_len[kNumSym];
   __shared__ uint32_t s_cw[kNumSym];
-  __shared__ uint32_t s_words[kChunk + 2];
-  __shared__ uint64_t s_tmp[4];
+  __shared__ uint32_t s_words[kWaves][kRoundSyms + 1];   // 32 bits per symbol at most
   __shared__ int s_ok;
   const uint32_t f = find_frame(bp.unit_prefix, bp.nframes, blockIdx.x);
   const FramePlan &fp = bp.frames[f];
@@ -859,69 +875,93 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
     s_len[s] = st->lens[s];
     s_cw[s] = st->cw[s];
   }
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t *stg = s_words[wv];
+  for (int k = lane; k <= kRoundSyms; k += 64) stg[k] = 0u;
+  __syncthreads();   // tables loaded
   const uint32_t c0 = (blockIdx.x - bp.unit_prefix[f]) * bp.cpw;
   const uint32_t c1 = min(c0 + bp.cpw, fp.nchunks);
   uint8_t *o = fp.out;
   const uint64_t cap = fp.out_cap;
   uint32_t *bw = (uint32_t *)(o + fp.off_bits);
-  // the codes region is padded to whole chunks: the 16-byte loads stay inside
-  uint4 n0 = make_uint4(0, 0, 0, 0);
-  if (c0 < c1) n0 = *(const uint4 *)(fp.codes + c0 * kChunk + threadIdx.x * 16);
-  for (uint32_t lc = c0; lc < c1; ++lc) {
-    const uint32_t g0 = lc * kChunk + threadIdx.x * 16;
-    const uint32_t w4[4] = {n0.x, n0.y, n0.z, n0.w};
-    if (lc + 1 < c1)   // next chunk's codes in flight while this one is packed
-      n0 = *(const uint4 *)(fp.codes + g0 + kChunk);
-    __syncthreads();   // tables loaded / previous chunk's words written out
-    uint32_t code[16];
-    uint32_t bits = 0, nout = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const uint32_t g = g0 + k;
-      const uint32_t b = (w4[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-      code[k] = g < fp.nbins ? b + (kRadius - 128) : 0xFFFFu;
-      if (g < fp.nbins && b == 0) code[k] = code_from_residual(fp.rbuf[g]);
-      if (g < fp.nbins) {
-        bits += s_len[code[k]];
-        nout += code[k] == 0;
-      }
-    }
-    uint64_t tot;
-    const uint64_t ex = block_exclusive_scan<uint64_t>(((uint64_t)nout << 32) | bits, s_tmp, tot);
+  for (uint32_t lc = c0 + wv; lc < c1; lc += kWaves) {
     const uint32_t S0 = fp.chunk_off[lc];
-    const uint32_t O0 = fp.chunk_oo[lc];
-    const uint32_t clen = (uint32_t)tot;
-    const uint32_t nwords = ((S0 & 31) + clen + 31) >> 5;
-    for (uint32_t k = threadIdx.x; k < nwords; k += 256) s_words[k] = 0u;
-    __syncthreads();
-    uint32_t pos = (S0 & 31) + (uint32_t)ex;
-    uint32_t oi = O0 + (uint32_t)(ex >> 32);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      if (code[k] == 0xFFFFu) continue;
-      const uint32_t L = s_len[code[k]];
-      const uint64_t v = ((uint64_t)s_cw[code[k]] << (64 - L)) >> (pos & 31);
-      atomicOr(&s_words[pos >> 5], (uint32_t)(v >> 32));
-      if ((pos & 31) + L > 32) atomicOr(&s_words[(pos >> 5) + 1], (uint32_t)v);
-      pos += L;
-      if (code[k] == 0) {
-        if (oi < fp.nbins) fp.obuf[oi] = g0 + k;
-        oi++;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && fp.off_chunks + 4ull * lc + 4 <= cap)
+    uint32_t oi = fp.chunk_oo[lc];
+    if (lane == 0 && fp.off_chunks + 4ull * lc + 4 <= cap)
       *(uint32_t *)(o + fp.off_chunks + 4ull * lc) = S0;
-    const uint32_t wlo = S0 >> 5;
-    for (uint32_t k = threadIdx.x; k < nwords; k += 256) {
-      const uint32_t v = s_words[k];
-      if (k == 0 && (S0 & 31)) {
-        fp.head[lc] = v;
-        continue;
+    uint32_t pos = S0 & 31;     // bit position in stg[0]
+    uint64_t widx = S0 >> 5;    // stream word of stg[0]
+    bool first = (S0 & 31) != 0;
+    // the codes region is padded to whole chunks: the 16-byte loads stay inside
+    uint4 nx = *(const uint4 *)(fp.codes + lc * kChunk + lane * 16);
+#pragma unroll 1
+    for (int r = 0; r < kChunk / kRoundSyms; ++r) {
+      const uint32_t g0 = lc * kChunk + r * kRoundSyms + lane * 16;
+      const uint32_t w4[4] = {nx.x, nx.y, nx.z, nx.w};
+      if (r + 1 < kChunk / kRoundSyms) nx = *(const uint4 *)(fp.codes + g0 + kRoundSyms);
+      uint32_t code[16];
+      uint32_t bits = 0, nout = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t g = g0 + k;
+        const uint32_t b = (w4[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+        code[k] = g < fp.nbins ? b + (kRadius - 128) : 0xFFFFu;
+        if (g < fp.nbins && b == 0) code[k] = code_from_residual(fp.rbuf[g]);
+        if (g < fp.nbins) {
+          bits += s_len[code[k]];
+          nout += code[k] == 0;
+        }
       }
-      const uint64_t widx = (uint64_t)wlo + k;
-      if (fp.off_bits + 4 * widx + 4 <= cap) bw[widx] = v;
+      uint64_t tot;
+      const uint64_t ex = wave_exclusive_scan(((uint64_t)nout << 32) | bits, tot);
+      uint32_t p = pos + (uint32_t)ex;
+      uint32_t q = oi + (uint32_t)(ex >> 32);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (code[k] == 0xFFFFu) continue;
+        const uint32_t L = s_len[code[k]];
+        const uint64_t v = ((uint64_t)s_cw[code[k]] << (64 - L)) >> (p & 31);
+        atomicOr(&stg[p >> 5], (uint32_t)(v >> 32));
+        if ((p & 31) + L > 32) atomicOr(&stg[(p >> 5) + 1], (uint32_t)v);
+        p += L;
+        if (code[k] == 0) {
+          if (q < fp.nbins) fp.obuf[q] = g0 + k;
+          q++;
+        }
+      }
+      wave_sync();
+      const uint32_t end = pos + (uint32_t)tot;   // bits in stg
+      const uint32_t nw = end >> 5;               // complete words
+      for (uint32_t k = lane; k < nw; k += 64) {
+        const uint32_t v = stg[k];
+        if (k == 0 && first) {
+          fp.head[lc] = v;
+          continue;
+        }
+        if (fp.off_bits + 4 * (widx + k) + 4 <= cap) bw[widx + k] = v;
+      }
+      if (nw) first = false;
+      const uint32_t carry = stg[nw];
+      wave_sync();
+      for (uint32_t k = lane; k <= nw; k += 64) stg[k] = k == 0 ? carry : 0u;
+      wave_sync();
+      pos = end & 31;
+      widx += nw;
+      oi += (uint32_t)(tot >> 32);
     }
+    // the chunk's last, partial word: this chunk owns it (the next chunk's
+    // bits in it arrive through head[])
+    if (pos) {
+      const uint32_t v = stg[0];
+      if (lane == 0) {
+        if (first) fp.head[lc] = v;
+        else if (fp.off_bits + 4 * widx + 4 <= cap) bw[widx] = v;
+      }
+    }
+    wave_sync();
+    if (lane == 0) stg[0] = 0u;
+    wave_sync();
   }
 }
 
