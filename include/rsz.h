@@ -194,6 +194,18 @@ int rsz_debug_intermediates(const rsz_params *p, const float *d_frame, const rsz
                             uint32_t npeaks, const rsz_debug_bufs *bufs, void *d_ws,
                             uint64_t ws_bytes, void *stream);
 
+/* Huffman code lengths and canonical codewords of one 1024-symbol histogram,
+ * computed by the kernel of the compression path (the Huffman stage of the
+ * SZ compressor, Sec. V-C: two-queue construction over leaves sorted by
+ * (count, symbol), a leaf first on equal weights, lengths limited to 32 by
+ * halving the counts, canonical codewords in (length, symbol) order).  For
+ * parity checks.  h_hist: 1024 counts (host), at least one nonzero, sum below
+ * 2^27; h_lens (1024 u8) and h_cw (1024 u32) receive the results (host).
+ * d_ws: device workspace of at least 16 KiB, 256-byte aligned.  Synchronous
+ * with respect to `stream`. */
+int rsz_debug_codebook(const uint32_t *h_hist, uint8_t *h_lens, uint32_t *h_cw, void *d_ws,
+                       uint64_t ws_bytes, void *stream);
+
 /* Kernel timing with HIP events recorded around every launch, on the stream
  * the kernel runs on.  rsz_profile_enable(1) clears and starts recording;
  * rsz_profile_read waits for the recorded events and returns, per kernel

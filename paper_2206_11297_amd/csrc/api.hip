@@ -182,8 +182,11 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     if (valid[f]) all_chunks += gs[f].nchunks;
   // chunks per encode workgroup (its waves take every kWaves-th chunk): a
   // multiple of kWaves, about 8192 workgroups for large batches
+  const bool enc_block = all_chunks < kBlockEncodeChunks;
   const uint32_t cpw =
-      kWaves * (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, all_chunks / (8192 * kWaves)));
+      enc_block ? 1u
+                : kWaves * (uint32_t)std::min<uint64_t>(
+                               8, std::max<uint64_t>(1, all_chunks / (8192 * kWaves)));
   for (uint32_t f = 0; f < nframes; ++f) {
     FramePlan &fp = fpl[f];
     memset(&fp, 0, sizeof fp);
@@ -272,6 +275,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   hp.bp.total_units = (uint32_t)units;
   hp.bp.total_peaks = (uint32_t)npk_total;
   hp.bp.cpw = cpw;
+  hp.bp.enc_block = enc_block ? 1u : 0u;
   hp.bp.frames = (const FramePlan *)(ws + L.plans);
   hp.bp.tile_prefix = (const uint32_t *)(ws + L.prefix);
   hp.bp.unit_prefix = hp.bp.tile_prefix + (nframes + 1);
@@ -662,6 +666,39 @@ int rsz_graph_launch(void *graph_exec, void *stream) {
 int rsz_graph_destroy(void *graph_exec) {
   if (!graph_exec) return RSZ_ERR_ARG;
   return hipGraphExecDestroy((hipGraphExec_t)graph_exec) == hipSuccess ? RSZ_OK : RSZ_ERR_HIP;
+}
+
+int rsz_debug_codebook(const uint32_t *h_hist, uint8_t *h_lens, uint32_t *h_cw, void *d_ws,
+                       uint64_t ws_bytes, void *stream) {
+  if (!h_hist || !h_lens || !h_cw || !d_ws || (uintptr_t)d_ws % 256) return RSZ_ERR_ARG;
+  uint64_t total = 0;
+  for (int i = 0; i < kNumSym; ++i) total += h_hist[i];
+  if (total == 0 || total >= (1ull << 27)) return RSZ_ERR_ARG;
+  const uint64_t off_state = align_up(sizeof(FramePlan), 256);
+  if (ws_bytes < off_state + sizeof(FrameState)) return RSZ_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t *ws = (uint8_t *)d_ws;
+  FramePlan fp;
+  memset(&fp, 0, sizeof fp);
+  fp.st = (FrameState *)(ws + off_state);
+  FrameState fs;
+  memset(&fs, 0, sizeof fs);
+  fs.status = RSZ_OK;
+  memcpy(fs.hist, h_hist, sizeof fs.hist);
+  BatchPlan bp;
+  memset(&bp, 0, sizeof bp);
+  bp.nframes = 1;
+  bp.frames = (const FramePlan *)ws;
+  if (hipMemcpyAsync(ws, &fp, sizeof fp, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ws + off_state, &fs, sizeof fs, hipMemcpyHostToDevice, s) != hipSuccess ||
+      launch_codebook(bp, s) != hipSuccess ||
+      hipMemcpyAsync(h_lens, ((FrameState *)(ws + off_state))->lens, kNumSym,
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(h_cw, ((FrameState *)(ws + off_state))->cw, 4 * kNumSym,
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return RSZ_ERR_HIP;
+  return RSZ_OK;
 }
 
 int rsz_profile_enable(int enable) {

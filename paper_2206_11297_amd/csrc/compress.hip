@@ -633,10 +633,12 @@ __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
 
 // ------------------------------------------------------------- k_codebook
 
-__device__ void bitonic_sort_1024(uint64_t *key) {
-  for (uint32_t k = 2; k <= 1024; k <<= 1)
+// Ascending bitonic sort of key[0, n), n a power of two <= 1024, by the
+// workgroup (unique keys).
+__device__ void bitonic_sort(uint64_t *key, uint32_t n) {
+  for (uint32_t k = 2; k <= n; k <<= 1)
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t t = threadIdx.x; t < 512; t += 256) {
+      for (uint32_t t = threadIdx.x; t < n / 2; t += 256) {
         const uint32_t i = 2 * t - (t & (j - 1));
         const uint32_t l = i + j;
         const bool asc = (i & k) == 0;
@@ -650,6 +652,30 @@ __device__ void bitonic_sort_1024(uint64_t *key) {
     }
 }
 
+// Gathers key(s) of the symbols with keep(s) into key[0, n) in symbol order,
+// pads with ~0 up to the next power of two and sorts; returns n.
+template <class KeyOf>
+__device__ uint32_t gather_and_sort(uint64_t *key, uint32_t *s_tmp32, KeyOf key_of) {
+  uint64_t kv[4];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    kv[e] = key_of(threadIdx.x * 4 + e);
+    cnt += kv[e] != ~0ull;
+  }
+  uint32_t n;
+  uint32_t pos = block_exclusive_scan<uint32_t>(cnt, s_tmp32, n);
+  uint32_t p2 = 1;
+  while (p2 < n) p2 <<= 1;
+  for (uint32_t i = n + threadIdx.x; i < p2; i += 256) key[i] = ~0ull;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (kv[e] != ~0ull) key[pos++] = kv[e];
+  __syncthreads();
+  if (p2 > 1) bitonic_sort(key, p2);
+  return n;
+}
+
 // Huffman code lengths by the two-queue method over leaves sorted by
 // (count, symbol), internal nodes in creation order, a leaf taken first on
 // equal weights; lengths above 32 make the counts halve (kept >= 1) and the
@@ -658,76 +684,103 @@ __global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
   const FramePlan &fp = bp.frames[blockIdx.x];
   FrameState *st = fp.st;
   __shared__ uint64_t s_key[kNumSym];
-  __shared__ uint64_t s_w[2 * kNumSym];
-  __shared__ uint64_t s_weight[kNumSym];
-  __shared__ uint16_t s_par[2 * kNumSym];
-  __shared__ uint16_t s_dep[2 * kNumSym];
+  __shared__ uint32_t s_w[2 * kNumSym];      // node weights: leaves, then internal nodes
+  __shared__ uint16_t s_anc[2][2 * kNumSym]; // parents, then ancestors (pointer jumping)
+  __shared__ uint16_t s_dep[2][2 * kNumSym];
+  __shared__ uint32_t s_weight[kNumSym];
   __shared__ uint8_t s_len[kNumSym];
   __shared__ uint32_t s_blc[kMaxLen + 1];
-  __shared__ uint64_t s_first[kMaxLen + 1];
+  __shared__ uint32_t s_first[kMaxLen + 1];
   __shared__ uint32_t s_start[kMaxLen + 1];
-  __shared__ int s_nl, s_maxlen, s_ok;
+  __shared__ uint32_t s_tmp32[4];
+  __shared__ int s_maxlen, s_ok;
   if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
   __syncthreads();
   if (!s_ok) return;
   for (int s = threadIdx.x; s < kNumSym; s += 256) {
-    s_weight[s] = st->hist[s];
+    s_weight[s] = st->hist[s];   // the counts sum to nbins < 2^27
     s_len[s] = 0;
   }
   __syncthreads();
+  uint32_t nl;
+  int cur = 0;   // pointer-jumping buffer holding the final depths
   for (;;) {
-    for (int s = threadIdx.x; s < kNumSym; s += 256)
-      s_key[s] = s_weight[s] ? ((s_weight[s] << 10) | (uint64_t)s) : ~0ull;
-    if (threadIdx.x == 0) s_nl = 0;
+    nl = gather_and_sort(s_key, s_tmp32, [&](uint32_t sym) {
+      const uint32_t w = s_weight[sym];
+      return w ? (((uint64_t)w << 10) | sym) : ~0ull;
+    });
+    const uint32_t nn = nl ? 2 * nl - 1 : 0;   // nodes; the root is nn - 1
+    for (uint32_t i = threadIdx.x; i < nl; i += 256) s_w[i] = (uint32_t)(s_key[i] >> 10);
     __syncthreads();
-    bitonic_sort_1024(s_key);
-    for (int i = threadIdx.x; i < kNumSym; i += 256)
-      if (s_key[i] != ~0ull && (i == kNumSym - 1 || s_key[i + 1] == ~0ull)) s_nl = i + 1;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int nl = s_nl;
-      int maxlen = 0;
-      if (nl == 1) {
-        s_dep[0] = 1;
-        maxlen = 1;
-      } else if (nl > 1) {
-        for (int i = 0; i < nl; ++i) s_w[i] = s_key[i] >> 10;
-        int lf = 0, nf = nl, ne = nl;
-        for (int m = 0; m < nl - 1; ++m) {
-          int a, c;
-          if (nf == ne || (lf < nl && s_w[lf] <= s_w[nf])) a = lf++; else a = nf++;
-          if (nf == ne || (lf < nl && s_w[lf] <= s_w[nf])) c = lf++; else c = nf++;
-          s_w[ne] = s_w[a] + s_w[c];
-          s_par[a] = (uint16_t)ne;
-          s_par[c] = (uint16_t)ne;
-          ne++;
+    if (threadIdx.x == 0 && nl > 1) {
+      // the merge is sequential; the next leaf weight is read ahead
+      uint32_t lf = 0, nf = nl, ne = nl;
+      uint32_t wl = s_w[0];
+      for (uint32_t m = 0; m + 1 < nl; ++m) {
+        uint32_t pick[2], wsum = 0;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const bool leaf = nf == ne || (lf < nl && wl <= s_w[nf]);
+          if (leaf) {
+            pick[t] = lf++;
+            wsum += wl;
+            wl = lf < nl ? s_w[lf] : 0u;
+          } else {
+            pick[t] = nf;
+            wsum += s_w[nf++];
+          }
         }
-        s_dep[ne - 1] = 0;
-        for (int v = ne - 2; v >= 0; --v) s_dep[v] = s_dep[s_par[v]] + 1;
-        for (int i = 0; i < nl; ++i) maxlen = max(maxlen, (int)s_dep[i]);
+        s_w[ne] = wsum;
+        s_anc[0][pick[0]] = (uint16_t)ne;
+        s_anc[0][pick[1]] = (uint16_t)ne;
+        ne++;
       }
-      s_maxlen = maxlen;
+    }
+    __syncthreads();
+    // depth of every node by pointer jumping: dep = distance to anc
+    const uint32_t root = nn ? nn - 1 : 0;
+    for (uint32_t v = threadIdx.x; v < nn; v += 256) {
+      s_dep[0][v] = v == root ? 0 : 1;
+      if (v == root) s_anc[0][v] = (uint16_t)root;
+    }
+    __syncthreads();
+    cur = 0;
+    for (uint32_t span = 1; span < nn; span <<= 1) {
+      for (uint32_t v = threadIdx.x; v < nn; v += 256) {
+        const uint32_t a = s_anc[cur][v];
+        s_dep[cur ^ 1][v] = s_dep[cur][v] + s_dep[cur][a];
+        s_anc[cur ^ 1][v] = s_anc[cur][a];
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    if (threadIdx.x == 0) s_maxlen = nl == 1 ? 1 : 0;
+    __syncthreads();
+    if (nl > 1) {
+      uint32_t mx = 0;
+      for (uint32_t i = threadIdx.x; i < nl; i += 256) mx = max(mx, (uint32_t)s_dep[cur][i]);
+      atomicMax(&s_maxlen, (int)mx);
     }
     __syncthreads();
     if (s_maxlen <= kMaxLen) break;
     for (int s = threadIdx.x; s < kNumSym; s += 256)
-      if (s_weight[s]) s_weight[s] = (s_weight[s] >> 1) ? (s_weight[s] >> 1) : 1ull;
+      if (s_weight[s]) s_weight[s] = (s_weight[s] >> 1) ? (s_weight[s] >> 1) : 1u;
     __syncthreads();
   }
-  const int nl = s_nl;
-  for (int i = threadIdx.x; i < nl; i += 256) s_len[s_key[i] & 1023] = (uint8_t)s_dep[i];
+  // lengths by symbol; a single used symbol gets length 1
+  for (uint32_t i = threadIdx.x; i < nl; i += 256)
+    s_len[s_key[i] & 1023] = nl == 1 ? 1 : (uint8_t)s_dep[cur][i];
   if (threadIdx.x <= kMaxLen) s_blc[threadIdx.x] = 0;
   __syncthreads();
-  for (int s = threadIdx.x; s < kNumSym; s += 256) {
-    const uint32_t L = s_len[s];
-    s_key[s] = L ? (((uint64_t)L << 10) | (uint64_t)s) : ~0ull;
-    if (L) atomicAdd(&s_blc[L], 1u);
-  }
+  // canonical order: the used symbols sorted by (length, symbol)
+  const uint32_t nu = gather_and_sort(s_key, s_tmp32, [&](uint32_t sym) {
+    const uint32_t L = s_len[sym];
+    return L ? (((uint64_t)L << 10) | sym) : ~0ull;
+  });
+  for (uint32_t i = threadIdx.x; i < nu; i += 256) atomicAdd(&s_blc[s_key[i] >> 10], 1u);
   __syncthreads();
-  bitonic_sort_1024(s_key);
   if (threadIdx.x == 0) {
-    uint64_t code = 0;
-    uint32_t start = 0;
+    uint32_t code = 0, start = 0;
     s_blc[0] = 0;
     for (int L = 1; L <= kMaxLen; ++L) {
       code = (code + s_blc[L - 1]) << 1;
@@ -742,11 +795,10 @@ __global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
     st->cw[s] = 0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kNumSym; i += 256) {
+  for (uint32_t i = threadIdx.x; i < nu; i += 256) {
     const uint64_t k = s_key[i];
-    if (k == ~0ull) continue;
-    const uint32_t L = (uint32_t)(k >> 10), s = (uint32_t)(k & 1023);
-    st->cw[s] = (uint32_t)(s_first[L] + (uint64_t)(i - s_start[L]));
+    const uint32_t L = (uint32_t)(k >> 10), sym = (uint32_t)(k & 1023);
+    st->cw[sym] = s_first[L] + (i - s_start[L]);
   }
 }
 
@@ -965,6 +1017,91 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
   }
 }
 
+// Small batches: one workgroup per run of bp.cpw chunks, all 256 threads on
+// one chunk at a time (16 symbols each), so a chunk is packed in one pass.
+// Same offsets, words and head[] protocol as k_encode.
+__global__ __launch_bounds__(256) void k_encode_block(BatchPlan bp) {
+  __shared__ uint8_t s_len[kNumSym];
+  __shared__ uint32_t s_cw[kNumSym];
+  __shared__ uint32_t s_words[kChunk + 2];
+  __shared__ uint64_t s_tmp[4];
+  __shared__ int s_ok;
+  const uint32_t f = find_frame(bp.unit_prefix, bp.nframes, blockIdx.x);
+  const FramePlan &fp = bp.frames[f];
+  const FrameState *st = fp.st;
+  if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
+  __syncthreads();
+  if (!s_ok) return;
+  for (int s = threadIdx.x; s < kNumSym; s += 256) {
+    s_len[s] = st->lens[s];
+    s_cw[s] = st->cw[s];
+  }
+  const uint32_t c0 = (blockIdx.x - bp.unit_prefix[f]) * bp.cpw;
+  const uint32_t c1 = min(c0 + bp.cpw, fp.nchunks);
+  uint8_t *o = fp.out;
+  const uint64_t cap = fp.out_cap;
+  uint32_t *bw = (uint32_t *)(o + fp.off_bits);
+  // the codes region is padded to whole chunks: the 16-byte loads stay inside
+  uint4 n0 = make_uint4(0, 0, 0, 0);
+  if (c0 < c1) n0 = *(const uint4 *)(fp.codes + c0 * kChunk + threadIdx.x * 16);
+  for (uint32_t lc = c0; lc < c1; ++lc) {
+    const uint32_t g0 = lc * kChunk + threadIdx.x * 16;
+    const uint32_t w4[4] = {n0.x, n0.y, n0.z, n0.w};
+    if (lc + 1 < c1)   // next chunk's codes in flight while this one is packed
+      n0 = *(const uint4 *)(fp.codes + g0 + kChunk);
+    __syncthreads();   // tables loaded / previous chunk's words written out
+    uint32_t code[16];
+    uint32_t bits = 0, nout = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t g = g0 + k;
+      const uint32_t b = (w4[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+      code[k] = g < fp.nbins ? b + (kRadius - 128) : 0xFFFFu;
+      if (g < fp.nbins && b == 0) code[k] = code_from_residual(fp.rbuf[g]);
+      if (g < fp.nbins) {
+        bits += s_len[code[k]];
+        nout += code[k] == 0;
+      }
+    }
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan<uint64_t>(((uint64_t)nout << 32) | bits, s_tmp, tot);
+    const uint32_t S0 = fp.chunk_off[lc];
+    const uint32_t O0 = fp.chunk_oo[lc];
+    const uint32_t clen = (uint32_t)tot;
+    const uint32_t nwords = ((S0 & 31) + clen + 31) >> 5;
+    for (uint32_t k = threadIdx.x; k < nwords; k += 256) s_words[k] = 0u;
+    __syncthreads();
+    uint32_t pos = (S0 & 31) + (uint32_t)ex;
+    uint32_t oi = O0 + (uint32_t)(ex >> 32);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (code[k] == 0xFFFFu) continue;
+      const uint32_t L = s_len[code[k]];
+      const uint64_t v = ((uint64_t)s_cw[code[k]] << (64 - L)) >> (pos & 31);
+      atomicOr(&s_words[pos >> 5], (uint32_t)(v >> 32));
+      if ((pos & 31) + L > 32) atomicOr(&s_words[(pos >> 5) + 1], (uint32_t)v);
+      pos += L;
+      if (code[k] == 0) {
+        if (oi < fp.nbins) fp.obuf[oi] = g0 + k;
+        oi++;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && fp.off_chunks + 4ull * lc + 4 <= cap)
+      *(uint32_t *)(o + fp.off_chunks + 4ull * lc) = S0;
+    const uint32_t wlo = S0 >> 5;
+    for (uint32_t k = threadIdx.x; k < nwords; k += 256) {
+      const uint32_t v = s_words[k];
+      if (k == 0 && (S0 & 31)) {
+        fp.head[lc] = v;
+        continue;
+      }
+      const uint64_t widx = (uint64_t)wlo + k;
+      if (fp.off_bits + 4 * widx + 4 <= cap) bw[widx] = v;
+    }
+  }
+}
+
 // ----------------------------------------------------------------- k_tail
 
 __device__ __forceinline__ void put_u32(uint8_t *o, uint64_t off, uint32_t v) {
@@ -1077,6 +1214,11 @@ __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
     if (e_ != hipSuccess) return e_;                              \
   } while (0)
 
+hipError_t launch_codebook(const BatchPlan &bp, hipStream_t s) {
+  hipLaunchKernelGGL(k_codebook, dim3(bp.nframes), dim3(256), 0, s, bp);
+  return hipGetLastError();
+}
+
 // Debug: the u16 codes of frame 0 of a plan, expanded from the code bytes.
 __global__ __launch_bounds__(256) void k_debug_codes(BatchPlan bp, uint16_t *out) {
   const FramePlan &fp = bp.frames[0];
@@ -1117,7 +1259,10 @@ hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t 
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
   if (bp.total_chunks) RSZ_LAUNCH("k_count", k_count, (bp.total_chunks + 3) / 4, s, bp);
   RSZ_LAUNCH("k_scan", k_scan, bp.nframes, s, bp);
-  if (bp.total_units) RSZ_LAUNCH("k_encode", k_encode, bp.total_units, s, bp);
+  if (bp.total_units) {
+    if (bp.enc_block) RSZ_LAUNCH("k_encode", k_encode_block, bp.total_units, s, bp);
+    else RSZ_LAUNCH("k_encode", k_encode, bp.total_units, s, bp);
+  }
   RSZ_LAUNCH("k_tail", k_tail, bp.nframes, s, bp);
   if (bp.total_peaks) RSZ_LAUNCH("k_roi", k_roi, bp.total_peaks, s, bp);
   return hipSuccess;

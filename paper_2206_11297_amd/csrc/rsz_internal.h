@@ -22,6 +22,7 @@ constexpr uint64_t kHeader = 80;
 constexpr int kWaves = 4;
 constexpr int kMaxTH = 32;
 constexpr int kMaskWords = 896;       // per wave: (TH+1)*b rows x (2b*strips+1) words
+constexpr uint32_t kBlockEncodeChunks = 4096;   // fewer chunks in a batch: k_encode_block
 
 // Strips per column group for bin factor b as compiled in the binning kernel
 // (0: any b, and batches mixing bin factors).
@@ -82,6 +83,7 @@ struct BatchPlan {
   uint32_t nframes;
   uint32_t total_tiles, total_units, total_peaks, total_chunks;
   uint32_t cpw;                  // chunks encoded by one k_encode workgroup
+  uint32_t enc_block;            // small batch: a workgroup packs one chunk at a time
   const FramePlan *frames;
   const uint32_t *tile_prefix;   // nframes + 1
   const uint32_t *unit_prefix;   // nframes + 1 (units of cpw chunks)
@@ -93,6 +95,7 @@ struct BatchPlan {
 // k_prep + k_bin + k_codebook; b = common bin factor of the batch, or 0.
 hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t s, bool debug);
 hipError_t launch_debug_codes(const BatchPlan &bp, uint32_t nbins, uint16_t *out, hipStream_t s);
+hipError_t launch_codebook(const BatchPlan &bp, hipStream_t s);
 // k_count + k_scan + k_encode + k_tail + k_roi.
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s);
 

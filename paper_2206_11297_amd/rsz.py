@@ -20,7 +20,8 @@ EXPORTS = ["rsz_status_string", "rsz_max_compressed_bytes", "rsz_workspace_bytes
            "rsz_batch_prepare", "rsz_batch_launch", "rsz_batch_graph_create",
            "rsz_graph_launch", "rsz_graph_destroy",
            "rsz_stream_info", "rsz_decompress_workspace_bytes", "rsz_decompress",
-           "rsz_debug_intermediates", "rsz_profile_enable", "rsz_profile_read"]
+           "rsz_debug_intermediates", "rsz_debug_codebook", "rsz_profile_enable",
+           "rsz_profile_read"]
 
 
 class RszError(RuntimeError):
@@ -84,6 +85,7 @@ def lib():
         L.rsz_decompress.argtypes = [vp, u64, vp, u64, vp, u64, vp]
         L.rsz_debug_intermediates.argtypes = [P(rsz_params), vp, vp, u32, P(rsz_debug_bufs), vp,
                                               u64, vp]
+        L.rsz_debug_codebook.argtypes = [vp, vp, vp, vp, u64, vp]
         L.rsz_profile_enable.argtypes = [C.c_int]
         L.rsz_profile_read.argtypes = [P(rsz_kernel_time), C.c_int, P(C.c_int)]
         _lib = L
@@ -182,6 +184,24 @@ def rsz_decompress(d_in, in_bytes, d_frame, frame_elems, d_ws, ws_bytes, stream)
 def rsz_debug_intermediates(p, d_frame, d_peaks, npeaks, bufs, d_ws, ws_bytes, stream):
     return lib().rsz_debug_intermediates(C.byref(p), d_frame, d_peaks, npeaks, C.byref(bufs),
                                          d_ws, ws_bytes, stream)
+
+
+def debug_codebook(hist):
+    """Code lengths and canonical codewords of a 1024-bin histogram from the
+    GPU codebook kernel (numpy in, numpy out)."""
+    import numpy as np
+    torch = _torch()
+    h = np.ascontiguousarray(hist, dtype=np.uint32)
+    if h.size != 1024:
+        raise ValueError("histogram must have 1024 bins")
+    lens = np.zeros(1024, np.uint8)
+    cw = np.zeros(1024, np.uint32)
+    ws = workspace(16 << 10, torch.device("cuda", torch.cuda.current_device()))
+    st = lib().rsz_debug_codebook(h.ctypes.data, lens.ctypes.data, cw.ctypes.data, _ptr(ws),
+                                  ws.numel(), _stream())
+    if st:
+        raise RszError(st, "rsz_debug_codebook")
+    return lens, cw
 
 
 def rsz_profile_enable(on):

@@ -284,3 +284,45 @@ def test_dense_peaks_every_band_split(torch, shape, b, npk, w):
         torch.cuda.synchronize()
         assert B.status.cpu().tolist() == [0]
         np.testing.assert_array_equal(B.stream(0).cpu().numpy(), ref)
+
+
+def _fib_hist(n, offset=0):
+    h = np.zeros(1024, np.uint32)
+    a, b = 1, 1
+    for i in range(n):
+        h[(offset + 37 * i) % 1024] = a
+        a, b = b, a + b
+    return h
+
+
+def _codebook_cases():
+    rng = np.random.default_rng([2206, 11297, 55])
+    cases = []
+    for n in (1, 2, 3, 17, 100, 500, 1024):
+        for rep in range(3):
+            h = np.zeros(1024, np.uint32)
+            sym = rng.choice(1024, n, replace=False)
+            h[sym] = np.maximum(1, (rng.zipf(1.3, n) % 100000)).astype(np.uint32)
+            cases.append((f"zipf{n}_{rep}", h))
+    for n in (2, 513, 1024):
+        h = np.zeros(1024, np.uint32)
+        h[:n] = 7
+        cases.append((f"equal{n}", h))
+    h = np.zeros(1024, np.uint32)
+    h[::3] = 1 << (np.arange(342) % 20)
+    cases.append(("powers", h))
+    for n in (33, 34, 36, 38):   # depths past 32: the halving rebuild
+        cases.append((f"fib{n}", _fib_hist(n, n)))
+    return cases
+
+
+@pytest.mark.parametrize("name,hist", _codebook_cases(), ids=[c[0] for c in _codebook_cases()])
+def test_codebook_matches_oracle(torch, name, hist):
+    """Lengths and canonical codewords of the GPU codebook kernel on chosen
+    histograms: few and many symbols, ties, powers of two, and Fibonacci
+    counts whose Huffman depth exceeds 32."""
+    lens, cw = rsz.debug_codebook(hist)
+    ref_lens = O.huffman_lengths(hist)
+    np.testing.assert_array_equal(lens, ref_lens)
+    np.testing.assert_array_equal(cw, O.canonical(ref_lens))
+    assert lens.max() <= 32
