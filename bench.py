@@ -236,6 +236,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="oracle time budget (half single-thread, half frame-parallel)")
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--autotune-seconds", type=float, default=20.0,
+                    help="time budget of the tile-shape autotuner when the shipped table "
+                         "has no entry for this workload (0: library default shape)")
+    ap.add_argument("--tune-store", default=None,
+                    help="JSON file that receives a new autotuner result")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_DIR"),
                     help="summarize two rocprofv3 --pmc runs (CSV output) and exit")
     ap.add_argument("--latency-frames", type=int, default=200)
@@ -273,7 +278,17 @@ def main():
     frames = [torch.from_numpy(f).to(dev) for f, _ in host]
     peaks = [torch.from_numpy(p).to(dev) for _, p in host]
     torch.cuda.synchronize()
-    B = rsz.Batch(frames, peaks, (WINDOW, BIN, EB, rsz.RSZ_BIN_BACKGROUND))
+    prm = (WINDOW, BIN, EB, rsz.RSZ_BIN_BACKGROUND)
+    tile = None
+    if args.autotune_seconds > 0:
+        from paper_2206_11297_amd import autotune
+        tile = autotune.tune(frames, peaks, prm, reps=3, budget_s=args.autotune_seconds,
+                             store_path=args.tune_store)
+        print(f"[bench] autotune: best tile {tile['best']} {tile['ms']} ms "
+              f"(default {tile['default_ms']} ms, {len(tile['table'])} shapes)",
+              file=sys.stderr, flush=True)
+    tile_rows, tile_strips = tile["best"] if tile else (0, 0)
+    B = rsz.Batch(frames, peaks, prm, tile_rows=tile_rows, tile_strips=tile_strips)
     raw_bytes = sum(f.numel() * 4 for f in frames)
     npix = raw_bytes // 4
 
@@ -350,7 +365,12 @@ def main():
         "config": {"workload": f"{WORKLOAD}-{len(frames)}: {len(frames)} frames "
                                f"{SHAPE[0]}x{SHAPE[1]}x{SHAPE[2]} f32, Poisson(60) peaks, "
                                "20% non-hit, window 17, bin 2x2, eb 10 ADU, one batched launch",
-                   "frames": len(frames), "raw_bytes": raw_bytes},
+                   "frames": len(frames), "raw_bytes": raw_bytes,
+                   "tile": {"rows": tile_rows, "strips": tile_strips,
+                            "autotuned": tile is not None,
+                            "from_table": bool(tile and tile.get("cached")),
+                            "default_ms": tile["default_ms"] if tile else None,
+                            "shapes_timed": len(tile["table"]) if tile else 0}},
         "roofline": roof,
         "cpu_baseline": cpu,
         "compression_ratio_u16": {"mean": round(float(cr_u16.mean()), 3),

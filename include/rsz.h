@@ -100,15 +100,19 @@ int rsz_compress(const rsz_params *p, const float *d_frame, const rsz_peak *d_pe
 
 /* One frame of a batch.  out/out_cap: that frame's own output buffer
  * (device); the frames of a batch may have different shapes, parameters and
- * peak counts.  tile_rows: tuning knob, the most bin rows one wave of the
- * binning kernel walks (0 = library default; clamped to what its LDS holds).
- * It changes speed only: the output bytes never depend on it. */
+ * peak counts.  tile_rows, tile_strips: tuning knobs of the binning kernel's
+ * tiles, the most bin rows and 64-column strips one wave walks (0 = library
+ * default: the coarsest tiles that give a batch about 8192 waves;
+ * clamped to what the kernel's LDS and registers hold).  They change speed
+ * only: the output bytes never depend on them.  reserved: set to 0. */
 typedef struct {
   rsz_params params;
   const float *frame;
   const rsz_peak *peaks;
   uint32_t npeaks;
   uint32_t tile_rows;
+  uint32_t tile_strips;
+  uint32_t reserved;
   void *out;
   uint64_t out_cap;
 } rsz_frame_desc;

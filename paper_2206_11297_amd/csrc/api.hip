@@ -164,9 +164,34 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     first = false;
   }
   const uint32_t gsw = (uint32_t)group_strips((int)hp.common_b);
+  // tile shape of each frame: the caller's tile_rows / tile_strips, else the
+  // coarsest shape of the ladder below that gives the batch kTargetWaves
+  // binning waves, down to 8-row single-strip tiles (shorter tiles re-read
+  // too many halo rows; measured on MI355X across 1..1000-frame batches)
+  static const uint32_t ladder[][2] = {{kMaxTH, 0}, {16, 0}, {8, 0}, {8, 1}};
+  auto shape_of = [&](uint32_t f, uint32_t rung, uint32_t &rows, uint32_t &strips) {
+    rows = d[f].tile_rows ? d[f].tile_rows : (th_cap ? th_cap : ladder[rung][0]);
+    const uint32_t sd = th_cap ? 0 : ladder[rung][1];
+    strips = d[f].tile_strips ? std::min(d[f].tile_strips, gsw) : (sd ? std::min(sd, gsw) : gsw);
+  };
+  uint32_t rung = 0;
+  for (; rung + 1 < sizeof ladder / sizeof ladder[0]; ++rung) {
+    uint64_t waves = 0;
+    for (uint32_t f = 0; f < nframes; ++f) {
+      if (!valid[f]) continue;
+      uint32_t rows, strips;
+      shape_of(f, rung, rows, strips);
+      const Geom g = geometry(ps[f], np[f], rows, strips);
+      waves += (uint64_t)ps[f]->panels * g.cgs * g.groups * kWaves;
+    }
+    if (waves >= kTargetWaves) break;
+  }
   for (uint32_t f = 0; f < nframes; ++f)
-    if (valid[f])
-      gs[f] = geometry(ps[f], np[f], d[f].tile_rows ? d[f].tile_rows : th_cap, gsw);
+    if (valid[f]) {
+      uint32_t rows, strips;
+      shape_of(f, rung, rows, strips);
+      gs[f] = geometry(ps[f], np[f], rows, strips);
+    }
   Layout L = layout(nframes, ps, np, gs, valid);
   if (need) *need = L.total;
   if (!ws) return RSZ_OK;
@@ -284,7 +309,6 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   return RSZ_OK;
 }
 
-static uint32_t default_th_cap(uint32_t nframes) { return nframes >= 16 ? kMaxTH : 8; }
 
 // Plans reach the device through a ring of pinned host buffers: a slot is
 // reused only after the event recorded behind its previous copy has fired, so
@@ -332,7 +356,7 @@ static int enqueue(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_byte
                    int32_t *res_status, void *ws, uint64_t ws_bytes, hipStream_t s,
                    const rsz_debug_bufs *dbg, bool front_only, HostPlan &hp) {
   const int st = build_plan(nframes, d, res_bytes, res_status, (uint8_t *)ws, ws_bytes,
-                            default_th_cap(nframes), hp, nullptr, dbg);
+                            0, hp, nullptr, dbg);
   if (st) return st;
   if (stage_to_device(ws, hp.bytes.data(), hp.bytes.size(), s) != RSZ_OK) return RSZ_ERR_HIP;
   if (launch_compress_front_b(hp.bp, hp.common_b, s, dbg != nullptr) != hipSuccess)
@@ -458,7 +482,7 @@ int rsz_workspace_bytes(const rsz_params *p, uint32_t npeaks, uint64_t *bytes) {
                               npeaks, (void *)256, 0);
   HostPlan hp;
   uint64_t need = 0;
-  build_plan(1, &d, nullptr, nullptr, nullptr, 0, default_th_cap(1), hp, &need, nullptr);
+  build_plan(1, &d, nullptr, nullptr, nullptr, 0, 0, hp, &need, nullptr);
   *bytes = need + single_extra();
   return RSZ_OK;
 }
@@ -467,7 +491,7 @@ int rsz_batch_workspace_bytes(uint32_t nframes, const rsz_frame_desc *h_descs, u
   if (!bytes || nframes == 0 || !h_descs) return RSZ_ERR_ARG;
   HostPlan hp;
   uint64_t need = 0;
-  build_plan(nframes, h_descs, nullptr, nullptr, nullptr, 0, default_th_cap(nframes), hp, &need,
+  build_plan(nframes, h_descs, nullptr, nullptr, nullptr, 0, 0, hp, &need,
              nullptr);
   *bytes = need;
   return RSZ_OK;
@@ -606,7 +630,7 @@ int rsz_batch_prepare(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t 
   if ((uintptr_t)d_ws % 256) return RSZ_ERR_ARG;
   HostPlan hp;
   const int st = build_plan(nframes, h_descs, d_out_bytes, d_status, (uint8_t *)d_ws, ws_bytes,
-                            default_th_cap(nframes), hp, nullptr, nullptr);
+                            0, hp, nullptr, nullptr);
   if (st) return st;
   if (stage_to_device(d_ws, hp.bytes.data(), hp.bytes.size(), (hipStream_t)stream) != RSZ_OK)
     return RSZ_ERR_HIP;

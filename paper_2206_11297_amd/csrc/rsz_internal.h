@@ -23,6 +23,7 @@ constexpr int kWaves = 4;
 constexpr int kMaxTH = 32;
 constexpr int kMaskWords = 896;       // per wave: (TH+1)*b rows x (2b*strips+1) words
 constexpr uint32_t kBlockEncodeChunks = 4096;   // fewer chunks in a batch: k_encode_block
+constexpr uint64_t kTargetWaves = 8192;         // default tiling: binning waves per batch
 
 // Strips per column group for bin factor b as compiled in the binning kernel
 // (0: any b, and batches mixing bin factors).

@@ -38,7 +38,8 @@ class rsz_params(C.Structure):
 
 class rsz_frame_desc(C.Structure):
     _fields_ = [("params", rsz_params), ("frame", C.c_void_p), ("peaks", C.c_void_p),
-                ("npeaks", C.c_uint32), ("tile_rows", C.c_uint32), ("out", C.c_void_p),
+                ("npeaks", C.c_uint32), ("tile_rows", C.c_uint32), ("tile_strips", C.c_uint32),
+                ("reserved", C.c_uint32), ("out", C.c_void_p),
                 ("out_cap", C.c_uint64)]
 
 
@@ -337,7 +338,7 @@ class Batch:
     tuple for all.  Output buffers are sized by rsz_max_compressed_bytes and
     packed into one uint8 tensor."""
 
-    def __init__(self, frames, peaks, prm, tile_rows=0):
+    def __init__(self, frames, peaks, prm, tile_rows=0, tile_strips=0):
         torch = _torch()
         self.frames = [f.contiguous() for f in frames]
         self.peaks = [pk.to(dtype=torch.int32).reshape(-1, 3).contiguous() for pk in peaks]
@@ -367,6 +368,7 @@ class Batch:
             d.peaks = self.peaks[i].data_ptr() if self.peaks[i].shape[0] else None
             d.npeaks = self.peaks[i].shape[0]
             d.tile_rows = int(tile_rows)
+            d.tile_strips = int(tile_strips)
             d.out = self.out.data_ptr() + self.offsets[i]
             d.out_cap = caps[i]
             self.descs.append(d)

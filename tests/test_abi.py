@@ -97,3 +97,34 @@ def test_stream_info_rejects_bad_headers_like_the_oracle():
         a = rsz.rsz_stream_info(s2.tobytes())[0]
         b = O.stream_info(s2)[0]
         assert (a == 0) == (b == 0), pos
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes mirror in the binding has the size and field offsets the
+    C compiler gives the structs of include/rsz.h."""
+    import subprocess
+    structs = {"rsz_peak": None, "rsz_params": rsz.rsz_params, "rsz_frame_desc": rsz.rsz_frame_desc,
+               "rsz_batch_plan": rsz.rsz_batch_plan, "rsz_debug_bufs": rsz.rsz_debug_bufs,
+               "rsz_kernel_time": rsz.rsz_kernel_time}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rsz.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in (cls._fields_ if cls is not None else []):
+            lines.append(f'  printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append('  return 0;\n}')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                           str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for name, cls in structs.items():
+        if cls is None:
+            assert got[(name, "size")] == 12
+            continue
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert got[(name, fname)] == getattr(cls, fname).offset, (name, fname)

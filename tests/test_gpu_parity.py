@@ -254,11 +254,13 @@ def test_batch_prepare_launch_and_graph_replays(torch):
             np.testing.assert_array_equal(B.stream(i).cpu().numpy(), ref)
 
 
-def test_tile_rows_never_change_bytes(torch):
+@pytest.mark.parametrize("ts", [0, 1, 2, 3, 4, 9])
+def test_tile_shape_never_changes_bytes(torch, ts):
     frame, peaks = synth.cspad_frame(10)
     ref = None
     for tr in (0, 1, 3, 8, 17, 32, 100):
-        B = rsz.Batch([_gpu(torch, frame)], [_gpu(torch, peaks)], (17, 2, 10.0, 0), tile_rows=tr)
+        B = rsz.Batch([_gpu(torch, frame)], [_gpu(torch, peaks)], (17, 2, 10.0, 0), tile_rows=tr,
+                      tile_strips=ts)
         B.run()
         torch.cuda.synchronize()
         got = B.stream(0).cpu().numpy()
