@@ -105,6 +105,49 @@ def serving_section(args, torch, dev):
     return out
 
 
+def decompress_section(args, torch, dev, B, sizes, host):
+    """Decompression of the first frames' streams, one frame per call
+    (rsz_decompress: header read, kernels, status read): per-frame latency,
+    reconstructed GB/s and per-kernel times; the first frames' outputs are
+    compared with the oracle's reconstruction bit for bit."""
+    import numpy as np
+    from oracle import rsz_oracle as O
+    from paper_2206_11297_amd import rsz
+    n = min(args.decompress_frames, len(sizes))
+    streams = [B.stream(i, sizes).clone() for i in range(n)]
+    head = streams[0][:80].cpu().numpy().tobytes()
+    st, wsb = rsz.rsz_decompress_workspace_bytes(head)
+    ws = rsz.workspace(wsb * 2, dev)
+    out = torch.empty(SHAPE, dtype=torch.float32, device=dev)
+    s = rsz._stream()
+    for i in range(min(3, n)):   # warm-up
+        rsz.rsz_decompress(rsz._ptr(streams[i]), streams[i].numel(), rsz._ptr(out), out.numel(),
+                           rsz._ptr(ws), ws.numel(), s)
+    torch.cuda.synchronize()
+    rsz.rsz_profile_enable(True)
+    lat = []
+    for i in range(n):
+        a = time.perf_counter()
+        st = rsz.rsz_decompress(rsz._ptr(streams[i]), streams[i].numel(), rsz._ptr(out),
+                                out.numel(), rsz._ptr(ws), ws.numel(), s)
+        lat.append(time.perf_counter() - a)
+        assert st == 0, f"decompress frame {i}: status {st}"
+        if i < 4:
+            ok, ref = O.decompress(streams[i].cpu().numpy())
+            assert ok == O.OK and np.array_equal(out.cpu().numpy().view(np.uint32),
+                                                 ref.view(np.uint32)), f"frame {i} differs"
+    prof = rsz.rsz_profile_read()
+    rsz.rsz_profile_enable(False)
+    lat_ms = np.array(lat) * 1e3
+    fb = SHAPE[0] * SHAPE[1] * SHAPE[2] * 4
+    return {"frames": n, "mode": "one frame per call (synchronous)",
+            "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
+            "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+            "gbps": round(n * fb / (lat_ms.sum() / 1e3) / 1e9, 2),
+            "kernel_ms_per_frame": {k: round(v[1] / v[0], 4) for k, v in prof.items()},
+            "equal_oracle_first": min(4, n)}
+
+
 def cpu_baseline(args, host, B, sizes):
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
@@ -246,6 +289,8 @@ def main():
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--decompress-frames", type=int, default=200,
+                    help="frames decompressed one per call for the decompression figures")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[1.0, 2.0, 5.0, 10.0],
                     help="Poisson arrival rates in kHz for the serving section ([] skips it)")
     ap.add_argument("--serve-frames", type=int, default=10000)
@@ -354,6 +399,7 @@ def main():
     # for byte
     cpu = cpu_baseline(args, host, B, sizes)
 
+    decomp = decompress_section(args, torch, dev, B, sizes, host) if args.decompress_frames else None
     serving = serving_section(args, torch, dev) if args.serve_rates else None
 
     line = {
@@ -383,6 +429,7 @@ def main():
                        "batched_all_frames": round(ms_step, 4)},
         "kernel_ms": {k: round(v, 4) for k, v in kernel_ms.items()},
         "serving": serving,
+        "decompress": decomp,
     }
     if serving:
         top = serving.get(f"{max(args.serve_rates):g}kHz")

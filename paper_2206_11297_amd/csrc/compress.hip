@@ -1182,24 +1182,34 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
 
 // ------------------------------------------------------------------ k_roi
 
+// ROI payload (Sec. IV-A: each peak's w x w window as a buffer, a constant
+// fill outside the panel): one wave per peak, kRoiPeaksPerWave peaks per
+// wave, flat over the window's w*w pixels.  Window row u = e / w from a
+// multiply-high by floor((2^32 - 1) / w) + 1, exact for e < w^2 since
+// w^3 < 2^32.
+constexpr uint32_t kRoiPeaksPerWave = 4;
 __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
-  const uint32_t kg = blockIdx.x;
-  const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
-  const FramePlan &fp = bp.frames[f];
-  if (load_status(fp.st) != RSZ_OK) return;
-  const uint32_t k = kg - bp.peak_prefix[f];
-  const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
-  if (pa < 0 || pa >= fp.P) return;
-  const int64_t h = fp.w / 2;
-  const uint32_t ww = fp.w * fp.w;
-  uint32_t *dst = (uint32_t *)(fp.out + fp.off_roi) + (size_t)k * ww;
-  const float *src = fp.frame + (size_t)pa * fp.H * fp.W;
-  for (uint32_t e = threadIdx.x; e < ww; e += 256) {
-    const uint32_t u = e / fp.w, v = e - u * fp.w;
-    const int64_t i = r - h + u, j = c - h + v;
-    uint32_t bits = 0u;
-    if (i >= 0 && i < fp.H && j >= 0 && j < fp.W) bits = __float_as_uint(src[i * fp.W + j]);
-    dst[e] = bits;
+  const int lane = threadIdx.x & 63;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t first = (blockIdx.x * kWaves + wv) * kRoiPeaksPerWave;
+  for (uint32_t kg = first; kg < first + kRoiPeaksPerWave && kg < bp.total_peaks; ++kg) {
+    const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
+    const FramePlan &fp = bp.frames[f];
+    if (load_status(fp.st) != RSZ_OK) continue;
+    const uint32_t k = kg - bp.peak_prefix[f];
+    const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
+    if (pa < 0 || pa >= fp.P) continue;
+    const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+    const int64_t h = w / 2;
+    uint32_t *dst = (uint32_t *)(fp.out + fp.off_roi) + (size_t)k * ww;
+    const float *src = fp.frame + (size_t)pa * fp.H * fp.W;
+    for (uint32_t e = lane; e < ww; e += 64) {
+      const uint32_t u = __umulhi(e, M), v = e - u * w;
+      const int64_t i = r - h + u, j = c - h + v;
+      uint32_t bits = 0u;
+      if (i >= 0 && i < fp.H && j >= 0 && j < fp.W) bits = __float_as_uint(src[i * fp.W + j]);
+      dst[e] = bits;
+    }
   }
 }
 
@@ -1264,7 +1274,10 @@ hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
     else RSZ_LAUNCH("k_encode", k_encode, bp.total_units, s, bp);
   }
   RSZ_LAUNCH("k_tail", k_tail, bp.nframes, s, bp);
-  if (bp.total_peaks) RSZ_LAUNCH("k_roi", k_roi, bp.total_peaks, s, bp);
+  if (bp.total_peaks) {
+    const uint32_t per_wg = kWaves * kRoiPeaksPerWave;
+    RSZ_LAUNCH("k_roi", k_roi, (bp.total_peaks + per_wg - 1) / per_wg, s, bp);
+  }
   return hipSuccess;
 }
 

@@ -2,8 +2,10 @@
 //
 //   k_dec_tables    one workgroup: check code lengths (<= 32, complete prefix
 //                   code), peaks and chunk offsets; build canonical decode
-//                   tables (11-bit lookup table + per-length first codes).
-//   k_dec_chunks    one lane per 4096-symbol chunk: Huffman decode to
+//                   tables (11-bit single- and multi-symbol lookup tables +
+//                   per-length first codes).
+//   k_dec_chunks    one wave per 4096-symbol chunk, lanes on slices of its
+//                   bits (self-synchronising starts): Huffman decode to
 //                   residuals; each chunk must end exactly at the next offset.
 //   k_dec_outliers  scatter outlier residuals onto the code-0 positions.
 //   k_dec_rows      inclusive prefix sum along each bin row (wrapping int32).
@@ -21,11 +23,13 @@ namespace rsz {
 constexpr int kLutBits = 11;
 constexpr int32_t kMark = INT32_MIN;  // residual slot waiting for its outlier
 
-// tables: [0,2048) lut (sym | len << 16, 0 = slow path), then first[33],
-// count[33], offs[33], sorted[1024]
+// tables: [0,2048) lut (sym | len << 16, 0 = longer code), then first[33],
+// count[33], offs[33], sorted[1024], then the multi-symbol table: per 11-bit
+// window two words, (up to 3 whole codewords' symbols, 10 bits each) | count
+// << 30 and the bit position after each of them (4 bits each)
 constexpr int kTabLut = 0, kTabFirst = 1 << kLutBits, kTabCount = kTabFirst + 33,
               kTabOffs = kTabCount + 33, kTabSorted = kTabOffs + 33,
-              kTabWords = kTabSorted + kNumSym;
+              kTabMulti = kTabSorted + kNumSym, kTabWords = kTabMulti + 2 * (1 << kLutBits);
 
 __device__ __forceinline__ void corrupt(int32_t *status) {
   atomicCAS(status, (int32_t)RSZ_OK, (int32_t)RSZ_ERR_CORRUPT);
@@ -41,7 +45,10 @@ __device__ __forceinline__ uint32_t rd32(const uint8_t *p, uint64_t off) {
 
 __global__ __launch_bounds__(256) void k_dec_tables(DecodePlan dp) {
   __shared__ uint8_t s_len[kNumSym];
-  __shared__ uint32_t s_count[kMaxLen + 1];
+  __shared__ uint32_t s_count[kMaxLen + 1], s_first[kMaxLen + 1], s_offs[kMaxLen + 1],
+      s_fill[kMaxLen + 1];
+  __shared__ uint16_t s_sorted[kNumSym];
+  __shared__ uint32_t s_lut[1 << kLutBits];
   __shared__ unsigned long long s_kraft;
   __shared__ int s_used, s_bad;
   if (threadIdx.x == 0) {
@@ -50,7 +57,11 @@ __global__ __launch_bounds__(256) void k_dec_tables(DecodePlan dp) {
     s_bad = 0;
     *dp.status = RSZ_OK;
   }
-  if (threadIdx.x <= kMaxLen) s_count[threadIdx.x] = 0;
+  if (threadIdx.x <= kMaxLen) {
+    s_count[threadIdx.x] = 0;
+    s_fill[threadIdx.x] = 0;
+  }
+  for (int i = threadIdx.x; i < kNumSym; i += 256) s_sorted[i] = 0;
   __syncthreads();
   for (int s = threadIdx.x; s < kNumSym; s += 256) {
     const uint32_t L = dp.in[dp.off_lens + s];
@@ -86,76 +97,165 @@ __global__ __launch_bounds__(256) void k_dec_tables(DecodePlan dp) {
     uint32_t start = 0, prev = 0;
     for (int L = 1; L <= kMaxLen; ++L) {
       code = (code + prev) << 1;
-      tab[kTabFirst + L] = (uint32_t)code;
-      tab[kTabCount + L] = s_count[L];
-      tab[kTabOffs + L] = start;
+      s_first[L] = (uint32_t)code;
+      s_offs[L] = start;
       start += s_count[L];
       prev = s_count[L];
     }
-    // symbols in (length, symbol) order
-    uint32_t fill[kMaxLen + 1];
-    for (int L = 0; L <= kMaxLen; ++L) fill[L] = 0;
-    for (int s = 0; s < kNumSym; ++s) {
-      const uint32_t L = s_len[s];
-      if (L) tab[kTabSorted + tab[kTabOffs + L] + fill[L]++] = (uint32_t)s;
+  }
+  __syncthreads();
+  if (threadIdx.x <= kMaxLen && threadIdx.x > 0) {
+    tab[kTabFirst + threadIdx.x] = s_first[threadIdx.x];
+    tab[kTabCount + threadIdx.x] = s_count[threadIdx.x];
+    tab[kTabOffs + threadIdx.x] = s_offs[threadIdx.x];
+  }
+  // symbols in (length, symbol) order: wave 0 walks the symbols 64 at a
+  // time; a symbol's rank among its length is the count of earlier ones
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    for (int i = 0; i < kNumSym / 64; ++i) {
+      const uint32_t sym = i * 64 + lane, L = s_len[sym];
+      uint64_t pending = __builtin_amdgcn_uicmp(L, 0u, 33 /* ne */);
+      while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const uint32_t Lc = __builtin_amdgcn_readlane(L, leader);
+        const uint64_t same = __builtin_amdgcn_uicmp(L, Lc, 32 /* eq */) & pending;
+        if ((same >> lane) & 1ull)
+          s_sorted[s_offs[Lc] + s_fill[Lc] + __builtin_popcountll(same & ((1ull << lane) - 1))] =
+              (uint16_t)sym;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane == leader) s_fill[Lc] += (uint32_t)__builtin_popcountll(same);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        pending &= ~same;
+      }
     }
   }
-  for (int i = threadIdx.x; i < (1 << kLutBits); i += 256) tab[kTabLut + i] = 0u;
   __syncthreads();
-  // lookup entries for codewords of at most kLutBits bits
-  for (int s = threadIdx.x; s < kNumSym; s += 256) {
-    const uint32_t L = s_len[s];
-    if (!L || L > (uint32_t)kLutBits) continue;
-    // rank of s among the symbols of length L
-    uint32_t rank = 0;
-    for (int t = 0; t < s; ++t) rank += s_len[t] == L;
-    const uint32_t code = tab[kTabFirst + L] + rank;
-    const uint32_t lo = code << (kLutBits - L), n = 1u << (kLutBits - L);
-    for (uint32_t e = 0; e < n; ++e) tab[kTabLut + lo + e] = (uint32_t)s | (L << 16);
+  for (int i = threadIdx.x; i < kNumSym; i += 256) tab[kTabSorted + i] = s_sorted[i];
+  // lookup entry of an 11-bit window: the codeword (at most 11 bits) that is
+  // its prefix, if any (the code is prefix-free: at most one)
+  for (uint32_t x = threadIdx.x; x < (1u << kLutBits); x += 256) {
+    uint32_t e = 0;
+    for (uint32_t L = 1; L <= (uint32_t)kLutBits; ++L) {
+      const uint32_t n = s_count[L];
+      const uint32_t cd = x >> (kLutBits - L);
+      if (n && cd - s_first[L] < n) {
+        e = (uint32_t)s_sorted[s_offs[L] + cd - s_first[L]] | (L << 16);
+        break;
+      }
+    }
+    s_lut[x] = e;
+    tab[kTabLut + x] = e;
+  }
+  __syncthreads();
+  // multi-symbol entry: the whole codewords (at most 3) that the window
+  // holds one after the other
+  for (uint32_t x = threadIdx.x; x < (1u << kLutBits); x += 256) {
+    uint32_t syms = 0, n = 0, pos = 0, ends = 0;
+    while (n < 3) {
+      const uint32_t e = s_lut[(x << pos) & ((1u << kLutBits) - 1)];
+      const uint32_t L = e >> 16;
+      if (!e || pos + L > (uint32_t)kLutBits) break;
+      syms |= (e & 0x3FFu) << (10 * n);
+      pos += L;
+      ends |= pos << (4 * n);
+      ++n;
+    }
+    tab[kTabMulti + 2 * x] = syms | n << 30;
+    tab[kTabMulti + 2 * x + 1] = ends;
   }
 }
 
-// Peek 32 stream bits starting at bit `pos`; bits past the stream read 0.
-__device__ __forceinline__ uint32_t peek32(const uint32_t *bw, uint64_t nwords, uint64_t pos) {
-  const uint64_t w = pos >> 5;
-  const uint64_t a = w < nwords ? bw[w] : 0u;
-  const uint64_t b = w + 1 < nwords ? bw[w + 1] : 0u;
-  return (uint32_t)((((a << 32) | b) << (pos & 31)) >> 32);
+// Four stream words from word index w (0 past the stream's end).
+__device__ __forceinline__ uint4 ld4(const uint32_t *bw, uint64_t nwords, uint64_t w) {
+  uint4 r;
+  r.x = w < nwords ? bw[w] : 0u;
+  r.y = w + 1 < nwords ? bw[w + 1] : 0u;
+  r.z = w + 2 < nwords ? bw[w + 2] : 0u;
+  r.w = w + 3 < nwords ? bw[w + 3] : 0u;
+  return r;
 }
 
-__global__ __launch_bounds__(64) void k_dec_chunks(DecodePlan dp) {
-  __shared__ uint32_t s_lut[1 << kLutBits];
-  __shared__ uint32_t s_first[kMaxLen + 1], s_count[kMaxLen + 1], s_offs[kMaxLen + 1];
-  __shared__ uint16_t s_sorted[kNumSym];
-  for (int i = threadIdx.x; i < (1 << kLutBits); i += 64) s_lut[i] = dp.tables[kTabLut + i];
-  for (int i = threadIdx.x; i < kNumSym; i += 64) s_sorted[i] = (uint16_t)dp.tables[kTabSorted + i];
-  if (threadIdx.x <= kMaxLen) {
-    s_first[threadIdx.x] = dp.tables[kTabFirst + threadIdx.x];
-    s_count[threadIdx.x] = dp.tables[kTabCount + threadIdx.x];
-    s_offs[threadIdx.x] = dp.tables[kTabOffs + threadIdx.x];
+// Exclusive prefix sum of v over the lanes of a wave; total of all lanes.
+__device__ __forceinline__ uint64_t wave_exclusive_scan_u64(uint64_t v, uint64_t &total) {
+  const int lane = threadIdx.x & 63;
+  uint64_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
   }
-  __syncthreads();
-  const uint32_t c = blockIdx.x * 64 + threadIdx.x;
-  if (c >= dp.nchunks || !dec_ok(dp.status)) return;
-  const uint32_t *co = (const uint32_t *)(dp.in + dp.off_chunks);
-  const uint32_t *bw = (const uint32_t *)(dp.in + dp.off_bits);
-  const uint64_t nwords = (dp.T + 31) / 32;
-  uint64_t pos = co[c];
-  const uint64_t end = c + 1 < dp.nchunks ? co[c + 1] : dp.T;
-  const uint32_t g0 = c * kChunk;
-  const uint32_t nsym = min(kChunk, dp.nbins - g0);
-  uint32_t zeros = 0;
-  bool bad = false;
-  for (uint32_t k = 0; k < nsym; ++k) {
-    const uint32_t v = peek32(bw, nwords, pos);
-    const uint32_t e = s_lut[v >> (32 - kLutBits)];
-    uint32_t sym, L;
-    if (e) {
-      sym = e & 0xFFFFu;
-      L = e >> 16;
+  total = __shfl(x, 63);
+  return x - v;
+}
+
+__device__ __forceinline__ uint32_t pick8(const uint4 &a, const uint4 &b, uint32_t i) {
+  const uint32_t lo = (i & 3) == 0 ? a.x : (i & 3) == 1 ? a.y : (i & 3) == 2 ? a.z : a.w;
+  const uint32_t hi = (i & 3) == 0 ? b.x : (i & 3) == 1 ? b.y : (i & 3) == 2 ? b.z : b.w;
+  return i < 4 ? lo : hi;
+}
+
+// Decoder state of one lane: its stream bits come through a window of three
+// 4-word blocks (the third loading while the first two are decoded).
+struct BitWindow {
+  const uint32_t *bw;
+  uint64_t nwords, wb;   // wb: word index of block A
+  uint4 A, B, C;
+  __device__ void init(const uint32_t *words, uint64_t n, uint64_t pos) {
+    bw = words;
+    nwords = n;
+    wb = pos >> 5;
+    A = ld4(bw, nwords, wb);
+    B = ld4(bw, nwords, wb + 4);
+    C = ld4(bw, nwords, wb + 8);
+  }
+  // the 32 stream bits from bit `pos` (pos never moves back)
+  __device__ uint32_t peek(uint64_t pos) {
+    uint32_t r = (uint32_t)((pos >> 5) - wb);
+    while (r >= 4) {
+      A = B;
+      B = C;
+      wb += 4;
+      C = ld4(bw, nwords, wb + 8);
+      r -= 4;
+    }
+    const uint64_t two = ((uint64_t)pick8(A, B, r) << 32) | pick8(A, B, r + 1);
+    return (uint32_t)((two << (pos & 31)) >> 32);
+  }
+};
+
+// Decodes codewords from `pos` while pos < lim: returns the count and leaves
+// pos at the first boundary >= lim; with `out`, writes each residual (kMark
+// for code 0) at out[k] for k < cap.  `inval` reports a bit pattern that is
+// no codeword.
+template <bool WRITE>
+__device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, uint64_t lim,
+                                               const uint2 *s_multi, const uint32_t *s_first,
+                                               const uint32_t *s_count, const uint32_t *s_offs,
+                                               const uint16_t *s_sorted, int32_t *out,
+                                               uint32_t cap, uint32_t &zeros, bool &inval) {
+  uint32_t m = 0;
+  while (pos < lim) {
+    const uint32_t v = win.peek(pos);
+    const uint2 e = s_multi[v >> (32 - kLutBits)];
+    const uint32_t n = e.x >> 30;
+    if (n) {
+      // up to n symbols, stopping after the first that reaches lim
+      uint32_t take = 1;
+      while (take < n && pos + ((e.y >> (4 * (take - 1))) & 0xFu) < lim) ++take;
+      for (uint32_t j = 0; j < take; ++j) {
+        const uint32_t sym = (e.x >> (10 * j)) & 0x3FFu;
+        zeros += sym == 0;
+        if (WRITE && m + j < cap) out[m + j] = sym ? (int32_t)sym - kRadius : kMark;
+      }
+      pos += (e.y >> (4 * (take - 1))) & 0xFu;
+      m += take;
     } else {
-      L = 0;
-      sym = 0;
+      uint32_t L = 0, sym = 0;
       for (uint32_t l = kLutBits + 1; l <= (uint32_t)kMaxLen; ++l) {
         const uint32_t cd = v >> (32 - l);
         if (s_count[l] && cd >= s_first[l] && cd - s_first[l] < s_count[l]) {
@@ -165,20 +265,94 @@ __global__ __launch_bounds__(64) void k_dec_chunks(DecodePlan dp) {
         }
       }
       if (L == 0) {
-        bad = true;
+        inval = true;
         break;
       }
+      zeros += sym == 0;
+      if (WRITE && m < cap) out[m] = sym ? (int32_t)sym - kRadius : kMark;
+      pos += L;
+      ++m;
     }
-    if (pos + L > end) {
-      bad = true;
-      break;
-    }
-    pos += L;
-    dp.res[g0 + k] = sym ? (int32_t)sym - kRadius : kMark;
-    zeros += sym == 0;
   }
-  if (bad || pos != end) corrupt(dp.status);
-  dp.zcount[c] = zeros;
+  return m;
+}
+
+// One wave per chunk.  The chunk's bits split into 64 equal slices; lane i
+// decodes from a start s_i until the first codeword boundary at or past the
+// next slice.  Lane 0 starts at the chunk offset, a true boundary; every
+// other lane starts at its slice's first bit, then again at the boundary the
+// lane before it stopped at, until no start changes: then every start is a
+// true boundary (by induction from lane 0).  Huffman decoding
+// resynchronises within a few codewords, so this takes one or two rounds
+// (64 at most).  A scan of the lanes' symbol counts places their outputs, and
+// a last pass writes them.  A valid chunk decodes to exactly its symbol count
+// and ends exactly at the next chunk offset.
+__global__ __launch_bounds__(256) void k_dec_chunks(DecodePlan dp) {
+  __shared__ uint2 s_multi[1 << kLutBits];
+  __shared__ uint32_t s_first[kMaxLen + 1], s_count[kMaxLen + 1], s_offs[kMaxLen + 1];
+  __shared__ uint16_t s_sorted[kNumSym];
+  for (int i = threadIdx.x; i < (1 << kLutBits); i += 256)
+    s_multi[i] = make_uint2(dp.tables[kTabMulti + 2 * i], dp.tables[kTabMulti + 2 * i + 1]);
+  for (int i = threadIdx.x; i < kNumSym; i += 256) s_sorted[i] = (uint16_t)dp.tables[kTabSorted + i];
+  if (threadIdx.x <= kMaxLen) {
+    s_first[threadIdx.x] = dp.tables[kTabFirst + threadIdx.x];
+    s_count[threadIdx.x] = dp.tables[kTabCount + threadIdx.x];
+    s_offs[threadIdx.x] = dp.tables[kTabOffs + threadIdx.x];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint32_t c = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (c >= dp.nchunks || !dec_ok(dp.status)) return;
+  const uint32_t *co = (const uint32_t *)(dp.in + dp.off_chunks);
+  const uint32_t *bw = (const uint32_t *)(dp.in + dp.off_bits);
+  const uint64_t nwords = (dp.T + 31) / 32;
+  const uint64_t S = co[c], E = c + 1 < dp.nchunks ? co[c + 1] : dp.T;
+  const uint32_t g0 = c * kChunk;
+  const uint32_t nsym = min(kChunk, dp.nbins - g0);
+  const uint64_t len = E > S ? E - S : 0;
+  const uint64_t lim = lane == 63 ? E : S + len * (uint64_t)(lane + 1) / 64;
+  uint64_t start = lane == 0 ? S : S + len * (uint64_t)lane / 64;
+  uint64_t stop = start;
+  uint32_t m = 0;
+  bool converged = false, inv = false;
+  for (int round = 0; round <= 64 && !converged; ++round) {
+    BitWindow win;
+    win.init(bw, nwords, start);
+    uint64_t pos = start;
+    uint32_t z = 0;
+    inv = false;
+    m = decode_run<false>(win, pos, lim, s_multi, s_first, s_count, s_offs, s_sorted, nullptr, 0,
+                          z, inv);
+    stop = inv ? ~0ull : pos;   // a lane stuck on a non-codeword hands on no boundary
+    // the boundary the lane before stopped at is this lane's next start
+    const uint64_t prev = __shfl_up(stop, 1);
+    const uint64_t next = lane == 0 ? S : prev;
+    const bool changed = lane > 0 && next != start;
+    converged = __builtin_amdgcn_uicmp((uint32_t)changed, 0u, 33 /* ne */) == 0;
+    if (!converged) start = next == ~0ull ? lim : next;
+  }
+  uint64_t tot;
+  const uint32_t off = (uint32_t)wave_exclusive_scan_u64(m, tot);
+  const uint64_t last = __shfl(stop, 63);
+  // a valid chunk converges (64 rounds at most) with no non-codeword on its path
+  bool bad = !converged || __builtin_amdgcn_uicmp((uint32_t)inv, 0u, 33 /* ne */) != 0 ||
+             tot != nsym || last != E;
+  inv = false;
+  // the output pass, from the true starts
+  BitWindow win;
+  win.init(bw, nwords, start);
+  uint64_t pos = start;
+  uint32_t zeros = 0;
+  if (!bad)
+    decode_run<true>(win, pos, lim, s_multi, s_first, s_count, s_offs, s_sorted, dp.res + g0 + off,
+                     off < nsym ? nsym - off : 0u, zeros, inv);
+  bad |= __builtin_amdgcn_uicmp((uint32_t)inv, 0u, 33 /* ne */) != 0;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) zeros += __shfl_xor(zeros, d);
+  if (lane == 0) {
+    if (bad) corrupt(dp.status);
+    dp.zcount[c] = zeros;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_dec_outliers(DecodePlan dp) {
@@ -301,7 +475,7 @@ __global__ __launch_bounds__(256) void k_dec_roi_check(DecodePlan dp) {
 
 hipError_t launch_decompress(const DecodePlan &dp, hipStream_t s) {
   RSZ_DLAUNCH("k_dec_tables", k_dec_tables, 1, 256, s);
-  RSZ_DLAUNCH("k_dec_chunks", k_dec_chunks, (dp.nchunks + 63) / 64, 64, s);
+  RSZ_DLAUNCH("k_dec_chunks", k_dec_chunks, (dp.nchunks + 3) / 4, 256, s);
   if (dp.n_out) RSZ_DLAUNCH("k_dec_outliers", k_dec_outliers, (dp.n_out + 255) / 256, 256, s);
   RSZ_DLAUNCH("k_dec_rows", k_dec_rows, (dp.P * dp.Hb + 3) / 4, 256, s);
   RSZ_DLAUNCH("k_dec_cols", k_dec_cols, (dp.P * dp.Wb + 255) / 256, 256, s);
