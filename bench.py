@@ -287,6 +287,8 @@ def main():
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_DIR"),
                     help="summarize two rocprofv3 --pmc runs (CSV output) and exit")
     ap.add_argument("--latency-frames", type=int, default=200)
+    ap.add_argument("--read-reference", type=int, default=1,
+                    help="time a plain 4 GiB streaming reduction as the measured read reference")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--decompress-frames", type=int, default=200,
@@ -337,6 +339,21 @@ def main():
     raw_bytes = sum(f.numel() * 4 for f in frames)
     npix = raw_bytes // 4
 
+    read_ref = None
+    if args.read_reference:
+        # a plain streaming read on this machine: a reduction over 4 GiB resident
+        # in HBM (the reference the kernel's read rate is compared with)
+        x = torch.empty(1 << 30, dtype=torch.float32, device=dev).fill_(1.0)
+        torch.cuda.synchronize()
+        x.sum()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(10):
+            x.sum()
+        torch.cuda.synchronize()
+        read_ref = 10 * x.numel() * 4 / (time.perf_counter() - a) / 1e9
+        del x
+
     if args.copy_calibration:
         # plain copy of a known size: 1 GiB read + 1 GiB written
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -372,6 +389,8 @@ def main():
     tr = traffic_record("k_bin")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
             "frac": round(achieved / 8000.0, 4),
+            "measured_read_reference_gbps": None if read_ref is None else round(read_ref, 1),
+            "frac_of_measured_read": None if read_ref is None else round(achieved / read_ref, 4),
             "traffic": None if tr is None else tr["hbm_bytes_per_launch"],
             "kernel": "k_bin", "algorithmic_bytes_per_launch": raw_bytes,
             "avg_launch_ms": round(kb_ms, 4)}
