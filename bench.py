@@ -288,7 +288,7 @@ def main():
                     help="summarize two rocprofv3 --pmc runs (CSV output) and exit")
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--read-reference", type=int, default=1,
-                    help="time a plain 4 GiB streaming reduction as the measured read reference")
+                    help="time a plain 4 GiB streaming read as the measured read reference")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--decompress-frames", type=int, default=200,
@@ -341,18 +341,10 @@ def main():
 
     read_ref = None
     if args.read_reference:
-        # a plain streaming read on this machine: a reduction over 4 GiB resident
-        # in HBM (the reference the kernel's read rate is compared with)
-        x = torch.empty(1 << 30, dtype=torch.float32, device=dev).fill_(1.0)
-        torch.cuda.synchronize()
-        x.sum()
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        for _ in range(10):
-            x.sum()
-        torch.cuda.synchronize()
-        read_ref = 10 * x.numel() * 4 / (time.perf_counter() - a) / 1e9
-        del x
+        # a plain streaming read of 4 GiB resident in HBM on this machine (the
+        # reference the kernel's read rate is compared with)
+        read_ref = rsz.measure_read(1 << 32, reps=10)
+        torch.cuda.empty_cache()
 
     if args.copy_calibration:
         # plain copy of a known size: 1 GiB read + 1 GiB written

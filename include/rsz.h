@@ -210,6 +210,16 @@ int rsz_debug_intermediates(const rsz_params *p, const float *d_frame, const rsz
 int rsz_debug_codebook(const uint32_t *h_hist, uint8_t *h_lens, uint32_t *h_cw, void *d_ws,
                        uint64_t ws_bytes, void *stream);
 
+/* Measurement helper: the rate of a plain streaming read of d_buf on this
+ * GPU, the measured reference that the binning kernel's read rate is compared
+ * with beside the HBM peak.  d_buf: `bytes` of device memory, 16-byte
+ * aligned (bytes / 16 16-byte loads per pass); d_sink: device scratch of at
+ * least 4 KiB (normally left untouched); reps passes are timed with HIP events
+ * after one untimed pass; *h_gbps receives 10^9 bytes per second.
+ * Synchronous with respect to `stream`. */
+int rsz_measure_read(const void *d_buf, uint64_t bytes, void *d_sink, int reps, double *h_gbps,
+                     void *stream);
+
 /* Kernel timing with HIP events recorded around every launch, on the stream
  * the kernel runs on.  rsz_profile_enable(1) clears and starts recording;
  * rsz_profile_read waits for the recorded events and returns, per kernel

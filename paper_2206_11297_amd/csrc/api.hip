@@ -725,6 +725,50 @@ int rsz_debug_codebook(const uint32_t *h_hist, uint8_t *h_lens, uint32_t *h_cw, 
   return RSZ_OK;
 }
 
+// Plain streaming read: grid-stride 16-byte loads, folded so the loads stay.
+__global__ __launch_bounds__(256) void k_measure_read(const uint4 *x, uint64_t n16,
+                                                      uint32_t *sink) {
+  uint32_t acc = 0;
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * 256) {
+    const uint4 v = x[i];
+    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  }
+  if (acc == 0x9E3779B9u) sink[blockIdx.x & 1023] = acc;
+}
+
+int rsz_measure_read(const void *d_buf, uint64_t bytes, void *d_sink, int reps, double *h_gbps,
+                     void *stream) {
+  if (!d_buf || !d_sink || !h_gbps || reps < 1 || bytes < 16 || (uintptr_t)d_buf % 16 ||
+      (uintptr_t)d_sink % 4)
+    return RSZ_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t n16 = bytes / 16;
+  const uint32_t grid = 8192;
+  hipEvent_t a, e;
+  if (hipEventCreate(&a) != hipSuccess) return RSZ_ERR_HIP;
+  if (hipEventCreate(&e) != hipSuccess) {
+    hipEventDestroy(a);
+    return RSZ_ERR_HIP;
+  }
+  int st = RSZ_OK;
+  hipLaunchKernelGGL(k_measure_read, dim3(grid), dim3(256), 0, s, (const uint4 *)d_buf, n16,
+                     (uint32_t *)d_sink);
+  hipEventRecord(a, s);
+  for (int r = 0; r < reps; ++r)
+    hipLaunchKernelGGL(k_measure_read, dim3(grid), dim3(256), 0, s, (const uint4 *)d_buf, n16,
+                       (uint32_t *)d_sink);
+  hipEventRecord(e, s);
+  float ms = 0.f;
+  if (hipGetLastError() != hipSuccess || hipEventSynchronize(e) != hipSuccess ||
+      hipEventElapsedTime(&ms, a, e) != hipSuccess || ms <= 0.f)
+    st = RSZ_ERR_HIP;
+  else
+    *h_gbps = (double)reps * (double)(n16 * 16) / ((double)ms * 1e6);
+  hipEventDestroy(a);
+  hipEventDestroy(e);
+  return st;
+}
+
 int rsz_profile_enable(int enable) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   for (auto &r : g_prof) {

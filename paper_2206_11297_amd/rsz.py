@@ -20,8 +20,8 @@ EXPORTS = ["rsz_status_string", "rsz_max_compressed_bytes", "rsz_workspace_bytes
            "rsz_batch_prepare", "rsz_batch_launch", "rsz_batch_graph_create",
            "rsz_graph_launch", "rsz_graph_destroy",
            "rsz_stream_info", "rsz_decompress_workspace_bytes", "rsz_decompress",
-           "rsz_debug_intermediates", "rsz_debug_codebook", "rsz_profile_enable",
-           "rsz_profile_read"]
+           "rsz_debug_intermediates", "rsz_debug_codebook", "rsz_measure_read",
+           "rsz_profile_enable", "rsz_profile_read"]
 
 
 class RszError(RuntimeError):
@@ -87,6 +87,7 @@ def lib():
         L.rsz_debug_intermediates.argtypes = [P(rsz_params), vp, vp, u32, P(rsz_debug_bufs), vp,
                                               u64, vp]
         L.rsz_debug_codebook.argtypes = [vp, vp, vp, vp, u64, vp]
+        L.rsz_measure_read.argtypes = [vp, u64, vp, C.c_int, P(C.c_double), vp]
         L.rsz_profile_enable.argtypes = [C.c_int]
         L.rsz_profile_read.argtypes = [P(rsz_kernel_time), C.c_int, P(C.c_int)]
         _lib = L
@@ -203,6 +204,19 @@ def debug_codebook(hist):
     if st:
         raise RszError(st, "rsz_debug_codebook")
     return lens, cw
+
+
+def measure_read(nbytes=1 << 32, reps=10):
+    """GB/s of a plain streaming read over nbytes of device memory."""
+    torch = _torch()
+    buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda").fill_(1)
+    sink = torch.zeros(1024, dtype=torch.int32, device="cuda")
+    out = C.c_double(0.0)
+    st = lib().rsz_measure_read(_ptr(buf), buf.numel(), _ptr(sink), int(reps), C.byref(out),
+                                _stream())
+    if st:
+        raise RszError(st, "rsz_measure_read")
+    return out.value
 
 
 def rsz_profile_enable(on):
