@@ -15,9 +15,12 @@
  *     Approach", and the footnote of Sec. VI).
  *   - The SZ stage is a black box in the paper (Sec. V-C names Lorenzo +
  *     regression + linear quantization).  Here it is the dual-quantisation
- *     recipe: prequantise to integers at step 2*eb, 2D Lorenzo on the integer
+ *     recipe: prequantise to integers at step 2*eb, Lorenzo on the integer
  *     field, outliers for residuals outside the radius, Huffman over 1024
- *     symbols.  Every constant the paper leaves open is a reading listed in the
+ *     symbols.  The Lorenzo predictor works in the dimension of Sec. VI's
+ *     grid search: 1 (the frame as one sequence of bins in raster order),
+ *     2 (each panel as an image; the default) or 3 (the stack of panels as
+ *     a volume).  Every constant the paper leaves open is a reading listed in the
  *     design notes (radius 512, chunk 4096, tie-breaks, container layout).
  *   - Compression ratio is relative to raw uint16 detector bytes (Sec. IV).
  *
@@ -55,7 +58,10 @@ typedef struct {
   uint32_t bin;                   /* bin factor b                          */
   uint32_t bin_mode;              /* 0 = background pixels only, 1 = all   */
   double eb;                      /* absolute bound on binned values       */
+  uint32_t dim;                   /* Lorenzo dimension 1, 2 or 3; 0 means 2 */
 } ro_params;
+
+static uint32_t ro_dim(const ro_params *p) { return p->dim ? p->dim : 2u; }
 
 /* ------------------------------------------------------------------ sizes */
 
@@ -65,7 +71,7 @@ static uint64_t ro_nbins(const ro_params *p) { return (uint64_t)p->panels * ro_h
 static uint64_t ro_align4(uint64_t x) { return (x + 3u) & ~(uint64_t)3u; }
 
 /* Argument validation.  Limits: each dimension 1..65535, window 1..1023,
- * bin 1..8, bin_mode 0/1, eb finite and > 0, pixels < 2^31, bins < 2^27,
+ * bin 1..8, bin_mode 0/1, dim 0..3, eb finite and > 0, pixels < 2^31, bins < 2^27,
  * npeaks * w * w <= 2^28 payload words. */
 int ro_check_params(const ro_params *p, uint32_t npeaks) {
   if (!p) return RO_ERR_ARG;
@@ -74,7 +80,7 @@ int ro_check_params(const ro_params *p, uint32_t npeaks) {
     return RO_ERR_ARG;
   if (p->window < 1 || p->window > 1023) return RO_ERR_ARG;
   if (p->bin < 1 || p->bin > 8) return RO_ERR_ARG;
-  if (p->bin_mode > 1) return RO_ERR_ARG;
+  if (p->bin_mode > 1 || p->dim > 3) return RO_ERR_ARG;
   if (!(p->eb > 0.0) || !isfinite(p->eb)) return RO_ERR_ARG;
   if ((uint64_t)p->panels * p->height * p->width >= (1ull << 31)) return RO_ERR_ARG;
   if (ro_nbins(p) >= (1ull << 27)) return RO_ERR_ARG;
@@ -195,19 +201,37 @@ int ro_prequant(const ro_params *p, const double *S, const uint32_t *n, int32_t 
   return status;
 }
 
-/* 2D Lorenzo predictor over each panel of the integer field (the SZ predictor
- * of Sec. V-C, dimension 2 of Sec. VI): r = q - q_up - q_left + q_upleft with
- * zeros outside the panel. */
+/* Lorenzo predictor on the integer field (the SZ predictor of Sec. V-C, in
+ * the dimension of Sec. VI).  The residual is q minus its prediction from the
+ * neighbours that precede it along each axis the predictor spans, with zeros
+ * outside the domain:
+ *   dim 1: the frame is one sequence of bins in raster order (panel, row,
+ *          column); r[g] = q[g] - q[g-1], and the first bin of a row follows
+ *          the last bin of the row before it, across panels too;
+ *   dim 2: each panel is an image; r = q - q_up - q_left + q_upleft;
+ *   dim 3: the panels form a volume; r is the signed sum over the eight
+ *          corners (p-a, I-c, J-e), a, c, e in {0,1}, of q with sign
+ *          (-1)^(a+c+e). */
 void ro_lorenzo(const ro_params *p, const int32_t *q, int32_t *r) {
-  const uint64_t Hb = ro_hb(p), Wb = ro_wb(p);
+  const uint64_t Hb = ro_hb(p), Wb = ro_wb(p), nb = ro_nbins(p);
+  const uint32_t dim = ro_dim(p);
+  if (dim == 1) {
+    for (uint64_t g = 0; g < nb; ++g)
+      r[g] = (int32_t)((int64_t)q[g] - (g > 0 ? (int64_t)q[g - 1] : 0));
+    return;
+  }
   for (uint64_t pa = 0; pa < p->panels; ++pa)
     for (uint64_t I = 0; I < Hb; ++I)
       for (uint64_t J = 0; J < Wb; ++J) {
-        const uint64_t g = (pa * Hb + I) * Wb + J;
-        const int64_t up = I > 0 ? q[g - Wb] : 0;
-        const int64_t left = J > 0 ? q[g - 1] : 0;
-        const int64_t ul = (I > 0 && J > 0) ? q[g - Wb - 1] : 0;
-        r[g] = (int32_t)((int64_t)q[g] - up - left + ul);
+        int64_t acc = 0;
+        for (int a = 0; a <= (dim == 3 ? 1 : 0); ++a)
+          for (int c = 0; c <= 1; ++c)
+            for (int e = 0; e <= 1; ++e) {
+              if ((uint64_t)a > pa || (uint64_t)c > I || (uint64_t)e > J) continue;
+              const int64_t v = q[((pa - a) * Hb + (I - c)) * Wb + (J - e)];
+              acc += ((a + c + e) & 1) ? -v : v;
+            }
+        r[(pa * Hb + I) * Wb + J] = (int32_t)acc;
       }
 }
 
@@ -481,7 +505,9 @@ int ro_compress(const ro_params *p, const float *frame, const int32_t *peaks, ui
       memset(out, 0, (size_t)L.total);
       memcpy(out, "RSZ1", 4);
       put16(out, 4, 1);
-      put16(out, 6, (uint16_t)(p->bin_mode & 1u));
+      /* flags: bit 0 bin_mode, bits 1-2 the Lorenzo dimension (0 for the
+       * default 2, else 1 or 3) */
+      put16(out, 6, (uint16_t)((p->bin_mode & 1u) | ((ro_dim(p) == 2 ? 0u : ro_dim(p)) << 1)));
       put32(out, 8, p->panels);
       put32(out, 12, p->height);
       put32(out, 16, p->width);
@@ -520,7 +546,10 @@ int ro_stream_info(const uint8_t *in, uint64_t in_bytes, ro_params *p, uint32_t 
   if (in_bytes < RO_HEADER || memcmp(in, "RSZ1", 4) != 0 || get16(in, 4) != 1)
     return RO_ERR_CORRUPT;
   ro_params q;
-  q.bin_mode = get16(in, 6);
+  const uint32_t flags = get16(in, 6), dcode = (flags >> 1) & 3u;
+  if ((flags >> 3) != 0 || dcode == 2) return RO_ERR_CORRUPT;
+  q.bin_mode = flags & 1u;
+  q.dim = dcode == 0 ? 2u : dcode;
   q.panels = get32(in, 8);
   q.height = get32(in, 12);
   q.width = get32(in, 16);
@@ -543,7 +572,7 @@ int ro_stream_info(const uint8_t *in, uint64_t in_bytes, ro_params *p, uint32_t 
 
 /* Decompress a stream into a panels x height x width float frame.
  * Structural validation first (any failure -> RO_ERR_CORRUPT); then
- * codes -> residuals -> q by 2D prefix sums -> bin value q*2eb replicated over
+ * codes -> residuals -> q by prefix sums -> bin value q*2eb replicated over
  * the bin -> ROI windows restored bit-exactly from the payload.  Overlapping
  * windows must carry identical bits for their shared pixels. */
 int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t frame_elems) {
@@ -627,6 +656,7 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
   }
   if (!bad && pos != T) bad = 1;
   /* outliers: strictly increasing indices at the code-0 positions, |r| >= 512 */
+  const int64_t rlim = (int64_t)1 << (28 + ro_dim(&p));
   if (!bad) {
     uint64_t k = 0;
     for (uint64_t g = 0; g < nb && !bad; ++g) {
@@ -637,8 +667,9 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
       if (k >= n_out) { bad = 1; break; }
       const uint32_t idx = get32(in, L.oidx + 4 * k);
       const int32_t rv = (int32_t)get32(in, L.ores + 4 * k);
-      /* |q| < 2^28 bounds every residual below 2^30 in magnitude */
-      if (idx != g || (rv > -RO_RADIUS && rv < RO_RADIUS) || rv <= -(1 << 30) || rv >= (1 << 30)) {
+      /* |q| < 2^28 bounds a residual of dimension d below 2^(28+d) */
+      if (idx != g || (rv > -RO_RADIUS && rv < RO_RADIUS) || (int64_t)rv <= -rlim ||
+          (int64_t)rv >= rlim) {
         bad = 1;
         break;
       }
@@ -651,20 +682,29 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
     free(pk); free(res); free(cd);
     return RO_ERR_CORRUPT;
   }
-  /* inverse Lorenzo: q is the 2D inclusive prefix sum of r over each panel
-   * (two's-complement wrap-around, as int32) */
+  /* inverse Lorenzo: q is the inclusive prefix sum of r along each axis the
+   * predictor spans -- the whole raster sequence (dim 1), the rows and
+   * columns of each panel (dim 2), and in addition the panel axis (dim 3) --
+   * with two's-complement wrap-around, as int32 */
   const uint64_t Hb = ro_hb(&p), Wb = ro_wb(&p), b = p.bin;
-  for (uint64_t pa = 0; pa < p.panels; ++pa) {
-    for (uint64_t I = 0; I < Hb; ++I)
-      for (uint64_t J = 1; J < Wb; ++J) {
-        const uint64_t g = (pa * Hb + I) * Wb + J;
-        res[g] = (int32_t)((uint32_t)res[g] + (uint32_t)res[g - 1]);
-      }
-    for (uint64_t I = 1; I < Hb; ++I)
-      for (uint64_t J = 0; J < Wb; ++J) {
-        const uint64_t g = (pa * Hb + I) * Wb + J;
-        res[g] = (int32_t)((uint32_t)res[g] + (uint32_t)res[g - Wb]);
-      }
+  if (ro_dim(&p) == 1) {
+    for (uint64_t g = 1; g < nb; ++g) res[g] = (int32_t)((uint32_t)res[g] + (uint32_t)res[g - 1]);
+  } else {
+    for (uint64_t pa = 0; pa < p.panels; ++pa) {
+      for (uint64_t I = 0; I < Hb; ++I)
+        for (uint64_t J = 1; J < Wb; ++J) {
+          const uint64_t g = (pa * Hb + I) * Wb + J;
+          res[g] = (int32_t)((uint32_t)res[g] + (uint32_t)res[g - 1]);
+        }
+      for (uint64_t I = 1; I < Hb; ++I)
+        for (uint64_t J = 0; J < Wb; ++J) {
+          const uint64_t g = (pa * Hb + I) * Wb + J;
+          res[g] = (int32_t)((uint32_t)res[g] + (uint32_t)res[g - Wb]);
+        }
+    }
+    if (ro_dim(&p) == 3)
+      for (uint64_t g = Hb * Wb; g < nb; ++g)
+        res[g] = (int32_t)((uint32_t)res[g] + (uint32_t)res[g - Hb * Wb]);
   }
   /* background: the bin value replicated over the bin */
   const double step = 2.0 * p.eb;

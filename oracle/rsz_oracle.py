@@ -18,7 +18,7 @@ CHUNK = 4096
 class Params(C.Structure):
     _fields_ = [("panels", C.c_uint32), ("height", C.c_uint32), ("width", C.c_uint32),
                 ("window", C.c_uint32), ("bin", C.c_uint32), ("bin_mode", C.c_uint32),
-                ("eb", C.c_double)]
+                ("eb", C.c_double), ("dim", C.c_uint32)]
 
 
 _lib = None
@@ -44,8 +44,8 @@ def lib():
     return _lib
 
 
-def params(panels, height, width, window, bin, eb, bin_mode=0):
-    return Params(panels, height, width, window, bin, bin_mode, float(eb))
+def params(panels, height, width, window, bin, eb, bin_mode=0, dim=2):
+    return Params(panels, height, width, window, bin, bin_mode, float(eb), dim)
 
 
 def _ptr(a):

@@ -3,7 +3,8 @@ definitions used as pins.  Test code only: written from the stated format and
 the paper's definitions, sharing nothing with the oracle or the HIP library.
 
 Layout (little-endian, sections 4-byte aligned):
-  header 80 B: magic 'RSZ1', u16 version 1, u16 flags (bit0 bin_mode),
+  header 80 B: magic 'RSZ1', u16 version 1, u16 flags (bit0 bin_mode, bits
+  1-2 the Lorenzo dimension, 0 standing for 2),
   u32 P, H, W, window, bin, radius(512), f64 eb, u32 npeaks, n_out, chunk(4096),
   n_chunks, u64 T (bits), u64 stream_bytes, u64 reserved 0;
   then peaks (npeaks x 3 u16, padded to 4), ROI payload (npeaks*w*w u32),
@@ -43,7 +44,8 @@ def parse(buf):
     off = sections(npk, w, n_out, nch, T)
     d = dict(magic=magic, version=ver, flags=flags, P=P, H=H, W=W, window=w, bin=b, radius=R,
              eb=eb, npeaks=npk, n_out=n_out, chunk=ch, n_chunks=nch, T=T, stream_bytes=total,
-             reserved=res, off=off)
+             reserved=res, off=off, bin_mode=flags & 1,
+             dim={0: 2, 1: 1, 3: 3}.get((flags >> 1) & 3))
     d["peaks"] = np.frombuffer(buf, np.uint16, 3 * npk, off["peaks"]).reshape(-1, 3)
     d["roi"] = np.frombuffer(buf, np.uint32, npk * w * w, off["roi"])
     d["lens"] = np.frombuffer(buf, np.uint8, 1024, off["lens"])
