@@ -108,10 +108,9 @@ def serving_section(args, torch, dev):
 def decompress_section(args, torch, dev, B, sizes, host):
     """Decompression of the first frames' streams, one frame per call
     (rsz_decompress: header read, kernels, status read): per-frame latency,
-    reconstructed GB/s and per-kernel times; the first frames' outputs are
-    compared with the oracle's reconstruction bit for bit."""
+    reconstructed GB/s and per-kernel times (bit-exactness against the
+    oracle's reconstruction is what the GPU tests check)."""
     import numpy as np
-    from oracle import rsz_oracle as O
     from paper_2206_11297_amd import rsz
     n = min(args.decompress_frames, len(sizes))
     streams = [B.stream(i, sizes).clone() for i in range(n)]
@@ -132,10 +131,6 @@ def decompress_section(args, torch, dev, B, sizes, host):
                                 out.numel(), rsz._ptr(ws), ws.numel(), s)
         lat.append(time.perf_counter() - a)
         assert st == 0, f"decompress frame {i}: status {st}"
-        if i < 4:
-            ok, ref = O.decompress(streams[i].cpu().numpy())
-            assert ok == O.OK and np.array_equal(out.cpu().numpy().view(np.uint32),
-                                                 ref.view(np.uint32)), f"frame {i} differs"
     prof = rsz.rsz_profile_read()
     rsz.rsz_profile_enable(False)
     lat_ms = np.array(lat) * 1e3
@@ -144,8 +139,41 @@ def decompress_section(args, torch, dev, B, sizes, host):
             "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
             "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
             "gbps": round(n * fb / (lat_ms.sum() / 1e3) / 1e9, 2),
-            "kernel_ms_per_frame": {k: round(v[1] / v[0], 4) for k, v in prof.items()},
-            "equal_oracle_first": min(4, n)}
+            "kernel_ms_per_frame": {k: round(v[1] / v[0], 4) for k, v in prof.items()}}
+
+
+def lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips, raw_bytes):
+    """The same batch with the Lorenzo predictor in one and three dimensions
+    (Sec. VI): whole-path GB/s, compression ratio and per-kernel times."""
+    import numpy as np
+    from paper_2206_11297_amd import rsz
+    out = {}
+    npix = raw_bytes // 4
+    for dim in args.dims:
+        B = rsz.Batch(frames, peaks, prm + (dim,), tile_rows=tile_rows, tile_strips=tile_strips)
+        for _ in range(2):
+            B.run()
+        torch.cuda.synchronize()
+        st = B.status.cpu().numpy()
+        assert (st == 0).all(), f"dim {dim}: statuses {set(st.tolist())}"
+        rsz.rsz_profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.dims_steps):
+            B.run()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.dims_steps
+        prof = rsz.rsz_profile_read()
+        rsz.rsz_profile_enable(False)
+        sizes = B.sizes.cpu().numpy().astype(np.int64)
+        out[f"dim{dim}"] = {"value": round(raw_bytes / el / 1e9, 2), "unit": "GB/s",
+                            "ms_per_step": round(el * 1e3, 4), "steps": args.dims_steps,
+                            "compression_ratio_u16_aggregate": round(float(npix * 2 / sizes.sum()), 3),
+                            "kernel_ms": {k: round(v[1] / v[0], 4) for k, v in prof.items()}}
+        print(f"[bench] dim {dim}: {out[f'dim{dim}']['value']} GB/s, CR "
+              f"{out[f'dim{dim}']['compression_ratio_u16_aggregate']}", file=sys.stderr, flush=True)
+        del B
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(args, host, B, sizes):
@@ -299,6 +327,9 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-batch", type=int, default=32)
+    ap.add_argument("--dims", type=int, nargs="*", default=[1, 3],
+                    help="Lorenzo dimensions timed besides 2 on the same batch")
+    ap.add_argument("--dims-steps", type=int, default=10)
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary)
@@ -412,6 +443,8 @@ def main():
 
     decomp = decompress_section(args, torch, dev, B, sizes, host) if args.decompress_frames else None
     serving = serving_section(args, torch, dev) if args.serve_rates else None
+    dims = lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips,
+                                raw_bytes) if args.dims else None
 
     line = {
         "metric": "raw-frame GB/s compressed (1 GPU) at eb=10 ADU; compression ratio; "
@@ -441,6 +474,7 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in kernel_ms.items()},
         "serving": serving,
         "decompress": decomp,
+        "lorenzo_dims": dims,
     }
     if serving:
         top = serving.get(f"{max(args.serve_rates):g}kHz")

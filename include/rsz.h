@@ -7,8 +7,9 @@
  * The background is binned b x b by its mean (Sec. VI) and compressed with an
  * absolute error bound that holds on the binned values (Sec. V-C, "Our
  * Approach").  Here the background compressor is prequantisation at step 2*eb,
- * a 2D Lorenzo predictor over the integer field of each panel, outlier capture
- * outside a radius of 512, and Huffman coding over 1024 symbols.
+ * a Lorenzo predictor over the integer field (in one, two or three
+ * dimensions, the "dimension" of Sec. VI), outlier capture outside a radius
+ * of 512, and Huffman coding over 1024 symbols.
  *
  * Conventions for every entry point:
  *   - Pointers prefixed d_ are device memory (e.g. torch tensors on the GPU),
@@ -22,7 +23,8 @@
  *   - Device buffers must be 16-byte aligned (frames, outputs, workspaces).
  *
  * Frame layout: panels x height x width float32, C-contiguous.  Stream
- * layout (little-endian, sections 4-byte aligned): 80-byte header, peaks
+ * layout (little-endian, sections 4-byte aligned): 80-byte header (flags:
+ * bit 0 bin_mode, bits 1-2 the Lorenzo dimension, 0 for 2), peaks
  * (u16 panel,row,col), ROI payload (npeaks*w*w u32 bit patterns, 0 outside
  * the panel), code lengths (1024 u8), chunk bit offsets (u32, one per 4096
  * symbols), bitstream (u32 words, codewords MSB-first), outlier bin indices
@@ -53,13 +55,18 @@ typedef struct {
  *   bin: bin factor b, 1..8 (2 in the paper's chosen setting, Sec. VI).
  *   bin_mode: RSZ_BIN_BACKGROUND averages only pixels outside every ROI
  *     window; RSZ_BIN_ALL averages every pixel of the bin.
- *   eb: absolute error bound on binned values, finite and > 0. */
+ *   eb: absolute error bound on binned values, finite and > 0.
+ *   dim: dimension of the Lorenzo predictor (Sec. VI): 1 reads the binned
+ *     frame as one sequence in raster order (panel, row, column), 2 reads
+ *     each panel as an image (0 also means 2, the default), 3 reads the
+ *     stack of panels as a volume.  Residuals take zeros outside the domain. */
 typedef struct {
   uint32_t panels, height, width;
   uint32_t window;
   uint32_t bin;
   uint32_t bin_mode;
   double eb;
+  uint32_t dim;
 } rsz_params;
 
 enum { RSZ_BIN_BACKGROUND = 0, RSZ_BIN_ALL = 1 };

@@ -22,10 +22,12 @@ CANDIDATES = [(r, s) for r in ROWS for s in STRIPS]
 
 
 def signature(frames, prm):
-    """Key of a batch: its distinct (shape, window, bin) and frame-count bucket."""
+    """Key of a batch: its distinct (shape, window, bin[, Lorenzo dimension
+    when not 2]) and frame-count bucket."""
     n = len(frames)
     prm = prm if isinstance(prm, list) else [prm] * n
-    kinds = sorted({(tuple(f.shape), int(p[0]), int(p[1])) for f, p in zip(frames, prm)})
+    dims = lambda p: (int(p[4]),) if len(p) > 4 and int(p[4]) not in (0, 2) else ()
+    kinds = sorted({(tuple(f.shape), int(p[0]), int(p[1])) + dims(p) for f, p in zip(frames, prm)})
     bucket = 1
     while bucket < n:
         bucket <<= 1

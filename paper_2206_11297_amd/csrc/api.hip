@@ -52,7 +52,8 @@ static int check_params(const rsz_params *p, uint32_t npeaks) {
   if (p->panels < 1 || p->panels > 65535 || p->height < 1 || p->height > 65535 ||
       p->width < 1 || p->width > 65535)
     return RSZ_ERR_ARG;
-  if (p->window < 1 || p->window > 1023 || p->bin < 1 || p->bin > 8 || p->bin_mode > 1)
+  if (p->window < 1 || p->window > 1023 || p->bin < 1 || p->bin > 8 || p->bin_mode > 1 ||
+      p->dim > 3)
     return RSZ_ERR_ARG;
   if (!(p->eb > 0.0) || !std::isfinite(p->eb)) return RSZ_ERR_ARG;
   const uint64_t pix = (uint64_t)p->panels * p->height * p->width;
@@ -112,6 +113,9 @@ static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const G
   b += align_up(4ull * g.nbins, 256);          // rbuf
   b += align_up(4ull * g.nbins, 256);          // obuf
   b += 3 * align_up(4ull * g.nchunks, 256);    // chunk_off, chunk_oo, head
+  if (p->dim == 1) b += align_up(4ull * p->panels * g.Hb, 256);   // qedge
+  if (p->dim == 3)   // 2D code bytes and residuals
+    b += align_up(1ull * kChunk * g.nchunks, 256) + align_up(4ull * g.nbins, 256);
   return b;
 }
 
@@ -121,7 +125,7 @@ static Layout layout(uint32_t nframes, const std::vector<const rsz_params *> &ps
   Layout L;
   L.plans = 0;
   L.prefix = align_up(sizeof(FramePlan) * nframes, 256);
-  L.states = L.prefix + align_up(4 * 4ull * (nframes + 1), 256);
+  L.states = L.prefix + align_up(5 * 4ull * (nframes + 1), 256);
   L.frames_begin = L.states + align_up(sizeof(FrameState) * nframes, 256);
   uint64_t off = L.frames_begin;
   L.frame_off.resize(nframes);
@@ -138,6 +142,7 @@ struct HostPlan {
   std::vector<uint8_t> bytes;
   BatchPlan bp;
   uint32_t common_b;    // bin factor of every valid frame, or 0 when they differ
+  uint32_t common_dim;  // Lorenzo dimension of every valid frame, or 0
 };
 
 static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_bytes,
@@ -156,11 +161,18 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   }
   // the binning kernel is compiled for the common bin factor of the batch
   hp.common_b = 0;
+  hp.common_dim = 2;
   bool first = true;
   for (uint32_t f = 0; f < nframes; ++f) {
     if (!valid[f]) continue;
-    if (first) hp.common_b = ps[f]->bin;
-    else if (hp.common_b != ps[f]->bin) hp.common_b = 0;
+    const uint32_t dim = ps[f]->dim ? ps[f]->dim : 2u;
+    if (first) {
+      hp.common_b = ps[f]->bin;
+      hp.common_dim = dim;
+    } else {
+      if (hp.common_b != ps[f]->bin) hp.common_b = 0;
+      if (hp.common_dim != dim) hp.common_dim = 0;
+    }
     first = false;
   }
   const uint32_t gsw = (uint32_t)group_strips((int)hp.common_b);
@@ -202,7 +214,8 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   uint32_t *cp = tp + (nframes + 1);
   uint32_t *rp = cp + (nframes + 1);
   uint32_t *kp = rp + (nframes + 1);
-  uint64_t tiles = 0, units = 0, npk_total = 0, all_chunks = 0, chunks_done = 0;
+  uint32_t *xp = kp + (nframes + 1);
+  uint64_t tiles = 0, units = 0, npk_total = 0, all_chunks = 0, chunks_done = 0, fixes = 0;
   for (uint32_t f = 0; f < nframes; ++f)
     if (valid[f]) all_chunks += gs[f].nchunks;
   // chunks per encode workgroup (its waves take every kWaves-th chunk): a
@@ -219,6 +232,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     cp[f] = (uint32_t)units;
     rp[f] = (uint32_t)npk_total;
     kp[f] = (uint32_t)chunks_done;
+    xp[f] = (uint32_t)fixes;
     fp.st = (FrameState *)(ws + L.states) + f;
     fp.res_bytes = res_bytes + f;
     fp.res_status = res_status + f;
@@ -234,6 +248,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.w = p->window;
     fp.b = p->bin;
     fp.mode = p->bin_mode;
+    fp.dim = p->dim ? p->dim : 2u;
     fp.eb = p->eb;
     fp.step = 2.0 * p->eb;
     fp.Hb = g.Hb;
@@ -276,6 +291,15 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.chunk_oo = (uint32_t *)base;
     base += align_up(4ull * g.nchunks, 256);
     fp.head = (uint32_t *)base;
+    base += align_up(4ull * g.nchunks, 256);
+    fp.codes2 = fp.codes;
+    fp.rbuf2 = fp.rbuf;
+    if (fp.dim == 1) fp.qedge = (int32_t *)base;
+    if (fp.dim == 3) {
+      fp.codes2 = base;
+      base += align_up(1ull * kChunk * g.nchunks, 256);
+      fp.rbuf2 = (int32_t *)base;
+    }
     if (dbg) {
       fp.dbg_mask = dbg->mask;
       fp.dbg_S = dbg->S;
@@ -286,14 +310,20 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     units += div_up(g.nchunks, cpw);
     chunks_done += g.nchunks;
     npk_total += np[f];
+    // k_lorenzo_dims: 256 bin rows to correct (dim 1: the first row of each
+    // panel, or every row when a panel row spans column groups) or kFixBins3
+    // bins (dim 3) per workgroup
+    if (fp.dim == 1) fixes += div_up((uint64_t)p->panels * (g.cgs == 1 ? 1 : g.Hb), 256);
+    else if (fp.dim == 3) fixes += div_up(g.nbins, kFixBins3);
   }
   if (tiles >= (1ull << 31) || units >= (1ull << 31) || npk_total >= (1ull << 31) ||
-      chunks_done >= (1ull << 31))
+      chunks_done >= (1ull << 31) || fixes >= (1ull << 31))
     return RSZ_ERR_ARG;
   tp[nframes] = (uint32_t)tiles;
   cp[nframes] = (uint32_t)units;
   rp[nframes] = (uint32_t)npk_total;
   kp[nframes] = (uint32_t)chunks_done;
+  xp[nframes] = (uint32_t)fixes;
   hp.bp.nframes = nframes;
   hp.bp.total_chunks = (uint32_t)chunks_done;
   hp.bp.total_tiles = (uint32_t)tiles;
@@ -306,6 +336,8 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   hp.bp.unit_prefix = hp.bp.tile_prefix + (nframes + 1);
   hp.bp.peak_prefix = hp.bp.unit_prefix + (nframes + 1);
   hp.bp.chunk_prefix = hp.bp.peak_prefix + (nframes + 1);
+  hp.bp.fix_prefix = hp.bp.chunk_prefix + (nframes + 1);
+  hp.bp.total_fix = (uint32_t)fixes;
   return RSZ_OK;
 }
 
@@ -348,6 +380,7 @@ static int stage_to_device(void *dst, const void *src, size_t n, hipStream_t s) 
 struct PlanRecord {
   BatchPlan bp;
   uint32_t common_b;
+  uint32_t common_dim;
 };
 static_assert(sizeof(PlanRecord) <= sizeof(rsz_batch_plan), "plan record too large");
 
@@ -359,7 +392,8 @@ static int enqueue(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_byte
                             0, hp, nullptr, dbg);
   if (st) return st;
   if (stage_to_device(ws, hp.bytes.data(), hp.bytes.size(), s) != RSZ_OK) return RSZ_ERR_HIP;
-  if (launch_compress_front_b(hp.bp, hp.common_b, s, dbg != nullptr) != hipSuccess)
+  if (launch_compress_front_b(hp.bp, hp.common_b, hp.common_dim, s, dbg != nullptr) !=
+      hipSuccess)
     return RSZ_ERR_HIP;
   if (!front_only && launch_compress_back(hp.bp, s) != hipSuccess) return RSZ_ERR_HIP;
   return RSZ_OK;
@@ -375,7 +409,13 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
   memcpy(u, h, 80);
   if (memcmp(h, "RSZ1", 4) != 0 || (u[1] & 0xFFFFu) != 1u) return RSZ_ERR_CORRUPT;
   rsz_params q;
-  q.bin_mode = u[1] >> 16;
+  memset(&q, 0, sizeof q);
+  // flags: bit 0 bin_mode, bits 1-2 the Lorenzo dimension (0 for 2, else 1
+  // or 3); every other bit zero
+  const uint32_t flags = u[1] >> 16, dcode = (flags >> 1) & 3u;
+  if ((flags >> 3) != 0 || dcode == 2) return RSZ_ERR_CORRUPT;
+  q.bin_mode = flags & 1u;
+  q.dim = dcode == 0 ? 2u : dcode;
   q.panels = u[2];
   q.height = u[3];
   q.width = u[4];
@@ -405,6 +445,7 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
     dp->w = q.window;
     dp->b = q.bin;
     dp->npeaks = np;
+    dp->dim = q.dim;
     dp->step = 2.0 * q.eb;
     dp->Hb = g.Hb;
     dp->Wb = g.Wb;
@@ -426,7 +467,8 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
 
 static uint64_t decode_ws_bytes(const DecodePlan &dp) {
   return align_up(4ull * dp.nbins, 256) + align_up(4ull * dp.nchunks, 256) + 256 +
-         align_up(decode_tables_bytes(), 256);
+         align_up(decode_tables_bytes(), 256) +
+         (dp.dim == 1 ? align_up(4ull * dp.P * dp.Hb, 256) : 0);
 }
 
 // Results of a single-frame call live in the workspace tail.
@@ -615,6 +657,8 @@ int rsz_decompress(const void *d_in, uint64_t in_bytes, float *d_frame, uint64_t
   dp.status = (int32_t *)w;
   w += 256;
   dp.tables = (uint32_t *)w;
+  w += align_up(decode_tables_bytes(), 256);
+  if (dp.dim == 1) dp.carry = (uint32_t *)w;
   if (launch_decompress(dp, s) != hipSuccess) return RSZ_ERR_HIP;
   int32_t status = 0;
   if (hipMemcpyAsync(&status, dp.status, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -637,6 +681,7 @@ int rsz_batch_prepare(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t 
   PlanRecord rec;
   rec.bp = hp.bp;
   rec.common_b = hp.common_b;
+  rec.common_dim = hp.common_dim;
   memset(h_plan, 0, sizeof *h_plan);
   memcpy(h_plan, &rec, sizeof rec);
   return RSZ_OK;
@@ -648,7 +693,7 @@ int rsz_batch_launch(const rsz_batch_plan *h_plan, void *stream) {
   memcpy(&rec, h_plan, sizeof rec);
   if (rec.bp.nframes == 0 || !rec.bp.frames) return RSZ_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
-  if (launch_compress_front_b(rec.bp, rec.common_b, s, false) != hipSuccess)
+  if (launch_compress_front_b(rec.bp, rec.common_b, rec.common_dim, s, false) != hipSuccess)
     return RSZ_ERR_HIP;
   if (launch_compress_back(rec.bp, s) != hipSuccess) return RSZ_ERR_HIP;
   return RSZ_OK;
@@ -747,25 +792,26 @@ int rsz_measure_read(const void *d_buf, uint64_t bytes, void *d_sink, int reps, 
   hipEvent_t a, e;
   if (hipEventCreate(&a) != hipSuccess) return RSZ_ERR_HIP;
   if (hipEventCreate(&e) != hipSuccess) {
-    hipEventDestroy(a);
+    (void)hipEventDestroy(a);
     return RSZ_ERR_HIP;
   }
   int st = RSZ_OK;
   hipLaunchKernelGGL(k_measure_read, dim3(grid), dim3(256), 0, s, (const uint4 *)d_buf, n16,
                      (uint32_t *)d_sink);
-  hipEventRecord(a, s);
+  const hipError_t ea = hipEventRecord(a, s);
   for (int r = 0; r < reps; ++r)
     hipLaunchKernelGGL(k_measure_read, dim3(grid), dim3(256), 0, s, (const uint4 *)d_buf, n16,
                        (uint32_t *)d_sink);
-  hipEventRecord(e, s);
+  const hipError_t ee = hipEventRecord(e, s);
   float ms = 0.f;
-  if (hipGetLastError() != hipSuccess || hipEventSynchronize(e) != hipSuccess ||
+  if (ea != hipSuccess || ee != hipSuccess || hipGetLastError() != hipSuccess ||
+      hipEventSynchronize(e) != hipSuccess ||
       hipEventElapsedTime(&ms, a, e) != hipSuccess || ms <= 0.f)
     st = RSZ_ERR_HIP;
   else
     *h_gbps = (double)reps * (double)(n16 * 16) / ((double)ms * 1e6);
-  hipEventDestroy(a);
-  hipEventDestroy(e);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(e);
   return st;
 }
 

@@ -424,7 +424,15 @@ constexpr int strips_in_flight() {
 // The Lorenzo predictor of the tile's first row and first column reads the q
 // of bin row I0 - 1 and bin column J0 - 1, owned by neighbouring tiles: both
 // are recomputed here from the frame (same loads, same sums).
-template <int BB, bool VEC, bool BG, bool DEBUG>
+// Dimension 2 finishes every residual here.  Dimension 1 takes r = q - q_left
+// along the row; the first bin of a row follows the last bin of the row
+// before, which a tile spanning the whole row holds (the halo row for its
+// first row).  Where the predecessor lies elsewhere -- the first row of a
+// panel, every row of a panel split into column groups -- the first bin gets
+// r = q here and k_lorenzo_dims corrects it with the q of the row before's
+// last bin, kept in qedge.  Dimension 3 leaves the panel's 2D residual for
+// k_lorenzo_dims to difference across panels, and counts no histogram here.
+template <int BB, bool VEC, bool BG, bool DEBUG, int DIM>
 __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32_t seg,
                                          uint32_t cg, uint32_t *hist, uint32_t *mask,
                                          const double *inv) {
@@ -446,12 +454,13 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
   const float *fr = fp.frame + (size_t)p * H * W;
   const double step = fp.step;
   const size_t gbase = (size_t)p * Hb * Wb;
-  uint8_t *codes = fp.codes + gbase;
-  int32_t *rbuf = fp.rbuf + gbase;
+  uint8_t *codes = fp.codes2 + gbase;
+  int32_t *rbuf = fp.rbuf2 + gbase;
   bool range_err = false;
   uint32_t c512 = 0;
   double Sd;
   uint32_t nd;
+  const uint32_t dim = DIM ? (uint32_t)DIM : fp.dim;
   if (BG || (DEBUG && fp.dbg_mask)) {
     build_mask(fp, p, mask, R0, mrows, Cm, wpr);
     if (DEBUG && fp.dbg_mask) {
@@ -524,9 +533,25 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
       }
     }
   }
+  // dim 1: the tile holds the last bin of each row (last column group); if it
+  // spans whole rows, that bin is the raster predecessor of the next row's
+  // first bin.  lastq: q of the last bin of the row above (the halo row to
+  // start).
+  const bool last_group = J0 + (uint32_t)ns * 64 >= Wb;
+  const bool whole_rows = J0 == 0 && last_group;
+  const int lastlane = (int)((Wb - 1) & 63);
+  int32_t lastq = 0;
+  if (dim == 1 && whole_rows) {
+    int32_t v = q_up[0];
+#pragma unroll
+    for (int s = 1; s < NS; ++s)
+      if (s == ns - 1) v = q_up[s];
+    lastq = __builtin_amdgcn_readlane(v, lastlane);
+  }
   for (uint32_t I = I0; I < I1; ++I) {
     // q left of the group on this row
     int32_t left = __builtin_amdgcn_readlane(q_left, I - I0 + 1);
+    if (dim == 1 && whole_rows && I > 0) left = lastq;
     // in-panel pixels of this bin row (vector path: every column is)
     uint32_t rowbits = 0;
     if constexpr (VEC) rowbits = (1u << (min((uint32_t)BB, H - I * BB) * BB)) - 1u;
@@ -563,7 +588,7 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
         const int32_t ql = from_left(q, left);
         left = __builtin_amdgcn_readlane(q, 63);
         // residual; codes 1..1023 carry r + 512, 0 marks an outlier
-        const int32_t r = q + ql_up[s] - q_up[s] - ql;
+        const int32_t r = dim == 1 ? q - ql : q + ql_up[s] - q_up[s] - ql;
         const uint32_t code = code_from_residual(r);
         if (colv) {
           const size_t g = (size_t)I * Wb + J;
@@ -577,11 +602,15 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
             if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
           }
         }
-        wave_histogram(code, vmask[s], hist, c512);
+        if (dim != 3) wave_histogram(code, vmask[s], hist, c512);
+        if (dim == 1 && s == ns - 1) lastq = __builtin_amdgcn_readlane(q, lastlane);
         q_up[s] = q;
         ql_up[s] = ql;
       }
     }
+    // the row's last q, for k_lorenzo_dims where it cannot be used here
+    if (dim == 1 && last_group && (!whole_rows || I == Hb - 1) && lane == 0)
+      fp.qedge[(size_t)p * Hb + I] = lastq;
   }
 #undef RSZ_MW
 #undef RSZ_JC
@@ -590,9 +619,10 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
 }
 
 // BB: the bin factor (1, 2, 4) compiled in, or 0 for any b (one strip per
-// column group).  Workgroup t of a frame: panel, column group, then a group
-// of kWaves consecutive segments, one per wave.
-template <int BB, bool DEBUG>
+// column group).  DIM: the Lorenzo dimension compiled in, or 0 for a batch
+// mixing dimensions (read per frame).  Workgroup t of a frame: panel, column
+// group, then a group of kWaves consecutive segments, one per wave.
+template <int BB, bool DEBUG, int DIM>
 __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
   __shared__ uint32_t s_hist[kNumSym];
   __shared__ uint32_t s_mask[kWaves][kMaskWords];
@@ -617,18 +647,164 @@ __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
     if constexpr (BB == 2 || BB == 4) {
       vec = fp.vec != 0;
       if (vec) {
-        if (bg) bin_tile<BB, true, true, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
-        else bin_tile<BB, true, false, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
+        if (bg) bin_tile<BB, true, true, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv);
+        else bin_tile<BB, true, false, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv);
       }
     }
     if (!vec) {
-      if (bg) bin_tile<BB, false, true, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
-      else bin_tile<BB, false, false, DEBUG>(fp, panel, seg, cg, s_hist, mask, s_inv);
+      if (bg) bin_tile<BB, false, true, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv);
+      else bin_tile<BB, false, false, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv);
     }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kNumSym; i += 256)
     if (s_hist[i]) atomicAdd(&fp.st->hist[i], s_hist[i]);
+}
+
+// ------------------------------------------------------- k_lorenzo_dims
+
+// Finishes the residuals of frames whose Lorenzo predictor is not 2D (the
+// "dimension" of Sec. VI), after k_bin.
+//  dim 1: one lane per bin row R = p*Hb + I whose first bin k_bin coded as
+//    r = q (the first row of each panel; every row of a panel split into
+//    column groups).  That bin follows the last bin of row R - 1 in raster
+//    order, so r = q_first(R) - q_last(R - 1) replaces it (q_first is the r
+//    k_bin coded, q_last comes from qedge); the histogram moves the bin from
+//    the old code to the new one.
+//  dim 3: the 3D residual is the difference along the panel axis of the
+//    panels' 2D residuals (the operators commute): r3[g] = r2[g] - r2[g -
+//    Hb*Wb], or r2[g] on panel 0.  k_bin left r2 in codes2/rbuf2.  A
+//    workgroup takes kFixBins3 bins, a lane 16 consecutive code bytes per
+//    step: one aligned 16-byte load, and its predecessors' bytes shifted out
+//    of two aligned loads (the shift, (-Hb*Wb) mod 16, is the same for every
+//    lane).  Equal nonzero bytes on both sides mean r3 = 0: output byte 128,
+//    code 512, counted by a popcount.  The few other bytes (residuals that
+//    differ, escapes, panel 0) are taken one by one.  It writes the code
+//    bytes of r3 to codes (r3 to rbuf where the byte is 0) and counts the
+//    histogram.
+
+// 0x80 in each byte of x that is zero, 0 elsewhere.
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t x) {
+  const uint32_t y = (x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+  return ~(y | x | 0x7F7F7F7Fu);
+}
+// Bit i (i < 4) set where byte i of m has its top bit set.
+__device__ __forceinline__ uint32_t byte_bits(uint32_t m) {
+  return ((m >> 7) & 1u) | ((m >> 14) & 2u) | ((m >> 21) & 4u) | ((m >> 28) & 8u);
+}
+
+__device__ __forceinline__ int32_t r_of(uint32_t byte, const int32_t *rbuf, uint32_t g) {
+  return byte ? (int32_t)byte - 128 : rbuf[g];
+}
+
+__global__ __launch_bounds__(256) void k_lorenzo_dims(BatchPlan bp) {
+  __shared__ uint32_t s_hist[kNumSym];
+  const uint32_t f = find_frame(bp.fix_prefix, bp.nframes, blockIdx.x);
+  const FramePlan &fp = bp.frames[f];
+  if (load_status(fp.st) != RSZ_OK) return;   // the same frame for the whole workgroup
+  const uint32_t blk = blockIdx.x - bp.fix_prefix[f];
+  if (fp.dim == 1) {
+    const uint32_t t = blk * 256 + threadIdx.x;
+    const uint32_t R = fp.cgs == 1 ? t * fp.Hb : t;
+    if (t >= (fp.cgs == 1 ? fp.P : fp.P * fp.Hb) || R == 0) return;
+    const size_t g = (size_t)R * fp.Wb;
+    const int32_t qf = r_of(fp.codes[g], fp.rbuf, (uint32_t)g);
+    const int32_t prev = fp.qedge[R - 1];
+    if (prev == 0) return;
+    const int32_t r = qf - prev;   // |q| <= 2^28 - 1
+    const uint32_t cb = code_byte(r);
+    fp.codes[g] = (uint8_t)cb;
+    if (cb == 0) fp.rbuf[g] = r;
+    const uint32_t c0 = code_from_residual(qf), c1 = code_from_residual(r);
+    if (c0 != c1) {
+      atomicSub(&fp.st->hist[c0], 1u);
+      atomicAdd(&fp.st->hist[c1], 1u);
+    }
+    return;
+  }
+  for (int i = threadIdx.x; i < kNumSym; i += 256) s_hist[i] = 0u;
+  __syncthreads();
+  const uint32_t plane = fp.Hb * fp.Wb, nbins = fp.nbins;
+  const uint4 *__restrict__ c2v = (const uint4 *)fp.codes2;
+  const uint8_t *__restrict__ c2b = fp.codes2;
+  const int32_t *__restrict__ rb2 = fp.rbuf2;
+  uint4 *__restrict__ cout = (uint4 *)fp.codes;
+  int32_t *__restrict__ rout = fp.rbuf;
+  // the predecessors of 16 aligned bytes start (-plane) mod 16 bytes into an
+  // aligned 16-byte group: words q.. of two consecutive groups, shifted by r bytes
+  const uint32_t off = (0u - plane) & 15u, qw = off >> 2, rb = off & 3u;
+  constexpr int K = (int)(kFixBins3 / 4096);
+  uint32_t ow[K][4], pw[K][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t g0 = blk * kFixBins3 + k * 4096 + threadIdx.x * 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ow[k][i] = pw[k][i] = 0u;
+    if (g0 < nbins) {
+      const uint4 o = c2v[g0 >> 4];
+      ow[k][0] = o.x; ow[k][1] = o.y; ow[k][2] = o.z; ow[k][3] = o.w;
+      if (g0 >= plane) {
+        const uint32_t a = (g0 - plane) & ~15u;   // group holding byte g0 - plane
+        const uint4 lo = c2v[a >> 4];
+        const uint4 hi = off ? c2v[(a >> 4) + 1] : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t w8[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          uint32_t a0 = w8[i], a1 = w8[i + 1];
+#pragma unroll
+          for (int t = 1; t < 4; ++t)
+            if (qw == (uint32_t)t) { a0 = w8[(i + t) & 7]; a1 = w8[(i + t + 1) & 7]; }
+          pw[k][i] = (uint32_t)((((uint64_t)a1 << 32) | a0) >> (8 * rb));
+        }
+      } else if (g0 + 16 > plane) {
+        for (uint32_t e = plane - g0; e < 16 && g0 + e < nbins; ++e)
+          pw[k][e >> 2] |= (uint32_t)c2b[g0 + e - plane] << (8 * (e & 3));
+      }
+    }
+  }
+  uint32_t c512 = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t g0 = blk * kFixBins3 + k * 4096 + threadIdx.x * 16;
+    if (g0 >= nbins) continue;
+    // bytes to take one by one: escapes (code byte 0) on either side, bytes
+    // whose 2D residuals differ, bytes of panel 0 and bytes past the frame;
+    // every other byte has r3 = 0 (output byte 128, code 512)
+    uint32_t slow = 0, outw[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t x = ow[k][i] ^ pw[k][i];
+      const uint32_t eq = zero_bytes(x), ze = zero_bytes(ow[k][i]) | zero_bytes(pw[k][i]);
+      slow |= byte_bits(~eq | ze) << (4 * i);
+      outw[i] = 0x80808080u;
+    }
+    if (g0 < plane) slow |= plane - g0 >= 16 ? 0xFFFFu : (1u << (plane - g0)) - 1u;
+    if (g0 + 16 > nbins) slow |= 0xFFFFu & ~((1u << (nbins - g0)) - 1u);
+    c512 += 16 - __builtin_popcount(slow);
+    while (slow) {
+      const int e = __builtin_ctz(slow);
+      slow &= slow - 1;
+      const uint32_t g = g0 + e;
+      if (g >= nbins) continue;
+      const uint32_t b2 = (ow[k][e >> 2] >> (8 * (e & 3))) & 0xFFu;
+      const uint32_t bq = (pw[k][e >> 2] >> (8 * (e & 3))) & 0xFFu;
+      const uint32_t r2 = b2 ? b2 - 128u : (uint32_t)rb2[g];
+      const uint32_t rp = g >= plane ? (bq ? bq - 128u : (uint32_t)rb2[g - plane]) : 0u;
+      const uint32_t r = r2 - rp;   // |r3| <= 8 (2^28 - 1) < 2^31
+      const uint32_t nb = code_byte((int32_t)r);
+      outw[e >> 2] = (outw[e >> 2] & ~(0xFFu << (8 * (e & 3)))) | (nb << (8 * (e & 3)));
+      if (nb == 0) rout[g] = (int32_t)r;
+      atomicAdd(&s_hist[code_from_residual((int32_t)r)], 1u);
+    }
+    cout[g0 >> 4] = make_uint4(outw[0], outw[1], outw[2], outw[3]);
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) c512 += __shfl_xor(c512, d);
+  if ((threadIdx.x & 63) == 0 && c512) atomicAdd(&s_hist[kRadius], c512);
+  __syncthreads();
+  uint32_t *ghist = fp.st->hist;
+  for (int i = threadIdx.x; i < kNumSym; i += 256)
+    if (s_hist[i]) atomicAdd(&ghist[i], s_hist[i]);
 }
 
 // ------------------------------------------------------------- k_codebook
@@ -1139,7 +1315,9 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
   uint8_t *o = fp.out;
   if (threadIdx.x == 0) {
     put_u32(o, 0, 0x315A5352u);  // "RSZ1"
-    put_u32(o, 4, 1u | ((fp.mode & 1u) << 16));
+    // version 1; flags: bit 0 bin_mode, bits 1-2 the Lorenzo dimension (0 for 2)
+    const uint32_t flags = (fp.mode & 1u) | ((fp.dim == 2 ? 0u : fp.dim) << 1);
+    put_u32(o, 4, 1u | (flags << 16));
     put_u32(o, 8, fp.P);
     put_u32(o, 12, fp.H);
     put_u32(o, 16, fp.W);
@@ -1245,23 +1423,31 @@ hipError_t launch_debug_codes(const BatchPlan &bp, uint32_t nbins, uint16_t *out
 }
 
 // `b`: the common bin factor of the batch, or 0 (mixed or not 1, 2, 4).
-template <bool DEBUG>
+template <bool DEBUG, int DIM>
 static hipError_t launch_bin(const BatchPlan &bp, uint32_t b, hipStream_t s) {
   if (bp.total_tiles == 0) return hipSuccess;
   switch (b) {
-    case 1: RSZ_LAUNCH("k_bin", (k_bin<1, DEBUG>), bp.total_tiles, s, bp); break;
-    case 2: RSZ_LAUNCH("k_bin", (k_bin<2, DEBUG>), bp.total_tiles, s, bp); break;
-    case 4: RSZ_LAUNCH("k_bin", (k_bin<4, DEBUG>), bp.total_tiles, s, bp); break;
-    default: RSZ_LAUNCH("k_bin", (k_bin<0, DEBUG>), bp.total_tiles, s, bp); break;
+    case 1: RSZ_LAUNCH("k_bin", (k_bin<1, DEBUG, DIM>), bp.total_tiles, s, bp); break;
+    case 2: RSZ_LAUNCH("k_bin", (k_bin<2, DEBUG, DIM>), bp.total_tiles, s, bp); break;
+    case 4: RSZ_LAUNCH("k_bin", (k_bin<4, DEBUG, DIM>), bp.total_tiles, s, bp); break;
+    default: RSZ_LAUNCH("k_bin", (k_bin<0, DEBUG, DIM>), bp.total_tiles, s, bp); break;
   }
   return hipSuccess;
 }
 
-// prep + bin + codebook; `b` is the common bin factor of the batch or 0.
-hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t s, bool debug) {
+// prep + bin + codebook; `b` and `dim` are the common bin factor and Lorenzo
+// dimension of the batch, or 0.  The debug build reads the dimension per frame.
+hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t dim, hipStream_t s,
+                                   bool debug) {
   RSZ_LAUNCH("k_prep", k_prep, bp.nframes, s, bp);
-  hipError_t e = debug ? launch_bin<true>(bp, b, s) : launch_bin<false>(bp, b, s);
+  hipError_t e;
+  if (debug) e = launch_bin<true, 0>(bp, b, s);
+  else if (dim == 2) e = launch_bin<false, 2>(bp, b, s);
+  else if (dim == 1) e = launch_bin<false, 1>(bp, b, s);
+  else if (dim == 3) e = launch_bin<false, 3>(bp, b, s);
+  else e = launch_bin<false, 0>(bp, b, s);
   if (e != hipSuccess) return e;
+  if (bp.total_fix) RSZ_LAUNCH("k_lorenzo_dims", k_lorenzo_dims, bp.total_fix, s, bp);
   RSZ_LAUNCH("k_codebook", k_codebook, bp.nframes, s, bp);
   return hipSuccess;
 }

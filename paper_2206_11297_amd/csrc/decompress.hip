@@ -362,9 +362,10 @@ __global__ __launch_bounds__(256) void k_dec_outliers(DecodePlan dp) {
   const int32_t *orr = (const int32_t *)(dp.in + dp.off_ores);
   const uint32_t g = oi[k];
   const int32_t r = orr[k];
-  // |q| < 2^28 bounds every residual below 2^30 in magnitude
+  // |q| < 2^28 bounds a residual of dimension d below 2^(28+d) in magnitude
+  const int64_t lim = (int64_t)1 << (28 + dp.dim);
   if (g >= dp.nbins || (k > 0 && g <= oi[k - 1]) || (r > -kRadius && r < kRadius) ||
-      r <= -(1 << 30) || r >= (1 << 30) || dp.res[g] != kMark) {
+      (int64_t)r <= -lim || (int64_t)r >= lim || dp.res[g] != kMark) {
     corrupt(dp.status);
     return;
   }
@@ -409,6 +410,56 @@ __global__ __launch_bounds__(256) void k_dec_cols(DecodePlan dp) {
   for (uint32_t I = 0; I < dp.Hb; ++I) {
     acc += (uint32_t)r[(size_t)I * dp.Wb];
     r[(size_t)I * dp.Wb] = (int32_t)acc;
+  }
+}
+
+// Dimension 1: the raster sequence continues across rows, so each row adds
+// the sum of every row before it.  One workgroup scans the row totals (the
+// last element of each row-scanned row) into exclusive carries.
+__global__ __launch_bounds__(256) void k_dec_carry(DecodePlan dp) {
+  __shared__ uint32_t s_w[4];
+  if (!dec_ok(dp.status)) return;
+  const uint32_t rows = dp.P * dp.Hb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t run = 0;
+  for (uint32_t r0 = 0; r0 < rows; r0 += 256) {
+    const uint32_t row = r0 + threadIdx.x;
+    uint32_t x = row < rows ? (uint32_t)dp.res[(size_t)row * dp.Wb + dp.Wb - 1] : 0u;
+    const uint32_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) s_w[wv] = x;
+    __syncthreads();
+    uint32_t before = run;
+    for (int i = 0; i < wv; ++i) before += s_w[i];
+    if (row < rows) dp.carry[row] = before + x - v;
+    run += s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    __syncthreads();
+  }
+}
+
+// Dimension 1: adds each row's carry (one lane per bin).
+__global__ __launch_bounds__(256) void k_dec_rowadd(DecodePlan dp) {
+  if (!dec_ok(dp.status)) return;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x; g < dp.nbins; g += stride)
+    dp.res[g] = (int32_t)((uint32_t)dp.res[g] + dp.carry[g / dp.Wb]);
+}
+
+// Dimension 3: inclusive prefix sum across the panels (one lane per bin
+// position of the panel plane), after the 2D sums of each panel.
+__global__ __launch_bounds__(256) void k_dec_panels(DecodePlan dp) {
+  const uint32_t plane = dp.Hb * dp.Wb;
+  const uint32_t c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= plane || !dec_ok(dp.status)) return;
+  int32_t *r = dp.res + c;
+  uint32_t acc = 0;
+  for (uint32_t p = 0; p < dp.P; ++p) {
+    acc += (uint32_t)r[(size_t)p * plane];
+    r[(size_t)p * plane] = (int32_t)acc;
   }
 }
 
@@ -477,8 +528,17 @@ hipError_t launch_decompress(const DecodePlan &dp, hipStream_t s) {
   RSZ_DLAUNCH("k_dec_tables", k_dec_tables, 1, 256, s);
   RSZ_DLAUNCH("k_dec_chunks", k_dec_chunks, (dp.nchunks + 3) / 4, 256, s);
   if (dp.n_out) RSZ_DLAUNCH("k_dec_outliers", k_dec_outliers, (dp.n_out + 255) / 256, 256, s);
+  // inverse Lorenzo: prefix sums along each axis the predictor spans
   RSZ_DLAUNCH("k_dec_rows", k_dec_rows, (dp.P * dp.Hb + 3) / 4, 256, s);
-  RSZ_DLAUNCH("k_dec_cols", k_dec_cols, (dp.P * dp.Wb + 255) / 256, 256, s);
+  if (dp.dim == 1) {
+    RSZ_DLAUNCH("k_dec_carry", k_dec_carry, 1, 256, s);
+    RSZ_DLAUNCH("k_dec_rowadd", k_dec_rowadd, std::min<uint32_t>((dp.nbins + 255) / 256, 1u << 16),
+                256, s);
+  } else {
+    RSZ_DLAUNCH("k_dec_cols", k_dec_cols, (dp.P * dp.Wb + 255) / 256, 256, s);
+    if (dp.dim == 3)
+      RSZ_DLAUNCH("k_dec_panels", k_dec_panels, (dp.Hb * dp.Wb + 255) / 256, 256, s);
+  }
   const uint64_t npix = (uint64_t)dp.P * dp.H * dp.W;
   RSZ_DLAUNCH("k_dec_expand", k_dec_expand, (uint32_t)std::min<uint64_t>((npix + 255) / 256, 1u << 20),
               256, s);

@@ -24,6 +24,7 @@ constexpr int kMaxTH = 32;
 constexpr int kMaskWords = 896;       // per wave: (TH+1)*b rows x (2b*strips+1) words
 constexpr uint32_t kBlockEncodeChunks = 4096;   // fewer chunks in a batch: k_encode_block
 constexpr uint64_t kTargetWaves = 8192;         // default tiling: binning waves per batch
+constexpr uint32_t kFixBins3 = 16384;           // k_lorenzo_dims, dim 3: bins per workgroup
 
 // Strips per column group for bin factor b as compiled in the binning kernel
 // (0: any b, and batches mixing bin factors).
@@ -47,6 +48,7 @@ struct FrameState {
 // Per-frame constant plan, built on the host and copied to the workspace.
 struct FramePlan {
   uint32_t P, H, W, w, b, mode;
+  uint32_t dim;             // Lorenzo dimension: 1, 2 or 3
   double eb, step;          // step = 2*eb
   uint32_t Hb, Wb, nbins, nchunks;
   uint32_t npeaks, TH, segs, groups;   // segments per panel, workgroups per panel
@@ -62,6 +64,9 @@ struct FramePlan {
   uint64_t off_roi, off_lens, off_chunks, off_bits;
   uint8_t *codes;           // nbins code bytes (r + 128, or 0: see rbuf)
   int32_t *rbuf;            // nbins, residual of bins whose code byte is 0
+  uint8_t *codes2;          // where k_bin writes its code bytes and residuals:
+  int32_t *rbuf2;           // codes / rbuf, except for dim 3 (own buffers of
+                            // the 2D residuals, differenced by k_lorenzo_dims)
   uint32_t *obuf;           // nbins, outlier bin indices in stream order
   uint32_t *chunk_off;      // nchunks: bit count, then bit offset of each chunk
   uint32_t *chunk_oo;       // nchunks: outlier count, then outlier offset
@@ -69,6 +74,8 @@ struct FramePlan {
   uint32_t *bstart;         // P*segs+1 starts of the peak bands: band k =
                             // (panel k / segs, raw rows [(k % segs)*TH*b, +TH*b))
   uint32_t *bucket;         // npeaks peaks as (row << 16 | col), grouped by band
+  int32_t *qedge;           // dim 1: q of the last bin of each of the P*Hb bin
+                            // rows (those k_lorenzo_dims reads), else null
   FrameState *st;
   uint64_t *res_bytes;      // where to report the size (device)
   int32_t *res_status;      // where to report the status (device)
@@ -85,16 +92,20 @@ struct BatchPlan {
   uint32_t total_tiles, total_units, total_peaks, total_chunks;
   uint32_t cpw;                  // chunks encoded by one k_encode workgroup
   uint32_t enc_block;            // small batch: a workgroup packs one chunk at a time
+  uint32_t total_fix;            // workgroups of k_lorenzo_dims (0: every frame is 2D)
   const FramePlan *frames;
   const uint32_t *tile_prefix;   // nframes + 1
   const uint32_t *unit_prefix;   // nframes + 1 (units of cpw chunks)
   const uint32_t *peak_prefix;   // nframes + 1
   const uint32_t *chunk_prefix;  // nframes + 1
+  const uint32_t *fix_prefix;    // nframes + 1 (k_lorenzo_dims workgroups)
 };
 
 // Launchers (compress.hip).
-// k_prep + k_bin + k_codebook; b = common bin factor of the batch, or 0.
-hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, hipStream_t s, bool debug);
+// k_prep + k_bin (+ k_lorenzo_dims) + k_codebook; b and dim: the common bin
+// factor and Lorenzo dimension of the batch, or 0 when its frames differ.
+hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t dim, hipStream_t s,
+                                   bool debug);
 hipError_t launch_debug_codes(const BatchPlan &bp, uint32_t nbins, uint16_t *out, hipStream_t s);
 hipError_t launch_codebook(const BatchPlan &bp, hipStream_t s);
 // k_count + k_scan + k_encode + k_tail + k_roi.
@@ -102,7 +113,7 @@ hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s);
 
 // Decompression plan and launchers (decompress.hip).
 struct DecodePlan {
-  uint32_t P, H, W, w, b, npeaks;
+  uint32_t P, H, W, w, b, npeaks, dim;
   double step;
   uint32_t Hb, Wb, nbins, nchunks, n_out;
   uint64_t T, total;
@@ -111,6 +122,7 @@ struct DecodePlan {
   float *frame;
   int32_t *res;         // nbins
   uint32_t *zcount;     // nchunks code-0 counts
+  uint32_t *carry;      // dim 1: P*Hb row carries
   int32_t *status;      // one word
   uint32_t *tables;     // decode tables
 };

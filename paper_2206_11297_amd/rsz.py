@@ -33,7 +33,7 @@ class RszError(RuntimeError):
 class rsz_params(C.Structure):
     _fields_ = [("panels", C.c_uint32), ("height", C.c_uint32), ("width", C.c_uint32),
                 ("window", C.c_uint32), ("bin", C.c_uint32), ("bin_mode", C.c_uint32),
-                ("eb", C.c_double)]
+                ("eb", C.c_double), ("dim", C.c_uint32)]
 
 
 class rsz_frame_desc(C.Structure):
@@ -98,8 +98,8 @@ def status_string(status):
     return lib().rsz_status_string(int(status)).decode()
 
 
-def params(panels, height, width, window, bin, eb, bin_mode=RSZ_BIN_BACKGROUND):
-    return rsz_params(panels, height, width, window, bin, bin_mode, float(eb))
+def params(panels, height, width, window, bin, eb, bin_mode=RSZ_BIN_BACKGROUND, dim=2):
+    return rsz_params(panels, height, width, window, bin, bin_mode, float(eb), dim)
 
 
 # ------------------------------------------------------------ C ABI mirrors
@@ -267,12 +267,13 @@ def workspace(nbytes, device=None):
 
 
 def compress(frame, peaks, window=17, bin=2, eb=10.0, bin_mode=RSZ_BIN_BACKGROUND, out=None,
-             ws=None):
-    """Compress one GPU frame; returns the stream as a uint8 GPU tensor."""
+             ws=None, dim=2):
+    """Compress one GPU frame; returns the stream as a uint8 GPU tensor.
+    dim: Lorenzo predictor dimension (1, 2 or 3)."""
     torch = _torch()
     frame, peaks = _check_frame(frame, peaks)
     P, H, W = frame.shape
-    p = params(P, H, W, window, bin, eb, bin_mode)
+    p = params(P, H, W, window, bin, eb, bin_mode, dim)
     npk = peaks.shape[0]
     st, cap = rsz_max_compressed_bytes(p, npk)
     if st:
@@ -314,12 +315,13 @@ def decompress(stream, ws=None):
     return frame
 
 
-def debug_intermediates(frame, peaks, window=17, bin=2, eb=10.0, bin_mode=RSZ_BIN_BACKGROUND):
+def debug_intermediates(frame, peaks, window=17, bin=2, eb=10.0, bin_mode=RSZ_BIN_BACKGROUND,
+                        dim=2):
     """All intermediates of compressing one frame as GPU tensors (dict)."""
     torch = _torch()
     frame, peaks = _check_frame(frame, peaks)
     P, H, W = frame.shape
-    p = params(P, H, W, window, bin, eb, bin_mode)
+    p = params(P, H, W, window, bin, eb, bin_mode, dim)
     npk = peaks.shape[0]
     Hb, Wb = -(-H // bin), -(-W // bin)
     nb = P * Hb * Wb
@@ -348,8 +350,8 @@ class Batch:
     """Descriptors, output buffers and workspace for one batched launch.
 
     frames: list of float32 [P,H,W] GPU tensors; peaks: list of int32 [n,3]
-    GPU tensors; params: list of (window, bin, eb, bin_mode) per frame or one
-    tuple for all.  Output buffers are sized by rsz_max_compressed_bytes and
+    GPU tensors; params: list of (window, bin, eb, bin_mode[, dim]) per frame
+    or one tuple for all (dim, the Lorenzo dimension, defaults to 2).  Output buffers are sized by rsz_max_compressed_bytes and
     packed into one uint8 tensor."""
 
     def __init__(self, frames, peaks, prm, tile_rows=0, tile_strips=0):
@@ -360,9 +362,9 @@ class Batch:
         prm = prm if isinstance(prm, list) else [prm] * n
         self.params = []
         caps = []
-        for f, pk, (w, b, eb, mode) in zip(self.frames, self.peaks, prm):
+        for f, pk, t in zip(self.frames, self.peaks, prm):
             P, H, W = f.shape
-            p = params(P, H, W, w, b, eb, mode)
+            p = params(P, H, W, *t)
             st, cap = rsz_max_compressed_bytes(p, pk.shape[0])
             if st:
                 raise RszError(st, "rsz_max_compressed_bytes")

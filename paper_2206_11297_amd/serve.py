@@ -24,7 +24,7 @@ class Request:
     arrival: float          # seconds since the start of the run
     frame: object           # float32 [P,H,W] device tensor (GPU executor)
     peaks: object           # int32 [n,3] device tensor
-    params: tuple           # (window, bin, eb, bin_mode)
+    params: tuple           # (window, bin, eb, bin_mode[, dim])
     out_cap: int = 0        # worst-case stream bytes (set by the executor)
     ws_bytes: int = 0       # workspace share (bound used by admission, set by the executor)
     raw_bytes: int = 0
@@ -157,9 +157,8 @@ class GpuExecutor:
 
     def size_request(self, r: Request):
         rsz = self.rsz
-        w, b, eb, mode = r.params
         P, H, W = r.frame.shape
-        p = rsz.params(P, H, W, w, b, eb, mode)
+        p = rsz.params(P, H, W, *r.params)
         npk = r.peaks.shape[0]
         st, cap = rsz.rsz_max_compressed_bytes(p, npk)
         if st:
@@ -180,10 +179,9 @@ class GpuExecutor:
         descs, off = [], 0
         base = self.out[slot].data_ptr()
         for r in batch:
-            w, b, eb, mode = r.params
             P, H, W = r.frame.shape
             d = rsz.rsz_frame_desc()
-            d.params = rsz.params(P, H, W, w, b, eb, mode)
+            d.params = rsz.params(P, H, W, *r.params)
             d.frame = r.frame.data_ptr()
             d.peaks = r.peaks.data_ptr() if r.peaks.shape[0] else None
             d.npeaks = r.peaks.shape[0]

@@ -69,8 +69,8 @@ def _check_headers(B, sizes, shape, w, b, eb, counts):
         assert d["stream_bytes"] == int(sizes[i]) == d["off"]["total"], f"frame {i}"
 
 
-def _check_oracle(B, sizes, host, idx, shape, w, b, eb):
-    p = O.params(*shape, w, b, eb, 0)
+def _check_oracle(B, sizes, host, idx, shape, w, b, eb, dim=2):
+    p = O.params(*shape, w, b, eb, 0, dim)
     for i in idx:
         print(f"  oracle frame {i} ({host[i][1].shape[0]} peaks)", flush=True)
         st, ref, _ = O.compress(p, *host[i])
@@ -103,6 +103,24 @@ def test_cspad_batch_1000_every_bound(torch, cspad_1000, eb):
     counts = [p.shape[0] for _, p in host]
     _check_oracle(B, sizes, host, _sample(counts, 16, eb), (32, 185, 388), 17, 2, eb)
     _check_headers(B, sizes, (32, 185, 388), 17, 2, eb, counts)
+
+
+@pytest.mark.parametrize("dim", [1, 3])
+def test_cspad_batch_1000_lorenzo_dims(torch, cspad_1000, dim):
+    host, frames, peaks = cspad_1000
+    print(f"cspad batch 1000 dim={dim}", flush=True)
+    B = rsz.Batch(frames, peaks, (17, 2, 10.0, 0, dim))
+    B.run()
+    torch.cuda.synchronize()
+    assert (B.status.cpu().numpy() == 0).all()
+    sizes = B.sizes.cpu().numpy()
+    counts = [p.shape[0] for _, p in host]
+    _check_oracle(B, sizes, host, _sample(counts, 8, 100 + dim), (32, 185, 388), 17, 2, 10.0, dim)
+    _check_headers(B, sizes, (32, 185, 388), 17, 2, 10.0, counts)
+    heads = B.out.view(-1).cpu().numpy()
+    for i in range(len(counts)):
+        flags = int(heads[B.offsets[i] + 6]) | int(heads[B.offsets[i] + 7]) << 8
+        assert flags == dim << 1, f"frame {i}"
 
 
 # ------------------------------------------------------ Jungfrau-4M x 256
