@@ -23,6 +23,8 @@
  *     a volume).  Every constant the paper leaves open is a reading listed in the
  *     design notes (radius 512, chunk 4096, tie-breaks, container layout).
  *   - Compression ratio is relative to raw uint16 detector bytes (Sec. IV).
+ *   - The peak list can also come from the peak finder at the end of this
+ *     file (Sec. V-A's peak_finder_v3 parameters), the step before the path.
  *
  * Arithmetic: fp64 sums in raster order, a correctly rounded divide and
  * rint() (round half to even).  Build with -ffp-contract=off and without
@@ -744,4 +746,145 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
   }
   free(pk); free(res); free(cd);
   return bad ? RO_ERR_CORRUPT : RO_OK;
+}
+
+/* ------------------------------------------------------------ peak finding */
+
+/* Peak finder feeding the ROI mask (the step before the path: Sec. V-A names
+ * the algorithm and its parameters; Sec. II and Sec. IV-B the non-hit
+ * rejection that counts its peaks).  Readings where the text is loose:
+ *   - local maximum: the pixel is >= every pixel of its (2h+1)^2 window
+ *     (clipped to the panel) and > every one before it in raster order, so
+ *     a plateau yields its first pixel;
+ *   - background: mean mu and population variance V/m of the m pixels whose
+ *     Chebyshev distance from the maximum lies in [ring_in, ring_out],
+ *     clipped to the panel (two passes, raster order); no such pixel, no
+ *     peak;
+ *   - peak pixels ("neighbouring pixels above 0 ADU"): the pixels of the
+ *     window 4-connected to the maximum through pixels x with x - mu >
+ *     pix_nsigma * sigma (pix_nsigma = 0 is the text taken relative to the
+ *     background; on noisy frames half of the background would then count);
+ *   - total intensity: the sum S of the peak pixels (raster order); signal
+ *     to noise: (S - n mu) / (sigma sqrt(n)).
+ * Square roots are avoided by comparing squares of non-negative sides:
+ * d > k sigma  <=>  d > 0 and d*d*m > k*k*V  (and the same for the SNR). */
+typedef struct {
+  uint32_t rank;                /* h: window (2h+1) x (2h+1), 1..3 (3: 7x7)   */
+  uint32_t ring_in, ring_out;   /* background ring, h < ring_in <= ring_out <= 15 */
+  uint32_t npix_min, npix_max;  /* peak pixel count bounds (2, 30)           */
+  uint32_t reserved;
+  double amax_min;              /* maximum >= amax_min (300 ADU)            */
+  double atot_min;              /* total intensity > atot_min (600 ADU)     */
+  double snr_min;               /* signal to noise > snr_min (10)           */
+  double pix_nsigma;            /* peak pixel cut above the background (3)  */
+} ro_peak_params;
+
+int ro_check_peak_params(const ro_peak_params *q) {
+  if (!q || q->rank < 1 || q->rank > 3 || q->ring_in <= q->rank || q->ring_out < q->ring_in ||
+      q->ring_out > 15 || q->npix_min > q->npix_max || q->reserved != 0)
+    return RO_ERR_ARG;
+  if (!isfinite(q->amax_min) || !isfinite(q->atot_min) || !isfinite(q->snr_min) ||
+      !(q->snr_min >= 0.0) || !isfinite(q->pix_nsigma) || !(q->pix_nsigma >= 0.0))
+    return RO_ERR_ARG;
+  return RO_OK;
+}
+
+/* Decision for the local maximum at (i, j) of panel x (H x W). */
+static int ro_peak_accept(const ro_peak_params *q, const float *x, int64_t H, int64_t W,
+                          int64_t i, int64_t j) {
+  const int64_t h = q->rank, ww = 2 * h + 1;
+  /* background ring */
+  double sum = 0.0;
+  int64_t m = 0;
+  for (int64_t u = i - (int64_t)q->ring_out; u <= i + (int64_t)q->ring_out; ++u)
+    for (int64_t v = j - (int64_t)q->ring_out; v <= j + (int64_t)q->ring_out; ++v) {
+      const int64_t d = llabs(u - i) > llabs(v - j) ? llabs(u - i) : llabs(v - j);
+      if (u < 0 || u >= H || v < 0 || v >= W || d < (int64_t)q->ring_in) continue;
+      sum += (double)x[u * W + v];
+      m++;
+    }
+  if (m == 0) return 0;
+  const double mu = sum / (double)m;
+  double V = 0.0;
+  for (int64_t u = i - (int64_t)q->ring_out; u <= i + (int64_t)q->ring_out; ++u)
+    for (int64_t v = j - (int64_t)q->ring_out; v <= j + (int64_t)q->ring_out; ++v) {
+      const int64_t d = llabs(u - i) > llabs(v - j) ? llabs(u - i) : llabs(v - j);
+      if (u < 0 || u >= H || v < 0 || v >= W || d < (int64_t)q->ring_in) continue;
+      const double e = (double)x[u * W + v] - mu;
+      V += e * e;
+    }
+  const double k2V = q->pix_nsigma * q->pix_nsigma * V;
+  /* window pixels above the cut, then the 4-connected component of the
+   * maximum by repeated growth over the 7x7 (at most) grid */
+  int above[7][7], comp[7][7];
+  for (int64_t a = 0; a < ww; ++a)
+    for (int64_t b = 0; b < ww; ++b) {
+      const int64_t u = i - h + a, v = j - h + b;
+      above[a][b] = 0;
+      comp[a][b] = 0;
+      if (u < 0 || u >= H || v < 0 || v >= W) continue;
+      const double d = (double)x[u * W + v] - mu;
+      above[a][b] = d > 0.0 && d * d * (double)m > k2V;
+    }
+  comp[h][h] = above[h][h];
+  for (int changed = 1; changed;) {
+    changed = 0;
+    for (int64_t a = 0; a < ww; ++a)
+      for (int64_t b = 0; b < ww; ++b) {
+        if (comp[a][b] || !above[a][b]) continue;
+        if ((a > 0 && comp[a - 1][b]) || (a + 1 < ww && comp[a + 1][b]) ||
+            (b > 0 && comp[a][b - 1]) || (b + 1 < ww && comp[a][b + 1])) {
+          comp[a][b] = 1;
+          changed = 1;
+        }
+      }
+  }
+  double S = 0.0;
+  int64_t n = 0;
+  for (int64_t a = 0; a < ww; ++a)
+    for (int64_t b = 0; b < ww; ++b)
+      if (comp[a][b]) {
+        S += (double)x[(i - h + a) * W + (j - h + b)];
+        n++;
+      }
+  if (n < (int64_t)q->npix_min || n > (int64_t)q->npix_max) return 0;
+  if (!(S > q->atot_min)) return 0;
+  const double num = S - (double)n * mu;
+  return num > 0.0 && num * num * (double)m > q->snr_min * q->snr_min * (double)n * V;
+}
+
+/* Peaks of a panels x height x width frame, in raster order (panel, row,
+ * col), as int32 triples in peaks[0 .. min(count, cap)); returns the count
+ * (which may exceed cap). */
+uint64_t ro_find_peaks(const ro_peak_params *q, uint32_t P, uint32_t H, uint32_t W,
+                       const float *frame, int32_t *peaks, uint64_t cap) {
+  const int64_t h = q->rank;
+  uint64_t cnt = 0;
+  for (int64_t p = 0; p < P; ++p) {
+    const float *x = frame + (uint64_t)p * H * W;
+    for (int64_t i = 0; i < H; ++i)
+      for (int64_t j = 0; j < W; ++j) {
+        const float c = x[i * W + j];
+        if (!((double)c >= q->amax_min)) continue;
+        int ismax = 1;
+        for (int64_t u = i - h; u <= i + h && ismax; ++u)
+          for (int64_t v = j - h; v <= j + h; ++v) {
+            if (u < 0 || u >= H || v < 0 || v >= W || (u == i && v == j)) continue;
+            const float o = x[u * W + v];
+            const int before = u < i || (u == i && v < j);
+            if (before ? !(o < c) : !(o <= c)) {
+              ismax = 0;
+              break;
+            }
+          }
+        if (!ismax || !ro_peak_accept(q, x, H, W, i, j)) continue;
+        if (cnt < cap) {
+          peaks[3 * cnt] = (int32_t)p;
+          peaks[3 * cnt + 1] = (int32_t)i;
+          peaks[3 * cnt + 2] = (int32_t)j;
+        }
+        cnt++;
+      }
+  }
+  return cnt;
 }

@@ -21,6 +21,19 @@ class Params(C.Structure):
                 ("eb", C.c_double), ("dim", C.c_uint32)]
 
 
+class PeakParams(C.Structure):
+    _fields_ = [("rank", C.c_uint32), ("ring_in", C.c_uint32), ("ring_out", C.c_uint32),
+                ("npix_min", C.c_uint32), ("npix_max", C.c_uint32), ("reserved", C.c_uint32),
+                ("amax_min", C.c_double), ("atot_min", C.c_double), ("snr_min", C.c_double),
+                ("pix_nsigma", C.c_double)]
+
+
+def peak_params(rank=3, ring_in=4, ring_out=5, npix_min=2, npix_max=30, amax_min=300.0,
+                atot_min=600.0, snr_min=10.0, pix_nsigma=3.0):
+    return PeakParams(rank, ring_in, ring_out, npix_min, npix_max, 0, amax_min, atot_min,
+                      snr_min, pix_nsigma)
+
+
 _lib = None
 
 
@@ -40,6 +53,10 @@ def lib():
         L.ro_stream_info.argtypes = [vp, C.c_uint64, P(Params), P(C.c_uint32), P(C.c_uint64)]
         L.ro_huffman_lengths.argtypes = [vp, vp]
         L.ro_canonical.argtypes = [vp, vp]
+        L.ro_check_peak_params.argtypes = [P(PeakParams)]
+        L.ro_find_peaks.argtypes = [P(PeakParams), C.c_uint32, C.c_uint32, C.c_uint32, vp, vp,
+                                    C.c_uint64]
+        L.ro_find_peaks.restype = C.c_uint64
         _lib = L
     return _lib
 
@@ -148,3 +165,16 @@ def canonical(lens):
     cw = np.zeros(NSYM, np.uint32)
     lib().ro_canonical(_ptr(lens), _ptr(cw))
     return cw
+
+
+def check_peak_params(q):
+    return lib().ro_check_peak_params(C.byref(q))
+
+
+def find_peaks(q, frame, cap=1 << 16):
+    """Peaks of a float32 [P,H,W] frame in raster order: (int32 [min(n,cap),3], n)."""
+    frame = np.ascontiguousarray(frame, dtype=np.float32)
+    P, H, W = frame.shape
+    out = np.zeros((max(cap, 1), 3), np.int32)
+    n = lib().ro_find_peaks(C.byref(q), P, H, W, _ptr(frame), _ptr(out), cap)
+    return out[:min(n, cap)].copy(), n
