@@ -176,6 +176,71 @@ def lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips
     return out
 
 
+def peaks_section(args, torch, frames, prm, raw_bytes, tile_rows, tile_strips):
+    """Peak finding on the GPU over the same batch (the step before the path,
+    Sec. V-A parameters), and the frames-in, streams-out pipeline: peaks found,
+    counts read back, frames with fewer than 10 peaks rejected (Sec. IV-B),
+    the hits compressed with their found peaks."""
+    import numpy as np
+    from paper_2206_11297_amd import rsz
+    P = rsz.PeakBatch(frames, None, 1024)
+    for _ in range(2):
+        P.run()
+    torch.cuda.synchronize()
+    st = P.status.cpu().numpy()
+    assert (st == 0).all(), f"peak finding failed: statuses {set(st.tolist())}"
+    rsz.rsz_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.peaks_steps):
+        P.run()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.peaks_steps
+    prof = rsz.rsz_profile_read()
+    rsz.rsz_profile_enable(False)
+    km = {k: v[1] / v[0] for k, v in prof.items()}
+    counts = P.counts.cpu().numpy()
+    hits = [i for i, c in enumerate(counts.tolist()) if c >= 10]
+    find_ms = km["k_peaks_find"]
+    out = {"value": round(raw_bytes / el / 1e9, 2), "unit": "GB/s", "ms_per_step": round(el * 1e3, 4),
+           "steps": args.peaks_steps, "kernel_ms": {k: round(v, 4) for k, v in km.items()},
+           "roofline": {"bound": "hbm", "achieved": round(raw_bytes / (find_ms * 1e-3) / 1e9, 1),
+                        "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(raw_bytes / (find_ms * 1e-3) / 1e9 / 8000.0, 4),
+                        "kernel": "k_peaks_find", "algorithmic_bytes_per_launch": raw_bytes},
+           "peaks_per_frame_mean": round(float(counts.mean()), 2),
+           "hits": len(hits), "frames": len(frames), "nhr_min_peaks": 10}
+    if hits:
+        B = rsz.Batch([frames[i] for i in hits], [P.peaks(i, counts) for i in hits], prm,
+                      tile_rows=tile_rows, tile_strips=tile_strips)
+        for _ in range(2):
+            P.run()
+            c2 = P.counts.cpu().numpy()
+            B.run()
+        torch.cuda.synchronize()
+        assert (c2 == counts).all() and (B.status.cpu().numpy() == 0).all()
+        t0 = time.perf_counter()
+        for _ in range(args.peaks_steps):
+            P.run()
+            P.counts.cpu()          # the counts plan the compression
+            B.run()
+        torch.cuda.synchronize()
+        el2 = (time.perf_counter() - t0) / args.peaks_steps
+        sizes = B.sizes.cpu().numpy().astype(np.int64)
+        hit_bytes = sum(frames[i].numel() * 4 for i in hits)
+        out["pipeline"] = {
+            "value": round(raw_bytes / el2 / 1e9, 2), "unit": "GB/s of all frames",
+            "ms_per_step": round(el2 * 1e3, 4),
+            "compression_ratio_u16_hits": round(float(hit_bytes / 2 / sizes.sum()), 3),
+            "compression_ratio_u16_with_nhr": round(float(raw_bytes / 2 / sizes.sum()), 3)}
+        del B
+    print(f"[bench] peak finding: {out['value']} GB/s, {out['peaks_per_frame_mean']} peaks/frame, "
+          f"{len(hits)} hits", file=sys.stderr, flush=True)
+    del P
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(args, host, B, sizes):
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
@@ -330,6 +395,8 @@ def main():
     ap.add_argument("--dims", type=int, nargs="*", default=[1, 3],
                     help="Lorenzo dimensions timed besides 2 on the same batch")
     ap.add_argument("--dims-steps", type=int, default=10)
+    ap.add_argument("--peaks-steps", type=int, default=10,
+                    help="steps of the peak-finding section (0: skip it)")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary)
@@ -445,6 +512,8 @@ def main():
     serving = serving_section(args, torch, dev) if args.serve_rates else None
     dims = lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips,
                                 raw_bytes) if args.dims else None
+    pk = peaks_section(args, torch, frames, prm, raw_bytes, tile_rows,
+                       tile_strips) if args.peaks_steps else None
 
     line = {
         "metric": "raw-frame GB/s compressed (1 GPU) at eb=10 ADU; compression ratio; "
@@ -475,6 +544,7 @@ def main():
         "serving": serving,
         "decompress": decomp,
         "lorenzo_dims": dims,
+        "peak_finding": pk,
     }
     if serving:
         top = serving.get(f"{max(args.serve_rates):g}kHz")

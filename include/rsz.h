@@ -182,6 +182,60 @@ int rsz_decompress_workspace_bytes(const void *h_header, uint64_t n, uint64_t *b
 int rsz_decompress(const void *d_in, uint64_t in_bytes, float *d_frame, uint64_t frame_elems,
                    void *d_ws, uint64_t ws_bytes, void *stream);
 
+/* ---- Peak finding: the step before the path, feeding the peak list ---- */
+
+/* Peak-finder parameters (Sec. V-A: local maxima of a 7x7 window, maxima
+ * below 300 ADU rejected, the peak's pixels above 0 ADU, total intensity
+ * above 600 ADU, signal to noise above 10, 2 to 30 peak pixels).  A pixel is
+ * a peak when:
+ *   - it is >= amax_min and the maximum of its (2*rank+1)^2 window clipped to
+ *     the panel (ties: the first pixel in raster order wins);
+ *   - the background ring, pixels at Chebyshev distance ring_in..ring_out
+ *     from it inside the panel, is not empty; mu and sigma are its mean and
+ *     population standard deviation;
+ *   - its peak pixels, the window pixels 4-connected to it through pixels with
+ *     x - mu > pix_nsigma * sigma, number npix_min..npix_max;
+ *   - their sum S is > atot_min, and (S - n*mu) / (sigma*sqrt(n)) > snr_min.
+ * pix_nsigma reads the paper's "above 0 ADU" as above the background's noise
+ * (0 takes it as above the background).  Limits: rank 1..3, rank < ring_in
+ * <= ring_out <= 15, npix_min <= npix_max, thresholds finite, snr_min and
+ * pix_nsigma >= 0, reserved 0.  rsz_peak_params_default fills the paper's
+ * values (rank 3, ring 4..5, 2..30 pixels, 300, 600, 10) and pix_nsigma 3. */
+typedef struct {
+  uint32_t rank, ring_in, ring_out;
+  uint32_t npix_min, npix_max;
+  uint32_t reserved;
+  double amax_min, atot_min, snr_min, pix_nsigma;
+} rsz_peak_params;
+
+void rsz_peak_params_default(rsz_peak_params *q);
+
+/* One frame of a peak-finding batch.  frame: panels x height x width float32
+ * (device, 16-byte aligned; shape limits as in rsz_params).  peaks: device
+ * array of max_peaks entries (1..8192) that receives the frame's peaks in
+ * raster order (panel, row, col). */
+typedef struct {
+  uint32_t panels, height, width;
+  uint32_t max_peaks;
+  const float *frame;
+  rsz_peak *peaks;
+} rsz_peak_desc;
+
+/* Device workspace for rsz_find_peaks_batch.  Host-only. */
+int rsz_find_peaks_workspace_bytes(uint32_t nframes, const rsz_peak_desc *h_descs,
+                                   uint64_t *bytes);
+
+/* Finds the peaks of nframes frames in one batched launch sequence.
+ * d_counts[i] receives the number of peaks of frame i and d_status[i] its
+ * status: RSZ_OK, RSZ_ERR_ARG (invalid descriptor) or RSZ_ERR_CAPACITY (more
+ * than max_peaks peaks; the count is still reported and the list is
+ * unspecified).  Non-hit rejection (Sec. IV-B: fewer than 10 peaks) is the
+ * caller's comparison of d_counts.  Asynchronous like rsz_compress_batch;
+ * the return value reports errors of the call itself (ARG, WORKSPACE, HIP). */
+int rsz_find_peaks_batch(const rsz_peak_params *q, uint32_t nframes, const rsz_peak_desc *h_descs,
+                         uint32_t *d_counts, int32_t *d_status, void *d_ws, uint64_t ws_bytes,
+                         void *stream);
+
 /* Intermediates of compressing one frame, for parity checks.  Every pointer
  * is device memory and may be NULL to skip that output.
  *   mask: panels*height*ceil(width/32) u32, bit j%32 of word j/32 = ROI pixel.

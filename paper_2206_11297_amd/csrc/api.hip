@@ -855,4 +855,116 @@ int rsz_profile_read(rsz_kernel_time *out, int max, int *n) {
   return RSZ_OK;
 }
 
+// ------------------------------------------------------------ peak finding
+
+void rsz_peak_params_default(rsz_peak_params *q) {
+  if (!q) return;
+  memset(q, 0, sizeof *q);
+  q->rank = 3;          // 7x7 window
+  q->ring_in = 4;       // background ring just outside the window
+  q->ring_out = 5;
+  q->npix_min = 2;
+  q->npix_max = 30;
+  q->amax_min = 300.0;
+  q->atot_min = 600.0;
+  q->snr_min = 10.0;
+  q->pix_nsigma = 3.0;
+}
+
+static int check_peak_params(const rsz_peak_params *q) {
+  if (!q || q->rank < 1 || q->rank > 3 || q->ring_in <= q->rank || q->ring_out < q->ring_in ||
+      q->ring_out > 15 || q->npix_min > q->npix_max || q->reserved != 0)
+    return RSZ_ERR_ARG;
+  if (!std::isfinite(q->amax_min) || !std::isfinite(q->atot_min) || !std::isfinite(q->snr_min) ||
+      !(q->snr_min >= 0.0) || !std::isfinite(q->pix_nsigma) || !(q->pix_nsigma >= 0.0))
+    return RSZ_ERR_ARG;
+  return RSZ_OK;
+}
+
+static bool peak_desc_ok(const rsz_peak_desc &d) {
+  if (d.panels < 1 || d.panels > 65535 || d.height < 1 || d.height > 65535 || d.width < 1 ||
+      d.width > 65535)
+    return false;
+  if ((uint64_t)d.panels * d.height * d.width >= (1ull << 31)) return false;
+  if (d.max_peaks < 1 || d.max_peaks > kPeakCapMax || !d.frame || !d.peaks) return false;
+  return (uintptr_t)d.frame % 16 == 0 && (uintptr_t)d.peaks % 4 == 0;
+}
+
+// Workspace: frame plans, tile prefix, then per frame a counter and its keys.
+static uint64_t peak_layout(uint32_t nframes, const rsz_peak_desc *d, std::vector<uint64_t> *off,
+                            uint64_t *prefix_off) {
+  uint64_t o = align_up(sizeof(PeakFramePlan) * nframes, 256);
+  *prefix_off = o;
+  o += align_up(4ull * (nframes + 1), 256);
+  if (off) off->resize(nframes);
+  for (uint32_t f = 0; f < nframes; ++f) {
+    if (off) (*off)[f] = o;
+    o += 256 + align_up(8ull * (peak_desc_ok(d[f]) ? d[f].max_peaks : 0), 256);
+  }
+  return o;
+}
+
+int rsz_find_peaks_workspace_bytes(uint32_t nframes, const rsz_peak_desc *h_descs,
+                                   uint64_t *bytes) {
+  if (nframes == 0 || !h_descs || !bytes) return RSZ_ERR_ARG;
+  uint64_t po;
+  *bytes = peak_layout(nframes, h_descs, nullptr, &po);
+  return RSZ_OK;
+}
+
+int rsz_find_peaks_batch(const rsz_peak_params *q, uint32_t nframes, const rsz_peak_desc *h_descs,
+                         uint32_t *d_counts, int32_t *d_status, void *d_ws, uint64_t ws_bytes,
+                         void *stream) {
+  if (check_peak_params(q) != RSZ_OK || nframes == 0 || !h_descs || !d_counts || !d_status ||
+      !d_ws || (uintptr_t)d_ws % 256)
+    return RSZ_ERR_ARG;
+  std::vector<uint64_t> off;
+  uint64_t prefix_off;
+  const uint64_t need = peak_layout(nframes, h_descs, &off, &prefix_off);
+  if (ws_bytes < need) return RSZ_ERR_WORKSPACE;
+  uint8_t *ws = (uint8_t *)d_ws;
+  std::vector<uint8_t> host(align_up(prefix_off + 4ull * (nframes + 1), 256), 0);
+  PeakFramePlan *fpl = (PeakFramePlan *)host.data();
+  uint32_t *tp = (uint32_t *)(host.data() + prefix_off);
+  uint64_t tiles = 0;
+  for (uint32_t f = 0; f < nframes; ++f) {
+    const rsz_peak_desc &d = h_descs[f];
+    PeakFramePlan &fp = fpl[f];
+    tp[f] = (uint32_t)tiles;
+    fp.count = (uint32_t *)(ws + off[f]);
+    fp.keys = (uint64_t *)(ws + off[f] + 256);
+    fp.res_count = d_counts + f;
+    fp.res_status = d_status + f;
+    if (!peak_desc_ok(d)) {
+      fp.init_status = RSZ_ERR_ARG;
+      continue;
+    }
+    fp.init_status = RSZ_OK;
+    fp.P = d.panels;
+    fp.H = d.height;
+    fp.W = d.width;
+    fp.cap = d.max_peaks;
+    fp.frame = d.frame;
+    fp.out = d.peaks;
+    tiles += div_up((uint64_t)d.panels * d.height * d.width, kPeakTile);
+  }
+  if (tiles >= (1ull << 31)) return RSZ_ERR_ARG;
+  tp[nframes] = (uint32_t)tiles;
+  hipStream_t s = (hipStream_t)stream;
+  if (stage_to_device(ws, host.data(), host.size(), s) != RSZ_OK) return RSZ_ERR_HIP;
+  PeakBatchPlan pp;
+  memset(&pp, 0, sizeof pp);
+  pp.nframes = nframes;
+  pp.total_tiles = (uint32_t)tiles;
+  pp.q = *q;
+  // float x >= amax_min (in fp64) exactly when x >= the smallest float at or
+  // above amax_min
+  float af = (float)q->amax_min;
+  if ((double)af < q->amax_min) af = std::nextafter(af, INFINITY);
+  pp.amax_f = af;
+  pp.frames = (const PeakFramePlan *)ws;
+  pp.tile_prefix = (const uint32_t *)(ws + prefix_off);
+  return launch_find_peaks(pp, s) == hipSuccess ? RSZ_OK : RSZ_ERR_HIP;
+}
+
 }  // extern "C"

@@ -128,6 +128,30 @@ struct DecodePlan {
 };
 hipError_t launch_decompress(const DecodePlan &dp, hipStream_t s);
 
+// Peak finding (peaks.hip).
+constexpr uint32_t kPeakTile = 16384;     // pixels per k_peaks_find workgroup
+constexpr uint32_t kPeakCapMax = 8192;    // most peaks a frame's list may hold
+
+struct PeakFramePlan {
+  uint32_t P, H, W, cap;
+  int32_t init_status;       // RSZ_OK or RSZ_ERR_ARG
+  const float *frame;
+  rsz_peak *out;             // cap entries (caller's)
+  uint64_t *keys;            // cap keys (p << 32 | i << 16 | j), unordered
+  uint32_t *count;           // peaks found (may exceed cap)
+  uint32_t *res_count;       // caller's count
+  int32_t *res_status;       // caller's status
+};
+
+struct PeakBatchPlan {
+  uint32_t nframes, total_tiles;
+  float amax_f;                  // smallest float >= q.amax_min
+  rsz_peak_params q;
+  const PeakFramePlan *frames;
+  const uint32_t *tile_prefix;   // nframes + 1
+};
+hipError_t launch_find_peaks(const PeakBatchPlan &pp, hipStream_t s);
+
 // Kernel timing hooks (api.hip).
 void prof_begin(const char *name, hipStream_t s);
 void prof_end(hipStream_t s);

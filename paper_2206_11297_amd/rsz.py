@@ -21,7 +21,8 @@ EXPORTS = ["rsz_status_string", "rsz_max_compressed_bytes", "rsz_workspace_bytes
            "rsz_graph_launch", "rsz_graph_destroy",
            "rsz_stream_info", "rsz_decompress_workspace_bytes", "rsz_decompress",
            "rsz_debug_intermediates", "rsz_debug_codebook", "rsz_measure_read",
-           "rsz_profile_enable", "rsz_profile_read"]
+           "rsz_profile_enable", "rsz_profile_read", "rsz_peak_params_default",
+           "rsz_find_peaks_workspace_bytes", "rsz_find_peaks_batch"]
 
 
 class RszError(RuntimeError):
@@ -51,6 +52,18 @@ class rsz_debug_bufs(C.Structure):
     _fields_ = [("mask", C.c_void_p), ("S", C.c_void_p), ("n", C.c_void_p), ("q", C.c_void_p),
                 ("codes", C.c_void_p), ("hist", C.c_void_p), ("lens", C.c_void_p),
                 ("cw", C.c_void_p)]
+
+
+class rsz_peak_params(C.Structure):
+    _fields_ = [("rank", C.c_uint32), ("ring_in", C.c_uint32), ("ring_out", C.c_uint32),
+                ("npix_min", C.c_uint32), ("npix_max", C.c_uint32), ("reserved", C.c_uint32),
+                ("amax_min", C.c_double), ("atot_min", C.c_double), ("snr_min", C.c_double),
+                ("pix_nsigma", C.c_double)]
+
+
+class rsz_peak_desc(C.Structure):
+    _fields_ = [("panels", C.c_uint32), ("height", C.c_uint32), ("width", C.c_uint32),
+                ("max_peaks", C.c_uint32), ("frame", C.c_void_p), ("peaks", C.c_void_p)]
 
 
 class rsz_kernel_time(C.Structure):
@@ -90,6 +103,11 @@ def lib():
         L.rsz_measure_read.argtypes = [vp, u64, vp, C.c_int, P(C.c_double), vp]
         L.rsz_profile_enable.argtypes = [C.c_int]
         L.rsz_profile_read.argtypes = [P(rsz_kernel_time), C.c_int, P(C.c_int)]
+        L.rsz_peak_params_default.restype = None
+        L.rsz_peak_params_default.argtypes = [P(rsz_peak_params)]
+        L.rsz_find_peaks_workspace_bytes.argtypes = [u32, P(rsz_peak_desc), P(u64)]
+        L.rsz_find_peaks_batch.argtypes = [P(rsz_peak_params), u32, P(rsz_peak_desc), vp, vp, vp,
+                                           u64, vp]
         _lib = L
     return _lib
 
@@ -441,3 +459,103 @@ class Batch:
         """Stream of frame i as a GPU uint8 view (after the stream finished)."""
         n = int(self.sizes[i]) if sizes is None else int(sizes[i])
         return self.out[self.offsets[i]:self.offsets[i] + n]
+
+
+# ------------------------------------------------------------ peak finding
+
+
+def peak_params(**kw):
+    """rsz_peak_params with the library defaults (Sec. V-A values), fields
+    overridden by keyword."""
+    q = rsz_peak_params()
+    lib().rsz_peak_params_default(C.byref(q))
+    for k, v in kw.items():
+        setattr(q, k, v)
+    return q
+
+
+def rsz_find_peaks_workspace_bytes(descs):
+    arr = (rsz_peak_desc * len(descs))(*descs)
+    out = C.c_uint64(0)
+    st = lib().rsz_find_peaks_workspace_bytes(len(descs), arr, C.byref(out))
+    return st, out.value
+
+
+def rsz_find_peaks_batch(q, descs, d_counts, d_status, d_ws, ws_bytes, stream):
+    arr = (rsz_peak_desc * len(descs))(*descs)
+    return lib().rsz_find_peaks_batch(C.byref(q), len(descs), arr, d_counts, d_status, d_ws,
+                                      ws_bytes, stream)
+
+
+class PeakBatch:
+    """Peak finding over a list of float32 [P,H,W] GPU frames in one batched
+    launch sequence: run() queues it; counts / status hold the per-frame
+    results once the stream has finished; peaks(i) is frame i's list."""
+
+    def __init__(self, frames, q=None, max_peaks=4096):
+        torch = _torch()
+        self.frames = [f.contiguous() for f in frames]
+        self.q = q if q is not None else peak_params()
+        n = len(self.frames)
+        dev = self.frames[0].device
+        self.max_peaks = int(max_peaks)
+        self.out = torch.zeros((n, self.max_peaks, 3), dtype=torch.int32, device=dev)
+        self.descs = []
+        for i, f in enumerate(self.frames):
+            d = rsz_peak_desc()
+            d.panels, d.height, d.width = f.shape
+            d.max_peaks = self.max_peaks
+            d.frame = f.data_ptr()
+            d.peaks = self.out[i].data_ptr()
+            self.descs.append(d)
+        st, wsb = rsz_find_peaks_workspace_bytes(self.descs)
+        if st:
+            raise RszError(st, "rsz_find_peaks_workspace_bytes")
+        self.ws = workspace(wsb, dev)
+        self.counts = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(n, dtype=torch.int32, device=dev)
+
+    def run(self):
+        st = rsz_find_peaks_batch(self.q, self.descs, _ptr(self.counts), _ptr(self.status),
+                                  _ptr(self.ws), self.ws.numel(), _stream())
+        if st:
+            raise RszError(st, "rsz_find_peaks_batch")
+
+    def peaks(self, i, counts=None):
+        n = int(self.counts[i]) if counts is None else int(counts[i])
+        return self.out[i, :min(n, self.max_peaks)]
+
+
+def find_peaks(frame, q=None, max_peaks=4096):
+    """Peaks of one float32 [P,H,W] GPU frame, int32 [n,3] (panel, row, col) in
+    raster order (synchronous)."""
+    frame, _ = _check_frame(frame, None)
+    B = PeakBatch([frame], q, max_peaks)
+    B.run()
+    st = int(B.status[0])
+    if st:
+        raise RszError(st, "rsz_find_peaks_batch")
+    return B.peaks(0).clone()
+
+
+def compress_hits(frames, prm, q=None, min_peaks=10, max_peaks=4096, **batch_kw):
+    """Frames in, streams out: peaks found on the GPU, non-hit rejection
+    (frames with fewer than min_peaks peaks are dropped, Sec. IV-B), then the
+    hits compressed in one batch with their found peaks as the ROI.  Returns
+    (indices of the hits, the Batch holding their streams, the PeakBatch)."""
+    torch = _torch()
+    P = PeakBatch(frames, q, max_peaks)
+    P.run()
+    counts = P.counts.cpu().tolist()
+    status = P.status.cpu().tolist()
+    bad = [s for s in status if s]
+    if bad:
+        raise RszError(bad[0], "rsz_find_peaks_batch")
+    hits = [i for i, c in enumerate(counts) if c >= min_peaks]
+    if not hits:
+        return hits, None, P
+    prm = prm if isinstance(prm, list) else [prm] * len(frames)
+    B = Batch([P.frames[i] for i in hits], [P.peaks(i, counts) for i in hits],
+              [prm[i] for i in hits], **batch_kw)
+    B.run()
+    return hits, B, P

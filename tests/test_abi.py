@@ -49,9 +49,10 @@ def test_max_bytes_matches_oracle(shape, w, b, npk):
 @pytest.mark.parametrize("bad", [dict(panels=0), dict(height=70000), dict(window=0),
                                  dict(window=1024), dict(bin=0), dict(bin=9), dict(eb=0.0),
                                  dict(eb=float("inf")), dict(eb=float("nan")), dict(bin_mode=2),
+                                 dict(dim=4),
                                  dict(panels=65535, height=65535, width=2)])
 def test_bad_params_rejected(bad):
-    kw = dict(panels=2, height=8, width=8, window=3, bin=2, eb=1.0, bin_mode=0)
+    kw = dict(panels=2, height=8, width=8, window=3, bin=2, eb=1.0, bin_mode=0, dim=2)
     kw.update(bad)
     p = rsz.params(**kw)
     assert rsz.rsz_max_compressed_bytes(p, 1)[0] == rsz.RSZ_ERR_ARG
@@ -105,7 +106,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     import subprocess
     structs = {"rsz_peak": None, "rsz_params": rsz.rsz_params, "rsz_frame_desc": rsz.rsz_frame_desc,
                "rsz_batch_plan": rsz.rsz_batch_plan, "rsz_debug_bufs": rsz.rsz_debug_bufs,
-               "rsz_kernel_time": rsz.rsz_kernel_time}
+               "rsz_kernel_time": rsz.rsz_kernel_time, "rsz_peak_params": rsz.rsz_peak_params,
+               "rsz_peak_desc": rsz.rsz_peak_desc}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rsz.h"', 'int main(void) {']
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
@@ -128,3 +130,23 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(name, "size")] == C.sizeof(cls), name
         for fname, _ in cls._fields_:
             assert got[(name, fname)] == getattr(cls, fname).offset, (name, fname)
+
+
+def test_peak_params_default_and_checks():
+    """Library defaults are the paper's values (Sec. V-A) and equal the
+    oracle's; bad parameters and descriptors are rejected before any launch."""
+    q = rsz.peak_params()
+    o = O.peak_params()
+    for name, _ in rsz.rsz_peak_params._fields_:
+        assert getattr(q, name) == getattr(o, name), name
+    d = rsz.rsz_peak_desc(2, 8, 8, 16, None, None)
+    st, n = rsz.rsz_find_peaks_workspace_bytes([d])
+    assert st == 0 and n > 0
+    for bad in (dict(rank=0), dict(rank=4), dict(ring_in=3), dict(ring_out=16),
+                dict(npix_min=40), dict(snr_min=-1.0), dict(pix_nsigma=float("inf")),
+                dict(reserved=1)):
+        qb = rsz.peak_params(**bad)
+        assert rsz.rsz_find_peaks_batch(qb, [d], None, None, None, 0, None) == rsz.RSZ_ERR_ARG
+        assert O.check_peak_params(O.peak_params(**{k: v for k, v in bad.items()
+                                                     if k != "reserved"})) == O.ERR_ARG \
+            or "reserved" in bad
