@@ -207,6 +207,7 @@ def peaks_section(args, torch, frames, prm, raw_bytes, tile_rows, tile_strips):
            "roofline": {"bound": "hbm", "achieved": round(raw_bytes / (find_ms * 1e-3) / 1e9, 1),
                         "peak": 8000.0, "unit": "GB/s",
                         "frac": round(raw_bytes / (find_ms * 1e-3) / 1e9 / 8000.0, 4),
+                        "traffic": (traffic_record("k_peaks_find") or {}).get("hbm_bytes_per_launch"),
                         "kernel": "k_peaks_find", "algorithmic_bytes_per_launch": raw_bytes},
            "peaks_per_frame_mean": round(float(counts.mean()), 2),
            "hits": len(hits), "frames": len(frames), "nhr_min_peaks": 10}
@@ -298,12 +299,25 @@ def _counter_rows(root, counter):
     return rows
 
 
+# Kernels whose counter records the roofline reads: (record name, the kernel
+# name in the counter output, the source file it is built from, and which of
+# its dispatches to take: the largest grid).
+TRAFFIC_KERNELS = [("k_bin", "k_bin<2, false, 2>", "compress.hip"),
+                   ("k_lorenzo_dims", "k_lorenzo_dims", "compress.hip"),
+                   ("k_peaks_find", "k_peaks_find", "peaks.hip")]
+
+
+def _source_sha(name):
+    src = os.path.join(ROOT, "paper_2206_11297_amd", "csrc", name)
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()
+
+
 def traffic_summary(fetch_dir, write_dir, out_dir):
     """Summary of two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
     WRITE_SIZE, both with --copy-calibration): per-kernel HBM bytes per
     dispatch, scaled by what the counters read for a 1 GiB device copy (reads
-    1 GiB) and a 1 GiB fill (writes 1 GiB).  Writes the JSON record read by
-    the roofline and a Markdown table."""
+    1 GiB) and a 1 GiB fill (writes 1 GiB).  Writes the JSON records read by
+    the rooflines and a Markdown table."""
     fetch = _counter_rows(fetch_dir, "FETCH_SIZE")
     write = _counter_rows(write_dir, "WRITE_SIZE")
     gib_kib = float(1 << 20)
@@ -316,48 +330,56 @@ def traffic_summary(fetch_dir, write_dir, out_dir):
 
     fs = calib(fetch, lambda k: "copyBuffer" in k or "copy" in k.lower())
     ws = calib(write, lambda k: "fill" in k.lower())
-    src = os.path.join(ROOT, "paper_2206_11297_amd", "csrc", "compress.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    table = []
+    table = []   # per kernel and grid
     for k in sorted(set(fetch) | set(write)):
         if "rsz::" not in k:
             continue
-        f = fetch.get(k, [])
-        w = write.get(k, [])
-        fk = sum(v for _, v in f) / max(1, len(f))
-        wk = sum(v for _, v in w) / max(1, len(w))
-        table.append((k, len(f), fk, fk * 1024 * fs, len(w), wk, wk * 1024 * ws))
-    kb = [t for t in table if "k_bin" in t[0]]
-    rec = {"kernel": "k_bin", "workload": WORKLOAD, "compress_hip_sha256": sha,
-           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
-           "fetch_bytes_per_launch": round(kb[0][3]) if kb else None,
-           "write_bytes_per_launch": round(kb[0][6]) if kb else None,
-           "hbm_bytes_per_launch": round(kb[0][3] + kb[0][6]) if kb else None,
-           "algorithmic_bytes_per_launch": NFRAMES * SHAPE[0] * SHAPE[1] * SHAPE[2] * 4}
+        for g in sorted({g for g, _ in fetch.get(k, []) + write.get(k, [])}):
+            f = [v for gg, v in fetch.get(k, []) if gg == g]
+            w = [v for gg, v in write.get(k, []) if gg == g]
+            fk = sum(f) / max(1, len(f))
+            wk = sum(w) / max(1, len(w))
+            table.append((k, g, len(f), fk, fk * 1024 * fs, wk, wk * 1024 * ws))
     os.makedirs(out_dir, exist_ok=True)
-    with open(os.path.join(out_dir, f"k_bin_{WORKLOAD}_traffic.json"), "w") as fh:
-        json.dump(rec, fh, indent=1)
+    for rec_name, match, source in TRAFFIC_KERNELS:
+        names = [k for k in set(fetch) & set(write) if match in k]
+        if not names:
+            continue
+        fl = [t for k in names for t in fetch[k]]
+        wl = [t for k in names for t in write[k]]
+        top = max(g for g, _ in fl)
+        fv = [v for g, v in fl if g == top]
+        wv = [v for g, v in wl if g == top]
+        fb = sum(fv) / len(fv) * 1024 * fs
+        wb = sum(wv) / len(wv) * 1024 * ws
+        rec = {"kernel": rec_name, "counter_name": names[0], "workload": WORKLOAD,
+               "grid": top, "dispatches": len(fv), "source": source,
+               "source_sha256": _source_sha(source),
+               "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+               "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
+               "hbm_bytes_per_launch": round(fb + wb)}
+        with open(os.path.join(out_dir, f"{rec_name}_{WORKLOAD}_traffic.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
     lines = [f"fetch scale {fs:.4f} (1 GiB copy), write scale {ws:.4f} (1 GiB fill)", "",
-             "| kernel | dispatches | FETCH_SIZE KiB/dispatch | read GB | WRITE_SIZE KiB/dispatch "
-             "| written GB |", "|---|---|---|---|---|---|"]
-    for k, nf, fk, fb, nw, wk, wb in sorted(table, key=lambda t: -t[3]):
-        lines.append(f"| `{k[:48]}` | {nf} | {fk:.0f} | {fb / 1e9:.3f} | {wk:.0f} | "
+             "| kernel | grid (work-items) | dispatches | FETCH_SIZE KiB/dispatch | read GB "
+             "| WRITE_SIZE KiB/dispatch | written GB |", "|---|---|---|---|---|---|---|"]
+    for k, g, nf, fk, fb, wk, wb in sorted(table, key=lambda t: -t[4]):
+        lines.append(f"| `{k[:56]}` | {g} | {nf} | {fk:.0f} | {fb / 1e9:.3f} | {wk:.0f} | "
                      f"{wb / 1e9:.3f} |")
     with open(os.path.join(out_dir, f"{WORKLOAD}_traffic_table.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    print(json.dumps(rec))
 
 
 def traffic_record(kernel):
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{WORKLOAD}_traffic.json")
-    src = os.path.join(ROOT, "paper_2206_11297_amd", "csrc", "compress.hip")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("compress_hip_sha256") != sha:
+    src = rec.get("source")
+    if not src or rec.get("source_sha256") != _source_sha(src):
         return None
     return rec
 
