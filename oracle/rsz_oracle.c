@@ -61,6 +61,7 @@ typedef struct {
   uint32_t bin_mode;              /* 0 = background pixels only, 1 = all   */
   double eb;                      /* absolute bound on binned values       */
   uint32_t dim;                   /* Lorenzo dimension 1, 2 or 3; 0 means 2 */
+  uint32_t roi_coding;            /* 0: ROI payload verbatim, 1: coded    */
 } ro_params;
 
 static uint32_t ro_dim(const ro_params *p) { return p->dim ? p->dim : 2u; }
@@ -82,11 +83,13 @@ int ro_check_params(const ro_params *p, uint32_t npeaks) {
     return RO_ERR_ARG;
   if (p->window < 1 || p->window > 1023) return RO_ERR_ARG;
   if (p->bin < 1 || p->bin > 8) return RO_ERR_ARG;
-  if (p->bin_mode > 1 || p->dim > 3) return RO_ERR_ARG;
+  if (p->bin_mode > 1 || p->dim > 3 || p->roi_coding > 1) return RO_ERR_ARG;
   if (!(p->eb > 0.0) || !isfinite(p->eb)) return RO_ERR_ARG;
   if ((uint64_t)p->panels * p->height * p->width >= (1ull << 31)) return RO_ERR_ARG;
   if (ro_nbins(p) >= (1ull << 27)) return RO_ERR_ARG;
   if ((uint64_t)npeaks * p->window * p->window > (1ull << 28)) return RO_ERR_ARG;
+  /* coded ROI bits (at most 63 per value) must fit u32 offsets */
+  if (p->roi_coding && (uint64_t)npeaks * p->window * p->window > (1ull << 26)) return RO_ERR_ARG;
   return RO_OK;
 }
 
@@ -382,23 +385,113 @@ uint64_t ro_bitstream(uint64_t nbins, const uint16_t *codes, const uint8_t *len,
 /* ---------------------------------------------------------------- container */
 
 /* Section order: header, peaks, ROI payload, code lengths, chunk offsets,
- * bitstream, outlier indices, outlier residuals. */
+ * bitstream, outlier indices, outlier residuals.  With the ROI coded the
+ * verbatim payload is absent and the coded ROI section closes the stream:
+ * 33 class code lengths (u8, padded to 36 bytes), one u32 bit offset per
+ * window, then the ROI bitstream (Troi bits in u32 words). */
+#define RO_ROI_CLASSES 33
+#define RO_ROI_LENS 36
 typedef struct {
-  uint64_t peaks, roi, lens, chunks, bits, oidx, ores, total;
+  uint64_t peaks, roi, lens, chunks, bits, oidx, ores, rsec, roffs, rbits, total;
 } ro_layout;
 
 static ro_layout ro_sections(const ro_params *p, uint32_t npeaks, uint64_t n_out,
-                             uint64_t n_chunks, uint64_t T) {
+                             uint64_t n_chunks, uint64_t T, uint64_t Troi) {
   ro_layout L;
   L.peaks = RO_HEADER;
   L.roi = L.peaks + ro_align4(6ull * npeaks);
-  L.lens = L.roi + 4ull * npeaks * p->window * p->window;
+  L.lens = L.roi + (p->roi_coding ? 0 : 4ull * npeaks * p->window * p->window);
   L.chunks = L.lens + RO_NSYM;
   L.bits = L.chunks + 4ull * n_chunks;
   L.oidx = L.bits + 4ull * ((T + 31) / 32);
   L.ores = L.oidx + 4ull * n_out;
-  L.total = L.ores + 4ull * n_out;
+  L.rsec = L.ores + 4ull * n_out;
+  L.roffs = L.rsec + RO_ROI_LENS;
+  L.rbits = L.roffs + 4ull * npeaks;
+  L.total = p->roi_coding ? L.rbits + 4ull * ((Troi + 31) / 32) : L.rsec;
   return L;
+}
+
+/* ---------------------------------------------------- lossless ROI coding */
+
+/* Predictive lossless coding of the ROI windows (the paper codes them with
+ * fpzip, Sec. IV; this is a coder of the same class written here).  Each
+ * window's w*w payload words b (fill 0 outside the panel) are mapped to
+ * order-preserving integers M (positive floats: b | 2^31, negative: ~b), so
+ * that near values are near integers.  M is predicted in raster order by the
+ * 2D Lorenzo predictor over the window, M[u-1][v] + M[u][v-1] - M[u-1][v-1]
+ * with M = 2^31 (mapped +0.0) outside it, all mod 2^32.  The residual r is
+ * zigzag-mapped to z = (r << 1) ^ (r >> 31); its class c = bit length of z
+ * (0..32) is Huffman coded (per frame, the two-queue rule and canonical
+ * codes of the main code) and followed by the low c - 1 bits of z (c >= 2;
+ * the leading 1 is implied), MSB-first. */
+static uint32_t ro_fmap(uint32_t b) { return (b & 0x80000000u) ? ~b : (b | 0x80000000u); }
+static uint32_t ro_funmap(uint32_t m) { return (m & 0x80000000u) ? (m & 0x7FFFFFFFu) : ~m; }
+static uint32_t ro_zclass(uint32_t z) {
+  uint32_t c = 0;
+  while (z) {
+    c++;
+    z >>= 1;
+  }
+  return c;
+}
+
+/* Zigzag residual of value (u, v) of a w x w window of mapped words M. */
+static uint32_t ro_roi_z(const uint32_t *M, int64_t w, int64_t u, int64_t v) {
+  const uint32_t zero = 0x80000000u;
+  const uint32_t up = u > 0 ? M[(u - 1) * w + v] : zero;
+  const uint32_t left = v > 0 ? M[u * w + v - 1] : zero;
+  const uint32_t ul = (u > 0 && v > 0) ? M[(u - 1) * w + v - 1] : zero;
+  const uint32_t pred = up + left - ul;
+  const int32_t r = (int32_t)(M[u * w + v] - pred);
+  return ((uint32_t)r << 1) ^ (uint32_t)(r >> 31);
+}
+
+static void ro_putbits(uint32_t *words, uint64_t *pos, uint32_t value, uint32_t nbits) {
+  for (uint32_t i = 0; i < nbits; ++i) {
+    const uint32_t bit = (value >> (nbits - 1 - i)) & 1u;
+    if (bit) words[*pos / 32] |= 1u << (31 - *pos % 32);
+    (*pos)++;
+  }
+}
+
+/* Codes the payload of npeaks windows: class lengths (33), window bit offsets
+ * and, if words is not NULL, the bitstream (words must be zeroed).  Returns
+ * the number of bits. */
+uint64_t ro_roi_code(const ro_params *p, const uint32_t *payload, uint32_t npeaks, uint8_t *lens33,
+                     uint32_t *offsets, uint32_t *words) {
+  const int64_t w = p->window, ww = w * w;
+  uint32_t *M = (uint32_t *)malloc(4 * (size_t)ww);
+  uint32_t hist[RO_NSYM];
+  memset(hist, 0, sizeof hist);
+  for (uint32_t k = 0; k < npeaks; ++k) {
+    for (int64_t t = 0; t < ww; ++t) M[t] = ro_fmap(payload[(uint64_t)k * ww + t]);
+    for (int64_t u = 0; u < w; ++u)
+      for (int64_t v = 0; v < w; ++v) hist[ro_zclass(ro_roi_z(M, w, u, v))]++;
+  }
+  uint8_t len[RO_NSYM];
+  uint32_t cw[RO_NSYM];
+  memset(len, 0, sizeof len);
+  if (npeaks) ro_huffman_lengths(hist, len);
+  ro_canonical(len, cw);
+  memcpy(lens33, len, RO_ROI_CLASSES);
+  uint64_t pos = 0;
+  for (uint32_t k = 0; k < npeaks; ++k) {
+    offsets[k] = (uint32_t)pos;
+    for (int64_t t = 0; t < ww; ++t) M[t] = ro_fmap(payload[(uint64_t)k * ww + t]);
+    for (int64_t u = 0; u < w; ++u)
+      for (int64_t v = 0; v < w; ++v) {
+        const uint32_t z = ro_roi_z(M, w, u, v), c = ro_zclass(z);
+        if (words) {
+          ro_putbits(words, &pos, cw[c], len[c]);
+          if (c >= 2) ro_putbits(words, &pos, z, c - 1);
+        } else {
+          pos += len[c] + (c >= 2 ? c - 1 : 0);
+        }
+      }
+  }
+  free(M);
+  return pos;
 }
 
 static void put16(uint8_t *b, uint64_t o, uint16_t v) { memcpy(b + o, &v, 2); }
@@ -413,7 +506,10 @@ int ro_max_bytes(const ro_params *p, uint32_t npeaks, uint64_t *bytes) {
   int st = ro_check_params(p, npeaks);
   if (st) return st;
   const uint64_t nb = ro_nbins(p), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
-  *bytes = ro_sections(p, npeaks, nb, nc, 32ull * nb).total;
+  /* worst case: every code 32 bits, every bin an outlier, every ROI value 63
+   * bits */
+  *bytes = ro_sections(p, npeaks, nb, nc, 32ull * nb,
+                       63ull * npeaks * p->window * p->window).total;
   return RO_OK;
 }
 
@@ -499,7 +595,14 @@ int ro_compress(const ro_params *p, const float *frame, const int32_t *peaks, ui
     ro_huffman_lengths(h, l);
     ro_canonical(l, c);
     const uint64_t T = ro_bitstream(nb, cd, l, c, NULL, co);
-    const ro_layout L = ro_sections(p, npeaks, n_out, nc, T);
+    /* the ROI payload, and its coded form when asked for */
+    const uint64_t nroi = (uint64_t)npeaks * p->window * p->window;
+    uint32_t *pay = (uint32_t *)malloc(4 * (size_t)(nroi ? nroi : 1));
+    uint32_t *roffs = (uint32_t *)malloc(4 * (size_t)(npeaks ? npeaks : 1));
+    uint8_t rl[RO_ROI_CLASSES];
+    ro_roi(p, frame, peaks, npeaks, pay);
+    const uint64_t Troi = p->roi_coding ? ro_roi_code(p, pay, npeaks, rl, roffs, NULL) : 0;
+    const ro_layout L = ro_sections(p, npeaks, n_out, nc, T, Troi);
     *out_bytes = L.total;
     if (L.total > out_cap) {
       st = RO_ERR_CAPACITY;
@@ -509,7 +612,8 @@ int ro_compress(const ro_params *p, const float *frame, const int32_t *peaks, ui
       put16(out, 4, 1);
       /* flags: bit 0 bin_mode, bits 1-2 the Lorenzo dimension (0 for the
        * default 2, else 1 or 3) */
-      put16(out, 6, (uint16_t)((p->bin_mode & 1u) | ((ro_dim(p) == 2 ? 0u : ro_dim(p)) << 1)));
+      put16(out, 6, (uint16_t)((p->bin_mode & 1u) | ((ro_dim(p) == 2 ? 0u : ro_dim(p)) << 1) |
+                               ((p->roi_coding & 1u) << 3)));
       put32(out, 8, p->panels);
       put32(out, 12, p->height);
       put32(out, 16, p->width);
@@ -523,10 +627,15 @@ int ro_compress(const ro_params *p, const float *frame, const int32_t *peaks, ui
       put32(out, 52, (uint32_t)nc);
       put64(out, 56, T);
       put64(out, 64, L.total);
-      put64(out, 72, 0);
+      put64(out, 72, Troi);   /* ROI bits (0 with the payload verbatim) */
       for (uint32_t k = 0; k < npeaks; ++k)
         for (int t = 0; t < 3; ++t) put16(out, L.peaks + 6ull * k + 2 * t, (uint16_t)peaks[3 * k + t]);
-      ro_roi(p, frame, peaks, npeaks, (uint32_t *)(out + L.roi));
+      if (p->roi_coding) {
+        ro_roi_code(p, pay, npeaks, out + L.rsec, roffs, (uint32_t *)(out + L.rbits));
+        for (uint32_t k = 0; k < npeaks; ++k) put32(out, L.roffs + 4ull * k, roffs[k]);
+      } else {
+        memcpy(out + L.roi, pay, 4 * (size_t)nroi);
+      }
       memcpy(out + L.lens, l, RO_NSYM);
       for (uint32_t k = 0; k < n_out; ++k) {
         put32(out, L.oidx + 4ull * k, oi[k]);
@@ -535,6 +644,7 @@ int ro_compress(const ro_params *p, const float *frame, const int32_t *peaks, ui
       for (uint64_t k = 0; k < nc; ++k) put32(out, L.chunks + 4 * k, co[k]);
       ro_bitstream(nb, cd, l, c, (uint32_t *)(out + L.bits), NULL);
     }
+    free(pay); free(roffs);
   }
   free(m); free(s); free(cnt); free(qq); free(rr); free(cd); free(oi); free(orr); free(co);
   return st;
@@ -549,9 +659,10 @@ int ro_stream_info(const uint8_t *in, uint64_t in_bytes, ro_params *p, uint32_t 
     return RO_ERR_CORRUPT;
   ro_params q;
   const uint32_t flags = get16(in, 6), dcode = (flags >> 1) & 3u;
-  if ((flags >> 3) != 0 || dcode == 2) return RO_ERR_CORRUPT;
+  if ((flags >> 4) != 0 || dcode == 2) return RO_ERR_CORRUPT;
   q.bin_mode = flags & 1u;
   q.dim = dcode == 0 ? 2u : dcode;
+  q.roi_coding = (flags >> 3) & 1u;
   q.panels = get32(in, 8);
   q.height = get32(in, 12);
   q.width = get32(in, 16);
@@ -560,16 +671,92 @@ int ro_stream_info(const uint8_t *in, uint64_t in_bytes, ro_params *p, uint32_t 
   memcpy(&q.eb, in + 32, 8);
   const uint32_t np = get32(in, 40);
   if (ro_check_params(&q, np) != RO_OK) return RO_ERR_CORRUPT;
-  if (get32(in, 28) != RO_RADIUS || get32(in, 48) != RO_CHUNK || get64(in, 72) != 0)
+  /* offset 72: the coded ROI bits, 0 when the payload is verbatim */
+  const uint64_t Troi = get64(in, 72);
+  if (get32(in, 28) != RO_RADIUS || get32(in, 48) != RO_CHUNK || (!q.roi_coding && Troi != 0) ||
+      Troi > 63ull * np * q.window * q.window)
     return RO_ERR_CORRUPT;
   const uint64_t nb = ro_nbins(&q), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
   const uint64_t n_out = get32(in, 44), T = get64(in, 56), total = get64(in, 64);
   if (get32(in, 52) != nc || n_out > nb || T > 32ull * nb) return RO_ERR_CORRUPT;
-  if (ro_sections(&q, np, n_out, nc, T).total != total || total > in_bytes) return RO_ERR_CORRUPT;
+  if (ro_sections(&q, np, n_out, nc, T, Troi).total != total || total > in_bytes)
+    return RO_ERR_CORRUPT;
   if (p) *p = q;
   if (npeaks) *npeaks = np;
   if (stream_bytes) *stream_bytes = total;
   return RO_OK;
+}
+
+/* Decodes the coded ROI section (see ro_roi_code) into payload (npeaks * w
+ * * w words).  The class lengths must form a complete prefix code (or one
+ * class of length 1; none when there is no window), padding bytes zero;
+ * window k starts at its offset (the first at 0, offsets non-decreasing) and
+ * ends exactly where window k + 1 starts, the last at Troi.  Anything else is
+ * RO_ERR_CORRUPT. */
+static int ro_roi_decode(const ro_params *p, const uint8_t *in, const ro_layout *L, uint32_t np,
+                         uint64_t Troi, uint32_t *payload) {
+  const uint8_t *lens = in + L->rsec;
+  uint64_t kraft = 0;
+  int used = 0;
+  for (int c = 0; c < RO_ROI_LENS; ++c) {
+    if (c >= RO_ROI_CLASSES ? lens[c] != 0 : lens[c] > RO_MAXLEN) return RO_ERR_CORRUPT;
+    if (c < RO_ROI_CLASSES && lens[c]) {
+      kraft += 1ull << (RO_MAXLEN - lens[c]);
+      used++;
+    }
+  }
+  if (np == 0) return (used == 0 && Troi == 0) ? RO_OK : RO_ERR_CORRUPT;
+  if (!(kraft == (1ull << RO_MAXLEN) || (used == 1 && kraft == (1ull << (RO_MAXLEN - 1)))))
+    return RO_ERR_CORRUPT;
+  uint8_t len[RO_NSYM];
+  uint32_t cw[RO_NSYM];
+  memset(len, 0, sizeof len);
+  memcpy(len, lens, RO_ROI_CLASSES);
+  ro_canonical(len, cw);
+  const uint32_t *words = (const uint32_t *)(in + L->rbits);
+  const int64_t w = p->window, ww = w * w;
+  uint32_t *M = (uint32_t *)malloc(4 * (size_t)ww);
+  int bad = 0;
+  uint64_t pos = 0;
+  for (uint32_t k = 0; k < np && !bad; ++k) {
+    const uint64_t start = get32(in, L->roffs + 4ull * k);
+    const uint64_t end = k + 1 < np ? get32(in, L->roffs + 4ull * (k + 1)) : Troi;
+    if (start != pos || end < start || end > Troi) {
+      bad = 1;
+      break;
+    }
+    for (int64_t u = 0; u < w && !bad; ++u)
+      for (int64_t v = 0; v < w && !bad; ++v) {
+        /* class: the codeword whose length and value match, read bit by bit */
+        uint64_t code = 0;
+        int cls = -1;
+        for (int n = 1; n <= RO_MAXLEN && cls < 0; ++n) {
+          if (pos >= end) { bad = 1; break; }
+          code = (code << 1) | ((words[pos / 32] >> (31 - pos % 32)) & 1u);
+          pos++;
+          for (int c = 0; c < RO_ROI_CLASSES; ++c)
+            if (len[c] == n && cw[c] == code) { cls = c; break; }
+        }
+        if (bad || cls < 0) { bad = 1; break; }
+        uint32_t z = cls == 0 ? 0u : 1u;
+        for (int b = 0; b + 1 < cls; ++b) {
+          if (pos >= end) { bad = 1; break; }
+          z = (z << 1) | ((words[pos / 32] >> (31 - pos % 32)) & 1u);
+          pos++;
+        }
+        if (bad) break;
+        const uint32_t r = (z >> 1) ^ (0u - (z & 1u));
+        const uint32_t zero = 0x80000000u;
+        const uint32_t up = u > 0 ? M[(u - 1) * w + v] : zero;
+        const uint32_t left = v > 0 ? M[u * w + v - 1] : zero;
+        const uint32_t ul = (u > 0 && v > 0) ? M[(u - 1) * w + v - 1] : zero;
+        M[u * w + v] = up + left - ul + r;
+        payload[(uint64_t)k * ww + u * w + v] = ro_funmap(M[u * w + v]);
+      }
+    if (!bad && pos != end) bad = 1;
+  }
+  free(M);
+  return bad ? RO_ERR_CORRUPT : RO_OK;
 }
 
 /* Decompress a stream into a panels x height x width float frame.
@@ -586,8 +773,8 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
   const uint64_t pix = (uint64_t)p.panels * p.height * p.width;
   if (frame_elems < pix) return RO_ERR_ARG;
   const uint64_t nb = ro_nbins(&p), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
-  const uint64_t n_out = get32(in, 44), T = get64(in, 56);
-  const ro_layout L = ro_sections(&p, np, n_out, nc, T);
+  const uint64_t n_out = get32(in, 44), T = get64(in, 56), Troi = get64(in, 72);
+  const ro_layout L = ro_sections(&p, np, n_out, nc, T, Troi);
   /* peaks */
   int32_t *pk = (int32_t *)malloc(12 * (size_t)(np ? np : 1));
   for (uint32_t k = 0; k < np; ++k)
@@ -716,8 +903,19 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
         const uint64_t g = (pa * Hb + i / b) * Wb + j / b;
         frame[(pa * p.height + i) * p.width + j] = (float)((double)res[g] * step);
       }
-  /* ROI windows, bit-exact from the payload */
+  /* ROI windows, bit-exact from the payload (verbatim, or decoded) */
   const int64_t h = p.window / 2, w = p.window;
+  const uint64_t nroi = (uint64_t)np * w * w;
+  uint32_t *dec = NULL;
+  const uint8_t *payload = in + L.roi;
+  if (p.roi_coding) {
+    dec = (uint32_t *)malloc(4 * (size_t)(nroi ? nroi : 1));
+    if (ro_roi_decode(&p, in, &L, np, Troi, dec) != RO_OK) {
+      free(pk); free(res); free(cd); free(dec);
+      return RO_ERR_CORRUPT;
+    }
+    payload = (const uint8_t *)dec;
+  }
   for (uint32_t k = 0; k < np; ++k) {
     const int64_t pa = pk[3 * k], r0 = pk[3 * k + 1] - h, c0 = pk[3 * k + 2] - h;
     for (int64_t u = 0; u < w; ++u)
@@ -725,7 +923,7 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
         const int64_t i = r0 + u, j = c0 + v;
         if (i < 0 || i >= (int64_t)p.height || j < 0 || j >= (int64_t)p.width) continue;
         memcpy(&frame[((uint64_t)pa * p.height + (uint64_t)i) * p.width + (uint64_t)j],
-               in + L.roi + 4 * (((uint64_t)k * w + (uint64_t)u) * w + (uint64_t)v), 4);
+               payload + 4 * (((uint64_t)k * w + (uint64_t)u) * w + (uint64_t)v), 4);
       }
   }
   /* windows that overlap copy the same frame pixel, so every payload entry
@@ -738,13 +936,13 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
         const int64_t i = r0 + u, j = c0 + v;
         if (i < 0 || i >= (int64_t)p.height || j < 0 || j >= (int64_t)p.width) continue;
         if (memcmp(&frame[((uint64_t)pa * p.height + (uint64_t)i) * p.width + (uint64_t)j],
-                   in + L.roi + 4 * (((uint64_t)k * w + (uint64_t)u) * w + (uint64_t)v), 4) != 0) {
+                   payload + 4 * (((uint64_t)k * w + (uint64_t)u) * w + (uint64_t)v), 4) != 0) {
           bad = 1;
           break;
         }
       }
   }
-  free(pk); free(res); free(cd);
+  free(pk); free(res); free(cd); free(dec);
   return bad ? RO_ERR_CORRUPT : RO_OK;
 }
 

@@ -24,16 +24,23 @@ def align4(x):
     return (x + 3) & ~3
 
 
-def sections(npeaks, window, n_out, n_chunks, T):
+def sections(npeaks, window, n_out, n_chunks, T, roi_coded=False, Troi=0):
     off = {}
     off["peaks"] = 80
     off["roi"] = 80 + align4(6 * npeaks)
-    off["lens"] = off["roi"] + 4 * npeaks * window * window
+    off["lens"] = off["roi"] + (0 if roi_coded else 4 * npeaks * window * window)
     off["chunks"] = off["lens"] + 1024
     off["bits"] = off["chunks"] + 4 * n_chunks
     off["oidx"] = off["bits"] + 4 * ((T + 31) // 32)
     off["ores"] = off["oidx"] + 4 * n_out
     off["total"] = off["ores"] + 4 * n_out
+    if roi_coded:
+        # coded ROI section at the end: 33 class lengths (padded to 36 bytes),
+        # one u32 bit offset per window, the ROI bitstream
+        off["rsec"] = off["total"]
+        off["roffs"] = off["rsec"] + 36
+        off["rbits"] = off["roffs"] + 4 * npeaks
+        off["total"] = off["rbits"] + 4 * ((Troi + 31) // 32)
     return off
 
 
@@ -41,13 +48,22 @@ def parse(buf):
     buf = bytes(np.asarray(buf, dtype=np.uint8).tobytes())
     (magic, ver, flags, P, H, W, w, b, R, eb, npk, n_out, ch, nch, T, total, res) = \
         HDR.unpack_from(buf, 0)
-    off = sections(npk, w, n_out, nch, T)
+    coded = bool(flags & 8)
+    off = sections(npk, w, n_out, nch, T, coded, res if coded else 0)
     d = dict(magic=magic, version=ver, flags=flags, P=P, H=H, W=W, window=w, bin=b, radius=R,
              eb=eb, npeaks=npk, n_out=n_out, chunk=ch, n_chunks=nch, T=T, stream_bytes=total,
              reserved=res, off=off, bin_mode=flags & 1,
              dim={0: 2, 1: 1, 3: 3}.get((flags >> 1) & 3))
     d["peaks"] = np.frombuffer(buf, np.uint16, 3 * npk, off["peaks"]).reshape(-1, 3)
-    d["roi"] = np.frombuffer(buf, np.uint32, npk * w * w, off["roi"])
+    d["roi_coded"] = coded
+    if coded:
+        d["Troi"] = res
+        d["roi_lens"] = np.frombuffer(buf, np.uint8, 36, off["rsec"])
+        d["roi_offsets"] = np.frombuffer(buf, np.uint32, npk, off["roffs"])
+        d["roi_words"] = np.frombuffer(buf, np.uint32, (res + 31) // 32, off["rbits"])
+        d["roi"] = decode_roi(d["roi_lens"], d["roi_offsets"], d["roi_words"], res, npk, w)
+    else:
+        d["roi"] = np.frombuffer(buf, np.uint32, npk * w * w, off["roi"])
     d["lens"] = np.frombuffer(buf, np.uint8, 1024, off["lens"])
     d["oidx"] = np.frombuffer(buf, np.uint32, n_out, off["oidx"])
     d["ores"] = np.frombuffer(buf, np.int32, n_out, off["ores"])
@@ -158,3 +174,45 @@ def closed_form_reconstruction(frame, peaks, window, b, eb, bin_mode):
     y = np.repeat(np.repeat(val, b, axis=1), b, axis=2)[:, :H, :W].copy()
     y[M] = frame[M]
     return y, M, S, n, q
+
+
+def decode_roi(lens, offsets, words, Troi, npeaks, w):
+    """Independent decoder of the coded ROI section: per window, class
+    codewords (canonical, from the lengths sorted by (length, class)) each
+    followed by class-1 raw bits of the zigzag residual; the residual is added
+    to the 2D Lorenzo prediction over the window in the order-preserving
+    integer domain (2^31 outside the window) and mapped back to float bits."""
+    syms = sorted((int(lens[c]), c) for c in range(33) if lens[c] > 0)
+    table, code, prev = {}, -1, 0
+    for L, c in syms:
+        code = 0 if code < 0 else (code + 1) << (L - prev)
+        prev = L
+        table[(L, code)] = c
+    bits = bits_of(words, Troi)
+    out = np.zeros((npeaks, w, w), np.uint32)
+    pos = 0
+    for k in range(npeaks):
+        assert pos == int(offsets[k])
+        M = np.zeros((w, w), np.int64)
+        for u in range(w):
+            for v in range(w):
+                c, L = 0, 0
+                while (L, c) not in table:
+                    c = (c << 1) | bits[pos]
+                    pos += 1
+                    L += 1
+                    assert L <= 32
+                cls = table[(L, c)]
+                z = 0 if cls == 0 else 1
+                for _ in range(cls - 1):
+                    z = (z << 1) | bits[pos]
+                    pos += 1
+                r = (z >> 1) ^ (-(z & 1) & 0xFFFFFFFF)
+                up = M[u - 1, v] if u else 1 << 31
+                left = M[u, v - 1] if v else 1 << 31
+                ul = M[u - 1, v - 1] if u and v else 1 << 31
+                M[u, v] = (up + left - ul + r) & 0xFFFFFFFF
+                m = int(M[u, v])
+                out[k, u, v] = (m & 0x7FFFFFFF) if m & 0x80000000 else (~m & 0xFFFFFFFF)
+    assert pos == Troi
+    return out.reshape(-1)
