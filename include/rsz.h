@@ -24,11 +24,14 @@
  *
  * Frame layout: panels x height x width float32, C-contiguous.  Stream
  * layout (little-endian, sections 4-byte aligned): 80-byte header (flags:
- * bit 0 bin_mode, bits 1-2 the Lorenzo dimension, 0 for 2), peaks
+ * bit 0 bin_mode, bits 1-2 the Lorenzo dimension, 0 for 2, bit 3 the ROI
+ * coded; bytes 72-79 the coded ROI bits, else 0), peaks
  * (u16 panel,row,col), ROI payload (npeaks*w*w u32 bit patterns, 0 outside
  * the panel), code lengths (1024 u8), chunk bit offsets (u32, one per 4096
  * symbols), bitstream (u32 words, codewords MSB-first), outlier bin indices
- * (u32), outlier residuals (i32).
+ * (u32), outlier residuals (i32).  With the ROI coded, the verbatim payload is
+ * absent and the coded ROI section ends the stream: 33 class code lengths
+ * (u8, padded to 36 bytes), one u32 bit offset per window, the ROI bitstream.
  */
 #ifndef RSZ_H
 #define RSZ_H
@@ -59,7 +62,12 @@ typedef struct {
  *   dim: dimension of the Lorenzo predictor (Sec. VI): 1 reads the binned
  *     frame as one sequence in raster order (panel, row, column), 2 reads
  *     each panel as an image (0 also means 2, the default), 3 reads the
- *     stack of panels as a volume.  Residuals take zeros outside the domain. */
+ *     stack of panels as a volume.  Residuals take zeros outside the domain.
+ *   roi_coding: 0 stores the ROI windows verbatim; 1 codes them losslessly
+ *     (the paper uses fpzip, Sec. IV): each window's float bits are mapped to
+ *     order-preserving integers, predicted by a 2D Lorenzo predictor over the
+ *     window, and the zigzag residual's bit length is Huffman coded and
+ *     followed by its remaining bits.  Needs npeaks*window^2 <= 2^26. */
 typedef struct {
   uint32_t panels, height, width;
   uint32_t window;
@@ -67,6 +75,7 @@ typedef struct {
   uint32_t bin_mode;
   double eb;
   uint32_t dim;
+  uint32_t roi_coding;
 } rsz_params;
 
 enum { RSZ_BIN_BACKGROUND = 0, RSZ_BIN_ALL = 1 };

@@ -53,13 +53,16 @@ static int check_params(const rsz_params *p, uint32_t npeaks) {
       p->width < 1 || p->width > 65535)
     return RSZ_ERR_ARG;
   if (p->window < 1 || p->window > 1023 || p->bin < 1 || p->bin > 8 || p->bin_mode > 1 ||
-      p->dim > 3)
+      p->dim > 3 || p->roi_coding > 1)
     return RSZ_ERR_ARG;
   if (!(p->eb > 0.0) || !std::isfinite(p->eb)) return RSZ_ERR_ARG;
   const uint64_t pix = (uint64_t)p->panels * p->height * p->width;
   const uint64_t nb = (uint64_t)p->panels * div_up(p->height, p->bin) * div_up(p->width, p->bin);
   if (pix >= (1ull << 31) || nb >= (1ull << 27)) return RSZ_ERR_ARG;
   if ((uint64_t)npeaks * p->window * p->window > (1ull << 28)) return RSZ_ERR_ARG;
+  // coded ROI bits (at most 63 per value) must fit u32 offsets
+  if (p->roi_coding && (uint64_t)npeaks * p->window * p->window > (1ull << 26))
+    return RSZ_ERR_ARG;
   return RSZ_OK;
 }
 
@@ -92,11 +95,14 @@ static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap, uint
   g.segs = (uint32_t)div_up(g.Hb, g.TH);
   g.groups = (uint32_t)div_up(g.segs, kWaves);
   g.off_roi = kHeader + align_up(6ull * npeaks, 4);
-  g.off_lens = g.off_roi + 4ull * npeaks * p->window * p->window;
+  const uint64_t nroi = (uint64_t)npeaks * p->window * p->window;
+  g.off_lens = g.off_roi + (p->roi_coding ? 0 : 4ull * nroi);
   g.off_chunks = g.off_lens + kNumSym;
   g.off_bits = g.off_chunks + 4ull * g.nchunks;
-  // worst case: every codeword 32 bits and every bin an outlier
-  g.max_bytes = g.off_bits + 4ull * g.nbins + 8ull * g.nbins;
+  // worst case: every codeword 32 bits and every bin an outlier (and every
+  // coded ROI value 63 bits)
+  g.max_bytes = g.off_bits + 4ull * g.nbins + 8ull * g.nbins +
+                (p->roi_coding ? kRoiLens + 4ull * npeaks + 4 * div_up(63 * nroi, 32) : 0);
   return g;
 }
 
@@ -116,6 +122,8 @@ static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const G
   if (p->dim == 1) b += align_up(4ull * p->panels * g.Hb, 256);   // qedge
   if (p->dim == 3)   // 2D code bytes and residuals
     b += align_up(1ull * kChunk * g.nchunks, 256) + align_up(4ull * g.nbins, 256);
+  if (p->roi_coding)   // class histogram, lengths, codewords, window bits
+    b += 4 * kNumSym + kNumSym + 4 * kNumSym + align_up(4ull * npeaks, 256);
   return b;
 }
 
@@ -209,6 +217,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   if (!ws) return RSZ_OK;
   if (ws_bytes < L.total) return RSZ_ERR_WORKSPACE;
   hp.bytes.assign(L.states, 0);
+  memset(&hp.bp, 0, sizeof hp.bp);
   FramePlan *fpl = (FramePlan *)hp.bytes.data();
   uint32_t *tp = (uint32_t *)(hp.bytes.data() + L.prefix);
   uint32_t *cp = tp + (nframes + 1);
@@ -249,6 +258,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.b = p->bin;
     fp.mode = p->bin_mode;
     fp.dim = p->dim ? p->dim : 2u;
+    fp.roi_coding = p->roi_coding;
     fp.eb = p->eb;
     fp.step = 2.0 * p->eb;
     fp.Hb = g.Hb;
@@ -294,11 +304,25 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     base += align_up(4ull * g.nchunks, 256);
     fp.codes2 = fp.codes;
     fp.rbuf2 = fp.rbuf;
-    if (fp.dim == 1) fp.qedge = (int32_t *)base;
+    if (fp.dim == 1) {
+      fp.qedge = (int32_t *)base;
+      base += align_up(4ull * p->panels * g.Hb, 256);
+    }
     if (fp.dim == 3) {
       fp.codes2 = base;
       base += align_up(1ull * kChunk * g.nchunks, 256);
       fp.rbuf2 = (int32_t *)base;
+      base += align_up(4ull * g.nbins, 256);
+    }
+    if (fp.roi_coding) {
+      fp.roi_hist = (uint32_t *)base;
+      base += 4 * kNumSym;
+      fp.roi_cw = (uint32_t *)base;
+      base += 4 * kNumSym;
+      fp.roi_lens = base;
+      base += kNumSym;
+      fp.roi_bits = (uint32_t *)base;
+      hp.bp.roi_coding = 1;
     }
     if (dbg) {
       fp.dbg_mask = dbg->mask;
@@ -411,11 +435,12 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
   rsz_params q;
   memset(&q, 0, sizeof q);
   // flags: bit 0 bin_mode, bits 1-2 the Lorenzo dimension (0 for 2, else 1
-  // or 3); every other bit zero
+  // or 3), bit 3 the ROI coded; every other bit zero
   const uint32_t flags = u[1] >> 16, dcode = (flags >> 1) & 3u;
-  if ((flags >> 3) != 0 || dcode == 2) return RSZ_ERR_CORRUPT;
+  if ((flags >> 4) != 0 || dcode == 2) return RSZ_ERR_CORRUPT;
   q.bin_mode = flags & 1u;
   q.dim = dcode == 0 ? 2u : dcode;
+  q.roi_coding = (flags >> 3) & 1u;
   q.panels = u[2];
   q.height = u[3];
   q.width = u[4];
@@ -424,17 +449,22 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
   memcpy(&q.eb, h + 32, 8);
   const uint32_t np = u[10];
   if (check_params(&q, np) != RSZ_OK) return RSZ_ERR_CORRUPT;
-  uint64_t T, total, reserved;
+  uint64_t T, total, Troi;   // Troi: coded ROI bits, 0 with the payload verbatim
   memcpy(&T, h + 56, 8);
   memcpy(&total, h + 64, 8);
-  memcpy(&reserved, h + 72, 8);
-  if (u[7] != (uint32_t)kRadius || u[12] != kChunk || reserved != 0) return RSZ_ERR_CORRUPT;
+  memcpy(&Troi, h + 72, 8);
+  if (u[7] != (uint32_t)kRadius || u[12] != kChunk || (!q.roi_coding && Troi != 0) ||
+      Troi > 63ull * np * q.window * q.window)
+    return RSZ_ERR_CORRUPT;
   const Geom g = geometry(&q, np, kMaxTH, 1);
   const uint64_t n_out = u[11];
   if (u[13] != g.nchunks || n_out > g.nbins || T > 32ull * g.nbins) return RSZ_ERR_CORRUPT;
   const uint64_t off_oidx = g.off_bits + 4 * ((T + 31) / 32);
   const uint64_t off_ores = off_oidx + 4 * n_out;
-  if (off_ores + 4 * n_out != total || total > in_bytes) return RSZ_ERR_CORRUPT;
+  const uint64_t off_rsec = off_ores + 4 * n_out;
+  const uint64_t off_rbits = off_rsec + kRoiLens + 4ull * np;
+  const uint64_t end = q.roi_coding ? off_rbits + 4 * ((Troi + 31) / 32) : off_rsec;
+  if (end != total || total > in_bytes) return RSZ_ERR_CORRUPT;
   if (p) *p = q;
   if (npeaks) *npeaks = np;
   if (dp) {
@@ -446,6 +476,11 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
     dp->b = q.bin;
     dp->npeaks = np;
     dp->dim = q.dim;
+    dp->roi_coding = q.roi_coding;
+    dp->Troi = Troi;
+    dp->off_rsec = off_rsec;
+    dp->off_roffs = off_rsec + kRoiLens;
+    dp->off_rbits = off_rbits;
     dp->step = 2.0 * q.eb;
     dp->Hb = g.Hb;
     dp->Wb = g.Wb;
@@ -465,10 +500,15 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
   return RSZ_OK;
 }
 
+uint64_t decode_roi_tables_bytes();
+
 static uint64_t decode_ws_bytes(const DecodePlan &dp) {
   return align_up(4ull * dp.nbins, 256) + align_up(4ull * dp.nchunks, 256) + 256 +
          align_up(decode_tables_bytes(), 256) +
-         (dp.dim == 1 ? align_up(4ull * dp.P * dp.Hb, 256) : 0);
+         (dp.dim == 1 ? align_up(4ull * dp.P * dp.Hb, 256) : 0) +
+         (dp.roi_coding ? align_up(4ull * dp.npeaks * dp.w * dp.w, 256) +
+                              align_up(decode_roi_tables_bytes(), 256)
+                        : 0);
 }
 
 // Results of a single-frame call live in the workspace tail.
@@ -658,7 +698,15 @@ int rsz_decompress(const void *d_in, uint64_t in_bytes, float *d_frame, uint64_t
   w += 256;
   dp.tables = (uint32_t *)w;
   w += align_up(decode_tables_bytes(), 256);
-  if (dp.dim == 1) dp.carry = (uint32_t *)w;
+  if (dp.dim == 1) {
+    dp.carry = (uint32_t *)w;
+    w += align_up(4ull * dp.P * dp.Hb, 256);
+  }
+  if (dp.roi_coding) {
+    dp.roi_payload = (uint32_t *)w;
+    w += align_up(4ull * dp.npeaks * dp.w * dp.w, 256);
+    dp.roi_tables = (uint32_t *)w;
+  }
   if (launch_decompress(dp, s) != hipSuccess) return RSZ_ERR_HIP;
   int32_t status = 0;
   if (hipMemcpyAsync(&status, dp.status, 4, hipMemcpyDeviceToHost, s) != hipSuccess)

@@ -84,12 +84,15 @@ __global__ __launch_bounds__(256) void k_prep(BatchPlan bp) {
   __shared__ uint32_t s_tmp[4];
   __shared__ uint32_t s_cnt[kPrepKeys];
   for (int i = threadIdx.x; i < kNumSym; i += 256) st->hist[i] = 0;
+  if (fp.roi_coding)
+    for (int i = threadIdx.x; i < kNumSym; i += 256) fp.roi_hist[i] = 0;
   if (threadIdx.x == 0) {
     s_bad = 0;
     st->status = fp.init_status;
     st->n_out = 0;
     st->T = 0;
     st->total = 0;
+    st->Troi = 0;
   }
   if (fp.init_status != RSZ_OK) return;
   __syncthreads();
@@ -856,9 +859,11 @@ __device__ uint32_t gather_and_sort(uint64_t *key, uint32_t *s_tmp32, KeyOf key_
 // (count, symbol), internal nodes in creation order, a leaf taken first on
 // equal weights; lengths above 32 make the counts halve (kept >= 1) and the
 // build repeat.  Then canonical codewords in (length, symbol) order.
-__global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
-  const FramePlan &fp = bp.frames[blockIdx.x];
-  FrameState *st = fp.st;
+// Huffman lengths (two-queue rule, halving rebuild above kMaxLen) and
+// canonical codewords of the histogram `hist` (kNumSym entries) into
+// lens / cw, by one workgroup.
+__device__ void build_code(FrameState *st, const uint32_t *hist, uint8_t *lens_out,
+                           uint32_t *cw_out) {
   __shared__ uint64_t s_key[kNumSym];
   __shared__ uint32_t s_w[2 * kNumSym];      // node weights: leaves, then internal nodes
   __shared__ uint16_t s_anc[2][2 * kNumSym]; // parents, then ancestors (pointer jumping)
@@ -874,7 +879,7 @@ __global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
   __syncthreads();
   if (!s_ok) return;
   for (int s = threadIdx.x; s < kNumSym; s += 256) {
-    s_weight[s] = st->hist[s];   // the counts sum to nbins < 2^27
+    s_weight[s] = hist[s];   // the counts sum to < 2^27
     s_len[s] = 0;
   }
   __syncthreads();
@@ -967,15 +972,20 @@ __global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
   }
   __syncthreads();
   for (int s = threadIdx.x; s < kNumSym; s += 256) {
-    st->lens[s] = s_len[s];
-    st->cw[s] = 0;
+    lens_out[s] = s_len[s];
+    cw_out[s] = 0;
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nu; i += 256) {
     const uint64_t k = s_key[i];
     const uint32_t L = (uint32_t)(k >> 10), sym = (uint32_t)(k & 1023);
-    st->cw[sym] = s_first[L] + (i - s_start[L]);
+    cw_out[sym] = s_first[L] + (i - s_start[L]);
   }
+}
+
+__global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
+  FrameState *st = bp.frames[blockIdx.x].st;
+  build_code(st, st->hist, st->lens, st->cw);
 }
 
 // ---------------------------------------------------------------- k_count
@@ -1302,7 +1312,11 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
   const uint64_t nwords = (T + 31) / 32;
   const uint64_t off_oidx = fp.off_bits + 4 * nwords;
   const uint64_t off_ores = off_oidx + 4ull * n_out;
-  const uint64_t total = off_ores + 4ull * n_out;
+  // coded ROI: its section closes the stream
+  const uint64_t Troi = fp.roi_coding ? st->Troi : 0;
+  const uint64_t off_rsec = off_ores + 4ull * n_out;
+  const uint64_t off_rbits = off_rsec + kRoiLens + 4ull * fp.npeaks;
+  const uint64_t total = fp.roi_coding ? off_rbits + 4 * ((Troi + 31) / 32) : off_rsec;
   const bool fits = total <= fp.out_cap;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1315,8 +1329,10 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
   uint8_t *o = fp.out;
   if (threadIdx.x == 0) {
     put_u32(o, 0, 0x315A5352u);  // "RSZ1"
-    // version 1; flags: bit 0 bin_mode, bits 1-2 the Lorenzo dimension (0 for 2)
-    const uint32_t flags = (fp.mode & 1u) | ((fp.dim == 2 ? 0u : fp.dim) << 1);
+    // version 1; flags: bit 0 bin_mode, bits 1-2 the Lorenzo dimension (0 for
+    // 2), bit 3 the ROI coded
+    const uint32_t flags =
+        (fp.mode & 1u) | ((fp.dim == 2 ? 0u : fp.dim) << 1) | ((fp.roi_coding & 1u) << 3);
     put_u32(o, 4, 1u | (flags << 16));
     put_u32(o, 8, fp.P);
     put_u32(o, 12, fp.H);
@@ -1335,8 +1351,18 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
     put_u32(o, 60, (uint32_t)(T >> 32));
     put_u32(o, 64, (uint32_t)total);
     put_u32(o, 68, (uint32_t)(total >> 32));
-    put_u32(o, 72, 0u);
-    put_u32(o, 76, 0u);
+    put_u32(o, 72, (uint32_t)Troi);
+    put_u32(o, 76, (uint32_t)(Troi >> 32));
+  }
+  if (fp.roi_coding) {
+    // class code lengths (padded), window bit offsets, zeroed ROI words that
+    // k_roi_pack ORs the codes into
+    for (uint32_t c = threadIdx.x; c < kRoiLens; c += 256)
+      o[off_rsec + c] = c < (uint32_t)kRoiClasses ? fp.roi_lens[c] : 0;
+    uint32_t *roffs = (uint32_t *)(o + off_rsec + kRoiLens);
+    for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) roffs[k] = fp.roi_bits[k];
+    uint32_t *rw = (uint32_t *)(o + off_rbits);
+    for (uint64_t t = threadIdx.x; t < (Troi + 31) / 32; t += 256) rw[t] = 0u;
   }
   // peaks as u16 triples, padded with zeros to 4 bytes
   uint16_t *pk = (uint16_t *)(o + kHeader);
@@ -1373,7 +1399,7 @@ __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
   for (uint32_t kg = first; kg < first + kRoiPeaksPerWave && kg < bp.total_peaks; ++kg) {
     const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
     const FramePlan &fp = bp.frames[f];
-    if (load_status(fp.st) != RSZ_OK) continue;
+    if (fp.roi_coding || load_status(fp.st) != RSZ_OK) continue;
     const uint32_t k = kg - bp.peak_prefix[f];
     const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
     if (pa < 0 || pa >= fp.P) continue;
@@ -1387,6 +1413,179 @@ __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
       uint32_t bits = 0u;
       if (i >= 0 && i < fp.H && j >= 0 && j < fp.W) bits = __float_as_uint(src[i * fp.W + j]);
       dst[e] = bits;
+    }
+  }
+}
+
+// ------------------------------------------------------ coded ROI windows
+
+// Lossless coding of the ROI windows (in place of the paper's fpzip, Sec.
+// IV): a window's payload words b (0 outside the panel) map to
+// order-preserving integers M (b | 2^31 for positive floats, ~b for
+// negative), predicted by the 2D Lorenzo predictor over the window with M =
+// 2^31 (mapped +0.0) outside it.  The zigzag residual z has class c = its bit
+// length (0..32), Huffman coded per frame, then its c - 1 low bits.  Every
+// value's residual depends only on the payload, so all are computed in
+// parallel: k_roi_classes (class histogram), k_roi_book (the code, by the
+// same block function as the main code), k_roi_count and k_roi_scan (window
+// bit offsets), then, after k_tail has checked the size and zeroed the
+// words, k_roi_pack.  One wave per window, kRoiPeaksPerWave windows per wave.
+struct RoiWin {
+  const float *src;
+  int64_t r0, c0, H, W;
+};
+
+__device__ __forceinline__ uint32_t roi_fmap(uint32_t b) {
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ uint32_t roi_word(const RoiWin &rw, int64_t u, int64_t v) {
+  const int64_t i = rw.r0 + u, j = rw.c0 + v;
+  return (i >= 0 && i < rw.H && j >= 0 && j < rw.W) ? __float_as_uint(rw.src[i * rw.W + j]) : 0u;
+}
+__device__ __forceinline__ uint32_t roi_z(const RoiWin &rw, int64_t u, int64_t v) {
+  const uint32_t zero = 0x80000000u;
+  const uint32_t m = roi_fmap(roi_word(rw, u, v));
+  const uint32_t up = u > 0 ? roi_fmap(roi_word(rw, u - 1, v)) : zero;
+  const uint32_t left = v > 0 ? roi_fmap(roi_word(rw, u, v - 1)) : zero;
+  const uint32_t ul = (u > 0 && v > 0) ? roi_fmap(roi_word(rw, u - 1, v - 1)) : zero;
+  const int32_t r = (int32_t)(m - (up + left - ul));
+  return ((uint32_t)r << 1) ^ (uint32_t)(r >> 31);
+}
+__device__ __forceinline__ uint32_t roi_class(uint32_t z) { return z ? 32u - __clz(z) : 0u; }
+
+// The window of global peak kg if its frame codes the ROI and is still fine.
+__device__ __forceinline__ bool roi_window(const BatchPlan &bp, uint32_t kg, uint32_t &f,
+                                           uint32_t &k, RoiWin &rw) {
+  f = find_frame(bp.peak_prefix, bp.nframes, kg);
+  const FramePlan &fp = bp.frames[f];
+  if (!fp.roi_coding || load_status(fp.st) != RSZ_OK) return false;
+  k = kg - bp.peak_prefix[f];
+  const int64_t pa = fp.peaks[3 * k], h = fp.w / 2;
+  if (pa < 0 || pa >= fp.P) return false;
+  rw.src = fp.frame + (size_t)pa * fp.H * fp.W;
+  rw.r0 = fp.peaks[3 * k + 1] - h;
+  rw.c0 = fp.peaks[3 * k + 2] - h;
+  rw.H = fp.H;
+  rw.W = fp.W;
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_roi_classes(BatchPlan bp) {
+  __shared__ uint32_t s_h[kWaves][kRoiClasses];
+  const int lane = threadIdx.x & 63;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t first = (blockIdx.x * kWaves + wv) * kRoiPeaksPerWave;
+  for (uint32_t kg = first; kg < first + kRoiPeaksPerWave && kg < bp.total_peaks; ++kg) {
+    uint32_t f, k;
+    RoiWin rw;
+    if (!roi_window(bp, kg, f, k, rw)) continue;
+    const FramePlan &fp = bp.frames[f];
+    const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+    for (int c = lane; c < kRoiClasses; c += 64) s_h[wv][c] = 0u;
+    wave_sync();
+    for (uint32_t e = lane; e < ww; e += 64) {
+      const uint32_t u = __umulhi(e, M), v = e - u * w;
+      atomicAdd(&s_h[wv][roi_class(roi_z(rw, u, v))], 1u);
+    }
+    wave_sync();
+    for (int c = lane; c < kRoiClasses; c += 64)
+      if (s_h[wv][c]) atomicAdd(&fp.roi_hist[c], s_h[wv][c]);
+    wave_sync();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_roi_book(BatchPlan bp) {
+  const FramePlan &fp = bp.frames[blockIdx.x];
+  if (!fp.roi_coding) return;   // the same frame for the whole workgroup
+  build_code(fp.st, fp.roi_hist, fp.roi_lens, fp.roi_cw);
+}
+
+// Bits of each window (class codeword + raw bits of every value).
+__global__ __launch_bounds__(256) void k_roi_count(BatchPlan bp) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t first = (blockIdx.x * kWaves + wv) * kRoiPeaksPerWave;
+  for (uint32_t kg = first; kg < first + kRoiPeaksPerWave && kg < bp.total_peaks; ++kg) {
+    uint32_t f, k;
+    RoiWin rw;
+    if (!roi_window(bp, kg, f, k, rw)) continue;
+    const FramePlan &fp = bp.frames[f];
+    const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+    uint32_t bits = 0;
+    for (uint32_t e = lane; e < ww; e += 64) {
+      const uint32_t u = __umulhi(e, M), v = e - u * w;
+      const uint32_t c = roi_class(roi_z(rw, u, v));
+      bits += fp.roi_lens[c] + (c >= 2 ? c - 1 : 0u);
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) bits += __shfl_xor(bits, d);
+    if (lane == 0) fp.roi_bits[k] = bits;   // < 2^26 * 63 / npeaks
+  }
+}
+
+// Window bits -> bit offsets (exclusive scan), and the frame's ROI bits.
+__global__ __launch_bounds__(256) void k_roi_scan(BatchPlan bp) {
+  __shared__ uint32_t s_tmp[4];
+  const FramePlan &fp = bp.frames[blockIdx.x];
+  if (!fp.roi_coding || load_status(fp.st) != RSZ_OK) return;   // uniform
+  uint32_t carry = 0;   // npeaks * w^2 <= 2^26 bounds the total below 2^32
+  for (uint32_t k0 = 0; k0 < fp.npeaks; k0 += 256) {
+    const uint32_t k = k0 + threadIdx.x;
+    const uint32_t v = k < fp.npeaks ? fp.roi_bits[k] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<uint32_t>(v, s_tmp, tot);
+    if (k < fp.npeaks) fp.roi_bits[k] = carry + ex;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) fp.st->Troi = carry;
+}
+
+// Writes the n-bit value (n <= 63) MSB-first at bit pos of words (zeroed).
+__device__ __forceinline__ void or_bits(uint32_t *words, uint64_t pos, uint64_t value, uint32_t n) {
+  uint64_t wi = pos >> 5;
+  uint32_t s = (uint32_t)(pos & 31);
+  int rem = (int)n;
+  while (rem > 0) {
+    const int take = min(rem, 32 - (int)s);
+    const uint32_t piece = (uint32_t)((value >> (rem - take)) & ((1ull << take) - 1));
+    if (piece) atomicOr(&words[wi], piece << (32 - s - take));
+    rem -= take;
+    wi++;
+    s = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_roi_pack(BatchPlan bp) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t first = (blockIdx.x * kWaves + wv) * kRoiPeaksPerWave;
+  for (uint32_t kg = first; kg < first + kRoiPeaksPerWave && kg < bp.total_peaks; ++kg) {
+    uint32_t f, k;
+    RoiWin rw;
+    if (!roi_window(bp, kg, f, k, rw)) continue;
+    const FramePlan &fp = bp.frames[f];
+    const FrameState *st = fp.st;
+    const uint64_t off_ores = fp.off_bits + 4 * ((st->T + 31) / 32) + 4ull * st->n_out;
+    uint32_t *words =
+        (uint32_t *)(fp.out + off_ores + 4ull * st->n_out + kRoiLens + 4ull * fp.npeaks);
+    const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+    uint64_t base = fp.roi_bits[k];
+    for (uint32_t e0 = 0; e0 < ww; e0 += 64) {
+      const uint32_t e = e0 + lane;
+      uint32_t n = 0;
+      uint64_t value = 0;
+      if (e < ww) {
+        const uint32_t u = __umulhi(e, M), v = e - u * w;
+        const uint32_t z = roi_z(rw, u, v), c = roi_class(z);
+        const uint32_t extra = c >= 2 ? c - 1 : 0u;
+        n = fp.roi_lens[c] + extra;
+        value = ((uint64_t)fp.roi_cw[c] << extra) | (extra ? (z & ((1u << extra) - 1u)) : 0u);
+      }
+      uint64_t tot;
+      const uint64_t ex = wave_exclusive_scan(n, tot);
+      if (n) or_bits(words, base + ex, value, n);
+      base += tot;
     }
   }
 }
@@ -1459,10 +1658,18 @@ hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
     if (bp.enc_block) RSZ_LAUNCH("k_encode", k_encode_block, bp.total_units, s, bp);
     else RSZ_LAUNCH("k_encode", k_encode, bp.total_units, s, bp);
   }
+  const uint32_t per_wg = kWaves * kRoiPeaksPerWave;
+  const uint32_t roi_grid = (bp.total_peaks + per_wg - 1) / per_wg;
+  if (bp.roi_coding) {
+    if (bp.total_peaks) RSZ_LAUNCH("k_roi_classes", k_roi_classes, roi_grid, s, bp);
+    RSZ_LAUNCH("k_roi_book", k_roi_book, bp.nframes, s, bp);
+    if (bp.total_peaks) RSZ_LAUNCH("k_roi_count", k_roi_count, roi_grid, s, bp);
+    RSZ_LAUNCH("k_roi_scan", k_roi_scan, bp.nframes, s, bp);
+  }
   RSZ_LAUNCH("k_tail", k_tail, bp.nframes, s, bp);
   if (bp.total_peaks) {
-    const uint32_t per_wg = kWaves * kRoiPeaksPerWave;
-    RSZ_LAUNCH("k_roi", k_roi, (bp.total_peaks + per_wg - 1) / per_wg, s, bp);
+    RSZ_LAUNCH("k_roi", k_roi, roi_grid, s, bp);
+    if (bp.roi_coding) RSZ_LAUNCH("k_roi_pack", k_roi_pack, roi_grid, s, bp);
   }
   return hipSuccess;
 }

@@ -475,13 +475,153 @@ __global__ __launch_bounds__(256) void k_dec_expand(DecodePlan dp) {
   }
 }
 
+// ------------------------------------------------------- coded ROI windows
+
+// Tables of the ROI class code: per length L the first canonical code, the
+// number of classes and where they start in the (length, class) order, then
+// that order.  The lengths must be a complete prefix code (or one class of
+// length 1), padding zero; no class at all when there is no window.
+constexpr int kRoiTabFirst = 0, kRoiTabCount = 33, kRoiTabBase = 66, kRoiTabSym = 99;
+constexpr int kRoiTabWords = 132;
+
+__global__ __launch_bounds__(64) void k_dec_roi_tables(DecodePlan dp) {
+  if (threadIdx.x != 0 || !dec_ok(dp.status)) return;
+  const uint8_t *lens = dp.in + dp.off_rsec;
+  uint32_t *t = dp.roi_tables;
+  uint64_t kraft = 0;
+  int used = 0;
+  bool bad = false;
+  for (int c = 0; c < (int)kRoiLens; ++c) {
+    const uint32_t L = lens[c];
+    if (c >= kRoiClasses ? L != 0 : L > (uint32_t)kMaxLen) bad = true;
+    if (c < kRoiClasses && L && L <= (uint32_t)kMaxLen) {
+      kraft += 1ull << (kMaxLen - L);
+      used++;
+    }
+  }
+  if (dp.npeaks == 0) bad |= used != 0;
+  else bad |= !(kraft == (1ull << kMaxLen) || (used == 1 && kraft == (1ull << (kMaxLen - 1))));
+  if (bad) {
+    corrupt(dp.status);
+    return;
+  }
+  uint32_t code = 0, n = 0, prev_count = 0;
+  for (int L = 1; L <= kMaxLen; ++L) {
+    code = (code + prev_count) << 1;
+    uint32_t cnt = 0;
+    t[kRoiTabBase + L - 1] = n;
+    for (int c = 0; c < kRoiClasses; ++c)
+      if (lens[c] == L) t[kRoiTabSym + n + cnt++] = (uint32_t)c;
+    t[kRoiTabFirst + L - 1] = code;
+    t[kRoiTabCount + L - 1] = cnt;
+    n += cnt;
+    prev_count = cnt;
+  }
+}
+
+// 32 stream bits from bit pos (zeros past the last word).
+__device__ __forceinline__ uint32_t roi_peek(const uint32_t *words, uint64_t nwords, uint64_t pos) {
+  const uint64_t i = pos >> 5;
+  const uint64_t w0 = i < nwords ? words[i] : 0u, w1 = i + 1 < nwords ? words[i + 1] : 0u;
+  return (uint32_t)((((w0 << 32) | w1) << (pos & 31)) >> 32);
+}
+
+// One lane per window: decode its classes and raw bits into the zigzag
+// residuals, written as r (mod 2^32) to roi_payload.  A window must start at
+// its offset (the first at 0) and end exactly at the next offset, the last
+// at Troi.
+__global__ __launch_bounds__(256) void k_dec_roi_decode(DecodePlan dp) {
+  const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= dp.npeaks || !dec_ok(dp.status)) return;
+  const uint32_t *t = dp.roi_tables;
+  const uint32_t *offs = (const uint32_t *)(dp.in + dp.off_roffs);
+  const uint32_t *words = (const uint32_t *)(dp.in + dp.off_rbits);
+  const uint64_t nwords = (dp.Troi + 31) / 32;
+  const uint64_t start = offs[k], end = k + 1 < dp.npeaks ? offs[k + 1] : dp.Troi;
+  if ((k == 0 && start != 0) || end < start || end > dp.Troi) {
+    corrupt(dp.status);
+    return;
+  }
+  const uint64_t ww = (uint64_t)dp.w * dp.w;
+  uint32_t *out = dp.roi_payload + k * ww;
+  uint64_t pos = start;
+  for (uint64_t e = 0; e < ww; ++e) {
+    const uint32_t peek = roi_peek(words, nwords, pos);
+    int cls = -1, L = 1;
+    for (; L <= kMaxLen; ++L) {
+      const uint32_t code = peek >> (32 - L);
+      const uint32_t cnt = t[kRoiTabCount + L - 1], first = t[kRoiTabFirst + L - 1];
+      if (cnt && code - first < cnt) {
+        cls = (int)t[kRoiTabSym + t[kRoiTabBase + L - 1] + (code - first)];
+        break;
+      }
+    }
+    if (cls < 0 || pos + L > end) {
+      corrupt(dp.status);
+      return;
+    }
+    pos += L;
+    uint32_t z = cls == 0 ? 0u : 1u;
+    if (cls >= 2) {
+      const uint32_t extra = (uint32_t)cls - 1;
+      if (pos + extra > end) {
+        corrupt(dp.status);
+        return;
+      }
+      z = (1u << extra) | (roi_peek(words, nwords, pos) >> (32 - extra));
+      pos += extra;
+    }
+    out[e] = (z >> 1) ^ (0u - (z & 1u));
+  }
+  if (pos != end) corrupt(dp.status);
+}
+
+// One wave per window: undo the prediction.  With D = M - 2^31 (zero outside
+// the window), D(u, v) = r + D(u-1, v) + D(u, v-1) - D(u-1, v-1), so D is the
+// 2D prefix sum of r: a wave scan along each row plus the column sums kept
+// per lane.  Then M = D + 2^31 maps back to the float bits.
+constexpr int kRoiMaxChunks = 16;   // w <= 1023: 16 chunks of 64 columns
+__global__ __launch_bounds__(256) void k_dec_roi_unpred(DecodePlan dp) {
+  const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= dp.npeaks || !dec_ok(dp.status)) return;
+  const uint32_t w = dp.w;
+  uint32_t *win = dp.roi_payload + (uint64_t)k * w * w;
+  uint32_t col[kRoiMaxChunks];
+#pragma unroll
+  for (int c = 0; c < kRoiMaxChunks; ++c) col[c] = 0u;
+  for (uint32_t u = 0; u < w; ++u) {
+    uint32_t carry = 0;
+#pragma unroll
+    for (int c = 0; c < kRoiMaxChunks; ++c) {
+      if (c * 64 < (int)w) {   // uniform
+        const uint32_t v = c * 64 + lane;
+        uint32_t x = v < w ? win[u * w + v] : 0u;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t y = __shfl_up(x, d);
+          if (lane >= d) x += y;
+        }
+        x += carry;
+        carry = __shfl(x, 63);
+        col[c] += x;   // D(u, v) = row prefix of row u + D(u - 1, v)
+        if (v < w) {
+          const uint32_t m = col[c] + 0x80000000u;
+          win[u * w + v] = (m & 0x80000000u) ? (m & 0x7FFFFFFFu) : ~m;
+        }
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_dec_roi(DecodePlan dp) {
   if (!dec_ok(dp.status)) return;
   const uint64_t ww = (uint64_t)dp.w * dp.w;
   const uint64_t n = (uint64_t)dp.npeaks * ww;
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   const uint16_t *pk = (const uint16_t *)(dp.in + dp.off_peaks);
-  const uint32_t *pay = (const uint32_t *)(dp.in + dp.off_roi);
+  const uint32_t *pay =
+      dp.roi_coding ? dp.roi_payload : (const uint32_t *)(dp.in + dp.off_roi);
   const int64_t h = dp.w / 2;
   for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) {
     const uint64_t k = e / ww, rem = e - k * ww;
@@ -501,7 +641,8 @@ __global__ __launch_bounds__(256) void k_dec_roi_check(DecodePlan dp) {
   const uint64_t n = (uint64_t)dp.npeaks * ww;
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   const uint16_t *pk = (const uint16_t *)(dp.in + dp.off_peaks);
-  const uint32_t *pay = (const uint32_t *)(dp.in + dp.off_roi);
+  const uint32_t *pay =
+      dp.roi_coding ? dp.roi_payload : (const uint32_t *)(dp.in + dp.off_roi);
   const int64_t h = dp.w / 2;
   bool bad = false;
   for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) {
@@ -543,6 +684,13 @@ hipError_t launch_decompress(const DecodePlan &dp, hipStream_t s) {
   RSZ_DLAUNCH("k_dec_expand", k_dec_expand, (uint32_t)std::min<uint64_t>((npix + 255) / 256, 1u << 20),
               256, s);
   const uint64_t nroi = (uint64_t)dp.npeaks * dp.w * dp.w;
+  if (dp.roi_coding) {
+    RSZ_DLAUNCH("k_dec_roi_tables", k_dec_roi_tables, 1, 64, s);
+    if (dp.npeaks) {
+      RSZ_DLAUNCH("k_dec_roi_decode", k_dec_roi_decode, (dp.npeaks + 255) / 256, 256, s);
+      RSZ_DLAUNCH("k_dec_roi_unpred", k_dec_roi_unpred, (dp.npeaks + 3) / 4, 256, s);
+    }
+  }
   if (nroi) {
     const uint32_t g = (uint32_t)std::min<uint64_t>((nroi + 255) / 256, 1u << 20);
     RSZ_DLAUNCH("k_dec_roi", k_dec_roi, g, 256, s);
@@ -552,5 +700,6 @@ hipError_t launch_decompress(const DecodePlan &dp, hipStream_t s) {
 }
 
 uint64_t decode_tables_bytes() { return 4ull * kTabWords; }
+uint64_t decode_roi_tables_bytes() { return 4ull * kRoiTabWords; }
 
 }  // namespace rsz

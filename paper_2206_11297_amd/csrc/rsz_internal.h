@@ -15,6 +15,8 @@ constexpr int kMaxLen = 32;           // longest Huffman codeword
 constexpr uint32_t kChunk = 4096;     // symbols between bitstream sync offsets
 constexpr double kQMax = 268435455.0; // |q| <= 2^28 - 1
 constexpr uint64_t kHeader = 80;
+constexpr int kRoiClasses = 33;       // coded ROI: bit lengths 0..32 of the zigzag residual
+constexpr uint64_t kRoiLens = 36;     // their code lengths, padded
 
 // Binning kernel geometry: 4 independent waves per workgroup, each owning a
 // tile of one panel: a segment of up to kMaxTH bin rows x a column group of
@@ -40,6 +42,7 @@ struct FrameState {
   uint32_t n_out;
   uint64_t T;          // bitstream bits
   uint64_t total;      // stream bytes
+  uint64_t Troi;       // coded ROI bits
   uint32_t hist[kNumSym];
   uint32_t cw[kNumSym];
   uint8_t lens[kNumSym];
@@ -49,6 +52,7 @@ struct FrameState {
 struct FramePlan {
   uint32_t P, H, W, w, b, mode;
   uint32_t dim;             // Lorenzo dimension: 1, 2 or 3
+  uint32_t roi_coding;      // ROI windows coded (1) or verbatim (0)
   double eb, step;          // step = 2*eb
   uint32_t Hb, Wb, nbins, nchunks;
   uint32_t npeaks, TH, segs, groups;   // segments per panel, workgroups per panel
@@ -74,6 +78,12 @@ struct FramePlan {
   uint32_t *bstart;         // P*segs+1 starts of the peak bands: band k =
                             // (panel k / segs, raw rows [(k % segs)*TH*b, +TH*b))
   uint32_t *bucket;         // npeaks peaks as (row << 16 | col), grouped by band
+  // coded ROI (else null): class histogram, code lengths and codewords (over
+  // kNumSym entries, the first kRoiClasses used), window bits then offsets
+  uint32_t *roi_hist;
+  uint8_t *roi_lens;
+  uint32_t *roi_cw;
+  uint32_t *roi_bits;
   int32_t *qedge;           // dim 1: q of the last bin of each of the P*Hb bin
                             // rows (those k_lorenzo_dims reads), else null
   FrameState *st;
@@ -93,6 +103,7 @@ struct BatchPlan {
   uint32_t cpw;                  // chunks encoded by one k_encode workgroup
   uint32_t enc_block;            // small batch: a workgroup packs one chunk at a time
   uint32_t total_fix;            // workgroups of k_lorenzo_dims (0: every frame is 2D)
+  uint32_t roi_coding;           // some frame codes its ROI windows
   const FramePlan *frames;
   const uint32_t *tile_prefix;   // nframes + 1
   const uint32_t *unit_prefix;   // nframes + 1 (units of cpw chunks)
@@ -113,7 +124,11 @@ hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s);
 
 // Decompression plan and launchers (decompress.hip).
 struct DecodePlan {
-  uint32_t P, H, W, w, b, npeaks, dim;
+  uint32_t P, H, W, w, b, npeaks, dim, roi_coding;
+  uint64_t Troi;
+  uint64_t off_rsec, off_roffs, off_rbits;   // coded ROI section
+  uint32_t *roi_payload;                      // coded ROI: npeaks*w*w decoded words
+  uint32_t *roi_tables;                       // coded ROI: decode tables
   double step;
   uint32_t Hb, Wb, nbins, nchunks, n_out;
   uint64_t T, total;

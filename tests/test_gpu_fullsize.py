@@ -69,8 +69,8 @@ def _check_headers(B, sizes, shape, w, b, eb, counts):
         assert d["stream_bytes"] == int(sizes[i]) == d["off"]["total"], f"frame {i}"
 
 
-def _check_oracle(B, sizes, host, idx, shape, w, b, eb, dim=2):
-    p = O.params(*shape, w, b, eb, 0, dim)
+def _check_oracle(B, sizes, host, idx, shape, w, b, eb, dim=2, roi_coding=0):
+    p = O.params(*shape, w, b, eb, 0, dim, roi_coding)
     for i in idx:
         print(f"  oracle frame {i} ({host[i][1].shape[0]} peaks)", flush=True)
         st, ref, _ = O.compress(p, *host[i])
@@ -121,6 +121,22 @@ def test_cspad_batch_1000_lorenzo_dims(torch, cspad_1000, dim):
     for i in range(len(counts)):
         flags = int(heads[B.offsets[i] + 6]) | int(heads[B.offsets[i] + 7]) << 8
         assert flags == dim << 1, f"frame {i}"
+
+
+def test_cspad_batch_1000_roi_coded(torch, cspad_1000):
+    host, frames, peaks = cspad_1000
+    print("cspad batch 1000 roi coded", flush=True)
+    B = rsz.Batch(frames, peaks, (17, 2, 10.0, 0, 2, 1))
+    B.run()
+    torch.cuda.synchronize()
+    assert (B.status.cpu().numpy() == 0).all()
+    sizes = B.sizes.cpu().numpy()
+    counts = [p.shape[0] for _, p in host]
+    _check_oracle(B, sizes, host, _sample(counts, 8, 200), (32, 185, 388), 17, 2, 10.0, 2, 1)
+    # every stream's sections add up to its size (independent reader)
+    for i in range(0, len(counts), 97):
+        d = F.parse(B.stream(i, sizes).cpu().numpy())
+        assert d["roi_coded"] and d["stream_bytes"] == int(sizes[i]) == d["off"]["total"]
 
 
 # ------------------------------------------------------ Jungfrau-4M x 256

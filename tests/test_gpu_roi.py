@@ -1,0 +1,146 @@
+"""GPU parity of the lossless ROI coding (the windows Sec. IV keeps exactly,
+coded by the predictive float coder): stream bytes and decompressed frames
+bit for bit against the oracle, through the C ABI, on small and ragged
+frames, special values, CSPAD and Jungfrau frames, mixed batches with graph
+replays, and corrupt coded sections (same status as the oracle)."""
+import numpy as np
+import pytest
+
+from oracle import rsz_oracle as O
+from paper_2206_11297_amd import rsz, synth
+from tests import streamfmt as F
+from tests.test_gpu_parity import TINY
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    rsz.lib()
+    return t
+
+
+def _gpu(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _check(torch, frame, peaks, w, b, eb, mode=0, dim=2):
+    st, ref, _ = O.compress(O.params(*frame.shape, w, b, eb, mode, dim, 1), frame, peaks)
+    assert st == O.OK
+    got = rsz.compress(_gpu(torch, frame), _gpu(torch, peaks), w, b, eb, mode, dim=dim,
+                       roi_coding=1)
+    np.testing.assert_array_equal(got.cpu().numpy(), ref)
+    st, yref = O.decompress(ref)
+    assert st == O.OK
+    y = rsz.decompress(got)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(y.cpu().numpy().view(np.uint32), yref.view(np.uint32))
+    return ref
+
+
+@pytest.mark.parametrize("case", TINY, ids=[f"seed{c[0]}" for c in TINY])
+def test_small_frames(torch, case):
+    seed, shape, npk, w, b, eb, kind = case
+    frame, peaks = synth.tiny_case(seed, shape, npk, kind)
+    print(f"case seed={seed} shape={shape} npk={npk} w={w}", flush=True)
+    _check(torch, frame, peaks, w, b, eb)
+
+
+def test_special_values_and_edges(torch):
+    f = np.random.default_rng(3).normal(0.0, 3.0, (2, 20, 24)).astype(np.float32)
+    f[0, 5, 5] = np.nan
+    f[0, 5, 6] = np.inf
+    f[0, 6, 5] = -np.inf
+    f[0, 6, 6] = -0.0
+    f[0, 4, 4] = np.float32(1e-45)
+    f[1, :3, :3] = 0.0
+    peaks = np.array([[0, 5, 5], [0, 0, 0], [1, 19, 23], [1, 1, 1], [0, 5, 5]], np.int32)
+    _check(torch, f, peaks, 9, 2, 1.0)
+    # no windows at all (the non-finite pixels would be background there)
+    _check(torch, np.nan_to_num(f, nan=0.0, posinf=0.0, neginf=0.0), np.zeros((0, 3), np.int32),
+           9, 2, 1.0)
+    _check(torch, f, peaks[:1], 9, 1, 1.0)   # one window over every special value
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_cspad_and_jungfrau(torch, dim):
+    frame, peaks = synth.cspad_frame(0)
+    _check(torch, frame, peaks, 17, 2, 10.0, dim=dim)
+    frame, peaks = synth.jungfrau_frame(1)
+    print(f"jungfrau {peaks.shape[0]} peaks", flush=True)
+    _check(torch, frame, peaks, 25, 4, 10.0, dim=dim)
+
+
+def test_batch_mixed_coding_and_graph(torch):
+    cases = [synth.cspad_frame(7), synth.tiny_case(40, (2, 50, 90), 3, "normal"),
+             synth.jungfrau_frame(2), synth.cspad_frame(8, npeaks=0),
+             synth.tiny_case(41, (1, 1, 1), 1, "normal")]
+    prm = [(17, 2, 10.0, 0, 2, 1), (5, 3, 1.0, 1, 1, 1), (11, 4, 10.0, 0, 2, 0),
+           (17, 2, 5.0, 0, 3, 1), (1, 1, 1.0, 0, 2, 1)]
+    frames = [_gpu(torch, f) for f, _ in cases]
+    peaks = [_gpu(torch, p) for _, p in cases]
+
+    def refs(cur):
+        out = []
+        for (f, pk), t in zip(cur, prm):
+            st, ref, _ = O.compress(O.params(*f.shape, *t), f, pk)
+            assert st == O.OK
+            out.append(ref)
+        return out
+
+    B = rsz.Batch(frames, peaks, prm)
+    B.run()
+    torch.cuda.synchronize()
+    assert B.status.cpu().tolist() == [0] * len(cases)
+    for i, ref in enumerate(refs(cases)):
+        np.testing.assert_array_equal(B.stream(i).cpu().numpy(), ref)
+    B.prepare()
+    B.graph()
+    rng = np.random.default_rng(79)
+    for rep in range(3):
+        cur = []
+        for (f, pk), g in zip(cases, frames):
+            f2 = (f + rng.normal(0, 3, f.shape)).astype(np.float32)
+            g.copy_(torch.from_numpy(f2))
+            cur.append((f2, pk))
+        torch.cuda.synchronize()
+        B.replay()
+        torch.cuda.synchronize()
+        assert B.status.cpu().tolist() == [0] * len(cases)
+        for i, ref in enumerate(refs(cur)):
+            np.testing.assert_array_equal(B.stream(i).cpu().numpy(), ref)
+
+
+def test_capacity_reports_the_coded_size(torch):
+    frame, peaks = synth.cspad_frame(3)
+    st, ref, need = O.compress(O.params(32, 185, 388, 17, 2, 10.0, 0, 2, 1), frame, peaks)
+    p = rsz.params(32, 185, 388, 17, 2, 10.0, 0, 2, 1)
+    g, pk = _gpu(torch, frame), _gpu(torch, peaks)
+    out = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
+    ws = rsz.workspace(rsz.rsz_workspace_bytes(p, peaks.shape[0])[1])
+    st, n = rsz.rsz_compress(p, rsz._ptr(g), rsz._ptr(pk), peaks.shape[0], rsz._ptr(out),
+                             out.numel(), rsz._ptr(ws), ws.numel(), rsz._stream())
+    assert st == rsz.RSZ_ERR_CAPACITY and n == need
+
+
+def test_corrupt_coded_sections_match_oracle(torch):
+    frame, peaks = synth.tiny_case(14, (2, 12, 16), 3, "normal", scale=200.0)
+    st, s1, _ = O.compress(O.params(2, 12, 16, 5, 2, 1.0, 0, 2, 1), frame, peaks)
+    rsec = F.parse(s1)["off"]["rsec"]
+    rng = np.random.default_rng(81)
+    for t in range(80):
+        s2 = s1.copy()
+        pos = int(rng.integers(rsec, s2.size))
+        s2[pos] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        sto, yo = O.decompress(s2)
+        try:
+            y = rsz.decompress(_gpu(torch, s2)).cpu().numpy()
+            stg = 0
+        except rsz.RszError as e:
+            stg = e.status
+        assert stg == sto, (t, pos)
+        if sto == 0:
+            np.testing.assert_array_equal(y.view(np.uint32), yo.view(np.uint32))
