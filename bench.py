@@ -176,6 +176,37 @@ def lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips
     return out
 
 
+def roi_coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_strips):
+    """The same batch with the ROI windows coded losslessly instead of stored
+    verbatim: whole-path GB/s, compression ratio and per-kernel times."""
+    import numpy as np
+    from paper_2206_11297_amd import rsz
+    B = rsz.Batch(frames, peaks, prm + (2, 1), tile_rows=tile_rows, tile_strips=tile_strips)
+    for _ in range(2):
+        B.run()
+    torch.cuda.synchronize()
+    st = B.status.cpu().numpy()
+    assert (st == 0).all(), f"roi coding: statuses {set(st.tolist())}"
+    rsz.rsz_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.roi_steps):
+        B.run()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.roi_steps
+    prof = rsz.rsz_profile_read()
+    rsz.rsz_profile_enable(False)
+    sizes = B.sizes.cpu().numpy().astype(np.int64)
+    out = {"value": round(raw_bytes / el / 1e9, 2), "unit": "GB/s", "ms_per_step": round(el * 1e3, 4),
+           "steps": args.roi_steps,
+           "compression_ratio_u16_aggregate": round(float(raw_bytes / 2 / sizes.sum()), 3),
+           "kernel_ms": {k: round(v[1] / v[0], 4) for k, v in prof.items()}}
+    print(f"[bench] roi coding: {out['value']} GB/s, CR {out['compression_ratio_u16_aggregate']}",
+          file=sys.stderr, flush=True)
+    del B
+    torch.cuda.empty_cache()
+    return out
+
+
 def peaks_section(args, torch, frames, prm, raw_bytes, tile_rows, tile_strips):
     """Peak finding on the GPU over the same batch (the step before the path,
     Sec. V-A parameters), and the frames-in, streams-out pipeline: peaks found,
@@ -417,6 +448,8 @@ def main():
     ap.add_argument("--dims", type=int, nargs="*", default=[1, 3],
                     help="Lorenzo dimensions timed besides 2 on the same batch")
     ap.add_argument("--dims-steps", type=int, default=10)
+    ap.add_argument("--roi-steps", type=int, default=10,
+                    help="steps of the ROI-coding section (0: skip it)")
     ap.add_argument("--peaks-steps", type=int, default=10,
                     help="steps of the peak-finding section (0: skip it)")
     args = ap.parse_args()
@@ -534,6 +567,8 @@ def main():
     serving = serving_section(args, torch, dev) if args.serve_rates else None
     dims = lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips,
                                 raw_bytes) if args.dims else None
+    roi = roi_coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows,
+                             tile_strips) if args.roi_steps else None
     pk = peaks_section(args, torch, frames, prm, raw_bytes, tile_rows,
                        tile_strips) if args.peaks_steps else None
 
@@ -566,6 +601,7 @@ def main():
         "serving": serving,
         "decompress": decomp,
         "lorenzo_dims": dims,
+        "roi_coding": roi,
         "peak_finding": pk,
     }
     if serving:
