@@ -62,6 +62,8 @@ typedef struct {
   double eb;                      /* absolute bound on binned values       */
   uint32_t dim;                   /* Lorenzo dimension 1, 2 or 3; 0 means 2 */
   uint32_t roi_coding;            /* 0: ROI payload verbatim, 1: coded    */
+  uint32_t run_coding;            /* 0: Huffman bits as they are, 1: runs */
+  uint32_t reserved;
 } ro_params;
 
 static uint32_t ro_dim(const ro_params *p) { return p->dim ? p->dim : 2u; }
@@ -74,7 +76,8 @@ static uint64_t ro_nbins(const ro_params *p) { return (uint64_t)p->panels * ro_h
 static uint64_t ro_align4(uint64_t x) { return (x + 3u) & ~(uint64_t)3u; }
 
 /* Argument validation.  Limits: each dimension 1..65535, window 1..1023,
- * bin 1..8, bin_mode 0/1, dim 0..3, eb finite and > 0, pixels < 2^31, bins < 2^27,
+ * bin 1..8, bin_mode 0/1, dim 0..3, roi_coding and run_coding 0/1, reserved 0,
+ * eb finite and > 0, pixels < 2^31, bins < 2^27 (so T and Trun fit u32 offsets),
  * npeaks * w * w <= 2^28 payload words. */
 int ro_check_params(const ro_params *p, uint32_t npeaks) {
   if (!p) return RO_ERR_ARG;
@@ -83,7 +86,8 @@ int ro_check_params(const ro_params *p, uint32_t npeaks) {
     return RO_ERR_ARG;
   if (p->window < 1 || p->window > 1023) return RO_ERR_ARG;
   if (p->bin < 1 || p->bin > 8) return RO_ERR_ARG;
-  if (p->bin_mode > 1 || p->dim > 3 || p->roi_coding > 1) return RO_ERR_ARG;
+  if (p->bin_mode > 1 || p->dim > 3 || p->roi_coding > 1 || p->run_coding > 1 || p->reserved)
+    return RO_ERR_ARG;
   if (!(p->eb > 0.0) || !isfinite(p->eb)) return RO_ERR_ARG;
   if ((uint64_t)p->panels * p->height * p->width >= (1ull << 31)) return RO_ERR_ARG;
   if (ro_nbins(p) >= (1ull << 27)) return RO_ERR_ARG;
@@ -386,30 +390,97 @@ uint64_t ro_bitstream(uint64_t nbins, const uint16_t *codes, const uint8_t *len,
 
 /* Section order: header, peaks, ROI payload, code lengths, chunk offsets,
  * bitstream, outlier indices, outlier residuals.  With the ROI coded the
- * verbatim payload is absent and the coded ROI section closes the stream:
+ * verbatim payload is absent and the coded ROI section follows the outliers:
  * 33 class code lengths (u8, padded to 36 bytes), one u32 bit offset per
- * window, then the ROI bitstream (Troi bits in u32 words). */
+ * window, then the ROI bitstream (Troi bits in u32 words).  With the runs
+ * coded the bitstream is absent and the run section closes the stream: one
+ * Rice parameter per chunk (u8, padded to 4 bytes), nchunks + 1 u32 bit
+ * offsets (the last one the section's bits, Trun), then Trun bits. */
 #define RO_ROI_CLASSES 33
 #define RO_ROI_LENS 36
+#define RO_RUN_KMAX 20
 typedef struct {
-  uint64_t peaks, roi, lens, chunks, bits, oidx, ores, rsec, roffs, rbits, total;
+  uint64_t peaks, roi, lens, chunks, bits, oidx, ores, rsec, roffs, rbits, run, runoffs, runbits,
+      total;
 } ro_layout;
 
 static ro_layout ro_sections(const ro_params *p, uint32_t npeaks, uint64_t n_out,
-                             uint64_t n_chunks, uint64_t T, uint64_t Troi) {
+                             uint64_t n_chunks, uint64_t T, uint64_t Troi, uint64_t Trun) {
   ro_layout L;
   L.peaks = RO_HEADER;
   L.roi = L.peaks + ro_align4(6ull * npeaks);
   L.lens = L.roi + (p->roi_coding ? 0 : 4ull * npeaks * p->window * p->window);
   L.chunks = L.lens + RO_NSYM;
   L.bits = L.chunks + 4ull * n_chunks;
-  L.oidx = L.bits + 4ull * ((T + 31) / 32);
+  L.oidx = L.bits + (p->run_coding ? 0 : 4ull * ((T + 31) / 32));
   L.ores = L.oidx + 4ull * n_out;
   L.rsec = L.ores + 4ull * n_out;
   L.roffs = L.rsec + RO_ROI_LENS;
   L.rbits = L.roffs + 4ull * npeaks;
-  L.total = p->roi_coding ? L.rbits + 4ull * ((Troi + 31) / 32) : L.rsec;
+  L.run = p->roi_coding ? L.rbits + 4ull * ((Troi + 31) / 32) : L.rsec;
+  L.runoffs = L.run + ro_align4(n_chunks);
+  L.runbits = L.runoffs + 4ull * (n_chunks + 1);
+  L.total = p->run_coding ? L.runbits + 4ull * ((Trun + 31) / 32) : L.run;
   return L;
+}
+
+/* ------------------------------------------------- lossless run stage */
+
+/* A lossless stage after the Huffman coder (SZ follows its Huffman stage with
+ * a lossless compressor; here one written for these bits).  The most common
+ * code (residual 0) is the all-zero codeword, so the Huffman bits are mostly
+ * zeros.  Per 4096-symbol chunk, the chunk's bits [off_c, off_c+1) are coded
+ * as the lengths r of the zero runs before each 1 bit, Rice coded with the
+ * chunk's parameter k: r >> k one bits, a zero bit, then the k low bits of r,
+ * MSB-first.  Zeros after the chunk's last 1 are implied by its length.  k
+ * (0..20) minimises the chunk's coded bits, the smallest k on ties. */
+static uint32_t ro_getbit(const uint32_t *words, uint64_t k) {
+  return (words[k / 32] >> (31 - k % 32)) & 1u;
+}
+
+/* Codes T Huffman bits in chunks starting at chunk_off[0..nc); writes the
+ * parameters kpar[nc], offsets runoffs[nc + 1] and, if out is not NULL
+ * (zeroed), the run bits; returns Trun. */
+uint64_t ro_run_code(const uint32_t *words, uint64_t T, const uint32_t *chunk_off, uint64_t nc,
+                     uint8_t *kpar, uint32_t *runoffs, uint32_t *out) {
+  uint64_t pos = 0;
+  for (uint64_t c = 0; c < nc; ++c) {
+    const uint64_t start = chunk_off[c], end = c + 1 < nc ? chunk_off[c + 1] : T;
+    uint64_t cost[RO_RUN_KMAX + 1];
+    memset(cost, 0, sizeof cost);
+    uint64_t prev = start;   /* first position after the previous 1 */
+    for (uint64_t b = start; b < end; ++b)
+      if (ro_getbit(words, b)) {
+        for (uint32_t k = 0; k <= RO_RUN_KMAX; ++k) cost[k] += ((b - prev) >> k) + 1 + k;
+        prev = b + 1;
+      }
+    uint32_t best = 0;
+    for (uint32_t k = 1; k <= RO_RUN_KMAX; ++k)
+      if (cost[k] < cost[best]) best = k;
+    kpar[c] = (uint8_t)best;
+    runoffs[c] = (uint32_t)pos;
+    if (out) {
+      prev = start;
+      for (uint64_t b = start; b < end; ++b)
+        if (ro_getbit(words, b)) {
+          const uint64_t r = b - prev;
+          for (uint64_t q = 0; q < (r >> best); ++q) {
+            out[pos / 32] |= 1u << (31 - pos % 32);
+            pos++;
+          }
+          pos++;   /* the zero that ends the unary part */
+          for (uint32_t t = 0; t < best; ++t) {
+            if ((r >> (best - 1 - t)) & 1u) out[pos / 32] |= 1u << (31 - pos % 32);
+            pos++;
+          }
+          prev = b + 1;
+        }
+    } else {
+      pos += cost[best];
+    }
+  }
+  runoffs[nc] = (uint32_t)pos;
+  return pos;
 }
 
 /* ---------------------------------------------------- lossless ROI coding */
@@ -507,9 +578,9 @@ int ro_max_bytes(const ro_params *p, uint32_t npeaks, uint64_t *bytes) {
   if (st) return st;
   const uint64_t nb = ro_nbins(p), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
   /* worst case: every code 32 bits, every bin an outlier, every ROI value 63
-   * bits */
-  *bytes = ro_sections(p, npeaks, nb, nc, 32ull * nb,
-                       63ull * npeaks * p->window * p->window).total;
+   * bits; the run section never exceeds the bits it codes */
+  *bytes = ro_sections(p, npeaks, nb, nc, 32ull * nb, 63ull * npeaks * p->window * p->window,
+                       32ull * nb).total;
   return RO_OK;
 }
 
@@ -602,7 +673,13 @@ int ro_compress(const ro_params *p, const float *frame, const int32_t *peaks, ui
     uint8_t rl[RO_ROI_CLASSES];
     ro_roi(p, frame, peaks, npeaks, pay);
     const uint64_t Troi = p->roi_coding ? ro_roi_code(p, pay, npeaks, rl, roffs, NULL) : 0;
-    const ro_layout L = ro_sections(p, npeaks, n_out, nc, T, Troi);
+    /* the Huffman bits, and their run coding when asked for */
+    uint32_t *hw = (uint32_t *)calloc((size_t)((T + 31) / 32 + 1), 4);
+    uint8_t *kpar = (uint8_t *)malloc((size_t)nc + 1);
+    uint32_t *runoffs = (uint32_t *)malloc(4 * (size_t)(nc + 1));
+    ro_bitstream(nb, cd, l, c, hw, NULL);
+    const uint64_t Trun = p->run_coding ? ro_run_code(hw, T, co, nc, kpar, runoffs, NULL) : 0;
+    const ro_layout L = ro_sections(p, npeaks, n_out, nc, T, Troi, Trun);
     *out_bytes = L.total;
     if (L.total > out_cap) {
       st = RO_ERR_CAPACITY;
@@ -611,9 +688,9 @@ int ro_compress(const ro_params *p, const float *frame, const int32_t *peaks, ui
       memcpy(out, "RSZ1", 4);
       put16(out, 4, 1);
       /* flags: bit 0 bin_mode, bits 1-2 the Lorenzo dimension (0 for the
-       * default 2, else 1 or 3) */
+       * default 2, else 1 or 3), bit 3 the ROI coded, bit 4 the runs coded */
       put16(out, 6, (uint16_t)((p->bin_mode & 1u) | ((ro_dim(p) == 2 ? 0u : ro_dim(p)) << 1) |
-                               ((p->roi_coding & 1u) << 3)));
+                               ((p->roi_coding & 1u) << 3) | ((p->run_coding & 1u) << 4)));
       put32(out, 8, p->panels);
       put32(out, 12, p->height);
       put32(out, 16, p->width);
@@ -642,9 +719,14 @@ int ro_compress(const ro_params *p, const float *frame, const int32_t *peaks, ui
         put32(out, L.ores + 4ull * k, (uint32_t)orr[k]);
       }
       for (uint64_t k = 0; k < nc; ++k) put32(out, L.chunks + 4 * k, co[k]);
-      ro_bitstream(nb, cd, l, c, (uint32_t *)(out + L.bits), NULL);
+      if (p->run_coding) {
+        ro_run_code(hw, T, co, nc, out + L.run, runoffs, (uint32_t *)(out + L.runbits));
+        for (uint64_t k = 0; k <= nc; ++k) put32(out, L.runoffs + 4 * k, runoffs[k]);
+      } else {
+        ro_bitstream(nb, cd, l, c, (uint32_t *)(out + L.bits), NULL);
+      }
     }
-    free(pay); free(roffs);
+    free(pay); free(roffs); free(hw); free(kpar); free(runoffs);
   }
   free(m); free(s); free(cnt); free(qq); free(rr); free(cd); free(oi); free(orr); free(co);
   return st;
@@ -659,10 +741,12 @@ int ro_stream_info(const uint8_t *in, uint64_t in_bytes, ro_params *p, uint32_t 
     return RO_ERR_CORRUPT;
   ro_params q;
   const uint32_t flags = get16(in, 6), dcode = (flags >> 1) & 3u;
-  if ((flags >> 4) != 0 || dcode == 2) return RO_ERR_CORRUPT;
+  if ((flags >> 5) != 0 || dcode == 2) return RO_ERR_CORRUPT;
+  memset(&q, 0, sizeof q);
   q.bin_mode = flags & 1u;
   q.dim = dcode == 0 ? 2u : dcode;
   q.roi_coding = (flags >> 3) & 1u;
+  q.run_coding = (flags >> 4) & 1u;
   q.panels = get32(in, 8);
   q.height = get32(in, 12);
   q.width = get32(in, 16);
@@ -679,8 +763,12 @@ int ro_stream_info(const uint8_t *in, uint64_t in_bytes, ro_params *p, uint32_t 
   const uint64_t nb = ro_nbins(&q), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
   const uint64_t n_out = get32(in, 44), T = get64(in, 56), total = get64(in, 64);
   if (get32(in, 52) != nc || n_out > nb || T > 32ull * nb) return RO_ERR_CORRUPT;
-  if (ro_sections(&q, np, n_out, nc, T, Troi).total != total || total > in_bytes)
+  /* the run section's size comes from its last offset: the header fixes its
+   * start, and the total must leave room for the offsets */
+  const ro_layout L0 = ro_sections(&q, np, n_out, nc, T, Troi, 0);
+  if (q.run_coding ? (total < L0.total || (total - L0.total) % 4 != 0) : L0.total != total)
     return RO_ERR_CORRUPT;
+  if (total > in_bytes) return RO_ERR_CORRUPT;
   if (p) *p = q;
   if (npeaks) *npeaks = np;
   if (stream_bytes) *stream_bytes = total;
@@ -759,6 +847,48 @@ static int ro_roi_decode(const ro_params *p, const uint8_t *in, const ro_layout 
   return bad ? RO_ERR_CORRUPT : RO_OK;
 }
 
+/* Expands the run section back into the T Huffman bits (words, zeroed,
+ * (T + 31) / 32 of them).  Offsets start at 0 and never decrease, the last
+ * one is the section's bits (which fill its words exactly); parameters are
+ * <= 20 and the padding is zero; each chunk's codes end exactly at the next
+ * chunk's offset and place their 1 bits inside the chunk.  Anything else is
+ * RO_ERR_CORRUPT. */
+static int ro_run_decode(const uint8_t *in, uint64_t total, const ro_layout *L, uint64_t nc,
+                         uint64_t T, const uint32_t *chunk_off, uint32_t *words) {
+  const uint8_t *kpar = in + L->run;
+  for (uint64_t c = 0; c < ro_align4(nc); ++c)
+    if (c < nc ? kpar[c] > RO_RUN_KMAX : kpar[c] != 0) return RO_ERR_CORRUPT;
+  const uint64_t Trun = get32(in, L->runoffs + 4 * nc);
+  if (L->runbits + 4 * ((Trun + 31) / 32) != total || get32(in, L->runoffs) != 0)
+    return RO_ERR_CORRUPT;
+  const uint32_t *rw = (const uint32_t *)(in + L->runbits);
+  for (uint64_t c = 0; c < nc; ++c) {
+    uint64_t pos = get32(in, L->runoffs + 4 * c);
+    const uint64_t rend = get32(in, L->runoffs + 4 * (c + 1));
+    const uint64_t start = chunk_off[c], end = c + 1 < nc ? chunk_off[c + 1] : T;
+    if (rend < pos || rend > Trun) return RO_ERR_CORRUPT;
+    const uint32_t k = kpar[c];
+    uint64_t b = start;   /* next Huffman bit position */
+    while (pos < rend) {
+      uint64_t q = 0;
+      while (pos < rend && ro_getbit(rw, pos)) {
+        q++;
+        pos++;
+      }
+      if (pos >= rend) return RO_ERR_CORRUPT;   /* no zero closing the unary part */
+      pos++;
+      if (pos + k > rend) return RO_ERR_CORRUPT;
+      uint64_t low = 0;
+      for (uint32_t t = 0; t < k; ++t) low = (low << 1) | ro_getbit(rw, pos++);
+      b += (q << k) | low;   /* the run of zeros */
+      if (b >= end) return RO_ERR_CORRUPT;
+      words[b / 32] |= 1u << (31 - b % 32);
+      b++;
+    }
+  }
+  return RO_OK;
+}
+
 /* Decompress a stream into a panels x height x width float frame.
  * Structural validation first (any failure -> RO_ERR_CORRUPT); then
  * codes -> residuals -> q by prefix sums -> bin value q*2eb replicated over
@@ -774,13 +904,33 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
   if (frame_elems < pix) return RO_ERR_ARG;
   const uint64_t nb = ro_nbins(&p), nc = (nb + RO_CHUNK - 1) / RO_CHUNK;
   const uint64_t n_out = get32(in, 44), T = get64(in, 56), Troi = get64(in, 72);
-  const ro_layout L = ro_sections(&p, np, n_out, nc, T, Troi);
+  const ro_layout L0 = ro_sections(&p, np, n_out, nc, T, Troi, 0);
+  const uint64_t Trun = p.run_coding ? get32(in, L0.runoffs + 4 * nc) : 0;
+  const ro_layout L = ro_sections(&p, np, n_out, nc, T, Troi, Trun);
+  /* the Huffman bits: in the stream, or expanded from the run section */
+  uint32_t *hw = NULL;
+  const uint8_t *bits = in + L.bits;
+  if (p.run_coding) {
+    uint32_t *co = (uint32_t *)malloc(4 * (size_t)(nc + 1));
+    for (uint64_t c = 0; c < nc; ++c) co[c] = get32(in, L.chunks + 4 * c);
+    hw = (uint32_t *)calloc((size_t)((T + 31) / 32 + 1), 4);
+    int okc = 1;
+    for (uint64_t c = 0; c < nc && okc; ++c)
+      okc = co[c] <= T && (c == 0 || co[c] >= co[c - 1]);
+    const int rs = okc ? ro_run_decode(in, total, &L, nc, T, co, hw) : RO_ERR_CORRUPT;
+    free(co);
+    if (rs != RO_OK) {
+      free(hw);
+      return RO_ERR_CORRUPT;
+    }
+    bits = (const uint8_t *)hw;
+  }
   /* peaks */
   int32_t *pk = (int32_t *)malloc(12 * (size_t)(np ? np : 1));
   for (uint32_t k = 0; k < np; ++k)
     for (int t = 0; t < 3; ++t) pk[3 * k + t] = get16(in, L.peaks + 6ull * k + 2 * t);
   if (ro_check_peaks(&p, pk, np) != RO_OK) {
-    free(pk);
+    free(pk); free(hw);
     return RO_ERR_CORRUPT;
   }
   /* code lengths: each <= 32 and a complete prefix code (Kraft sum 1), or one
@@ -790,11 +940,11 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
   uint64_t kraft = 0;
   int used = 0;
   for (int s = 0; s < RO_NSYM; ++s) {
-    if (len[s] > RO_MAXLEN) { free(pk); return RO_ERR_CORRUPT; }
+    if (len[s] > RO_MAXLEN) { free(pk); free(hw); return RO_ERR_CORRUPT; }
     if (len[s]) { kraft += 1ull << (RO_MAXLEN - len[s]); used++; }
   }
   if (!(kraft == (1ull << RO_MAXLEN) || (used == 1 && kraft == (1ull << (RO_MAXLEN - 1))))) {
-    free(pk);
+    free(pk); free(hw);
     return RO_ERR_CORRUPT;
   }
   /* canonical decoding tables: per length, first code, count and offset into
@@ -818,7 +968,6 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
   /* decode every symbol sequentially, checking the chunk offsets */
   int32_t *res = (int32_t *)malloc(4 * (size_t)nb);
   uint16_t *cd = (uint16_t *)malloc(2 * (size_t)nb);
-  const uint8_t *bits = in + L.bits;
   uint64_t pos = 0, prev_off = 0;
   int bad = 0;
   for (uint64_t g = 0; g < nb && !bad; ++g) {
@@ -868,7 +1017,7 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
     if (k != n_out) bad = 1;
   }
   if (bad) {
-    free(pk); free(res); free(cd);
+    free(pk); free(hw); free(res); free(cd);
     return RO_ERR_CORRUPT;
   }
   /* inverse Lorenzo: q is the inclusive prefix sum of r along each axis the
@@ -911,7 +1060,7 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
   if (p.roi_coding) {
     dec = (uint32_t *)malloc(4 * (size_t)(nroi ? nroi : 1));
     if (ro_roi_decode(&p, in, &L, np, Troi, dec) != RO_OK) {
-      free(pk); free(res); free(cd); free(dec);
+      free(pk); free(hw); free(res); free(cd); free(dec);
       return RO_ERR_CORRUPT;
     }
     payload = (const uint8_t *)dec;
@@ -942,7 +1091,7 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
         }
       }
   }
-  free(pk); free(res); free(cd); free(dec);
+  free(pk); free(hw); free(res); free(cd); free(dec);
   return bad ? RO_ERR_CORRUPT : RO_OK;
 }
 

@@ -18,7 +18,8 @@ CHUNK = 4096
 class Params(C.Structure):
     _fields_ = [("panels", C.c_uint32), ("height", C.c_uint32), ("width", C.c_uint32),
                 ("window", C.c_uint32), ("bin", C.c_uint32), ("bin_mode", C.c_uint32),
-                ("eb", C.c_double), ("dim", C.c_uint32), ("roi_coding", C.c_uint32)]
+                ("eb", C.c_double), ("dim", C.c_uint32), ("roi_coding", C.c_uint32),
+                ("run_coding", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class PeakParams(C.Structure):
@@ -61,8 +62,9 @@ def lib():
     return _lib
 
 
-def params(panels, height, width, window, bin, eb, bin_mode=0, dim=2, roi_coding=0):
-    return Params(panels, height, width, window, bin, bin_mode, float(eb), dim, roi_coding)
+def params(panels, height, width, window, bin, eb, bin_mode=0, dim=2, roi_coding=0, run_coding=0):
+    return Params(panels, height, width, window, bin, bin_mode, float(eb), dim, roi_coding,
+                  run_coding, 0)
 
 
 def _ptr(a):

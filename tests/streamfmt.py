@@ -11,6 +11,10 @@ Layout (little-endian, sections 4-byte aligned):
   code lengths (1024 u8), chunk bit offsets (n_chunks u32), bitstream
   (ceil(T/32) u32, codewords MSB-first within each word), outlier indices
   (n_out u32), outlier residuals (n_out i32).
+  Flag bit 3: the ROI payload is replaced by a coded ROI section at the end.
+  Flag bit 4: the bitstream is replaced by a run section at the very end:
+  one Rice parameter per chunk (u8, padded to 4), n_chunks + 1 u32 bit
+  offsets (the last is the section's bits), then the run bits.
 """
 import struct
 
@@ -24,14 +28,15 @@ def align4(x):
     return (x + 3) & ~3
 
 
-def sections(npeaks, window, n_out, n_chunks, T, roi_coded=False, Troi=0):
+def sections(npeaks, window, n_out, n_chunks, T, roi_coded=False, Troi=0, run_coded=False,
+             Trun=0):
     off = {}
     off["peaks"] = 80
     off["roi"] = 80 + align4(6 * npeaks)
     off["lens"] = off["roi"] + (0 if roi_coded else 4 * npeaks * window * window)
     off["chunks"] = off["lens"] + 1024
     off["bits"] = off["chunks"] + 4 * n_chunks
-    off["oidx"] = off["bits"] + 4 * ((T + 31) // 32)
+    off["oidx"] = off["bits"] + (0 if run_coded else 4 * ((T + 31) // 32))
     off["ores"] = off["oidx"] + 4 * n_out
     off["total"] = off["ores"] + 4 * n_out
     if roi_coded:
@@ -41,6 +46,11 @@ def sections(npeaks, window, n_out, n_chunks, T, roi_coded=False, Troi=0):
         off["roffs"] = off["rsec"] + 36
         off["rbits"] = off["roffs"] + 4 * npeaks
         off["total"] = off["rbits"] + 4 * ((Troi + 31) // 32)
+    if run_coded:
+        off["run"] = off["total"]
+        off["runoffs"] = off["run"] + align4(n_chunks)
+        off["runbits"] = off["runoffs"] + 4 * (n_chunks + 1)
+        off["total"] = off["runbits"] + 4 * ((Trun + 31) // 32)
     return off
 
 
@@ -48,8 +58,12 @@ def parse(buf):
     buf = bytes(np.asarray(buf, dtype=np.uint8).tobytes())
     (magic, ver, flags, P, H, W, w, b, R, eb, npk, n_out, ch, nch, T, total, res) = \
         HDR.unpack_from(buf, 0)
-    coded = bool(flags & 8)
+    coded, runs = bool(flags & 8), bool(flags & 16)
     off = sections(npk, w, n_out, nch, T, coded, res if coded else 0)
+    if runs:
+        Trun = struct.unpack_from("<I", buf, sections(npk, w, n_out, nch, T, coded, res, True)
+                                  ["runoffs"] + 4 * nch)[0]
+        off = sections(npk, w, n_out, nch, T, coded, res, True, Trun)
     d = dict(magic=magic, version=ver, flags=flags, P=P, H=H, W=W, window=w, bin=b, radius=R,
              eb=eb, npeaks=npk, n_out=n_out, chunk=ch, n_chunks=nch, T=T, stream_bytes=total,
              reserved=res, off=off, bin_mode=flags & 1,
@@ -68,8 +82,49 @@ def parse(buf):
     d["oidx"] = np.frombuffer(buf, np.uint32, n_out, off["oidx"])
     d["ores"] = np.frombuffer(buf, np.int32, n_out, off["ores"])
     d["chunk_offsets"] = np.frombuffer(buf, np.uint32, nch, off["chunks"])
-    d["bit_words"] = np.frombuffer(buf, np.uint32, (T + 31) // 32, off["bits"])
+    d["run_coded"] = runs
+    if runs:
+        d["Trun"] = Trun
+        d["run_k"] = np.frombuffer(buf, np.uint8, align4(nch), off["run"])
+        d["run_offsets"] = np.frombuffer(buf, np.uint32, nch + 1, off["runoffs"])
+        d["run_words"] = np.frombuffer(buf, np.uint32, (Trun + 31) // 32, off["runbits"])
+        d["bit_words"] = decode_runs(d["run_k"], d["run_offsets"], d["run_words"],
+                                     d["chunk_offsets"], T)
+    else:
+        d["bit_words"] = np.frombuffer(buf, np.uint32, (T + 31) // 32, off["bits"])
     return d
+
+
+def decode_runs(kpar, offsets, words, chunk_offsets, T):
+    """Independent reader of the run section: per chunk, codes of a unary
+    quotient (ones closed by a zero) and k remainder bits give the number of
+    zero bits before each one bit; the rest of the chunk is zeros.  Returns
+    the T bitstream bits packed MSB-first into u32 words."""
+    Trun = int(offsets[-1])
+    src = bits_of(words, Trun)
+    bits = np.zeros(32 * ((T + 31) // 32), np.uint8)
+    nch = len(chunk_offsets)
+    for c in range(nch):
+        pos, end = int(offsets[c]), int(offsets[c + 1])
+        k = int(kpar[c])
+        at = int(chunk_offsets[c])
+        stop = int(chunk_offsets[c + 1]) if c + 1 < nch else T
+        while pos < end:
+            q = 0
+            while src[pos]:
+                q += 1
+                pos += 1
+            pos += 1
+            r = q * (1 << k)
+            for t in range(k):
+                r += src[pos] << (k - 1 - t)
+                pos += 1
+            at += r
+            assert at < stop
+            bits[at] = 1
+            at += 1
+        assert pos == end
+    return np.packbits(bits).view(">u4").astype(np.uint32)
 
 
 def bits_of(words, T):
