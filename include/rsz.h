@@ -25,13 +25,16 @@
  * Frame layout: panels x height x width float32, C-contiguous.  Stream
  * layout (little-endian, sections 4-byte aligned): 80-byte header (flags:
  * bit 0 bin_mode, bits 1-2 the Lorenzo dimension, 0 for 2, bit 3 the ROI
- * coded; bytes 72-79 the coded ROI bits, else 0), peaks
+ * coded, bit 4 the runs coded; bytes 72-79 the coded ROI bits, else 0), peaks
  * (u16 panel,row,col), ROI payload (npeaks*w*w u32 bit patterns, 0 outside
  * the panel), code lengths (1024 u8), chunk bit offsets (u32, one per 4096
  * symbols), bitstream (u32 words, codewords MSB-first), outlier bin indices
  * (u32), outlier residuals (i32).  With the ROI coded, the verbatim payload is
  * absent and the coded ROI section ends the stream: 33 class code lengths
  * (u8, padded to 36 bytes), one u32 bit offset per window, the ROI bitstream.
+ * With the runs coded, the bitstream is absent and a run section ends the
+ * stream: one Rice parameter per chunk (u8, padded to 4 bytes), one u32 bit
+ * offset per chunk plus the section's total bits, then the run bits.
  */
 #ifndef RSZ_H
 #define RSZ_H
@@ -67,7 +70,16 @@ typedef struct {
  *     (the paper uses fpzip, Sec. IV): each window's float bits are mapped to
  *     order-preserving integers, predicted by a 2D Lorenzo predictor over the
  *     window, and the zigzag residual's bit length is Huffman coded and
- *     followed by its remaining bits.  Needs npeaks*window^2 <= 2^26. */
+ *     followed by its remaining bits.  Needs npeaks*window^2 <= 2^26.
+ *   run_coding: 0 stores the Huffman bitstream as it is; 1 passes it through
+ *     a lossless stage of this library's own (the paper does not describe
+ *     one; SZ-family coders follow their Huffman coder with a general
+ *     lossless pass): in each 4096-symbol chunk the lengths of the zero runs
+ *     before each one bit are Rice coded (a unary quotient, then k low bits)
+ *     with the chunk's cheapest parameter k in 0..20.  Never more bits than
+ *     the bitstream; it pays off where residual 0 dominates, as its codeword
+ *     is the all-zero one.
+ *   reserved: set to 0. */
 typedef struct {
   uint32_t panels, height, width;
   uint32_t window;
@@ -76,6 +88,8 @@ typedef struct {
   double eb;
   uint32_t dim;
   uint32_t roi_coding;
+  uint32_t run_coding;
+  uint32_t reserved;
 } rsz_params;
 
 enum { RSZ_BIN_BACKGROUND = 0, RSZ_BIN_ALL = 1 };

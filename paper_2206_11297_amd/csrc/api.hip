@@ -53,11 +53,12 @@ static int check_params(const rsz_params *p, uint32_t npeaks) {
       p->width < 1 || p->width > 65535)
     return RSZ_ERR_ARG;
   if (p->window < 1 || p->window > 1023 || p->bin < 1 || p->bin > 8 || p->bin_mode > 1 ||
-      p->dim > 3 || p->roi_coding > 1)
+      p->dim > 3 || p->roi_coding > 1 || p->run_coding > 1 || p->reserved != 0)
     return RSZ_ERR_ARG;
   if (!(p->eb > 0.0) || !std::isfinite(p->eb)) return RSZ_ERR_ARG;
   const uint64_t pix = (uint64_t)p->panels * p->height * p->width;
   const uint64_t nb = (uint64_t)p->panels * div_up(p->height, p->bin) * div_up(p->width, p->bin);
+  // (bins < 2^27 keeps the bitstream's and the run section's bits below 2^32)
   if (pix >= (1ull << 31) || nb >= (1ull << 27)) return RSZ_ERR_ARG;
   if ((uint64_t)npeaks * p->window * p->window > (1ull << 28)) return RSZ_ERR_ARG;
   // coded ROI bits (at most 63 per value) must fit u32 offsets
@@ -100,9 +101,11 @@ static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap, uint
   g.off_chunks = g.off_lens + kNumSym;
   g.off_bits = g.off_chunks + 4ull * g.nchunks;
   // worst case: every codeword 32 bits and every bin an outlier (and every
-  // coded ROI value 63 bits)
+  // coded ROI value 63 bits; the run section codes at most the bitstream's
+  // bits, plus its parameters and offsets)
   g.max_bytes = g.off_bits + 4ull * g.nbins + 8ull * g.nbins +
-                (p->roi_coding ? kRoiLens + 4ull * npeaks + 4 * div_up(63 * nroi, 32) : 0);
+                (p->roi_coding ? kRoiLens + 4ull * npeaks + 4 * div_up(63 * nroi, 32) : 0) +
+                (p->run_coding ? align_up(g.nchunks, 4) + 4ull * (g.nchunks + 1) : 0);
   return g;
 }
 
@@ -124,6 +127,9 @@ static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const G
     b += align_up(1ull * kChunk * g.nchunks, 256) + align_up(4ull * g.nbins, 256);
   if (p->roi_coding)   // class histogram, lengths, codewords, window bits
     b += 4 * kNumSym + kNumSym + 4 * kNumSym + align_up(4ull * npeaks, 256);
+  if (p->run_coding)   // Huffman words, chunk run bits then offsets, parameters
+    b += align_up(4ull * (g.nbins + 2), 256) + align_up(4ull * (g.nchunks + 1), 256) +
+         align_up(g.nchunks, 256);
   return b;
 }
 
@@ -322,7 +328,23 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
       fp.roi_lens = base;
       base += kNumSym;
       fp.roi_bits = (uint32_t *)base;
+      base += align_up(4ull * np[f], 256);
       hp.bp.roi_coding = 1;
+    }
+    // the bitstream's words: in the stream, or in the workspace when the run
+    // stage codes them
+    fp.run_coding = p->run_coding;
+    fp.bw = (uint32_t *)(fp.out + g.off_bits);
+    fp.bw_cap = fp.out_cap >= g.off_bits ? (fp.out_cap - g.off_bits) / 4 : 0;
+    if (fp.run_coding) {
+      fp.bw = (uint32_t *)base;
+      fp.bw_cap = g.nbins + 2;   // T <= 32 * nbins
+      base += align_up(4ull * (g.nbins + 2), 256);
+      fp.run_off = (uint32_t *)base;
+      base += align_up(4ull * (g.nchunks + 1), 256);
+      fp.run_k = base;
+      base += align_up(g.nchunks, 256);
+      hp.bp.run_coding = 1;
     }
     if (dbg) {
       fp.dbg_mask = dbg->mask;
@@ -435,12 +457,13 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
   rsz_params q;
   memset(&q, 0, sizeof q);
   // flags: bit 0 bin_mode, bits 1-2 the Lorenzo dimension (0 for 2, else 1
-  // or 3), bit 3 the ROI coded; every other bit zero
+  // or 3), bit 3 the ROI coded, bit 4 the runs coded; every other bit zero
   const uint32_t flags = u[1] >> 16, dcode = (flags >> 1) & 3u;
-  if ((flags >> 4) != 0 || dcode == 2) return RSZ_ERR_CORRUPT;
+  if ((flags >> 5) != 0 || dcode == 2) return RSZ_ERR_CORRUPT;
   q.bin_mode = flags & 1u;
   q.dim = dcode == 0 ? 2u : dcode;
   q.roi_coding = (flags >> 3) & 1u;
+  q.run_coding = (flags >> 4) & 1u;
   q.panels = u[2];
   q.height = u[3];
   q.width = u[4];
@@ -459,12 +482,18 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
   const Geom g = geometry(&q, np, kMaxTH, 1);
   const uint64_t n_out = u[11];
   if (u[13] != g.nchunks || n_out > g.nbins || T > 32ull * g.nbins) return RSZ_ERR_CORRUPT;
-  const uint64_t off_oidx = g.off_bits + 4 * ((T + 31) / 32);
+  const uint64_t off_oidx = g.off_bits + (q.run_coding ? 0 : 4 * ((T + 31) / 32));
   const uint64_t off_ores = off_oidx + 4 * n_out;
   const uint64_t off_rsec = off_ores + 4 * n_out;
   const uint64_t off_rbits = off_rsec + kRoiLens + 4ull * np;
   const uint64_t end = q.roi_coding ? off_rbits + 4 * ((Troi + 31) / 32) : off_rsec;
-  if (end != total || total > in_bytes) return RSZ_ERR_CORRUPT;
+  // run section: its size comes from its last offset, checked on the device;
+  // the total must leave room for the offsets and end on a whole word
+  const uint64_t off_runoffs = end + align_up(g.nchunks, 4);
+  const uint64_t off_runbits = off_runoffs + 4ull * (g.nchunks + 1);
+  if (q.run_coding ? (total < off_runbits || (total - off_runbits) % 4 != 0) : end != total)
+    return RSZ_ERR_CORRUPT;
+  if (total > in_bytes) return RSZ_ERR_CORRUPT;
   if (p) *p = q;
   if (npeaks) *npeaks = np;
   if (dp) {
@@ -496,6 +525,10 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
     dp->off_bits = g.off_bits;
     dp->off_oidx = off_oidx;
     dp->off_ores = off_ores;
+    dp->run_coding = q.run_coding;
+    dp->off_run = end;
+    dp->off_runoffs = off_runoffs;
+    dp->off_runbits = off_runbits;
   }
   return RSZ_OK;
 }
@@ -508,7 +541,8 @@ static uint64_t decode_ws_bytes(const DecodePlan &dp) {
          (dp.dim == 1 ? align_up(4ull * dp.P * dp.Hb, 256) : 0) +
          (dp.roi_coding ? align_up(4ull * dp.npeaks * dp.w * dp.w, 256) +
                               align_up(decode_roi_tables_bytes(), 256)
-                        : 0);
+                        : 0) +
+         (dp.run_coding ? align_up(4 * ((dp.T + 31) / 32 + 2), 256) : 0);
 }
 
 // Results of a single-frame call live in the workspace tail.
@@ -706,6 +740,13 @@ int rsz_decompress(const void *d_in, uint64_t in_bytes, float *d_frame, uint64_t
     dp.roi_payload = (uint32_t *)w;
     w += align_up(4ull * dp.npeaks * dp.w * dp.w, 256);
     dp.roi_tables = (uint32_t *)w;
+    w += align_up(decode_roi_tables_bytes(), 256);
+  }
+  // the Huffman words: in the stream, or expanded from the run section
+  dp.bits = (const uint32_t *)(dp.in + dp.off_bits);
+  if (dp.run_coding) {
+    dp.hbits = (uint32_t *)w;
+    dp.bits = dp.hbits;
   }
   if (launch_decompress(dp, s) != hipSuccess) return RSZ_ERR_HIP;
   int32_t status = 0;

@@ -1096,7 +1096,9 @@ __device__ __forceinline__ uint64_t wave_exclusive_scan(uint64_t v, uint64_t &to
 // the codewords are ORed into the wave's LDS words, and the complete words
 // are stored whole; the round's last partial word carries into the next.  A
 // chunk's first word, when it starts mid-word, is shared with the previous
-// chunk and goes to head[] for k_tail to merge.
+// chunk and goes to head[] for k_tail to merge.  The words go to fp.bw: the
+// stream's bitstream section, or a workspace buffer when the run stage codes
+// them (whose kernels take a chunk's first word from head[] themselves).
 constexpr int kRoundSyms = 1024;
 __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
   __shared__ uint8_t s_len[kNumSym];
@@ -1122,7 +1124,8 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
   const uint32_t c1 = min(c0 + bp.cpw, fp.nchunks);
   uint8_t *o = fp.out;
   const uint64_t cap = fp.out_cap;
-  uint32_t *bw = (uint32_t *)(o + fp.off_bits);
+  uint32_t *bw = fp.bw;
+  const uint64_t bcap = fp.bw_cap;
   for (uint32_t lc = c0 + wv; lc < c1; lc += kWaves) {
     const uint32_t S0 = fp.chunk_off[lc];
     uint32_t oi = fp.chunk_oo[lc];
@@ -1177,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
           fp.head[lc] = v;
           continue;
         }
-        if (fp.off_bits + 4 * (widx + k) + 4 <= cap) bw[widx + k] = v;
+        if (widx + k < bcap) bw[widx + k] = v;
       }
       if (nw) first = false;
       const uint32_t carry = stg[nw];
@@ -1194,7 +1197,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
       const uint32_t v = stg[0];
       if (lane == 0) {
         if (first) fp.head[lc] = v;
-        else if (fp.off_bits + 4 * widx + 4 <= cap) bw[widx] = v;
+        else if (widx < bcap) bw[widx] = v;
       }
     }
     wave_sync();
@@ -1226,7 +1229,8 @@ __global__ __launch_bounds__(256) void k_encode_block(BatchPlan bp) {
   const uint32_t c1 = min(c0 + bp.cpw, fp.nchunks);
   uint8_t *o = fp.out;
   const uint64_t cap = fp.out_cap;
-  uint32_t *bw = (uint32_t *)(o + fp.off_bits);
+  uint32_t *bw = fp.bw;
+  const uint64_t bcap = fp.bw_cap;
   // the codes region is padded to whole chunks: the 16-byte loads stay inside
   uint4 n0 = make_uint4(0, 0, 0, 0);
   if (c0 < c1) n0 = *(const uint4 *)(fp.codes + c0 * kChunk + threadIdx.x * 16);
@@ -1283,7 +1287,7 @@ __global__ __launch_bounds__(256) void k_encode_block(BatchPlan bp) {
         continue;
       }
       const uint64_t widx = (uint64_t)wlo + k;
-      if (fp.off_bits + 4 * widx + 4 <= cap) bw[widx] = v;
+      if (widx < bcap) bw[widx] = v;
     }
   }
 }
@@ -1310,17 +1314,24 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
   const uint64_t T = st->T;
   const uint32_t n_out = st->n_out;
   const uint64_t nwords = (T + 31) / 32;
-  const uint64_t off_oidx = fp.off_bits + 4 * nwords;
+  // with the runs coded the bitstream is not in the stream
+  const uint64_t off_oidx = fp.off_bits + (fp.run_coding ? 0 : 4 * nwords);
   const uint64_t off_ores = off_oidx + 4ull * n_out;
-  // coded ROI: its section closes the stream
+  // coded ROI: its section follows the outliers
   const uint64_t Troi = fp.roi_coding ? st->Troi : 0;
   const uint64_t off_rsec = off_ores + 4ull * n_out;
   const uint64_t off_rbits = off_rsec + kRoiLens + 4ull * fp.npeaks;
-  const uint64_t total = fp.roi_coding ? off_rbits + 4 * ((Troi + 31) / 32) : off_rsec;
+  const uint64_t end_roi = fp.roi_coding ? off_rbits + 4 * ((Troi + 31) / 32) : off_rsec;
+  // run section: parameters, offsets, run bits -- the end of the stream
+  const uint64_t Trun = fp.run_coding ? fp.run_off[fp.nchunks] : 0;
+  const uint64_t off_runoffs = end_roi + align_up(fp.nchunks, 4);
+  const uint64_t off_runbits = off_runoffs + 4ull * (fp.nchunks + 1);
+  const uint64_t total = fp.run_coding ? off_runbits + 4 * ((Trun + 31) / 32) : end_roi;
   const bool fits = total <= fp.out_cap;
   __syncthreads();
   if (threadIdx.x == 0) {
     st->total = total;
+    st->off_runbits = off_runbits;
     if (!fits) st->status = RSZ_ERR_CAPACITY;
     *fp.res_status = fits ? RSZ_OK : RSZ_ERR_CAPACITY;
     *fp.res_bytes = total;
@@ -1330,9 +1341,9 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
   if (threadIdx.x == 0) {
     put_u32(o, 0, 0x315A5352u);  // "RSZ1"
     // version 1; flags: bit 0 bin_mode, bits 1-2 the Lorenzo dimension (0 for
-    // 2), bit 3 the ROI coded
-    const uint32_t flags =
-        (fp.mode & 1u) | ((fp.dim == 2 ? 0u : fp.dim) << 1) | ((fp.roi_coding & 1u) << 3);
+    // 2), bit 3 the ROI coded, bit 4 the runs coded
+    const uint32_t flags = (fp.mode & 1u) | ((fp.dim == 2 ? 0u : fp.dim) << 1) |
+                           ((fp.roi_coding & 1u) << 3) | ((fp.run_coding & 1u) << 4);
     put_u32(o, 4, 1u | (flags << 16));
     put_u32(o, 8, fp.P);
     put_u32(o, 12, fp.H);
@@ -1369,11 +1380,22 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
   for (uint32_t e = threadIdx.x; e < 3 * fp.npeaks; e += 256) pk[e] = (uint16_t)fp.peaks[e];
   if (threadIdx.x == 0 && (3 * fp.npeaks) % 2) pk[3 * fp.npeaks] = 0;
   for (int s = threadIdx.x; s < kNumSym; s += 256) o[fp.off_lens + s] = st->lens[s];
-  // chunk boundary words: previous chunk's bits (stored by it) | this chunk's
-  uint32_t *bw = (uint32_t *)(o + fp.off_bits);
-  for (uint32_t c = threadIdx.x; c < fp.nchunks; c += 256) {
-    const uint32_t S0 = fp.chunk_off[c];
-    if (S0 & 31) bw[S0 >> 5] |= fp.head[c];
+  if (fp.run_coding) {
+    // Rice parameters (padded with zeros to 4 bytes), chunk bit offsets and
+    // the section's bits, zeroed run words that k_run_pack ORs the codes into
+    for (uint32_t c = threadIdx.x; c < align_up(fp.nchunks, 4); c += 256)
+      o[end_roi + c] = c < fp.nchunks ? fp.run_k[c] : 0;
+    uint32_t *ro = (uint32_t *)(o + off_runoffs);
+    for (uint32_t c = threadIdx.x; c <= fp.nchunks; c += 256) ro[c] = fp.run_off[c];
+    uint32_t *rw = (uint32_t *)(o + off_runbits);
+    for (uint64_t t = threadIdx.x; t < (Trun + 31) / 32; t += 256) rw[t] = 0u;
+  } else {
+    // chunk boundary words: previous chunk's bits (stored by it) | this chunk's
+    uint32_t *bw = (uint32_t *)(o + fp.off_bits);
+    for (uint32_t c = threadIdx.x; c < fp.nchunks; c += 256) {
+      const uint32_t S0 = fp.chunk_off[c];
+      if (S0 & 31) bw[S0 >> 5] |= fp.head[c];
+    }
   }
   uint32_t *oidx = (uint32_t *)(o + off_oidx);
   int32_t *ores = (int32_t *)(o + off_ores);
@@ -1566,7 +1588,8 @@ __global__ __launch_bounds__(256) void k_roi_pack(BatchPlan bp) {
     if (!roi_window(bp, kg, f, k, rw)) continue;
     const FramePlan &fp = bp.frames[f];
     const FrameState *st = fp.st;
-    const uint64_t off_ores = fp.off_bits + 4 * ((st->T + 31) / 32) + 4ull * st->n_out;
+    const uint64_t off_ores =
+        fp.off_bits + (fp.run_coding ? 0 : 4 * ((st->T + 31) / 32)) + 4ull * st->n_out;
     uint32_t *words =
         (uint32_t *)(fp.out + off_ores + 4ull * st->n_out + kRoiLens + 4ull * fp.npeaks);
     const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
@@ -1587,6 +1610,192 @@ __global__ __launch_bounds__(256) void k_roi_pack(BatchPlan bp) {
       if (n) or_bits(words, base + ex, value, n);
       base += tot;
     }
+  }
+}
+
+// ------------------------------------------------------------ run stage
+
+// A lossless stage after the Huffman coder: per 4096-symbol chunk, the
+// lengths r of the zero runs before each one bit of the chunk's Huffman bits
+// are Rice coded with the chunk's parameter k (r >> k one bits, a zero, the
+// k low bits of r, MSB-first); zeros after the last one are implied by the
+// chunk's end.  k in 0..kRunKMax minimises the chunk's bits, the smallest on
+// ties.  One wave per chunk, lanes on consecutive words of its bits.
+constexpr uint32_t kRunKMax = 20;
+
+// Word i of the Huffman bits as chunk c sees it: a chunk that starts
+// mid-word has its share of that word in head[c] (the word in bw holds the
+// previous chunk's bits); every other word of the chunk holds its bits only
+// (a later chunk's bits in its last word go to that chunk's head).
+__device__ __forceinline__ uint32_t chunk_word(const FramePlan &fp, uint32_t c, uint32_t S0,
+                                               uint32_t i) {
+  return (i == (S0 >> 5) && (S0 & 31)) ? fp.head[c] : fp.bw[i];
+}
+
+// Inclusive max over the lanes of a wave.
+__device__ __forceinline__ uint32_t wave_max_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(v, d);
+    if (lane >= d) v = max(v, y);
+  }
+  return v;
+}
+
+// The walk shared by k_run_count and k_run_pack: blocks of 64 words, lane l
+// on word base + l.  For each block, `prev` is the position after the last
+// one bit before the lane's word (the chunk start if none); ones give runs
+// one - prev, in raster order within the lane.  Returns the word, with its
+// bits outside the chunk cleared.
+struct RunWalk {
+  uint32_t S0, S1, w0, w1, carry;   // carry: after the last one of earlier blocks
+  __device__ void init(const FramePlan &fp, const FrameState *st, uint32_t c) {
+    S0 = fp.chunk_off[c];
+    S1 = c + 1 < fp.nchunks ? fp.chunk_off[c + 1] : (uint32_t)st->T;
+    w0 = S0 >> 5;
+    w1 = (S1 + 31) >> 5;
+    carry = S0;
+  }
+  // this lane's word of the block at `base`, and the position after the last
+  // one bit before it
+  __device__ uint32_t load(const FramePlan &fp, uint32_t c, uint32_t base, uint32_t &prev) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t i = base + lane;
+    const uint32_t word = i < w1 ? chunk_word(fp, c, S0, i) : 0u;
+    const uint32_t after = word ? 32 * i + (32 - __builtin_ctz(word)) : 0u;
+    const uint32_t incl = wave_max_scan(after);
+    const uint32_t excl = __shfl_up(incl, 1);
+    prev = max(carry, lane ? excl : 0u);
+    carry = max(carry, __shfl(incl, 63));
+    return word;
+  }
+};
+
+__global__ __launch_bounds__(256) void k_run_count(BatchPlan bp) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t item = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (item >= bp.total_chunks) return;
+  const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, item);
+  const FramePlan &fp = bp.frames[f];
+  if (!fp.run_coding || load_status(fp.st) != RSZ_OK) return;
+  const uint32_t c = item - bp.chunk_prefix[f];
+  RunWalk rw;
+  rw.init(fp, fp.st, c);
+  // acc[k] = sum of r >> k over the chunk's ones; a chunk holds at most
+  // 4096 * 32 bits, so every cost fits 32 bits
+  uint32_t acc[kRunKMax + 1];
+#pragma unroll
+  for (int k = 0; k <= (int)kRunKMax; ++k) acc[k] = 0;
+  uint32_t ones = 0;
+  for (uint32_t base = rw.w0; base < rw.w1; base += 64) {
+    uint32_t prev;
+    uint32_t word = rw.load(fp, c, base, prev);
+    const uint32_t at = 32 * (base + lane);
+    while (word) {
+      const uint32_t t = __builtin_clz(word);
+      word &= ~(0x80000000u >> t);
+      const uint32_t r = at + t - prev;
+      prev = at + t + 1;
+      ones++;
+#pragma unroll
+      for (int k = 0; k <= (int)kRunKMax; ++k) acc[k] += r >> k;
+    }
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    ones += __shfl_xor(ones, d);
+#pragma unroll
+    for (int k = 0; k <= (int)kRunKMax; ++k) acc[k] += __shfl_xor(acc[k], d);
+  }
+  uint32_t best = 0, cost = acc[0] + ones;
+#pragma unroll
+  for (int k = 1; k <= (int)kRunKMax; ++k) {
+    const uint32_t ck = acc[k] + ones * (1u + k);
+    if (ck < cost) {
+      cost = ck;
+      best = k;
+    }
+  }
+  if (lane == 0) {
+    fp.run_off[c] = cost;
+    fp.run_k[c] = (uint8_t)best;
+  }
+}
+
+// Chunk run bits -> bit offsets (exclusive scan), the section's bits last.
+__global__ __launch_bounds__(256) void k_run_scan(BatchPlan bp) {
+  __shared__ uint32_t s_tmp[4];
+  const FramePlan &fp = bp.frames[blockIdx.x];
+  if (!fp.run_coding || load_status(fp.st) != RSZ_OK) return;   // uniform
+  uint32_t carry = 0;   // at most the bitstream's bits, below 2^32
+  for (uint32_t c0 = 0; c0 < fp.nchunks; c0 += 256) {
+    const uint32_t c = c0 + threadIdx.x;
+    const uint32_t v = c < fp.nchunks ? fp.run_off[c] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<uint32_t>(v, s_tmp, tot);
+    if (c < fp.nchunks) fp.run_off[c] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) fp.run_off[fp.nchunks] = carry;
+}
+
+// Sets the n bits at bit position pos of words (zeroed) to one.
+__device__ __forceinline__ void or_ones(uint32_t *words, uint64_t pos, uint64_t n) {
+  while (n) {
+    const uint32_t s = (uint32_t)(pos & 31);
+    const uint32_t take = (uint32_t)min<uint64_t>(n, 32 - s);
+    const uint32_t mask = (take == 32 ? 0xFFFFFFFFu : ((1u << take) - 1u)) << (32 - s - take);
+    atomicOr(&words[pos >> 5], mask);
+    pos += take;
+    n -= take;
+  }
+}
+
+// The codes of each chunk at its offset, ORed into the run words k_tail
+// zeroed (chunks share their boundary words).
+__global__ __launch_bounds__(256) void k_run_pack(BatchPlan bp) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t item = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (item >= bp.total_chunks) return;
+  const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, item);
+  const FramePlan &fp = bp.frames[f];
+  const FrameState *st = fp.st;
+  if (!fp.run_coding || load_status(st) != RSZ_OK) return;
+  const uint32_t c = item - bp.chunk_prefix[f];
+  uint32_t *out = (uint32_t *)(fp.out + st->off_runbits);
+  const uint32_t k = fp.run_k[c];
+  uint64_t base_bit = fp.run_off[c];
+  RunWalk rw;
+  rw.init(fp, st, c);
+  for (uint32_t base = rw.w0; base < rw.w1; base += 64) {
+    uint32_t prev;
+    const uint32_t word = rw.load(fp, c, base, prev);
+    const uint32_t at = 32 * (base + lane);
+    // this lane's code bits, placed by a wave scan
+    uint32_t bits = 0, p = prev, w = word;
+    while (w) {
+      const uint32_t t = __builtin_clz(w);
+      w &= ~(0x80000000u >> t);
+      bits += ((at + t - p) >> k) + 1 + k;
+      p = at + t + 1;
+    }
+    uint64_t tot;
+    uint64_t pos = base_bit + wave_exclusive_scan(bits, tot);
+    p = prev;
+    w = word;
+    while (w) {
+      const uint32_t t = __builtin_clz(w);
+      w &= ~(0x80000000u >> t);
+      const uint32_t r = at + t - p;
+      p = at + t + 1;
+      const uint32_t q = r >> k;
+      or_ones(out, pos, q);
+      pos += q + 1;   // the zero closing the unary part
+      if (k) or_bits(out, pos, r & ((1u << k) - 1u), k);
+      pos += k;
+    }
+    base_bit += tot;
   }
 }
 
@@ -1666,11 +1875,17 @@ hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
     if (bp.total_peaks) RSZ_LAUNCH("k_roi_count", k_roi_count, roi_grid, s, bp);
     RSZ_LAUNCH("k_roi_scan", k_roi_scan, bp.nframes, s, bp);
   }
+  const uint32_t run_grid = (bp.total_chunks + kWaves - 1) / kWaves;
+  if (bp.run_coding) {
+    if (bp.total_chunks) RSZ_LAUNCH("k_run_count", k_run_count, run_grid, s, bp);
+    RSZ_LAUNCH("k_run_scan", k_run_scan, bp.nframes, s, bp);
+  }
   RSZ_LAUNCH("k_tail", k_tail, bp.nframes, s, bp);
   if (bp.total_peaks) {
     RSZ_LAUNCH("k_roi", k_roi, roi_grid, s, bp);
     if (bp.roi_coding) RSZ_LAUNCH("k_roi_pack", k_roi_pack, roi_grid, s, bp);
   }
+  if (bp.run_coding && bp.total_chunks) RSZ_LAUNCH("k_run_pack", k_run_pack, run_grid, s, bp);
   return hipSuccess;
 }
 

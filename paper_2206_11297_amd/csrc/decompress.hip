@@ -4,6 +4,10 @@
 //                   code), peaks and chunk offsets; build canonical decode
 //                   tables (11-bit single- and multi-symbol lookup tables +
 //                   per-length first codes).
+//   k_dec_run_zero  runs coded: clear the words the runs expand into.
+//   k_dec_runs      runs coded: one thread per chunk expands its Rice-coded
+//                   zero runs back into the Huffman bits, checking parameters,
+//                   offsets and that every one bit stays inside its chunk.
 //   k_dec_chunks    one wave per 4096-symbol chunk, lanes on slices of its
 //                   bits (self-synchronising starts): Huffman decode to
 //                   residuals; each chunk must end exactly at the next offset.
@@ -277,6 +281,88 @@ __device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, ui
   return m;
 }
 
+// ------------------------------------------------------------ run stage
+
+constexpr uint32_t kRunKMax = 20;
+
+__global__ __launch_bounds__(256) void k_dec_run_zero(DecodePlan dp) {
+  const uint64_t n = (dp.T + 31) / 32 + 2;
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull)
+    dp.hbits[i] = 0u;
+}
+
+// The 32 bits of words (n of them, zero beyond) from bit pos, MSB-first.
+__device__ __forceinline__ uint32_t peek_bits(const uint32_t *w, uint64_t n, uint64_t pos) {
+  const uint64_t i = pos >> 5;
+  const uint32_t s = (uint32_t)(pos & 31);
+  const uint32_t hi = i < n ? w[i] : 0u, lo = i + 1 < n ? w[i + 1] : 0u;
+  return s ? (hi << s) | (lo >> (32 - s)) : hi;
+}
+
+// Chunk c's codes occupy run bits [runoffs[c], runoffs[c + 1]): each is a
+// unary quotient q (ones closed by a zero) and k low bits, giving the zero
+// run before the chunk's next one bit.  A valid section has parameters <= 20
+// (zero padding), offsets from 0 that never decrease, a last offset whose
+// words end the stream exactly, codes that end exactly at the next offset,
+// and every one bit inside its chunk [chunk_off[c], chunk_off[c + 1]).
+// Reads stay inside the section once its size is checked; the loop ends
+// after at most one step per run bit.
+__global__ __launch_bounds__(256) void k_dec_runs(DecodePlan dp) {
+  const uint32_t c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= dp.nchunks || !dec_ok(dp.status)) return;
+  const uint8_t *kpar = dp.in + dp.off_run;
+  const uint32_t *ro = (const uint32_t *)(dp.in + dp.off_runoffs);
+  const uint64_t Trun = ro[dp.nchunks];
+  const uint64_t nrw = (Trun + 31) / 32;
+  bool bad = dp.off_runbits + 4 * nrw != dp.total || ro[0] != 0 || kpar[c] > kRunKMax;
+  if (c + 1 == dp.nchunks)   // padding of the parameters
+    for (uint64_t t = dp.nchunks; t < align_up(dp.nchunks, 4); ++t) bad |= kpar[t] != 0;
+  const uint32_t *co = (const uint32_t *)(dp.in + dp.off_chunks);
+  const uint64_t start = co[c], end = c + 1 < dp.nchunks ? co[c + 1] : dp.T;
+  uint64_t pos = ro[c];
+  const uint64_t rend = ro[c + 1];
+  bad |= start > end || end > dp.T || rend < pos || rend > Trun;
+  if (bad) {
+    corrupt(dp.status);
+    return;
+  }
+  const uint32_t *rw = (const uint32_t *)(dp.in + dp.off_runbits);
+  const uint32_t k = kpar[c];
+  uint64_t b = start;   // next Huffman bit position
+  while (pos < rend) {
+    uint64_t q = 0;
+    for (;;) {   // the unary part, up to 32 bits a step
+      const uint32_t x = peek_bits(rw, nrw, pos);
+      const uint64_t avail = min<uint64_t>(32, rend - pos);
+      const uint64_t n = ~x ? (uint64_t)__builtin_clz(~x) : 32;   // leading ones
+      if (n < avail) {
+        q += n;
+        pos += n + 1;   // and the closing zero
+        break;
+      }
+      q += avail;
+      pos += avail;
+      // no closing zero before the chunk's end, or a run past the chunk
+      if (pos >= rend || b + (q << k) >= end) bad = true;
+      if (bad) break;
+    }
+    if (bad || pos + k > rend) {
+      bad = true;
+      break;
+    }
+    const uint64_t low = k ? peek_bits(rw, nrw, pos) >> (32 - k) : 0;
+    pos += k;
+    b += (q << k) | low;
+    if (b >= end) {
+      bad = true;
+      break;
+    }
+    atomicOr(&dp.hbits[b >> 5], 0x80000000u >> (b & 31));
+    b++;
+  }
+  if (bad) corrupt(dp.status);
+}
+
 // One wave per chunk.  The chunk's bits split into 64 equal slices; lane i
 // decodes from a start s_i until the first codeword boundary at or past the
 // next slice.  Lane 0 starts at the chunk offset, a true boundary; every
@@ -304,7 +390,7 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecodePlan dp) {
   const uint32_t c = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c >= dp.nchunks || !dec_ok(dp.status)) return;
   const uint32_t *co = (const uint32_t *)(dp.in + dp.off_chunks);
-  const uint32_t *bw = (const uint32_t *)(dp.in + dp.off_bits);
+  const uint32_t *bw = dp.bits;   // the stream's bitstream, or the expanded runs
   const uint64_t nwords = (dp.T + 31) / 32;
   const uint64_t S = co[c], E = c + 1 < dp.nchunks ? co[c + 1] : dp.T;
   const uint32_t g0 = c * kChunk;
@@ -667,6 +753,12 @@ __global__ __launch_bounds__(256) void k_dec_roi_check(DecodePlan dp) {
 
 hipError_t launch_decompress(const DecodePlan &dp, hipStream_t s) {
   RSZ_DLAUNCH("k_dec_tables", k_dec_tables, 1, 256, s);
+  if (dp.run_coding) {
+    const uint64_t nw = (dp.T + 31) / 32 + 2;
+    RSZ_DLAUNCH("k_dec_run_zero", k_dec_run_zero,
+                (uint32_t)std::min<uint64_t>((nw + 255) / 256, 1u << 16), 256, s);
+    RSZ_DLAUNCH("k_dec_runs", k_dec_runs, (dp.nchunks + 255) / 256, 256, s);
+  }
   RSZ_DLAUNCH("k_dec_chunks", k_dec_chunks, (dp.nchunks + 3) / 4, 256, s);
   if (dp.n_out) RSZ_DLAUNCH("k_dec_outliers", k_dec_outliers, (dp.n_out + 255) / 256, 256, s);
   // inverse Lorenzo: prefix sums along each axis the predictor spans

@@ -43,6 +43,7 @@ struct FrameState {
   uint64_t T;          // bitstream bits
   uint64_t total;      // stream bytes
   uint64_t Troi;       // coded ROI bits
+  uint64_t off_runbits;  // run coding: stream offset of the run bits
   uint32_t hist[kNumSym];
   uint32_t cw[kNumSym];
   uint8_t lens[kNumSym];
@@ -53,6 +54,7 @@ struct FramePlan {
   uint32_t P, H, W, w, b, mode;
   uint32_t dim;             // Lorenzo dimension: 1, 2 or 3
   uint32_t roi_coding;      // ROI windows coded (1) or verbatim (0)
+  uint32_t run_coding;      // Huffman bits run coded (1) or verbatim (0)
   double eb, step;          // step = 2*eb
   uint32_t Hb, Wb, nbins, nchunks;
   uint32_t npeaks, TH, segs, groups;   // segments per panel, workgroups per panel
@@ -86,6 +88,15 @@ struct FramePlan {
   uint32_t *roi_bits;
   int32_t *qedge;           // dim 1: q of the last bin of each of the P*Hb bin
                             // rows (those k_lorenzo_dims reads), else null
+  // where k_encode writes the Huffman words: the stream's bitstream section
+  // (bw_cap = the words the output buffer holds there), or with the runs
+  // coded a workspace buffer of nbins + 2 words
+  uint32_t *bw;
+  uint64_t bw_cap;
+  // run coding (else null): per chunk the run bits, then their bit offsets
+  // (nchunks + 1, the last the section's bits), and the Rice parameters
+  uint32_t *run_off;
+  uint8_t *run_k;
   FrameState *st;
   uint64_t *res_bytes;      // where to report the size (device)
   int32_t *res_status;      // where to report the status (device)
@@ -104,6 +115,7 @@ struct BatchPlan {
   uint32_t enc_block;            // small batch: a workgroup packs one chunk at a time
   uint32_t total_fix;            // workgroups of k_lorenzo_dims (0: every frame is 2D)
   uint32_t roi_coding;           // some frame codes its ROI windows
+  uint32_t run_coding;           // some frame codes its Huffman bits' runs
   const FramePlan *frames;
   const uint32_t *tile_prefix;   // nframes + 1
   const uint32_t *unit_prefix;   // nframes + 1 (units of cpw chunks)
@@ -129,6 +141,10 @@ struct DecodePlan {
   uint64_t off_rsec, off_roffs, off_rbits;   // coded ROI section
   uint32_t *roi_payload;                      // coded ROI: npeaks*w*w decoded words
   uint32_t *roi_tables;                       // coded ROI: decode tables
+  uint32_t run_coding;                        // run section instead of the bitstream:
+  uint64_t off_run, off_runoffs, off_runbits; // parameters, offsets, run bits
+  const uint32_t *bits;                       // the Huffman words (stream or hbits)
+  uint32_t *hbits;                            // runs coded: ceil(T/32) + 2 expanded words
   double step;
   uint32_t Hb, Wb, nbins, nchunks, n_out;
   uint64_t T, total;

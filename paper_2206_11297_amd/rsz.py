@@ -34,7 +34,8 @@ class RszError(RuntimeError):
 class rsz_params(C.Structure):
     _fields_ = [("panels", C.c_uint32), ("height", C.c_uint32), ("width", C.c_uint32),
                 ("window", C.c_uint32), ("bin", C.c_uint32), ("bin_mode", C.c_uint32),
-                ("eb", C.c_double), ("dim", C.c_uint32), ("roi_coding", C.c_uint32)]
+                ("eb", C.c_double), ("dim", C.c_uint32), ("roi_coding", C.c_uint32),
+                ("run_coding", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class rsz_frame_desc(C.Structure):
@@ -117,8 +118,9 @@ def status_string(status):
 
 
 def params(panels, height, width, window, bin, eb, bin_mode=RSZ_BIN_BACKGROUND, dim=2,
-           roi_coding=0):
-    return rsz_params(panels, height, width, window, bin, bin_mode, float(eb), dim, roi_coding)
+           roi_coding=0, run_coding=0):
+    return rsz_params(panels, height, width, window, bin, bin_mode, float(eb), dim, roi_coding,
+                      run_coding, 0)
 
 
 # ------------------------------------------------------------ C ABI mirrors
@@ -286,14 +288,15 @@ def workspace(nbytes, device=None):
 
 
 def compress(frame, peaks, window=17, bin=2, eb=10.0, bin_mode=RSZ_BIN_BACKGROUND, out=None,
-             ws=None, dim=2, roi_coding=0):
+             ws=None, dim=2, roi_coding=0, run_coding=0):
     """Compress one GPU frame; returns the stream as a uint8 GPU tensor.
     dim: Lorenzo predictor dimension (1, 2 or 3); roi_coding: 1 codes the ROI
-    windows losslessly instead of storing them verbatim."""
+    windows losslessly instead of storing them verbatim; run_coding: 1 Rice
+    codes the zero runs of the Huffman bits."""
     torch = _torch()
     frame, peaks = _check_frame(frame, peaks)
     P, H, W = frame.shape
-    p = params(P, H, W, window, bin, eb, bin_mode, dim, roi_coding)
+    p = params(P, H, W, window, bin, eb, bin_mode, dim, roi_coding, run_coding)
     npk = peaks.shape[0]
     st, cap = rsz_max_compressed_bytes(p, npk)
     if st:
@@ -370,10 +373,11 @@ class Batch:
     """Descriptors, output buffers and workspace for one batched launch.
 
     frames: list of float32 [P,H,W] GPU tensors; peaks: list of int32 [n,3]
-    GPU tensors; params: list of (window, bin, eb, bin_mode[, dim[, roi_coding]])
-    per frame or one tuple for all (dim, the Lorenzo dimension, defaults to 2;
-    roi_coding to 0, the ROI windows verbatim).  Output buffers are sized by rsz_max_compressed_bytes and
-    packed into one uint8 tensor."""
+    GPU tensors; params: list of (window, bin, eb, bin_mode[, dim[, roi_coding[,
+    run_coding]]]) per frame or one tuple for all (dim, the Lorenzo dimension,
+    defaults to 2; roi_coding to 0, the ROI windows verbatim; run_coding to 0,
+    the Huffman bits verbatim).  Output buffers are sized by
+    rsz_max_compressed_bytes and packed into one uint8 tensor."""
 
     def __init__(self, frames, peaks, prm, tile_rows=0, tile_strips=0):
         torch = _torch()

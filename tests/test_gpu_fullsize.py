@@ -69,8 +69,8 @@ def _check_headers(B, sizes, shape, w, b, eb, counts):
         assert d["stream_bytes"] == int(sizes[i]) == d["off"]["total"], f"frame {i}"
 
 
-def _check_oracle(B, sizes, host, idx, shape, w, b, eb, dim=2, roi_coding=0):
-    p = O.params(*shape, w, b, eb, 0, dim, roi_coding)
+def _check_oracle(B, sizes, host, idx, shape, w, b, eb, dim=2, roi_coding=0, run_coding=0):
+    p = O.params(*shape, w, b, eb, 0, dim, roi_coding, run_coding)
     for i in idx:
         print(f"  oracle frame {i} ({host[i][1].shape[0]} peaks)", flush=True)
         st, ref, _ = O.compress(p, *host[i])
@@ -137,6 +137,29 @@ def test_cspad_batch_1000_roi_coded(torch, cspad_1000):
     for i in range(0, len(counts), 97):
         d = F.parse(B.stream(i, sizes).cpu().numpy())
         assert d["roi_coded"] and d["stream_bytes"] == int(sizes[i]) == d["off"]["total"]
+
+
+def test_cspad_batch_1000_run_coded(torch, cspad_1000):
+    """The run stage over the whole batch, with the ROI coded too: sampled
+    frames bit for bit, every stream's sections add up, and the decoder
+    restores frame 0 like the oracle's."""
+    host, frames, peaks = cspad_1000
+    print("cspad batch 1000 runs coded", flush=True)
+    B = rsz.Batch(frames, peaks, (17, 2, 10.0, 0, 2, 1, 1))
+    B.run()
+    torch.cuda.synchronize()
+    assert (B.status.cpu().numpy() == 0).all()
+    sizes = B.sizes.cpu().numpy()
+    counts = [p.shape[0] for _, p in host]
+    _check_oracle(B, sizes, host, _sample(counts, 8, 300), (32, 185, 388), 17, 2, 10.0, 2, 1, 1)
+    for i in range(0, len(counts), 97):
+        d = F.parse(B.stream(i, sizes).cpu().numpy())
+        assert d["run_coded"] and d["stream_bytes"] == int(sizes[i]) == d["off"]["total"]
+    s0 = B.stream(0, sizes)
+    y = rsz.decompress(s0).cpu().numpy()
+    st, yref = O.decompress(s0.cpu().numpy())
+    assert st == O.OK
+    np.testing.assert_array_equal(y.view(np.uint32), yref.view(np.uint32))
 
 
 # ------------------------------------------------------ Jungfrau-4M x 256
