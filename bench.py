@@ -176,31 +176,34 @@ def lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips
     return out
 
 
-def roi_coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_strips):
+def coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_strips, roi, run,
+                   steps, label):
     """The same batch with the ROI windows coded losslessly instead of stored
-    verbatim: whole-path GB/s, compression ratio and per-kernel times."""
+    verbatim (roi) and/or the Huffman bits' zero runs Rice coded (run):
+    whole-path GB/s, compression ratio and per-kernel times."""
     import numpy as np
     from paper_2206_11297_amd import rsz
-    B = rsz.Batch(frames, peaks, prm + (2, 1), tile_rows=tile_rows, tile_strips=tile_strips)
+    B = rsz.Batch(frames, peaks, prm + (2, roi, run), tile_rows=tile_rows,
+                  tile_strips=tile_strips)
     for _ in range(2):
         B.run()
     torch.cuda.synchronize()
     st = B.status.cpu().numpy()
-    assert (st == 0).all(), f"roi coding: statuses {set(st.tolist())}"
+    assert (st == 0).all(), f"{label}: statuses {set(st.tolist())}"
     rsz.rsz_profile_enable(True)
     t0 = time.perf_counter()
-    for _ in range(args.roi_steps):
+    for _ in range(steps):
         B.run()
     torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / args.roi_steps
+    el = (time.perf_counter() - t0) / steps
     prof = rsz.rsz_profile_read()
     rsz.rsz_profile_enable(False)
     sizes = B.sizes.cpu().numpy().astype(np.int64)
     out = {"value": round(raw_bytes / el / 1e9, 2), "unit": "GB/s", "ms_per_step": round(el * 1e3, 4),
-           "steps": args.roi_steps,
+           "steps": steps,
            "compression_ratio_u16_aggregate": round(float(raw_bytes / 2 / sizes.sum()), 3),
            "kernel_ms": {k: round(v[1] / v[0], 4) for k, v in prof.items()}}
-    print(f"[bench] roi coding: {out['value']} GB/s, CR {out['compression_ratio_u16_aggregate']}",
+    print(f"[bench] {label}: {out['value']} GB/s, CR {out['compression_ratio_u16_aggregate']}",
           file=sys.stderr, flush=True)
     del B
     torch.cuda.empty_cache()
@@ -450,6 +453,9 @@ def main():
     ap.add_argument("--dims-steps", type=int, default=10)
     ap.add_argument("--roi-steps", type=int, default=10,
                     help="steps of the ROI-coding section (0: skip it)")
+    ap.add_argument("--run-steps", type=int, default=10,
+                    help="steps of the run-coding sections, alone and with the ROI coded "
+                         "(0: skip them)")
     ap.add_argument("--peaks-steps", type=int, default=10,
                     help="steps of the peak-finding section (0: skip it)")
     args = ap.parse_args()
@@ -567,8 +573,12 @@ def main():
     serving = serving_section(args, torch, dev) if args.serve_rates else None
     dims = lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips,
                                 raw_bytes) if args.dims else None
-    roi = roi_coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows,
-                             tile_strips) if args.roi_steps else None
+    roi = coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_strips, 1, 0,
+                         args.roi_steps, "roi coding") if args.roi_steps else None
+    runs = coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_strips, 0,
+                          1, args.run_steps, "run coding") if args.run_steps else None
+    both = coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_strips, 1,
+                          1, args.run_steps, "roi + run coding") if args.run_steps else None
     pk = peaks_section(args, torch, frames, prm, raw_bytes, tile_rows,
                        tile_strips) if args.peaks_steps else None
 
@@ -602,6 +612,8 @@ def main():
         "decompress": decomp,
         "lorenzo_dims": dims,
         "roi_coding": roi,
+        "run_coding": runs,
+        "roi_and_run_coding": both,
         "peak_finding": pk,
     }
     if serving:

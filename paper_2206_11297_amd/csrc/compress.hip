@@ -1643,79 +1643,129 @@ __device__ __forceinline__ uint32_t wave_max_scan(uint32_t v) {
   return v;
 }
 
-// The walk shared by k_run_count and k_run_pack: blocks of 64 words, lane l
-// on word base + l.  For each block, `prev` is the position after the last
-// one bit before the lane's word (the chunk start if none); ones give runs
-// one - prev, in raster order within the lane.  Returns the word, with its
-// bits outside the chunk cleared.
-struct RunWalk {
-  uint32_t S0, S1, w0, w1, carry;   // carry: after the last one of earlier blocks
-  __device__ void init(const FramePlan &fp, const FrameState *st, uint32_t c) {
-    S0 = fp.chunk_off[c];
-    S1 = c + 1 < fp.nchunks ? fp.chunk_off[c + 1] : (uint32_t)st->T;
-    w0 = S0 >> 5;
-    w1 = (S1 + 31) >> 5;
-    carry = S0;
+// A chunk's Huffman bits [S0, S1), words w0 .. w1 - 1, walked in blocks of
+// 64 words (lane l on word base + l).  The first kRunPre blocks are loaded
+// up front (their loads in flight together); later blocks, rare, load as
+// they come.
+constexpr int kRunPre = 4;
+struct RunChunk {
+  uint32_t S0, S1, w0, w1, nblk;
+  uint32_t word[kRunPre];
+};
+
+__device__ __forceinline__ void run_chunk(const FramePlan &fp, const FrameState *st, uint32_t c,
+                                          RunChunk &ch) {
+  const int lane = threadIdx.x & 63;
+  ch.S0 = fp.chunk_off[c];
+  ch.S1 = c + 1 < fp.nchunks ? fp.chunk_off[c + 1] : (uint32_t)st->T;
+  ch.w0 = ch.S0 >> 5;
+  ch.w1 = (ch.S1 + 31) >> 5;
+  ch.nblk = (ch.w1 - ch.w0 + 63) / 64;
+#pragma unroll
+  for (int b = 0; b < kRunPre; ++b) {
+    const uint32_t i = ch.w0 + 64 * b + lane;
+    ch.word[b] = i < ch.w1 ? chunk_word(fp, c, ch.S0, i) : 0u;
   }
-  // this lane's word of the block at `base`, and the position after the last
-  // one bit before it
-  __device__ uint32_t load(const FramePlan &fp, uint32_t c, uint32_t base, uint32_t &prev) {
-    const int lane = threadIdx.x & 63;
+}
+
+// Calls g(base, word) for each block, base its first word's index.
+template <class G>
+__device__ __forceinline__ void for_each_word(const FramePlan &fp, uint32_t c, const RunChunk &ch,
+                                              G &&g) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int b = 0; b < kRunPre; ++b)
+    if (b < (int)ch.nblk) g(ch.w0 + 64 * b, ch.word[b]);
+  for (uint32_t b = kRunPre; b < ch.nblk; ++b) {
+    const uint32_t base = ch.w0 + 64 * b, i = base + lane;
+    g(base, i < ch.w1 ? chunk_word(fp, c, ch.S0, i) : 0u);
+  }
+}
+
+// Calls g(at, word, prev) for each block: at = the bit position of the
+// lane's word, prev = the position after the last one bit before that word
+// (the chunk start if none).  The runs of the lane's ones, in order, are
+// one - prev, then one - (previous one + 1).
+template <class G>
+__device__ __forceinline__ void for_each_block(const FramePlan &fp, uint32_t c, const RunChunk &ch,
+                                               G &&g) {
+  const int lane = threadIdx.x & 63;
+  uint32_t carry = ch.S0;   // after the last one of the earlier blocks
+  for_each_word(fp, c, ch, [&](uint32_t base, uint32_t word) {
     const uint32_t i = base + lane;
-    const uint32_t word = i < w1 ? chunk_word(fp, c, S0, i) : 0u;
     const uint32_t after = word ? 32 * i + (32 - __builtin_ctz(word)) : 0u;
     const uint32_t incl = wave_max_scan(after);
     const uint32_t excl = __shfl_up(incl, 1);
-    prev = max(carry, lane ? excl : 0u);
+    const uint32_t prev = max(carry, lane ? excl : 0u);
     carry = max(carry, __shfl(incl, 63));
-    return word;
-  }
-};
+    g(32 * i, word, prev);
+  });
+}
 
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d));
+  return v;
+}
+
+// The chunk's cost f(k) = sum(r >> k) + n (1 + k) is convex in k: f(k+1) -
+// f(k) = n - sum(ceil((r >> k) / 2)), which never decreases.  While 3 n 2^k
+// < S (S the sum of the runs) that difference is negative, and once n 2^k >=
+// S it is >= 0, so the smallest minimiser lies in [kl, kl + 2] with kl the
+// smallest k where 3 n 2^k >= S.  n is the popcount of the chunk's bits and
+// S telescopes to (last one + 1) - S0 - n; one walk over the ones then
+// gives the three costs.  A chunk holds at most 4096 * 32 bits, so every
+// sum fits 32 bits.
 __global__ __launch_bounds__(256) void k_run_count(BatchPlan bp) {
   const int lane = threadIdx.x & 63;
   const uint32_t item = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (item >= bp.total_chunks) return;
   const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, item);
   const FramePlan &fp = bp.frames[f];
-  if (!fp.run_coding || load_status(fp.st) != RSZ_OK) return;
+  const FrameState *st = fp.st;
+  if (!fp.run_coding || load_status(st) != RSZ_OK) return;
   const uint32_t c = item - bp.chunk_prefix[f];
-  RunWalk rw;
-  rw.init(fp, fp.st, c);
-  // acc[k] = sum of r >> k over the chunk's ones; a chunk holds at most
-  // 4096 * 32 bits, so every cost fits 32 bits
-  uint32_t acc[kRunKMax + 1];
-#pragma unroll
-  for (int k = 0; k <= (int)kRunKMax; ++k) acc[k] = 0;
-  uint32_t ones = 0;
-  for (uint32_t base = rw.w0; base < rw.w1; base += 64) {
-    uint32_t prev;
-    uint32_t word = rw.load(fp, c, base, prev);
-    const uint32_t at = 32 * (base + lane);
+  RunChunk ch;
+  run_chunk(fp, st, c, ch);
+  uint32_t n = 0, after = 0;
+  for_each_word(fp, c, ch, [&](uint32_t base, uint32_t word) {
+    n += __popc(word);
+    if (word) after = max(after, 32 * (base + lane) + (32 - __builtin_ctz(word)));
+  });
+  n = wave_sum(n);
+  after = wave_max(after);
+  const uint32_t S = n ? after - ch.S0 - n : 0u;
+  uint32_t kl = 0;
+  while (kl < kRunKMax && 3ull * n * (1ull << kl) < S) kl++;
+  uint32_t a0 = 0, a1 = 0, a2 = 0;
+  for_each_block(fp, c, ch, [&](uint32_t at, uint32_t word, uint32_t prev) {
     while (word) {
       const uint32_t t = __builtin_clz(word);
       word &= ~(0x80000000u >> t);
       const uint32_t r = at + t - prev;
       prev = at + t + 1;
-      ones++;
-#pragma unroll
-      for (int k = 0; k <= (int)kRunKMax; ++k) acc[k] += r >> k;
+      a0 += r >> kl;
+      a1 += r >> (kl + 1);
+      a2 += r >> (kl + 2);
     }
+  });
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  uint32_t best = kl, cost = a0 + n * (1 + kl);
+  if (kl + 1 <= kRunKMax && a1 + n * (2 + kl) < cost) {
+    best = kl + 1;
+    cost = a1 + n * (2 + kl);
   }
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) {
-    ones += __shfl_xor(ones, d);
-#pragma unroll
-    for (int k = 0; k <= (int)kRunKMax; ++k) acc[k] += __shfl_xor(acc[k], d);
-  }
-  uint32_t best = 0, cost = acc[0] + ones;
-#pragma unroll
-  for (int k = 1; k <= (int)kRunKMax; ++k) {
-    const uint32_t ck = acc[k] + ones * (1u + k);
-    if (ck < cost) {
-      cost = ck;
-      best = k;
-    }
+  if (kl + 2 <= kRunKMax && a2 + n * (3 + kl) < cost) {
+    best = kl + 2;
+    cost = a2 + n * (3 + kl);
   }
   if (lane == 0) {
     fp.run_off[c] = cost;
@@ -1752,11 +1802,75 @@ __device__ __forceinline__ void or_ones(uint32_t *words, uint64_t pos, uint64_t 
   }
 }
 
-// The codes of each chunk at its offset, ORed into the run words k_tail
-// zeroed (chunks share their boundary words).
+// A lane's codes occupy one contiguous range of bits: they are assembled in
+// a 64-bit register and leave as whole words, aligned to the destination's
+// words.  Only the range's first and last words can be shared with another
+// lane (or chunk), so only they are ORed atomically; the words between are
+// stored.
+struct LaneBits {
+  uint32_t *dst;
+  uint64_t w;      // destination word of the next whole word
+  uint64_t acc;    // pending bits in the low n bits (higher bits are stale)
+  uint32_t n;
+  bool first;
+  __device__ void init(uint32_t *d, uint64_t pos) {
+    dst = d;
+    w = pos >> 5;
+    acc = 0;
+    n = (uint32_t)(pos & 31);   // zero bits that align the words
+    first = true;
+  }
+  // appends the len (1..32) low bits of v, MSB-first
+  __device__ void put(uint32_t v, uint32_t len) {
+    acc = (acc << len) | v;
+    n += len;
+    if (n >= 32) {
+      const uint32_t word = (uint32_t)(acc >> (n - 32));
+      if (first) {
+        if (word) atomicOr(&dst[w], word);
+        first = false;
+      } else {
+        dst[w] = word;
+      }
+      w++;
+      n -= 32;
+    }
+  }
+  __device__ void finish() {
+    if (n) {
+      const uint32_t word = (uint32_t)(acc << (32 - n));
+      if (word) atomicOr(&dst[w], word);
+    }
+  }
+};
+
+// Words [0, nw) of a wave's staging buffer to the stream words from word
+// `wbase`: the first and last by atomicOr (a neighbouring chunk, or codes
+// written directly, may share them), the rest by plain stores (this chunk's
+// alone).
+constexpr uint32_t kRunBufWords = 512;
+__device__ __forceinline__ void run_flush(const uint32_t *buf, uint32_t *out, uint64_t wbase,
+                                          uint32_t nw) {
+  for (uint32_t i = threadIdx.x & 63; i < nw; i += 64) {
+    const uint32_t v = buf[i];
+    if (i == 0 || i + 1 == nw) {
+      if (v) atomicOr(&out[wbase + i], v);
+    } else {
+      out[wbase + i] = v;
+    }
+  }
+}
+
+// The codes of each chunk at its offset in the run words k_tail zeroed.  A
+// wave stages its chunk's codes in an LDS buffer of kRunBufWords words (ORed
+// in by LDS atomics) and stores whole words; a block of 64 input words whose
+// codes would overflow the buffer flushes it first, and if they still do not
+// fit, ORs them straight into the stream.
 __global__ __launch_bounds__(256) void k_run_pack(BatchPlan bp) {
+  __shared__ uint32_t s_buf[kWaves][kRunBufWords];
   const int lane = threadIdx.x & 63;
-  const uint32_t item = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t item = blockIdx.x * kWaves + wv;
   if (item >= bp.total_chunks) return;
   const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, item);
   const FramePlan &fp = bp.frames[f];
@@ -1764,14 +1878,15 @@ __global__ __launch_bounds__(256) void k_run_pack(BatchPlan bp) {
   if (!fp.run_coding || load_status(st) != RSZ_OK) return;
   const uint32_t c = item - bp.chunk_prefix[f];
   uint32_t *out = (uint32_t *)(fp.out + st->off_runbits);
+  uint32_t *buf = s_buf[wv];
+  for (uint32_t i = lane; i < kRunBufWords; i += 64) buf[i] = 0u;
+  wave_sync();
   const uint32_t k = fp.run_k[c];
   uint64_t base_bit = fp.run_off[c];
-  RunWalk rw;
-  rw.init(fp, st, c);
-  for (uint32_t base = rw.w0; base < rw.w1; base += 64) {
-    uint32_t prev;
-    const uint32_t word = rw.load(fp, c, base, prev);
-    const uint32_t at = 32 * (base + lane);
+  uint64_t wbase = base_bit >> 5;   // stream word of buf[0]
+  RunChunk ch;
+  run_chunk(fp, st, c, ch);
+  for_each_block(fp, c, ch, [&](uint32_t at, uint32_t word, uint32_t prev) {
     // this lane's code bits, placed by a wave scan
     uint32_t bits = 0, p = prev, w = word;
     while (w) {
@@ -1781,7 +1896,27 @@ __global__ __launch_bounds__(256) void k_run_pack(BatchPlan bp) {
       p = at + t + 1;
     }
     uint64_t tot;
-    uint64_t pos = base_bit + wave_exclusive_scan(bits, tot);
+    const uint64_t ex = wave_exclusive_scan(bits, tot);
+    bool direct = false;
+    if ((base_bit + tot + 31) / 32 - wbase > kRunBufWords) {
+      // keep only the partial word at base_bit
+      const uint32_t nw = (uint32_t)((base_bit >> 5) - wbase);
+      run_flush(buf, out, wbase, nw);
+      const uint32_t part = nw < kRunBufWords ? buf[nw] : 0u;
+      wave_sync();
+      for (uint32_t i = lane; i < kRunBufWords; i += 64) buf[i] = i == 0 ? part : 0u;
+      wave_sync();
+      wbase += nw;
+      if ((base_bit + tot + 31) / 32 - wbase > kRunBufWords) {
+        direct = true;
+        if (lane == 0 && part) atomicOr(&out[wbase], part);
+        wave_sync();
+        if (lane == 0) buf[0] = 0u;
+        wave_sync();
+      }
+    }
+    LaneBits lb;
+    lb.init(direct ? out : buf, base_bit + ex - (direct ? 0 : 32 * wbase));
     p = prev;
     w = word;
     while (w) {
@@ -1789,14 +1924,17 @@ __global__ __launch_bounds__(256) void k_run_pack(BatchPlan bp) {
       w &= ~(0x80000000u >> t);
       const uint32_t r = at + t - p;
       p = at + t + 1;
-      const uint32_t q = r >> k;
-      or_ones(out, pos, q);
-      pos += q + 1;   // the zero closing the unary part
-      if (k) or_bits(out, pos, r & ((1u << k) - 1u), k);
-      pos += k;
+      uint32_t q = r >> k;
+      for (; q >= 32; q -= 32) lb.put(0xFFFFFFFFu, 32);
+      lb.put(((1u << q) - 1u) << 1, q + 1);   // q ones and the closing zero
+      if (k) lb.put(r & ((1u << k) - 1u), k);
     }
+    lb.finish();
+    wave_sync();
     base_bit += tot;
-  }
+    if (direct) wbase = base_bit >> 5;   // the buffer is empty again
+  });
+  run_flush(buf, out, wbase, (uint32_t)((base_bit + 31) / 32 - wbase));
 }
 
 // -------------------------------------------------------------- launchers

@@ -228,3 +228,42 @@ def test_a_one_bit_past_its_chunk_is_rejected():
     moved[0].append(moved[1].pop(0))
     s2 = _rebuild(s1, d, moved)
     assert O.decompress(s2)[0] == O.ERR_CORRUPT
+
+
+def test_rice_parameter_window():
+    """The fact the GPU parameter search rests on.  With n runs of sum S, the
+    cost f(k) = sum(r >> k) + n (1 + k) is convex in k (f(k+1) - f(k) = n -
+    sum(ceil((r >> k) / 2)) never decreases), f(k+1) < f(k) while 3 n 2^k <
+    S, and f(k+1) >= f(k) once n 2^k >= S.  So the smallest minimiser over
+    0..20 lies in [kl, kl + 2] with kl the smallest k with 3 n 2^k >= S (then
+    clamped to 20).  Checked exhaustively against the argmin on random run
+    lists of many shapes, and the window is tight (every offset occurs)."""
+    rng = np.random.default_rng(5)
+    seen = set()
+    for t in range(4000):
+        n = int(rng.integers(1, 60))
+        kind = t % 4
+        if kind == 0:
+            r = rng.geometric(1.0 / float(rng.uniform(1, 5000)), n) - 1
+        elif kind == 1:
+            r = rng.integers(0, 1 << int(rng.integers(0, 18)), n)
+        elif kind == 2:
+            r = np.where(rng.random(n) < 0.9, 0, rng.integers(0, 1 << 17, n))
+        else:
+            r = np.full(n, int(rng.integers(0, 1 << 17)))
+        if t % 50 == 0:
+            # one run of 6 * 2^j and three of 2 * 2^j: S = 3 n 2^j, so kl = j,
+            # and the costs give k = j + 2 (the window's last value)
+            j = int(rng.integers(0, 15))
+            r, n = np.array([6 << j] + [2 << j] * 3), 4
+        r = r.astype(np.int64)
+        cost = [int((r >> k).sum()) + n * (1 + k) for k in range(21)]
+        best = int(np.argmin(cost))
+        S = int(r.sum())
+        kl = 0
+        while 3 * n * (1 << kl) < S:
+            kl += 1
+        kl = min(kl, 20)
+        assert kl <= best <= min(kl + 2, 20), (n, S, kl, best)
+        seen.add(best - kl)
+    assert seen == {0, 1, 2}
