@@ -9,14 +9,22 @@
 //               2D Lorenzo + code/outlier + histogram; one wave per tile
 //               (segment of bin rows x column group of 64-column strips of a
 //               panel), walking it row by row.
+//   k_lorenzo_dims  Lorenzo dimensions 1 and 3: the residuals k_bin's 2D
+//               predictor leaves to finish (row ends; the panel axis).
 //   k_codebook  one workgroup per frame: Huffman lengths and canonical codes.
 //   k_count     one wave per 4096-symbol chunk: its bits and outliers.
 //   k_scan      one workgroup per frame: chunk bit and outlier offsets.
 //   k_encode    one workgroup per run of chunks: bit-packing and outlier
 //               indices at the offsets k_codebook computed.
+//   k_roi_classes, k_roi_book, k_roi_count, k_roi_scan  coded ROI: class
+//               histogram, class code, window bits and offsets.
+//   k_run_count, k_run_scan  run stage: each chunk's Rice parameter and run
+//               bits, then their offsets.
 //   k_tail      one workgroup per frame: sizes, capacity, header, chunk
-//               boundary words, outlier sections.
-//   k_roi       one workgroup per peak: ROI window payload, bit copies.
+//               boundary words, outlier sections, coded ROI and run section
+//               tables.
+//   k_roi       one wave per four peaks: ROI window payload, bit copies.
+//   k_roi_pack, k_run_pack  the coded ROI bits and the run codes.
 #include <algorithm>
 
 #include "rsz_internal.h"
