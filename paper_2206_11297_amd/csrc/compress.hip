@@ -23,7 +23,7 @@
 //   k_tail      one workgroup per frame: sizes, capacity, header, chunk
 //               boundary words, outlier sections, coded ROI and run section
 //               tables.
-//   k_roi       one wave per four peaks: ROI window payload, bit copies.
+//   k_roi       one wave per peak: ROI window payload, bit copies.
 //   k_roi_pack, k_run_pack  the coded ROI bits and the run codes.
 #include <algorithm>
 
@@ -1417,32 +1417,41 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
 // ------------------------------------------------------------------ k_roi
 
 // ROI payload (Sec. IV-A: each peak's w x w window as a buffer, a constant
-// fill outside the panel): one wave per peak, kRoiPeaksPerWave peaks per
-// wave, flat over the window's w*w pixels.  Window row u = e / w from a
-// multiply-high by floor((2^32 - 1) / w) + 1, exact for e < w^2 since
-// w^3 < 2^32.
-constexpr uint32_t kRoiPeaksPerWave = 4;
+// fill outside the panel): one wave per peak, flat over the window's w*w
+// pixels, kRoiSlots pixels per lane loaded before any is stored (so a
+// window's loads are in flight together: the stores could alias the frame as
+// far as the compiler knows).  Window row u = e / w from a multiply-high by
+// floor((2^32 - 1) / w) + 1, exact for e < w^2 since w^3 < 2^32.
+constexpr uint32_t kRoiPeaksPerWave = 4;   // the coded-ROI kernels
+constexpr uint32_t kRoiSlots = 8;
 __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
   const int lane = threadIdx.x & 63;
-  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t first = (blockIdx.x * kWaves + wv) * kRoiPeaksPerWave;
-  for (uint32_t kg = first; kg < first + kRoiPeaksPerWave && kg < bp.total_peaks; ++kg) {
-    const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
-    const FramePlan &fp = bp.frames[f];
-    if (fp.roi_coding || load_status(fp.st) != RSZ_OK) continue;
-    const uint32_t k = kg - bp.peak_prefix[f];
-    const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
-    if (pa < 0 || pa >= fp.P) continue;
-    const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
-    const int64_t h = w / 2;
-    uint32_t *dst = (uint32_t *)(fp.out + fp.off_roi) + (size_t)k * ww;
-    const float *src = fp.frame + (size_t)pa * fp.H * fp.W;
-    for (uint32_t e = lane; e < ww; e += 64) {
+  const uint32_t kg = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (kg >= bp.total_peaks) return;
+  const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
+  const FramePlan &fp = bp.frames[f];
+  if (fp.roi_coding || load_status(fp.st) != RSZ_OK) return;
+  const uint32_t k = kg - bp.peak_prefix[f];
+  const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
+  if (pa < 0 || pa >= fp.P) return;
+  const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+  const int64_t h = w / 2, H = fp.H, W = fp.W;
+  uint32_t *dst = (uint32_t *)(fp.out + fp.off_roi) + (size_t)k * ww;
+  const float *src = fp.frame + (size_t)pa * H * W;
+  for (uint32_t e0 = 0; e0 < ww; e0 += 64 * kRoiSlots) {
+    uint32_t val[kRoiSlots];
+#pragma unroll
+    for (uint32_t t = 0; t < kRoiSlots; ++t) {
+      const uint32_t e = e0 + 64 * t + lane;
       const uint32_t u = __umulhi(e, M), v = e - u * w;
       const int64_t i = r - h + u, j = c - h + v;
-      uint32_t bits = 0u;
-      if (i >= 0 && i < fp.H && j >= 0 && j < fp.W) bits = __float_as_uint(src[i * fp.W + j]);
-      dst[e] = bits;
+      val[t] = 0u;
+      if (e < ww && i >= 0 && i < H && j >= 0 && j < W) val[t] = __float_as_uint(src[i * W + j]);
+    }
+#pragma unroll
+    for (uint32_t t = 0; t < kRoiSlots; ++t) {
+      const uint32_t e = e0 + 64 * t + lane;
+      if (e < ww) dst[e] = val[t];
     }
   }
 }
@@ -2028,7 +2037,7 @@ hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
   }
   RSZ_LAUNCH("k_tail", k_tail, bp.nframes, s, bp);
   if (bp.total_peaks) {
-    RSZ_LAUNCH("k_roi", k_roi, roi_grid, s, bp);
+    RSZ_LAUNCH("k_roi", k_roi, (bp.total_peaks + kWaves - 1) / kWaves, s, bp);
     if (bp.roi_coding) RSZ_LAUNCH("k_roi_pack", k_roi_pack, roi_grid, s, bp);
   }
   if (bp.run_coding && bp.total_chunks) RSZ_LAUNCH("k_run_pack", k_run_pack, run_grid, s, bp);
