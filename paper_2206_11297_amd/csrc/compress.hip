@@ -1021,6 +1021,34 @@ __global__ __launch_bounds__(256) void k_count(BatchPlan bp) {
   s_len4[wv][lane] = ((const uint4 *)fp.st->lens)[lane];
   wave_sync();
   const uint8_t *lens = (const uint8_t *)s_len4[wv];
+  // fast path, the common case: a whole chunk with no escape byte in the
+  // wave (a zero byte is found four at a time: (x - 0x01010101) & ~x &
+  // 0x80808080 is non-zero exactly when x has one); then every code is its
+  // byte + 384 and no bin is an outlier
+  uint32_t zero = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t w4[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) zero |= (w4[e] - 0x01010101u) & ~w4[e] & 0x80808080u;
+  }
+  if ((c + 1) * kChunk <= fp.nbins && __ballot(zero != 0) == 0) {
+    const uint8_t *lb = lens + (kRadius - 128);
+    uint32_t fbits = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t w4[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+      for (int e = 0; e < 16; ++e) fbits += lb[(w4[e >> 2] >> (8 * (e & 3))) & 0xFFu];
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) fbits += __shfl_xor(fbits, d);
+    if (lane == 0) {
+      fp.chunk_off[c] = fbits;
+      fp.chunk_oo[c] = 0;
+    }
+    return;
+  }
   uint32_t bits = 0, nout = 0;
   uint64_t esc = 0;   // this lane's bytes that defer to the residual
 #pragma unroll
@@ -1097,6 +1125,18 @@ __device__ __forceinline__ uint64_t wave_exclusive_scan(uint64_t v, uint64_t &to
   return x - v;
 }
 
+__device__ __forceinline__ uint32_t wave_exclusive_scan32(uint32_t v, uint32_t &total) {
+  const int lane = threadIdx.x & 63;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  total = __shfl(x, 63);
+  return x - v;
+}
+
 // One workgroup per run of bp.cpw consecutive chunks of a frame; its four
 // waves take every fourth chunk, each chunk's bit and outlier offsets come
 // from k_scan, so nothing waits across waves.  A wave packs its chunk in four
@@ -1149,6 +1189,48 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
       const uint32_t g0 = lc * kChunk + r * kRoundSyms + lane * 16;
       const uint32_t w4[4] = {nx.x, nx.y, nx.z, nx.w};
       if (r + 1 < kChunk / kRoundSyms) nx = *(const uint4 *)(fp.codes + g0 + kRoundSyms);
+      // fast path, the common case: a whole round with no escape byte in the
+      // wave, so every code is its byte + 384 and there is no outlier
+      uint32_t zero = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) zero |= (w4[e] - 0x01010101u) & ~w4[e] & 0x80808080u;
+      if ((lc * kChunk + (r + 1) * kRoundSyms) <= fp.nbins && __ballot(zero != 0) == 0) {
+        const uint8_t *lb = s_len + (kRadius - 128);
+        const uint32_t *cb = s_cw + (kRadius - 128);
+        uint32_t bits = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) bits += lb[(w4[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+        uint32_t tot;
+        uint32_t p = pos + wave_exclusive_scan32(bits, tot);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const uint32_t b = (w4[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+          const uint32_t L = lb[b];
+          const uint64_t v = ((uint64_t)cb[b] << (64 - L)) >> (p & 31);
+          if (v >> 32) atomicOr(&stg[p >> 5], (uint32_t)(v >> 32));
+          if ((uint32_t)v) atomicOr(&stg[(p >> 5) + 1], (uint32_t)v);
+          p += L;
+        }
+        wave_sync();
+        const uint32_t end = pos + tot;   // bits in stg
+        const uint32_t nw = end >> 5;     // complete words
+        for (uint32_t k = lane; k < nw; k += 64) {
+          const uint32_t v = stg[k];
+          if (k == 0 && first) {
+            fp.head[lc] = v;
+            continue;
+          }
+          if (widx + k < bcap) bw[widx + k] = v;
+        }
+        if (nw) first = false;
+        const uint32_t carry = stg[nw];
+        wave_sync();
+        for (uint32_t k = lane; k <= nw; k += 64) stg[k] = k == 0 ? carry : 0u;
+        wave_sync();
+        pos = end & 31;
+        widx += nw;
+        continue;
+      }
       uint32_t code[16];
       uint32_t bits = 0, nout = 0;
 #pragma unroll
