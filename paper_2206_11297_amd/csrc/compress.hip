@@ -996,6 +996,33 @@ __global__ __launch_bounds__(256) void k_codebook(BatchPlan bp) {
   build_code(st, st->hist, st->lens, st->cw);
 }
 
+// Bit k of the result (k = 0..15) is set where byte k of the 16 bytes w
+// differs from 0x80, the code byte of residual 0.  Per 32-bit word, x = w ^
+// 0x80808080 has a zero byte exactly where w has 0x80, and ((x & 0x7F7F7F7F)
+// + 0x7F7F7F7F) | x sets each byte's top bit exactly where that byte of x is
+// not zero (no carry crosses a byte).
+__device__ __forceinline__ uint32_t non_zero_residuals(const uint32_t (&w)[4]) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t x = w[e] ^ 0x80808080u;
+    const uint32_t hi = (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+    m |= ((hi >> 7) & 1u) << (4 * e) | ((hi >> 15) & 1u) << (4 * e + 1) |
+         ((hi >> 23) & 1u) << (4 * e + 2) | (hi >> 31) << (4 * e + 3);
+  }
+  return m;
+}
+
+// Byte k (0..15, any lane value) of the 16 bytes w.
+__device__ __forceinline__ uint32_t byte_at(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                            uint32_t k) {
+  const uint32_t x = k < 8 ? (k < 4 ? w0 : w1) : (k < 12 ? w2 : w3);
+  return (x >> (8 * (k & 3))) & 0xFFu;
+}
+
+// Sparse rounds: at most this many bytes per lane differ from residual 0's.
+constexpr uint32_t kSparseBytes = 4;
+
 // ---------------------------------------------------------------- k_count
 
 // Bits and outliers of every 4096-symbol chunk: one wave per chunk, 64 code
@@ -1197,19 +1224,38 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
       if ((lc * kChunk + (r + 1) * kRoundSyms) <= fp.nbins && __ballot(zero != 0) == 0) {
         const uint8_t *lb = s_len + (kRadius - 128);
         const uint32_t *cb = s_cw + (kRadius - 128);
-        uint32_t bits = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) bits += lb[(w4[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+        const uint32_t nz = non_zero_residuals(w4);
         uint32_t tot;
-        uint32_t p = pos + wave_exclusive_scan32(bits, tot);
+        if (cb[128] == 0 && __ballot(__builtin_popcount(nz) > kSparseBytes) == 0) {
+          // residual 0's codeword is all zeros: its bins only advance the
+          // position; the few other bytes are placed from their index
+          const uint32_t L0 = lb[128];
+          uint32_t bits = 16 * L0;
+          for (uint32_t m = nz; m; m &= m - 1) bits += lb[byte_at(w4[0], w4[1], w4[2], w4[3], __builtin_ctz(m))] - L0;
+          const uint32_t p0 = pos + wave_exclusive_scan32(bits, tot);
+          uint32_t extra = 0;
+          for (uint32_t m = nz; m; m &= m - 1) {
+            const uint32_t k = __builtin_ctz(m), b = byte_at(w4[0], w4[1], w4[2], w4[3], k), L = lb[b];
+            const uint32_t p = p0 + k * L0 + extra;
+            const uint64_t v = ((uint64_t)cb[b] << (64 - L)) >> (p & 31);
+            if (v >> 32) atomicOr(&stg[p >> 5], (uint32_t)(v >> 32));
+            if ((uint32_t)v) atomicOr(&stg[(p >> 5) + 1], (uint32_t)v);
+            extra += L - L0;
+          }
+        } else {
+          uint32_t bits = 0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const uint32_t b = (w4[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-          const uint32_t L = lb[b];
-          const uint64_t v = ((uint64_t)cb[b] << (64 - L)) >> (p & 31);
-          if (v >> 32) atomicOr(&stg[p >> 5], (uint32_t)(v >> 32));
-          if ((uint32_t)v) atomicOr(&stg[(p >> 5) + 1], (uint32_t)v);
-          p += L;
+          for (int k = 0; k < 16; ++k) bits += lb[(w4[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+          uint32_t p = pos + wave_exclusive_scan32(bits, tot);
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const uint32_t b = (w4[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+            const uint32_t L = lb[b];
+            const uint64_t v = ((uint64_t)cb[b] << (64 - L)) >> (p & 31);
+            if (v >> 32) atomicOr(&stg[p >> 5], (uint32_t)(v >> 32));
+            if ((uint32_t)v) atomicOr(&stg[(p >> 5) + 1], (uint32_t)v);
+            p += L;
+          }
         }
         wave_sync();
         const uint32_t end = pos + tot;   // bits in stg
