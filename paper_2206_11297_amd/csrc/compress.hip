@@ -1935,18 +1935,6 @@ __global__ __launch_bounds__(256) void k_run_scan(BatchPlan bp) {
   if (threadIdx.x == 0) fp.run_off[fp.nchunks] = carry;
 }
 
-// Sets the n bits at bit position pos of words (zeroed) to one.
-__device__ __forceinline__ void or_ones(uint32_t *words, uint64_t pos, uint64_t n) {
-  while (n) {
-    const uint32_t s = (uint32_t)(pos & 31);
-    const uint32_t take = (uint32_t)min<uint64_t>(n, 32 - s);
-    const uint32_t mask = (take == 32 ? 0xFFFFFFFFu : ((1u << take) - 1u)) << (32 - s - take);
-    atomicOr(&words[pos >> 5], mask);
-    pos += take;
-    n -= take;
-  }
-}
-
 // A lane's codes occupy one contiguous range of bits: they are assembled in
 // a 64-bit register and leave as whole words, aligned to the destination's
 // words.  Only the range's first and last words can be shared with another

@@ -144,7 +144,6 @@ __global__ __launch_bounds__(256) void k_peaks_find(PeakBatchPlan pp) {
   if (fp.init_status != RSZ_OK) return;
   const uint64_t npix = (uint64_t)fp.P * fp.H * fp.W;
   const uint64_t base = (uint64_t)(blockIdx.x - pp.tile_prefix[f]) * kPeakTile;
-  const double amax = pp.q.amax_min;
   const float *x = fp.frame;
   constexpr int K = (int)(kPeakTile / 1024);   // float4 loads per lane
   float v[K][4];
