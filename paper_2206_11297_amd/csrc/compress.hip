@@ -1550,7 +1550,6 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
 // window's loads are in flight together: the stores could alias the frame as
 // far as the compiler knows).  Window row u = e / w from a multiply-high by
 // floor((2^32 - 1) / w) + 1, exact for e < w^2 since w^3 < 2^32.
-constexpr uint32_t kRoiPeaksPerWave = 4;   // the coded-ROI kernels
 constexpr uint32_t kRoiSlots = 8;
 __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
   const int lane = threadIdx.x & 63;
@@ -1596,7 +1595,7 @@ __global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
 // parallel: k_roi_classes (class histogram), k_roi_book (the code, by the
 // same block function as the main code), k_roi_count and k_roi_scan (window
 // bit offsets), then, after k_tail has checked the size and zeroed the
-// words, k_roi_pack.  One wave per window, kRoiPeaksPerWave windows per wave.
+// words, k_roi_pack.  One wave per window.
 struct RoiWin {
   const float *src;
   int64_t r0, c0, H, W;
@@ -1620,6 +1619,56 @@ __device__ __forceinline__ uint32_t roi_z(const RoiWin &rw, int64_t u, int64_t v
 }
 __device__ __forceinline__ uint32_t roi_class(uint32_t z) { return z ? 32u - __clz(z) : 0u; }
 
+// Windows up to kRoiStageW pixels wide are staged in LDS, one wave per
+// window: the mapped values at row stride w + 1 after a border row and column
+// of mapped +0.0 (the predictor's value outside the window), loaded
+// kRoiSlots per lane before any is stored.  A residual then takes four LDS
+// reads instead of four global loads.  Wider windows read the frame directly.
+constexpr uint32_t kRoiStageW = 31;
+constexpr uint32_t kRoiStageWords = (kRoiStageW + 1) * (kRoiStageW + 1);
+struct RoiVals {
+  RoiWin rw;
+  const uint32_t *s;   // the staged values, or null
+  uint32_t st;         // their row stride
+  __device__ uint32_t z(uint32_t u, uint32_t v) const {
+    if (!s) return roi_z(rw, u, v);
+    const uint32_t *p = s + (u + 1) * st + (v + 1);
+    const int32_t r = (int32_t)(p[0] - (p[-(int)st] + p[-1] - p[-(int)st - 1]));
+    return ((uint32_t)r << 1) ^ (uint32_t)(r >> 31);
+  }
+};
+
+__device__ __forceinline__ void roi_stage(const RoiWin &rw, uint32_t w, uint32_t *buf,
+                                          RoiVals &rv) {
+  rv.rw = rw;
+  rv.s = nullptr;
+  if (w > kRoiStageW) return;
+  const int lane = threadIdx.x & 63;
+  const uint32_t st = w + 1, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+  for (uint32_t e = lane; e < st; e += 64) {
+    buf[e] = 0x80000000u;
+    buf[e * st] = 0x80000000u;
+  }
+  for (uint32_t e0 = 0; e0 < ww; e0 += 64 * kRoiSlots) {
+    uint32_t val[kRoiSlots];
+#pragma unroll
+    for (uint32_t t = 0; t < kRoiSlots; ++t) {
+      const uint32_t e = e0 + 64 * t + lane;
+      const uint32_t u = __umulhi(e, M), v = e - u * w;
+      val[t] = e < ww ? roi_fmap(roi_word(rw, u, v)) : 0u;
+    }
+#pragma unroll
+    for (uint32_t t = 0; t < kRoiSlots; ++t) {
+      const uint32_t e = e0 + 64 * t + lane;
+      const uint32_t u = __umulhi(e, M), v = e - u * w;
+      if (e < ww) buf[(u + 1) * st + v + 1] = val[t];
+    }
+  }
+  wave_sync();
+  rv.s = buf;
+  rv.st = st;
+}
+
 // The window of global peak kg if its frame codes the ROI and is still fine.
 __device__ __forceinline__ bool roi_window(const BatchPlan &bp, uint32_t kg, uint32_t &f,
                                            uint32_t &k, RoiWin &rw) {
@@ -1639,26 +1688,27 @@ __device__ __forceinline__ bool roi_window(const BatchPlan &bp, uint32_t kg, uin
 
 __global__ __launch_bounds__(256) void k_roi_classes(BatchPlan bp) {
   __shared__ uint32_t s_h[kWaves][kRoiClasses];
+  __shared__ uint32_t s_v[kWaves][kRoiStageWords];
   const int lane = threadIdx.x & 63;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t first = (blockIdx.x * kWaves + wv) * kRoiPeaksPerWave;
-  for (uint32_t kg = first; kg < first + kRoiPeaksPerWave && kg < bp.total_peaks; ++kg) {
-    uint32_t f, k;
-    RoiWin rw;
-    if (!roi_window(bp, kg, f, k, rw)) continue;
-    const FramePlan &fp = bp.frames[f];
-    const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
-    for (int c = lane; c < kRoiClasses; c += 64) s_h[wv][c] = 0u;
-    wave_sync();
-    for (uint32_t e = lane; e < ww; e += 64) {
-      const uint32_t u = __umulhi(e, M), v = e - u * w;
-      atomicAdd(&s_h[wv][roi_class(roi_z(rw, u, v))], 1u);
-    }
-    wave_sync();
-    for (int c = lane; c < kRoiClasses; c += 64)
-      if (s_h[wv][c]) atomicAdd(&fp.roi_hist[c], s_h[wv][c]);
-    wave_sync();
+  const uint32_t kg = blockIdx.x * kWaves + wv;
+  if (kg >= bp.total_peaks) return;
+  uint32_t f, k;
+  RoiWin rw;
+  if (!roi_window(bp, kg, f, k, rw)) return;
+  const FramePlan &fp = bp.frames[f];
+  const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+  for (int c = lane; c < kRoiClasses; c += 64) s_h[wv][c] = 0u;
+  RoiVals rv;
+  roi_stage(rw, w, s_v[wv], rv);
+  wave_sync();
+  for (uint32_t e = lane; e < ww; e += 64) {
+    const uint32_t u = __umulhi(e, M), v = e - u * w;
+    atomicAdd(&s_h[wv][roi_class(rv.z(u, v))], 1u);
   }
+  wave_sync();
+  for (int c = lane; c < kRoiClasses; c += 64)
+    if (s_h[wv][c]) atomicAdd(&fp.roi_hist[c], s_h[wv][c]);
 }
 
 __global__ __launch_bounds__(256) void k_roi_book(BatchPlan bp) {
@@ -1669,25 +1719,34 @@ __global__ __launch_bounds__(256) void k_roi_book(BatchPlan bp) {
 
 // Bits of each window (class codeword + raw bits of every value).
 __global__ __launch_bounds__(256) void k_roi_count(BatchPlan bp) {
+  __shared__ uint32_t s_v[kWaves][kRoiStageWords];
   const int lane = threadIdx.x & 63;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t first = (blockIdx.x * kWaves + wv) * kRoiPeaksPerWave;
-  for (uint32_t kg = first; kg < first + kRoiPeaksPerWave && kg < bp.total_peaks; ++kg) {
-    uint32_t f, k;
-    RoiWin rw;
-    if (!roi_window(bp, kg, f, k, rw)) continue;
-    const FramePlan &fp = bp.frames[f];
-    const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
-    uint32_t bits = 0;
-    for (uint32_t e = lane; e < ww; e += 64) {
+  const uint32_t kg = blockIdx.x * kWaves + wv;
+  if (kg >= bp.total_peaks) return;
+  uint32_t f, k;
+  RoiWin rw;
+  if (!roi_window(bp, kg, f, k, rw)) return;
+  const FramePlan &fp = bp.frames[f];
+  const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+  // class c costs its code length plus c - 1 raw bits; lane c holds it
+  const uint32_t cost = lane < kRoiClasses ? fp.roi_lens[lane] + (lane >= 2 ? lane - 1 : 0) : 0u;
+  RoiVals rv;
+  roi_stage(rw, w, s_v[wv], rv);
+  uint32_t bits = 0;
+  for (uint32_t e0 = 0; e0 < ww; e0 += 64) {   // every lane takes part in the shuffle
+    const uint32_t e = e0 + lane;
+    uint32_t c = 0;
+    if (e < ww) {
       const uint32_t u = __umulhi(e, M), v = e - u * w;
-      const uint32_t c = roi_class(roi_z(rw, u, v));
-      bits += fp.roi_lens[c] + (c >= 2 ? c - 1 : 0u);
+      c = roi_class(rv.z(u, v));
     }
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) bits += __shfl_xor(bits, d);
-    if (lane == 0) fp.roi_bits[k] = bits;   // < 2^26 * 63 / npeaks
+    const uint32_t x = __shfl(cost, (int)c);
+    if (e < ww) bits += x;
   }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) bits += __shfl_xor(bits, d);
+  if (lane == 0) fp.roi_bits[k] = bits;   // < 2^26 * 63 / npeaks
 }
 
 // Window bits -> bit offsets (exclusive scan), and the frame's ROI bits.
@@ -1723,37 +1782,68 @@ __device__ __forceinline__ void or_bits(uint32_t *words, uint64_t pos, uint64_t 
   }
 }
 
+// The window's bits go to an LDS buffer of kRoiOutWords words when they fit
+// (ORed in there, then stored as whole words: the first and last by atomicOr,
+// shared with the neighbouring windows), else straight into the stream.
+constexpr uint32_t kRoiOutWords = 512;
 __global__ __launch_bounds__(256) void k_roi_pack(BatchPlan bp) {
+  __shared__ uint32_t s_v[kWaves][kRoiStageWords];
+  __shared__ uint32_t s_o[kWaves][kRoiOutWords];
   const int lane = threadIdx.x & 63;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t first = (blockIdx.x * kWaves + wv) * kRoiPeaksPerWave;
-  for (uint32_t kg = first; kg < first + kRoiPeaksPerWave && kg < bp.total_peaks; ++kg) {
-    uint32_t f, k;
-    RoiWin rw;
-    if (!roi_window(bp, kg, f, k, rw)) continue;
-    const FramePlan &fp = bp.frames[f];
-    const FrameState *st = fp.st;
-    const uint64_t off_ores =
-        fp.off_bits + (fp.run_coding ? 0 : 4 * ((st->T + 31) / 32)) + 4ull * st->n_out;
-    uint32_t *words =
-        (uint32_t *)(fp.out + off_ores + 4ull * st->n_out + kRoiLens + 4ull * fp.npeaks);
-    const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
-    uint64_t base = fp.roi_bits[k];
-    for (uint32_t e0 = 0; e0 < ww; e0 += 64) {
-      const uint32_t e = e0 + lane;
-      uint32_t n = 0;
-      uint64_t value = 0;
-      if (e < ww) {
-        const uint32_t u = __umulhi(e, M), v = e - u * w;
-        const uint32_t z = roi_z(rw, u, v), c = roi_class(z);
-        const uint32_t extra = c >= 2 ? c - 1 : 0u;
-        n = fp.roi_lens[c] + extra;
-        value = ((uint64_t)fp.roi_cw[c] << extra) | (extra ? (z & ((1u << extra) - 1u)) : 0u);
+  const uint32_t kg = blockIdx.x * kWaves + wv;
+  if (kg >= bp.total_peaks) return;
+  uint32_t f, k;
+  RoiWin rw;
+  if (!roi_window(bp, kg, f, k, rw)) return;
+  const FramePlan &fp = bp.frames[f];
+  const FrameState *st = fp.st;
+  const uint64_t off_ores =
+      fp.off_bits + (fp.run_coding ? 0 : 4 * ((st->T + 31) / 32)) + 4ull * st->n_out;
+  uint32_t *words =
+      (uint32_t *)(fp.out + off_ores + 4ull * st->n_out + kRoiLens + 4ull * fp.npeaks);
+  const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+  const uint32_t len = lane < kRoiClasses ? fp.roi_lens[lane] : 0u;
+  const uint32_t cwd = lane < kRoiClasses ? fp.roi_cw[lane] : 0u;
+  const uint64_t start = fp.roi_bits[k];
+  const uint64_t end = k + 1 < fp.npeaks ? fp.roi_bits[k + 1] : st->Troi;
+  // the staging buffer's word 0 is stream word start / 32
+  const uint64_t w0 = start >> 5;
+  const bool staged = ((end + 31) >> 5) - w0 <= kRoiOutWords;
+  uint32_t *ob = s_o[wv];
+  if (staged)
+    for (uint32_t i = lane; i < kRoiOutWords; i += 64) ob[i] = 0u;
+  RoiVals rv;
+  roi_stage(rw, w, s_v[wv], rv);
+  uint32_t *dst = staged ? ob : words;
+  uint64_t base = start - (staged ? 32 * w0 : 0);
+  for (uint32_t e0 = 0; e0 < ww; e0 += 64) {
+    const uint32_t e = e0 + lane;
+    uint32_t z = 0, c = 0;
+    if (e < ww) {
+      const uint32_t u = __umulhi(e, M), v = e - u * w;
+      z = rv.z(u, v);
+      c = roi_class(z);
+    }
+    const uint32_t extra = c >= 2 ? c - 1 : 0u;
+    const uint32_t cl = __shfl(len, (int)c), cc = __shfl(cwd, (int)c);
+    const uint32_t n = e < ww ? cl + extra : 0u;
+    const uint64_t value = ((uint64_t)cc << extra) | (extra ? (z & ((1u << extra) - 1u)) : 0u);
+    uint64_t tot;
+    const uint64_t ex = wave_exclusive_scan(n, tot);
+    if (n) or_bits(dst, base + ex, value, n);
+    base += tot;
+  }
+  if (staged) {
+    wave_sync();
+    const uint32_t nw = (uint32_t)(((end + 31) >> 5) - w0);
+    for (uint32_t i = lane; i < nw; i += 64) {
+      const uint32_t v = ob[i];
+      if (i == 0 || i + 1 == nw) {
+        if (v) atomicOr(&words[w0 + i], v);
+      } else {
+        words[w0 + i] = v;
       }
-      uint64_t tot;
-      const uint64_t ex = wave_exclusive_scan(n, tot);
-      if (n) or_bits(words, base + ex, value, n);
-      base += tot;
     }
   }
 }
@@ -2138,8 +2228,7 @@ hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
     if (bp.enc_block) RSZ_LAUNCH("k_encode", k_encode_block, bp.total_units, s, bp);
     else RSZ_LAUNCH("k_encode", k_encode, bp.total_units, s, bp);
   }
-  const uint32_t per_wg = kWaves * kRoiPeaksPerWave;
-  const uint32_t roi_grid = (bp.total_peaks + per_wg - 1) / per_wg;
+  const uint32_t roi_grid = (bp.total_peaks + kWaves - 1) / kWaves;   // a wave per window
   if (bp.roi_coding) {
     if (bp.total_peaks) RSZ_LAUNCH("k_roi_classes", k_roi_classes, roi_grid, s, bp);
     RSZ_LAUNCH("k_roi_book", k_roi_book, bp.nframes, s, bp);

@@ -144,3 +144,18 @@ def test_corrupt_coded_sections_match_oracle(torch):
         assert stg == sto, (t, pos)
         if sto == 0:
             np.testing.assert_array_equal(y.view(np.uint32), yo.view(np.uint32))
+
+
+@pytest.mark.parametrize("w", [21, 31, 32, 45, 63])
+def test_window_widths_across_the_staging_limits(torch, w):
+    """Windows up to 31 pixels are staged in LDS, wider ones read the frame;
+    a window's bits go through an LDS buffer of 512 words when they fit.
+    Widths on both sides of both limits, with windows at the panel edges and
+    overlapping, and full-entropy values (about 28 bits each)."""
+    rng = np.random.default_rng(w)
+    f = rng.normal(0.0, 50.0, (2, 100, 120)).astype(np.float32)
+    peaks = np.array([[0, 50, 60], [0, 0, 0], [1, 99, 119], [1, 50, 2], [0, 52, 70], [1, 3, 117]],
+                     np.int32)
+    print(f"window {w}", flush=True)
+    _check(torch, f, peaks, w, 2, 5.0)
+    _check(torch, f, peaks[:2], w, 1, 5.0, dim=3)
