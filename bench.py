@@ -135,11 +135,34 @@ def decompress_section(args, torch, dev, B, sizes, host):
     rsz.rsz_profile_enable(False)
     lat_ms = np.array(lat) * 1e3
     fb = SHAPE[0] * SHAPE[1] * SHAPE[2] * 4
+    del streams, ws, out
+    # every stream of the batch in one batched call (rsz_decompress_batch:
+    # one launch of each decoder kernel for all of them)
+    D = rsz.DecodeBatch([B.stream(i, sizes) for i in range(len(sizes))])
+    for _ in range(2):
+        D.run()
+    torch.cuda.synchronize()
+    assert (D.status.cpu().numpy() == 0).all()
+    rsz.rsz_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.decompress_steps):
+        D.run()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.decompress_steps
+    bprof = rsz.rsz_profile_read()
+    rsz.rsz_profile_enable(False)
+    batched = {"frames": len(sizes), "ms_per_batch": round(el * 1e3, 4),
+               "gbps": round(len(sizes) * fb / el / 1e9, 2),
+               "kernel_ms": {k: round(v[1] / v[0], 4) for k, v in bprof.items()}}
+    print(f"[bench] batched decompression: {batched['gbps']} GB/s", file=sys.stderr, flush=True)
+    del D
+    torch.cuda.empty_cache()
     return {"frames": n, "mode": "one frame per call (synchronous)",
             "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
             "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
             "gbps": round(n * fb / (lat_ms.sum() / 1e3) / 1e9, 2),
-            "kernel_ms_per_frame": {k: round(v[1] / v[0], 4) for k, v in prof.items()}}
+            "kernel_ms_per_frame": {k: round(v[1] / v[0], 4) for k, v in prof.items()},
+            "batched": batched}
 
 
 def lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips, raw_bytes):
@@ -442,6 +465,8 @@ def main():
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--decompress-frames", type=int, default=200,
                     help="frames decompressed one per call for the decompression figures")
+    ap.add_argument("--decompress-steps", type=int, default=10,
+                    help="timed batched decompressions of the whole batch")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[1.0, 2.0, 5.0, 10.0],
                     help="Poisson arrival rates in kHz for the serving section ([] skips it)")
     ap.add_argument("--serve-frames", type=int, default=10000)

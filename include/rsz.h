@@ -205,6 +205,35 @@ int rsz_decompress_workspace_bytes(const void *h_header, uint64_t n, uint64_t *b
 int rsz_decompress(const void *d_in, uint64_t in_bytes, float *d_frame, uint64_t frame_elems,
                    void *d_ws, uint64_t ws_bytes, void *stream);
 
+/* One stream of a batched decompression.
+ *   in/in_bytes: the stream (device).  header: a host copy of its first 80
+ *   bytes (the call plans from it without reading device memory).
+ *   frame/frame_elems: the output frame (device, panels*height*width float32
+ *   at least). */
+typedef struct {
+  const void *in;
+  uint64_t in_bytes;
+  const void *header;
+  float *frame;
+  uint64_t frame_elems;
+} rsz_decode_desc;
+
+/* Device workspace for rsz_decompress_batch of these streams.  Host-only. */
+int rsz_decompress_batch_workspace_bytes(uint32_t n, const rsz_decode_desc *h_descs,
+                                         uint64_t *bytes);
+
+/* Decompress n streams (the decompression of Sec. IV-A, as rsz_decompress)
+ * with one launch of each decoder kernel for all of them: a kernel's
+ * workgroups are numbered across the streams.  d_status[i] (device) receives
+ * stream i's status: RSZ_OK, RSZ_ERR_CORRUPT for a malformed stream (also a
+ * header the host rejects), RSZ_ERR_ARG for a frame buffer that is null,
+ * misaligned or too small.  Asynchronous: queued on `stream`, no host
+ * synchronisation.  Returns RSZ_ERR_ARG for n == 0 or a null pointer,
+ * RSZ_ERR_WORKSPACE for a workspace below
+ * rsz_decompress_batch_workspace_bytes. */
+int rsz_decompress_batch(uint32_t n, const rsz_decode_desc *h_descs, int32_t *d_status,
+                         void *d_ws, uint64_t ws_bytes, void *stream);
+
 /* ---- Peak finding: the step before the path, feeding the peak list ---- */
 
 /* Peak-finder parameters (Sec. V-A: local maxima of a 7x7 window, maxima

@@ -548,6 +548,117 @@ static uint64_t decode_ws_bytes(const DecodePlan &dp) {
 // Results of a single-frame call live in the workspace tail.
 static uint64_t single_extra() { return 256; }
 
+// Decoder workspace: the plans and the per-kernel workgroup prefixes of the n
+// streams, then each valid stream's region (decode_ws_bytes).
+static uint64_t decode_head_bytes(uint32_t n) {
+  return align_up((uint64_t)sizeof(DecodePlan) * n, 256) +
+         align_up(4ull * kDecKernels * (n + 1), 256);
+}
+
+// One stream to decode: its device bytes, a host copy of its header, the
+// output frame and where its status goes (device).
+struct DecodeItem {
+  const void *in;
+  uint64_t in_bytes;
+  const uint8_t *header;
+  float *frame;
+  uint64_t frame_elems;
+  int32_t *status;   // null: the status word of the stream's region
+};
+
+// Plans the streams (a stream the host rejects gets RSZ_ERR_CORRUPT or
+// RSZ_ERR_ARG as its status and no other work), and with a workspace lays
+// out the regions, uploads the plans and launches the decoder.  *need: the
+// workspace bytes.
+static int decode_streams(uint32_t n, const DecodeItem *it, uint8_t *ws, uint64_t ws_bytes,
+                          hipStream_t s, uint64_t *need, int32_t **status_words) {
+  const uint64_t head = decode_head_bytes(n);
+  std::vector<DecodePlan> dps(n);
+  std::vector<uint64_t> region(n, 0);
+  uint64_t total = head;
+  for (uint32_t f = 0; f < n; ++f) {
+    DecodePlan &dp = dps[f];
+    int st = parse_header(it[f].header, kHeader, it[f].in_bytes, nullptr, nullptr, &dp);
+    if (st == RSZ_OK) {
+      if (!it[f].in || (uintptr_t)it[f].in % 16 || !it[f].frame || (uintptr_t)it[f].frame % 16 ||
+          it[f].frame_elems < (uint64_t)dp.P * dp.H * dp.W)
+        st = RSZ_ERR_ARG;
+    }
+    if (st != RSZ_OK) {
+      memset(&dp, 0, sizeof dp);
+      dp.init_status = st;
+      continue;
+    }
+    dp.init_status = RSZ_OK;
+    region[f] = decode_ws_bytes(dp);
+    total += region[f];
+  }
+  if (need) *need = total;
+  if (!ws) return RSZ_OK;
+  if (ws_bytes < total) return RSZ_ERR_WORKSPACE;
+  // regions
+  uint64_t off = head;
+  for (uint32_t f = 0; f < n; ++f) {
+    DecodePlan &dp = dps[f];
+    uint8_t *w = ws + off;
+    off += region[f];
+    if (dp.init_status == RSZ_OK) {
+      dp.in = (const uint8_t *)it[f].in;
+      dp.frame = it[f].frame;
+      dp.res = (int32_t *)w;
+      w += align_up(4ull * dp.nbins, 256);
+      dp.zcount = (uint32_t *)w;
+      w += align_up(4ull * dp.nchunks, 256);
+      dp.status = (int32_t *)w;
+      w += 256;
+      dp.tables = (uint32_t *)w;
+      w += align_up(decode_tables_bytes(), 256);
+      if (dp.dim == 1) {
+        dp.carry = (uint32_t *)w;
+        w += align_up(4ull * dp.P * dp.Hb, 256);
+      }
+      if (dp.roi_coding) {
+        dp.roi_payload = (uint32_t *)w;
+        w += align_up(4ull * dp.npeaks * dp.w * dp.w, 256);
+        dp.roi_tables = (uint32_t *)w;
+        w += align_up(decode_roi_tables_bytes(), 256);
+      }
+      // the Huffman words: in the stream, or expanded from the run section
+      dp.bits = (const uint32_t *)(dp.in + dp.off_bits);
+      if (dp.run_coding) {
+        dp.hbits = (uint32_t *)w;
+        dp.bits = dp.hbits;
+      }
+    }
+    if (it[f].status) dp.status = it[f].status;
+    if (!dp.status) return RSZ_ERR_ARG;   // a rejected stream needs a status word
+    if (status_words) status_words[f] = dp.status;
+  }
+  // plans and prefixes, one upload
+  std::vector<uint8_t> host(head, 0);
+  memcpy(host.data(), dps.data(), sizeof(DecodePlan) * n);
+  uint32_t *pre = (uint32_t *)(host.data() + align_up((uint64_t)sizeof(DecodePlan) * n, 256));
+  uint32_t total_blocks[kDecKernels] = {0};
+  for (uint32_t f = 0; f < n; ++f) {
+    uint32_t nb[kDecKernels];
+    decode_blocks(dps[f], nb);
+    for (int k = 0; k < kDecKernels; ++k) {
+      pre[(size_t)k * (n + 1) + f] = total_blocks[k];
+      if ((uint64_t)total_blocks[k] + nb[k] > 0x7FFFFFFFull) return RSZ_ERR_ARG;
+      total_blocks[k] += nb[k];
+    }
+  }
+  for (int k = 0; k < kDecKernels; ++k) pre[(size_t)k * (n + 1) + n] = total_blocks[k];
+  const int st = stage_to_device(ws, host.data(), head, s);
+  if (st) return st;
+  DecBatch db;
+  db.n = n;
+  db.plans = (const DecodePlan *)ws;
+  db.pre = (const uint32_t *)(ws + align_up((uint64_t)sizeof(DecodePlan) * n, 256));
+  if (launch_decompress(db, total_blocks, s) != hipSuccess) return RSZ_ERR_HIP;
+  return RSZ_OK;
+}
+
 }  // namespace rsz
 
 using namespace rsz;
@@ -702,7 +813,7 @@ int rsz_decompress_workspace_bytes(const void *h_header, uint64_t n, uint64_t *b
   const int st = parse_header((const uint8_t *)h_header, n, ~0ull, nullptr, nullptr, &dp);
   if (st) return st;
   if (!bytes) return RSZ_ERR_ARG;
-  *bytes = decode_ws_bytes(dp);
+  *bytes = decode_head_bytes(1) + decode_ws_bytes(dp);
   return RSZ_OK;
 }
 
@@ -720,40 +831,47 @@ int rsz_decompress(const void *d_in, uint64_t in_bytes, float *d_frame, uint64_t
   int st = parse_header(hdr, 80, in_bytes, nullptr, nullptr, &dp);
   if (st) return st;
   if (frame_elems < (uint64_t)dp.P * dp.H * dp.W) return RSZ_ERR_ARG;
-  if (ws_bytes < decode_ws_bytes(dp)) return RSZ_ERR_WORKSPACE;
-  uint8_t *w = (uint8_t *)d_ws;
-  dp.in = (const uint8_t *)d_in;
-  dp.frame = d_frame;
-  dp.res = (int32_t *)w;
-  w += align_up(4ull * dp.nbins, 256);
-  dp.zcount = (uint32_t *)w;
-  w += align_up(4ull * dp.nchunks, 256);
-  dp.status = (int32_t *)w;
-  w += 256;
-  dp.tables = (uint32_t *)w;
-  w += align_up(decode_tables_bytes(), 256);
-  if (dp.dim == 1) {
-    dp.carry = (uint32_t *)w;
-    w += align_up(4ull * dp.P * dp.Hb, 256);
-  }
-  if (dp.roi_coding) {
-    dp.roi_payload = (uint32_t *)w;
-    w += align_up(4ull * dp.npeaks * dp.w * dp.w, 256);
-    dp.roi_tables = (uint32_t *)w;
-    w += align_up(decode_roi_tables_bytes(), 256);
-  }
-  // the Huffman words: in the stream, or expanded from the run section
-  dp.bits = (const uint32_t *)(dp.in + dp.off_bits);
-  if (dp.run_coding) {
-    dp.hbits = (uint32_t *)w;
-    dp.bits = dp.hbits;
-  }
-  if (launch_decompress(dp, s) != hipSuccess) return RSZ_ERR_HIP;
+  // a batch of one stream
+  DecodeItem it{d_in, in_bytes, hdr, d_frame, frame_elems, nullptr};
+  int32_t *status_word = nullptr;
+  st = decode_streams(1, &it, (uint8_t *)d_ws, ws_bytes, s, nullptr, &status_word);
+  if (st) return st;
   int32_t status = 0;
-  if (hipMemcpyAsync(&status, dp.status, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+  if (hipMemcpyAsync(&status, status_word, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
     return RSZ_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return RSZ_ERR_HIP;
   return status;
+}
+
+static int decode_items(uint32_t n, const rsz_decode_desc *d, int32_t *d_status,
+                        std::vector<DecodeItem> &items) {
+  if (n == 0 || !d) return RSZ_ERR_ARG;
+  items.resize(n);
+  for (uint32_t f = 0; f < n; ++f) {
+    if (!d[f].header) return RSZ_ERR_ARG;
+    items[f] = DecodeItem{d[f].in, d[f].in_bytes, (const uint8_t *)d[f].header, d[f].frame,
+                          d[f].frame_elems, d_status ? d_status + f : nullptr};
+  }
+  return RSZ_OK;
+}
+
+int rsz_decompress_batch_workspace_bytes(uint32_t n, const rsz_decode_desc *h_descs,
+                                         uint64_t *bytes) {
+  std::vector<DecodeItem> items;
+  const int st = decode_items(n, h_descs, nullptr, items);
+  if (st) return st;
+  if (!bytes) return RSZ_ERR_ARG;
+  return decode_streams(n, items.data(), nullptr, 0, nullptr, bytes, nullptr);
+}
+
+int rsz_decompress_batch(uint32_t n, const rsz_decode_desc *h_descs, int32_t *d_status,
+                         void *d_ws, uint64_t ws_bytes, void *stream) {
+  if (!d_status || !d_ws || (uintptr_t)d_ws % 256) return RSZ_ERR_ARG;
+  std::vector<DecodeItem> items;
+  const int st = decode_items(n, h_descs, d_status, items);
+  if (st) return st;
+  return decode_streams(n, items.data(), (uint8_t *)d_ws, ws_bytes, (hipStream_t)stream, nullptr,
+                        nullptr);
 }
 
 int rsz_batch_prepare(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t *d_out_bytes,

@@ -47,7 +47,29 @@ __device__ __forceinline__ uint32_t rd32(const uint8_t *p, uint64_t off) {
   return *(const uint32_t *)(p + off);
 }
 
-__global__ __launch_bounds__(256) void k_dec_tables(DecodePlan dp) {
+// A batch of streams: each kernel's workgroups are numbered across the
+// frames, kernel K's per-frame counts in the prefix pre[K * (n + 1) ...]; a
+// workgroup finds its frame (the last with prefix <= its index) and works on
+// that frame's plan with its index and count inside the frame.
+__device__ __forceinline__ uint32_t dec_frame(const uint32_t *pre, uint32_t n, uint32_t b) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+#define RSZ_DEC_FRAME(K)                                                   \
+  const uint32_t *pre_ = db.pre + (size_t)(K) * (db.n + 1);                \
+  const uint32_t f_ = dec_frame(pre_, db.n, blockIdx.x);                   \
+  const uint32_t bid = blockIdx.x - pre_[f_];                              \
+  const uint32_t nblk = pre_[f_ + 1] - pre_[f_];                           \
+  (void)bid;                                                               \
+  (void)nblk;                                                              \
+  const DecodePlan &dp = db.plans[f_]
+
+__global__ __launch_bounds__(256) void k_dec_tables(DecBatch db) {
+  RSZ_DEC_FRAME(0);
   __shared__ uint8_t s_len[kNumSym];
   __shared__ uint32_t s_count[kMaxLen + 1], s_first[kMaxLen + 1], s_offs[kMaxLen + 1],
       s_fill[kMaxLen + 1];
@@ -55,6 +77,11 @@ __global__ __launch_bounds__(256) void k_dec_tables(DecodePlan dp) {
   __shared__ uint32_t s_lut[1 << kLutBits];
   __shared__ unsigned long long s_kraft;
   __shared__ int s_used, s_bad;
+  // a stream the host already rejected gets its status and no other work
+  if (dp.init_status != RSZ_OK) {
+    if (threadIdx.x == 0) *dp.status = dp.init_status;
+    return;
+  }
   if (threadIdx.x == 0) {
     s_kraft = 0;
     s_used = 0;
@@ -285,9 +312,10 @@ __device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, ui
 
 constexpr uint32_t kRunKMax = 20;
 
-__global__ __launch_bounds__(256) void k_dec_run_zero(DecodePlan dp) {
+__global__ __launch_bounds__(256) void k_dec_run_zero(DecBatch db) {
+  RSZ_DEC_FRAME(1);
   const uint64_t n = (dp.T + 31) / 32 + 2;
-  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull)
+  for (uint64_t i = bid * 256ull + threadIdx.x; i < n; i += nblk * 256ull)
     dp.hbits[i] = 0u;
 }
 
@@ -307,8 +335,9 @@ __device__ __forceinline__ uint32_t peek_bits(const uint32_t *w, uint64_t n, uin
 // and every one bit inside its chunk [chunk_off[c], chunk_off[c + 1]).
 // Reads stay inside the section once its size is checked; the loop ends
 // after at most one step per run bit.
-__global__ __launch_bounds__(256) void k_dec_runs(DecodePlan dp) {
-  const uint32_t c = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_dec_runs(DecBatch db) {
+  RSZ_DEC_FRAME(2);
+  const uint32_t c = bid * 256 + threadIdx.x;
   if (c >= dp.nchunks || !dec_ok(dp.status)) return;
   const uint8_t *kpar = dp.in + dp.off_run;
   const uint32_t *ro = (const uint32_t *)(dp.in + dp.off_runoffs);
@@ -373,7 +402,8 @@ __global__ __launch_bounds__(256) void k_dec_runs(DecodePlan dp) {
 // (64 at most).  A scan of the lanes' symbol counts places their outputs, and
 // a last pass writes them.  A valid chunk decodes to exactly its symbol count
 // and ends exactly at the next chunk offset.
-__global__ __launch_bounds__(256) void k_dec_chunks(DecodePlan dp) {
+__global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
+  RSZ_DEC_FRAME(3);
   __shared__ uint2 s_multi[1 << kLutBits];
   __shared__ uint32_t s_first[kMaxLen + 1], s_count[kMaxLen + 1], s_offs[kMaxLen + 1];
   __shared__ uint16_t s_sorted[kNumSym];
@@ -387,7 +417,7 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecodePlan dp) {
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const uint32_t c = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t c = bid * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c >= dp.nchunks || !dec_ok(dp.status)) return;
   const uint32_t *co = (const uint32_t *)(dp.in + dp.off_chunks);
   const uint32_t *bw = dp.bits;   // the stream's bitstream, or the expanded runs
@@ -441,8 +471,9 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecodePlan dp) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_dec_outliers(DecodePlan dp) {
-  const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_dec_outliers(DecBatch db) {
+  RSZ_DEC_FRAME(4);
+  const uint32_t k = bid * 256 + threadIdx.x;
   if (k >= dp.n_out || !dec_ok(dp.status)) return;
   const uint32_t *oi = (const uint32_t *)(dp.in + dp.off_oidx);
   const int32_t *orr = (const int32_t *)(dp.in + dp.off_ores);
@@ -459,18 +490,27 @@ __global__ __launch_bounds__(256) void k_dec_outliers(DecodePlan dp) {
 }
 
 // One wave per bin row: inclusive prefix sum along the row.
-__global__ __launch_bounds__(256) void k_dec_rows(DecodePlan dp) {
-  const uint32_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(256) void k_dec_rows(DecBatch db) {
+  RSZ_DEC_FRAME(5);
+  const uint32_t row = bid * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= dp.P * dp.Hb || !dec_ok(dp.status)) return;
   int32_t *r = dp.res + (size_t)row * dp.Wb;
   uint32_t carry = 0;
   bool bad = false;
+  // the row's first four blocks of 64 loaded before any store
+  int32_t pre[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const uint32_t j = 64 * t + lane;
+    pre[t] = j < dp.Wb ? r[j] : 0;
+  }
   for (uint32_t j0 = 0; j0 < dp.Wb; j0 += 64) {
     const uint32_t j = j0 + lane;
     uint32_t x = 0;
     if (j < dp.Wb) {
-      const int32_t v = r[j];
+      const int32_t v = j0 == 0 ? pre[0] : j0 == 64 ? pre[1] : j0 == 128 ? pre[2]
+                      : j0 == 192 ? pre[3] : r[j];
       bad |= v == kMark;
       x = (uint32_t)v;
     }
@@ -487,22 +527,38 @@ __global__ __launch_bounds__(256) void k_dec_rows(DecodePlan dp) {
 }
 
 // One lane per bin column: inclusive prefix sum down the column.
-__global__ __launch_bounds__(256) void k_dec_cols(DecodePlan dp) {
-  const uint32_t col = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_dec_cols(DecBatch db) {
+  RSZ_DEC_FRAME(8);
+  const uint32_t col = bid * 256 + threadIdx.x;
   if (col >= dp.P * dp.Wb || !dec_ok(dp.status)) return;
   const uint32_t p = col / dp.Wb, J = col - p * dp.Wb;
   int32_t *r = dp.res + (size_t)p * dp.Hb * dp.Wb + J;
+  const size_t Wb = dp.Wb;
   uint32_t acc = 0;
-  for (uint32_t I = 0; I < dp.Hb; ++I) {
-    acc += (uint32_t)r[(size_t)I * dp.Wb];
-    r[(size_t)I * dp.Wb] = (int32_t)acc;
+  uint32_t I = 0;
+  // eight rows loaded before any is stored (a store would otherwise hold
+  // back the next load: the compiler cannot reorder them)
+  for (; I + 8 <= dp.Hb; I += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = (uint32_t)r[(I + k) * Wb];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      acc += v[k];
+      r[(I + k) * Wb] = (int32_t)acc;
+    }
+  }
+  for (; I < dp.Hb; ++I) {
+    acc += (uint32_t)r[I * Wb];
+    r[I * Wb] = (int32_t)acc;
   }
 }
 
 // Dimension 1: the raster sequence continues across rows, so each row adds
 // the sum of every row before it.  One workgroup scans the row totals (the
 // last element of each row-scanned row) into exclusive carries.
-__global__ __launch_bounds__(256) void k_dec_carry(DecodePlan dp) {
+__global__ __launch_bounds__(256) void k_dec_carry(DecBatch db) {
+  RSZ_DEC_FRAME(6);
   __shared__ uint32_t s_w[4];
   if (!dec_ok(dp.status)) return;
   const uint32_t rows = dp.P * dp.Hb;
@@ -528,18 +584,20 @@ __global__ __launch_bounds__(256) void k_dec_carry(DecodePlan dp) {
 }
 
 // Dimension 1: adds each row's carry (one lane per bin).
-__global__ __launch_bounds__(256) void k_dec_rowadd(DecodePlan dp) {
+__global__ __launch_bounds__(256) void k_dec_rowadd(DecBatch db) {
+  RSZ_DEC_FRAME(7);
   if (!dec_ok(dp.status)) return;
-  const uint64_t stride = (uint64_t)gridDim.x * 256;
-  for (uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x; g < dp.nbins; g += stride)
+  const uint64_t stride = (uint64_t)nblk * 256;
+  for (uint64_t g = (uint64_t)bid * 256 + threadIdx.x; g < dp.nbins; g += stride)
     dp.res[g] = (int32_t)((uint32_t)dp.res[g] + dp.carry[g / dp.Wb]);
 }
 
 // Dimension 3: inclusive prefix sum across the panels (one lane per bin
 // position of the panel plane), after the 2D sums of each panel.
-__global__ __launch_bounds__(256) void k_dec_panels(DecodePlan dp) {
+__global__ __launch_bounds__(256) void k_dec_panels(DecBatch db) {
+  RSZ_DEC_FRAME(9);
   const uint32_t plane = dp.Hb * dp.Wb;
-  const uint32_t c = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t c = bid * 256 + threadIdx.x;
   if (c >= plane || !dec_ok(dp.status)) return;
   int32_t *r = dp.res + c;
   uint32_t acc = 0;
@@ -549,15 +607,43 @@ __global__ __launch_bounds__(256) void k_dec_panels(DecodePlan dp) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_dec_expand(DecodePlan dp) {
-  if (!dec_ok(dp.status)) return;
-  const uint64_t npix = (uint64_t)dp.P * dp.H * dp.W;
-  const uint64_t stride = (uint64_t)gridDim.x * 256;
-  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < npix; e += stride) {
-    const uint64_t j = e % dp.W, t = e / dp.W;
-    const uint64_t i = t % dp.H, p = t / dp.H;
-    const uint64_t g = (p * dp.Hb + i / dp.b) * dp.Wb + j / dp.b;
-    dp.frame[e] = (float)((double)dp.res[g] * dp.step);
+// One wave per bin row: each lane takes a bin, computes its value once and
+// writes it to the bin's b x b pixels (clipped at the panel edges), a raw
+// row at a time, so the wave's stores of a row are contiguous.
+__global__ __launch_bounds__(256) void k_dec_expand(DecBatch db) {
+  RSZ_DEC_FRAME(10);
+  const uint32_t brow = bid * 4 + (threadIdx.x >> 6);
+  if (brow >= dp.P * dp.Hb || !dec_ok(dp.status)) return;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t p = brow / dp.Hb, I = brow - p * dp.Hb;
+  const uint32_t b = dp.b, W = dp.W;
+  const uint32_t i0 = I * b, i1 = min(i0 + b, dp.H);
+  const int32_t *rb = dp.res + (size_t)brow * dp.Wb;
+  float *out = dp.frame + ((size_t)p * dp.H + i0) * W;
+  const double step = dp.step;
+  // b = 2 or 4 with W a multiple of b: a bin's pixels of a row are one
+  // aligned float2 / float4 (the frame is 16-byte aligned)
+  if (b == 2 && W % 2 == 0) {
+    for (uint32_t J = lane; J < dp.Wb; J += 64) {
+      const float v = (float)((double)rb[J] * step);
+      for (uint32_t i = i0; i < i1; ++i)
+        *(float2 *)(out + (size_t)(i - i0) * W + 2 * J) = make_float2(v, v);
+    }
+  } else if (b == 4 && W % 4 == 0) {
+    for (uint32_t J = lane; J < dp.Wb; J += 64) {
+      const float v = (float)((double)rb[J] * step);
+      for (uint32_t i = i0; i < i1; ++i)
+        *(float4 *)(out + (size_t)(i - i0) * W + 4 * J) = make_float4(v, v, v, v);
+    }
+  } else {
+    for (uint32_t J = lane; J < dp.Wb; J += 64) {
+      const float v = (float)((double)rb[J] * step);
+      const uint32_t j0 = J * b, j1 = min(j0 + b, W);
+      for (uint32_t i = i0; i < i1; ++i) {
+        float *o = out + (size_t)(i - i0) * W;
+        for (uint32_t j = j0; j < j1; ++j) o[j] = v;
+      }
+    }
   }
 }
 
@@ -570,7 +656,8 @@ __global__ __launch_bounds__(256) void k_dec_expand(DecodePlan dp) {
 constexpr int kRoiTabFirst = 0, kRoiTabCount = 33, kRoiTabBase = 66, kRoiTabSym = 99;
 constexpr int kRoiTabWords = 132;
 
-__global__ __launch_bounds__(64) void k_dec_roi_tables(DecodePlan dp) {
+__global__ __launch_bounds__(64) void k_dec_roi_tables(DecBatch db) {
+  RSZ_DEC_FRAME(11);
   if (threadIdx.x != 0 || !dec_ok(dp.status)) return;
   const uint8_t *lens = dp.in + dp.off_rsec;
   uint32_t *t = dp.roi_tables;
@@ -616,8 +703,9 @@ __device__ __forceinline__ uint32_t roi_peek(const uint32_t *words, uint64_t nwo
 // residuals, written as r (mod 2^32) to roi_payload.  A window must start at
 // its offset (the first at 0) and end exactly at the next offset, the last
 // at Troi.
-__global__ __launch_bounds__(256) void k_dec_roi_decode(DecodePlan dp) {
-  const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_dec_roi_decode(DecBatch db) {
+  RSZ_DEC_FRAME(12);
+  const uint32_t k = bid * 256 + threadIdx.x;
   if (k >= dp.npeaks || !dec_ok(dp.status)) return;
   const uint32_t *t = dp.roi_tables;
   const uint32_t *offs = (const uint32_t *)(dp.in + dp.off_roffs);
@@ -667,8 +755,9 @@ __global__ __launch_bounds__(256) void k_dec_roi_decode(DecodePlan dp) {
 // 2D prefix sum of r: a wave scan along each row plus the column sums kept
 // per lane.  Then M = D + 2^31 maps back to the float bits.
 constexpr int kRoiMaxChunks = 16;   // w <= 1023: 16 chunks of 64 columns
-__global__ __launch_bounds__(256) void k_dec_roi_unpred(DecodePlan dp) {
-  const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(256) void k_dec_roi_unpred(DecBatch db) {
+  RSZ_DEC_FRAME(13);
+  const uint32_t k = bid * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (k >= dp.npeaks || !dec_ok(dp.status)) return;
   const uint32_t w = dp.w;
@@ -700,16 +789,17 @@ __global__ __launch_bounds__(256) void k_dec_roi_unpred(DecodePlan dp) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_dec_roi(DecodePlan dp) {
+__global__ __launch_bounds__(256) void k_dec_roi(DecBatch db) {
+  RSZ_DEC_FRAME(14);
   if (!dec_ok(dp.status)) return;
   const uint64_t ww = (uint64_t)dp.w * dp.w;
   const uint64_t n = (uint64_t)dp.npeaks * ww;
-  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  const uint64_t stride = (uint64_t)nblk * 256;
   const uint16_t *pk = (const uint16_t *)(dp.in + dp.off_peaks);
   const uint32_t *pay =
       dp.roi_coding ? dp.roi_payload : (const uint32_t *)(dp.in + dp.off_roi);
   const int64_t h = dp.w / 2;
-  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) {
+  for (uint64_t e = (uint64_t)bid * 256 + threadIdx.x; e < n; e += stride) {
     const uint64_t k = e / ww, rem = e - k * ww;
     const int64_t u = rem / dp.w, v = rem - u * dp.w;
     const int64_t pa = pk[3 * k], i = (int64_t)pk[3 * k + 1] - h + u,
@@ -721,17 +811,18 @@ __global__ __launch_bounds__(256) void k_dec_roi(DecodePlan dp) {
 
 // Overlapping windows copy the same frame pixel: every payload entry must
 // match what was restored at its pixel, else the stream is malformed.
-__global__ __launch_bounds__(256) void k_dec_roi_check(DecodePlan dp) {
+__global__ __launch_bounds__(256) void k_dec_roi_check(DecBatch db) {
+  RSZ_DEC_FRAME(15);
   if (!dec_ok(dp.status)) return;
   const uint64_t ww = (uint64_t)dp.w * dp.w;
   const uint64_t n = (uint64_t)dp.npeaks * ww;
-  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  const uint64_t stride = (uint64_t)nblk * 256;
   const uint16_t *pk = (const uint16_t *)(dp.in + dp.off_peaks);
   const uint32_t *pay =
       dp.roi_coding ? dp.roi_payload : (const uint32_t *)(dp.in + dp.off_roi);
   const int64_t h = dp.w / 2;
   bool bad = false;
-  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += stride) {
+  for (uint64_t e = (uint64_t)bid * 256 + threadIdx.x; e < n; e += stride) {
     const uint64_t k = e / ww, rem = e - k * ww;
     const int64_t u = rem / dp.w, v = rem - u * dp.w;
     const int64_t pa = pk[3 * k], i = (int64_t)pk[3 * k + 1] - h + u,
@@ -742,52 +833,63 @@ __global__ __launch_bounds__(256) void k_dec_roi_check(DecodePlan dp) {
   if (bad) corrupt(dp.status);
 }
 
-#define RSZ_DLAUNCH(name, kern, grid, block, s)                      \
-  do {                                                               \
-    prof_begin(name, s);                                             \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, dp);     \
-    prof_end(s);                                                     \
-    hipError_t e_ = hipGetLastError();                               \
-    if (e_ != hipSuccess) return e_;                                 \
+void decode_blocks(const DecodePlan &dp, uint32_t *nb) {
+  for (int k = 0; k < kDecKernels; ++k) nb[k] = 0;
+  nb[0] = 1;   // k_dec_tables writes every frame's status
+  if (dp.init_status != RSZ_OK) return;
+  const uint64_t nroi = (uint64_t)dp.npeaks * dp.w * dp.w;
+  if (dp.run_coding) {
+    nb[1] = (uint32_t)std::min<uint64_t>(((dp.T + 31) / 32 + 2 + 255) / 256, 1u << 16);
+    nb[2] = (dp.nchunks + 255) / 256;
+  }
+  nb[3] = (dp.nchunks + 3) / 4;
+  nb[4] = (dp.n_out + 255) / 256;
+  // inverse Lorenzo: prefix sums along each axis the predictor spans
+  nb[5] = (dp.P * dp.Hb + 3) / 4;
+  if (dp.dim == 1) {
+    nb[6] = 1;
+    nb[7] = std::min<uint32_t>((dp.nbins + 255) / 256, 1u << 16);
+  } else {
+    nb[8] = (dp.P * dp.Wb + 255) / 256;
+    if (dp.dim == 3) nb[9] = (dp.Hb * dp.Wb + 255) / 256;
+  }
+  nb[10] = (dp.P * dp.Hb + 3) / 4;
+  if (dp.roi_coding) {
+    nb[11] = 1;
+    nb[12] = (dp.npeaks + 255) / 256;
+    nb[13] = (dp.npeaks + 3) / 4;
+  }
+  nb[14] = nb[15] = (uint32_t)std::min<uint64_t>((nroi + 255) / 256, 1u << 20);
+}
+
+#define RSZ_DLAUNCH(k, name, kern, block)                              \
+  do {                                                                 \
+    if (total[k]) {                                                    \
+      prof_begin(name, s);                                             \
+      hipLaunchKernelGGL(kern, dim3(total[k]), dim3(block), 0, s, db); \
+      prof_end(s);                                                     \
+      hipError_t e_ = hipGetLastError();                               \
+      if (e_ != hipSuccess) return e_;                                 \
+    }                                                                  \
   } while (0)
 
-hipError_t launch_decompress(const DecodePlan &dp, hipStream_t s) {
-  RSZ_DLAUNCH("k_dec_tables", k_dec_tables, 1, 256, s);
-  if (dp.run_coding) {
-    const uint64_t nw = (dp.T + 31) / 32 + 2;
-    RSZ_DLAUNCH("k_dec_run_zero", k_dec_run_zero,
-                (uint32_t)std::min<uint64_t>((nw + 255) / 256, 1u << 16), 256, s);
-    RSZ_DLAUNCH("k_dec_runs", k_dec_runs, (dp.nchunks + 255) / 256, 256, s);
-  }
-  RSZ_DLAUNCH("k_dec_chunks", k_dec_chunks, (dp.nchunks + 3) / 4, 256, s);
-  if (dp.n_out) RSZ_DLAUNCH("k_dec_outliers", k_dec_outliers, (dp.n_out + 255) / 256, 256, s);
-  // inverse Lorenzo: prefix sums along each axis the predictor spans
-  RSZ_DLAUNCH("k_dec_rows", k_dec_rows, (dp.P * dp.Hb + 3) / 4, 256, s);
-  if (dp.dim == 1) {
-    RSZ_DLAUNCH("k_dec_carry", k_dec_carry, 1, 256, s);
-    RSZ_DLAUNCH("k_dec_rowadd", k_dec_rowadd, std::min<uint32_t>((dp.nbins + 255) / 256, 1u << 16),
-                256, s);
-  } else {
-    RSZ_DLAUNCH("k_dec_cols", k_dec_cols, (dp.P * dp.Wb + 255) / 256, 256, s);
-    if (dp.dim == 3)
-      RSZ_DLAUNCH("k_dec_panels", k_dec_panels, (dp.Hb * dp.Wb + 255) / 256, 256, s);
-  }
-  const uint64_t npix = (uint64_t)dp.P * dp.H * dp.W;
-  RSZ_DLAUNCH("k_dec_expand", k_dec_expand, (uint32_t)std::min<uint64_t>((npix + 255) / 256, 1u << 20),
-              256, s);
-  const uint64_t nroi = (uint64_t)dp.npeaks * dp.w * dp.w;
-  if (dp.roi_coding) {
-    RSZ_DLAUNCH("k_dec_roi_tables", k_dec_roi_tables, 1, 64, s);
-    if (dp.npeaks) {
-      RSZ_DLAUNCH("k_dec_roi_decode", k_dec_roi_decode, (dp.npeaks + 255) / 256, 256, s);
-      RSZ_DLAUNCH("k_dec_roi_unpred", k_dec_roi_unpred, (dp.npeaks + 3) / 4, 256, s);
-    }
-  }
-  if (nroi) {
-    const uint32_t g = (uint32_t)std::min<uint64_t>((nroi + 255) / 256, 1u << 20);
-    RSZ_DLAUNCH("k_dec_roi", k_dec_roi, g, 256, s);
-    RSZ_DLAUNCH("k_dec_roi_check", k_dec_roi_check, g, 256, s);
-  }
+hipError_t launch_decompress(const DecBatch &db, const uint32_t *total, hipStream_t s) {
+  RSZ_DLAUNCH(0, "k_dec_tables", k_dec_tables, 256);
+  RSZ_DLAUNCH(1, "k_dec_run_zero", k_dec_run_zero, 256);
+  RSZ_DLAUNCH(2, "k_dec_runs", k_dec_runs, 256);
+  RSZ_DLAUNCH(3, "k_dec_chunks", k_dec_chunks, 256);
+  RSZ_DLAUNCH(4, "k_dec_outliers", k_dec_outliers, 256);
+  RSZ_DLAUNCH(5, "k_dec_rows", k_dec_rows, 256);
+  RSZ_DLAUNCH(6, "k_dec_carry", k_dec_carry, 256);
+  RSZ_DLAUNCH(7, "k_dec_rowadd", k_dec_rowadd, 256);
+  RSZ_DLAUNCH(8, "k_dec_cols", k_dec_cols, 256);
+  RSZ_DLAUNCH(9, "k_dec_panels", k_dec_panels, 256);
+  RSZ_DLAUNCH(10, "k_dec_expand", k_dec_expand, 256);
+  RSZ_DLAUNCH(11, "k_dec_roi_tables", k_dec_roi_tables, 64);
+  RSZ_DLAUNCH(12, "k_dec_roi_decode", k_dec_roi_decode, 256);
+  RSZ_DLAUNCH(13, "k_dec_roi_unpred", k_dec_roi_unpred, 256);
+  RSZ_DLAUNCH(14, "k_dec_roi", k_dec_roi, 256);
+  RSZ_DLAUNCH(15, "k_dec_roi_check", k_dec_roi_check, 256);
   return hipSuccess;
 }
 

@@ -156,8 +156,22 @@ struct DecodePlan {
   uint32_t *carry;      // dim 1: P*Hb row carries
   int32_t *status;      // one word
   uint32_t *tables;     // decode tables
+  int32_t init_status;  // RSZ_OK, or the host's verdict on the stream (no other work)
 };
-hipError_t launch_decompress(const DecodePlan &dp, hipStream_t s);
+
+// Streams decoded together: every decoder kernel is launched once for all of
+// them, its workgroups numbered across the frames.  pre holds kDecKernels
+// prefix arrays of n + 1 entries, kernel K's per-frame workgroup counts.
+constexpr int kDecKernels = 16;
+struct DecBatch {
+  uint32_t n;
+  const DecodePlan *plans;
+  const uint32_t *pre;
+};
+// Workgroups of each decoder kernel for one frame (0: not launched for it).
+void decode_blocks(const DecodePlan &dp, uint32_t *nb);
+// Launches the kernels with total[K] workgroups (the prefixes' last entries).
+hipError_t launch_decompress(const DecBatch &db, const uint32_t *total, hipStream_t s);
 
 // Peak finding (peaks.hip).
 constexpr uint32_t kPeakTile = 16384;     // pixels per k_peaks_find workgroup

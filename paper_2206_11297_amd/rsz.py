@@ -20,6 +20,7 @@ EXPORTS = ["rsz_status_string", "rsz_max_compressed_bytes", "rsz_workspace_bytes
            "rsz_batch_prepare", "rsz_batch_launch", "rsz_batch_graph_create",
            "rsz_graph_launch", "rsz_graph_destroy",
            "rsz_stream_info", "rsz_decompress_workspace_bytes", "rsz_decompress",
+           "rsz_decompress_batch_workspace_bytes", "rsz_decompress_batch",
            "rsz_debug_intermediates", "rsz_debug_codebook", "rsz_measure_read",
            "rsz_profile_enable", "rsz_profile_read", "rsz_peak_params_default",
            "rsz_find_peaks_workspace_bytes", "rsz_find_peaks_batch"]
@@ -36,6 +37,11 @@ class rsz_params(C.Structure):
                 ("window", C.c_uint32), ("bin", C.c_uint32), ("bin_mode", C.c_uint32),
                 ("eb", C.c_double), ("dim", C.c_uint32), ("roi_coding", C.c_uint32),
                 ("run_coding", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class rsz_decode_desc(C.Structure):
+    _fields_ = [("in", C.c_void_p), ("in_bytes", C.c_uint64), ("header", C.c_void_p),
+                ("frame", C.c_void_p), ("frame_elems", C.c_uint64)]
 
 
 class rsz_frame_desc(C.Structure):
@@ -98,6 +104,8 @@ def lib():
         L.rsz_stream_info.argtypes = [vp, u64, P(rsz_params), P(u32), P(u64)]
         L.rsz_decompress_workspace_bytes.argtypes = [vp, u64, P(u64)]
         L.rsz_decompress.argtypes = [vp, u64, vp, u64, vp, u64, vp]
+        L.rsz_decompress_batch_workspace_bytes.argtypes = [u32, P(rsz_decode_desc), P(u64)]
+        L.rsz_decompress_batch.argtypes = [u32, P(rsz_decode_desc), vp, vp, u64, vp]
         L.rsz_debug_intermediates.argtypes = [P(rsz_params), vp, vp, u32, P(rsz_debug_bufs), vp,
                                               u64, vp]
         L.rsz_debug_codebook.argtypes = [vp, vp, vp, vp, u64, vp]
@@ -202,6 +210,23 @@ def rsz_decompress_workspace_bytes(h_header):
 
 def rsz_decompress(d_in, in_bytes, d_frame, frame_elems, d_ws, ws_bytes, stream):
     return lib().rsz_decompress(d_in, in_bytes, d_frame, frame_elems, d_ws, ws_bytes, stream)
+
+
+def _decode_descs(descs):
+    arr = (rsz_decode_desc * len(descs))(*descs)
+    return arr
+
+
+def rsz_decompress_batch_workspace_bytes(descs):
+    out = C.c_uint64(0)
+    st = lib().rsz_decompress_batch_workspace_bytes(len(descs), _decode_descs(descs),
+                                                    C.byref(out))
+    return st, out.value
+
+
+def rsz_decompress_batch(descs, d_status, d_ws, ws_bytes, stream):
+    return lib().rsz_decompress_batch(len(descs), _decode_descs(descs), d_status, d_ws, ws_bytes,
+                                      stream)
 
 
 def rsz_debug_intermediates(p, d_frame, d_peaks, npeaks, bufs, d_ws, ws_bytes, stream):
@@ -336,6 +361,44 @@ def decompress(stream, ws=None):
     if st:
         raise RszError(st, "rsz_decompress")
     return frame
+
+
+class DecodeBatch:
+    """Many streams decompressed with one launch of each decoder kernel.
+
+    streams: uint8 GPU tensors.  The headers are gathered to the host in one
+    transfer; frames (float32 [P,H,W] GPU tensors), the status tensor and the
+    workspace are allocated here.  run() queues the decompression
+    (asynchronous); status[i] is stream i's status."""
+
+    def __init__(self, streams):
+        torch = _torch()
+        self.streams = [s if s.data_ptr() % 16 == 0 else s.clone() for s in
+                        (x.contiguous() for x in streams)]
+        dev = self.streams[0].device
+        n = len(self.streams)
+        heads = torch.stack([torch.nn.functional.pad(s[:80], (0, max(0, 80 - s.numel())))
+                             for s in self.streams]).cpu().numpy()
+        self.headers = [C.create_string_buffer(heads[i].tobytes(), 80) for i in range(n)]
+        self.frames = []
+        for i, s in enumerate(self.streams):
+            st, p, _, _ = rsz_stream_info(heads[i].tobytes())
+            shape = (p.panels, p.height, p.width) if st == 0 else (1, 1, 1)
+            self.frames.append(torch.empty(shape, dtype=torch.float32, device=dev))
+        self.descs = [rsz_decode_desc(s.data_ptr(), s.numel(), C.addressof(h), f.data_ptr(),
+                                      f.numel())
+                      for s, h, f in zip(self.streams, self.headers, self.frames)]
+        st, wsb = rsz_decompress_batch_workspace_bytes(self.descs)
+        if st:
+            raise RszError(st, "rsz_decompress_batch_workspace_bytes")
+        self.ws = workspace(wsb, dev)
+        self.status = torch.zeros(n, dtype=torch.int32, device=dev)
+
+    def run(self):
+        st = rsz_decompress_batch(self.descs, _ptr(self.status), _ptr(self.ws), self.ws.numel(),
+                                  _stream())
+        if st:
+            raise RszError(st, "rsz_decompress_batch")
 
 
 def debug_intermediates(frame, peaks, window=17, bin=2, eb=10.0, bin_mode=RSZ_BIN_BACKGROUND,

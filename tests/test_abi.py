@@ -107,7 +107,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     structs = {"rsz_peak": None, "rsz_params": rsz.rsz_params, "rsz_frame_desc": rsz.rsz_frame_desc,
                "rsz_batch_plan": rsz.rsz_batch_plan, "rsz_debug_bufs": rsz.rsz_debug_bufs,
                "rsz_kernel_time": rsz.rsz_kernel_time, "rsz_peak_params": rsz.rsz_peak_params,
-               "rsz_peak_desc": rsz.rsz_peak_desc}
+               "rsz_peak_desc": rsz.rsz_peak_desc, "rsz_decode_desc": rsz.rsz_decode_desc}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rsz.h"', 'int main(void) {']
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
@@ -150,3 +150,29 @@ def test_peak_params_default_and_checks():
         assert O.check_peak_params(O.peak_params(**{k: v for k, v in bad.items()
                                                      if k != "reserved"})) == O.ERR_ARG \
             or "reserved" in bad
+
+
+def test_batch_decode_workspace_on_the_host():
+    """rsz_decompress_batch_workspace_bytes plans from host headers only: one
+    stream needs what rsz_decompress needs, a rejected header adds no region,
+    and each further stream adds its own region."""
+    f, pk = synth.cspad_frame(2)
+    st, s, n = O.compress(O.params(32, 185, 388, 17, 2, 10.0, 0, 2, 1, 1), f, pk)
+    head = C.create_string_buffer(s.tobytes()[:80], 80)
+    bad = C.create_string_buffer(b"XXXX" + s.tobytes()[4:80], 80)
+    fake = 1 << 20   # device addresses are not read by the host planner
+
+    def desc(h):
+        return rsz.rsz_decode_desc(fake, n, C.addressof(h), fake, 32 * 185 * 388)
+
+    st1, one = rsz.rsz_decompress_batch_workspace_bytes([desc(head)])
+    st0, single = rsz.rsz_decompress_workspace_bytes(s.tobytes()[:80])
+    assert st1 == st0 == 0 and one == single
+    st, with_bad = rsz.rsz_decompress_batch_workspace_bytes([desc(head), desc(bad)])
+    assert st == 0 and 0 <= with_bad - one <= 2048
+    st, two = rsz.rsz_decompress_batch_workspace_bytes([desc(head), desc(head)])
+    assert st == 0 and two >= 2 * one - 4096
+    assert rsz.rsz_decompress_batch_workspace_bytes([])[0] == rsz.RSZ_ERR_ARG
+    d = desc(head)
+    d.header = None
+    assert rsz.rsz_decompress_batch_workspace_bytes([d])[0] == rsz.RSZ_ERR_ARG
