@@ -490,38 +490,74 @@ __global__ __launch_bounds__(256) void k_dec_outliers(DecBatch db) {
 }
 
 // One wave per bin row: inclusive prefix sum along the row.
+constexpr uint32_t kDecRowsPerWave = 4;   // bin rows per wave of k_dec_rows
 __global__ __launch_bounds__(256) void k_dec_rows(DecBatch db) {
   RSZ_DEC_FRAME(5);
-  const uint32_t row = bid * 4 + (threadIdx.x >> 6);
+  const uint32_t row0 = (bid * 4 + (threadIdx.x >> 6)) * kDecRowsPerWave;
   const int lane = threadIdx.x & 63;
-  if (row >= dp.P * dp.Hb || !dec_ok(dp.status)) return;
-  int32_t *r = dp.res + (size_t)row * dp.Wb;
-  uint32_t carry = 0;
-  bool bad = false;
-  // the row's first four blocks of 64 loaded before any store
-  int32_t pre[4];
+  const uint32_t nrows = dp.P * dp.Hb;
+  if (row0 >= nrows || !dec_ok(dp.status)) return;
+  const uint32_t Wb = dp.Wb;
+  if (Wb <= 256) {
+    // four consecutive bins per lane, the wave's rows all loaded first; per
+    // row the lanes' prefixes and one wave scan of their totals
+    int32_t v[kDecRowsPerWave][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const uint32_t j = 64 * t + lane;
-    pre[t] = j < dp.Wb ? r[j] : 0;
+    for (uint32_t rr = 0; rr < kDecRowsPerWave; ++rr)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t j = 4 * lane + t;
+        v[rr][t] = row0 + rr < nrows && j < Wb ? dp.res[(size_t)(row0 + rr) * Wb + j] : 0;
+      }
+    bool bad = false;
+#pragma unroll
+    for (uint32_t rr = 0; rr < kDecRowsPerWave; ++rr) {
+      if (row0 + rr >= nrows) break;
+      uint32_t x[4], sum = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        bad |= v[rr][t] == kMark;
+        sum += (uint32_t)v[rr][t];
+        x[t] = sum;
+      }
+      uint32_t incl = sum;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+      }
+      const uint32_t before = incl - sum;
+      int32_t *r = dp.res + (size_t)(row0 + rr) * Wb;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t j = 4 * lane + t;
+        if (j < Wb) r[j] = (int32_t)(x[t] + before);
+      }
+    }
+    if (bad) corrupt(dp.status);
+    return;
   }
-  for (uint32_t j0 = 0; j0 < dp.Wb; j0 += 64) {
-    const uint32_t j = j0 + lane;
-    uint32_t x = 0;
-    if (j < dp.Wb) {
-      const int32_t v = j0 == 0 ? pre[0] : j0 == 64 ? pre[1] : j0 == 128 ? pre[2]
-                      : j0 == 192 ? pre[3] : r[j];
-      bad |= v == kMark;
-      x = (uint32_t)v;
-    }
+  bool bad = false;
+  for (uint32_t row = row0; row < min(row0 + kDecRowsPerWave, nrows); ++row) {
+    int32_t *r = dp.res + (size_t)row * Wb;
+    uint32_t carry = 0;
+    for (uint32_t j0 = 0; j0 < Wb; j0 += 64) {
+      const uint32_t j = j0 + lane;
+      uint32_t x = 0;
+      if (j < Wb) {
+        const int32_t v = r[j];
+        bad |= v == kMark;
+        x = (uint32_t)v;
+      }
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t y = __shfl_up(x, d);
-      if (lane >= d) x += y;
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+      }
+      x += carry;
+      if (j < Wb) r[j] = (int32_t)x;
+      carry = __shfl(x, 63);
     }
-    x += carry;
-    if (j < dp.Wb) r[j] = (int32_t)x;
-    carry = __shfl(x, 63);
   }
   if (bad) corrupt(dp.status);
 }
@@ -845,7 +881,7 @@ void decode_blocks(const DecodePlan &dp, uint32_t *nb) {
   nb[3] = (dp.nchunks + 3) / 4;
   nb[4] = (dp.n_out + 255) / 256;
   // inverse Lorenzo: prefix sums along each axis the predictor spans
-  nb[5] = (dp.P * dp.Hb + 3) / 4;
+  nb[5] = (dp.P * dp.Hb + 4 * kDecRowsPerWave - 1) / (4 * kDecRowsPerWave);
   if (dp.dim == 1) {
     nb[6] = 1;
     nb[7] = std::min<uint32_t>((dp.nbins + 255) / 256, 1u << 16);
