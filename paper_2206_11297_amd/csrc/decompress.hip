@@ -262,16 +262,28 @@ struct BitWindow {
 // Decodes codewords from `pos` while pos < lim: returns the count and leaves
 // pos at the first boundary >= lim; with `out`, writes each residual (kMark
 // for code 0) at out[k] for k < cap.  `inval` reports a bit pattern that is
-// no codeword.
+// no codeword.  With `zrun` (residual 0's codeword is the single bit 0), a
+// run of z zero bits is z residual-0 symbols, taken at once up to lim.
 template <bool WRITE>
 __device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, uint64_t lim,
                                                const uint2 *s_multi, const uint32_t *s_first,
                                                const uint32_t *s_count, const uint32_t *s_offs,
                                                const uint16_t *s_sorted, int32_t *out,
-                                               uint32_t cap, uint32_t &zeros, bool &inval) {
+                                               uint32_t cap, uint32_t &zeros, bool &inval,
+                                               bool zrun) {
   uint32_t m = 0;
   while (pos < lim) {
     const uint32_t v = win.peek(pos);
+    if (zrun && !(v >> 31)) {
+      const uint32_t z = v ? (uint32_t)__builtin_clz(v) : 32u;
+      const uint32_t take = (uint32_t)min<uint64_t>(z, lim - pos);
+      if (WRITE)
+        for (uint32_t j = 0; j < take; ++j)
+          if (m + j < cap) out[m + j] = 0;
+      pos += take;
+      m += take;
+      continue;
+    }
     const uint2 e = s_multi[v >> (32 - kLutBits)];
     const uint32_t n = e.x >> 30;
     if (n) {
@@ -416,6 +428,9 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
     s_offs[threadIdx.x] = dp.tables[kTabOffs + threadIdx.x];
   }
   __syncthreads();
+  // residual 0 (symbol 512) coded as the single bit 0: the only length-1
+  // code, canonical code 0
+  const bool zrun = s_count[1] == 1 && s_first[1] == 0 && s_sorted[s_offs[1]] == kRadius;
   const int lane = threadIdx.x & 63;
   const uint32_t c = bid * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c >= dp.nchunks || !dec_ok(dp.status)) return;
@@ -438,7 +453,7 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
     uint32_t z = 0;
     inv = false;
     m = decode_run<false>(win, pos, lim, s_multi, s_first, s_count, s_offs, s_sorted, nullptr, 0,
-                          z, inv);
+                          z, inv, zrun);
     stop = inv ? ~0ull : pos;   // a lane stuck on a non-codeword hands on no boundary
     // the boundary the lane before stopped at is this lane's next start
     const uint64_t prev = __shfl_up(stop, 1);
@@ -461,7 +476,7 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
   uint32_t zeros = 0;
   if (!bad)
     decode_run<true>(win, pos, lim, s_multi, s_first, s_count, s_offs, s_sorted, dp.res + g0 + off,
-                     off < nsym ? nsym - off : 0u, zeros, inv);
+                     off < nsym ? nsym - off : 0u, zeros, inv, zrun);
   bad |= __builtin_amdgcn_uicmp((uint32_t)inv, 0u, 33 /* ne */) != 0;
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) zeros += __shfl_xor(zeros, d);
