@@ -545,6 +545,10 @@ def main():
     st = B.status.cpu().numpy()
     assert (st == 0).all(), f"compression failed: statuses {set(st.tolist())}"
 
+    # the timed region records HIP events around the binning kernel only (the
+    # roofline's launch time); every kernel's time comes from a profiled pass
+    # after it
+    rsz.rsz_profile_only("k_bin")
     rsz.rsz_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -554,13 +558,21 @@ def main():
     elapsed = time.perf_counter() - t0
     prof = rsz.rsz_profile_read()
     rsz.rsz_profile_enable(False)
+    rsz.rsz_profile_only(None)
     ms_step = elapsed * 1e3 / args.steps
     gbps = raw_bytes / (elapsed / args.steps) / 1e9
+    kprof_steps = max(1, min(args.steps, 5))
+    rsz.rsz_profile_enable(True)
+    for _ in range(kprof_steps):
+        B.run()
+    torch.cuda.synchronize()
+    prof_all = rsz.rsz_profile_read()
+    rsz.rsz_profile_enable(False)
 
     sizes = B.sizes.cpu().numpy().astype(np.int64)
     cr_u16 = (npix // len(frames)) * 2 / sizes
-    kernel_ms = {k: v[1] / v[0] for k, v in prof.items()}
-    kb_ms = kernel_ms["k_bin"]
+    kernel_ms = {k: v[1] / v[0] for k, v in prof_all.items()}
+    kb_ms = prof["k_bin"][1] / prof["k_bin"][0]
     achieved = raw_bytes / (kb_ms * 1e-3) / 1e9
     tr = traffic_record("k_bin")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
@@ -633,6 +645,8 @@ def main():
                        "one_frame_per_launch_p99": round(float(np.percentile(lat_ms, 99)), 4),
                        "batched_all_frames": round(ms_step, 4)},
         "kernel_ms": {k: round(v, 4) for k, v in kernel_ms.items()},
+        "kernel_ms_source": f"HIP events around every launch in {kprof_steps} steps after the "
+                            "timed region (inside it, events around k_bin only)",
         "serving": serving,
         "decompress": decomp,
         "lorenzo_dims": dims,

@@ -346,6 +346,9 @@ typedef struct {
 
 int rsz_profile_enable(int enable);
 int rsz_profile_read(rsz_kernel_time *h_out, int max, int *n);
+/* Record only the launches of the kernel with this name (NULL or "": every
+ * kernel), so that a timed region carries the events of one kernel only. */
+int rsz_profile_only(const char *name);
 
 #ifdef __cplusplus
 }

@@ -21,12 +21,15 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+std::string g_prof_only;   // record only this kernel's launches (empty: all)
 std::vector<ProfRec> g_prof;
 thread_local ProfRec *g_open = nullptr;
 }  // namespace
 
 void prof_begin(const char *name, hipStream_t s) {
   if (!g_prof_on) return;
+  g_open = nullptr;
+  if (!g_prof_only.empty() && g_prof_only != name) return;
   ProfRec r;
   r.name = name;
   if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
@@ -1031,6 +1034,12 @@ int rsz_profile_enable(int enable) {
   g_prof.clear();
   g_prof.reserve(1 << 16);
   g_prof_on = enable != 0;
+  return RSZ_OK;
+}
+
+int rsz_profile_only(const char *name) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_only = name ? name : "";
   return RSZ_OK;
 }
 

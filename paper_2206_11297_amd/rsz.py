@@ -22,7 +22,8 @@ EXPORTS = ["rsz_status_string", "rsz_max_compressed_bytes", "rsz_workspace_bytes
            "rsz_stream_info", "rsz_decompress_workspace_bytes", "rsz_decompress",
            "rsz_decompress_batch_workspace_bytes", "rsz_decompress_batch",
            "rsz_debug_intermediates", "rsz_debug_codebook", "rsz_measure_read",
-           "rsz_profile_enable", "rsz_profile_read", "rsz_peak_params_default",
+           "rsz_profile_enable", "rsz_profile_read", "rsz_profile_only",
+           "rsz_peak_params_default",
            "rsz_find_peaks_workspace_bytes", "rsz_find_peaks_batch"]
 
 
@@ -112,6 +113,7 @@ def lib():
         L.rsz_measure_read.argtypes = [vp, u64, vp, C.c_int, P(C.c_double), vp]
         L.rsz_profile_enable.argtypes = [C.c_int]
         L.rsz_profile_read.argtypes = [P(rsz_kernel_time), C.c_int, P(C.c_int)]
+        L.rsz_profile_only.argtypes = [C.c_char_p]
         L.rsz_peak_params_default.restype = None
         L.rsz_peak_params_default.argtypes = [P(rsz_peak_params)]
         L.rsz_find_peaks_workspace_bytes.argtypes = [u32, P(rsz_peak_desc), P(u64)]
@@ -267,6 +269,11 @@ def measure_read(nbytes=1 << 32, reps=10):
 
 def rsz_profile_enable(on):
     return lib().rsz_profile_enable(1 if on else 0)
+
+
+def rsz_profile_only(name=None):
+    """Record only the launches of kernel `name` (None: every kernel)."""
+    return lib().rsz_profile_only(name.encode() if name else None)
 
 
 def rsz_profile_read(max_entries=64):
