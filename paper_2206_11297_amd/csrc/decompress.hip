@@ -1,23 +1,35 @@
-// decompress.hip -- HIP kernels that decode a ROIBIN-SZ stream on gfx950.
+// decompress.hip -- HIP kernels that decode ROIBIN-SZ streams on gfx950.
 //
-//   k_dec_tables    one workgroup: check code lengths (<= 32, complete prefix
-//                   code), peaks and chunk offsets; build canonical decode
-//                   tables (11-bit single- and multi-symbol lookup tables +
-//                   per-length first codes).
+// Each kernel is launched once for all the streams of a call: its workgroups
+// are numbered across the streams (per-kernel prefixes of per-stream
+// counts), and a workgroup works on one stream's plan.
+//   k_dec_tables    one workgroup per stream: check code lengths (<= 32,
+//                   complete prefix code), peaks and chunk offsets; build
+//                   canonical decode tables (11-bit single- and multi-symbol
+//                   lookup tables + per-length first codes); write the
+//                   status of a stream the host rejected.
 //   k_dec_run_zero  runs coded: clear the words the runs expand into.
 //   k_dec_runs      runs coded: one thread per chunk expands its Rice-coded
 //                   zero runs back into the Huffman bits, checking parameters,
 //                   offsets and that every one bit stays inside its chunk.
 //   k_dec_chunks    one wave per 4096-symbol chunk, lanes on slices of its
 //                   bits (self-synchronising starts): Huffman decode to
-//                   residuals; each chunk must end exactly at the next offset.
+//                   residuals (runs of the one-bit residual-0 codeword 32 at
+//                   a time); each chunk must end exactly at the next offset.
 //   k_dec_outliers  scatter outlier residuals onto the code-0 positions.
-//   k_dec_rows      inclusive prefix sum along each bin row (wrapping int32).
+//   k_dec_rows      inclusive prefix sum along each bin row (wrapping int32),
+//                   four rows per wave.
+//   k_dec_carry, k_dec_rowadd  dimension 1: carries across the rows.
 //   k_dec_cols      inclusive prefix sum down each bin column -> q.
-//   k_dec_expand    every pixel gets float(q * 2eb) of its bin.
+//   k_dec_panels    dimension 3: prefix sum across the panels.
+//   k_dec_expand    one wave per bin row: every pixel gets float(q * 2eb) of
+//                   its bin.
+//   k_dec_roi_tables, k_dec_roi_decode, k_dec_roi_unpred  coded ROI: class
+//                   tables, per-window decode, inverse prediction.
 //   k_dec_roi       ROI windows restored from the payload bits.
 //   k_dec_roi_check overlapping windows must agree on their shared pixels.
-// The inverse Lorenzo step is the 2D prefix sum of the residuals per panel.
+// The inverse Lorenzo step is the prefix sum of the residuals along each
+// axis the predictor spans.
 #include <algorithm>
 
 #include "rsz_internal.h"

@@ -176,3 +176,13 @@ def test_batch_decode_workspace_on_the_host():
     d = desc(head)
     d.header = None
     assert rsz.rsz_decompress_batch_workspace_bytes([d])[0] == rsz.RSZ_ERR_ARG
+
+
+def test_profile_filter_on_the_host():
+    """rsz_profile_only selects the kernel whose launches are timed; with no
+    launch recorded the read-back is empty."""
+    assert rsz.rsz_profile_only("k_bin") == 0
+    assert rsz.rsz_profile_enable(True) == 0
+    assert rsz.rsz_profile_read() == {}
+    assert rsz.rsz_profile_enable(False) == 0
+    assert rsz.rsz_profile_only(None) == 0
