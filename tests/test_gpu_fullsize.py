@@ -103,6 +103,16 @@ def test_cspad_batch_1000_every_bound(torch, cspad_1000, eb):
     counts = [p.shape[0] for _, p in host]
     _check_oracle(B, sizes, host, _sample(counts, 16, eb), (32, 185, 388), 17, 2, eb)
     _check_headers(B, sizes, (32, 185, 388), 17, 2, eb, counts)
+    if eb == 1.0:   # the densest codes and the most outliers: decode them all at once
+        D = rsz.DecodeBatch([B.stream(i, sizes) for i in range(len(counts))])
+        D.run()
+        torch.cuda.synchronize()
+        assert (D.status.cpu().numpy() == 0).all()
+        for i in _sample(counts, 4, 1001):
+            st, yo = O.decompress(B.stream(i, sizes).cpu().numpy())
+            assert st == O.OK
+            np.testing.assert_array_equal(D.frames[i].cpu().numpy().view(np.uint32),
+                                          yo.view(np.uint32), err_msg=f"frame {i}")
 
 
 @pytest.mark.parametrize("dim", [1, 3])
@@ -160,6 +170,18 @@ def test_cspad_batch_1000_run_coded(torch, cspad_1000):
     st, yref = O.decompress(s0.cpu().numpy())
     assert st == O.OK
     np.testing.assert_array_equal(y.view(np.uint32), yref.view(np.uint32))
+    # all 1000 streams in one batched decompression: every status, and
+    # sampled frames against the oracle's decompression
+    print("  batched decompression of the 1000 streams", flush=True)
+    D = rsz.DecodeBatch([B.stream(i, sizes) for i in range(len(counts))])
+    D.run()
+    torch.cuda.synchronize()
+    assert (D.status.cpu().numpy() == 0).all()
+    for i in _sample(counts, 6, 301):
+        st, yo = O.decompress(B.stream(i, sizes).cpu().numpy())
+        assert st == O.OK
+        np.testing.assert_array_equal(D.frames[i].cpu().numpy().view(np.uint32),
+                                      yo.view(np.uint32), err_msg=f"frame {i}")
 
 
 # ------------------------------------------------------ Jungfrau-4M x 256
