@@ -207,6 +207,18 @@ def test_jungfrau4m_batch_256(torch, jf4m_256, w, b):
     counts = [p.shape[0] for _, p in host]
     _check_oracle(B, sizes, host, _sample(counts, 4, 10 * w + b), synth.JUNGFRAU4M, w, b, 10.0)
     _check_headers(B, sizes, synth.JUNGFRAU4M, w, b, 10.0, counts)
+    if w == 11:   # b = 2 and b = 4 (a row of exactly 256 bins): decode them all at once
+        D = rsz.DecodeBatch([B.stream(i, sizes) for i in range(len(counts))])
+        D.run()
+        torch.cuda.synchronize()
+        assert (D.status.cpu().numpy() == 0).all()
+        for i in _sample(counts, 2, 77 + b):
+            st, yo = O.decompress(B.stream(i, sizes).cpu().numpy())
+            assert st == O.OK
+            np.testing.assert_array_equal(D.frames[i].cpu().numpy().view(np.uint32),
+                                          yo.view(np.uint32), err_msg=f"frame {i}")
+        del D
+        torch.cuda.empty_cache()
 
 
 # ------------------------------------------- Jungfrau-16M x 512 from a graph
