@@ -20,10 +20,12 @@
 //   k_dec_rows      inclusive prefix sum along each bin row (wrapping int32),
 //                   four rows per wave.
 //   k_dec_carry, k_dec_rowadd  dimension 1: carries across the rows.
-//   k_dec_cols      inclusive prefix sum down each bin column -> q.
+//   k_dec_cols      inclusive prefix sum down each bin column -> q; for
+//                   dimension 2 it also writes every pixel float(q * 2eb)
+//                   of its bin.
 //   k_dec_panels    dimension 3: prefix sum across the panels.
-//   k_dec_expand    one wave per bin row: every pixel gets float(q * 2eb) of
-//                   its bin.
+//   k_dec_expand    dimensions 1 and 3, one wave per bin row: every pixel
+//                   gets float(q * 2eb) of its bin.
 //   k_dec_roi_tables, k_dec_roi_decode, k_dec_roi_unpred  coded ROI: class
 //                   tables, per-window decode, inverse prediction.
 //   k_dec_roi       ROI windows restored from the payload bits.
@@ -590,6 +592,25 @@ __global__ __launch_bounds__(256) void k_dec_rows(DecBatch db) {
 }
 
 // One lane per bin column: inclusive prefix sum down the column.
+// The pixels of bin (I, J) of a panel whose first pixel is out get v:
+// rows [I*b, min(I*b + b, H)), columns [J*b, min(J*b + b, W)).  For b = 2 or 4
+// with W a multiple of b a bin's pixels of one row are an aligned float2 /
+// float4 (the frame is 16-byte aligned).
+__device__ __forceinline__ void fill_bin(float *out, uint32_t H, uint32_t W, uint32_t b,
+                                         uint32_t I, uint32_t J, float v) {
+  const uint32_t i0 = I * b, i1 = min(i0 + b, H), j0 = J * b;
+  if (b == 2 && W % 2 == 0) {
+    for (uint32_t i = i0; i < i1; ++i) *(float2 *)(out + (size_t)i * W + j0) = make_float2(v, v);
+  } else if (b == 4 && W % 4 == 0) {
+    for (uint32_t i = i0; i < i1; ++i)
+      *(float4 *)(out + (size_t)i * W + j0) = make_float4(v, v, v, v);
+  } else {
+    const uint32_t j1 = min(j0 + b, W);
+    for (uint32_t i = i0; i < i1; ++i)
+      for (uint32_t j = j0; j < j1; ++j) out[(size_t)i * W + j] = v;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_dec_cols(DecBatch db) {
   RSZ_DEC_FRAME(8);
   const uint32_t col = bid * 256 + threadIdx.x;
@@ -597,6 +618,17 @@ __global__ __launch_bounds__(256) void k_dec_cols(DecBatch db) {
   const uint32_t p = col / dp.Wb, J = col - p * dp.Wb;
   int32_t *r = dp.res + (size_t)p * dp.Hb * dp.Wb + J;
   const size_t Wb = dp.Wb;
+  // dimension 2: q is final here, so its pixels are written at once (no
+  // expansion pass re-reads the residuals); dimension 3 stores q for the
+  // sum across the panels
+  const bool fill = dp.dim == 2;
+  float *out = dp.frame + (size_t)p * dp.H * dp.W;
+  const uint32_t H = dp.H, W = dp.W, b = dp.b;
+  const double step = dp.step;
+  auto put = [&](uint32_t I, uint32_t acc) {
+    if (fill) fill_bin(out, H, W, b, I, J, (float)((double)(int32_t)acc * step));
+    else r[I * Wb] = (int32_t)acc;
+  };
   uint32_t acc = 0;
   uint32_t I = 0;
   // eight rows loaded before any is stored (a store would otherwise hold
@@ -608,12 +640,12 @@ __global__ __launch_bounds__(256) void k_dec_cols(DecBatch db) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       acc += v[k];
-      r[(I + k) * Wb] = (int32_t)acc;
+      put(I + k, acc);
     }
   }
   for (; I < dp.Hb; ++I) {
     acc += (uint32_t)r[I * Wb];
-    r[I * Wb] = (int32_t)acc;
+    put(I, acc);
   }
 }
 
@@ -679,35 +711,11 @@ __global__ __launch_bounds__(256) void k_dec_expand(DecBatch db) {
   if (brow >= dp.P * dp.Hb || !dec_ok(dp.status)) return;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t p = brow / dp.Hb, I = brow - p * dp.Hb;
-  const uint32_t b = dp.b, W = dp.W;
-  const uint32_t i0 = I * b, i1 = min(i0 + b, dp.H);
   const int32_t *rb = dp.res + (size_t)brow * dp.Wb;
-  float *out = dp.frame + ((size_t)p * dp.H + i0) * W;
+  float *out = dp.frame + (size_t)p * dp.H * dp.W;
   const double step = dp.step;
-  // b = 2 or 4 with W a multiple of b: a bin's pixels of a row are one
-  // aligned float2 / float4 (the frame is 16-byte aligned)
-  if (b == 2 && W % 2 == 0) {
-    for (uint32_t J = lane; J < dp.Wb; J += 64) {
-      const float v = (float)((double)rb[J] * step);
-      for (uint32_t i = i0; i < i1; ++i)
-        *(float2 *)(out + (size_t)(i - i0) * W + 2 * J) = make_float2(v, v);
-    }
-  } else if (b == 4 && W % 4 == 0) {
-    for (uint32_t J = lane; J < dp.Wb; J += 64) {
-      const float v = (float)((double)rb[J] * step);
-      for (uint32_t i = i0; i < i1; ++i)
-        *(float4 *)(out + (size_t)(i - i0) * W + 4 * J) = make_float4(v, v, v, v);
-    }
-  } else {
-    for (uint32_t J = lane; J < dp.Wb; J += 64) {
-      const float v = (float)((double)rb[J] * step);
-      const uint32_t j0 = J * b, j1 = min(j0 + b, W);
-      for (uint32_t i = i0; i < i1; ++i) {
-        float *o = out + (size_t)(i - i0) * W;
-        for (uint32_t j = j0; j < j1; ++j) o[j] = v;
-      }
-    }
-  }
+  for (uint32_t J = lane; J < dp.Wb; J += 64)
+    fill_bin(out, dp.H, dp.W, dp.b, I, J, (float)((double)rb[J] * step));
 }
 
 // ------------------------------------------------------- coded ROI windows
@@ -916,7 +924,7 @@ void decode_blocks(const DecodePlan &dp, uint32_t *nb) {
     nb[8] = (dp.P * dp.Wb + 255) / 256;
     if (dp.dim == 3) nb[9] = (dp.Hb * dp.Wb + 255) / 256;
   }
-  nb[10] = (dp.P * dp.Hb + 3) / 4;
+  if (dp.dim != 2) nb[10] = (dp.P * dp.Hb + 3) / 4;   // dimension 2: k_dec_cols
   if (dp.roi_coding) {
     nb[11] = 1;
     nb[12] = (dp.npeaks + 255) / 256;
