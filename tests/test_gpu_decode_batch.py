@@ -115,3 +115,20 @@ def test_full_cspad_batch_decodes_like_single_calls(torch):
         assert torch.equal(y.view(torch.int32), D.frames[i].view(torch.int32))
         st, yo = O.decompress(streams[i].cpu().numpy())
         np.testing.assert_array_equal(D.frames[i].cpu().numpy().view(np.uint32), yo.view(np.uint32))
+
+
+def test_pixel_write_paths(torch):
+    """Dimension 2 writes the pixels in the column sums: b = 2 / 4 with W a
+    multiple of b as one float2 / float4 per pixel row of a bin, other shapes
+    pixel by pixel; odd H leaves a last bin row of fewer pixel rows.
+    Dimensions 1 and 3 expand in a pass of their own."""
+    cases = [((2, 31, 40), 2, 2), ((3, 29, 42), 2, 2), ((2, 17, 41), 2, 2), ((2, 33, 44), 4, 2),
+             ((2, 35, 46), 4, 2), ((2, 23, 39), 3, 2), ((1, 9, 4), 2, 2), ((2, 31, 40), 2, 1),
+             ((3, 29, 44), 2, 3)]
+    streams = []
+    for k, (shape, b, dim) in enumerate(cases):
+        f, pk = synth.tiny_case(60 + k, shape, 3, "normal", scale=50.0)
+        st, s, _ = O.compress(O.params(*shape, 3, b, 0.5, 0, dim), f, pk)
+        assert st == O.OK
+        streams.append(s)
+    _check(torch, streams)
