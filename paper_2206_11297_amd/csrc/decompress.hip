@@ -23,6 +23,9 @@
 //   k_dec_cols      inclusive prefix sum down each bin column -> q; for
 //                   dimension 2 it also writes every pixel float(q * 2eb)
 //                   of its bin.
+//   k_dec_panel     dimension 2 with a panel's bins in LDS (instead of
+//                   k_dec_rows and k_dec_cols): one workgroup per panel, row
+//                   sums, column sums and pixels.
 //   k_dec_panels    dimension 3: prefix sum across the panels.
 //   k_dec_expand    dimensions 1 and 3, one wave per bin row: every pixel
 //                   gets float(q * 2eb) of its bin.
@@ -705,6 +708,94 @@ __global__ __launch_bounds__(256) void k_dec_panels(DecBatch db) {
 // One wave per bin row: each lane takes a bin, computes its value once and
 // writes it to the bin's b x b pixels (clipped at the panel edges), a raw
 // row at a time, so the wave's stores of a row are contiguous.
+// Dimension 2 where a panel's bins fit in LDS (and a bin row in one
+// workgroup's threads): one workgroup per panel takes the row sums, the
+// column sums and the pixel writes, so the residuals make one trip from HBM.
+constexpr uint32_t kPanelBins = 19200;
+constexpr uint32_t kPanelThreads = 1024;
+__host__ __device__ inline bool panel_in_lds(const DecodePlan &dp) {
+  return dp.dim == 2 && (uint64_t)dp.Hb * dp.Wb <= kPanelBins && dp.Wb <= kPanelThreads;
+}
+
+__global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
+  RSZ_DEC_FRAME(16);
+  __shared__ uint32_t s_v[kPanelBins];
+  __shared__ uint32_t s_part[kPanelThreads];
+  __shared__ int s_ok, s_bad;
+  const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // one read of the status for the whole workgroup (another panel may
+  // change it meanwhile), so every thread takes the same branch
+  if (t == 0) {
+    s_ok = dec_ok(dp.status);
+    s_bad = 0;
+  }
+  __syncthreads();
+  if (!s_ok) return;
+  const uint32_t Hb = dp.Hb, Wb = dp.Wb, n = Hb * Wb;
+  const int32_t *r = dp.res + (size_t)bid * n;
+  // the panel's residuals into LDS, eight loads per thread in flight
+  bool bad = false;
+  for (uint32_t i0 = 0; i0 < n; i0 += 8 * kPanelThreads) {
+    int32_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t i = i0 + k * kPanelThreads + t;
+      v[k] = i < n ? r[i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t i = i0 + k * kPanelThreads + t;
+      if (i < n) {
+        bad |= v[k] == kMark;
+        s_v[i] = (uint32_t)v[k];
+      }
+    }
+  }
+  if (bad) s_bad = 1;
+  __syncthreads();
+  if (s_bad) {
+    if (t == 0) corrupt(dp.status);
+    return;
+  }
+  // row sums: wave w takes rows w, w + 16, ...
+  for (uint32_t I = wave; I < Hb; I += kPanelThreads / 64) {
+    uint32_t carry = 0;
+    for (uint32_t j0 = 0; j0 < Wb; j0 += 64) {
+      const uint32_t j = j0 + lane;
+      uint32_t x = j < Wb ? s_v[I * Wb + j] : 0u;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+      }
+      x += carry;
+      if (j < Wb) s_v[I * Wb + j] = x;
+      carry = __shfl(x, 63);
+    }
+  }
+  __syncthreads();
+  // column sums: thread (g, J) = (t / Wb, t % Wb) takes bin column J over
+  // the g-th block of rows; the blocks' totals give each its carry
+  const uint32_t G = min(kPanelThreads / Wb, Hb), per = (Hb + G - 1) / G;
+  const uint32_t g = t / Wb, J = t - g * Wb;
+  const uint32_t I0 = min(g * per, Hb), I1 = min(I0 + per, Hb);
+  uint32_t part = 0;
+  if (g < G)
+    for (uint32_t I = I0; I < I1; ++I) part += s_v[I * Wb + J];
+  s_part[t] = part;
+  __syncthreads();
+  if (g >= G) return;
+  uint32_t acc = 0;
+  for (uint32_t h = 0; h < g; ++h) acc += s_part[h * Wb + J];
+  float *out = dp.frame + (size_t)bid * dp.H * dp.W;
+  const uint32_t H = dp.H, W = dp.W, b = dp.b;
+  const double step = dp.step;
+  for (uint32_t I = I0; I < I1; ++I) {
+    acc += s_v[I * Wb + J];
+    fill_bin(out, H, W, b, I, J, (float)((double)(int32_t)acc * step));
+  }
+}
+
 __global__ __launch_bounds__(256) void k_dec_expand(DecBatch db) {
   RSZ_DEC_FRAME(10);
   const uint32_t brow = bid * 4 + (threadIdx.x >> 6);
@@ -916,13 +1007,17 @@ void decode_blocks(const DecodePlan &dp, uint32_t *nb) {
   nb[3] = (dp.nchunks + 3) / 4;
   nb[4] = (dp.n_out + 255) / 256;
   // inverse Lorenzo: prefix sums along each axis the predictor spans
-  nb[5] = (dp.P * dp.Hb + 4 * kDecRowsPerWave - 1) / (4 * kDecRowsPerWave);
-  if (dp.dim == 1) {
-    nb[6] = 1;
-    nb[7] = std::min<uint32_t>((dp.nbins + 255) / 256, 1u << 16);
+  if (panel_in_lds(dp)) {
+    nb[16] = dp.P;   // k_dec_panel: rows, columns and pixels
   } else {
-    nb[8] = (dp.P * dp.Wb + 255) / 256;
-    if (dp.dim == 3) nb[9] = (dp.Hb * dp.Wb + 255) / 256;
+    nb[5] = (dp.P * dp.Hb + 4 * kDecRowsPerWave - 1) / (4 * kDecRowsPerWave);
+    if (dp.dim == 1) {
+      nb[6] = 1;
+      nb[7] = std::min<uint32_t>((dp.nbins + 255) / 256, 1u << 16);
+    } else {
+      nb[8] = (dp.P * dp.Wb + 255) / 256;
+      if (dp.dim == 3) nb[9] = (dp.Hb * dp.Wb + 255) / 256;
+    }
   }
   if (dp.dim != 2) nb[10] = (dp.P * dp.Hb + 3) / 4;   // dimension 2: k_dec_cols
   if (dp.roi_coding) {
@@ -956,6 +1051,7 @@ hipError_t launch_decompress(const DecBatch &db, const uint32_t *total, hipStrea
   RSZ_DLAUNCH(8, "k_dec_cols", k_dec_cols, 256);
   RSZ_DLAUNCH(9, "k_dec_panels", k_dec_panels, 256);
   RSZ_DLAUNCH(10, "k_dec_expand", k_dec_expand, 256);
+  RSZ_DLAUNCH(16, "k_dec_panel", k_dec_panel, 1024);
   RSZ_DLAUNCH(11, "k_dec_roi_tables", k_dec_roi_tables, 64);
   RSZ_DLAUNCH(12, "k_dec_roi_decode", k_dec_roi_decode, 256);
   RSZ_DLAUNCH(13, "k_dec_roi_unpred", k_dec_roi_unpred, 256);

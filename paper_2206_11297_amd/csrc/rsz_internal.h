@@ -162,7 +162,7 @@ struct DecodePlan {
 // Streams decoded together: every decoder kernel is launched once for all of
 // them, its workgroups numbered across the frames.  pre holds kDecKernels
 // prefix arrays of n + 1 entries, kernel K's per-frame workgroup counts.
-constexpr int kDecKernels = 16;
+constexpr int kDecKernels = 17;
 struct DecBatch {
   uint32_t n;
   const DecodePlan *plans;

@@ -118,13 +118,19 @@ def test_full_cspad_batch_decodes_like_single_calls(torch):
 
 
 def test_pixel_write_paths(torch):
-    """Dimension 2 writes the pixels in the column sums: b = 2 / 4 with W a
-    multiple of b as one float2 / float4 per pixel row of a bin, other shapes
-    pixel by pixel; odd H leaves a last bin row of fewer pixel rows.
+    """Dimension 2 writes the pixels where q becomes final: in one workgroup
+    per panel when the panel's bins fit in LDS (at most 19200 of them, at
+    most 1024 per row), else in the column sums.  b = 2 / 4 with W a
+    multiple of b writes one float2 / float4 per pixel row of a bin, other
+    shapes pixel by pixel; odd H leaves a last bin row of fewer pixel rows.
     Dimensions 1 and 3 expand in a pass of their own."""
     cases = [((2, 31, 40), 2, 2), ((3, 29, 42), 2, 2), ((2, 17, 41), 2, 2), ((2, 33, 44), 4, 2),
              ((2, 35, 46), 4, 2), ((2, 23, 39), 3, 2), ((1, 9, 4), 2, 2), ((2, 31, 40), 2, 1),
-             ((3, 29, 44), 2, 3)]
+             ((3, 29, 44), 2, 3),
+             # at and past the LDS limits: 19200 / 19456 bins, 1024 / 1250 bins a row
+             ((2, 75, 256), 1, 2), ((1, 76, 256), 1, 2), ((1, 4, 2048), 2, 2), ((1, 3, 2500), 2, 2),
+             # column sums writing the pixels: float2, pixel by pixel, float4
+             ((1, 401, 202), 2, 2), ((1, 5, 2501), 2, 2), ((1, 650, 480), 4, 2)]
     streams = []
     for k, (shape, b, dim) in enumerate(cases):
         f, pk = synth.tiny_case(60 + k, shape, 3, "normal", scale=50.0)
