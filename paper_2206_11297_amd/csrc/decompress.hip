@@ -15,7 +15,9 @@
 //   k_dec_chunks    one wave per 4096-symbol chunk, lanes on slices of its
 //                   bits (self-synchronising starts): Huffman decode to
 //                   residuals (runs of the one-bit residual-0 codeword 32 at
-//                   a time); each chunk must end exactly at the next offset.
+//                   a time; the chunk zeroed with whole-row stores first, then
+//                   only nonzero residuals stored); each chunk must end
+//                   exactly at the next offset.
 //   k_dec_outliers  scatter outlier residuals onto the code-0 positions.
 //   k_dec_rows      inclusive prefix sum along each bin row (wrapping int32),
 //                   four rows per wave.
@@ -277,10 +279,11 @@ struct BitWindow {
 };
 
 // Decodes codewords from `pos` while pos < lim: returns the count and leaves
-// pos at the first boundary >= lim; with `out`, writes each residual (kMark
-// for code 0) at out[k] for k < cap.  `inval` reports a bit pattern that is
-// no codeword.  With `zrun` (residual 0's codeword is the single bit 0), a
-// run of z zero bits is z residual-0 symbols, taken at once up to lim.
+// pos at the first boundary >= lim; with WRITE, writes each nonzero residual
+// (kMark for code 0) at out[k] for k < cap (out holds zeros already).
+// `inval` reports a bit pattern that is no codeword.  With `zrun` (residual
+// 0's codeword is the single bit 0), a run of z zero bits is z residual-0
+// symbols, taken at once up to lim.
 template <bool WRITE>
 __device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, uint64_t lim,
                                                const uint2 *s_multi, const uint32_t *s_first,
@@ -294,9 +297,6 @@ __device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, ui
     if (zrun && !(v >> 31)) {
       const uint32_t z = v ? (uint32_t)__builtin_clz(v) : 32u;
       const uint32_t take = (uint32_t)min<uint64_t>(z, lim - pos);
-      if (WRITE)
-        for (uint32_t j = 0; j < take; ++j)
-          if (m + j < cap) out[m + j] = 0;
       pos += take;
       m += take;
       continue;
@@ -310,7 +310,7 @@ __device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, ui
       for (uint32_t j = 0; j < take; ++j) {
         const uint32_t sym = (e.x >> (10 * j)) & 0x3FFu;
         zeros += sym == 0;
-        if (WRITE && m + j < cap) out[m + j] = sym ? (int32_t)sym - kRadius : kMark;
+        if (WRITE && m + j < cap && sym != kRadius) out[m + j] = sym ? (int32_t)sym - kRadius : kMark;
       }
       pos += (e.y >> (4 * (take - 1))) & 0xFu;
       m += take;
@@ -329,7 +329,7 @@ __device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, ui
         break;
       }
       zeros += sym == 0;
-      if (WRITE && m < cap) out[m] = sym ? (int32_t)sym - kRadius : kMark;
+      if (WRITE && m < cap && sym != kRadius) out[m] = sym ? (int32_t)sym - kRadius : kMark;
       pos += L;
       ++m;
     }
@@ -486,7 +486,20 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
   bool bad = !converged || __builtin_amdgcn_uicmp((uint32_t)inv, 0u, 33 /* ne */) != 0 ||
              tot != nsym || last != E;
   inv = false;
-  // the output pass, from the true starts
+  // the output pass, from the true starts: the wave zeroes the chunk's
+  // residuals with whole-row stores, waits for them to complete, and the
+  // lanes then store only their nonzero residuals (most are 0)
+  if (!bad) {
+    int32_t *rc = dp.res + g0;
+    for (uint32_t i = 4 * lane; i < nsym; i += 256) {
+      if (i + 4 <= nsym) {
+        *(int4 *)(rc + i) = make_int4(0, 0, 0, 0);
+      } else {
+        for (uint32_t k = i; k < nsym; ++k) rc[k] = 0;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  }
   BitWindow win;
   win.init(bw, nwords, start);
   uint64_t pos = start;
