@@ -33,8 +33,10 @@
 //                   gets float(q * 2eb) of its bin.
 //   k_dec_roi_tables, k_dec_roi_decode, k_dec_roi_unpred  coded ROI: class
 //                   tables, per-window decode, inverse prediction.
-//   k_dec_roi       ROI windows restored from the payload bits.
-//   k_dec_roi_check overlapping windows must agree on their shared pixels.
+//   k_dec_roi       ROI windows restored from the payload bits, one wave
+//                   per window.
+//   k_dec_roi_check overlapping windows must agree on their shared pixels
+//                   (one wave per window).
 // The inverse Lorenzo step is the prefix sum of the residuals along each
 // axis the predictor spans.
 #include <algorithm>
@@ -964,55 +966,58 @@ __global__ __launch_bounds__(256) void k_dec_roi_unpred(DecBatch db) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_dec_roi(DecBatch db) {
-  RSZ_DEC_FRAME(14);
-  if (!dec_ok(dp.status)) return;
-  const uint64_t ww = (uint64_t)dp.w * dp.w;
-  const uint64_t n = (uint64_t)dp.npeaks * ww;
-  const uint64_t stride = (uint64_t)nblk * 256;
+// Window k of a frame, one wave: lane l starts at window element l and steps
+// 64 elements at a time, its (row, column) in the window advanced without a
+// division.  Pixels outside the frame are not part of the window.  CHECK
+// compares the frame with the payload instead of writing it.
+template <bool CHECK>
+__device__ __forceinline__ bool roi_window(const DecodePlan &dp, uint32_t k, uint32_t lane) {
+  const uint32_t w = dp.w, ww = w * w;
   const uint16_t *pk = (const uint16_t *)(dp.in + dp.off_peaks);
   const uint32_t *pay =
-      dp.roi_coding ? dp.roi_payload : (const uint32_t *)(dp.in + dp.off_roi);
-  const int64_t h = dp.w / 2;
-  for (uint64_t e = (uint64_t)bid * 256 + threadIdx.x; e < n; e += stride) {
-    const uint64_t k = e / ww, rem = e - k * ww;
-    const int64_t u = rem / dp.w, v = rem - u * dp.w;
-    const int64_t pa = pk[3 * k], i = (int64_t)pk[3 * k + 1] - h + u,
-                  j = (int64_t)pk[3 * k + 2] - h + v;
-    if (pa < dp.P && i >= 0 && i < dp.H && j >= 0 && j < dp.W)
-      ((uint32_t *)dp.frame)[((uint64_t)pa * dp.H + i) * dp.W + j] = pay[e];
+      (dp.roi_coding ? dp.roi_payload : (const uint32_t *)(dp.in + dp.off_roi)) + (size_t)k * ww;
+  const uint32_t pa = pk[3 * k];
+  if (pa >= dp.P) return false;
+  const int32_t h = (int32_t)(w / 2), H = (int32_t)dp.H, W = (int32_t)dp.W;
+  const int32_t i0 = (int32_t)pk[3 * k + 1] - h, j0 = (int32_t)pk[3 * k + 2] - h;
+  uint32_t *fr = (uint32_t *)dp.frame + (size_t)pa * dp.H * dp.W;
+  const uint32_t du = 64 / w, dv = 64 % w;
+  uint32_t u = lane / w, v = lane - u * w;
+  bool bad = false;
+  for (uint32_t e = lane; e < ww; e += 64) {
+    const int32_t i = i0 + (int32_t)u, j = j0 + (int32_t)v;
+    if (i >= 0 && i < H && j >= 0 && j < W) {
+      uint32_t *px = fr + (size_t)i * dp.W + j;
+      if (CHECK) bad |= *px != pay[e];
+      else *px = pay[e];
+    }
+    u += du;
+    v += dv;
+    if (v >= w) {
+      v -= w;
+      ++u;
+    }
   }
+  return bad;
 }
 
-// Overlapping windows copy the same frame pixel: every payload entry must
-// match what was restored at its pixel, else the stream is malformed.
+__global__ __launch_bounds__(256) void k_dec_roi(DecBatch db) {
+  RSZ_DEC_FRAME(14);
+  const uint32_t k = bid * 4 + (threadIdx.x >> 6);
+  if (k >= dp.npeaks || !dec_ok(dp.status)) return;
+  roi_window<false>(dp, k, threadIdx.x & 63);
+}
 __global__ __launch_bounds__(256) void k_dec_roi_check(DecBatch db) {
   RSZ_DEC_FRAME(15);
-  if (!dec_ok(dp.status)) return;
-  const uint64_t ww = (uint64_t)dp.w * dp.w;
-  const uint64_t n = (uint64_t)dp.npeaks * ww;
-  const uint64_t stride = (uint64_t)nblk * 256;
-  const uint16_t *pk = (const uint16_t *)(dp.in + dp.off_peaks);
-  const uint32_t *pay =
-      dp.roi_coding ? dp.roi_payload : (const uint32_t *)(dp.in + dp.off_roi);
-  const int64_t h = dp.w / 2;
-  bool bad = false;
-  for (uint64_t e = (uint64_t)bid * 256 + threadIdx.x; e < n; e += stride) {
-    const uint64_t k = e / ww, rem = e - k * ww;
-    const int64_t u = rem / dp.w, v = rem - u * dp.w;
-    const int64_t pa = pk[3 * k], i = (int64_t)pk[3 * k + 1] - h + u,
-                  j = (int64_t)pk[3 * k + 2] - h + v;
-    if (pa < dp.P && i >= 0 && i < dp.H && j >= 0 && j < dp.W)
-      bad |= ((const uint32_t *)dp.frame)[((uint64_t)pa * dp.H + i) * dp.W + j] != pay[e];
-  }
-  if (bad) corrupt(dp.status);
+  const uint32_t k = bid * 4 + (threadIdx.x >> 6);
+  if (k >= dp.npeaks || !dec_ok(dp.status)) return;
+  if (roi_window<true>(dp, k, threadIdx.x & 63)) corrupt(dp.status);
 }
 
 void decode_blocks(const DecodePlan &dp, uint32_t *nb) {
   for (int k = 0; k < kDecKernels; ++k) nb[k] = 0;
   nb[0] = 1;   // k_dec_tables writes every frame's status
   if (dp.init_status != RSZ_OK) return;
-  const uint64_t nroi = (uint64_t)dp.npeaks * dp.w * dp.w;
   if (dp.run_coding) {
     nb[1] = (uint32_t)std::min<uint64_t>(((dp.T + 31) / 32 + 2 + 255) / 256, 1u << 16);
     nb[2] = (dp.nchunks + 255) / 256;
@@ -1038,7 +1043,7 @@ void decode_blocks(const DecodePlan &dp, uint32_t *nb) {
     nb[12] = (dp.npeaks + 255) / 256;
     nb[13] = (dp.npeaks + 3) / 4;
   }
-  nb[14] = nb[15] = (uint32_t)std::min<uint64_t>((nroi + 255) / 256, 1u << 20);
+  nb[14] = nb[15] = (dp.npeaks + 3) / 4;   // a wave per window
 }
 
 #define RSZ_DLAUNCH(k, name, kern, block)                              \

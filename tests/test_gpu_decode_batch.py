@@ -138,3 +138,19 @@ def test_pixel_write_paths(torch):
         assert st == O.OK
         streams.append(s)
     _check(torch, streams)
+
+
+def test_window_widths(torch):
+    """ROI windows are restored and cross-checked one wave per window, the
+    lanes stepping 64 window elements at a time: widths below, at and above
+    64 (a step wraps a row at most once), a width of 1, and windows clipped
+    by the frame's edges or overlapping each other."""
+    streams = []
+    for k, w in enumerate((1, 2, 7, 63, 64, 65, 129)):
+        f, pk = synth.tiny_case(80 + k, (2, 150, 170), 6, "normal", scale=50.0)
+        pk[0, 1:] = (0, 0)                  # clipped at a corner
+        pk[1, :] = (pk[2, 0], pk[2, 1], min(pk[2, 2] + 1, 169))   # overlaps peak 2
+        st, s, _ = O.compress(O.params(2, 150, 170, w, 2, 0.5, 0, 2, k % 2), f, pk)
+        assert st == O.OK, w
+        streams.append(s)
+    _check(torch, streams)
