@@ -136,37 +136,43 @@ def decompress_section(args, torch, dev, B, sizes, host):
     lat_ms = np.array(lat) * 1e3
     fb = SHAPE[0] * SHAPE[1] * SHAPE[2] * 4
     del streams, ws, out
-    # every stream of the batch in one batched call (rsz_decompress_batch:
-    # one launch of each decoder kernel for all of them)
-    D = rsz.DecodeBatch([B.stream(i, sizes) for i in range(len(sizes))])
-    for _ in range(2):
-        D.run()
-    torch.cuda.synchronize()
-    assert (D.status.cpu().numpy() == 0).all()
-    # timed with no events; per-kernel times from a profiled pass after it
-    t0 = time.perf_counter()
-    for _ in range(args.decompress_steps):
-        D.run()
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / args.decompress_steps
-    rsz.rsz_profile_enable(True)
-    for _ in range(max(1, min(args.decompress_steps, 3))):
-        D.run()
-    torch.cuda.synchronize()
-    bprof = rsz.rsz_profile_read()
-    rsz.rsz_profile_enable(False)
-    batched = {"frames": len(sizes), "ms_per_batch": round(el * 1e3, 4),
-               "gbps": round(len(sizes) * fb / el / 1e9, 2),
-               "kernel_ms": {k: round(v[1] / v[0], 4) for k, v in bprof.items()}}
+    batched = batched_decode(torch, B, sizes, args.decompress_steps, len(sizes) * fb)
     print(f"[bench] batched decompression: {batched['gbps']} GB/s", file=sys.stderr, flush=True)
-    del D
-    torch.cuda.empty_cache()
     return {"frames": n, "mode": "one frame per call (synchronous)",
             "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
             "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
             "gbps": round(n * fb / (lat_ms.sum() / 1e3) / 1e9, 2),
             "kernel_ms_per_frame": {k: round(v[1] / v[0], 4) for k, v in prof.items()},
             "batched": batched}
+
+
+def batched_decode(torch, B, sizes, steps, raw_bytes):
+    """Every stream of batch B decoded in one batched call
+    (rsz_decompress_batch: one launch of each decoder kernel for all of
+    them), timed with no events; per-kernel times from a profiled pass after
+    it."""
+    from paper_2206_11297_amd import rsz
+    D = rsz.DecodeBatch([B.stream(i, sizes) for i in range(len(sizes))])
+    for _ in range(2):
+        D.run()
+    torch.cuda.synchronize()
+    assert (D.status.cpu().numpy() == 0).all()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        D.run()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    rsz.rsz_profile_enable(True)
+    for _ in range(max(1, min(steps, 3))):
+        D.run()
+    torch.cuda.synchronize()
+    prof = rsz.rsz_profile_read()
+    rsz.rsz_profile_enable(False)
+    del D
+    torch.cuda.empty_cache()
+    return {"frames": len(sizes), "ms_per_batch": round(el * 1e3, 4),
+            "gbps": round(raw_bytes / el / 1e9, 2),
+            "kernel_ms": {k: round(v[1] / v[0], 4) for k, v in prof.items()}}
 
 
 def timed_steps(torch, B, steps):
@@ -235,7 +241,10 @@ def coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_s
            "steps": steps,
            "compression_ratio_u16_aggregate": round(float(raw_bytes / 2 / sizes.sum()), 3),
            "kernel_ms": kms}
-    print(f"[bench] {label}: {out['value']} GB/s, CR {out['compression_ratio_u16_aggregate']}",
+    # the same streams decoded in one batched call
+    out["decompress_batched"] = batched_decode(torch, B, sizes, steps, raw_bytes)
+    print(f"[bench] {label}: {out['value']} GB/s, CR {out['compression_ratio_u16_aggregate']}; "
+          f"batched decompression {out['decompress_batched']['gbps']} GB/s",
           file=sys.stderr, flush=True)
     del B
     torch.cuda.empty_cache()

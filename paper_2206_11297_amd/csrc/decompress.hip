@@ -832,6 +832,7 @@ __global__ __launch_bounds__(256) void k_dec_expand(DecBatch db) {
 // length 1), padding zero; no class at all when there is no window.
 constexpr int kRoiTabFirst = 0, kRoiTabCount = 33, kRoiTabBase = 66, kRoiTabSym = 99;
 constexpr int kRoiTabWords = 132;
+constexpr int kRoiLutBits = 10;   // k_dec_roi_decode: codes this short by one lookup
 
 __global__ __launch_bounds__(64) void k_dec_roi_tables(DecBatch db) {
   RSZ_DEC_FRAME(11);
@@ -882,9 +883,33 @@ __device__ __forceinline__ uint32_t roi_peek(const uint32_t *words, uint64_t nwo
 // at Troi.
 __global__ __launch_bounds__(256) void k_dec_roi_decode(DecBatch db) {
   RSZ_DEC_FRAME(12);
+  // the frame's class tables in LDS, and a lookup of every code of at most
+  // kRoiLutBits bits by the stream's next kRoiLutBits bits: class | L << 8
+  // (0: a longer code, or none)
+  __shared__ uint32_t s_t[kRoiTabWords];
+  __shared__ uint16_t s_lut[1 << kRoiLutBits];
+  __shared__ int s_ok;
+  // one read of the status for the workgroup (a window may set it
+  // meanwhile), so that every thread takes the same branch
+  if (threadIdx.x == 0) s_ok = dec_ok(dp.status);
+  for (uint32_t x = threadIdx.x; x < (uint32_t)kRoiTabWords; x += 256) s_t[x] = dp.roi_tables[x];
+  __syncthreads();
+  if (!s_ok) return;
+  for (uint32_t x = threadIdx.x; x < (1u << kRoiLutBits); x += 256) {
+    uint16_t e = 0;
+    for (int L = 1; L <= kRoiLutBits; ++L) {
+      const uint32_t code = x >> (kRoiLutBits - L);
+      const uint32_t cnt = s_t[kRoiTabCount + L - 1], first = s_t[kRoiTabFirst + L - 1];
+      if (cnt && code - first < cnt) {
+        e = (uint16_t)(s_t[kRoiTabSym + s_t[kRoiTabBase + L - 1] + (code - first)] | (L << 8));
+        break;
+      }
+    }
+    s_lut[x] = e;
+  }
+  __syncthreads();
   const uint32_t k = bid * 256 + threadIdx.x;
-  if (k >= dp.npeaks || !dec_ok(dp.status)) return;
-  const uint32_t *t = dp.roi_tables;
+  if (k >= dp.npeaks) return;
   const uint32_t *offs = (const uint32_t *)(dp.in + dp.off_roffs);
   const uint32_t *words = (const uint32_t *)(dp.in + dp.off_rbits);
   const uint64_t nwords = (dp.Troi + 31) / 32;
@@ -898,13 +923,19 @@ __global__ __launch_bounds__(256) void k_dec_roi_decode(DecBatch db) {
   uint64_t pos = start;
   for (uint64_t e = 0; e < ww; ++e) {
     const uint32_t peek = roi_peek(words, nwords, pos);
+    const uint32_t hit = s_lut[peek >> (32 - kRoiLutBits)];
     int cls = -1, L = 1;
-    for (; L <= kMaxLen; ++L) {
-      const uint32_t code = peek >> (32 - L);
-      const uint32_t cnt = t[kRoiTabCount + L - 1], first = t[kRoiTabFirst + L - 1];
-      if (cnt && code - first < cnt) {
-        cls = (int)t[kRoiTabSym + t[kRoiTabBase + L - 1] + (code - first)];
-        break;
+    if (hit) {
+      cls = (int)(hit & 0xFFu);
+      L = (int)(hit >> 8);
+    } else {
+      for (L = kRoiLutBits + 1; L <= kMaxLen; ++L) {
+        const uint32_t code = peek >> (32 - L);
+        const uint32_t cnt = s_t[kRoiTabCount + L - 1], first = s_t[kRoiTabFirst + L - 1];
+        if (cnt && code - first < cnt) {
+          cls = (int)s_t[kRoiTabSym + s_t[kRoiTabBase + L - 1] + (code - first)];
+          break;
+        }
       }
     }
     if (cls < 0 || pos + L > end) {
