@@ -10,8 +10,9 @@
 //                   status of a stream the host rejected.
 //   k_dec_run_zero  runs coded: clear the words the runs expand into.
 //   k_dec_runs      runs coded: one thread per chunk expands its Rice-coded
-//                   zero runs back into the Huffman bits, checking parameters,
-//                   offsets and that every one bit stays inside its chunk.
+//                   zero runs back into the Huffman bits (a word at a time),
+//                   checking parameters, offsets and that every one bit stays
+//                   inside its chunk.
 //   k_dec_chunks    one wave per 4096-symbol chunk, lanes on slices of its
 //                   bits (self-synchronising starts): Huffman decode to
 //                   residuals (runs of the one-bit residual-0 codeword 32 at
@@ -389,6 +390,16 @@ __global__ __launch_bounds__(256) void k_dec_runs(DecBatch db) {
   const uint32_t *rw = (const uint32_t *)(dp.in + dp.off_runbits);
   const uint32_t k = kpar[c];
   uint64_t b = start;   // next Huffman bit position
+  // the one bits of the current word gather in acc; a word wholly inside
+  // the chunk is this thread's alone (a plain store), the two it may share
+  // with the chunks beside it take an atomic OR
+  uint64_t cw = 0;
+  uint32_t acc = 0;
+  auto flush = [&]() {
+    if (!acc) return;
+    if (cw * 32 >= start && cw * 32 + 32 <= end) dp.hbits[cw] = acc;
+    else atomicOr(&dp.hbits[cw], acc);
+  };
   while (pos < rend) {
     uint64_t q = 0;
     for (;;) {   // the unary part, up to 32 bits a step
@@ -417,10 +428,16 @@ __global__ __launch_bounds__(256) void k_dec_runs(DecBatch db) {
       bad = true;
       break;
     }
-    atomicOr(&dp.hbits[b >> 5], 0x80000000u >> (b & 31));
+    if ((b >> 5) != cw) {
+      flush();
+      cw = b >> 5;
+      acc = 0;
+    }
+    acc |= 0x80000000u >> (b & 31);
     b++;
   }
   if (bad) corrupt(dp.status);
+  else flush();
 }
 
 // One wave per chunk.  The chunk's bits split into 64 equal slices; lane i
