@@ -887,13 +887,6 @@ __global__ __launch_bounds__(64) void k_dec_roi_tables(DecBatch db) {
   }
 }
 
-// 32 stream bits from bit pos (zeros past the last word).
-__device__ __forceinline__ uint32_t roi_peek(const uint32_t *words, uint64_t nwords, uint64_t pos) {
-  const uint64_t i = pos >> 5;
-  const uint64_t w0 = i < nwords ? words[i] : 0u, w1 = i + 1 < nwords ? words[i + 1] : 0u;
-  return (uint32_t)((((w0 << 32) | w1) << (pos & 31)) >> 32);
-}
-
 // One lane per window: decode its classes and raw bits into the zigzag
 // residuals, written as r (mod 2^32) to roi_payload.  A window must start at
 // its offset (the first at 0) and end exactly at the next offset, the last
@@ -938,8 +931,10 @@ __global__ __launch_bounds__(256) void k_dec_roi_decode(DecBatch db) {
   const uint64_t ww = (uint64_t)dp.w * dp.w;
   uint32_t *out = dp.roi_payload + k * ww;
   uint64_t pos = start;
+  BitWindow win;   // the window's bits through registers, 4 words a load
+  win.init(words, nwords, start);
   for (uint64_t e = 0; e < ww; ++e) {
-    const uint32_t peek = roi_peek(words, nwords, pos);
+    const uint32_t peek = win.peek(pos);
     const uint32_t hit = s_lut[peek >> (32 - kRoiLutBits)];
     int cls = -1, L = 1;
     if (hit) {
@@ -967,7 +962,7 @@ __global__ __launch_bounds__(256) void k_dec_roi_decode(DecBatch db) {
         corrupt(dp.status);
         return;
       }
-      z = (1u << extra) | (roi_peek(words, nwords, pos) >> (32 - extra));
+      z = (1u << extra) | (win.peek(pos) >> (32 - extra));
       pos += extra;
     }
     out[e] = (z >> 1) ^ (0u - (z & 1u));
