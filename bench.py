@@ -253,8 +253,8 @@ def coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_s
 
 def peaks_section(args, torch, frames, prm, raw_bytes, tile_rows, tile_strips):
     """Peak finding on the GPU over the same batch (the step before the path,
-    Sec. V-A parameters), and the frames-in, streams-out pipeline: peaks found,
-    counts read back, frames with fewer than 10 peaks rejected (Sec. IV-B),
+    Sec. IV-B parameters), and the frames-in, streams-out pipeline: peaks found,
+    counts read back, frames with fewer than 10 peaks rejected (Sec. IV),
     the hits compressed with their found peaks."""
     import numpy as np
     from paper_2206_11297_amd import rsz

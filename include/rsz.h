@@ -105,14 +105,19 @@ typedef enum {
   RSZ_ERR_HIP = -7        /* HIP runtime error                             */
 } rsz_status;
 
-/* Human-readable name of a status value (static string). */
+/* Human-readable name of a status value (static string).  A diagnostic of
+ * this library's status codes; no passage of the paper defines it. */
 const char *rsz_status_string(int status);
 
 /* Upper bound of the compressed size of one frame with npeaks peaks (every
- * bin an outlier and every codeword 32 bits).  Host-only. */
+ * bin an outlier and every codeword 32 bits).  Host-only.  With the workspace
+ * query below it lets the caller preallocate every buffer, so compression
+ * itself allocates nothing (the zero-allocation compression into
+ * preallocated buffers of Sec. IV-A). */
 int rsz_max_compressed_bytes(const rsz_params *p, uint32_t npeaks, uint64_t *bytes);
 
-/* Device workspace needed by rsz_compress for one frame.  Host-only. */
+/* Device workspace needed by rsz_compress for one frame (preallocated by the
+ * caller, Sec. IV-A).  Host-only. */
 int rsz_workspace_bytes(const rsz_params *p, uint32_t npeaks, uint64_t *bytes);
 
 /* Compress one device-resident frame (Sec. IV: ROI extraction, binning,
@@ -147,13 +152,17 @@ typedef struct {
   uint64_t out_cap;
 } rsz_frame_desc;
 
-/* Device workspace for rsz_compress_batch over these descriptors.  Host-only.
- * Descriptors with invalid parameters are sized as empty. */
+/* Device workspace for rsz_compress_batch over these descriptors (preallocated
+ * by the caller, Sec. IV-A).  Host-only.  Descriptors with invalid parameters
+ * are sized as empty. */
 int rsz_batch_workspace_bytes(uint32_t nframes, const rsz_frame_desc *h_descs,
                               uint64_t *bytes);
 
 /* Compress nframes frames in one batched launch sequence (every step of the
- * path is one kernel launch over all frames).  h_descs is host memory and may
+ * path is one kernel launch over all frames): the GPU form of compressing a
+ * chunk of several events per compressor invocation (Sec. V-C, "Choice of
+ * Chunk Size"), where each frame keeps its own self-contained stream so that
+ * single events stay accessible.  h_descs is host memory and may
  * be reused once the call returns.  Per-frame results go to device arrays:
  * d_out_bytes[i] (stream size, or the size needed on RSZ_ERR_CAPACITY) and
  * d_status[i] (an rsz_status).  Asynchronous: returns after queueing; the
@@ -188,7 +197,9 @@ int rsz_graph_launch(void *graph_exec, void *stream);
 int rsz_graph_destroy(void *graph_exec);
 
 /* Parse and check the 80-byte header of a stream held in host memory
- * (h_stream, n >= 80 bytes).  Fills *p, *npeaks and *stream_bytes.
+ * (h_stream, n >= 80 bytes).  The container is this library's own format (the
+ * paper composes its stages through LibPressio, Sec. IV, and fixes no byte
+ * layout).  Fills *p, *npeaks and *stream_bytes.
  * Returns RSZ_ERR_CORRUPT for a malformed header.  Host-only. */
 int rsz_stream_info(const void *h_stream, uint64_t n, rsz_params *p, uint32_t *npeaks,
                     uint64_t *stream_bytes);
@@ -236,7 +247,7 @@ int rsz_decompress_batch(uint32_t n, const rsz_decode_desc *h_descs, int32_t *d_
 
 /* ---- Peak finding: the step before the path, feeding the peak list ---- */
 
-/* Peak-finder parameters (Sec. V-A: local maxima of a 7x7 window, maxima
+/* Peak-finder parameters (Sec. IV-B: local maxima of a 7x7 window, maxima
  * below 300 ADU rejected, the peak's pixels above 0 ADU, total intensity
  * above 600 ADU, signal to noise above 10, 2 to 30 peak pixels).  A pixel is
  * a peak when:
@@ -281,7 +292,7 @@ int rsz_find_peaks_workspace_bytes(uint32_t nframes, const rsz_peak_desc *h_desc
  * d_counts[i] receives the number of peaks of frame i and d_status[i] its
  * status: RSZ_OK, RSZ_ERR_ARG (invalid descriptor) or RSZ_ERR_CAPACITY (more
  * than max_peaks peaks; the count is still reported and the list is
- * unspecified).  Non-hit rejection (Sec. IV-B: fewer than 10 peaks) is the
+ * unspecified).  Non-hit rejection (Sec. IV: fewer than 10 peaks) is the
  * caller's comparison of d_counts.  Asynchronous like rsz_compress_batch;
  * the return value reports errors of the call itself (ARG, WORKSPACE, HIP). */
 int rsz_find_peaks_batch(const rsz_peak_params *q, uint32_t nframes, const rsz_peak_desc *h_descs,

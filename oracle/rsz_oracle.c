@@ -24,7 +24,7 @@
  *     design notes (radius 512, chunk 4096, tie-breaks, container layout).
  *   - Compression ratio is relative to raw uint16 detector bytes (Sec. IV).
  *   - The peak list can also come from the peak finder at the end of this
- *     file (Sec. V-A's peak_finder_v3 parameters), the step before the path.
+ *     file (Sec. IV-B's peak_finder_v3 parameters), the step before the path.
  *
  * Arithmetic: fp64 sums in raster order, a correctly rounded divide and
  * rint() (round half to even).  Build with -ffp-contract=off and without
@@ -32,8 +32,12 @@
  *
  * Parity pins (tests): brute-force masks, numpy sums, the closed-form
  * reconstruction, prefix-sum inverse of the Lorenzo step, an independent heap
- * Huffman cost, Kraft sums, brute-force optimality on tiny alphabets and a
- * hand-derived stream fixture.  Nothing here is "parity unpinned".
+ * Huffman cost, Kraft sums, brute-force optimality on tiny alphabets and
+ * hand-derived stream fixtures.  The Huffman build's three stated rules
+ * (equal counts taken in symbol order, a leaf winning a tie with an internal
+ * node, floor-halving of the counts when a length exceeds 32) decide the code
+ * lengths among several optimal ones; each has a hand-derived fixture that
+ * fails when the rule is changed.
  */
 #include <math.h>
 #include <stdint.h>
@@ -1097,8 +1101,8 @@ int ro_decompress(const uint8_t *in, uint64_t in_bytes, float *frame, uint64_t f
 
 /* ------------------------------------------------------------ peak finding */
 
-/* Peak finder feeding the ROI mask (the step before the path: Sec. V-A names
- * the algorithm and its parameters; Sec. II and Sec. IV-B the non-hit
+/* Peak finder feeding the ROI mask (the step before the path: Sec. IV-B names
+ * the algorithm and its parameters; Sec. II and Sec. IV the non-hit
  * rejection that counts its peaks).  Readings where the text is loose:
  *   - local maximum: the pixel is >= every pixel of its (2h+1)^2 window
  *     (clipped to the panel) and > every one before it in raster order, so

@@ -1,6 +1,6 @@
 // peaks.hip -- peak finding on the GPU: the step before the compression path,
-// producing the peak list whose windows form the ROI mask (Sec. V-A names
-// peak_finder_v3 and its parameters; non-hit rejection, Sec. IV-B, counts
+// producing the peak list whose windows form the ROI mask (Sec. IV-B names
+// peak_finder_v3 and its parameters; non-hit rejection, Sec. IV, counts
 // these peaks).
 //
 // k_peaks_init  zeroes each frame's peak counter.

@@ -542,7 +542,7 @@ class Batch:
 
 
 def peak_params(**kw):
-    """rsz_peak_params with the library defaults (Sec. V-A values), fields
+    """rsz_peak_params with the library defaults (Sec. IV-B values), fields
     overridden by keyword."""
     q = rsz_peak_params()
     lib().rsz_peak_params_default(C.byref(q))
@@ -617,7 +617,7 @@ def find_peaks(frame, q=None, max_peaks=4096):
 
 def compress_hits(frames, prm, q=None, min_peaks=10, max_peaks=4096, **batch_kw):
     """Frames in, streams out: peaks found on the GPU, non-hit rejection
-    (frames with fewer than min_peaks peaks are dropped, Sec. IV-B), then the
+    (frames with fewer than min_peaks peaks are dropped, Sec. IV), then the
     hits compressed in one batch with their found peaks as the ROI.  Returns
     (indices of the hits, the Batch holding their streams, the PeakBatch)."""
     torch = _torch()

@@ -133,7 +133,7 @@ def test_struct_layouts_match_the_header(tmp_path):
 
 
 def test_peak_params_default_and_checks():
-    """Library defaults are the paper's values (Sec. V-A) and equal the
+    """Library defaults are the paper's values (Sec. IV-B) and equal the
     oracle's; bad parameters and descriptors are rejected before any launch."""
     q = rsz.peak_params()
     o = O.peak_params()

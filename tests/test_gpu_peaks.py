@@ -1,5 +1,5 @@
-"""GPU parity of the peak finder (the step before the path, Sec. V-A) and of
-the frames-in, streams-out pipeline with non-hit rejection (Sec. IV-B),
+"""GPU parity of the peak finder (the step before the path, Sec. IV-B) and of
+the frames-in, streams-out pipeline with non-hit rejection (Sec. IV),
 through the C ABI, against the oracle: peak lists (raster order) and counts
 bit for bit, statuses, and the streams of the hits."""
 from concurrent.futures import ThreadPoolExecutor

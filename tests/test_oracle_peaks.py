@@ -1,6 +1,6 @@
-"""Pins of the oracle's peak finder (Sec. V-A's peak_finder_v3 parameters:
+"""Pins of the oracle's peak finder (Sec. IV-B's peak_finder_v3 parameters:
 7x7 local maxima, maximum >= 300 ADU, total > 600 ADU, signal to noise > 10,
-2-30 peak pixels; non-hit rejection below 10 peaks, Sec. IV-B).
+2-30 peak pixels; non-hit rejection below 10 peaks, Sec. IV).
 
 An independent definition is written here with numpy and scipy: window
 maxima by explicit comparison, the peak pixels as the 4-connected component

@@ -285,6 +285,100 @@ def test_huffman_single_symbol_and_length_limit():
     assert lens.max() <= 32
 
 
+HUFF_LIMIT = os.path.join(os.path.dirname(__file__), "golden", "huffman", "length_limit.json")
+
+
+def test_huffman_tie_rules_hand_derived():
+    """Equal counts go in symbol order and a leaf wins a tie with a node (the
+    two hand-derived fixtures in tests/golden), here on the histograms alone."""
+    hist = np.zeros(1024, np.uint32)
+    hist[[512, 513, 514]] = 1
+    lens = O.huffman_lengths(hist)
+    assert [int(lens[s]) for s in (512, 513, 514)] == [2, 2, 1]
+    hist = np.zeros(1024, np.uint32)
+    hist[[512, 513, 514, 515]] = [1, 1, 2, 2]
+    lens = O.huffman_lengths(hist)
+    assert [int(lens[s]) for s in (512, 513, 514, 515)] == [2, 2, 2, 2]
+    # the same shapes on other symbols: only the order of the symbols matters
+    hist = np.zeros(1024, np.uint32)
+    hist[[3, 700, 1000]] = 5
+    lens = O.huffman_lengths(hist)
+    assert [int(lens[s]) for s in (3, 700, 1000)] == [2, 2, 1]
+
+
+def _trace_depths(lines, prefix):
+    """Leaf depths from a written-out merge trace ("merge k: a(x) + b(y) ->
+    nk=z"), checking every sum on the way."""
+    import re
+    parent, weight, last = {}, {}, None
+    pat = re.compile(r"merge \d+: (\w+)\((\d+)\) \+ (\w+)\((\d+)\) -> (\w+)=(\d+)$")
+    for line in lines:
+        if not line.startswith(prefix):
+            continue
+        a, x, b, y, n, z = pat.match(line[len(prefix):]).groups()
+        assert int(x) + int(y) == int(z), line
+        for name, wt in ((a, x), (b, y)):
+            if name.startswith("n"):
+                assert weight[name] == int(wt), line
+            parent[name] = n
+        weight[n] = int(z)
+        last = n
+
+    def depth(k):
+        d = 0
+        while k != last:
+            k, d = parent[k], d + 1
+        return d
+    return {int(k[1:]): depth(k) for k in parent if k.startswith("s")}
+
+
+def test_huffman_length_limit_hand_derived():
+    """Fibonacci counts on 34 symbols: the first build is 33 deep, the counts
+    are floor-halved (kept >= 1) and the rebuild gives the written-out lengths
+    (tests/golden/huffman/length_limit.json, merge traces in full)."""
+    g = json.load(open(HUFF_LIMIT))
+    syms, counts = g["symbols"], g["counts"]
+    assert g["halved_counts"] == [max(1, c >> 1) for c in counts]
+    first = _trace_depths(g["derivation"], "first build ")
+    assert max(first.values()) == g["max_length_first_build"] == 33
+    second = _trace_depths(g["derivation"], "second build ")
+    assert {str(s): d for s, d in second.items()} == g["lengths"]
+    hist = np.zeros(1024, np.uint32)
+    hist[syms] = counts
+    lens = O.huffman_lengths(hist)
+    assert {str(s): int(lens[s]) for s in syms} == g["lengths"]
+    assert int(lens.sum()) == sum(g["lengths"].values())
+    _check_code(hist, lens)
+
+
+def limit_frame():
+    """A 37 x 113 x 3571 frame (F(36) - 1 bins) whose dimension-1 codes at
+    eb = 0.5 have exactly the Fibonacci counts of the length-limit fixture:
+    the residuals in a seeded order, q their running sum, x = q."""
+    g = json.load(open(HUFF_LIMIT))
+    r = np.repeat(np.array(g["symbols"], np.int64) - 512, g["counts"])
+    assert r.size == 37 * 113 * 3571
+    np.random.default_rng([2206, 11297, 34]).shuffle(r)
+    q = np.cumsum(r)
+    assert np.abs(q).max() < 2 ** 24
+    return g, q.astype(np.float32).reshape(37, 113, 3571)
+
+
+def test_huffman_length_limit_through_the_stream():
+    g, frame = limit_frame()
+    p = O.params(37, 113, 3571, 1, 1, 0.5, dim=1)
+    st, stream, n = O.compress(p, frame, np.zeros((0, 3), np.int32))
+    assert st == O.OK
+    d = F.parse(stream)
+    lens = np.frombuffer(stream.tobytes(), np.uint8, 1024, d["off"]["lens"])
+    assert {str(s): int(lens[s]) for s in g["symbols"]} == g["lengths"]
+    assert int(lens.sum()) == sum(g["lengths"].values())
+    assert d["T"] == sum(c * g["lengths"][str(s)] for s, c in zip(g["symbols"], g["counts"]))
+    st, y = O.decompress(stream)
+    assert st == O.OK
+    np.testing.assert_array_equal(y, frame)
+
+
 # ------------------------------------------------------------ special cases
 
 
