@@ -113,15 +113,27 @@ static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap, uint
 }
 
 struct Layout {
-  uint64_t plans, prefix, states, frames_begin, total;
+  uint64_t plans, prefix, cframe, states, frames_begin, total;
   std::vector<uint64_t> frame_off;  // per frame start of its private region
 };
+
+// Bytes of one binning tile's region of sparse code bytes: room for every
+// bin of the tile, in whole 128-byte lines.
+static uint32_t tile_cap(const Geom &g) {
+  return (uint32_t)align_up(64ull * g.TH * g.gstrips, 128);
+}
 
 static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const Geom &g) {
   uint64_t b = 0;
   b += align_up(4ull * ((uint64_t)p->panels * g.segs + 1), 256);  // bstart
   b += align_up(4ull * npeaks, 256);                              // bucket
-  b += align_up(1ull * kChunk * g.nchunks, 256);  // code bytes, padded to whole chunks
+  // code bytes (dense, then the chunk form), whole chunks and 32 bytes past the
+  // last; the chunk form's masks
+  b += align_up(1ull * kChunk * g.nchunks + 32, 256) + align_up(512ull * g.nchunks, 256);
+  if (p->dim != 3) {   // sparse codes: zero-map words, counts, bytes per binning tile
+    const uint64_t nt = (uint64_t)p->panels * g.cgs * g.segs, ne = nt * kTileEntries;
+    b += align_up(8ull * ne, 256) + align_up(2ull * ne, 256) + align_up(nt * tile_cap(g), 256);
+  }
   b += align_up(4ull * g.nbins, 256);          // rbuf
   b += align_up(4ull * g.nbins, 256);          // obuf
   b += 3 * align_up(4ull * g.nchunks, 256);    // chunk_off, chunk_oo, head
@@ -142,7 +154,12 @@ static Layout layout(uint32_t nframes, const std::vector<const rsz_params *> &ps
   Layout L;
   L.plans = 0;
   L.prefix = align_up(sizeof(FramePlan) * nframes, 256);
-  L.states = L.prefix + align_up(5 * 4ull * (nframes + 1), 256);
+  // frame of each k_count workgroup's first chunk
+  uint64_t chunks = 0;
+  for (uint32_t f = 0; f < nframes; ++f)
+    if (valid[f]) chunks += gs[f].nchunks;
+  L.cframe = L.prefix + align_up(5 * 4ull * (nframes + 1), 256);
+  L.states = L.cframe + align_up(4 * div_up(chunks, kWaves) + 4, 256);
   L.frames_begin = L.states + align_up(sizeof(FrameState) * nframes, 256);
   uint64_t off = L.frames_begin;
   L.frame_off.resize(nframes);
@@ -234,15 +251,13 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   uint32_t *kp = rp + (nframes + 1);
   uint32_t *xp = kp + (nframes + 1);
   uint64_t tiles = 0, units = 0, npk_total = 0, all_chunks = 0, chunks_done = 0, fixes = 0;
+  bool all_vec = true;
   for (uint32_t f = 0; f < nframes; ++f)
     if (valid[f]) all_chunks += gs[f].nchunks;
   // chunks per encode workgroup (its waves take every kWaves-th chunk): a
   // multiple of kWaves, about 8192 workgroups for large batches
-  const bool enc_block = all_chunks < kBlockEncodeChunks;
-  const uint32_t cpw =
-      enc_block ? 1u
-                : kWaves * (uint32_t)std::min<uint64_t>(
-                               8, std::max<uint64_t>(1, all_chunks / (8192 * kWaves)));
+  const uint32_t cpw = kWaves * (uint32_t)std::min<uint64_t>(
+                                    8, std::max<uint64_t>(1, all_chunks / (8192 * kWaves)));
   for (uint32_t f = 0; f < nframes; ++f) {
     FramePlan &fp = fpl[f];
     memset(&fp, 0, sizeof fp);
@@ -284,6 +299,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.init_status = RSZ_OK;
     fp.vec = (p->bin == 2 || p->bin == 4) && p->width % p->bin == 0 &&
              (uintptr_t)d[f].frame % (4 * p->bin) == 0;
+    all_vec = all_vec && fp.vec;
     fp.inv[0] = 0.0;
     for (uint32_t n = 1; n <= 64; ++n) fp.inv[n] = 1.0 / ((double)n * fp.step);
     fp.frame = d[f].frame;
@@ -299,8 +315,25 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     base += align_up(4ull * ((uint64_t)p->panels * g.segs + 1), 256);
     fp.bucket = (uint32_t *)base;
     base += align_up(4ull * np[f], 256);
+    fp.sparse = fp.dim != 3;
+    if (fp.sparse) {
+      const uint64_t nt = (uint64_t)p->panels * g.cgs * g.segs, ne = nt * kTileEntries;
+      fp.tile_cap = tile_cap(g);
+      fp.fd_Wb = fast_div(g.Wb);
+      fp.fd_Hb = fast_div(g.Hb);
+      fp.fd_TH = fast_div(g.TH);
+      fp.fd_gs = fast_div(g.gstrips);
+      fp.zm = (uint64_t *)base;
+      base += align_up(8ull * ne, 256);
+      fp.zp = (uint16_t *)base;
+      base += align_up(2ull * ne, 256);
+      fp.zb = base;
+      base += align_up(nt * fp.tile_cap, 256);
+    }
     fp.codes = base;
-    base += align_up(1ull * kChunk * g.nchunks, 256);
+    base += align_up(1ull * kChunk * g.nchunks + 32, 256);
+    fp.cmask = (uint64_t *)base;
+    base += align_up(512ull * g.nchunks, 256);
     fp.rbuf = (int32_t *)base;
     base += align_up(4ull * g.nbins, 256);
     fp.obuf = (uint32_t *)base;
@@ -379,7 +412,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   hp.bp.total_units = (uint32_t)units;
   hp.bp.total_peaks = (uint32_t)npk_total;
   hp.bp.cpw = cpw;
-  hp.bp.enc_block = enc_block ? 1u : 0u;
+  hp.bp.all_vec = all_vec ? 1u : 0u;
   hp.bp.frames = (const FramePlan *)(ws + L.plans);
   hp.bp.tile_prefix = (const uint32_t *)(ws + L.prefix);
   hp.bp.unit_prefix = hp.bp.tile_prefix + (nframes + 1);
@@ -387,6 +420,17 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   hp.bp.chunk_prefix = hp.bp.peak_prefix + (nframes + 1);
   hp.bp.fix_prefix = hp.bp.chunk_prefix + (nframes + 1);
   hp.bp.total_fix = (uint32_t)fixes;
+  uint32_t *cf = (uint32_t *)(hp.bytes.data() + L.cframe);
+  uint32_t fr = 0;
+  for (uint64_t w = 0; w < div_up(chunks_done, kWaves); ++w) {
+    while (kp[fr + 1] <= w * kWaves) ++fr;
+    cf[w] = fr;
+  }
+  hp.bp.count_frame = (const uint32_t *)(ws + L.cframe);
+  bool all_sparse = true;
+  for (uint32_t f = 0; f < nframes; ++f)
+    if (valid[f] && fpl[f].dim == 3) all_sparse = false;
+  hp.bp.all_sparse = all_sparse ? 1u : 0u;
   return RSZ_OK;
 }
 

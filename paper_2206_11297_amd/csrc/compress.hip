@@ -37,6 +37,25 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The plan's pointers are generic; the path's buffers are all device (global)
+// memory, and accesses through an address_space(1) pointer compile to global
+// loads and stores.  Generic (flat) ones would also count against the LDS
+// wait counter, so every LDS wait would wait for the HBM loads in flight too.
+#define RSZ_G __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ RSZ_G T *gm(T *p) {
+  return (RSZ_G T *)p;
+}
+// Plain vector types for such accesses (loads and stores of 8 and 16 bytes).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld16(const void *p) {
+  const u32x4 v = *gm((const u32x4 *)p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // Frame owning flat work item `item`: the largest f with prefix[f] <= item.
 __device__ __forceinline__ uint32_t find_frame(const uint32_t *prefix, uint32_t nframes,
                                                uint32_t item) {
@@ -251,11 +270,11 @@ __device__ __forceinline__ void load_bin(BinPix<BB> &px, const float *__restrict
     const float *row = fr + (size_t)i * W;
     const uint32_t j0 = Jc * b;
     if constexpr (VEC && BB == 2) {
-      const float2 x = *(const float2 *)(row + j0);
+      const f32x2 x = *gm((const f32x2 *)(row + j0));
       px.v[di][0] = x.x;
       px.v[di][1] = x.y;
     } else if constexpr (VEC && BB == 4) {
-      const float4 x = *(const float4 *)(row + j0);
+      const f32x4 x = *gm((const f32x4 *)(row + j0));
       px.v[di][0] = x.x;
       px.v[di][1] = x.y;
       px.v[di][2] = x.z;
@@ -264,7 +283,7 @@ __device__ __forceinline__ void load_bin(BinPix<BB> &px, const float *__restrict
 #pragma unroll
       for (int dj = 0; dj < NB; ++dj) {
         if (!BB && dj >= b) break;
-        px.v[di][dj] = row[min(j0 + dj, W - 1)];
+        px.v[di][dj] = *gm(row + min(j0 + dj, W - 1));
       }
     }
     if constexpr (BG) {
@@ -336,11 +355,11 @@ __device__ __forceinline__ void load_vec(BinPix<BB> &px, const float *__restrict
     const uint32_t i = min(I * BB + di, H - 1);
     const char *row = (const char *)(fr + (size_t)i * W);
     if constexpr (BB == 2) {
-      const float2 x = *(const float2 *)(row + lofs);
+      const f32x2 x = *gm((const f32x2 *)(row + lofs));
       px.v[di][0] = x.x;
       px.v[di][1] = x.y;
     } else {
-      const float4 x = *(const float4 *)(row + lofs);
+      const f32x4 x = *gm((const f32x4 *)(row + lofs));
       px.v[di][0] = x.x;
       px.v[di][1] = x.y;
       px.v[di][2] = x.z;
@@ -424,6 +443,28 @@ __device__ __forceinline__ void build_mask(const FramePlan &fp, uint32_t p, uint
   wave_sync();
 }
 
+// Sparse codes of one binning tile, staged so that they reach HBM as whole
+// cache lines: the tile's zero-map words and byte counts (one per tile row
+// and strip) collect in lanes of a few registers and are stored when the
+// tile ends; its code bytes other than 128 go through an LDS ring, written
+// 256 at a time.  Partial lines written a few bytes at a time, as a row's
+// scattered stores would be, cost far more than the bytes they carry.
+constexpr uint32_t kZbRing = 512;
+constexpr uint32_t kZbFlush = 256;   // <= kZbRing - 4 * 64: a row adds at most 256
+struct SparseStage {
+  uint8_t zb[kZbRing];
+};
+
+// Writes the ring's bytes [from, to) of the tile (from a multiple of 8, both
+// within kZbRing of each other) to zb, 8 bytes a lane; the last 8-byte group
+// may carry bytes past `to` (the tile's region holds whole groups).
+__device__ __forceinline__ void flush_zb(const SparseStage &stg, uint8_t *zb, uint32_t from,
+                                         uint32_t to) {
+  const int lane = threadIdx.x & 63;
+  for (uint32_t o = from + 8u * lane; o < to; o += 512u)
+    *gm((u32x2 *)(zb + o)) = *(const u32x2 *)(stg.zb + (o & (kZbRing - 1)));
+}
+
 // Strips of a row whose loads are issued together.
 template <int BB>
 constexpr int strips_in_flight() {
@@ -446,7 +487,7 @@ constexpr int strips_in_flight() {
 template <int BB, bool VEC, bool BG, bool DEBUG, int DIM>
 __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32_t seg,
                                          uint32_t cg, uint32_t *hist, uint32_t *mask,
-                                         const double *inv) {
+                                         const double *inv, SparseStage *stg) {
   constexpr int G = strips_in_flight<BB>();
   constexpr int NS = group_strips(BB);
   const int lane = threadIdx.x & 63;
@@ -472,6 +513,13 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
   double Sd;
   uint32_t nd;
   const uint32_t dim = DIM ? (uint32_t)DIM : fp.dim;
+  // sparse codes (dimensions 1 and 2): the tile's entries and byte region
+  const bool sparse = DIM ? DIM != 3 : fp.sparse != 0;
+  const uint32_t tix = (p * fp.cgs + cg) * fp.segs + seg;
+  const uint32_t gsl = fp.gstrips;   // strips of a column group
+  uint32_t zcount = 0, zflushed = 0;
+  // entry (strip s, tile row i) sits in lane (s & 1) * 32 + i of pair s >> 1
+  uint32_t zmlo[2] = {0u, 0u}, zmhi[2] = {0u, 0u}, zpv[2] = {0u, 0u};
   if (BG || (DEBUG && fp.dbg_mask)) {
     build_mask(fp, p, mask, R0, mrows, Cm, wpr);
     if (DEBUG && fp.dbg_mask) {
@@ -519,18 +567,9 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
       q_up[s] = J0 + s * 64 + lane < Wb ? qh : 0;
     }
   }
-  // per strip, loop-invariant: the lane's load offset (vector path) and its
-  // mask word in LDS
-  uint32_t lofs[NS];
-  const uint32_t *mlane[NS];
   uint64_t vmask[NS];   // lanes of strip s inside the panel
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const uint32_t jc = RSZ_JC(s < ns ? s : 0);
-    lofs[s] = jc * (uint32_t)b * 4u;
-    mlane[s] = mask + RSZ_MW(jc);
-    vmask[s] = __builtin_amdgcn_uicmp(J0 + s * 64 + lane, Wb, 36 /* ult */);
-  }
+  for (int s = 0; s < NS; ++s) vmask[s] = __builtin_amdgcn_uicmp(J0 + s * 64 + lane, Wb, 36 /* ult */);
   // ql_up[s]: left neighbours of the row above (row I0 - 1 to start)
   int32_t ql_up[NS];
   {
@@ -559,6 +598,25 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
       if (s == ns - 1) v = q_up[s];
     lastq = __builtin_amdgcn_readlane(v, lastlane);
   }
+  // The strips of a row are loaded together; each strip's registers take the
+  // next row's loads as soon as the strip is reduced, so that they are in
+  // flight while the rest of the row is computed.
+  static_assert(G == NS, "one group of strips per row");
+  BinPix<BB> px[NS];
+#define RSZ_LOAD(s, Irow)                                                                   \
+  do {                                                                                      \
+    if constexpr (VEC) {                                                                    \
+      const uint32_t jv_ = RSZ_JC(s);                                                       \
+      load_vec<BB, BG>(px[s], fr, H, W, (Irow), jv_ * (uint32_t)b * 4u, mask + RSZ_MW(jv_), \
+                       R0, wpr);                                                            \
+    } else {                                                                                \
+      const uint32_t jc_ = RSZ_JC(s);                                                       \
+      load_bin<BB, VEC, BG>(px[s], fr, H, W, b, (Irow), jc_, mask, R0, wpr, RSZ_MW(jc_));  \
+    }                                                                                       \
+  } while (0)
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    if (s < ns) RSZ_LOAD(s, I0);
   for (uint32_t I = I0; I < I1; ++I) {
     // q left of the group on this row
     int32_t left = __builtin_amdgcn_readlane(q_left, I - I0 + 1);
@@ -566,47 +624,60 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
     // in-panel pixels of this bin row (vector path: every column is)
     uint32_t rowbits = 0;
     if constexpr (VEC) rowbits = (1u << (min((uint32_t)BB, H - I * BB) * BB)) - 1u;
+    {
 #pragma unroll
-    for (int s0 = 0; s0 < NS; s0 += G) {
-      if (s0 >= ns) break;
-      BinPix<BB> px[G];
-#pragma unroll
-      for (int gi = 0; gi < G; ++gi)
-        if (s0 + gi < ns) {
-          if constexpr (VEC) {
-            load_vec<BB, BG>(px[gi], fr, H, W, I, lofs[s0 + gi], mlane[s0 + gi], R0, wpr);
-          } else {
-            const uint32_t jc = RSZ_JC(s0 + gi);
-            load_bin<BB, VEC, BG>(px[gi], fr, H, W, b, I, jc, mask, R0, wpr, RSZ_MW(jc));
-          }
-        }
-#pragma unroll
-      for (int gi = 0; gi < G; ++gi) {
-        const int s = s0 + gi;
+      for (int s = 0; s < NS; ++s) {
         if (s >= ns) break;
         const uint32_t J = J0 + s * 64 + lane;
         const bool colv = J < Wb;
         const uint32_t jc = RSZ_JC(s);
         int32_t qv;
         if constexpr (VEC) {
-          qv = reduce_vec<BB, BG>(px[gi], rowbits, (int)((jc * b) & 31), inv, step, range_err,
+          qv = reduce_vec<BB, BG>(px[s], rowbits, (int)((jc * b) & 31), inv, step, range_err,
                                   DEBUG, Sd, nd);
         } else {
-          qv = reduce_bin<BB, BG>(px[gi], H, W, b, I, J, step, inv, range_err, Sd, nd,
+          qv = reduce_bin<BB, BG>(px[s], H, W, b, I, J, step, inv, range_err, Sd, nd,
                                   (int)((jc * b) & 31), mask, R0, wpr, RSZ_MW(jc));
         }
+        if (I + 1 < I1) RSZ_LOAD(s, I + 1);
         const int32_t q = colv ? qv : 0;
         const int32_t ql = from_left(q, left);
         left = __builtin_amdgcn_readlane(q, 63);
         // residual; codes 1..1023 carry r + 512, 0 marks an outlier
         const int32_t r = dim == 1 ? q - ql : q + ql_up[s] - q_up[s] - ql;
         const uint32_t code = code_from_residual(r);
-        if (colv) {
+        if (sparse) {
+          // the first bin of a row whose dimension-1 predecessor lies in
+          // another tile (k_lorenzo_dims corrects it) always goes to rbuf
+          const bool forced = dim == 1 && s == 0 && J == 0 && (!whole_rows || I == 0) &&
+                              (p | I) != 0;
+          const uint32_t cb = forced ? 0u : code_byte(r);
+          const bool nz = colv && cb != 128u;
+          const uint64_t m = __ballot(nz);
+          if (nz) {
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            stg->zb[(zcount + rank) & (kZbRing - 1)] = (uint8_t)cb;
+            if (cb == 0) *gm((int32_t *)((char *)(rbuf + (size_t)I * Wb) + J * 4u)) = r;
+          }
+          // every lane writes the same wave-uniform entry (no branch)
+          const bool here = (uint32_t)lane == (uint32_t)(s & 1) * 32u + (I - I0);
+          zmlo[s >> 1] = here ? (uint32_t)m : zmlo[s >> 1];
+          zmhi[s >> 1] = here ? (uint32_t)(m >> 32) : zmhi[s >> 1];
+          zpv[s >> 1] = here ? zcount : zpv[s >> 1];
+          zcount += (uint32_t)__builtin_popcountll(m);
+          if (DEBUG && colv) {
+            const size_t g = (size_t)I * Wb + J;
+            if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
+            if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
+            if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
+          }
+        } else if (colv) {
           const size_t g = (size_t)I * Wb + J;
           const uint32_t cb = code_byte(r);
           // row pointer (wave-uniform) + 32-bit lane offset
-          codes[(size_t)I * Wb + J] = (uint8_t)cb;
-          if (cb == 0) *(int32_t *)((char *)(rbuf + (size_t)I * Wb) + J * 4u) = r;
+          *gm(codes + (size_t)I * Wb + J) = (uint8_t)cb;
+          if (cb == 0) *gm((int32_t *)((char *)(rbuf + (size_t)I * Wb) + J * 4u)) = r;
           if (DEBUG) {
             if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
             if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
@@ -622,7 +693,27 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
     // the row's last q, for k_lorenzo_dims where it cannot be used here
     if (dim == 1 && last_group && (!whole_rows || I == Hb - 1) && lane == 0)
       fp.qedge[(size_t)p * Hb + I] = lastq;
+    if (sparse && zcount - zflushed >= kZbFlush) {
+      wave_sync();
+      flush_zb(*stg, fp.zb + (size_t)tix * fp.tile_cap, zflushed, zflushed + kZbFlush);
+      zflushed += kZbFlush;
+      wave_sync();
+    }
   }
+  if (sparse) {
+    wave_sync();
+    flush_zb(*stg, fp.zb + (size_t)tix * fp.tile_cap, zflushed, zcount);
+    uint64_t *zm = fp.zm + (size_t)tix * kTileEntries;
+    uint16_t *zp = fp.zp + (size_t)tix * kTileEntries;
+    *gm(zm + lane) = (uint64_t)zmhi[0] << 32 | zmlo[0];
+    *gm(zp + lane) = (uint16_t)zpv[0];
+    if (NS > 2 && gsl > 2) {
+      *gm(zm + 64 + lane) = (uint64_t)zmhi[1] << 32 | zmlo[1];
+      *gm(zp + 64 + lane) = (uint16_t)zpv[1];
+    }
+    wave_sync();
+  }
+#undef RSZ_LOAD
 #undef RSZ_MW
 #undef RSZ_JC
   if (lane == 0 && c512) atomicAdd(&hist[kRadius], c512);   // c512 is a wave total
@@ -633,11 +724,12 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
 // column group).  DIM: the Lorenzo dimension compiled in, or 0 for a batch
 // mixing dimensions (read per frame).  Workgroup t of a frame: panel, column
 // group, then a group of kWaves consecutive segments, one per wave.
-template <int BB, bool DEBUG, int DIM>
-__global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
+template <int BB, bool DEBUG, int DIM, bool VONLY>
+__device__ __forceinline__ void k_bin_body(BatchPlan bp) {
   __shared__ uint32_t s_hist[kNumSym];
   __shared__ uint32_t s_mask[kWaves][kMaskWords];
   __shared__ double s_inv[65];
+  __shared__ SparseStage s_stage[DIM == 3 ? 1 : kWaves];
   const uint32_t f = find_frame(bp.tile_prefix, bp.nframes, blockIdx.x);
   const FramePlan &fp = bp.frames[f];
   for (int i = threadIdx.x; i < kNumSym; i += 256) s_hist[i] = 0u;
@@ -654,22 +746,40 @@ __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
   if (ok && seg < fp.segs) {
     const bool bg = fp.mode == RSZ_BIN_BACKGROUND;
     uint32_t *mask = s_mask[wv];
+    SparseStage *stg = &s_stage[DIM == 3 ? 0 : wv];
     bool vec = false;
     if constexpr (BB == 2 || BB == 4) {
       vec = fp.vec != 0;
       if (vec) {
-        if (bg) bin_tile<BB, true, true, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv);
-        else bin_tile<BB, true, false, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv);
+        if (bg) bin_tile<BB, true, true, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv, stg);
+        else bin_tile<BB, true, false, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv, stg);
       }
     }
-    if (!vec) {
-      if (bg) bin_tile<BB, false, true, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv);
-      else bin_tile<BB, false, false, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv);
+    // VONLY: every frame of the batch takes the vector path, and the kernel
+    // holds only its registers (the scalar path needs more)
+    if (!VONLY && !vec) {
+      if (bg) bin_tile<BB, false, true, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv, stg);
+      else bin_tile<BB, false, false, DEBUG, DIM>(fp, panel, seg, cg, s_hist, mask, s_inv, stg);
     }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kNumSym; i += 256)
     if (s_hist[i]) atomicAdd(&fp.st->hist[i], s_hist[i]);
+}
+
+template <int BB, bool DEBUG, int DIM>
+__global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
+  k_bin_body<BB, DEBUG, DIM, false>(bp);
+}
+
+// Batches whose frames all take the vector path: without the scalar path's
+// registers the kernel keeps five waves per SIMD with room to spare, which
+// the compiler uses to keep more loads in flight (measured: six waves with
+// spills, or five without the bound, are both slower).
+template <int BB, int DIM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_bin_vec(
+    BatchPlan bp) {
+  k_bin_body<BB, false, DIM, true>(bp);
 }
 
 // ------------------------------------------------------- k_lorenzo_dims
@@ -708,6 +818,47 @@ __device__ __forceinline__ int32_t r_of(uint32_t byte, const int32_t *rbuf, uint
   return byte ? (int32_t)byte - 128 : rbuf[g];
 }
 
+// The 16 code bytes of bins [g0, g0 + 16) (g0 a multiple of 16) of a frame
+// with sparse codes, as the dense form would hold them: 128 where the
+// zero-map bit is clear, the stored byte where it is set; bytes past the
+// frame read 128.  The bins are taken in pieces that lie within one strip of
+// one bin row; a piece's stored bytes start at the entry's count plus the
+// set bits before the piece.
+__device__ uint4 sparse_group(const FramePlan &fp, uint32_t g0) {
+  uint32_t w[4] = {0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u};
+  const uint32_t end = min(g0 + 16u, fp.nbins);
+  for (uint32_t g = g0; g < end;) {
+    const uint32_t R = fdiv(fp.fd_Wb, g), J = g - R * fp.Wb;
+    const uint32_t pn = fdiv(fp.fd_Hb, R), I = R - pn * fp.Hb;
+    const uint32_t seg = fdiv(fp.fd_TH, I), li = I - seg * fp.TH;
+    const uint32_t st = J >> 6, a = J & 63u;
+    const uint32_t cg = fdiv(fp.fd_gs, st), ls = st - cg * fp.gstrips;
+    const uint32_t tix = (pn * fp.cgs + cg) * fp.segs + seg;
+    const size_t e = (size_t)tix * kTileEntries + ls * 32u + li;
+    const uint32_t n = min(min(64u - a, fp.Wb - J), end - g);
+    const uint64_t word = fp.zm[e];
+    uint64_t m = (word >> a) & (n == 64 ? ~0ull : (1ull << n) - 1ull);
+    if (m) {
+      const uint8_t *zb = fp.zb + (size_t)tix * fp.tile_cap + fp.zp[e] +
+                          __builtin_popcountll(word & ((1ull << a) - 1ull));
+      for (uint32_t k = 0; m; m &= m - 1, ++k) {
+        const uint32_t pos = g - g0 + (uint32_t)__builtin_ctzll(m);
+        const uint32_t sh = 8 * (pos & 3);
+        w[pos >> 2] = (w[pos >> 2] & ~(0xFFu << sh)) | ((uint32_t)zb[k] << sh);
+      }
+    }
+    g += n;
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// 16 code bytes of bins [g0, g0 + 16): the dense bytes, or the sparse form
+// expanded (the dense region is padded to whole chunks, so its 16-byte loads
+// stay inside it).
+__device__ __forceinline__ uint4 code_group(const FramePlan &fp, uint32_t g0) {
+  return fp.sparse ? sparse_group(fp, g0) : *(const uint4 *)(fp.codes + g0);
+}
+
 __global__ __launch_bounds__(256) void k_lorenzo_dims(BatchPlan bp) {
   __shared__ uint32_t s_hist[kNumSym];
   const uint32_t f = find_frame(bp.fix_prefix, bp.nframes, blockIdx.x);
@@ -719,13 +870,12 @@ __global__ __launch_bounds__(256) void k_lorenzo_dims(BatchPlan bp) {
     const uint32_t R = fp.cgs == 1 ? t * fp.Hb : t;
     if (t >= (fp.cgs == 1 ? fp.P : fp.P * fp.Hb) || R == 0) return;
     const size_t g = (size_t)R * fp.Wb;
-    const int32_t qf = r_of(fp.codes[g], fp.rbuf, (uint32_t)g);
+    // k_bin stored this bin's r = q as an escape (sparse codes: its byte is 0)
+    const int32_t qf = fp.rbuf[g];
     const int32_t prev = fp.qedge[R - 1];
     if (prev == 0) return;
     const int32_t r = qf - prev;   // |q| <= 2^28 - 1
-    const uint32_t cb = code_byte(r);
-    fp.codes[g] = (uint8_t)cb;
-    if (cb == 0) fp.rbuf[g] = r;
+    fp.rbuf[g] = r;
     const uint32_t c0 = code_from_residual(qf), c1 = code_from_residual(r);
     if (c0 != c1) {
       atomicSub(&fp.st->hist[c0], 1u);
@@ -1025,77 +1175,234 @@ constexpr uint32_t kSparseBytes = 4;
 
 // ---------------------------------------------------------------- k_count
 
-// Bits and outliers of every 4096-symbol chunk: one wave per chunk, 64 code
-// bytes per lane (the codes region is padded to whole chunks, so the 16-byte
-// loads stay inside it).  Work item = (frame, chunk) through the chunk prefix, four
-// per workgroup.
-__global__ __launch_bounds__(256) void k_count(BatchPlan bp) {
-  __shared__ uint4 s_len4[4][kNumSym / 16];   // each wave's frame code lengths
-  // the four chunks of a workgroup may span frames: each wave finds its own
+// Exclusive prefix sums over the lanes of a wave, and the wave total.
+__device__ __forceinline__ uint64_t wave_exclusive_scan(uint64_t v, uint64_t &total) {
   const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t item = blockIdx.x * 4 + wv;
-  if (item >= bp.total_chunks) return;
-  const uint32_t fw = find_frame(bp.chunk_prefix, bp.nframes, item);
-  const FramePlan &fp = bp.frames[fw];
-  if (load_status(fp.st) != RSZ_OK) return;
-  const uint32_t c = item - bp.chunk_prefix[fw];
-  const uint32_t g0 = c * kChunk + lane * 64;
-  const uint4 *cv = (const uint4 *)(fp.codes + g0);
-  uint4 v[4];
+  uint64_t x = v;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = cv[k];
-  s_len4[wv][lane] = ((const uint4 *)fp.st->lens)[lane];
-  wave_sync();
-  const uint8_t *lens = (const uint8_t *)s_len4[wv];
-  // fast path, the common case: a whole chunk with no escape byte in the
-  // wave (a zero byte is found four at a time: (x - 0x01010101) & ~x &
-  // 0x80808080 is non-zero exactly when x has one); then every code is its
-  // byte + 384 and no bin is an outlier
-  uint32_t zero = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t w4[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
-#pragma unroll
-    for (int e = 0; e < 4; ++e) zero |= (w4[e] - 0x01010101u) & ~w4[e] & 0x80808080u;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
   }
-  if ((c + 1) * kChunk <= fp.nbins && __ballot(zero != 0) == 0) {
-    const uint8_t *lb = lens + (kRadius - 128);
-    uint32_t fbits = 0;
+  total = __shfl(x, 63);
+  return x - v;
+}
+
+__device__ __forceinline__ uint32_t wave_exclusive_scan32(uint32_t v, uint32_t &total) {
+  const int lane = threadIdx.x & 63;
+  uint32_t x = v;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t w4[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
-#pragma unroll
-      for (int e = 0; e < 16; ++e) fbits += lb[(w4[e >> 2] >> (8 * (e & 3))) & 0xFFu];
-    }
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) fbits += __shfl_xor(fbits, d);
-    if (lane == 0) {
-      fp.chunk_off[c] = fbits;
-      fp.chunk_oo[c] = 0;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  total = __shfl(x, 63);
+  return x - v;
+}
+
+__device__ __forceinline__ uint64_t low_bits(uint32_t n) {
+  return n >= 64 ? ~0ull : (1ull << n) - 1ull;
+}
+
+// Position of a bin of a frame with sparse codes, for walking its bins in
+// raster order piece by piece: a piece lies in one strip (64 bin columns) of
+// one bin row.  J, I, pn: column, row and panel; seg, li: segment and row
+// within it; st, cg, ls: strip, column group and strip within the group.
+struct BinCursor {
+  uint32_t g, J, I, pn, seg, li, st, cg, ls;
+};
+
+__device__ __forceinline__ BinCursor bin_cursor(const FramePlan &fp, uint32_t g) {
+  BinCursor c;
+  c.g = g;
+  const uint32_t R = fdiv(fp.fd_Wb, g);
+  c.J = g - R * fp.Wb;
+  c.pn = fdiv(fp.fd_Hb, R);
+  c.I = R - c.pn * fp.Hb;
+  c.seg = fdiv(fp.fd_TH, c.I);
+  c.li = c.I - c.seg * fp.TH;
+  c.st = c.J >> 6;
+  c.cg = fdiv(fp.fd_gs, c.st);
+  c.ls = c.st - c.cg * fp.gstrips;
+  return c;
+}
+
+// The cursor's piece: its binning tile, entry, first column within the
+// strip, and length (at most `left` bins).
+__device__ __forceinline__ uint32_t cursor_tile(const FramePlan &fp, const BinCursor &c) {
+  return (c.pn * fp.cgs + c.cg) * fp.segs + c.seg;
+}
+__device__ __forceinline__ size_t cursor_entry(const FramePlan &fp, const BinCursor &c) {
+  return (size_t)cursor_tile(fp, c) * kTileEntries + c.ls * 32u + c.li;
+}
+__device__ __forceinline__ uint32_t cursor_len(const FramePlan &fp, const BinCursor &c,
+                                               uint32_t left) {
+  return min(min(64u - (c.J & 63u), fp.Wb - c.J), left);
+}
+
+// Moves the cursor past its piece of n bins (n = cursor_len).
+__device__ __forceinline__ void cursor_advance(const FramePlan &fp, BinCursor &c, uint32_t n) {
+  c.g += n;
+  c.J += n;
+  if (c.J < fp.Wb) {   // the next strip of the row
+    c.st++;
+    if (++c.ls == fp.gstrips) {
+      c.ls = 0;
+      c.cg++;
     }
     return;
   }
-  uint32_t bits = 0, nout = 0;
-  uint64_t esc = 0;   // this lane's bytes that defer to the residual
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t w4[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const uint32_t b = (w4[e >> 2] >> (8 * (e & 3))) & 0xFFu;
-      const bool in = g0 + k * 16 + e < fp.nbins;
-      bits += (in && b) ? lens[b + (kRadius - 128)] : 0u;
-      esc |= (uint64_t)(in && !b) << (k * 16 + e);
-    }
+  c.J = c.st = c.cg = c.ls = 0;   // the next row
+  if (++c.I == fp.Hb) {
+    c.I = c.seg = c.li = 0;
+    c.pn++;
+  } else if (++c.li == fp.TH) {
+    c.li = 0;
+    c.seg++;
   }
-  while (esc) {
-    const int e = __builtin_ctzll(esc);
-    esc &= esc - 1;
-    const uint32_t code = code_from_residual(fp.rbuf[g0 + e]);
+}
+
+// Calls f(g, n, a, tix, e) for the pieces of bins [g, end) of a frame with
+// sparse codes: a is the piece's first column within its strip, tix its
+// binning tile, e its entry.
+template <class F>
+__device__ __forceinline__ void for_pieces(const FramePlan &fp, uint32_t g, uint32_t end, F f) {
+  if (g >= end) return;
+  BinCursor c = bin_cursor(fp, g);
+  while (c.g < end) {
+    const uint32_t n = cursor_len(fp, c, end - c.g);
+    f(c.g, n, c.J & 63u, cursor_tile(fp, c), cursor_entry(fp, c));
+    cursor_advance(fp, c, n);
+  }
+}
+
+// The chunk form of the codes, which k_count leaves for k_encode: for chunk
+// c, cmask[c * 64 + j] has bit k set where bin c * 4096 + 64 j + k carries a
+// code byte other than 128 (residual 0), and those bytes follow in bin order
+// from codes + c * 4096.
+//
+// One wave per 4096-symbol chunk, four per workgroup (a workgroup's frame
+// from count_frame): the chunk form from the sparse codes of k_bin (or from
+// the dense bytes of dimension 3, compacted in place), and the chunk's bits
+// and outliers.  Lane l takes bins [64 l, 64 l + 64) of the chunk: the
+// pieces of its window are located first and their zero-map words loaded
+// together; the lane keeps its bytes in its own 64-byte LDS slot, and a wave
+// scan of the lanes' counts then places them.  SPARSE: every frame of the
+// batch has sparse codes (the kernel holds no dense path).
+template <bool SPARSE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_count(BatchPlan bp) {
+  __shared__ uint4 s_len4[kWaves][kNumSym / 16];   // each wave's frame code lengths
+  __shared__ uint8_t s_slot[kWaves][kChunk];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t item = blockIdx.x * kWaves + wv;
+  if (item >= bp.total_chunks) return;
+  // the four chunks of a workgroup may span frames: each wave finds its own
+  uint32_t fw = bp.count_frame[blockIdx.x];
+  while (bp.chunk_prefix[fw + 1] <= item) ++fw;
+  const FramePlan &fp = bp.frames[fw];
+  if (load_status(fp.st) != RSZ_OK) return;
+  const uint32_t c = item - bp.chunk_prefix[fw];
+  s_len4[wv][lane] = ((const uint4 *)fp.st->lens)[lane];
+  const uint32_t g0 = c * kChunk + lane * 64u;
+  const uint32_t end = min(g0 + 64u, fp.nbins);
+  const uint32_t nvalid = end > g0 ? end - g0 : 0u;
+  uint8_t *slot = s_slot[wv] + lane * 64;
+  uint64_t mask = 0;
+  uint32_t nz = 0, bits = 0, nout = 0;
+  const uint8_t *lens = (const uint8_t *)s_len4[wv];
+  auto take = [&](uint32_t b, uint32_t g) {
+    slot[nz++] = (uint8_t)b;
+    const uint32_t code = b ? b + (kRadius - 128) : code_from_residual(*gm(fp.rbuf + g));
     bits += lens[code];
     nout += code == 0;
+  };
+  // the bytes of one piece: m its bins, word its zero-map word
+  auto piece_bytes = [&](uint32_t g, uint32_t a, uint32_t tix, uint64_t m, uint64_t word,
+                         uint32_t zp) {
+    const uint8_t *zb = fp.zb + (size_t)tix * fp.tile_cap + zp + __builtin_popcountll(word & low_bits(a));
+    for (uint32_t k = 0; m; m &= m - 1, ++k) take(*gm(zb + k), g + (uint32_t)__builtin_ctzll(m));
+  };
+  if (SPARSE || fp.sparse) {
+    // a window of 64 bins in a row of at least 64 bins meets at most three
+    // strip pieces (the end of one strip, a row's last strip, the next row's
+    // first); their words are loaded together
+    constexpr int kP = 3;
+    uint32_t pg[kP], pa[kP], pt[kP], pnn[kP];
+    size_t pe[kP];
+    bool short_rows = false;
+    {
+      // lanes past the frame's last bin walk nothing (pnn = 0)
+      BinCursor cu = bin_cursor(fp, min(g0, fp.nbins - 1));
+      uint32_t left = nvalid;
+#pragma unroll
+      for (int i = 0; i < kP; ++i) {
+        pg[i] = cu.g;
+        pa[i] = cu.J & 63u;
+        pt[i] = cursor_tile(fp, cu);
+        pe[i] = cursor_entry(fp, cu);
+        pnn[i] = left ? cursor_len(fp, cu, left) : 0u;
+        if (pnn[i]) cursor_advance(fp, cu, pnn[i]);
+        left -= pnn[i];
+      }
+      short_rows = left != 0;
+    }
+    if (short_rows) {
+      // rows of fewer than 64 bins: piece by piece
+      wave_sync();   // lengths in LDS
+      for_pieces(fp, g0, end, [&](uint32_t gg, uint32_t n, uint32_t a, uint32_t tix, size_t e) {
+        const uint64_t word = *gm(fp.zm + e);
+        const uint64_t m = (word >> a) & low_bits(n);
+        if (!m) return;
+        mask |= m << (gg - g0);
+        piece_bytes(gg, a, tix, m, word, *gm(fp.zp + e));
+      });
+    } else {
+      uint64_t w[kP];
+      uint32_t z[kP];
+#pragma unroll
+      for (int i = 0; i < kP; ++i) {
+        w[i] = pnn[i] ? *gm(fp.zm + pe[i]) : 0ull;
+        z[i] = pnn[i] ? *gm(fp.zp + pe[i]) : 0u;
+      }
+      wave_sync();   // lengths in LDS
+#pragma unroll
+      for (int i = 0; i < kP; ++i) {
+        const uint64_t m = (w[i] >> pa[i]) & low_bits(pnn[i]);
+        if (m) {
+          mask |= m << (pg[i] - g0);
+          piece_bytes(pg[i], pa[i], pt[i], m, w[i], z[i]);
+        }
+      }
+    }
+  } else {
+    uint32_t dw[16];   // the lane's 64 bytes (the region holds whole chunks)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint4 q = ld16(fp.codes + g0 + 16 * k);
+      dw[4 * k] = q.x;
+      dw[4 * k + 1] = q.y;
+      dw[4 * k + 2] = q.z;
+      dw[4 * k + 3] = q.w;
+      const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+      mask |= (uint64_t)non_zero_residuals(w4) << (16 * k);
+    }
+    mask &= low_bits(nvalid);
+    wave_sync();   // lengths in LDS
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      for (uint32_t m = (uint32_t)(mask >> (16 * q)) & 0xFFFFu; m; m &= m - 1) {
+        const uint32_t k = (uint32_t)__builtin_ctz(m);
+        take(byte_at(dw[4 * q], dw[4 * q + 1], dw[4 * q + 2], dw[4 * q + 3], k), g0 + 16 * q + k);
+      }
   }
+  bits += (nvalid - nz) * lens[kRadius];
+  uint32_t nz_total;
+  const uint32_t rank = wave_exclusive_scan32(nz, nz_total);
+  // the chunk form (dense bytes: every load of the wave is done by now)
+  *gm(fp.cmask + (size_t)c * 64 + lane) = mask;
+  uint8_t *dst = fp.codes + (size_t)c * kChunk + rank;
+  for (uint32_t k = 0; k < nz; ++k) *gm(dst + k) = slot[k];
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
     bits += __shfl_xor(bits, d);
@@ -1139,41 +1446,93 @@ __global__ __launch_bounds__(256) void k_scan(BatchPlan bp) {
 
 // --------------------------------------------------------------- k_encode
 
-// Exclusive prefix sum over the lanes of a wave, and the wave total.
-__device__ __forceinline__ uint64_t wave_exclusive_scan(uint64_t v, uint64_t &total) {
-  const int lane = threadIdx.x & 63;
-  uint64_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint64_t y = __shfl_up(x, d);
-    if (lane >= d) x += y;
-  }
-  total = __shfl(x, 63);
-  return x - v;
-}
-
-__device__ __forceinline__ uint32_t wave_exclusive_scan32(uint32_t v, uint32_t &total) {
-  const int lane = threadIdx.x & 63;
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d);
-    if (lane >= d) x += y;
-  }
-  total = __shfl(x, 63);
-  return x - v;
-}
-
 // One workgroup per run of bp.cpw consecutive chunks of a frame; its four
 // waves take every fourth chunk, each chunk's bit and outlier offsets come
-// from k_scan, so nothing waits across waves.  A wave packs its chunk in four
-// rounds of 1024 symbols (16 per lane): a wave scan places each lane's bits,
-// the codewords are ORed into the wave's LDS words, and the complete words
-// are stored whole; the round's last partial word carries into the next.  A
-// chunk's first word, when it starts mid-word, is shared with the previous
-// chunk and goes to head[] for k_tail to merge.  The words go to fp.bw: the
-// stream's bitstream section, or a workspace buffer when the run stage codes
-// them (whose kernels take a chunk's first word from head[] themselves).
+// from k_scan, so nothing waits across waves.  The chunk's codes come in the
+// chunk form of k_count.  When residual 0's codeword is all zeros (the
+// canonical code gives it the first codeword whenever it is the only
+// shortest symbol) and the chunk's bits fit the wave's LDS words, only the
+// bins with other codes are placed: lane i takes the chunk's i-th such bin,
+// its position is the bins before it times residual 0's length plus the
+// extra length of the other codes before it (a wave scan), and its codeword
+// is ORed into the zeroed LDS words, which are stored whole.  Otherwise the
+// wave packs the chunk in four rounds of 1024 symbols (16 per lane): a wave
+// scan places each lane's bits, the codewords are ORed into the wave's LDS
+// words, and the complete words are stored whole; the round's last partial
+// word carries into the next.  A chunk's first word, when it starts
+// mid-word, is shared with the previous chunk and goes to head[] for k_tail
+// to merge.  The words go to fp.bw: the stream's bitstream section, or a
+// workspace buffer when the run stage codes them (whose kernels take a
+// chunk's first word from head[] themselves).
+// Bytes [off, off + 16) of p (p 16-byte aligned, with 32 readable bytes
+// from off rounded down to 16): two aligned loads and a byte alignment.
+__device__ __forceinline__ void load16_at(const uint8_t *p, uint32_t off, uint32_t (&y)[4]) {
+  const uint4 lo = ld16(p + (off & ~15u));
+  const uint4 hi = ld16(p + (off & ~15u) + 16);
+  const uint32_t x[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  const uint32_t q = (off >> 2) & 3u, r = off & 3u;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    uint32_t u = x[i], w = x[i + 1];
+#pragma unroll
+    for (int t = 1; t < 4; ++t)
+      if (q == (uint32_t)t) {
+        u = x[i + t];
+        w = x[i + t + 1];
+      }
+    y[i] = __builtin_amdgcn_alignbyte(w, u, r);
+  }
+}
+
+// The 16 code bytes of bins [16 i, 16 i + 16) of a chunk from its chunk form:
+// m (16 bits), the bins whose byte is not 128; their bytes in bin order from
+// cb + rank (the region holds 32 bytes past every chunk).
+__device__ __forceinline__ uint4 expand16(const uint8_t *cb, uint32_t m, uint32_t rank) {
+  uint32_t w[4] = {0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u};
+  if (m) {
+    uint32_t y[4];
+    load16_at(cb, rank, y);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if ((m >> k) & 1u) {
+        w[k >> 2] = (w[k >> 2] & ~(0xFFu << (8 * (k & 3)))) | ((y[0] & 0xFFu) << (8 * (k & 3)));
+        y[0] = __builtin_amdgcn_alignbyte(y[1], y[0], 1);
+        y[1] = __builtin_amdgcn_alignbyte(y[2], y[1], 1);
+        y[2] = __builtin_amdgcn_alignbyte(y[3], y[2], 1);
+        y[3] >>= 8;
+      }
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Position of the set bit of x with j set bits below it (x has more than j).
+__device__ __forceinline__ uint32_t select_bit(uint64_t x, uint32_t j) {
+  uint32_t w = (uint32_t)x, pos = 0;
+  const uint32_t c = __builtin_popcount(w);
+  if (j >= c) {
+    j -= c;
+    w = (uint32_t)(x >> 32);
+    pos = 32;
+  }
+#pragma unroll
+  for (uint32_t half = 16; half; half >>= 1) {
+    const uint32_t cl = __builtin_popcount(w & ((1u << half) - 1u));
+    if (j >= cl) {
+      j -= cl;
+      w >>= half;
+      pos += half;
+    }
+  }
+  return pos;
+}
+
+// ORs the L-bit codeword cw (L >= 1) into the staged words at bit p.
+__device__ __forceinline__ void or_codeword(uint32_t *stg, uint32_t p, uint32_t cw, uint32_t L) {
+  const uint64_t v = ((uint64_t)cw << (64 - L)) >> (p & 31);
+  if (v >> 32) atomicOr(&stg[p >> 5], (uint32_t)(v >> 32));
+  if ((uint32_t)v) atomicOr(&stg[(p >> 5) + 1], (uint32_t)v);
+}
+
 constexpr int kRoundSyms = 1024;
 __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
   __shared__ uint8_t s_len[kNumSym];
@@ -1209,13 +1568,61 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
     uint32_t pos = S0 & 31;     // bit position in stg[0]
     uint64_t widx = S0 >> 5;    // stream word of stg[0]
     bool first = (S0 & 31) != 0;
-    // the codes region is padded to whole chunks: the 16-byte loads stay inside
-    uint4 nx = *(const uint4 *)(fp.codes + lc * kChunk + lane * 16);
+    // the chunk form: lane j holds mask word j and the bytes before it
+    const uint8_t *cbytes = fp.codes + (size_t)lc * kChunk;
+    const uint64_t mword = *gm(fp.cmask + (size_t)lc * 64 + lane);
+    uint32_t nz_total;
+    const uint32_t wr = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mword), nz_total);
+    const uint32_t nbits = (lc + 1 < fp.nchunks ? fp.chunk_off[lc + 1] : (uint32_t)st->T) - S0;
+    const uint32_t L0 = s_len[kRadius];
+    if (s_cw[kRadius] == 0 && L0 && pos + nbits <= 32u * kRoundSyms) {
+      const uint32_t nw = (pos + nbits + 31) >> 5;
+      uint32_t extra = 0;
+      for (uint32_t i0 = 0; i0 < nz_total; i0 += 64) {
+        const uint32_t i = i0 + lane;
+        const bool valid = i < nz_total;
+        const uint32_t ic = valid ? i : nz_total - 1;
+        // the mask word holding the ic-th set bit: the last word whose
+        // count of set bits before it is <= ic
+        uint32_t wsel = 0;
+#pragma unroll
+        for (uint32_t step = 32; step; step >>= 1)
+          if ((uint32_t)__shfl((int)wr, (int)(wsel + step)) <= ic) wsel += step;
+        const uint64_t word = __shfl(mword, (int)wsel);
+        const uint32_t k = wsel * 64 + select_bit(word, ic - (uint32_t)__shfl((int)wr, (int)wsel));
+        const uint32_t g = lc * kChunk + k;
+        const uint32_t b = *gm(cbytes + ic);
+        const uint32_t code = b ? b + (kRadius - 128) : code_from_residual(*gm(fp.rbuf + g));
+        const uint32_t L = s_len[code];
+        uint32_t tx, to;
+        const uint32_t ex = extra + wave_exclusive_scan32(valid ? L - L0 : 0u, tx);
+        const uint32_t orank = oi + wave_exclusive_scan32(valid && code == 0 ? 1u : 0u, to);
+        if (valid) {
+          or_codeword(stg, pos + k * L0 + ex, s_cw[code], L);
+          if (code == 0 && orank < fp.nbins) *gm(fp.obuf + orank) = g;
+        }
+        extra += tx;
+        oi += to;
+      }
+      wave_sync();
+      for (uint32_t k = lane; k < nw; k += 64) {
+        const uint32_t v = stg[k];
+        stg[k] = 0u;
+        if (k == 0 && first) fp.head[lc] = v;
+        else if (widx + k < bcap) *gm(bw + widx + k) = v;
+      }
+      wave_sync();
+      continue;
+    }
 #pragma unroll 1
     for (int r = 0; r < kChunk / kRoundSyms; ++r) {
       const uint32_t g0 = lc * kChunk + r * kRoundSyms + lane * 16;
+      const uint32_t wi = (uint32_t)r * 16 + (lane >> 2), sh = (lane & 3) * 16;
+      const uint64_t wm = __shfl(mword, (int)wi);
+      const uint4 nx = expand16(cbytes, (uint32_t)(wm >> sh) & 0xFFFFu,
+                                (uint32_t)__shfl((int)wr, (int)wi) +
+                                    (uint32_t)__builtin_popcountll(wm & low_bits(sh)));
       const uint32_t w4[4] = {nx.x, nx.y, nx.z, nx.w};
-      if (r + 1 < kChunk / kRoundSyms) nx = *(const uint4 *)(fp.codes + g0 + kRoundSyms);
       // fast path, the common case: a whole round with no escape byte in the
       // wave, so every code is its byte + 384 and there is no outlier
       uint32_t zero = 0;
@@ -1266,7 +1673,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
             fp.head[lc] = v;
             continue;
           }
-          if (widx + k < bcap) bw[widx + k] = v;
+          if (widx + k < bcap) *gm(bw + widx + k) = v;
         }
         if (nw) first = false;
         const uint32_t carry = stg[nw];
@@ -1284,7 +1691,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
         const uint32_t g = g0 + k;
         const uint32_t b = (w4[k >> 2] >> (8 * (k & 3))) & 0xFFu;
         code[k] = g < fp.nbins ? b + (kRadius - 128) : 0xFFFFu;
-        if (g < fp.nbins && b == 0) code[k] = code_from_residual(fp.rbuf[g]);
+        if (g < fp.nbins && b == 0) code[k] = code_from_residual(*gm(fp.rbuf + g));
         if (g < fp.nbins) {
           bits += s_len[code[k]];
           nout += code[k] == 0;
@@ -1303,7 +1710,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
         if ((p & 31) + L > 32) atomicOr(&stg[(p >> 5) + 1], (uint32_t)v);
         p += L;
         if (code[k] == 0) {
-          if (q < fp.nbins) fp.obuf[q] = g0 + k;
+          if (q < fp.nbins) *gm(fp.obuf + q) = g0 + k;
           q++;
         }
       }
@@ -1316,7 +1723,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
           fp.head[lc] = v;
           continue;
         }
-        if (widx + k < bcap) bw[widx + k] = v;
+        if (widx + k < bcap) *gm(bw + widx + k) = v;
       }
       if (nw) first = false;
       const uint32_t carry = stg[nw];
@@ -1333,98 +1740,12 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
       const uint32_t v = stg[0];
       if (lane == 0) {
         if (first) fp.head[lc] = v;
-        else if (widx < bcap) bw[widx] = v;
+        else if (widx < bcap) *gm(bw + widx) = v;
       }
     }
     wave_sync();
     if (lane == 0) stg[0] = 0u;
     wave_sync();
-  }
-}
-
-// Small batches: one workgroup per run of bp.cpw chunks, all 256 threads on
-// one chunk at a time (16 symbols each), so a chunk is packed in one pass.
-// Same offsets, words and head[] protocol as k_encode.
-__global__ __launch_bounds__(256) void k_encode_block(BatchPlan bp) {
-  __shared__ uint8_t s_len[kNumSym];
-  __shared__ uint32_t s_cw[kNumSym];
-  __shared__ uint32_t s_words[kChunk + 2];
-  __shared__ uint64_t s_tmp[4];
-  __shared__ int s_ok;
-  const uint32_t f = find_frame(bp.unit_prefix, bp.nframes, blockIdx.x);
-  const FramePlan &fp = bp.frames[f];
-  const FrameState *st = fp.st;
-  if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
-  __syncthreads();
-  if (!s_ok) return;
-  for (int s = threadIdx.x; s < kNumSym; s += 256) {
-    s_len[s] = st->lens[s];
-    s_cw[s] = st->cw[s];
-  }
-  const uint32_t c0 = (blockIdx.x - bp.unit_prefix[f]) * bp.cpw;
-  const uint32_t c1 = min(c0 + bp.cpw, fp.nchunks);
-  uint8_t *o = fp.out;
-  const uint64_t cap = fp.out_cap;
-  uint32_t *bw = fp.bw;
-  const uint64_t bcap = fp.bw_cap;
-  // the codes region is padded to whole chunks: the 16-byte loads stay inside
-  uint4 n0 = make_uint4(0, 0, 0, 0);
-  if (c0 < c1) n0 = *(const uint4 *)(fp.codes + c0 * kChunk + threadIdx.x * 16);
-  for (uint32_t lc = c0; lc < c1; ++lc) {
-    const uint32_t g0 = lc * kChunk + threadIdx.x * 16;
-    const uint32_t w4[4] = {n0.x, n0.y, n0.z, n0.w};
-    if (lc + 1 < c1)   // next chunk's codes in flight while this one is packed
-      n0 = *(const uint4 *)(fp.codes + g0 + kChunk);
-    __syncthreads();   // tables loaded / previous chunk's words written out
-    uint32_t code[16];
-    uint32_t bits = 0, nout = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const uint32_t g = g0 + k;
-      const uint32_t b = (w4[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-      code[k] = g < fp.nbins ? b + (kRadius - 128) : 0xFFFFu;
-      if (g < fp.nbins && b == 0) code[k] = code_from_residual(fp.rbuf[g]);
-      if (g < fp.nbins) {
-        bits += s_len[code[k]];
-        nout += code[k] == 0;
-      }
-    }
-    uint64_t tot;
-    const uint64_t ex = block_exclusive_scan<uint64_t>(((uint64_t)nout << 32) | bits, s_tmp, tot);
-    const uint32_t S0 = fp.chunk_off[lc];
-    const uint32_t O0 = fp.chunk_oo[lc];
-    const uint32_t clen = (uint32_t)tot;
-    const uint32_t nwords = ((S0 & 31) + clen + 31) >> 5;
-    for (uint32_t k = threadIdx.x; k < nwords; k += 256) s_words[k] = 0u;
-    __syncthreads();
-    uint32_t pos = (S0 & 31) + (uint32_t)ex;
-    uint32_t oi = O0 + (uint32_t)(ex >> 32);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      if (code[k] == 0xFFFFu) continue;
-      const uint32_t L = s_len[code[k]];
-      const uint64_t v = ((uint64_t)s_cw[code[k]] << (64 - L)) >> (pos & 31);
-      atomicOr(&s_words[pos >> 5], (uint32_t)(v >> 32));
-      if ((pos & 31) + L > 32) atomicOr(&s_words[(pos >> 5) + 1], (uint32_t)v);
-      pos += L;
-      if (code[k] == 0) {
-        if (oi < fp.nbins) fp.obuf[oi] = g0 + k;
-        oi++;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && fp.off_chunks + 4ull * lc + 4 <= cap)
-      *(uint32_t *)(o + fp.off_chunks + 4ull * lc) = S0;
-    const uint32_t wlo = S0 >> 5;
-    for (uint32_t k = threadIdx.x; k < nwords; k += 256) {
-      const uint32_t v = s_words[k];
-      if (k == 0 && (S0 & 31)) {
-        fp.head[lc] = v;
-        continue;
-      }
-      const uint64_t widx = (uint64_t)wlo + k;
-      if (widx < bcap) bw[widx] = v;
-    }
   }
 }
 
@@ -2180,7 +2501,9 @@ hipError_t launch_codebook(const BatchPlan &bp, hipStream_t s) {
 __global__ __launch_bounds__(256) void k_debug_codes(BatchPlan bp, uint16_t *out) {
   const FramePlan &fp = bp.frames[0];
   for (uint32_t g = blockIdx.x * 256 + threadIdx.x; g < fp.nbins; g += gridDim.x * 256) {
-    const uint32_t b = fp.codes[g];
+    const uint4 v = code_group(fp, g & ~15u);
+    const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+    const uint32_t b = (w4[(g >> 2) & 3] >> (8 * (g & 3))) & 0xFFu;
     out[g] = (uint16_t)(b ? b + (kRadius - 128) : code_from_residual(fp.rbuf[g]));
   }
 }
@@ -2197,8 +2520,14 @@ static hipError_t launch_bin(const BatchPlan &bp, uint32_t b, hipStream_t s) {
   if (bp.total_tiles == 0) return hipSuccess;
   switch (b) {
     case 1: RSZ_LAUNCH("k_bin", (k_bin<1, DEBUG, DIM>), bp.total_tiles, s, bp); break;
-    case 2: RSZ_LAUNCH("k_bin", (k_bin<2, DEBUG, DIM>), bp.total_tiles, s, bp); break;
-    case 4: RSZ_LAUNCH("k_bin", (k_bin<4, DEBUG, DIM>), bp.total_tiles, s, bp); break;
+    case 2:
+      if (!DEBUG && bp.all_vec) RSZ_LAUNCH("k_bin", (k_bin_vec<2, DIM>), bp.total_tiles, s, bp);
+      else RSZ_LAUNCH("k_bin", (k_bin<2, DEBUG, DIM>), bp.total_tiles, s, bp);
+      break;
+    case 4:
+      if (!DEBUG && bp.all_vec) RSZ_LAUNCH("k_bin", (k_bin_vec<4, DIM>), bp.total_tiles, s, bp);
+      else RSZ_LAUNCH("k_bin", (k_bin<4, DEBUG, DIM>), bp.total_tiles, s, bp);
+      break;
     default: RSZ_LAUNCH("k_bin", (k_bin<0, DEBUG, DIM>), bp.total_tiles, s, bp); break;
   }
   return hipSuccess;
@@ -2222,11 +2551,13 @@ hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t dim
 }
 
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
-  if (bp.total_chunks) RSZ_LAUNCH("k_count", k_count, (bp.total_chunks + 3) / 4, s, bp);
+  if (bp.total_chunks) {
+    if (bp.all_sparse) RSZ_LAUNCH("k_count", k_count<true>, (bp.total_chunks + 3) / 4, s, bp);
+    else RSZ_LAUNCH("k_count", k_count<false>, (bp.total_chunks + 3) / 4, s, bp);
+  }
   RSZ_LAUNCH("k_scan", k_scan, bp.nframes, s, bp);
   if (bp.total_units) {
-    if (bp.enc_block) RSZ_LAUNCH("k_encode", k_encode_block, bp.total_units, s, bp);
-    else RSZ_LAUNCH("k_encode", k_encode, bp.total_units, s, bp);
+    RSZ_LAUNCH("k_encode", k_encode, bp.total_units, s, bp);
   }
   const uint32_t roi_grid = (bp.total_peaks + kWaves - 1) / kWaves;   // a wave per window
   if (bp.roi_coding) {

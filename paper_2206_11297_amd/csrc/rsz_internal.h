@@ -24,9 +24,9 @@ constexpr uint64_t kRoiLens = 36;     // their code lengths, padded
 constexpr int kWaves = 4;
 constexpr int kMaxTH = 32;
 constexpr int kMaskWords = 896;       // per wave: (TH+1)*b rows x (2b*strips+1) words
-constexpr uint32_t kBlockEncodeChunks = 4096;   // fewer chunks in a batch: k_encode_block
 constexpr uint64_t kTargetWaves = 8192;         // default tiling: binning waves per batch
 constexpr uint32_t kFixBins3 = 16384;           // k_lorenzo_dims, dim 3: bins per workgroup
+constexpr uint32_t kTileEntries = kMaxTH * 4;   // sparse codes: entries per binning tile
 
 // Strips per column group for bin factor b as compiled in the binning kernel
 // (0: any b, and batches mixing bin factors).
@@ -35,6 +35,23 @@ __host__ __device__ constexpr int group_strips(int b) {
 }
 
 inline __host__ __device__ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// Division by a run-time constant d (1 <= d < 2^16) through a multiply: with
+// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, n / d = (hi32(n m) +
+// n) >> l for every n < 2^31 (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994: the round-up multiplier; the sum
+// stays below 2^32 because hi32(n m) < n).
+struct FastDiv {
+  uint32_t m, l;
+};
+inline FastDiv fast_div(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  return FastDiv{(uint32_t)((((1ull << l) - d) << 32) / d + 1), l};
+}
+__host__ __device__ __forceinline__ uint32_t fdiv(FastDiv f, uint32_t n) {
+  return (uint32_t)((((uint64_t)n * f.m) >> 32) + n) >> f.l;
+}
 
 // Per-frame mutable state in the workspace.
 struct FrameState {
@@ -68,8 +85,23 @@ struct FramePlan {
   uint64_t out_cap;
   // stream sections before the bitstream have fixed offsets
   uint64_t off_roi, off_lens, off_chunks, off_bits;
-  uint8_t *codes;           // nbins code bytes (r + 128, or 0: see rbuf)
+  uint8_t *codes;           // nbins code bytes (r + 128, or 0: see rbuf), dense
+                            // (dimension 3), then the chunk form's bytes
   int32_t *rbuf;            // nbins, residual of bins whose code byte is 0
+  uint64_t *cmask;          // nchunks * 64: the chunk form's masks (k_count)
+  // Sparse codes (frames of Lorenzo dimension 1 or 2; dimension 3 keeps the
+  // dense bytes above): per binning tile (index (panel * cgs + cg) * segs +
+  // seg), kTileEntries entries, entry s * 32 + i for strip s of the column
+  // group and tile row i: zm, bit k set where column 64 * strip + k carries a
+  // code byte other than 128 (residual 0); zp, how many such bytes the tile
+  // holds before the entry.  The bytes themselves, in tile order (row,
+  // strip, column), at zb + tile * tile_cap.
+  uint32_t sparse;
+  uint32_t tile_cap;
+  FastDiv fd_Wb, fd_Hb, fd_TH, fd_gs;
+  uint64_t *zm;
+  uint16_t *zp;
+  uint8_t *zb;
   uint8_t *codes2;          // where k_bin writes its code bytes and residuals:
   int32_t *rbuf2;           // codes / rbuf, except for dim 3 (own buffers of
                             // the 2D residuals, differenced by k_lorenzo_dims)
@@ -112,7 +144,7 @@ struct BatchPlan {
   uint32_t nframes;
   uint32_t total_tiles, total_units, total_peaks, total_chunks;
   uint32_t cpw;                  // chunks encoded by one k_encode workgroup
-  uint32_t enc_block;            // small batch: a workgroup packs one chunk at a time
+  uint32_t all_vec;              // every frame's rows load as float2/float4 (k_bin)
   uint32_t total_fix;            // workgroups of k_lorenzo_dims (0: every frame is 2D)
   uint32_t roi_coding;           // some frame codes its ROI windows
   uint32_t run_coding;           // some frame codes its Huffman bits' runs
@@ -122,6 +154,8 @@ struct BatchPlan {
   const uint32_t *peak_prefix;   // nframes + 1
   const uint32_t *chunk_prefix;  // nframes + 1
   const uint32_t *fix_prefix;    // nframes + 1 (k_lorenzo_dims workgroups)
+  const uint32_t *count_frame;   // per k_count workgroup: the frame of its first chunk
+  uint32_t all_sparse;           // every frame has sparse codes (no dimension 3)
 };
 
 // Launchers (compress.hip).
