@@ -250,12 +250,14 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   uint32_t *rp = cp + (nframes + 1);
   uint32_t *kp = rp + (nframes + 1);
   uint32_t *xp = kp + (nframes + 1);
-  uint64_t tiles = 0, units = 0, npk_total = 0, all_chunks = 0, chunks_done = 0, fixes = 0;
+  uint64_t tiles = 0, units = 0, npk_total = 0, chunks_done = 0, fixes = 0;
   bool all_vec = true;
+  // chunks per encode workgroup (its waves take every kWaves-th chunk): a
+  // multiple of kWaves, about 8192 workgroups for large batches (a workgroup
+  // first copies the code tables to LDS; one chunk per wave measured slower)
+  uint64_t all_chunks = 0;
   for (uint32_t f = 0; f < nframes; ++f)
     if (valid[f]) all_chunks += gs[f].nchunks;
-  // chunks per encode workgroup (its waves take every kWaves-th chunk): a
-  // multiple of kWaves, about 8192 workgroups for large batches
   const uint32_t cpw = kWaves * (uint32_t)std::min<uint64_t>(
                                     8, std::max<uint64_t>(1, all_chunks / (8192 * kWaves)));
   for (uint32_t f = 0; f < nframes; ++f) {

@@ -8,14 +8,17 @@
 //   k_bin       fused ROI mask + b x b background binning + prequantisation +
 //               2D Lorenzo + code/outlier + histogram; one wave per tile
 //               (segment of bin rows x column group of 64-column strips of a
-//               panel), walking it row by row.
+//               panel), walking it row by row; the codes leave in a sparse
+//               form (a zero-map and the bytes of nonzero residuals).
 //   k_lorenzo_dims  Lorenzo dimensions 1 and 3: the residuals k_bin's 2D
 //               predictor leaves to finish (row ends; the panel axis).
 //   k_codebook  one workgroup per frame: Huffman lengths and canonical codes.
-//   k_count     one wave per 4096-symbol chunk: its bits and outliers.
+//   k_count     one wave per 4096-symbol chunk: its codes gathered into a
+//               mask and compacted bytes, its bits and outliers; then one
+//               wave per peak: ROI window payload, bit copies.
 //   k_scan      one workgroup per frame: chunk bit and outlier offsets.
 //   k_encode    one workgroup per run of chunks: bit-packing and outlier
-//               indices at the offsets k_codebook computed.
+//               indices at the offsets k_scan computed.
 //   k_roi_classes, k_roi_book, k_roi_count, k_roi_scan  coded ROI: class
 //               histogram, class code, window bits and offsets.
 //   k_run_count, k_run_scan  run stage: each chunk's Rice parameter and run
@@ -23,7 +26,6 @@
 //   k_tail      one workgroup per frame: sizes, capacity, header, chunk
 //               boundary words, outlier sections, coded ROI and run section
 //               tables.
-//   k_roi       one wave per peak: ROI window payload, bit copies.
 //   k_roi_pack, k_run_pack  the coded ROI bits and the run codes.
 #include <algorithm>
 
@@ -54,6 +56,11 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint4 ld16(const void *p) {
   const u32x4 v = *gm((const u32x4 *)p);
   return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// The n lowest bits (n <= 64).
+__device__ __forceinline__ uint64_t low_bits(uint32_t n) {
+  return n >= 64 ? ~0ull : (1ull << n) - 1ull;
 }
 
 // Frame owning flat work item `item`: the largest f with prefix[f] <= item.
@@ -598,6 +605,23 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
       if (s == ns - 1) v = q_up[s];
     lastq = __builtin_amdgcn_readlane(v, lastlane);
   }
+  // A panel row whose last strip holds only a few bins (CSPAD at b = 2: 194
+  // = 3 * 64 + 2) would spend a whole strip's work per row on them.  When
+  // the group's last strip has rem bins and rem * TH <= 64, its bins of all
+  // the tile's rows are done after the row loop in one packed vector (lane =
+  // tile row * rem + column), their left neighbours kept per row in qlast.
+  // Dimension 1 needs each row's last q before the next row, so it keeps
+  // the unpacked strip.
+  const uint32_t rem = Wb - (J0 + 64 * (uint32_t)(ns - 1));
+  const bool packed = VEC && dim != 1 && last_group && ns >= 2 && rem * fp.TH <= 64;
+  const int nsr = packed ? ns - 1 : ns;   // strips done row by row
+  int32_t qlast = 0;                      // lane i: q of the row loop's last bin of tile row i
+  int32_t qhl = 0;                        // q of bin (I0 - 1, last column of the row loop)
+  if (packed) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (s == nsr - 1) qhl = __builtin_amdgcn_readlane(q_up[s], 63);
+  }
   // The strips of a row are loaded together; each strip's registers take the
   // next row's loads as soon as the strip is reduced, so that they are in
   // flight while the rest of the row is computed.
@@ -616,7 +640,7 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
   } while (0)
 #pragma unroll
   for (int s = 0; s < NS; ++s)
-    if (s < ns) RSZ_LOAD(s, I0);
+    if (s < nsr) RSZ_LOAD(s, I0);
   for (uint32_t I = I0; I < I1; ++I) {
     // q left of the group on this row
     int32_t left = __builtin_amdgcn_readlane(q_left, I - I0 + 1);
@@ -627,7 +651,7 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
     {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        if (s >= ns) break;
+        if (s >= nsr) break;
         const uint32_t J = J0 + s * 64 + lane;
         const bool colv = J < Wb;
         const uint32_t jc = RSZ_JC(s);
@@ -690,6 +714,7 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
         ql_up[s] = ql;
       }
     }
+    if (packed) qlast = (uint32_t)lane == I - I0 ? left : qlast;
     // the row's last q, for k_lorenzo_dims where it cannot be used here
     if (dim == 1 && last_group && (!whole_rows || I == Hb - 1) && lane == 0)
       fp.qedge[(size_t)p * Hb + I] = lastq;
@@ -698,6 +723,73 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
       flush_zb(*stg, fp.zb + (size_t)tix * fp.tile_cap, zflushed, zflushed + kZbFlush);
       zflushed += kZbFlush;
       wave_sync();
+    }
+  }
+  if constexpr (VEC) {
+    if (packed) {
+      const uint32_t nr = I1 - I0;
+      const uint32_t r = (uint32_t)lane / rem, c = (uint32_t)lane - r * rem;
+      const bool valid = r < nr;
+      const uint32_t I = I0 + min(r, nr - 1), Jb = J0 + 64 * (uint32_t)nsr, J = Jb + c;
+      // q of the halo row over the packed columns
+      int32_t qh = 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (s == nsr) qh = q_up[s];
+      BinPix<BB> pxp;
+      load_vec<BB, BG>(pxp, fr, H, W, I, J * (uint32_t)b * 4u, mask + RSZ_MW(J), R0, wpr);
+      const uint32_t rowbits = (1u << (min((uint32_t)BB, H - I * BB) * BB)) - 1u;
+      const int32_t qv = reduce_vec<BB, BG>(pxp, rowbits, (int)((J * b) & 31), inv, step,
+                                            range_err, DEBUG, Sd, nd);
+      const int32_t q = valid ? qv : 0;
+      // neighbours: within the vector, or the row loop's last column (qlast)
+      // and the halo row
+      const int32_t sl = __shfl(q, max(lane - 1, 0)), su = __shfl(q, max(lane - (int)rem, 0));
+      const int32_t sul = __shfl(q, max(lane - (int)rem - 1, 0));
+      const int32_t ql0 = __shfl(qlast, (int)r), qlu = __shfl(qlast, (int)r - 1 < 0 ? 0 : (int)r - 1);
+      const int32_t qhc = __shfl(qh, (int)c), qhcl = __shfl(qh, c > 0 ? (int)c - 1 : 0);
+      const int32_t ql = c > 0 ? sl : ql0;
+      const int32_t qu = r > 0 ? su : qhc;
+      const int32_t qul = r > 0 ? (c > 0 ? sul : qlu) : (c > 0 ? qhcl : qhl);
+      const int32_t res = q + qul - qu - ql;
+      const uint32_t code = code_from_residual(res);
+      const uint32_t cb = code_byte(res);
+      const size_t g = (size_t)I * Wb + J;
+      if (sparse) {
+        const bool nz = valid && cb != 128u;
+        const uint64_t m = __ballot(nz);
+        if (nz) {
+          const uint32_t rank =
+              __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          stg->zb[(zcount + rank) & (kZbRing - 1)] = (uint8_t)cb;
+          if (cb == 0) *gm(rbuf + g) = res;
+        }
+        // entry (strip nsr, tile row i): lane i takes its rem bits, and the
+        // count of the set bits before them
+        const uint64_t ev = (uint32_t)lane < nr ? (m >> ((uint32_t)lane * rem)) & low_bits(rem) : 0ull;
+        const uint32_t ez = zcount + (uint32_t)__builtin_popcountll(m & low_bits((uint32_t)lane * rem));
+        const int src = lane - 32 * (nsr & 1);
+        const bool here = src >= 0 && (uint32_t)src < nr;
+        const uint32_t elo = __shfl((uint32_t)ev, max(src, 0)), ehi = __shfl((uint32_t)(ev >> 32), max(src, 0));
+        const uint32_t ezs = __shfl(ez, max(src, 0));
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr)
+          if (pr == (nsr >> 1) && here) {
+            zmlo[pr] = elo;
+            zmhi[pr] = ehi;
+            zpv[pr] = ezs;
+          }
+        zcount += (uint32_t)__builtin_popcountll(m);
+      } else if (valid) {
+        *gm(codes + g) = (uint8_t)cb;
+        if (cb == 0) *gm(rbuf + g) = res;
+      }
+      if (DEBUG && valid) {
+        if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
+        if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
+        if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
+      }
+      if (dim != 3) wave_histogram(code, __ballot(valid), hist, c512);
     }
   }
   if (sparse) {
@@ -1173,6 +1265,51 @@ __device__ __forceinline__ uint32_t byte_at(uint32_t w0, uint32_t w1, uint32_t w
 // Sparse rounds: at most this many bytes per lane differ from residual 0's.
 constexpr uint32_t kSparseBytes = 4;
 
+// ------------------------------------------------------------------ k_roi
+
+// ROI payload (Sec. IV-A: each peak's w x w window as a buffer, a constant
+// fill outside the panel), the work items of k_count past its chunks: one
+// wave per peak, flat over the window's w*w
+// pixels, kRoiSlots pixels per lane loaded before any is stored (so a
+// window's loads are in flight together: the stores could alias the frame as
+// far as the compiler knows).  Window row u = e / w from a multiply-high by
+// floor((2^32 - 1) / w) + 1, exact for e < w^2 since w^3 < 2^32.
+constexpr uint32_t kRoiSlots = 8;
+__device__ __forceinline__ void roi_copy(const BatchPlan &bp, uint32_t kg) {
+  const int lane = threadIdx.x & 63;
+  if (kg >= bp.total_peaks) return;
+  const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
+  const FramePlan &fp = bp.frames[f];
+  if (fp.roi_coding || load_status(fp.st) != RSZ_OK) return;
+  // the section lies inside the output buffer (a stream that does not fit
+  // it altogether gets RSZ_ERR_CAPACITY from k_tail, and its bytes are
+  // unspecified)
+  if (fp.off_roi + 4ull * fp.npeaks * fp.w * fp.w > fp.out_cap) return;
+  const uint32_t k = kg - bp.peak_prefix[f];
+  const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
+  if (pa < 0 || pa >= fp.P) return;
+  const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+  const int64_t h = w / 2, H = fp.H, W = fp.W;
+  uint32_t *dst = (uint32_t *)(fp.out + fp.off_roi) + (size_t)k * ww;
+  const float *src = fp.frame + (size_t)pa * H * W;
+  for (uint32_t e0 = 0; e0 < ww; e0 += 64 * kRoiSlots) {
+    uint32_t val[kRoiSlots];
+#pragma unroll
+    for (uint32_t t = 0; t < kRoiSlots; ++t) {
+      const uint32_t e = e0 + 64 * t + lane;
+      const uint32_t u = __umulhi(e, M), v = e - u * w;
+      const int64_t i = r - h + u, j = c - h + v;
+      val[t] = 0u;
+      if (e < ww && i >= 0 && i < H && j >= 0 && j < W) val[t] = __float_as_uint(*gm(src + i * W + j));
+    }
+#pragma unroll
+    for (uint32_t t = 0; t < kRoiSlots; ++t) {
+      const uint32_t e = e0 + 64 * t + lane;
+      if (e < ww) *gm(dst + e) = val[t];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- k_count
 
 // Exclusive prefix sums over the lanes of a wave, and the wave total.
@@ -1200,9 +1337,6 @@ __device__ __forceinline__ uint32_t wave_exclusive_scan32(uint32_t v, uint32_t &
   return x - v;
 }
 
-__device__ __forceinline__ uint64_t low_bits(uint32_t n) {
-  return n >= 64 ? ~0ull : (1ull << n) - 1ull;
-}
 
 // Position of a bin of a frame with sparse codes, for walking its bins in
 // raster order piece by piece: a piece lies in one strip (64 bin columns) of
@@ -1296,9 +1430,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t item = blockIdx.x * kWaves + wv;
-  if (item >= bp.total_chunks) return;
+  if (item >= bp.total_chunks) {
+    // the ROI windows' payload, in the same launch (it needs only k_prep's
+    // peak check, and this kernel leaves HBM bandwidth to spare)
+    if (bp.roi_in_count) roi_copy(bp, item - bp.total_chunks);
+    return;
+  }
   // the four chunks of a workgroup may span frames: each wave finds its own
-  uint32_t fw = bp.count_frame[blockIdx.x];
+  uint32_t fw = bp.count_frame[min(blockIdx.x, (bp.total_chunks - 1) / kWaves)];
   while (bp.chunk_prefix[fw + 1] <= item) ++fw;
   const FramePlan &fp = bp.frames[fw];
   if (load_status(fp.st) != RSZ_OK) return;
@@ -1860,47 +1999,6 @@ __global__ __launch_bounds__(256) void k_tail(BatchPlan bp) {
     const uint32_t g = fp.obuf[k];
     oidx[k] = g;
     ores[k] = fp.rbuf[g];
-  }
-}
-
-// ------------------------------------------------------------------ k_roi
-
-// ROI payload (Sec. IV-A: each peak's w x w window as a buffer, a constant
-// fill outside the panel): one wave per peak, flat over the window's w*w
-// pixels, kRoiSlots pixels per lane loaded before any is stored (so a
-// window's loads are in flight together: the stores could alias the frame as
-// far as the compiler knows).  Window row u = e / w from a multiply-high by
-// floor((2^32 - 1) / w) + 1, exact for e < w^2 since w^3 < 2^32.
-constexpr uint32_t kRoiSlots = 8;
-__global__ __launch_bounds__(256) void k_roi(BatchPlan bp) {
-  const int lane = threadIdx.x & 63;
-  const uint32_t kg = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (kg >= bp.total_peaks) return;
-  const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
-  const FramePlan &fp = bp.frames[f];
-  if (fp.roi_coding || load_status(fp.st) != RSZ_OK) return;
-  const uint32_t k = kg - bp.peak_prefix[f];
-  const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
-  if (pa < 0 || pa >= fp.P) return;
-  const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
-  const int64_t h = w / 2, H = fp.H, W = fp.W;
-  uint32_t *dst = (uint32_t *)(fp.out + fp.off_roi) + (size_t)k * ww;
-  const float *src = fp.frame + (size_t)pa * H * W;
-  for (uint32_t e0 = 0; e0 < ww; e0 += 64 * kRoiSlots) {
-    uint32_t val[kRoiSlots];
-#pragma unroll
-    for (uint32_t t = 0; t < kRoiSlots; ++t) {
-      const uint32_t e = e0 + 64 * t + lane;
-      const uint32_t u = __umulhi(e, M), v = e - u * w;
-      const int64_t i = r - h + u, j = c - h + v;
-      val[t] = 0u;
-      if (e < ww && i >= 0 && i < H && j >= 0 && j < W) val[t] = __float_as_uint(src[i * W + j]);
-    }
-#pragma unroll
-    for (uint32_t t = 0; t < kRoiSlots; ++t) {
-      const uint32_t e = e0 + 64 * t + lane;
-      if (e < ww) dst[e] = val[t];
-    }
   }
 }
 
@@ -2551,9 +2649,12 @@ hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t dim
 }
 
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
-  if (bp.total_chunks) {
-    if (bp.all_sparse) RSZ_LAUNCH("k_count", k_count<true>, (bp.total_chunks + 3) / 4, s, bp);
-    else RSZ_LAUNCH("k_count", k_count<false>, (bp.total_chunks + 3) / 4, s, bp);
+  BatchPlan bc = bp;   // k_count also copies the verbatim ROI windows
+  bc.roi_in_count = 1;
+  const uint32_t citems = bp.total_chunks + bp.total_peaks;
+  if (citems) {
+    if (bp.all_sparse) RSZ_LAUNCH("k_count", k_count<true>, (citems + kWaves - 1) / kWaves, s, bc);
+    else RSZ_LAUNCH("k_count", k_count<false>, (citems + kWaves - 1) / kWaves, s, bc);
   }
   RSZ_LAUNCH("k_scan", k_scan, bp.nframes, s, bp);
   if (bp.total_units) {
@@ -2572,10 +2673,7 @@ hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
     RSZ_LAUNCH("k_run_scan", k_run_scan, bp.nframes, s, bp);
   }
   RSZ_LAUNCH("k_tail", k_tail, bp.nframes, s, bp);
-  if (bp.total_peaks) {
-    RSZ_LAUNCH("k_roi", k_roi, (bp.total_peaks + kWaves - 1) / kWaves, s, bp);
-    if (bp.roi_coding) RSZ_LAUNCH("k_roi_pack", k_roi_pack, roi_grid, s, bp);
-  }
+  if (bp.total_peaks && bp.roi_coding) RSZ_LAUNCH("k_roi_pack", k_roi_pack, roi_grid, s, bp);
   if (bp.run_coding && bp.total_chunks) RSZ_LAUNCH("k_run_pack", k_run_pack, run_grid, s, bp);
   return hipSuccess;
 }

@@ -156,6 +156,7 @@ struct BatchPlan {
   const uint32_t *fix_prefix;    // nframes + 1 (k_lorenzo_dims workgroups)
   const uint32_t *count_frame;   // per k_count workgroup: the frame of its first chunk
   uint32_t all_sparse;           // every frame has sparse codes (no dimension 3)
+  uint32_t roi_in_count;         // k_count's items past the chunks copy ROI windows
 };
 
 // Launchers (compress.hip).
