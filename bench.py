@@ -536,8 +536,9 @@ def main():
         print(f"[bench] autotune: best tile {tile['best']} {tile['ms']} ms "
               f"(default {tile['default_ms']} ms, {len(tile['table'])} shapes)",
               file=sys.stderr, flush=True)
-    tile_rows, tile_strips = tile["best"] if tile else (0, 0)
-    B = rsz.Batch(frames, peaks, prm, tile_rows=tile_rows, tile_strips=tile_strips)
+    tile_rows, tile_strips, tile_waves = (list(tile["best"]) + [0])[:3] if tile else (0, 0, 0)
+    B = rsz.Batch(frames, peaks, prm, tile_rows=tile_rows, tile_strips=tile_strips,
+                  tile_waves=tile_waves)
     raw_bytes = sum(f.numel() * 4 for f in frames)
     npix = raw_bytes // 4
 

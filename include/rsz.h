@@ -138,8 +138,12 @@ int rsz_compress(const rsz_params *p, const float *d_frame, const rsz_peak *d_pe
  * peak counts.  tile_rows, tile_strips: tuning knobs of the binning kernel's
  * tiles, the most bin rows and 64-column strips one wave walks (0 = library
  * default: the coarsest tiles that give a batch about 8192 waves;
- * clamped to what the kernel's LDS and registers hold).  They change speed
- * only: the output bytes never depend on them.  reserved: set to 0. */
+ * clamped to what the kernel's LDS and registers hold).  tile_waves: waves
+ * (tiles of consecutive row segments) per binning workgroup, 1..4 (0 = 4;
+ * the batch takes its first valid frame's value).  These knobs change speed
+ * only: the output bytes never depend on them (the autotuning of thread
+ * counts in Sec. V-C, "Autotuning Configuration", likewise leaves the
+ * output unchanged). */
 typedef struct {
   rsz_params params;
   const float *frame;
@@ -147,7 +151,7 @@ typedef struct {
   uint32_t npeaks;
   uint32_t tile_rows;
   uint32_t tile_strips;
-  uint32_t reserved;
+  uint32_t tile_waves;
   void *out;
   uint64_t out_cap;
 } rsz_frame_desc;

@@ -1,11 +1,15 @@
-"""Autotuner for the binning kernel's tile shape.
+"""Autotuner for the binning kernel's tile shape and block schedule.
 
 The binning kernel walks tiles of `tile_rows` bin rows x `tile_strips`
-64-column strips per wave (rsz_frame_desc).  Taller tiles re-read fewer halo
+64-column strips per wave, `tile_waves` waves (tiles of consecutive row
+segments) per workgroup (rsz_frame_desc).  Taller tiles re-read fewer halo
 rows; shorter and narrower ones give a batch more waves, which small batches
-need to fill the chip.  The tuner times the batched compression of one batch
-for each candidate shape, checks that every candidate writes the same streams
-as the library default (the shape may change speed only), and returns the
+need to fill the chip; the waves per workgroup set how a panel's rows split
+into segments and how many tiles share a workgroup's LDS.  The tuner times
+the batched compression of one batch for each candidate, checks that every
+candidate writes the same streams as the library default (the knobs may
+change speed only, as the thread-count tuning of the paper's Sec. V-C
+"Autotuning Configuration" leaves the output unchanged), and returns the
 fastest.  Results are cached in a JSON table keyed by the batch signature
 (frame shapes, bin factors, windows and a power-of-two bucket of the frame
 count).
@@ -16,9 +20,17 @@ import time
 
 from . import rsz
 
-ROWS = (0, 1, 2, 4, 8, 12, 16, 24, 32)
+ROWS = (0, 4, 8, 12, 16, 24, 32)
 STRIPS = (0, 1, 2, 4)
-CANDIDATES = [(r, s) for r in ROWS for s in STRIPS]
+WAVES = (0, 2, 3)   # 0: the library default (4)
+CANDIDATES = [(r, s, w) for w in WAVES for r in ROWS for s in STRIPS]
+
+
+def _knobs(c):
+    """(rows, strips, waves) of a candidate or stored entry (older tables
+    hold (rows, strips))."""
+    c = list(c)
+    return (int(c[0]), int(c[1]), int(c[2]) if len(c) > 2 else 0)
 
 
 def signature(frames, prm):
@@ -61,18 +73,21 @@ TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_tiles.js
 
 def tune(frames, peaks, prm, candidates=None, reps=5, budget_s=30.0, cache_path=TABLE,
          store_path=None, log=None):
-    """Times `candidates` (default: CANDIDATES) on this batch; returns
-    {"best": (rows, strips), "ms": ..., "default_ms": ..., "table": [...]}.
-    Candidates whose streams differ from the default's raise an error: the
-    tile shape must never change the output.  A result stored in cache_path
-    (default: the table shipped with the package, tuned on MI355X) for the
-    same signature is returned without timing; store_path receives new
+    """Times `candidates` (default: CANDIDATES, each (rows, strips, waves))
+    on this batch; returns {"best": (rows, strips, waves), "ms": ...,
+    "default_ms": ..., "table": [...], "cached": False}.  Candidates whose
+    streams differ from the default's raise an error: the knobs must never
+    change the output.  A result stored in cache_path (default: the table
+    shipped with the package, tuned on MI355X) for the same signature is
+    returned without timing, with "cached": True; store_path receives new
     results."""
     key = signature(frames, prm)
     if cache_path and os.path.exists(cache_path):
         table = json.load(open(cache_path))
         if key in table:
-            return dict(table[key], cached=True)
+            out = dict(table[key], cached=True)
+            out["best"] = list(_knobs(out["best"]))
+            return out
     torch = rsz._torch()
     base = rsz.Batch(frames, peaks, prm)
     base.run()
@@ -86,19 +101,20 @@ def tune(frames, peaks, prm, candidates=None, reps=5, budget_s=30.0, cache_path=
     del base
     rows = []
     t0 = time.perf_counter()
-    for r, s in candidates or CANDIDATES:
+    for c in candidates or CANDIDATES:
         if time.perf_counter() - t0 > budget_s:
             break
-        B = rsz.Batch(frames, peaks, prm, tile_rows=r, tile_strips=s)
+        r, s, w = _knobs(c)
+        B = rsz.Batch(frames, peaks, prm, tile_rows=r, tile_strips=s, tile_waves=w)
         ms = _time_batch(B, reps)
         if not _same_streams(B, ref_sizes, ref):
-            raise RuntimeError(f"autotune: tile shape ({r}, {s}) changed the output")
-        rows.append((r, s, round(ms, 4)))
+            raise RuntimeError(f"autotune: tile shape ({r}, {s}, {w}) changed the output")
+        rows.append((r, s, w, round(ms, 4)))
         if log:
-            log(f"tile_rows={r} tile_strips={s}: {ms:.4f} ms")
+            log(f"tile_rows={r} tile_strips={s} tile_waves={w}: {ms:.4f} ms")
         del B
-    best = min(rows, key=lambda t: t[2]) if rows else (0, 0, default_ms)
-    out = {"best": [best[0], best[1]], "ms": best[2], "default_ms": round(default_ms, 4),
+    best = min(rows, key=lambda t: t[3]) if rows else (0, 0, 0, default_ms)
+    out = {"best": [best[0], best[1], best[2]], "ms": best[3], "default_ms": round(default_ms, 4),
            "table": rows, "cached": False}
     if store_path:
         table = json.load(open(store_path)) if os.path.exists(store_path) else {}

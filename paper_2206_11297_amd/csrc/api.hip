@@ -79,8 +79,9 @@ struct Geom {
 // Binning tiles: column groups of at most `gs` strips (the kernel's compiled
 // width for this batch) and segments of at most kMaxTH bin rows whose LDS
 // mask, (TH+1)*b raw rows of wpr words, fits kMaskWords; segments are
-// balanced in groups of kWaves per workgroup.
-static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap, uint32_t gs) {
+// balanced in groups of wpg (waves per workgroup).
+static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap, uint32_t gs,
+                     uint32_t wpg = kWaves) {
   Geom g;
   g.Hb = (uint32_t)div_up(p->height, p->bin);
   g.Wb = (uint32_t)div_up(p->width, p->bin);
@@ -94,10 +95,10 @@ static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap, uint
   uint32_t thmax = (uint32_t)kMaskWords / (p->bin * wpr);
   thmax = thmax > 1 ? thmax - 1 : 1;
   thmax = std::max<uint32_t>(1, std::min({thmax, (uint32_t)kMaxTH, th_cap}));
-  const uint32_t nseg = kWaves * (uint32_t)div_up(g.Hb, (uint64_t)kWaves * thmax);
+  const uint32_t nseg = wpg * (uint32_t)div_up(g.Hb, (uint64_t)wpg * thmax);
   g.TH = (uint32_t)div_up(g.Hb, nseg);
   g.segs = (uint32_t)div_up(g.Hb, g.TH);
-  g.groups = (uint32_t)div_up(g.segs, kWaves);
+  g.groups = (uint32_t)div_up(g.segs, wpg);
   g.off_roi = kHeader + align_up(6ull * npeaks, 4);
   const uint64_t nroi = (uint64_t)npeaks * p->window * p->window;
   g.off_lens = g.off_roi + (p->roi_coding ? 0 : 4ull * nroi);
@@ -159,7 +160,7 @@ static Layout layout(uint32_t nframes, const std::vector<const rsz_params *> &ps
   for (uint32_t f = 0; f < nframes; ++f)
     if (valid[f]) chunks += gs[f].nchunks;
   L.cframe = L.prefix + align_up(5 * 4ull * (nframes + 1), 256);
-  L.states = L.cframe + align_up(4 * div_up(chunks, kWaves) + 4, 256);
+  L.states = L.cframe + align_up(8 * div_up(chunks, kWaves) + 8, 256);
   L.frames_begin = L.states + align_up(sizeof(FrameState) * nframes, 256);
   uint64_t off = L.frames_begin;
   L.frame_off.resize(nframes);
@@ -210,6 +211,13 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     first = false;
   }
   const uint32_t gsw = (uint32_t)group_strips((int)hp.common_b);
+  // waves per binning workgroup: the first valid frame's tile_waves
+  uint32_t wpg = kWaves;
+  for (uint32_t f = 0; f < nframes; ++f)
+    if (valid[f]) {
+      if (d[f].tile_waves) wpg = std::min<uint32_t>(d[f].tile_waves, kWaves);
+      break;
+    }
   // tile shape of each frame: the caller's tile_rows / tile_strips, else the
   // coarsest shape of the ladder below that gives the batch kTargetWaves
   // binning waves, down to 8-row single-strip tiles (shorter tiles re-read
@@ -227,8 +235,8 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
       if (!valid[f]) continue;
       uint32_t rows, strips;
       shape_of(f, rung, rows, strips);
-      const Geom g = geometry(ps[f], np[f], rows, strips);
-      waves += (uint64_t)ps[f]->panels * g.cgs * g.groups * kWaves;
+      const Geom g = geometry(ps[f], np[f], rows, strips, wpg);
+      waves += (uint64_t)ps[f]->panels * g.cgs * g.groups * wpg;
     }
     if (waves >= kTargetWaves) break;
   }
@@ -236,7 +244,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     if (valid[f]) {
       uint32_t rows, strips;
       shape_of(f, rung, rows, strips);
-      gs[f] = geometry(ps[f], np[f], rows, strips);
+      gs[f] = geometry(ps[f], np[f], rows, strips, wpg);
     }
   Layout L = layout(nframes, ps, np, gs, valid);
   if (need) *need = L.total;
@@ -302,8 +310,6 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     fp.vec = (p->bin == 2 || p->bin == 4) && p->width % p->bin == 0 &&
              (uintptr_t)d[f].frame % (4 * p->bin) == 0;
     all_vec = all_vec && fp.vec;
-    fp.inv[0] = 0.0;
-    for (uint32_t n = 1; n <= 64; ++n) fp.inv[n] = 1.0 / ((double)n * fp.step);
     fp.frame = d[f].frame;
     fp.peaks = (const int32_t *)d[f].peaks;
     fp.out = (uint8_t *)d[f].out;
@@ -415,6 +421,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   hp.bp.total_peaks = (uint32_t)npk_total;
   hp.bp.cpw = cpw;
   hp.bp.all_vec = all_vec ? 1u : 0u;
+  hp.bp.bin_waves = wpg;
   hp.bp.frames = (const FramePlan *)(ws + L.plans);
   hp.bp.tile_prefix = (const uint32_t *)(ws + L.prefix);
   hp.bp.unit_prefix = hp.bp.tile_prefix + (nframes + 1);
@@ -426,9 +433,10 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   uint32_t fr = 0;
   for (uint64_t w = 0; w < div_up(chunks_done, kWaves); ++w) {
     while (kp[fr + 1] <= w * kWaves) ++fr;
-    cf[w] = fr;
+    cf[2 * w] = fr;
+    cf[2 * w + 1] = (uint32_t)(w * kWaves - kp[fr]);
   }
-  hp.bp.count_frame = (const uint32_t *)(ws + L.cframe);
+  hp.bp.count_frame = (const uint2 *)(ws + L.cframe);
   bool all_sparse = true;
   for (uint32_t f = 0; f < nframes; ++f)
     if (valid[f] && fpl[f].dim == 3) all_sparse = false;

@@ -129,6 +129,11 @@ __global__ __launch_bounds__(256) void k_prep(BatchPlan bp) {
     st->Troi = 0;
   }
   if (fp.init_status != RSZ_OK) return;
+  // the quantiser's reciprocals, computed here rather than carried in the
+  // plan (the device divide and multiply are the IEEE operations, so the
+  // bits equal the host's): inv[n] = 1 / (n * 2eb), inv[0] = 0
+  if (threadIdx.x <= 64)
+    st->inv[threadIdx.x] = threadIdx.x ? 1.0 / ((double)threadIdx.x * fp.step) : 0.0;
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < fp.npeaks; k += 256) {
     const int32_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
@@ -201,6 +206,51 @@ __device__ __forceinline__ void peak_range(const FramePlan &fp, uint32_t p, int6
   k1 = fp.bstart[(size_t)p * fp.segs + (uint32_t)(hi / band) + 1];
 }
 
+// ------------------------------------------------------------------ k_roi
+
+// ROI payload (Sec. IV-A: each peak's w x w window as a buffer, a constant
+// fill outside the panel), the work items of k_count past its chunks: one
+// wave per peak, flat over the window's w*w
+// pixels, kRoiSlots pixels per lane loaded before any is stored (so a
+// window's loads are in flight together: the stores could alias the frame as
+// far as the compiler knows).  Window row u = e / w from a multiply-high by
+// floor((2^32 - 1) / w) + 1, exact for e < w^2 since w^3 < 2^32.
+constexpr uint32_t kRoiSlots = 8;
+__device__ __forceinline__ void roi_copy(const BatchPlan &bp, uint32_t kg) {
+  const int lane = threadIdx.x & 63;
+  if (kg >= bp.total_peaks) return;
+  const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
+  const FramePlan &fp = bp.frames[f];
+  if (fp.roi_coding || load_status(fp.st) != RSZ_OK) return;
+  // the section lies inside the output buffer (a stream that does not fit
+  // it altogether gets RSZ_ERR_CAPACITY from k_tail, and its bytes are
+  // unspecified)
+  if (fp.off_roi + 4ull * fp.npeaks * fp.w * fp.w > fp.out_cap) return;
+  const uint32_t k = kg - bp.peak_prefix[f];
+  const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
+  if (pa < 0 || pa >= fp.P) return;
+  const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
+  const int64_t h = w / 2, H = fp.H, W = fp.W;
+  uint32_t *dst = (uint32_t *)(fp.out + fp.off_roi) + (size_t)k * ww;
+  const float *src = fp.frame + (size_t)pa * H * W;
+  for (uint32_t e0 = 0; e0 < ww; e0 += 64 * kRoiSlots) {
+    uint32_t val[kRoiSlots];
+#pragma unroll
+    for (uint32_t t = 0; t < kRoiSlots; ++t) {
+      const uint32_t e = e0 + 64 * t + lane;
+      const uint32_t u = __umulhi(e, M), v = e - u * w;
+      const int64_t i = r - h + u, j = c - h + v;
+      val[t] = 0u;
+      if (e < ww && i >= 0 && i < H && j >= 0 && j < W) val[t] = __float_as_uint(*gm(src + i * W + j));
+    }
+#pragma unroll
+    for (uint32_t t = 0; t < kRoiSlots; ++t) {
+      const uint32_t e = e0 + 64 * t + lane;
+      if (e < ww) *gm(dst + e) = val[t];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ k_bin
 
 // Histogram update with one LDS atomic per distinct code in the wave; the
@@ -212,6 +262,22 @@ __device__ __forceinline__ void wave_histogram(uint32_t code, uint64_t vmask, ui
   c512 += (uint32_t)__builtin_popcountll(
       __builtin_amdgcn_uicmp(code, (uint32_t)kRadius, 32 /* eq */) & vmask);
   uint64_t pending = __builtin_amdgcn_uicmp(code, (uint32_t)kRadius, 33 /* ne */) & vmask;
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const uint32_t lc = __builtin_amdgcn_readlane(code, leader);
+    const uint64_t same = __builtin_amdgcn_uicmp(code, lc, 32 /* eq */) & pending;
+    if (lane == leader) atomicAdd(&hist[lc], (uint32_t)__builtin_popcountll(same));
+    pending &= ~same;
+  }
+}
+
+// The same from the wave's ballot m of the lanes whose residual is not 0
+// (code other than 512): the others are counted from the mask alone.
+__device__ __forceinline__ void wave_histogram_nz(uint32_t code, uint64_t m, uint64_t vmask,
+                                                  uint32_t *hist, uint32_t &c512) {
+  const int lane = threadIdx.x & 63;
+  c512 += (uint32_t)__builtin_popcountll(vmask & ~m);
+  uint64_t pending = m;
   while (pending) {
     const int leader = __builtin_ctzll(pending);
     const uint32_t lc = __builtin_amdgcn_readlane(code, leader);
@@ -690,6 +756,9 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
           zmhi[s >> 1] = here ? (uint32_t)(m >> 32) : zmhi[s >> 1];
           zpv[s >> 1] = here ? zcount : zpv[s >> 1];
           zcount += (uint32_t)__builtin_popcountll(m);
+          // m holds exactly the lanes whose code is not 512 (a forced bin
+          // with r = 0 is counted through the loop, to the same total)
+          if (dim != 3) wave_histogram_nz(code, m, vmask[s], hist, c512);
           if (DEBUG && colv) {
             const size_t g = (size_t)I * Wb + J;
             if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
@@ -708,7 +777,7 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
             if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
           }
         }
-        if (dim != 3) wave_histogram(code, vmask[s], hist, c512);
+        if (!sparse && dim != 3) wave_histogram(code, vmask[s], hist, c512);
         if (dim == 1 && s == ns - 1) lastq = __builtin_amdgcn_readlane(q, lastlane);
         q_up[s] = q;
         ql_up[s] = ql;
@@ -824,8 +893,8 @@ __device__ __forceinline__ void k_bin_body(BatchPlan bp) {
   __shared__ SparseStage s_stage[DIM == 3 ? 1 : kWaves];
   const uint32_t f = find_frame(bp.tile_prefix, bp.nframes, blockIdx.x);
   const FramePlan &fp = bp.frames[f];
-  for (int i = threadIdx.x; i < kNumSym; i += 256) s_hist[i] = 0u;
-  if (threadIdx.x < 65) s_inv[threadIdx.x] = fp.inv[threadIdx.x];
+  for (int i = threadIdx.x; i < kNumSym; i += blockDim.x) s_hist[i] = 0u;
+  for (int i = threadIdx.x; i < 65; i += blockDim.x) s_inv[i] = fp.st->inv[i];
   __syncthreads();
   // wave index as a wave-uniform (scalar) value: everything per tile and
   // per row below stays in scalar registers
@@ -833,7 +902,7 @@ __device__ __forceinline__ void k_bin_body(BatchPlan bp) {
   const uint32_t t = blockIdx.x - bp.tile_prefix[f];
   const uint32_t per_panel = fp.groups * fp.cgs;
   const uint32_t panel = t / per_panel, rem = t % per_panel;
-  const uint32_t cg = rem / fp.groups, seg = (rem % fp.groups) * kWaves + wv;
+  const uint32_t cg = rem / fp.groups, seg = (rem % fp.groups) * bp.bin_waves + wv;
   const bool ok = load_status(fp.st) == RSZ_OK;
   if (ok && seg < fp.segs) {
     const bool bg = fp.mode == RSZ_BIN_BACKGROUND;
@@ -855,7 +924,7 @@ __device__ __forceinline__ void k_bin_body(BatchPlan bp) {
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kNumSym; i += 256)
+  for (int i = threadIdx.x; i < kNumSym; i += blockDim.x)
     if (s_hist[i]) atomicAdd(&fp.st->hist[i], s_hist[i]);
 }
 
@@ -1265,51 +1334,6 @@ __device__ __forceinline__ uint32_t byte_at(uint32_t w0, uint32_t w1, uint32_t w
 // Sparse rounds: at most this many bytes per lane differ from residual 0's.
 constexpr uint32_t kSparseBytes = 4;
 
-// ------------------------------------------------------------------ k_roi
-
-// ROI payload (Sec. IV-A: each peak's w x w window as a buffer, a constant
-// fill outside the panel), the work items of k_count past its chunks: one
-// wave per peak, flat over the window's w*w
-// pixels, kRoiSlots pixels per lane loaded before any is stored (so a
-// window's loads are in flight together: the stores could alias the frame as
-// far as the compiler knows).  Window row u = e / w from a multiply-high by
-// floor((2^32 - 1) / w) + 1, exact for e < w^2 since w^3 < 2^32.
-constexpr uint32_t kRoiSlots = 8;
-__device__ __forceinline__ void roi_copy(const BatchPlan &bp, uint32_t kg) {
-  const int lane = threadIdx.x & 63;
-  if (kg >= bp.total_peaks) return;
-  const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
-  const FramePlan &fp = bp.frames[f];
-  if (fp.roi_coding || load_status(fp.st) != RSZ_OK) return;
-  // the section lies inside the output buffer (a stream that does not fit
-  // it altogether gets RSZ_ERR_CAPACITY from k_tail, and its bytes are
-  // unspecified)
-  if (fp.off_roi + 4ull * fp.npeaks * fp.w * fp.w > fp.out_cap) return;
-  const uint32_t k = kg - bp.peak_prefix[f];
-  const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
-  if (pa < 0 || pa >= fp.P) return;
-  const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
-  const int64_t h = w / 2, H = fp.H, W = fp.W;
-  uint32_t *dst = (uint32_t *)(fp.out + fp.off_roi) + (size_t)k * ww;
-  const float *src = fp.frame + (size_t)pa * H * W;
-  for (uint32_t e0 = 0; e0 < ww; e0 += 64 * kRoiSlots) {
-    uint32_t val[kRoiSlots];
-#pragma unroll
-    for (uint32_t t = 0; t < kRoiSlots; ++t) {
-      const uint32_t e = e0 + 64 * t + lane;
-      const uint32_t u = __umulhi(e, M), v = e - u * w;
-      const int64_t i = r - h + u, j = c - h + v;
-      val[t] = 0u;
-      if (e < ww && i >= 0 && i < H && j >= 0 && j < W) val[t] = __float_as_uint(*gm(src + i * W + j));
-    }
-#pragma unroll
-    for (uint32_t t = 0; t < kRoiSlots; ++t) {
-      const uint32_t e = e0 + 64 * t + lane;
-      if (e < ww) *gm(dst + e) = val[t];
-    }
-  }
-}
-
 // ---------------------------------------------------------------- k_count
 
 // Exclusive prefix sums over the lanes of a wave, and the wave total.
@@ -1433,16 +1457,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   if (item >= bp.total_chunks) {
     // the ROI windows' payload, in the same launch (it needs only k_prep's
     // peak check, and this kernel leaves HBM bandwidth to spare)
-    if (bp.roi_in_count) roi_copy(bp, item - bp.total_chunks);
+    roi_copy(bp, item - bp.total_chunks);
     return;
   }
-  // the four chunks of a workgroup may span frames: each wave finds its own
-  uint32_t fw = bp.count_frame[min(blockIdx.x, (bp.total_chunks - 1) / kWaves)];
-  while (bp.chunk_prefix[fw + 1] <= item) ++fw;
+  // the workgroup's first chunk (frame, chunk) from the table; the four
+  // chunks of a workgroup may span frames
+  const uint2 fc = bp.count_frame[blockIdx.x];
+  uint32_t fw = fc.x, c = fc.y + (uint32_t)wv;
+  while (c >= bp.frames[fw].nchunks) c -= bp.frames[fw].nchunks, ++fw;
   const FramePlan &fp = bp.frames[fw];
-  if (load_status(fp.st) != RSZ_OK) return;
-  const uint32_t c = item - bp.chunk_prefix[fw];
-  s_len4[wv][lane] = ((const uint4 *)fp.st->lens)[lane];
+  // the status, the code lengths and (below) the zero-map words are loaded
+  // together; the status gates only what the wave writes, and every read
+  // stays inside the frame's buffers whatever they hold
+  const bool ok = load_status(fp.st) == RSZ_OK;
+  const uint4 lv = ((const uint4 *)fp.st->lens)[lane];
   const uint32_t g0 = c * kChunk + lane * 64u;
   const uint32_t end = min(g0 + 64u, fp.nbins);
   const uint32_t nvalid = end > g0 ? end - g0 : 0u;
@@ -1450,6 +1478,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   uint64_t mask = 0;
   uint32_t nz = 0, bits = 0, nout = 0;
   const uint8_t *lens = (const uint8_t *)s_len4[wv];
+  const uint32_t zb_last = fp.tile_cap - 1;
   auto take = [&](uint32_t b, uint32_t g) {
     slot[nz++] = (uint8_t)b;
     const uint32_t code = b ? b + (kRadius - 128) : code_from_residual(*gm(fp.rbuf + g));
@@ -1459,8 +1488,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   // the bytes of one piece: m its bins, word its zero-map word
   auto piece_bytes = [&](uint32_t g, uint32_t a, uint32_t tix, uint64_t m, uint64_t word,
                          uint32_t zp) {
-    const uint8_t *zb = fp.zb + (size_t)tix * fp.tile_cap + zp + __builtin_popcountll(word & low_bits(a));
-    for (uint32_t k = 0; m; m &= m - 1, ++k) take(*gm(zb + k), g + (uint32_t)__builtin_ctzll(m));
+    const uint8_t *zb = fp.zb + (size_t)tix * fp.tile_cap;
+    const uint32_t o = zp + (uint32_t)__builtin_popcountll(word & low_bits(a));
+    for (uint32_t k = 0; m; m &= m - 1, ++k)
+      take(*gm(zb + min(o + k, zb_last)), g + (uint32_t)__builtin_ctzll(m));
   };
   if (SPARSE || fp.sparse) {
     // a window of 64 bins in a row of at least 64 bins meets at most three
@@ -1488,6 +1519,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     }
     if (short_rows) {
       // rows of fewer than 64 bins: piece by piece
+      s_len4[wv][lane] = lv;
       wave_sync();   // lengths in LDS
       for_pieces(fp, g0, end, [&](uint32_t gg, uint32_t n, uint32_t a, uint32_t tix, size_t e) {
         const uint64_t word = *gm(fp.zm + e);
@@ -1504,6 +1536,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         w[i] = pnn[i] ? *gm(fp.zm + pe[i]) : 0ull;
         z[i] = pnn[i] ? *gm(fp.zp + pe[i]) : 0u;
       }
+      s_len4[wv][lane] = lv;
       wave_sync();   // lengths in LDS
 #pragma unroll
       for (int i = 0; i < kP; ++i) {
@@ -1527,6 +1560,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       mask |= (uint64_t)non_zero_residuals(w4) << (16 * k);
     }
     mask &= low_bits(nvalid);
+    s_len4[wv][lane] = lv;
     wave_sync();   // lengths in LDS
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -1538,6 +1572,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   bits += (nvalid - nz) * lens[kRadius];
   uint32_t nz_total;
   const uint32_t rank = wave_exclusive_scan32(nz, nz_total);
+  if (!ok) return;   // a frame that failed earlier (k_tail reports it)
   // the chunk form (dense bytes: every load of the wave is done by now)
   *gm(fp.cmask + (size_t)c * 64 + lane) = mask;
   uint8_t *dst = fp.codes + (size_t)c * kChunk + rank;
@@ -2379,7 +2414,12 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 __global__ __launch_bounds__(256) void k_run_count(BatchPlan bp) {
   const int lane = threadIdx.x & 63;
   const uint32_t item = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (item >= bp.total_chunks) return;
+  if (item >= bp.total_chunks) {
+    // the ROI windows' payload, in the same launch (it needs only k_prep's
+    // peak check, and this kernel leaves HBM bandwidth to spare)
+    roi_copy(bp, item - bp.total_chunks);
+    return;
+  }
   const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, item);
   const FramePlan &fp = bp.frames[f];
   const FrameState *st = fp.st;
@@ -2513,7 +2553,12 @@ __global__ __launch_bounds__(256) void k_run_pack(BatchPlan bp) {
   const int lane = threadIdx.x & 63;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t item = blockIdx.x * kWaves + wv;
-  if (item >= bp.total_chunks) return;
+  if (item >= bp.total_chunks) {
+    // the ROI windows' payload, in the same launch (it needs only k_prep's
+    // peak check, and this kernel leaves HBM bandwidth to spare)
+    roi_copy(bp, item - bp.total_chunks);
+    return;
+  }
   const uint32_t f = find_frame(bp.chunk_prefix, bp.nframes, item);
   const FramePlan &fp = bp.frames[f];
   const FrameState *st = fp.st;
@@ -2581,14 +2626,15 @@ __global__ __launch_bounds__(256) void k_run_pack(BatchPlan bp) {
 
 // -------------------------------------------------------------- launchers
 
-#define RSZ_LAUNCH(name, kern, grid, s, ...)                      \
+#define RSZ_LAUNCH_B(name, kern, grid, block, s, ...)             \
   do {                                                            \
     prof_begin(name, s);                                          \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, __VA_ARGS__); \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, __VA_ARGS__); \
     prof_end(s);                                                  \
     hipError_t e_ = hipGetLastError();                            \
     if (e_ != hipSuccess) return e_;                              \
   } while (0)
+#define RSZ_LAUNCH(name, kern, grid, s, ...) RSZ_LAUNCH_B(name, kern, grid, 256, s, __VA_ARGS__)
 
 hipError_t launch_codebook(const BatchPlan &bp, hipStream_t s) {
   hipLaunchKernelGGL(k_codebook, dim3(bp.nframes), dim3(256), 0, s, bp);
@@ -2616,17 +2662,18 @@ hipError_t launch_debug_codes(const BatchPlan &bp, uint32_t nbins, uint16_t *out
 template <bool DEBUG, int DIM>
 static hipError_t launch_bin(const BatchPlan &bp, uint32_t b, hipStream_t s) {
   if (bp.total_tiles == 0) return hipSuccess;
+  const uint32_t grid = bp.total_tiles;
   switch (b) {
-    case 1: RSZ_LAUNCH("k_bin", (k_bin<1, DEBUG, DIM>), bp.total_tiles, s, bp); break;
+    case 1: RSZ_LAUNCH_B("k_bin", (k_bin<1, DEBUG, DIM>), grid, 64 * bp.bin_waves, s, bp); break;
     case 2:
-      if (!DEBUG && bp.all_vec) RSZ_LAUNCH("k_bin", (k_bin_vec<2, DIM>), bp.total_tiles, s, bp);
-      else RSZ_LAUNCH("k_bin", (k_bin<2, DEBUG, DIM>), bp.total_tiles, s, bp);
+      if (!DEBUG && bp.all_vec) RSZ_LAUNCH_B("k_bin", (k_bin_vec<2, DIM>), grid, 64 * bp.bin_waves, s, bp);
+      else RSZ_LAUNCH_B("k_bin", (k_bin<2, DEBUG, DIM>), grid, 64 * bp.bin_waves, s, bp);
       break;
     case 4:
-      if (!DEBUG && bp.all_vec) RSZ_LAUNCH("k_bin", (k_bin_vec<4, DIM>), bp.total_tiles, s, bp);
-      else RSZ_LAUNCH("k_bin", (k_bin<4, DEBUG, DIM>), bp.total_tiles, s, bp);
+      if (!DEBUG && bp.all_vec) RSZ_LAUNCH_B("k_bin", (k_bin_vec<4, DIM>), grid, 64 * bp.bin_waves, s, bp);
+      else RSZ_LAUNCH_B("k_bin", (k_bin<4, DEBUG, DIM>), grid, 64 * bp.bin_waves, s, bp);
       break;
-    default: RSZ_LAUNCH("k_bin", (k_bin<0, DEBUG, DIM>), bp.total_tiles, s, bp); break;
+    default: RSZ_LAUNCH_B("k_bin", (k_bin<0, DEBUG, DIM>), grid, 64 * bp.bin_waves, s, bp); break;
   }
   return hipSuccess;
 }
@@ -2649,12 +2696,11 @@ hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t dim
 }
 
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s) {
-  BatchPlan bc = bp;   // k_count also copies the verbatim ROI windows
-  bc.roi_in_count = 1;
-  const uint32_t citems = bp.total_chunks + bp.total_peaks;
-  if (citems) {
-    if (bp.all_sparse) RSZ_LAUNCH("k_count", k_count<true>, (citems + kWaves - 1) / kWaves, s, bc);
-    else RSZ_LAUNCH("k_count", k_count<false>, (citems + kWaves - 1) / kWaves, s, bc);
+  // k_count's items: the chunks, then the peaks (ROI payload)
+  const uint32_t cgrid = (bp.total_chunks + bp.total_peaks + kWaves - 1) / kWaves;
+  if (cgrid) {
+    if (bp.all_sparse) RSZ_LAUNCH("k_count", k_count<true>, cgrid, s, bp);
+    else RSZ_LAUNCH("k_count", k_count<false>, cgrid, s, bp);
   }
   RSZ_LAUNCH("k_scan", k_scan, bp.nframes, s, bp);
   if (bp.total_units) {

@@ -18,12 +18,12 @@ constexpr uint64_t kHeader = 80;
 constexpr int kRoiClasses = 33;       // coded ROI: bit lengths 0..32 of the zigzag residual
 constexpr uint64_t kRoiLens = 36;     // their code lengths, padded
 
-// Binning kernel geometry: 4 independent waves per workgroup, each owning a
-// tile of one panel: a segment of up to kMaxTH bin rows x a column group of
-// up to group_strips(b) strips of 64 bin columns.
+// Binning kernel geometry: up to 4 independent waves per workgroup, each
+// owning a tile of one panel: a segment of up to kMaxTH bin rows x a column
+// group of up to group_strips(b) strips of 64 bin columns.
 constexpr int kWaves = 4;
 constexpr int kMaxTH = 32;
-constexpr int kMaskWords = 896;       // per wave: (TH+1)*b rows x (2b*strips+1) words
+constexpr int kMaskWords = 1024;      // per wave: (TH+1)*b rows x (2b*strips+1) words
 constexpr uint64_t kTargetWaves = 8192;         // default tiling: binning waves per batch
 constexpr uint32_t kFixBins3 = 16384;           // k_lorenzo_dims, dim 3: bins per workgroup
 constexpr uint32_t kTileEntries = kMaxTH * 4;   // sparse codes: entries per binning tile
@@ -64,6 +64,7 @@ struct FrameState {
   uint32_t hist[kNumSym];
   uint32_t cw[kNumSym];
   uint8_t lens[kNumSym];
+  double inv[65];      // inv[n] = 1 / (n * 2eb), correctly rounded (k_prep)
 };
 
 // Per-frame constant plan, built on the host and copied to the workspace.
@@ -78,7 +79,6 @@ struct FramePlan {
   uint32_t nstrips, gstrips, cgs;   // strips per panel row, per column group; groups
   int32_t init_status;      // RSZ_OK or RSZ_ERR_ARG
   uint32_t vec;             // rows load as float2/float4 (W % b == 0, aligned)
-  double inv[65];           // inv[n] = 1 / (n * 2eb), correctly rounded
   const float *frame;
   const int32_t *peaks;     // npeaks x (panel,row,col)
   uint8_t *out;
@@ -145,6 +145,7 @@ struct BatchPlan {
   uint32_t total_tiles, total_units, total_peaks, total_chunks;
   uint32_t cpw;                  // chunks encoded by one k_encode workgroup
   uint32_t all_vec;              // every frame's rows load as float2/float4 (k_bin)
+  uint32_t bin_waves;            // waves per k_bin workgroup (1..kWaves)
   uint32_t total_fix;            // workgroups of k_lorenzo_dims (0: every frame is 2D)
   uint32_t roi_coding;           // some frame codes its ROI windows
   uint32_t run_coding;           // some frame codes its Huffman bits' runs
@@ -154,9 +155,8 @@ struct BatchPlan {
   const uint32_t *peak_prefix;   // nframes + 1
   const uint32_t *chunk_prefix;  // nframes + 1
   const uint32_t *fix_prefix;    // nframes + 1 (k_lorenzo_dims workgroups)
-  const uint32_t *count_frame;   // per k_count workgroup: the frame of its first chunk
+  const uint2 *count_frame;       // per k_count workgroup: (frame, chunk) of its first chunk
   uint32_t all_sparse;           // every frame has sparse codes (no dimension 3)
-  uint32_t roi_in_count;         // k_count's items past the chunks copy ROI windows
 };
 
 // Launchers (compress.hip).

@@ -48,7 +48,7 @@ class rsz_decode_desc(C.Structure):
 class rsz_frame_desc(C.Structure):
     _fields_ = [("params", rsz_params), ("frame", C.c_void_p), ("peaks", C.c_void_p),
                 ("npeaks", C.c_uint32), ("tile_rows", C.c_uint32), ("tile_strips", C.c_uint32),
-                ("reserved", C.c_uint32), ("out", C.c_void_p),
+                ("tile_waves", C.c_uint32), ("out", C.c_void_p),
                 ("out_cap", C.c_uint64)]
 
 
@@ -449,7 +449,7 @@ class Batch:
     the Huffman bits verbatim).  Output buffers are sized by
     rsz_max_compressed_bytes and packed into one uint8 tensor."""
 
-    def __init__(self, frames, peaks, prm, tile_rows=0, tile_strips=0):
+    def __init__(self, frames, peaks, prm, tile_rows=0, tile_strips=0, tile_waves=0):
         torch = _torch()
         self.frames = [f.contiguous() for f in frames]
         self.peaks = [pk.to(dtype=torch.int32).reshape(-1, 3).contiguous() for pk in peaks]
@@ -480,6 +480,7 @@ class Batch:
             d.npeaks = self.peaks[i].shape[0]
             d.tile_rows = int(tile_rows)
             d.tile_strips = int(tile_strips)
+            d.tile_waves = int(tile_waves)
             d.out = self.out.data_ptr() + self.offsets[i]
             d.out_cap = caps[i]
             self.descs.append(d)
