@@ -29,16 +29,15 @@ def _gen(i):
     return synth.batch_frame(i, counts)
 
 
-def generate(n, workers):
-    from concurrent.futures import ProcessPoolExecutor
-    import multiprocessing as mp
+def generate(fn, n, workers):
+    """[fn(0), ..., fn(n-1)] on a pool of threads (the generators spend their
+    time in numpy, which releases the interpreter lock); no process is
+    forked, before or after the GPU is initialised."""
+    from concurrent.futures import ThreadPoolExecutor
     if workers <= 1:
-        for i in range(n):
-            yield _gen(i)
-        return
-    with ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
-        for item in ex.map(_gen, range(n), chunksize=4):
-            yield item
+        return [fn(i) for i in range(n)]
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(fn, range(n)))
 
 
 def _gen_pool(k):
@@ -55,16 +54,13 @@ def _gen_pool(k):
     return synth.jungfrau_frame(k, shape=shape, npeaks=npk, workload=synth.W_SERVE)
 
 
-def serving_section(args, torch, dev):
+def serving_section(args, torch, dev, pool):
     """Poisson-arrival serving of mixed geometries: continuous batching vs one
-    frame per launch at the same offered load, plus a backlogged run."""
+    frame per launch at the same offered load, plus a backlogged run.  pool:
+    the resident frames (host arrays, drawn before the GPU was touched)."""
     import numpy as np
-    from concurrent.futures import ProcessPoolExecutor
-    import multiprocessing as mp
     from paper_2206_11297_amd import serve
-    npool = args.serve_pool
-    with ProcessPoolExecutor(min(args.workers, npool), mp_context=mp.get_context("fork")) as ex:
-        pool = list(ex.map(_gen_pool, range(npool)))
+    npool = len(pool)
     gpool = [(torch.from_numpy(f).to(dev), torch.from_numpy(p).to(dev)) for f, p in pool]
     torch.cuda.synchronize()
     out = {"workload": f"serving: Poisson arrivals, pool of {npool} resident frames cycling "
@@ -194,7 +190,7 @@ def timed_steps(torch, B, steps):
     return el, {k: round(v[1] / v[0], 4) for k, v in prof.items()}
 
 
-def lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips, raw_bytes):
+def lorenzo_dims_section(args, torch, frames, peaks, prm, knobs, raw_bytes):
     """The same batch with the Lorenzo predictor in one and three dimensions
     (Sec. VI): whole-path GB/s, compression ratio and per-kernel times."""
     import numpy as np
@@ -202,7 +198,7 @@ def lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips
     out = {}
     npix = raw_bytes // 4
     for dim in args.dims:
-        B = rsz.Batch(frames, peaks, prm + (dim,), tile_rows=tile_rows, tile_strips=tile_strips)
+        B = rsz.Batch(frames, peaks, prm + (dim,), **knobs)
         for _ in range(2):
             B.run()
         torch.cuda.synchronize()
@@ -221,15 +217,13 @@ def lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips
     return out
 
 
-def coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_strips, roi, run,
-                   steps, label):
+def coding_section(args, torch, frames, peaks, prm, raw_bytes, knobs, roi, run, steps, label):
     """The same batch with the ROI windows coded losslessly instead of stored
     verbatim (roi) and/or the Huffman bits' zero runs Rice coded (run):
     whole-path GB/s, compression ratio and per-kernel times."""
     import numpy as np
     from paper_2206_11297_amd import rsz
-    B = rsz.Batch(frames, peaks, prm + (2, roi, run), tile_rows=tile_rows,
-                  tile_strips=tile_strips)
+    B = rsz.Batch(frames, peaks, prm + (2, roi, run), **knobs)
     for _ in range(2):
         B.run()
     torch.cuda.synchronize()
@@ -251,7 +245,7 @@ def coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_s
     return out
 
 
-def peaks_section(args, torch, frames, prm, raw_bytes, tile_rows, tile_strips):
+def peaks_section(args, torch, frames, prm, raw_bytes, knobs):
     """Peak finding on the GPU over the same batch (the step before the path,
     Sec. IV-B parameters), and the frames-in, streams-out pipeline: peaks found,
     counts read back, frames with fewer than 10 peaks rejected (Sec. IV),
@@ -287,8 +281,7 @@ def peaks_section(args, torch, frames, prm, raw_bytes, tile_rows, tile_strips):
            "peaks_per_frame_mean": round(float(counts.mean()), 2),
            "hits": len(hits), "frames": len(frames), "nhr_min_peaks": 10}
     if hits:
-        B = rsz.Batch([frames[i] for i in hits], [P.peaks(i, counts) for i in hits], prm,
-                      tile_rows=tile_rows, tile_strips=tile_strips)
+        B = rsz.Batch([frames[i] for i in hits], [P.peaks(i, counts) for i in hits], prm, **knobs)
         for _ in range(2):
             P.run()
             c2 = P.counts.cpu().numpy()
@@ -459,6 +452,156 @@ def traffic_record(kernel):
     return rec
 
 
+def _child_processes():
+    """Processes this one has started that are still alive."""
+    try:
+        import psutil
+        return len(psutil.Process().children(recursive=True))
+    except Exception:
+        return None
+
+
+def _path_roofline(raw_bytes, out_bytes, el, kms):
+    """Whole-path and dominant-kernel roofline figures of one line: the path
+    must at least read every raw frame byte and write every stream byte once
+    (4 + s bytes a pixel, s the output bytes a pixel); k_bin reads the raw
+    frames once."""
+    path_bytes = raw_bytes + out_bytes
+    out = {"path_achieved_gbps": round(path_bytes / el / 1e9, 1),
+           "path_frac": round(path_bytes / el / 1e9 / 8000.0, 4),
+           "out_bytes_per_pixel": round(4.0 * out_bytes / raw_bytes, 5)}
+    kb = kms.get("k_bin")
+    if kb:
+        out["k_bin_frac"] = round(raw_bytes / (kb * 1e-3) / 1e9 / 8000.0, 4)
+    return out
+
+
+def _line(torch, B, steps, raw_bytes, label):
+    """Timed steps of batch B (already warmed up and checked): GB/s,
+    roofline fractions, compression ratio and per-kernel times."""
+    import numpy as np
+    el, kms = timed_steps(torch, B, steps)
+    sizes = B.sizes.cpu().numpy().astype(np.int64)
+    out = {"value": round(raw_bytes / el / 1e9, 2), "unit": "GB/s",
+           "ms_per_step": round(el * 1e3, 4), "steps": steps,
+           "compression_ratio_u16_aggregate": round(float(raw_bytes / 2 / sizes.sum()), 3)}
+    out.update(_path_roofline(raw_bytes, int(sizes.sum()), el, kms))
+    out["kernel_ms"] = kms
+    print(f"[bench] {label}: {out['value']} GB/s, path {out['path_frac']}, k_bin "
+          f"{out.get('k_bin_frac')}, CR {out['compression_ratio_u16_aggregate']}",
+          file=sys.stderr, flush=True)
+    return out
+
+
+def _warm(torch, B, label, n=2, launch=None):
+    for _ in range(n):
+        (launch or B.run)()
+    torch.cuda.synchronize()
+    st = B.status.cpu().numpy()
+    assert (st == 0).all(), f"{label}: statuses {set(st.tolist())}"
+
+
+def cspad_bounds_section(args, torch, frames, peaks, knobs, raw_bytes):
+    """The 1000-frame CSPAD batch at the other error bounds (1, 5, 20 ADU),
+    one batched launch a step."""
+    from paper_2206_11297_amd import rsz
+    out = {}
+    for eb in (1.0, 5.0, 20.0):
+        B = rsz.Batch(frames, peaks, (WINDOW, BIN, eb, rsz.RSZ_BIN_BACKGROUND), **knobs)
+        _warm(torch, B, f"cspad eb {eb:g}")
+        out[f"cspad-batch-{len(frames)}_eb{eb:g}"] = _line(torch, B, args.config_steps, raw_bytes,
+                                                           f"cspad eb {eb:g}")
+        del B
+        torch.cuda.empty_cache()
+    return out
+
+
+def jungfrau4m_section(args, torch, dev):
+    """Batches of Jungfrau-4M-like frames (8x512x1024 f32, 20-800 peaks) at
+    window {11, 25} x bin {2, 4}, eb 10 ADU, each with the autotuned tile
+    shape and waves per workgroup."""
+    from paper_2206_11297_amd import autotune, rsz, synth
+    n = args.jf4m_frames
+    host = generate(lambda i: synth.jungfrau_frame(i, workload=synth.W_JF), n, args.workers)
+    frames = [torch.from_numpy(f).to(dev) for f, _ in host]
+    peaks = [torch.from_numpy(p).to(dev) for _, p in host]
+    del host
+    raw_bytes = sum(f.numel() * 4 for f in frames)
+    out = {}
+    for w in (11, 25):
+        for b in (2, 4):
+            prm = (w, b, 10.0, rsz.RSZ_BIN_BACKGROUND)
+            label = f"jungfrau4m-{n}_w{w}_b{b}"
+            t = autotune.tune(frames, peaks, prm, reps=3, budget_s=args.config_autotune_seconds)
+            knobs = dict(zip(("tile_rows", "tile_strips", "tile_waves"), t["best"]))
+            B = rsz.Batch(frames, peaks, prm, **knobs)
+            _warm(torch, B, label)
+            out[label] = _line(torch, B, args.config_steps, raw_bytes, label)
+            out[label]["tile"] = {"best": list(t["best"]), "from_table": bool(t.get("cached")),
+                                  "autotuned": not t.get("cached"),
+                                  "default_ms": t.get("default_ms"), "ms": t.get("ms")}
+            del B
+            torch.cuda.empty_cache()
+    del frames, peaks
+    torch.cuda.empty_cache()
+    return out
+
+
+def jungfrau16m_graph_section(args, torch, dev):
+    """Batches of Jungfrau-16M-like frames (16x512x1024 f32, 0-3000 peaks),
+    window 11, bin 2, eb 1 and 10 ADU: the prepared batch captured in a HIP
+    graph and replayed, each replay recomputing every stream; the same
+    streams decoded in one batched call."""
+    import numpy as np
+    from paper_2206_11297_amd import rsz, synth
+    n = args.jf16m_frames
+    host = generate(lambda i: synth.jungfrau_frame(i, shape=synth.JUNGFRAU16M,
+                                                   workload=synth.W_JF16, max_peaks=3000),
+                    n, args.workers)
+    frames = [torch.from_numpy(f).to(dev) for f, _ in host]
+    peaks = [torch.from_numpy(p).to(dev) for _, p in host]
+    del host
+    raw_bytes = sum(f.numel() * 4 for f in frames)
+    out = {}
+    for eb in (1.0, 10.0):
+        label = f"jungfrau16m-{n}_graph_eb{eb:g}"
+        B = rsz.Batch(frames, peaks, (11, 2, eb, rsz.RSZ_BIN_BACKGROUND))
+        B.prepare()
+        B.graph()
+        _warm(torch, B, label, launch=B.replay)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.config_steps):
+            B.replay()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.config_steps
+        rsz.rsz_profile_enable(True)
+        for _ in range(2):
+            B.launch()
+        torch.cuda.synchronize()
+        kms = {k: round(v[1] / v[0], 4) for k, v in rsz.rsz_profile_read().items()}
+        rsz.rsz_profile_enable(False)
+        sizes = B.sizes.cpu().numpy().astype(np.int64)
+        line = {"value": round(raw_bytes / el / 1e9, 2), "unit": "GB/s",
+                "ms_per_step": round(el * 1e3, 4), "steps": args.config_steps,
+                "mode": "graph replay",
+                "compression_ratio_u16_aggregate": round(float(raw_bytes / 2 / sizes.sum()), 3)}
+        line.update(_path_roofline(raw_bytes, int(sizes.sum()), el, kms))
+        line["kernel_ms"] = kms
+        line["kernel_ms_source"] = "HIP events around every launch of 2 eager launches"
+        line["decompress_batched"] = batched_decode(torch, B, sizes, 3, raw_bytes)
+        print(f"[bench] {label}: {line['value']} GB/s, path {line['path_frac']}, k_bin "
+              f"{line.get('k_bin_frac')}, CR {line['compression_ratio_u16_aggregate']}; batched "
+              f"decompression {line['decompress_batched']['gbps']} GB/s",
+              file=sys.stderr, flush=True)
+        out[label] = line
+        del B
+        torch.cuda.empty_cache()
+    del frames, peaks
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -501,6 +644,15 @@ def main():
                          "(0: skip them)")
     ap.add_argument("--peaks-steps", type=int, default=10,
                     help="steps of the peak-finding section (0: skip it)")
+    ap.add_argument("--config-steps", type=int, default=10,
+                    help="steps of each line of the other workloads: the CSPAD batch at eb "
+                         "1/5/20, Jungfrau-4M batches over window x bin, the Jungfrau-16M "
+                         "graph replays (0: skip them)")
+    ap.add_argument("--jf4m-frames", type=int, default=256)
+    ap.add_argument("--jf16m-frames", type=int, default=512)
+    ap.add_argument("--config-autotune-seconds", type=float, default=6.0,
+                    help="autotuner budget per Jungfrau-4M line when the shipped table has "
+                         "no entry for it")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary)
@@ -513,9 +665,10 @@ def main():
 
     import numpy as np
 
-    # frames are drawn before the GPU is touched (fork-safe worker pool)
+    # frames are drawn before the GPU is touched (threads; nothing is forked)
     t0 = time.time()
-    host = list(generate(args.frames, args.workers))
+    host = generate(_gen, args.frames, args.workers)
+    serve_pool = generate(_gen_pool, args.serve_pool, args.workers) if args.serve_rates else None
     gen_s = time.time() - t0
     print(f"[bench] generated {len(host)} frames in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
@@ -537,8 +690,8 @@ def main():
               f"(default {tile['default_ms']} ms, {len(tile['table'])} shapes)",
               file=sys.stderr, flush=True)
     tile_rows, tile_strips, tile_waves = (list(tile["best"]) + [0])[:3] if tile else (0, 0, 0)
-    B = rsz.Batch(frames, peaks, prm, tile_rows=tile_rows, tile_strips=tile_strips,
-                  tile_waves=tile_waves)
+    knobs = dict(tile_rows=tile_rows, tile_strips=tile_strips, tile_waves=tile_waves)
+    B = rsz.Batch(frames, peaks, prm, **knobs)
     raw_bytes = sum(f.numel() * 4 for f in frames)
     npix = raw_bytes // 4
 
@@ -601,6 +754,12 @@ def main():
             "traffic": None if tr is None else tr["hbm_bytes_per_launch"],
             "kernel": "k_bin", "algorithmic_bytes_per_launch": raw_bytes,
             "avg_launch_ms": round(kb_ms, 4)}
+    # the whole path against the least traffic it needs: every raw byte read
+    # and every stream byte written once, in the timed step time
+    path = _path_roofline(raw_bytes, int(sizes.sum()), elapsed / args.steps, {})
+    roof["path_frac"] = path["path_frac"]
+    roof["path_achieved_gbps"] = path["path_achieved_gbps"]
+    roof["path_bytes_per_step"] = raw_bytes + int(sizes.sum())
 
     # one-frame-per-launch latency at the same bound (synchronous calls)
     lat = []
@@ -626,17 +785,25 @@ def main():
     cpu = cpu_baseline(args, host, B, sizes)
 
     decomp = decompress_section(args, torch, dev, B, sizes, host) if args.decompress_frames else None
-    serving = serving_section(args, torch, dev) if args.serve_rates else None
-    dims = lorenzo_dims_section(args, torch, frames, peaks, prm, tile_rows, tile_strips,
+    serving = serving_section(args, torch, dev, serve_pool) if args.serve_rates else None
+    dims = lorenzo_dims_section(args, torch, frames, peaks, prm, knobs,
                                 raw_bytes) if args.dims else None
-    roi = coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_strips, 1, 0,
+    roi = coding_section(args, torch, frames, peaks, prm, raw_bytes, knobs, 1, 0,
                          args.roi_steps, "roi coding") if args.roi_steps else None
-    runs = coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_strips, 0,
+    runs = coding_section(args, torch, frames, peaks, prm, raw_bytes, knobs, 0,
                           1, args.run_steps, "run coding") if args.run_steps else None
-    both = coding_section(args, torch, frames, peaks, prm, raw_bytes, tile_rows, tile_strips, 1,
+    both = coding_section(args, torch, frames, peaks, prm, raw_bytes, knobs, 1,
                           1, args.run_steps, "roi + run coding") if args.run_steps else None
-    pk = peaks_section(args, torch, frames, prm, raw_bytes, tile_rows,
-                       tile_strips) if args.peaks_steps else None
+    pk = peaks_section(args, torch, frames, prm, raw_bytes, knobs) if args.peaks_steps else None
+    nfr = len(frames)
+    cfg = cspad_bounds_section(args, torch, frames, peaks, knobs, raw_bytes) \
+        if args.config_steps else None
+    if cfg is not None:
+        # the larger workloads need the CSPAD batch's memory
+        del B, frames, peaks
+        torch.cuda.empty_cache()
+        cfg.update(jungfrau4m_section(args, torch, dev))
+        cfg.update(jungfrau16m_graph_section(args, torch, dev))
 
     line = {
         "metric": "raw-frame GB/s compressed (1 GPU) at eb=10 ADU; compression ratio; "
@@ -644,12 +811,12 @@ def main():
         "value": round(gbps, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{WORKLOAD}-{len(frames)}: {len(frames)} frames "
+        "config": {"workload": f"{WORKLOAD}-{nfr}: {nfr} frames "
                                f"{SHAPE[0]}x{SHAPE[1]}x{SHAPE[2]} f32, Poisson(60) peaks, "
                                "20% non-hit, window 17, bin 2x2, eb 10 ADU, one batched launch",
-                   "frames": len(frames), "raw_bytes": raw_bytes,
-                   "tile": {"rows": tile_rows, "strips": tile_strips,
-                            "autotuned": tile is not None,
+                   "frames": nfr, "raw_bytes": raw_bytes,
+                   "tile": {"rows": tile_rows, "strips": tile_strips, "waves": tile_waves,
+                            "autotuned": bool(tile and not tile.get("cached")),
                             "from_table": bool(tile and tile.get("cached")),
                             "default_ms": tile["default_ms"] if tile else None,
                             "shapes_timed": len(tile["table"]) if tile else 0}},
@@ -673,6 +840,7 @@ def main():
         "run_coding": runs,
         "roi_and_run_coding": both,
         "peak_finding": pk,
+        "configs": cfg,
     }
     if serving:
         top = serving.get(f"{max(args.serve_rates):g}kHz")
@@ -680,6 +848,7 @@ def main():
             line["latency_ms"]["serving_p50"] = top["continuous_batching"]["p50_ms"]
             line["latency_ms"]["serving_p99"] = top["continuous_batching"]["p99_ms"]
             line["latency_ms"]["serving_rate_khz"] = max(args.serve_rates)
+    line["procs_at_end"] = _child_processes()
     print(json.dumps(line), flush=True)
 
 

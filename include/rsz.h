@@ -308,7 +308,10 @@ int rsz_find_peaks_batch(const rsz_peak_params *q, uint32_t nframes, const rsz_p
  *   mask: panels*height*ceil(width/32) u32, bit j%32 of word j/32 = ROI pixel.
  *   S: nbins f64 sums, n: nbins u32 counts, q: nbins i32 quantised bins,
  *   codes: nbins u16, hist: 1024 u32, lens: 1024 u8, cw: 1024 u32 canonical
- *   codewords.  Bins are ordered (panel, bin row, bin column). */
+ *   codewords; n_out: 1 u32, the number of outliers (bins whose Lorenzo
+ *   residual lies outside the codes' range, Sec. V-C), out_idx: up to nbins
+ *   u32 their bin indices in increasing order, out_res: up to nbins i32 their
+ *   residuals.  Bins are ordered (panel, bin row, bin column). */
 typedef struct {
   uint32_t *mask;
   double *S;
@@ -318,6 +321,9 @@ typedef struct {
   uint32_t *hist;
   uint8_t *lens;
   uint32_t *cw;
+  uint32_t *n_out;
+  uint32_t *out_idx;
+  int32_t *out_res;
 } rsz_debug_bufs;
 
 /* Runs the compression kernels of one frame up to the codebook and copies the

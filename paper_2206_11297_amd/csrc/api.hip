@@ -808,6 +808,9 @@ static int single_frame(const rsz_params *p, const float *d_frame, const rsz_pea
     const FrameState *fs = fp->st;
     if (dbg->codes && launch_debug_codes(hp.bp, fp->nbins, dbg->codes, s) != hipSuccess)
       return RSZ_ERR_HIP;
+    if ((dbg->n_out || dbg->out_idx || dbg->out_res) &&
+        launch_debug_outliers(hp.bp, dbg->n_out, dbg->out_idx, dbg->out_res, s) != hipSuccess)
+      return RSZ_ERR_HIP;
     if (dbg->hist && hipMemcpyAsync(dbg->hist, fs->hist, 4 * kNumSym, hipMemcpyDeviceToDevice, s))
       return RSZ_ERR_HIP;
     if (dbg->lens && hipMemcpyAsync(dbg->lens, fs->lens, kNumSym, hipMemcpyDeviceToDevice, s))

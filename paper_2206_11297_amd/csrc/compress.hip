@@ -2652,6 +2652,43 @@ __global__ __launch_bounds__(256) void k_debug_codes(BatchPlan bp, uint16_t *out
   }
 }
 
+// The outliers of frame 0 (bins whose residual has no code) in bin order:
+// their count, indices and residuals, from the codes k_bin leaves (the
+// outlier section of the stream holds the same list).  One workgroup.
+__global__ __launch_bounds__(256) void k_debug_outliers(BatchPlan bp, uint32_t *n_out,
+                                                        uint32_t *idx, int32_t *res) {
+  const FramePlan &fp = bp.frames[0];
+  __shared__ uint32_t s_tmp[4];
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < fp.nbins; base += 256) {
+    const uint32_t g = base + threadIdx.x;
+    uint32_t o = 0;
+    int32_t r = 0;
+    if (g < fp.nbins) {
+      const uint4 v = code_group(fp, g & ~15u);
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+      if (((w4[(g >> 2) & 3] >> (8 * (g & 3))) & 0xFFu) == 0) {
+        r = fp.rbuf[g];
+        o = code_from_residual(r) == 0;
+      }
+    }
+    uint32_t tot;
+    const uint32_t at = carry + block_exclusive_scan<uint32_t>(o, s_tmp, tot);
+    if (o) {
+      if (idx) idx[at] = g;
+      if (res) res[at] = r;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && n_out) *n_out = carry;
+}
+
+hipError_t launch_debug_outliers(const BatchPlan &bp, uint32_t *n_out, uint32_t *idx,
+                                 int32_t *res, hipStream_t s) {
+  hipLaunchKernelGGL(k_debug_outliers, dim3(1), dim3(256), 0, s, bp, n_out, idx, res);
+  return hipGetLastError();
+}
+
 hipError_t launch_debug_codes(const BatchPlan &bp, uint32_t nbins, uint16_t *out, hipStream_t s) {
   const uint32_t grid = std::max(1u, std::min(4096u, (nbins + 255) / 256));
   hipLaunchKernelGGL(k_debug_codes, dim3(grid), dim3(256), 0, s, bp, out);

@@ -165,6 +165,8 @@ struct BatchPlan {
 hipError_t launch_compress_front_b(const BatchPlan &bp, uint32_t b, uint32_t dim, hipStream_t s,
                                    bool debug);
 hipError_t launch_debug_codes(const BatchPlan &bp, uint32_t nbins, uint16_t *out, hipStream_t s);
+hipError_t launch_debug_outliers(const BatchPlan &bp, uint32_t *n_out, uint32_t *idx,
+                                 int32_t *res, hipStream_t s);
 hipError_t launch_codebook(const BatchPlan &bp, hipStream_t s);
 // k_count + k_scan + k_encode + k_tail + k_roi.
 hipError_t launch_compress_back(const BatchPlan &bp, hipStream_t s);

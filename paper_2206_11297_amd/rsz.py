@@ -16,7 +16,8 @@ RSZ_ERR_CAPACITY, RSZ_ERR_CORRUPT, RSZ_ERR_WORKSPACE, RSZ_ERR_HIP = -4, -5, -6, 
 RSZ_BIN_BACKGROUND, RSZ_BIN_ALL = 0, 1
 
 EXPORTS = ["rsz_status_string", "rsz_max_compressed_bytes", "rsz_workspace_bytes",
-           "rsz_compress", "rsz_batch_workspace_bytes", "rsz_compress_batch",
+           "rsz_compress", "rsz_batch_workspace_bytes",
+           "rsz_compress_batch",
            "rsz_batch_prepare", "rsz_batch_launch", "rsz_batch_graph_create",
            "rsz_graph_launch", "rsz_graph_destroy",
            "rsz_stream_info", "rsz_decompress_workspace_bytes", "rsz_decompress",
@@ -59,7 +60,8 @@ class rsz_batch_plan(C.Structure):
 class rsz_debug_bufs(C.Structure):
     _fields_ = [("mask", C.c_void_p), ("S", C.c_void_p), ("n", C.c_void_p), ("q", C.c_void_p),
                 ("codes", C.c_void_p), ("hist", C.c_void_p), ("lens", C.c_void_p),
-                ("cw", C.c_void_p)]
+                ("cw", C.c_void_p), ("n_out", C.c_void_p), ("out_idx", C.c_void_p),
+                ("out_res", C.c_void_p)]
 
 
 class rsz_peak_params(C.Structure):
@@ -426,9 +428,13 @@ def debug_intermediates(frame, peaks, window=17, bin=2, eb=10.0, bin_mode=RSZ_BI
              codes=torch.zeros(nb, dtype=torch.int16, device=dev),
              hist=torch.zeros(1024, dtype=torch.int32, device=dev),
              lens=torch.zeros(1024, dtype=torch.uint8, device=dev),
-             cw=torch.zeros(1024, dtype=torch.int32, device=dev))
+             cw=torch.zeros(1024, dtype=torch.int32, device=dev),
+             n_out=torch.zeros(1, dtype=torch.int32, device=dev),
+             out_idx=torch.zeros(max(nb, 1), dtype=torch.int32, device=dev),
+             out_res=torch.zeros(max(nb, 1), dtype=torch.int32, device=dev))
     bufs = rsz_debug_bufs(*[d[k].data_ptr() for k in
-                            ("mask", "S", "n", "q", "codes", "hist", "lens", "cw")])
+                            ("mask", "S", "n", "q", "codes", "hist", "lens", "cw", "n_out",
+                             "out_idx", "out_res")])
     st, wsb = rsz_workspace_bytes(p, npk)
     if st:
         raise RszError(st, "rsz_workspace_bytes")

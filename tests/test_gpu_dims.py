@@ -40,6 +40,11 @@ def _check_all(torch, frame, peaks, w, b, eb, mode, dim, intermediates=True):
         np.testing.assert_array_equal(d["codes"].cpu().numpy().view(np.uint16), ref["codes"])
         np.testing.assert_array_equal(d["hist"].cpu().numpy().view(np.uint32), ref["hist"])
         np.testing.assert_array_equal(d["lens"].cpu().numpy(), ref["lens"])
+        n_out = int(d["n_out"].cpu()[0])
+        assert n_out == ref["n_out"]
+        np.testing.assert_array_equal(d["out_idx"][:n_out].cpu().numpy().view(np.uint32),
+                                      ref["out_idx"])
+        np.testing.assert_array_equal(d["out_res"][:n_out].cpu().numpy(), ref["out_res"])
     st, sref, _ = O.compress(p, frame, peaks)
     assert st == O.OK
     got = rsz.compress(_gpu(torch, frame), _gpu(torch, peaks), w, b, eb, mode, dim=dim)

@@ -47,6 +47,11 @@ def _check_intermediates(torch, frame, peaks, w, b, eb, mode):
     np.testing.assert_array_equal(d["hist"].cpu().numpy().view(np.uint32), ref["hist"])
     np.testing.assert_array_equal(d["lens"].cpu().numpy(), ref["lens"])
     np.testing.assert_array_equal(d["cw"].cpu().numpy().view(np.uint32), ref["cw"])
+    n_out = int(d["n_out"].cpu()[0])
+    assert n_out == ref["n_out"]
+    np.testing.assert_array_equal(d["out_idx"][:n_out].cpu().numpy().view(np.uint32),
+                                  ref["out_idx"])
+    np.testing.assert_array_equal(d["out_res"][:n_out].cpu().numpy(), ref["out_res"])
 
 
 TINY = [
@@ -69,6 +74,8 @@ TINY = [
     (16, (1, 64, 1030), 15, 25, 8, 0.3, "normal"),
     (17, (2, 90, 200), 9, 6, 6, 1.0, "normal"),
     (18, (1, 70, 500), 9, 8, 7, 1.0, "normal"),
+    # a fine bound: about half the bins are outliers
+    (19, (2, 80, 300), 10, 7, 2, 0.02, "normal"),
 ]
 
 
