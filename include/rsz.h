@@ -133,6 +133,26 @@ int rsz_compress(const rsz_params *p, const float *d_frame, const rsz_peak *d_pe
                  uint32_t npeaks, void *d_out, uint64_t out_cap, uint64_t *h_out_bytes,
                  void *d_ws, uint64_t ws_bytes, void *stream);
 
+/* rsz_compress without a workspace argument, for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no hipMalloc, hipFree, hipHostMalloc or other
+ * allocating routine.  Its workspace is a static device array of
+ * RSZ_NOALLOC_SCRATCH_BYTES in the library's code object, one per GPU the
+ * library runs on, held until the process ends; a frame whose
+ * rsz_workspace_bytes exceeds it gives RSZ_ERR_WORKSPACE before any work is
+ * queued (64 MiB covers e.g. a 32x512x1024 frame at bin 2).  The array keeps
+ * the last call's contents, which the path never reads before writing.
+ * Every call on a GPU shares that GPU's array, so two calls overlapping on
+ * one GPU would race: the library holds a per-GPU lock for the whole call,
+ * which (like rsz_compress) returns only after `stream` has finished its
+ * work.  Other arguments, results and errors as rsz_compress; the stream
+ * must belong to the current device.  Not for use under stream capture (the
+ * call synchronizes). */
+#define RSZ_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int rsz_compress_noalloc(const rsz_params *p, const float *d_frame, const rsz_peak *d_peaks,
+                         uint32_t npeaks, void *d_out, uint64_t out_cap, uint64_t *h_out_bytes,
+                         void *stream);
+
 /* One frame of a batch.  out/out_cap: that frame's own output buffer
  * (device); the frames of a batch may have different shapes, parameters and
  * peak counts.  tile_rows, tile_strips: tuning knobs of the binning kernel's

@@ -490,11 +490,18 @@ static_assert(sizeof(PlanRecord) <= sizeof(rsz_batch_plan), "plan record too lar
 // Queue the whole path for a batch; results land in res_bytes/res_status.
 static int enqueue(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_bytes,
                    int32_t *res_status, void *ws, uint64_t ws_bytes, hipStream_t s,
-                   const rsz_debug_bufs *dbg, bool front_only, HostPlan &hp) {
+                   const rsz_debug_bufs *dbg, bool front_only, HostPlan &hp,
+                   bool direct_copy = false) {
   const int st = build_plan(nframes, d, res_bytes, res_status, (uint8_t *)ws, ws_bytes,
                             0, hp, nullptr, dbg);
   if (st) return st;
-  if (stage_to_device(ws, hp.bytes.data(), hp.bytes.size(), s) != RSZ_OK) return RSZ_ERR_HIP;
+  // direct_copy: the plan goes straight from hp (which the caller keeps
+  // until the stream has finished) instead of through the pinned staging
+  // slots, which may grow
+  if (direct_copy ? hipMemcpyAsync(ws, hp.bytes.data(), hp.bytes.size(), hipMemcpyHostToDevice,
+                                   s) != hipSuccess
+                  : stage_to_device(ws, hp.bytes.data(), hp.bytes.size(), s) != RSZ_OK)
+    return RSZ_ERR_HIP;
   if (launch_compress_front_b(hp.bp, hp.common_b, hp.common_dim, s, dbg != nullptr) !=
       hipSuccess)
     return RSZ_ERR_HIP;
@@ -720,6 +727,32 @@ static int decode_streams(uint32_t n, const DecodeItem *it, uint8_t *ws, uint64_
 
 using namespace rsz;
 
+// The workspace of rsz_compress_noalloc: one array per GPU, in the code
+// object, so that the call allocates nothing.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is only a stand-in);
+// it uses the device address that hipGetSymbolAddress returns for the
+// current GPU, looked up once per device.
+static __device__ __align__(256) uint8_t scratch[RSZ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_init_mu;
+std::mutex g_scratch_mu[kMaxDevices];
+void *g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+// The current GPU's address of `scratch` (dev is the current device).
+static int scratch_address(int dev, void **ptr) {
+  std::lock_guard<std::mutex> lk(g_scratch_init_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RSZ_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return RSZ_OK;
+}
+
 extern "C" {
 
 const char *rsz_status_string(int s) {
@@ -783,7 +816,8 @@ int rsz_batch_workspace_bytes(uint32_t nframes, const rsz_frame_desc *h_descs, u
 
 static int single_frame(const rsz_params *p, const float *d_frame, const rsz_peak *d_peaks,
                         uint32_t npeaks, void *d_out, uint64_t out_cap, uint64_t *h_out_bytes,
-                        void *d_ws, uint64_t ws_bytes, hipStream_t s, const rsz_debug_bufs *dbg) {
+                        void *d_ws, uint64_t ws_bytes, hipStream_t s, const rsz_debug_bufs *dbg,
+                        bool direct_copy = false) {
   int st = check_params(p, npeaks);
   if (st) return st;
   if (!d_frame || !d_ws || (npeaks && !d_peaks) || (!dbg && (!d_out || !h_out_bytes)))
@@ -800,7 +834,7 @@ static int single_frame(const rsz_params *p, const float *d_frame, const rsz_pea
   rsz_frame_desc d = one_desc(p, d_frame, d_peaks, npeaks, d_out ? d_out : (void *)d_ws, out_cap);
   HostPlan hp;
   st = enqueue(1, &d, res_bytes, res_status, d_ws, need - single_extra(), s, dbg, dbg != nullptr,
-               hp);
+               hp, direct_copy);
   if (st) return st;
   if (dbg) {
     // the codebook intermediates sit in the frame's state and region
@@ -836,6 +870,26 @@ int rsz_compress(const rsz_params *p, const float *d_frame, const rsz_peak *d_pe
                  void *d_ws, uint64_t ws_bytes, void *stream) {
   return single_frame(p, d_frame, d_peaks, npeaks, d_out, out_cap, h_out_bytes, d_ws, ws_bytes,
                       (hipStream_t)stream, nullptr);
+}
+
+int rsz_compress_noalloc(const rsz_params *p, const float *d_frame, const rsz_peak *d_peaks,
+                         uint32_t npeaks, void *d_out, uint64_t out_cap, uint64_t *h_out_bytes,
+                         void *stream) {
+  int st = check_params(p, npeaks);
+  if (st) return st;
+  uint64_t need = 0;
+  rsz_workspace_bytes(p, npeaks, &need);
+  if (need > RSZ_NOALLOC_SCRATCH_BYTES) return RSZ_ERR_WORKSPACE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RSZ_ERR_HIP;
+  void *ws = nullptr;
+  st = scratch_address(dev, &ws);
+  if (st) return st;
+  // the call waits for its own kernels, so holding the device's lock keeps
+  // calls from several host threads off each other's scratch
+  std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+  return single_frame(p, d_frame, d_peaks, npeaks, d_out, out_cap, h_out_bytes, ws,
+                      RSZ_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream, nullptr, true);
 }
 
 int rsz_debug_intermediates(const rsz_params *p, const float *d_frame, const rsz_peak *d_peaks,

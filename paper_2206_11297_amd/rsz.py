@@ -16,7 +16,7 @@ RSZ_ERR_CAPACITY, RSZ_ERR_CORRUPT, RSZ_ERR_WORKSPACE, RSZ_ERR_HIP = -4, -5, -6, 
 RSZ_BIN_BACKGROUND, RSZ_BIN_ALL = 0, 1
 
 EXPORTS = ["rsz_status_string", "rsz_max_compressed_bytes", "rsz_workspace_bytes",
-           "rsz_compress", "rsz_batch_workspace_bytes",
+           "rsz_compress", "rsz_compress_noalloc", "rsz_batch_workspace_bytes",
            "rsz_compress_batch",
            "rsz_batch_prepare", "rsz_batch_launch", "rsz_batch_graph_create",
            "rsz_graph_launch", "rsz_graph_destroy",
@@ -96,6 +96,7 @@ def lib():
         L.rsz_max_compressed_bytes.argtypes = [P(rsz_params), u32, P(u64)]
         L.rsz_workspace_bytes.argtypes = [P(rsz_params), u32, P(u64)]
         L.rsz_compress.argtypes = [P(rsz_params), vp, vp, u32, vp, u64, P(u64), vp, u64, vp]
+        L.rsz_compress_noalloc.argtypes = [P(rsz_params), vp, vp, u32, vp, u64, P(u64), vp]
         L.rsz_batch_workspace_bytes.argtypes = [u32, P(rsz_frame_desc), P(u64)]
         L.rsz_compress_batch.argtypes = [u32, P(rsz_frame_desc), vp, vp, vp, u64, vp]
         L.rsz_batch_prepare.argtypes = [u32, P(rsz_frame_desc), vp, vp, vp, u64, vp,
@@ -154,6 +155,17 @@ def rsz_compress(p, d_frame, d_peaks, npeaks, d_out, out_cap, d_ws, ws_bytes, st
     nbytes = C.c_uint64(0)
     st = lib().rsz_compress(C.byref(p), d_frame, d_peaks, npeaks, d_out, out_cap,
                             C.byref(nbytes), d_ws, ws_bytes, stream)
+    return st, nbytes.value
+
+
+# RSZ_NOALLOC_SCRATCH_BYTES: the workspace size rsz_compress_noalloc holds per GPU
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def rsz_compress_noalloc(p, d_frame, d_peaks, npeaks, d_out, out_cap, stream):
+    nbytes = C.c_uint64(0)
+    st = lib().rsz_compress_noalloc(C.byref(p), d_frame, d_peaks, npeaks, d_out, out_cap,
+                                    C.byref(nbytes), stream)
     return st, nbytes.value
 
 
