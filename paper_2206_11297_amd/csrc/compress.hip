@@ -253,22 +253,18 @@ __device__ __forceinline__ void roi_copy(const BatchPlan &bp, uint32_t kg) {
 
 // ------------------------------------------------------------------ k_bin
 
-// Histogram update with one LDS atomic per distinct code in the wave; the
-// zero-residual code 512 is counted from a lane mask into a wave-uniform
-// total that is added once at the end.  vmask: the lanes holding a bin.
+// Histogram update: the zero-residual code 512 is counted from a lane mask
+// into a wave-uniform total that is added once at the end; every other code
+// is one LDS atomic of its lane (cheaper, measured, than one add per
+// distinct code of the wave, which takes up to 64 rounds on a wide residual
+// distribution).  vmask: the lanes holding a bin.
 __device__ __forceinline__ void wave_histogram(uint32_t code, uint64_t vmask, uint32_t *hist,
                                                uint32_t &c512) {
   const int lane = threadIdx.x & 63;
   c512 += (uint32_t)__builtin_popcountll(
       __builtin_amdgcn_uicmp(code, (uint32_t)kRadius, 32 /* eq */) & vmask);
   uint64_t pending = __builtin_amdgcn_uicmp(code, (uint32_t)kRadius, 33 /* ne */) & vmask;
-  while (pending) {
-    const int leader = __builtin_ctzll(pending);
-    const uint32_t lc = __builtin_amdgcn_readlane(code, leader);
-    const uint64_t same = __builtin_amdgcn_uicmp(code, lc, 32 /* eq */) & pending;
-    if (lane == leader) atomicAdd(&hist[lc], (uint32_t)__builtin_popcountll(same));
-    pending &= ~same;
-  }
+  if ((pending >> lane) & 1u) atomicAdd(&hist[code], 1u);
 }
 
 // The same from the wave's ballot m of the lanes whose residual is not 0
@@ -277,14 +273,7 @@ __device__ __forceinline__ void wave_histogram_nz(uint32_t code, uint64_t m, uin
                                                   uint32_t *hist, uint32_t &c512) {
   const int lane = threadIdx.x & 63;
   c512 += (uint32_t)__builtin_popcountll(vmask & ~m);
-  uint64_t pending = m;
-  while (pending) {
-    const int leader = __builtin_ctzll(pending);
-    const uint32_t lc = __builtin_amdgcn_readlane(code, leader);
-    const uint64_t same = __builtin_amdgcn_uicmp(code, lc, 32 /* eq */) & pending;
-    if (lane == leader) atomicAdd(&hist[lc], (uint32_t)__builtin_popcountll(same));
-    pending &= ~same;
-  }
+  if ((m >> lane) & 1u) atomicAdd(&hist[code], 1u);
 }
 
 // Value of lane-1 (lane 0 gets `first`): the left neighbour along a row.
@@ -1439,18 +1428,49 @@ __device__ __forceinline__ void for_pieces(const FramePlan &fp, uint32_t g, uint
 // code byte other than 128 (residual 0), and those bytes follow in bin order
 // from codes + c * 4096.
 //
-// One wave per 4096-symbol chunk, four per workgroup (a workgroup's frame
-// from count_frame): the chunk form from the sparse codes of k_bin (or from
-// the dense bytes of dimension 3, compacted in place), and the chunk's bits
-// and outliers.  Lane l takes bins [64 l, 64 l + 64) of the chunk: the
+// One wave per 4096-symbol chunk, four per workgroup (a workgroup's first
+// chunk from count_frame): the chunk form from the sparse codes of k_bin (or
+// from the dense bytes of dimension 3, compacted in place), and the chunk's
+// bits and outliers.  Lane l takes bins [64 l, 64 l + 64) of the chunk: the
 // pieces of its window are located first and their zero-map words loaded
-// together; the lane keeps its bytes in its own 64-byte LDS slot, and a wave
-// scan of the lanes' counts then places them.  SPARSE: every frame of the
-// batch has sparse codes (the kernel holds no dense path).
+// together, which gives the lane's count of bytes and so (by a wave scan) its
+// place in the chunk before any byte is read.  Each piece's bytes are then
+// read 16 at a time with aligned word loads and put straight into their
+// compacted place in the wave's LDS buffer, which is copied out in whole
+// 16-byte stores.  SPARSE: every frame of the batch has sparse codes (the
+// kernel holds no dense path).
+
+// Reads the n (<= 64) bytes at zb + o of a tile's byte region (cap bytes, a
+// multiple of 16) 16 at a time with aligned word loads; for each, in order,
+// calls f(byte).  Words past the region are never read (the index is
+// clamped; their bytes are not used).
+template <typename F>
+__device__ __forceinline__ void for_bytes(const uint8_t *zb, uint32_t cap, uint32_t o, uint32_t n,
+                                          F f) {
+  const uint32_t *w = (const uint32_t *)zb;
+  const uint32_t last = cap / 4u - 1u, sh = o & 3u;
+  uint32_t wi = o >> 2;
+  for (uint32_t k = 0; k < n; k += 16, wi += 4) {
+    const uint32_t cnt = min(n - k, 16u);
+    uint32_t d[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+      d[t] = 4u * t < sh + cnt ? *gm(w + min(wi + (uint32_t)t, last)) : 0u;
+    // bytes o + k + 4t .. + 3 (alignbyte takes the byte offset mod 4)
+    uint32_t e[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) e[t] = __builtin_amdgcn_alignbyte(d[t + 1], d[t], sh);
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const uint32_t v = j < 8 ? (j < 4 ? e[0] : e[1]) : (j < 12 ? e[2] : e[3]);
+      f((v >> (8 * (j & 3))) & 0xFFu);
+    }
+  }
+}
+
 template <bool SPARSE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_count(BatchPlan bp) {
   __shared__ uint4 s_len4[kWaves][kNumSym / 16];   // each wave's frame code lengths
-  __shared__ uint8_t s_slot[kWaves][kChunk];
+  __shared__ __align__(16) uint8_t s_comp[kWaves][kChunk];   // each wave's compacted bytes
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t item = blockIdx.x * kWaves + wv;
@@ -1474,25 +1494,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const uint32_t g0 = c * kChunk + lane * 64u;
   const uint32_t end = min(g0 + 64u, fp.nbins);
   const uint32_t nvalid = end > g0 ? end - g0 : 0u;
-  uint8_t *slot = s_slot[wv] + lane * 64;
-  uint64_t mask = 0;
-  uint32_t nz = 0, bits = 0, nout = 0;
+  uint8_t *comp = s_comp[wv];
   const uint8_t *lens = (const uint8_t *)s_len4[wv];
-  const uint32_t zb_last = fp.tile_cap - 1;
+  uint64_t mask = 0;
+  uint32_t bits = 0, nout = 0, at = 0;
+  // one code byte of bin g: to its compacted place, its bits and outliers
   auto take = [&](uint32_t b, uint32_t g) {
-    slot[nz++] = (uint8_t)b;
+    comp[at++] = (uint8_t)b;
     const uint32_t code = b ? b + (kRadius - 128) : code_from_residual(*gm(fp.rbuf + g));
     bits += lens[code];
     nout += code == 0;
   };
-  // the bytes of one piece: m its bins, word its zero-map word
+  // the bytes of one piece: m its bins (from bin g, the piece starting at
+  // column a of its strip), word its zero-map word, zp its byte count
   auto piece_bytes = [&](uint32_t g, uint32_t a, uint32_t tix, uint64_t m, uint64_t word,
                          uint32_t zp) {
-    const uint8_t *zb = fp.zb + (size_t)tix * fp.tile_cap;
     const uint32_t o = zp + (uint32_t)__builtin_popcountll(word & low_bits(a));
-    for (uint32_t k = 0; m; m &= m - 1, ++k)
-      take(*gm(zb + min(o + k, zb_last)), g + (uint32_t)__builtin_ctzll(m));
+    for_bytes(fp.zb + (size_t)tix * fp.tile_cap, fp.tile_cap, o, (uint32_t)__builtin_popcountll(m),
+              [&](uint32_t b) {
+                take(b, g + (uint32_t)__builtin_ctzll(m));
+                m &= m - 1;
+              });
   };
+  uint32_t nz_total;
   if (SPARSE || fp.sparse) {
     // a window of 64 bins in a row of at least 64 bins meets at most three
     // strip pieces (the end of one strip, a row's last strip, the next row's
@@ -1515,37 +1539,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         if (pnn[i]) cursor_advance(fp, cu, pnn[i]);
         left -= pnn[i];
       }
-      short_rows = left != 0;
+      // wave-uniform: both ways scan the lanes' counts
+      short_rows = __ballot(left != 0) != 0;
     }
     if (short_rows) {
-      // rows of fewer than 64 bins: piece by piece
+      // rows of fewer than 64 bins: piece by piece, the mask first
+      for_pieces(fp, g0, end, [&](uint32_t gg, uint32_t n, uint32_t a, uint32_t, size_t e) {
+        mask |= ((*gm(fp.zm + e) >> a) & low_bits(n)) << (gg - g0);
+      });
+      at = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mask), nz_total);
       s_len4[wv][lane] = lv;
       wave_sync();   // lengths in LDS
       for_pieces(fp, g0, end, [&](uint32_t gg, uint32_t n, uint32_t a, uint32_t tix, size_t e) {
         const uint64_t word = *gm(fp.zm + e);
         const uint64_t m = (word >> a) & low_bits(n);
-        if (!m) return;
-        mask |= m << (gg - g0);
-        piece_bytes(gg, a, tix, m, word, *gm(fp.zp + e));
+        if (m) piece_bytes(gg, a, tix, m, word, *gm(fp.zp + e));
       });
     } else {
-      uint64_t w[kP];
+      uint64_t w[kP], m[kP];
       uint32_t z[kP];
 #pragma unroll
       for (int i = 0; i < kP; ++i) {
         w[i] = pnn[i] ? *gm(fp.zm + pe[i]) : 0ull;
         z[i] = pnn[i] ? *gm(fp.zp + pe[i]) : 0u;
       }
+#pragma unroll
+      for (int i = 0; i < kP; ++i) {
+        m[i] = (w[i] >> pa[i]) & low_bits(pnn[i]);
+        mask |= m[i] << (pg[i] - g0);
+      }
+      at = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mask), nz_total);
       s_len4[wv][lane] = lv;
       wave_sync();   // lengths in LDS
 #pragma unroll
-      for (int i = 0; i < kP; ++i) {
-        const uint64_t m = (w[i] >> pa[i]) & low_bits(pnn[i]);
-        if (m) {
-          mask |= m << (pg[i] - g0);
-          piece_bytes(pg[i], pa[i], pt[i], m, w[i], z[i]);
-        }
-      }
+      for (int i = 0; i < kP; ++i)
+        if (m[i]) piece_bytes(pg[i], pa[i], pt[i], m[i], w[i], z[i]);
     }
   } else {
     uint32_t dw[16];   // the lane's 64 bytes (the region holds whole chunks)
@@ -1560,6 +1588,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       mask |= (uint64_t)non_zero_residuals(w4) << (16 * k);
     }
     mask &= low_bits(nvalid);
+    at = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mask), nz_total);
     s_len4[wv][lane] = lv;
     wave_sync();   // lengths in LDS
 #pragma unroll
@@ -1569,14 +1598,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         take(byte_at(dw[4 * q], dw[4 * q + 1], dw[4 * q + 2], dw[4 * q + 3], k), g0 + 16 * q + k);
       }
   }
-  bits += (nvalid - nz) * lens[kRadius];
-  uint32_t nz_total;
-  const uint32_t rank = wave_exclusive_scan32(nz, nz_total);
+  bits += (nvalid - (uint32_t)__builtin_popcountll(mask)) * lens[kRadius];
+  wave_sync();   // the compacted bytes in LDS (dense bytes: every load of the wave is done)
   if (!ok) return;   // a frame that failed earlier (k_tail reports it)
-  // the chunk form (dense bytes: every load of the wave is done by now)
   *gm(fp.cmask + (size_t)c * 64 + lane) = mask;
-  uint8_t *dst = fp.codes + (size_t)c * kChunk + rank;
-  for (uint32_t k = 0; k < nz; ++k) *gm(dst + k) = slot[k];
+  // whole 16-byte groups (the chunk's region holds 4096 bytes; bytes past
+  // nz_total are not read)
+  uint8_t *dst = fp.codes + (size_t)c * kChunk;
+  for (uint32_t k = 16u * lane; k < nz_total; k += 1024u)
+    *gm((u32x4 *)(dst + k)) = *(const u32x4 *)(comp + k);
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
     bits += __shfl_xor(bits, d);
