@@ -204,7 +204,7 @@ int rsz_compress_batch(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t
  * replay recomputes all outputs from the frames' current contents; the
  * descriptors (pointers, shapes, peak counts) are fixed at prepare time. */
 typedef struct {
-  uint64_t opaque[16];
+  uint64_t opaque[32];
 } rsz_batch_plan;
 
 int rsz_batch_prepare(uint32_t nframes, const rsz_frame_desc *h_descs, uint64_t *d_out_bytes,

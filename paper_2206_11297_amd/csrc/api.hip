@@ -114,7 +114,9 @@ static Geom geometry(const rsz_params *p, uint32_t npeaks, uint32_t th_cap, uint
 }
 
 struct Layout {
-  uint64_t plans, prefix, cframe, states, frames_begin, total;
+  // plans and prefixes are copied from the host; the frame tables after
+  // them are written by k_prep
+  uint64_t plans, prefix, tables, tile_frame, unit_frame, peak_frame, states, frames_begin, total;
   std::vector<uint64_t> frame_off;  // per frame start of its private region
 };
 
@@ -130,7 +132,8 @@ static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const G
   b += align_up(4ull * npeaks, 256);                              // bucket
   // code bytes (dense, then the chunk form), whole chunks and 32 bytes past the
   // last; the chunk form's masks
-  b += align_up(1ull * kChunk * g.nchunks + 32, 256) + align_up(512ull * g.nchunks, 256);
+  b += align_up(1ull * kChunk * g.nchunks + 32, 256) + align_up(512ull * g.nchunks, 256) +
+       align_up(256ull * g.nchunks, 256);   // and the lanes' bit and outlier counts
   if (p->dim != 3) {   // sparse codes: zero-map words, counts, bytes per binning tile
     const uint64_t nt = (uint64_t)p->panels * g.cgs * g.segs, ne = nt * kTileEntries;
     b += align_up(8ull * ne, 256) + align_up(2ull * ne, 256) + align_up(nt * tile_cap(g), 256);
@@ -149,18 +152,36 @@ static uint64_t frame_region_bytes(const rsz_params *p, uint32_t npeaks, const G
   return b;
 }
 
+// Chunks per encode workgroup (its waves take every kWaves-th chunk): a
+// multiple of kWaves, about 8192 workgroups for large batches (a workgroup
+// first copies the code tables to LDS; one chunk per wave measured slower).
+static uint32_t encode_cpw(uint64_t all_chunks) {
+  return kWaves * (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, all_chunks / (8192 * kWaves)));
+}
+
 static Layout layout(uint32_t nframes, const std::vector<const rsz_params *> &ps,
                      const std::vector<uint32_t> &np, const std::vector<Geom> &gs,
                      const std::vector<int> &valid) {
   Layout L;
   L.plans = 0;
   L.prefix = align_up(sizeof(FramePlan) * nframes, 256);
-  // frame of each k_count workgroup's first chunk
-  uint64_t chunks = 0;
+  // the frame tables: (frame, chunk) of each k_count workgroup's first
+  // chunk, the frame of each k_bin and k_encode workgroup and of each peak
+  uint64_t chunks = 0, tiles = 0, units = 0, peaks = 0;
   for (uint32_t f = 0; f < nframes; ++f)
     if (valid[f]) chunks += gs[f].nchunks;
-  L.cframe = L.prefix + align_up(5 * 4ull * (nframes + 1), 256);
-  L.states = L.cframe + align_up(8 * div_up(chunks, kWaves) + 8, 256);
+  const uint32_t cpw = encode_cpw(chunks);
+  for (uint32_t f = 0; f < nframes; ++f)
+    if (valid[f]) {
+      tiles += (uint64_t)ps[f]->panels * gs[f].cgs * gs[f].groups;
+      units += div_up(gs[f].nchunks, cpw);
+      peaks += np[f];
+    }
+  L.tables = L.prefix + align_up(5 * 4ull * (nframes + 1), 256);
+  L.tile_frame = L.tables + align_up(8 * div_up(chunks, kWaves) + 8, 256);
+  L.unit_frame = L.tile_frame + align_up(4 * tiles + 4, 256);
+  L.peak_frame = L.unit_frame + align_up(4 * units + 4, 256);
+  L.states = L.peak_frame + align_up(4 * peaks + 4, 256);
   L.frames_begin = L.states + align_up(sizeof(FrameState) * nframes, 256);
   uint64_t off = L.frames_begin;
   L.frame_off.resize(nframes);
@@ -250,7 +271,7 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   if (need) *need = L.total;
   if (!ws) return RSZ_OK;
   if (ws_bytes < L.total) return RSZ_ERR_WORKSPACE;
-  hp.bytes.assign(L.states, 0);
+  hp.bytes.assign(L.tables, 0);
   memset(&hp.bp, 0, sizeof hp.bp);
   FramePlan *fpl = (FramePlan *)hp.bytes.data();
   uint32_t *tp = (uint32_t *)(hp.bytes.data() + L.prefix);
@@ -260,14 +281,10 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   uint32_t *xp = kp + (nframes + 1);
   uint64_t tiles = 0, units = 0, npk_total = 0, chunks_done = 0, fixes = 0;
   bool all_vec = true;
-  // chunks per encode workgroup (its waves take every kWaves-th chunk): a
-  // multiple of kWaves, about 8192 workgroups for large batches (a workgroup
-  // first copies the code tables to LDS; one chunk per wave measured slower)
   uint64_t all_chunks = 0;
   for (uint32_t f = 0; f < nframes; ++f)
     if (valid[f]) all_chunks += gs[f].nchunks;
-  const uint32_t cpw = kWaves * (uint32_t)std::min<uint64_t>(
-                                    8, std::max<uint64_t>(1, all_chunks / (8192 * kWaves)));
+  const uint32_t cpw = encode_cpw(all_chunks);
   for (uint32_t f = 0; f < nframes; ++f) {
     FramePlan &fp = fpl[f];
     memset(&fp, 0, sizeof fp);
@@ -342,6 +359,8 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
     base += align_up(1ull * kChunk * g.nchunks + 32, 256);
     fp.cmask = (uint64_t *)base;
     base += align_up(512ull * g.nchunks, 256);
+    fp.lanecnt = (uint32_t *)base;
+    base += align_up(256ull * g.nchunks, 256);
     fp.rbuf = (int32_t *)base;
     base += align_up(4ull * g.nbins, 256);
     fp.obuf = (uint32_t *)base;
@@ -429,14 +448,10 @@ static int build_plan(uint32_t nframes, const rsz_frame_desc *d, uint64_t *res_b
   hp.bp.chunk_prefix = hp.bp.peak_prefix + (nframes + 1);
   hp.bp.fix_prefix = hp.bp.chunk_prefix + (nframes + 1);
   hp.bp.total_fix = (uint32_t)fixes;
-  uint32_t *cf = (uint32_t *)(hp.bytes.data() + L.cframe);
-  uint32_t fr = 0;
-  for (uint64_t w = 0; w < div_up(chunks_done, kWaves); ++w) {
-    while (kp[fr + 1] <= w * kWaves) ++fr;
-    cf[2 * w] = fr;
-    cf[2 * w + 1] = (uint32_t)(w * kWaves - kp[fr]);
-  }
-  hp.bp.count_frame = (const uint2 *)(ws + L.cframe);
+  hp.bp.count_frame = (uint2 *)(ws + L.tables);
+  hp.bp.tile_frame = (uint32_t *)(ws + L.tile_frame);
+  hp.bp.unit_frame = (uint32_t *)(ws + L.unit_frame);
+  hp.bp.peak_frame = (uint32_t *)(ws + L.peak_frame);
   bool all_sparse = true;
   for (uint32_t f = 0; f < nframes; ++f)
     if (valid[f] && fpl[f].dim == 3) all_sparse = false;

@@ -112,11 +112,29 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *s_tmp, T &total) {
 constexpr uint32_t kPrepKeys = 4096;
 
 __global__ __launch_bounds__(256) void k_prep(BatchPlan bp) {
-  const FramePlan &fp = bp.frames[blockIdx.x];
+  const uint32_t f = blockIdx.x;
+  const FramePlan &fp = bp.frames[f];
   FrameState *st = fp.st;
   __shared__ int s_bad;
   __shared__ uint32_t s_tmp[4];
   __shared__ uint32_t s_cnt[kPrepKeys];
+  // this frame's entries of the frame tables (a later kernel finds a
+  // workgroup's or peak's frame with one load instead of a search); written
+  // for every frame, failed or not
+  for (uint32_t i = bp.tile_prefix[f] + threadIdx.x; i < bp.tile_prefix[f + 1]; i += 256)
+    bp.tile_frame[i] = f;
+  for (uint32_t i = bp.unit_prefix[f] + threadIdx.x; i < bp.unit_prefix[f + 1]; i += 256)
+    bp.unit_frame[i] = f;
+  for (uint32_t i = bp.peak_prefix[f] + threadIdx.x; i < bp.peak_prefix[f + 1]; i += 256)
+    bp.peak_frame[i] = f;
+  {
+    // k_count workgroup w takes chunks [4 w, 4 w + 4) of the batch: its
+    // entry belongs to the frame holding chunk 4 w
+    const uint32_t c0 = bp.chunk_prefix[f], c1 = bp.chunk_prefix[f + 1];
+    for (uint32_t w = (c0 + kWaves - 1) / kWaves + threadIdx.x; w < (c1 + kWaves - 1) / kWaves;
+         w += 256)
+      bp.count_frame[w] = make_uint2(f, w * kWaves - c0);
+  }
   for (int i = threadIdx.x; i < kNumSym; i += 256) st->hist[i] = 0;
   if (fp.roi_coding)
     for (int i = threadIdx.x; i < kNumSym; i += 256) fp.roi_hist[i] = 0;
@@ -219,7 +237,7 @@ constexpr uint32_t kRoiSlots = 8;
 __device__ __forceinline__ void roi_copy(const BatchPlan &bp, uint32_t kg) {
   const int lane = threadIdx.x & 63;
   if (kg >= bp.total_peaks) return;
-  const uint32_t f = find_frame(bp.peak_prefix, bp.nframes, kg);
+  const uint32_t f = bp.peak_frame[kg];
   const FramePlan &fp = bp.frames[f];
   if (fp.roi_coding || load_status(fp.st) != RSZ_OK) return;
   // the section lies inside the output buffer (a stream that does not fit
@@ -880,7 +898,7 @@ __device__ __forceinline__ void k_bin_body(BatchPlan bp) {
   __shared__ uint32_t s_mask[kWaves][kMaskWords];
   __shared__ double s_inv[65];
   __shared__ SparseStage s_stage[DIM == 3 ? 1 : kWaves];
-  const uint32_t f = find_frame(bp.tile_prefix, bp.nframes, blockIdx.x);
+  const uint32_t f = bp.tile_frame[blockIdx.x];
   const FramePlan &fp = bp.frames[f];
   for (int i = threadIdx.x; i < kNumSym; i += blockDim.x) s_hist[i] = 0u;
   for (int i = threadIdx.x; i < 65; i += blockDim.x) s_inv[i] = fp.st->inv[i];
@@ -1456,46 +1474,38 @@ __device__ __forceinline__ void for_bytes(const uint8_t *zb, uint32_t cap, uint3
 #pragma unroll
     for (int t = 0; t < 5; ++t)
       d[t] = 4u * t < sh + cnt ? *gm(w + min(wi + (uint32_t)t, last)) : 0u;
-    // bytes o + k + 4t .. + 3 (alignbyte takes the byte offset mod 4)
-    uint32_t e[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) e[t] = __builtin_amdgcn_alignbyte(d[t + 1], d[t], sh);
+    // bytes o + k + 4t .. + 3 (alignbyte takes the byte offset mod 4), as
+    // four named words (an indexed array would live in scratch memory)
+    const uint32_t e0 = __builtin_amdgcn_alignbyte(d[1], d[0], sh);
+    const uint32_t e1 = __builtin_amdgcn_alignbyte(d[2], d[1], sh);
+    const uint32_t e2 = __builtin_amdgcn_alignbyte(d[3], d[2], sh);
+    const uint32_t e3 = __builtin_amdgcn_alignbyte(d[4], d[3], sh);
     for (uint32_t j = 0; j < cnt; ++j) {
-      const uint32_t v = j < 8 ? (j < 4 ? e[0] : e[1]) : (j < 12 ? e[2] : e[3]);
+      const uint32_t v = j < 8 ? (j < 4 ? e0 : e1) : (j < 12 ? e2 : e3);
       f((v >> (8 * (j & 3))) & 0xFFu);
     }
   }
 }
 
+// The counting of chunk c of a frame by one wave: the lanes' masks (bit k
+// of lane l: bin 64 l + k carries a byte other than 128), bits and
+// outliers, and the chunk's bytes compacted into comp in bin order (lane l's
+// from comp + rank).  lv: the frame's code lengths (16 per lane), which go to
+// len4 (the wave's LDS copy).  Every read stays inside the frame's buffers
+// whatever they hold.
+struct ChunkCount {
+  uint64_t mask;
+  uint32_t bits, nout, rank, nz_total, nvalid;
+};
+
 template <bool SPARSE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_count(BatchPlan bp) {
-  __shared__ uint4 s_len4[kWaves][kNumSym / 16];   // each wave's frame code lengths
-  __shared__ __align__(16) uint8_t s_comp[kWaves][kChunk];   // each wave's compacted bytes
+__device__ __forceinline__ ChunkCount count_chunk(const FramePlan &fp, uint32_t c, uint4 lv,
+                                                  uint4 *len4, uint8_t *comp) {
   const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t item = blockIdx.x * kWaves + wv;
-  if (item >= bp.total_chunks) {
-    // the ROI windows' payload, in the same launch (it needs only k_prep's
-    // peak check, and this kernel leaves HBM bandwidth to spare)
-    roi_copy(bp, item - bp.total_chunks);
-    return;
-  }
-  // the workgroup's first chunk (frame, chunk) from the table; the four
-  // chunks of a workgroup may span frames
-  const uint2 fc = bp.count_frame[blockIdx.x];
-  uint32_t fw = fc.x, c = fc.y + (uint32_t)wv;
-  while (c >= bp.frames[fw].nchunks) c -= bp.frames[fw].nchunks, ++fw;
-  const FramePlan &fp = bp.frames[fw];
-  // the status, the code lengths and (below) the zero-map words are loaded
-  // together; the status gates only what the wave writes, and every read
-  // stays inside the frame's buffers whatever they hold
-  const bool ok = load_status(fp.st) == RSZ_OK;
-  const uint4 lv = ((const uint4 *)fp.st->lens)[lane];
   const uint32_t g0 = c * kChunk + lane * 64u;
   const uint32_t end = min(g0 + 64u, fp.nbins);
   const uint32_t nvalid = end > g0 ? end - g0 : 0u;
-  uint8_t *comp = s_comp[wv];
-  const uint8_t *lens = (const uint8_t *)s_len4[wv];
+  const uint8_t *lens = (const uint8_t *)len4;
   uint64_t mask = 0;
   uint32_t bits = 0, nout = 0, at = 0;
   // one code byte of bin g: to its compacted place, its bits and outliers
@@ -1505,18 +1515,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     bits += lens[code];
     nout += code == 0;
   };
-  // the bytes of one piece: m its bins (from bin g, the piece starting at
-  // column a of its strip), word its zero-map word, zp its byte count
-  auto piece_bytes = [&](uint32_t g, uint32_t a, uint32_t tix, uint64_t m, uint64_t word,
-                         uint32_t zp) {
-    const uint32_t o = zp + (uint32_t)__builtin_popcountll(word & low_bits(a));
+  // the bytes of one piece: m its bins (from bin g), o the tile offset of
+  // its first byte
+  auto piece_bytes = [&](uint32_t g, uint32_t tix, uint64_t m, uint32_t o) {
     for_bytes(fp.zb + (size_t)tix * fp.tile_cap, fp.tile_cap, o, (uint32_t)__builtin_popcountll(m),
               [&](uint32_t b) {
                 take(b, g + (uint32_t)__builtin_ctzll(m));
                 m &= m - 1;
               });
   };
-  uint32_t nz_total;
+  // the tile offset of a piece's first byte: the entry's count plus the
+  // bytes of the strip's columns before column a
+  auto piece_start = [](uint64_t word, uint32_t a, uint32_t zp) {
+    return zp + (uint32_t)__builtin_popcountll(word & low_bits(a));
+  };
+  uint32_t nz_total, rank;
   if (SPARSE || fp.sparse) {
     // a window of 64 bins in a row of at least 64 bins meets at most three
     // strip pieces (the end of one strip, a row's last strip, the next row's
@@ -1547,17 +1560,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       for_pieces(fp, g0, end, [&](uint32_t gg, uint32_t n, uint32_t a, uint32_t, size_t e) {
         mask |= ((*gm(fp.zm + e) >> a) & low_bits(n)) << (gg - g0);
       });
-      at = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mask), nz_total);
-      s_len4[wv][lane] = lv;
+      rank = at = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mask), nz_total);
+      len4[lane] = lv;
       wave_sync();   // lengths in LDS
       for_pieces(fp, g0, end, [&](uint32_t gg, uint32_t n, uint32_t a, uint32_t tix, size_t e) {
         const uint64_t word = *gm(fp.zm + e);
         const uint64_t m = (word >> a) & low_bits(n);
-        if (m) piece_bytes(gg, a, tix, m, word, *gm(fp.zp + e));
+        if (m) piece_bytes(gg, tix, m, piece_start(word, a, *gm(fp.zp + e)));
       });
     } else {
       uint64_t w[kP], m[kP];
-      uint32_t z[kP];
+      uint32_t z[kP], po[kP];
 #pragma unroll
       for (int i = 0; i < kP; ++i) {
         w[i] = pnn[i] ? *gm(fp.zm + pe[i]) : 0ull;
@@ -1566,14 +1579,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 #pragma unroll
       for (int i = 0; i < kP; ++i) {
         m[i] = (w[i] >> pa[i]) & low_bits(pnn[i]);
+        po[i] = piece_start(w[i], pa[i], z[i]);
         mask |= m[i] << (pg[i] - g0);
       }
-      at = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mask), nz_total);
-      s_len4[wv][lane] = lv;
+      rank = at = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mask), nz_total);
+      len4[lane] = lv;
       wave_sync();   // lengths in LDS
 #pragma unroll
       for (int i = 0; i < kP; ++i)
-        if (m[i]) piece_bytes(pg[i], pa[i], pt[i], m[i], w[i], z[i]);
+        if (m[i]) piece_bytes(pg[i], pt[i], m[i], po[i]);
     }
   } else {
     uint32_t dw[16];   // the lane's 64 bytes (the region holds whole chunks)
@@ -1588,8 +1602,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       mask |= (uint64_t)non_zero_residuals(w4) << (16 * k);
     }
     mask &= low_bits(nvalid);
-    at = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mask), nz_total);
-    s_len4[wv][lane] = lv;
+    rank = at = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mask), nz_total);
+    len4[lane] = lv;
     wave_sync();   // lengths in LDS
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -1600,13 +1614,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   }
   bits += (nvalid - (uint32_t)__builtin_popcountll(mask)) * lens[kRadius];
   wave_sync();   // the compacted bytes in LDS (dense bytes: every load of the wave is done)
+  ChunkCount cc;
+  cc.mask = mask;
+  cc.bits = bits;
+  cc.nout = nout;
+  cc.rank = rank;
+  cc.nz_total = nz_total;
+  cc.nvalid = nvalid;
+  return cc;
+}
+
+// The frame and chunk of wave wv of k_count's workgroup slot t: the table
+// holds the slot's first chunk; the four chunks of a slot may span frames.
+__device__ __forceinline__ void slot_chunk(const BatchPlan &bp, uint32_t t, uint32_t wv,
+                                           uint32_t &fw, uint32_t &c) {
+  const uint2 fc = bp.count_frame[t];
+  fw = fc.x;
+  c = fc.y + wv;
+  while (c >= bp.frames[fw].nchunks) c -= bp.frames[fw].nchunks, ++fw;
+}
+
+template <bool SPARSE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_count(BatchPlan bp) {
+  __shared__ uint4 s_len4[kWaves][kNumSym / 16];   // each wave's frame code lengths
+  __shared__ __align__(16) uint8_t s_comp[kWaves][kChunk];   // each wave's compacted bytes
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t item = blockIdx.x * kWaves + wv;
+  if (item >= bp.total_chunks) {
+    // the ROI windows' payload, in the same launch (it needs only k_prep's
+    // peak check, and this kernel leaves HBM bandwidth to spare)
+    roi_copy(bp, item - bp.total_chunks);
+    return;
+  }
+  uint32_t fw, c;
+  slot_chunk(bp, blockIdx.x, (uint32_t)wv, fw, c);
+  const FramePlan &fp = bp.frames[fw];
+  // the status, the code lengths and (inside) the zero-map words are loaded
+  // together; the status gates only what the wave writes
+  const bool ok = load_status(fp.st) == RSZ_OK;
+  const uint4 lv = ((const uint4 *)fp.st->lens)[lane];
+  uint8_t *comp = s_comp[wv];
+  const ChunkCount cc = count_chunk<SPARSE>(fp, c, lv, s_len4[wv], comp);
   if (!ok) return;   // a frame that failed earlier (k_tail reports it)
-  *gm(fp.cmask + (size_t)c * 64 + lane) = mask;
+  *gm(fp.cmask + (size_t)c * 64 + lane) = cc.mask;
+  *gm(fp.lanecnt + (size_t)c * 64 + lane) = cc.bits | cc.nout << 16;
   // whole 16-byte groups (the chunk's region holds 4096 bytes; bytes past
   // nz_total are not read)
   uint8_t *dst = fp.codes + (size_t)c * kChunk;
-  for (uint32_t k = 16u * lane; k < nz_total; k += 1024u)
+  for (uint32_t k = 16u * lane; k < cc.nz_total; k += 1024u)
     *gm((u32x4 *)(dst + k)) = *(const u32x4 *)(comp + k);
+  uint32_t bits = cc.bits, nout = cc.nout;
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
     bits += __shfl_xor(bits, d);
@@ -1743,7 +1801,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
   __shared__ uint32_t s_cw[kNumSym];
   __shared__ uint32_t s_words[kWaves][kRoundSyms + 1];   // 32 bits per symbol at most
   __shared__ int s_ok;
-  const uint32_t f = find_frame(bp.unit_prefix, bp.nframes, blockIdx.x);
+  const uint32_t f = bp.unit_frame[blockIdx.x];
   const FramePlan &fp = bp.frames[f];
   const FrameState *st = fp.st;
   if (threadIdx.x == 0) s_ok = load_status(st) == RSZ_OK;
@@ -1775,39 +1833,36 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
     // the chunk form: lane j holds mask word j and the bytes before it
     const uint8_t *cbytes = fp.codes + (size_t)lc * kChunk;
     const uint64_t mword = *gm(fp.cmask + (size_t)lc * 64 + lane);
+    const uint32_t lc_lane = *gm(fp.lanecnt + (size_t)lc * 64 + lane);
     uint32_t nz_total;
     const uint32_t wr = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mword), nz_total);
     const uint32_t nbits = (lc + 1 < fp.nchunks ? fp.chunk_off[lc + 1] : (uint32_t)st->T) - S0;
     const uint32_t L0 = s_len[kRadius];
     if (s_cw[kRadius] == 0 && L0 && pos + nbits <= 32u * kRoundSyms) {
+      // residual 0's codeword is all zeros, so its bins only advance the
+      // position: lane j places the codewords of its own bins [64 j, 64 j +
+      // 64) from its first bit, pb (the bits of the lanes before it, which
+      // k_count counted), and its outliers from its first outlier slot
       const uint32_t nw = (pos + nbits + 31) >> 5;
+      uint32_t tb, to;
+      const uint32_t pb = pos + wave_exclusive_scan32(lc_lane & 0xFFFFu, tb);
+      uint32_t oq = oi + wave_exclusive_scan32(lc_lane >> 16, to);
+      const uint32_t gl = lc * kChunk + (uint32_t)lane * 64u;
+      uint64_t m = mword;
       uint32_t extra = 0;
-      for (uint32_t i0 = 0; i0 < nz_total; i0 += 64) {
-        const uint32_t i = i0 + lane;
-        const bool valid = i < nz_total;
-        const uint32_t ic = valid ? i : nz_total - 1;
-        // the mask word holding the ic-th set bit: the last word whose
-        // count of set bits before it is <= ic
-        uint32_t wsel = 0;
-#pragma unroll
-        for (uint32_t step = 32; step; step >>= 1)
-          if ((uint32_t)__shfl((int)wr, (int)(wsel + step)) <= ic) wsel += step;
-        const uint64_t word = __shfl(mword, (int)wsel);
-        const uint32_t k = wsel * 64 + select_bit(word, ic - (uint32_t)__shfl((int)wr, (int)wsel));
-        const uint32_t g = lc * kChunk + k;
-        const uint32_t b = *gm(cbytes + ic);
+      for_bytes(cbytes, kChunk, wr, (uint32_t)__builtin_popcountll(m), [&](uint32_t b) {
+        const uint32_t k = (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        const uint32_t g = gl + k;
         const uint32_t code = b ? b + (kRadius - 128) : code_from_residual(*gm(fp.rbuf + g));
         const uint32_t L = s_len[code];
-        uint32_t tx, to;
-        const uint32_t ex = extra + wave_exclusive_scan32(valid ? L - L0 : 0u, tx);
-        const uint32_t orank = oi + wave_exclusive_scan32(valid && code == 0 ? 1u : 0u, to);
-        if (valid) {
-          or_codeword(stg, pos + k * L0 + ex, s_cw[code], L);
-          if (code == 0 && orank < fp.nbins) *gm(fp.obuf + orank) = g;
+        or_codeword(stg, pb + k * L0 + extra, s_cw[code], L);
+        extra += L - L0;
+        if (code == 0) {
+          if (oq < fp.nbins) *gm(fp.obuf + oq) = g;
+          ++oq;
         }
-        extra += tx;
-        oi += to;
-      }
+      });
       wave_sync();
       for (uint32_t k = lane; k < nw; k += 64) {
         const uint32_t v = stg[k];
@@ -2156,7 +2211,7 @@ __device__ __forceinline__ void roi_stage(const RoiWin &rw, uint32_t w, uint32_t
 // The window of global peak kg if its frame codes the ROI and is still fine.
 __device__ __forceinline__ bool roi_window(const BatchPlan &bp, uint32_t kg, uint32_t &f,
                                            uint32_t &k, RoiWin &rw) {
-  f = find_frame(bp.peak_prefix, bp.nframes, kg);
+  f = bp.peak_frame[kg];
   const FramePlan &fp = bp.frames[f];
   if (!fp.roi_coding || load_status(fp.st) != RSZ_OK) return false;
   k = kg - bp.peak_prefix[f];

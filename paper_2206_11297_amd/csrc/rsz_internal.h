@@ -89,6 +89,8 @@ struct FramePlan {
                             // (dimension 3), then the chunk form's bytes
   int32_t *rbuf;            // nbins, residual of bins whose code byte is 0
   uint64_t *cmask;          // nchunks * 64: the chunk form's masks (k_count)
+  uint32_t *lanecnt;        // nchunks * 64: per 64 bins of a chunk, their bits
+                            // (low 16) and outliers (high 16) (k_count)
   // Sparse codes (frames of Lorenzo dimension 1 or 2; dimension 3 keeps the
   // dense bytes above): per binning tile (index (panel * cgs + cg) * segs +
   // seg), kTileEntries entries, entry s * 32 + i for strip s of the column
@@ -155,7 +157,13 @@ struct BatchPlan {
   const uint32_t *peak_prefix;   // nframes + 1
   const uint32_t *chunk_prefix;  // nframes + 1
   const uint32_t *fix_prefix;    // nframes + 1 (k_lorenzo_dims workgroups)
-  const uint2 *count_frame;       // per k_count workgroup: (frame, chunk) of its first chunk
+  // frame tables, written by k_prep (every frame's workgroup writes its own
+  // entries): per k_count workgroup (frame, chunk) of its first chunk; the
+  // frame of each k_bin workgroup, k_encode workgroup and peak
+  uint2 *count_frame;
+  uint32_t *tile_frame;
+  uint32_t *unit_frame;
+  uint32_t *peak_frame;
   uint32_t all_sparse;           // every frame has sparse codes (no dimension 3)
 };
 

@@ -54,7 +54,7 @@ class rsz_frame_desc(C.Structure):
 
 
 class rsz_batch_plan(C.Structure):
-    _fields_ = [("opaque", C.c_uint64 * 16)]
+    _fields_ = [("opaque", C.c_uint64 * 32)]
 
 
 class rsz_debug_bufs(C.Structure):
