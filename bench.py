@@ -370,9 +370,50 @@ def _counter_rows(root, counter):
 # Kernels whose counter records the roofline reads: (record name, the kernel
 # name in the counter output, the source file it is built from, and which of
 # its dispatches to take: the largest grid).
-TRAFFIC_KERNELS = [("k_bin", "k_bin<2, false, 2>", "compress.hip"),
+TRAFFIC_KERNELS = [("k_bin", "k_bin_vec<2, 2>", "compress.hip"),
+                   ("k_count", "k_count<true>", "compress.hip"),
+                   ("k_encode", "k_encode", "compress.hip"),
                    ("k_lorenzo_dims", "k_lorenzo_dims", "compress.hip"),
                    ("k_peaks_find", "k_peaks_find", "peaks.hip")]
+
+# The counters of the SQ passes summarised per kernel, and what is derived
+# from them (SQ_*_CYCLES and SQ_BUSY_CYCLES count in units of 4 cycles on
+# this chip's counter blocks; ratios of like counters need no scale).
+SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+               "SQ_INSTS_VMEM_WR", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+               "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+               "SQ_LDS_BANK_CONFLICT", "MeanOccupancyPerCU"]
+
+
+def counter_summary(dirs, out_path):
+    """Markdown table of the SQ counter passes (rocprofv3 CSV output under
+    each of dirs): per kernel and grid, the mean per dispatch of each
+    counter, the share of wave time spent waiting, and LDS bank conflicts
+    per LDS instruction."""
+    vals = {}
+    for d in dirs:
+        for c in SQ_COUNTERS:
+            for k, lst in _counter_rows(d, c).items():
+                for g, v in lst:
+                    vals.setdefault((k, g), {}).setdefault(c, []).append(v)
+    mean = lambda x: sum(x) / len(x) if x else float("nan")
+    head = ["kernel", "grid", "waves", "VALU insts", "SALU insts", "LDS insts", "VMEM rd",
+            "VMEM wr", "wait share", "LDS conflicts / LDS inst", "mean occupancy / CU"]
+    lines = ["| " + " | ".join(head) + " |", "|" + "---|" * len(head)]
+    for (k, g), d in sorted(vals.items(), key=lambda t: -mean(t[1].get("SQ_WAVE_CYCLES", [0]))):
+        if "rsz::" not in k:
+            continue
+        m = {c: mean(d.get(c, [])) for c in SQ_COUNTERS}
+        wait = m["SQ_WAIT_ANY"] / m["SQ_WAVE_CYCLES"] if m["SQ_WAVE_CYCLES"] else float("nan")
+        conf = m["SQ_LDS_BANK_CONFLICT"] / m["SQ_INSTS_LDS"] if m["SQ_INSTS_LDS"] else 0.0
+        name = k.replace("(rsz::BatchPlan)", "").replace("void ", "")
+        lines.append(f"| `{name[:48]}` | {g} | {m['SQ_WAVES']:.0f} | {m['SQ_INSTS_VALU']:.3g} | "
+                     f"{m['SQ_INSTS_SALU']:.3g} | {m['SQ_INSTS_LDS']:.3g} | "
+                     f"{m['SQ_INSTS_VMEM_RD']:.3g} | {m['SQ_INSTS_VMEM_WR']:.3g} | {wait:.2f} | "
+                     f"{conf:.3f} | {m['MeanOccupancyPerCU']:.1f} |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def _source_sha(name):
@@ -450,6 +491,30 @@ def traffic_record(kernel):
     if not src or rec.get("source_sha256") != _source_sha(src):
         return None
     return rec
+
+
+def launch_modes(torch, B, steps):
+    """The same batch as prepared once (rsz_batch_prepare) and then queued
+    as kernels only (rsz_batch_launch), and as a HIP graph replay of that
+    launch: ms a step of each, beside the per-step plan of `value`.  Every
+    replay still recomputes every stream from the frames' contents."""
+    out = {}
+    B.prepare()
+    for name, fn in (("prepared_launch", B.launch), ("graph_replay", None)):
+        if fn is None:
+            B.graph()
+            fn = B.replay
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+    st = B.status.cpu().numpy()
+    assert (st == 0).all(), f"launch modes: statuses {set(st.tolist())}"
+    return out
 
 
 def _child_processes():
@@ -619,6 +684,9 @@ def main():
                     help="JSON file that receives a new autotuner result")
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_DIR"),
                     help="summarize two rocprofv3 --pmc runs (CSV output) and exit")
+    ap.add_argument("--counter-summary", nargs="+", metavar="PATH",
+                    help="summarize rocprofv3 --pmc runs of the SQ counters (CSV output under "
+                         "the given directories) into the Markdown file named last, and exit")
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--read-reference", type=int, default=1,
                     help="time a plain 4 GiB streaming read as the measured read reference")
@@ -656,6 +724,9 @@ def main():
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary)
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary[:-1], args.counter_summary[-1])
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the compression path is not sharded across "
@@ -742,6 +813,10 @@ def main():
     rsz.rsz_profile_enable(False)
 
     sizes = B.sizes.cpu().numpy().astype(np.int64)
+    modes = launch_modes(torch, B, args.steps)
+    modes["plan_each_step_ms"] = round(ms_step, 4)
+    modes["note"] = ("value times plan_each_step: each step plans the batch on the host and "
+                     "uploads the plan, as a stream of new batches would")
     cr_u16 = (npix // len(frames)) * 2 / sizes
     kernel_ms = {k: v[1] / v[0] for k, v in prof_all.items()}
     kb_ms = prof["k_bin"][1] / prof["k_bin"][0]
@@ -831,6 +906,7 @@ def main():
                        "one_frame_per_launch_p99": round(float(np.percentile(lat_ms, 99)), 4),
                        "batched_all_frames": round(ms_step, 4)},
         "kernel_ms": {k: round(v, 4) for k, v in kernel_ms.items()},
+        "launch_modes": modes,
         "kernel_ms_source": f"HIP events around every launch in {kprof_steps} steps after the "
                             "timed region (inside it, events around k_bin only)",
         "serving": serving,
