@@ -618,7 +618,7 @@ def jungfrau16m_graph_section(args, torch, dev):
     graph and replayed, each replay recomputing every stream; the same
     streams decoded in one batched call."""
     import numpy as np
-    from paper_2206_11297_amd import rsz, synth
+    from paper_2206_11297_amd import autotune, rsz, synth
     n = args.jf16m_frames
     host = generate(lambda i: synth.jungfrau_frame(i, shape=synth.JUNGFRAU16M,
                                                    workload=synth.W_JF16, max_peaks=3000),
@@ -630,7 +630,9 @@ def jungfrau16m_graph_section(args, torch, dev):
     out = {}
     for eb in (1.0, 10.0):
         label = f"jungfrau16m-{n}_graph_eb{eb:g}"
-        B = rsz.Batch(frames, peaks, (11, 2, eb, rsz.RSZ_BIN_BACKGROUND))
+        prm = (11, 2, eb, rsz.RSZ_BIN_BACKGROUND)
+        t = autotune.tune(frames, peaks, prm, reps=3, budget_s=args.config_autotune_seconds)
+        B = rsz.Batch(frames, peaks, prm, *t["best"])
         B.prepare()
         B.graph()
         _warm(torch, B, label, launch=B.replay)
@@ -654,6 +656,8 @@ def jungfrau16m_graph_section(args, torch, dev):
         line.update(_path_roofline(raw_bytes, int(sizes.sum()), el, kms))
         line["kernel_ms"] = kms
         line["kernel_ms_source"] = "HIP events around every launch of 2 eager launches"
+        line["tile"] = {"best": list(t["best"]), "from_table": bool(t.get("cached")),
+                        "autotuned": not t.get("cached")}
         line["decompress_batched"] = batched_decode(torch, B, sizes, 3, raw_bytes)
         print(f"[bench] {label}: {line['value']} GB/s, path {line['path_frac']}, k_bin "
               f"{line.get('k_bin_frac')}, CR {line['compression_ratio_u16_aggregate']}; batched "

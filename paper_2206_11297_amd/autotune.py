@@ -131,13 +131,16 @@ def _workloads():
     cspad = lambda i: synth.batch_frame(i, counts)
     jf = lambda i: synth.jungfrau_frame(i, workload=synth.W_JF)
     sq = lambda i: synth.jungfrau_frame(i, shape=synth.SQUARE4M, npeaks=800, workload=synth.W_SERVE)
+    jf16 = lambda i: synth.jungfrau_frame(i, shape=synth.JUNGFRAU16M, workload=synth.W_JF16,
+                                          max_peaks=3000)
     out = [("cspad-batch-1000", cspad, 1000, [(17, 2, 10.0, 0)]),
            ("cspad-1", cspad, 1, [(17, 2, 10.0, 0)]),
            ("jungfrau4m-1", jf, 1, [(17, 2, 10.0, 0)]),
            ("jungfrau4m-32", jf, 32, [(17, 2, 10.0, 0)]),
            ("jungfrau4m-256", jf, 256, [(w, b, 10.0, 0) for w in (11, 25) for b in (2, 4)]),
            ("square2048-1", sq, 1, [(17, 2, 10.0, 0)]),
-           ("square2048-32", sq, 32, [(17, 2, 10.0, 0)])]
+           ("square2048-32", sq, 32, [(17, 2, 10.0, 0)]),
+           ("jungfrau16m-512", jf16, 512, [(11, 2, 1.0, 0), (11, 2, 10.0, 0)])]
     return out
 
 
