@@ -615,7 +615,8 @@ static int parse_header(const uint8_t *h, uint64_t n, uint64_t in_bytes, rsz_par
 uint64_t decode_roi_tables_bytes();
 
 static uint64_t decode_ws_bytes(const DecodePlan &dp) {
-  return align_up(4ull * dp.nbins, 256) + align_up(4ull * dp.nchunks, 256) + 256 +
+  return align_up(4ull * dp.nbins, 256) + align_up(dp.nbins + 64ull, 256) +
+         align_up(4ull * dp.nchunks, 256) + 256 +
          align_up(decode_tables_bytes(), 256) +
          (dp.dim == 1 ? align_up(4ull * dp.P * dp.Hb, 256) : 0) +
          (dp.roi_coding ? align_up(4ull * dp.npeaks * dp.w * dp.w, 256) +
@@ -686,6 +687,8 @@ static int decode_streams(uint32_t n, const DecodeItem *it, uint8_t *ws, uint64_
       dp.frame = it[f].frame;
       dp.res = (int32_t *)w;
       w += align_up(4ull * dp.nbins, 256);
+      dp.res8 = w;
+      w += align_up(dp.nbins + 64ull, 256);
       dp.zcount = (uint32_t *)w;
       w += align_up(4ull * dp.nchunks, 256);
       dp.status = (int32_t *)w;

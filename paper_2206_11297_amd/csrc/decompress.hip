@@ -49,6 +49,16 @@ namespace rsz {
 constexpr int kLutBits = 11;
 constexpr int32_t kMark = INT32_MIN;  // residual slot waiting for its outlier
 
+// Dimension 2 where a panel's bins fit in LDS (and a bin row in one
+// workgroup's threads): one workgroup per panel takes the row sums, the
+// column sums and the pixel writes, so the residuals make one trip from HBM.
+constexpr uint32_t kPanelBins = 19200;
+constexpr uint32_t kPanelThreads = 1024;
+__host__ __device__ inline bool panel_in_lds(const DecodePlan &dp) {
+  return dp.dim == 2 && (uint64_t)dp.Hb * dp.Wb <= kPanelBins && dp.Wb <= kPanelThreads;
+}
+
+
 // tables: [0,2048) lut (sym | len << 16, 0 = longer code), then first[33],
 // count[33], offs[33], sorted[1024], then the multi-symbol table: per 11-bit
 // window two words, (up to 3 whole codewords' symbols, 10 bits each) | count
@@ -287,13 +297,27 @@ struct BitWindow {
 // `inval` reports a bit pattern that is no codeword.  With `zrun` (residual
 // 0's codeword is the single bit 0), a run of z zero bits is z residual-0
 // symbols, taken at once up to lim.
+// One decoded symbol other than residual 0 into slot k: a residual, or the
+// outlier mark for code 0; with out8 (k_dec_panel's streams) a code byte,
+// and the residual in out only when the byte is 0.
+__device__ __forceinline__ void put_sym(int32_t *out, uint8_t *out8, uint32_t k, uint32_t sym) {
+  const int32_t r = sym ? (int32_t)sym - kRadius : kMark;
+  if (out8) {
+    const bool small = sym && (uint32_t)(r + 127) < 255u;
+    out8[k] = small ? (uint8_t)(r + 128) : (uint8_t)0;
+    if (!small) out[k] = r;
+  } else {
+    out[k] = r;
+  }
+}
+
 template <bool WRITE>
 __device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, uint64_t lim,
                                                const uint2 *s_multi, const uint32_t *s_first,
                                                const uint32_t *s_count, const uint32_t *s_offs,
                                                const uint16_t *s_sorted, int32_t *out,
                                                uint32_t cap, uint32_t &zeros, bool &inval,
-                                               bool zrun) {
+                                               bool zrun, uint8_t *out8 = nullptr) {
   uint32_t m = 0;
   while (pos < lim) {
     const uint32_t v = win.peek(pos);
@@ -313,7 +337,7 @@ __device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, ui
       for (uint32_t j = 0; j < take; ++j) {
         const uint32_t sym = (e.x >> (10 * j)) & 0x3FFu;
         zeros += sym == 0;
-        if (WRITE && m + j < cap && sym != kRadius) out[m + j] = sym ? (int32_t)sym - kRadius : kMark;
+        if (WRITE && m + j < cap && sym != kRadius) put_sym(out, out8, m + j, sym);
       }
       pos += (e.y >> (4 * (take - 1))) & 0xFu;
       m += take;
@@ -332,7 +356,7 @@ __device__ __forceinline__ uint32_t decode_run(BitWindow &win, uint64_t &pos, ui
         break;
       }
       zeros += sym == 0;
-      if (WRITE && m < cap && sym != kRadius) out[m] = sym ? (int32_t)sym - kRadius : kMark;
+      if (WRITE && m < cap && sym != kRadius) put_sym(out, out8, m, sym);
       pos += L;
       ++m;
     }
@@ -508,13 +532,22 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
   // the output pass, from the true starts: the wave zeroes the chunk's
   // residuals with whole-row stores, waits for them to complete, and the
   // lanes then store only their nonzero residuals (most are 0)
+  // (code bytes: 128, residual 0, in 16-byte stores; the region holds 64
+  // bytes past the last chunk)
+  const bool bytes = panel_in_lds(dp);
   if (!bad) {
-    int32_t *rc = dp.res + g0;
-    for (uint32_t i = 4 * lane; i < nsym; i += 256) {
-      if (i + 4 <= nsym) {
-        *(int4 *)(rc + i) = make_int4(0, 0, 0, 0);
-      } else {
-        for (uint32_t k = i; k < nsym; ++k) rc[k] = 0;
+    if (bytes) {
+      uint8_t *rc = dp.res8 + g0;
+      for (uint32_t i = 16 * lane; i < nsym; i += 1024) *(uint4 *)(rc + i) = make_uint4(
+          0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
+    } else {
+      int32_t *rc = dp.res + g0;
+      for (uint32_t i = 4 * lane; i < nsym; i += 256) {
+        if (i + 4 <= nsym) {
+          *(int4 *)(rc + i) = make_int4(0, 0, 0, 0);
+        } else {
+          for (uint32_t k = i; k < nsym; ++k) rc[k] = 0;
+        }
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -525,7 +558,8 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
   uint32_t zeros = 0;
   if (!bad)
     decode_run<true>(win, pos, lim, s_multi, s_first, s_count, s_offs, s_sorted, dp.res + g0 + off,
-                     off < nsym ? nsym - off : 0u, zeros, inv, zrun);
+                     off < nsym ? nsym - off : 0u, zeros, inv, zrun,
+                     bytes ? dp.res8 + g0 + off : nullptr);
   bad |= __builtin_amdgcn_uicmp((uint32_t)inv, 0u, 33 /* ne */) != 0;
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) zeros += __shfl_xor(zeros, d);
@@ -545,8 +579,10 @@ __global__ __launch_bounds__(256) void k_dec_outliers(DecBatch db) {
   const int32_t r = orr[k];
   // |q| < 2^28 bounds a residual of dimension d below 2^(28+d) in magnitude
   const int64_t lim = (int64_t)1 << (28 + dp.dim);
+  // the bin must have decoded as code 0 (its code byte 0 and the mark in res)
   if (g >= dp.nbins || (k > 0 && g <= oi[k - 1]) || (r > -kRadius && r < kRadius) ||
-      (int64_t)r <= -lim || (int64_t)r >= lim || dp.res[g] != kMark) {
+      (int64_t)r <= -lim || (int64_t)r >= lim || (panel_in_lds(dp) && dp.res8[g] != 0) ||
+      dp.res[g] != kMark) {
     corrupt(dp.status);
     return;
   }
@@ -740,15 +776,6 @@ __global__ __launch_bounds__(256) void k_dec_panels(DecBatch db) {
 // One wave per bin row: each lane takes a bin, computes its value once and
 // writes it to the bin's b x b pixels (clipped at the panel edges), a raw
 // row at a time, so the wave's stores of a row are contiguous.
-// Dimension 2 where a panel's bins fit in LDS (and a bin row in one
-// workgroup's threads): one workgroup per panel takes the row sums, the
-// column sums and the pixel writes, so the residuals make one trip from HBM.
-constexpr uint32_t kPanelBins = 19200;
-constexpr uint32_t kPanelThreads = 1024;
-__host__ __device__ inline bool panel_in_lds(const DecodePlan &dp) {
-  return dp.dim == 2 && (uint64_t)dp.Hb * dp.Wb <= kPanelBins && dp.Wb <= kPanelThreads;
-}
-
 __global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
   RSZ_DEC_FRAME(16);
   __shared__ uint32_t s_v[kPanelBins];
@@ -765,23 +792,34 @@ __global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
   if (!s_ok) return;
   const uint32_t Hb = dp.Hb, Wb = dp.Wb, n = Hb * Wb;
   const int32_t *r = dp.res + (size_t)bid * n;
-  // the panel's residuals into LDS, eight loads per thread in flight
-  bool bad = false;
+  const uint8_t *r8 = dp.res8 + (size_t)bid * n;
+  // the panel's code bytes into LDS as residuals, eight loads per thread in
+  // flight; a byte 0 (its residual in res) is marked and filled in a second
+  // pass, so that no load waits on another
+  bool bad = false, esc = false;
   for (uint32_t i0 = 0; i0 < n; i0 += 8 * kPanelThreads) {
-    int32_t v[8];
+    uint32_t v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const uint32_t i = i0 + k * kPanelThreads + t;
-      v[k] = i < n ? r[i] : 0;
+      v[k] = i < n ? r8[i] : 128u;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const uint32_t i = i0 + k * kPanelThreads + t;
       if (i < n) {
-        bad |= v[k] == kMark;
-        s_v[i] = (uint32_t)v[k];
+        esc |= v[k] == 0;
+        s_v[i] = v[k] ? (uint32_t)((int32_t)v[k] - 128) : (uint32_t)kMark;
       }
     }
+  }
+  if (__syncthreads_or(esc)) {
+    for (uint32_t i = t; i < n; i += kPanelThreads)
+      if (s_v[i] == (uint32_t)kMark) {
+        const int32_t x = r[i];
+        bad |= x == kMark;
+        s_v[i] = (uint32_t)x;
+      }
   }
   if (bad) s_bad = 1;
   __syncthreads();

@@ -196,7 +196,10 @@ struct DecodePlan {
   uint64_t off_peaks, off_roi, off_lens, off_oidx, off_ores, off_chunks, off_bits;
   const uint8_t *in;
   float *frame;
-  int32_t *res;         // nbins
+  int32_t *res;         // nbins: residuals; for k_dec_panel's streams only those
+                        // whose code byte (res8) is 0
+  uint8_t *res8;        // nbins (+64): k_dec_panel's streams, r + 128 for
+                        // |r| <= 127, else 0 with r (or the outlier mark) in res
   uint32_t *zcount;     // nchunks code-0 counts
   uint32_t *carry;      // dim 1: P*Hb row carries
   int32_t *status;      // one word
