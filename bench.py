@@ -616,7 +616,8 @@ def jungfrau16m_graph_section(args, torch, dev):
     """Batches of Jungfrau-16M-like frames (16x512x1024 f32, 0-3000 peaks),
     window 11, bin 2, eb 1 and 10 ADU: the prepared batch captured in a HIP
     graph and replayed, each replay recomputing every stream; the same
-    streams decoded in one batched call."""
+    streams decoded in one batched call; and the graph of compression
+    followed by the on-device verification stage (rsz_verify_*)."""
     import numpy as np
     from paper_2206_11297_amd import autotune, rsz, synth
     n = args.jf16m_frames
@@ -659,9 +660,30 @@ def jungfrau16m_graph_section(args, torch, dev):
         line["tile"] = {"best": list(t["best"]), "from_table": bool(t.get("cached")),
                         "autotuned": not t.get("cached")}
         line["decompress_batched"] = batched_decode(torch, B, sizes, 3, raw_bytes)
+        # the same batch with the verification stage in its graph: every
+        # stream decoded and every pixel checked on the device
+        V = rsz.Verify(B)
+        V.graph()
+        V.replay()
+        torch.cuda.synchronize()
+        bad = V.bad_counts()
+        assert not any(bad), f"{label}: verification failed on {sum(1 for v in bad if v)} frames"
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.config_steps // 2)):
+            V.replay()
+        torch.cuda.synchronize()
+        el_v = (time.perf_counter() - t0) / max(1, args.config_steps // 2)
+        line["with_verification"] = {
+            "ms_per_step": round(el_v * 1e3, 4), "value": round(raw_bytes / el_v / 1e9, 2),
+            "unit": "GB/s", "frames_verified": len(bad),
+            "note": "one graph: compression, then every stream decoded on the device and every "
+                    "pixel checked against its frame (ROI bit-exact, background within eb of its "
+                    "bin mean)"}
+        del V
         print(f"[bench] {label}: {line['value']} GB/s, path {line['path_frac']}, k_bin "
               f"{line.get('k_bin_frac')}, CR {line['compression_ratio_u16_aggregate']}; batched "
-              f"decompression {line['decompress_batched']['gbps']} GB/s",
+              f"decompression {line['decompress_batched']['gbps']} GB/s; with on-device "
+              f"verification {line['with_verification']['ms_per_step']} ms a step",
               file=sys.stderr, flush=True)
         out[label] = line
         del B

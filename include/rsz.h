@@ -218,6 +218,39 @@ int rsz_batch_launch(const rsz_batch_plan *h_plan, void *stream);
  * stream; rsz_graph_destroy frees it. */
 int rsz_batch_graph_create(const rsz_batch_plan *h_plan, void *stream, void **h_graph_exec);
 int rsz_graph_launch(void *graph_exec, void *stream);
+
+/* On-device verification of a prepared batch, the decompress-and-check stage
+ * of a graph-captured pipeline: every stream the batch writes is decoded on
+ * the device (the decoder kernels of rsz_decompress_batch, their plans
+ * completed on the device from the totals the compression left there) into
+ * h_frames_out[i] (device, panels*height*width float32), and every pixel is
+ * checked against the frame it came from: a pixel of an ROI window must
+ * carry the frame's bits (Sec. IV), any other pixel must lie within eb of
+ * the mean of its bin's pixels (Sec. V-C, the absolute bound on binned
+ * values; Sec. IV-A, the bin value restored to each pixel), with the
+ * float32 rounding of the stored value and a 2^-40 relative slack for the
+ * fp64 sums.  d_bad[i] (device) receives frame i's count of pixels that
+ * fail, 0xFFFFFFFF when its compression or decoding failed or it is not
+ * verified (only frames with the ROI verbatim and no run stage are).
+ * h_plan: from rsz_batch_prepare over the same descriptors; the plan,
+ * descriptors and buffers are fixed at prepare time, and every launch
+ * decodes and checks the batch's current streams.  rsz_verify_launch
+ * queues kernels only (capturable); rsz_verify_graph_create captures the
+ * batch's launch followed by the verification into one HIP graph (replay
+ * with rsz_graph_launch, free with rsz_graph_destroy).  The workspace is
+ * the caller's, separate from the batch's. */
+typedef struct {
+  uint64_t opaque[32];
+} rsz_verify_plan;
+
+int rsz_verify_workspace_bytes(const rsz_batch_plan *h_plan, uint32_t nframes,
+                               const rsz_frame_desc *h_descs, uint64_t *bytes);
+int rsz_verify_prepare(const rsz_batch_plan *h_plan, uint32_t nframes,
+                       const rsz_frame_desc *h_descs, float *const *h_frames_out, uint32_t *d_bad,
+                       void *d_ws, uint64_t ws_bytes, void *stream, rsz_verify_plan *h_vplan);
+int rsz_verify_launch(const rsz_verify_plan *h_vplan, void *stream);
+int rsz_verify_graph_create(const rsz_batch_plan *h_plan, const rsz_verify_plan *h_vplan,
+                            void *stream, void **h_graph_exec);
 int rsz_graph_destroy(void *graph_exec);
 
 /* Parse and check the 80-byte header of a stream held in host memory

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librsz.so")
-SOURCES = ["api.hip", "compress.hip", "decompress.hip", "peaks.hip"]
+SOURCES = ["api.hip", "compress.hip", "decompress.hip", "peaks.hip", "verify.hip"]
 
 # -ffp-contract=off: no FMA contraction (the fp64 sums and the divide must be
 # the plain IEEE operations); denormals preserved; packed fp32 disabled.

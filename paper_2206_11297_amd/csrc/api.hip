@@ -1064,6 +1064,230 @@ int rsz_batch_graph_create(const rsz_batch_plan *h_plan, void *stream, void **h_
   return RSZ_OK;
 }
 
+// ------------------------------------------------------------ verification
+
+}  // extern "C"
+
+namespace rsz {
+// Host record of a prepared verification (the public rsz_verify_plan is its
+// storage): the verification batch, the decoder batch and its grid sizes.
+struct VerifyRecord {
+  VerifyBatch vb;
+  DecBatch db;
+  uint32_t dec_total[kDecKernels];
+};
+static_assert(sizeof(VerifyRecord) <= sizeof(rsz_verify_plan), "verify record too large");
+
+// Plans the verification of a prepared batch: per frame a decoder plan whose
+// geometry and pointers are fixed here (k_vplan fills in the totals on the
+// device), its workspace region, and the k_verify blocks.  With ws, uploads
+// it all and fills *vr; *need: the workspace bytes.
+static int verify_plan(const PlanRecord &rec, uint32_t n, const rsz_frame_desc *d,
+                       float *const *frames_out, uint32_t *d_bad, uint8_t *ws, uint64_t ws_bytes,
+                       hipStream_t s, uint64_t *need, VerifyRecord *vr) {
+  if (n == 0 || !d || n != rec.bp.nframes || !rec.bp.frames) return RSZ_ERR_ARG;
+  std::vector<DecodePlan> dps(n);
+  std::vector<VerifyFrame> vfs(n);
+  std::vector<uint64_t> region(n, 0);
+  const uint64_t h_dp = align_up((uint64_t)sizeof(DecodePlan) * n, 256);
+  const uint64_t h_pre = align_up(4ull * kDecKernels * (n + 1), 256);
+  const uint64_t h_vf = align_up((uint64_t)sizeof(VerifyFrame) * n, 256);
+  const uint64_t h_vp = align_up(4ull * (n + 1), 256);
+  const uint64_t head = h_dp + h_pre + h_vf + h_vp;
+  uint64_t total = head;
+  for (uint32_t f = 0; f < n; ++f) {
+    DecodePlan &dp = dps[f];
+    VerifyFrame &vf = vfs[f];
+    memset(&dp, 0, sizeof dp);
+    memset(&vf, 0, sizeof vf);
+    const rsz_params *p = &d[f].params;
+    // (the sizing pass has no output frames yet; the prepare pass needs them)
+    bool ok = check_params(p, d[f].npeaks) == RSZ_OK && !p->roi_coding && !p->run_coding &&
+              d[f].frame && d[f].out && (d[f].npeaks == 0 || d[f].peaks);
+    if (ok && ws && !(frames_out && frames_out[f])) return RSZ_ERR_ARG;
+    uint32_t rows = 0;
+    if (ok) {
+      const uint32_t wpr = (p->width + 31) / 32;
+      rows = (kVerifyMaskWords / wpr) / p->bin * p->bin;
+      ok = rows > 0;
+    }
+    if (!ok) {
+      dp.init_status = RSZ_ERR_ARG;
+      region[f] = 256;   // its status word
+      total += region[f];
+      continue;
+    }
+    const Geom g = geometry(p, d[f].npeaks, kMaxTH, 1);
+    dp.P = p->panels;
+    dp.H = p->height;
+    dp.W = p->width;
+    dp.w = p->window;
+    dp.b = p->bin;
+    dp.npeaks = d[f].npeaks;
+    dp.dim = p->dim ? p->dim : 2u;
+    dp.step = 2.0 * p->eb;
+    dp.Hb = g.Hb;
+    dp.Wb = g.Wb;
+    dp.nbins = g.nbins;
+    dp.nchunks = g.nchunks;
+    dp.off_peaks = kHeader;
+    dp.off_roi = g.off_roi;
+    dp.off_lens = g.off_lens;
+    dp.off_chunks = g.off_chunks;
+    dp.off_bits = g.off_bits;
+    dp.init_status = RSZ_OK;
+    region[f] = decode_ws_bytes(dp);
+    total += region[f];
+    rows = std::min<uint32_t>(rows, (uint32_t)align_up(p->height, p->bin));
+    vf.x = d[f].frame;
+    vf.y = frames_out ? frames_out[f] : nullptr;
+    vf.peaks = (const int32_t *)d[f].peaks;
+    vf.npeaks = d[f].npeaks;
+    vf.P = p->panels;
+    vf.H = p->height;
+    vf.W = p->width;
+    vf.w = p->window;
+    vf.b = p->bin;
+    vf.mode = p->bin_mode;
+    vf.eb = p->eb;
+    vf.rows = rows;
+    vf.chunks = (p->height + rows - 1) / rows;
+    vf.valid = 1;
+  }
+  if (need) *need = total;
+  if (!ws) return RSZ_OK;
+  if (!d_bad || (uintptr_t)ws % 256) return RSZ_ERR_ARG;
+  if (ws_bytes < total) return RSZ_ERR_WORKSPACE;
+  std::vector<uint8_t> host(head, 0);
+  uint32_t *pre = (uint32_t *)(host.data() + h_dp);
+  uint32_t *vpre = (uint32_t *)(host.data() + h_dp + h_pre + h_vf);
+  uint64_t off = head;
+  uint32_t dec_total[kDecKernels] = {0};
+  uint64_t wgs = 0;
+  for (uint32_t f = 0; f < n; ++f) {
+    DecodePlan &dp = dps[f];
+    VerifyFrame &vf = vfs[f];
+    uint8_t *w = ws + off;
+    off += region[f];
+    if (vf.valid) {
+      dp.in = (const uint8_t *)d[f].out;
+      dp.frame = frames_out[f];
+      dp.res = (int32_t *)w;
+      w += align_up(4ull * dp.nbins, 256);
+      dp.res8 = w;
+      w += align_up(dp.nbins + 64ull, 256);
+      dp.zcount = (uint32_t *)w;
+      w += align_up(4ull * dp.nchunks, 256);
+      dp.status = (int32_t *)w;
+      w += 256;
+      dp.tables = (uint32_t *)w;
+      w += align_up(decode_tables_bytes(), 256);
+      if (dp.dim == 1) dp.carry = (uint32_t *)w;
+      dp.bits = (const uint32_t *)(dp.in + dp.off_bits);
+    } else {
+      dp.status = (int32_t *)w;
+    }
+    vf.cplan = rec.bp.frames + f;
+    vf.dplan = (DecodePlan *)ws + f;
+    vf.bad = d_bad + f;
+    uint32_t nb[kDecKernels];
+    decode_blocks(dp, nb);
+    // the outliers: a fixed number of workgroups (their count is known only
+    // on the device), each striding over them
+    if (vf.valid) nb[4] = std::min<uint32_t>(kVerifyOutlierBlocks, (dp.nbins + 255) / 256);
+    for (int k = 0; k < kDecKernels; ++k) {
+      pre[(size_t)k * (n + 1) + f] = dec_total[k];
+      if ((uint64_t)dec_total[k] + nb[k] > 0x7FFFFFFFull) return RSZ_ERR_ARG;
+      dec_total[k] += nb[k];
+    }
+    vpre[f] = (uint32_t)wgs;
+    if (vf.valid) wgs += (uint64_t)vf.P * vf.chunks;
+    if (wgs > 0x7FFFFFFFull) return RSZ_ERR_ARG;
+  }
+  for (int k = 0; k < kDecKernels; ++k) pre[(size_t)k * (n + 1) + n] = dec_total[k];
+  vpre[n] = (uint32_t)wgs;
+  memcpy(host.data(), dps.data(), sizeof(DecodePlan) * n);
+  memcpy(host.data() + h_dp + h_pre, vfs.data(), sizeof(VerifyFrame) * n);
+  const int st = stage_to_device(ws, host.data(), head, s);
+  if (st) return st;
+  memset(vr, 0, sizeof *vr);
+  vr->vb.n = n;
+  vr->vb.frames = (const VerifyFrame *)(ws + h_dp + h_pre);
+  vr->vb.wg_prefix = (const uint32_t *)(ws + h_dp + h_pre + h_vf);
+  vr->vb.total_wgs = (uint32_t)wgs;
+  vr->db.n = n;
+  vr->db.plans = (const DecodePlan *)ws;
+  vr->db.pre = (const uint32_t *)(ws + h_dp);
+  memcpy(vr->dec_total, dec_total, sizeof dec_total);
+  return RSZ_OK;
+}
+}  // namespace rsz
+
+extern "C" {
+
+int rsz_verify_workspace_bytes(const rsz_batch_plan *h_plan, uint32_t nframes,
+                               const rsz_frame_desc *h_descs, uint64_t *bytes) {
+  if (!h_plan || !bytes) return RSZ_ERR_ARG;
+  PlanRecord rec;
+  memcpy(&rec, h_plan, sizeof rec);
+  return verify_plan(rec, nframes, h_descs, nullptr, nullptr, nullptr, 0, nullptr, bytes,
+                     nullptr);
+}
+
+int rsz_verify_prepare(const rsz_batch_plan *h_plan, uint32_t nframes,
+                       const rsz_frame_desc *h_descs, float *const *h_frames_out, uint32_t *d_bad,
+                       void *d_ws, uint64_t ws_bytes, void *stream, rsz_verify_plan *h_vplan) {
+  if (!h_plan || !h_vplan || !d_ws || !h_frames_out) return RSZ_ERR_ARG;
+  PlanRecord rec;
+  memcpy(&rec, h_plan, sizeof rec);
+  VerifyRecord vr;
+  const int st = verify_plan(rec, nframes, h_descs, h_frames_out, d_bad, (uint8_t *)d_ws,
+                             ws_bytes, (hipStream_t)stream, nullptr, &vr);
+  if (st) return st;
+  memset(h_vplan, 0, sizeof *h_vplan);
+  memcpy(h_vplan, &vr, sizeof vr);
+  return RSZ_OK;
+}
+
+int rsz_verify_launch(const rsz_verify_plan *h_vplan, void *stream) {
+  if (!h_vplan) return RSZ_ERR_ARG;
+  VerifyRecord vr;
+  memcpy(&vr, h_vplan, sizeof vr);
+  if (vr.vb.n == 0 || !vr.vb.frames) return RSZ_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_verify_plan(vr.vb, s) != hipSuccess) return RSZ_ERR_HIP;
+  if (launch_decompress(vr.db, vr.dec_total, s) != hipSuccess) return RSZ_ERR_HIP;
+  if (launch_verify_check(vr.vb, s) != hipSuccess) return RSZ_ERR_HIP;
+  return RSZ_OK;
+}
+
+int rsz_verify_graph_create(const rsz_batch_plan *h_plan, const rsz_verify_plan *h_vplan,
+                            void *stream, void **h_graph_exec) {
+  if (!h_plan || !h_vplan || !h_graph_exec) return RSZ_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipGraph_t g = nullptr;
+  const bool prof = g_prof_on;
+  g_prof_on = false;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    g_prof_on = prof;
+    return RSZ_ERR_HIP;
+  }
+  int st = rsz_batch_launch(h_plan, stream);
+  if (st == RSZ_OK) st = rsz_verify_launch(h_vplan, stream);
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  g_prof_on = prof;
+  if (st != RSZ_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != RSZ_OK ? st : RSZ_ERR_HIP;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return RSZ_ERR_HIP;
+  *h_graph_exec = (void *)ex;
+  return RSZ_OK;
+}
+
 int rsz_graph_launch(void *graph_exec, void *stream) {
   if (!graph_exec) return RSZ_ERR_ARG;
   return hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream) == hipSuccess

@@ -569,24 +569,28 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
   }
 }
 
+// The outliers into their bins' residual slots; the frame's workgroups take
+// every nblk-th block of 256 (a verification plan launches a fixed number
+// per frame, the outlier count being known only on the device).
 __global__ __launch_bounds__(256) void k_dec_outliers(DecBatch db) {
   RSZ_DEC_FRAME(4);
-  const uint32_t k = bid * 256 + threadIdx.x;
-  if (k >= dp.n_out || !dec_ok(dp.status)) return;
+  if (!dec_ok(dp.status)) return;
   const uint32_t *oi = (const uint32_t *)(dp.in + dp.off_oidx);
   const int32_t *orr = (const int32_t *)(dp.in + dp.off_ores);
-  const uint32_t g = oi[k];
-  const int32_t r = orr[k];
   // |q| < 2^28 bounds a residual of dimension d below 2^(28+d) in magnitude
   const int64_t lim = (int64_t)1 << (28 + dp.dim);
-  // the bin must have decoded as code 0 (its code byte 0 and the mark in res)
-  if (g >= dp.nbins || (k > 0 && g <= oi[k - 1]) || (r > -kRadius && r < kRadius) ||
-      (int64_t)r <= -lim || (int64_t)r >= lim || (panel_in_lds(dp) && dp.res8[g] != 0) ||
-      dp.res[g] != kMark) {
-    corrupt(dp.status);
-    return;
+  for (uint32_t k = bid * 256 + threadIdx.x; k < dp.n_out; k += nblk * 256) {
+    const uint32_t g = oi[k];
+    const int32_t r = orr[k];
+    // the bin must have decoded as code 0 (its code byte 0 and the mark in res)
+    if (g >= dp.nbins || (k > 0 && g <= oi[k - 1]) || (r > -kRadius && r < kRadius) ||
+        (int64_t)r <= -lim || (int64_t)r >= lim || (panel_in_lds(dp) && dp.res8[g] != 0) ||
+        dp.res[g] != kMark) {
+      corrupt(dp.status);
+      return;
+    }
+    dp.res[g] = r;
   }
-  dp.res[g] = r;
 }
 
 // One wave per bin row: inclusive prefix sum along the row.

@@ -221,6 +221,34 @@ void decode_blocks(const DecodePlan &dp, uint32_t *nb);
 // Launches the kernels with total[K] workgroups (the prefixes' last entries).
 hipError_t launch_decompress(const DecBatch &db, const uint32_t *total, hipStream_t s);
 
+// On-device verification of a compressed batch (verify.hip): the batch's
+// streams decoded by the decoder kernels (their plans completed on the
+// device from the compression's totals), then every pixel checked against
+// the frame it came from.
+constexpr uint32_t kVerifyMaskWords = 8192;   // LDS ROI bitmap of a workgroup's rows
+constexpr uint32_t kVerifyOutlierBlocks = 16; // k_dec_outliers workgroups per frame
+struct VerifyFrame {
+  const float *x;           // the frame
+  const float *y;           // its decoding
+  const int32_t *peaks;
+  uint32_t npeaks, P, H, W, w, b, mode;
+  double eb;
+  uint32_t rows;            // raw rows per k_verify workgroup (a multiple of b)
+  uint32_t chunks;          // k_verify workgroups per panel
+  int32_t valid;            // the descriptor was valid
+  const FramePlan *cplan;   // the compression's plan of the frame (device)
+  DecodePlan *dplan;        // the decoder's plan (device; k_vplan completes it)
+  uint32_t *bad;            // device: violations, or 0xFFFFFFFF when a stage failed
+};
+struct VerifyBatch {
+  uint32_t n;
+  const VerifyFrame *frames;  // device
+  const uint32_t *wg_prefix;  // device, n + 1: k_verify workgroups per frame
+  uint32_t total_wgs;
+};
+hipError_t launch_verify_plan(const VerifyBatch &vb, hipStream_t s);
+hipError_t launch_verify_check(const VerifyBatch &vb, hipStream_t s);
+
 // Peak finding (peaks.hip).
 constexpr uint32_t kPeakTile = 16384;     // pixels per k_peaks_find workgroup
 constexpr uint32_t kPeakCapMax = 8192;    // most peaks a frame's list may hold

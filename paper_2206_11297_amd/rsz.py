@@ -20,6 +20,8 @@ EXPORTS = ["rsz_status_string", "rsz_max_compressed_bytes", "rsz_workspace_bytes
            "rsz_compress_batch",
            "rsz_batch_prepare", "rsz_batch_launch", "rsz_batch_graph_create",
            "rsz_graph_launch", "rsz_graph_destroy",
+           "rsz_verify_workspace_bytes", "rsz_verify_prepare", "rsz_verify_launch",
+           "rsz_verify_graph_create",
            "rsz_stream_info", "rsz_decompress_workspace_bytes", "rsz_decompress",
            "rsz_decompress_batch_workspace_bytes", "rsz_decompress_batch",
            "rsz_debug_intermediates", "rsz_debug_codebook", "rsz_measure_read",
@@ -54,6 +56,10 @@ class rsz_frame_desc(C.Structure):
 
 
 class rsz_batch_plan(C.Structure):
+    _fields_ = [("opaque", C.c_uint64 * 32)]
+
+
+class rsz_verify_plan(C.Structure):
     _fields_ = [("opaque", C.c_uint64 * 32)]
 
 
@@ -103,6 +109,12 @@ def lib():
                                         P(rsz_batch_plan)]
         L.rsz_batch_launch.argtypes = [P(rsz_batch_plan), vp]
         L.rsz_batch_graph_create.argtypes = [P(rsz_batch_plan), vp, P(vp)]
+        L.rsz_verify_workspace_bytes.argtypes = [P(rsz_batch_plan), u32, P(rsz_frame_desc),
+                                                 P(u64)]
+        L.rsz_verify_prepare.argtypes = [P(rsz_batch_plan), u32, P(rsz_frame_desc), P(vp), vp, vp,
+                                         u64, vp, P(rsz_verify_plan)]
+        L.rsz_verify_launch.argtypes = [P(rsz_verify_plan), vp]
+        L.rsz_verify_graph_create.argtypes = [P(rsz_batch_plan), P(rsz_verify_plan), vp, P(vp)]
         L.rsz_graph_launch.argtypes = [vp, vp]
         L.rsz_graph_destroy.argtypes = [vp]
         L.rsz_stream_info.argtypes = [vp, u64, P(rsz_params), P(u32), P(u64)]
@@ -197,6 +209,32 @@ def rsz_batch_launch(plan, stream):
 def rsz_batch_graph_create(plan, stream):
     ex = C.c_void_p()
     st = lib().rsz_batch_graph_create(C.byref(plan), stream, C.byref(ex))
+    return st, ex
+
+
+def rsz_verify_workspace_bytes(plan, descs):
+    arr = (rsz_frame_desc * len(descs))(*descs)
+    out = C.c_uint64(0)
+    st = lib().rsz_verify_workspace_bytes(C.byref(plan), len(descs), arr, C.byref(out))
+    return st, out.value
+
+
+def rsz_verify_prepare(plan, descs, frames_out, d_bad, d_ws, ws_bytes, stream):
+    arr = (rsz_frame_desc * len(descs))(*descs)
+    fo = (C.c_void_p * len(frames_out))(*frames_out)
+    vplan = rsz_verify_plan()
+    st = lib().rsz_verify_prepare(C.byref(plan), len(descs), arr, fo, d_bad, d_ws, ws_bytes,
+                                  stream, C.byref(vplan))
+    return st, vplan
+
+
+def rsz_verify_launch(vplan, stream):
+    return lib().rsz_verify_launch(C.byref(vplan), stream)
+
+
+def rsz_verify_graph_create(plan, vplan, stream):
+    ex = C.c_void_p(0)
+    st = lib().rsz_verify_graph_create(C.byref(plan), C.byref(vplan), stream, C.byref(ex))
     return st, ex
 
 
@@ -555,6 +593,67 @@ class Batch:
         """Stream of frame i as a GPU uint8 view (after the stream finished)."""
         n = int(self.sizes[i]) if sizes is None else int(sizes[i])
         return self.out[self.offsets[i]:self.offsets[i] + n]
+
+
+class Verify:
+    """On-device verification of a prepared Batch (rsz_verify_*): every
+    stream the batch writes decoded into frames of its own and every pixel
+    checked against its frame.  launch() queues it after the batch's work;
+    graph() captures the batch's launch and the verification into one HIP
+    graph (replay()).  bad[i] (uint32 in an int32 tensor): frame i's failing
+    pixels, 0xFFFFFFFF when a stage failed or the frame is not verified."""
+
+    def __init__(self, B):
+        torch = _torch()
+        if getattr(B, "plan", None) is None:
+            raise RuntimeError("Verify needs a prepared Batch (B.prepare())")
+        self.B = B
+        dev = B.frames[0].device
+        self.frames = [torch.empty_like(f) for f in B.frames]
+        self.bad = torch.zeros(len(B.frames), dtype=torch.int32, device=dev)
+        st, wsb = rsz_verify_workspace_bytes(B.plan, B.descs)
+        if st:
+            raise RszError(st, "rsz_verify_workspace_bytes")
+        self.ws = workspace(wsb, dev)
+        st, self.vplan = rsz_verify_prepare(B.plan, B.descs, [f.data_ptr() for f in self.frames],
+                                            _ptr(self.bad), _ptr(self.ws), self.ws.numel(),
+                                            _stream())
+        if st:
+            raise RszError(st, "rsz_verify_prepare")
+        self.graph_exec = None
+
+    def launch(self):
+        st = rsz_verify_launch(self.vplan, _stream())
+        if st:
+            raise RszError(st, "rsz_verify_launch")
+
+    def graph(self):
+        """Capture the batch's launch followed by the verification."""
+        torch = _torch()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        st, self.graph_exec = rsz_verify_graph_create(self.B.plan, self.vplan,
+                                                      C.c_void_p(side.cuda_stream))
+        if st:
+            raise RszError(st, "rsz_verify_graph_create")
+        torch.cuda.current_stream().wait_stream(side)
+
+    def replay(self):
+        st = rsz_graph_launch(self.graph_exec, _stream())
+        if st:
+            raise RszError(st, "rsz_graph_launch")
+
+    def bad_counts(self):
+        """Per-frame failing-pixel counts as Python ints (0xFFFFFFFF: not verified)."""
+        return [int(v) & 0xFFFFFFFF for v in self.bad.cpu().tolist()]
+
+    def __del__(self):
+        ex = getattr(self, "graph_exec", None)
+        if ex is not None and ex.value:
+            try:
+                rsz_graph_destroy(ex)
+            except Exception:
+                pass
 
 
 # ------------------------------------------------------------ peak finding

@@ -107,7 +107,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     structs = {"rsz_peak": None, "rsz_params": rsz.rsz_params, "rsz_frame_desc": rsz.rsz_frame_desc,
                "rsz_batch_plan": rsz.rsz_batch_plan, "rsz_debug_bufs": rsz.rsz_debug_bufs,
                "rsz_kernel_time": rsz.rsz_kernel_time, "rsz_peak_params": rsz.rsz_peak_params,
-               "rsz_peak_desc": rsz.rsz_peak_desc, "rsz_decode_desc": rsz.rsz_decode_desc}
+               "rsz_peak_desc": rsz.rsz_peak_desc, "rsz_decode_desc": rsz.rsz_decode_desc,
+               "rsz_verify_plan": rsz.rsz_verify_plan}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rsz.h"', 'int main(void) {']
     for name, cls in structs.items():
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
@@ -186,3 +187,34 @@ def test_profile_filter_on_the_host():
     assert rsz.rsz_profile_read() == {}
     assert rsz.rsz_profile_enable(False) == 0
     assert rsz.rsz_profile_only(None) == 0
+
+
+def test_verify_planner_on_the_host():
+    """rsz_verify_workspace_bytes plans from the descriptors alone (no device
+    memory is touched): every frame the stage verifies adds its decoder
+    region, a frame with the ROI coded or invalid parameters only a status
+    word; a plan for another frame count, or a prepare without output
+    frames, is refused before any upload."""
+    cases = [((32, 185, 388), (17, 2, 10.0, 0), 60), ((8, 512, 1024), (25, 4, 10.0, 0), 100),
+             ((3, 70, 130), (7, 3, 1.0, 1), 6), ((1, 1, 1), (1, 1, 1.0, 0), 1)]
+    fake = 1 << 20   # device addresses are not read by the host planner
+
+    def desc(shape, prm, npk):
+        d = rsz.rsz_frame_desc()
+        d.params = rsz.params(*shape, *prm)
+        d.frame, d.peaks, d.npeaks, d.out, d.out_cap = fake, fake if npk else None, npk, fake, 1 << 30
+        return d
+
+    descs = [desc(*c) for c in cases]
+    plan = rsz.rsz_batch_plan()
+    for i in range(len(plan.opaque)):
+        plan.opaque[i] = len(descs)   # a frame count of 4 and non-null pointers
+    st, full = rsz.rsz_verify_workspace_bytes(plan, descs)
+    assert st == 0 and full > 32 * 185 * 388
+    coded = list(descs)
+    coded[1] = desc((8, 512, 1024), (25, 4, 10.0, 0, 2, 1), 100)
+    st, less = rsz.rsz_verify_workspace_bytes(plan, coded)
+    assert st == 0 and less < full - 8 * 512 * 1024 // 16
+    assert rsz.rsz_verify_workspace_bytes(plan, descs[:3])[0] == rsz.RSZ_ERR_ARG
+    st, _ = rsz.rsz_verify_prepare(plan, descs, [0] * 4, fake, fake, 1 << 40, None)
+    assert st == rsz.RSZ_ERR_ARG

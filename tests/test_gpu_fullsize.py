@@ -5,8 +5,8 @@ configurations, every frame against the oracle:
   every error bound {1, 5, 10, 20}, one batched launch each;
 - 256-frame Jungfrau-4M batches (8x512x1024) over window {11, 25} x bin {2, 4};
 - 512-frame Jungfrau-16M batches (16x512x1024, 0-3000 peaks) captured in a
-  HIP graph and replayed, at eb 1 and 10, with every frame decompressed and
-  checked on the device too.
+  HIP graph with the library's verification stage and replayed, at eb 1 and
+  10: every frame decompressed and checked on the device.
 
 Every stream of every batch is compared with the oracle's byte for byte (the
 oracle runs on a pool of threads: its C calls release the interpreter lock),
@@ -274,16 +274,24 @@ def _verify_on_device(torch, x, pk, y, w, b, eb):
 
 @pytest.mark.parametrize("w,eb", [(11, 1.0), (25, 10.0)])
 def test_jungfrau16m_graph_512_verified_on_device(torch, jf16m_512, w, eb):
+    """Compression and the library's verification stage (rsz_verify_*) in one
+    HIP graph, replayed: every frame decoded and checked on the device (no
+    failing pixel), every stream equal to the oracle's, sampled decodings
+    equal to the oracle's decompression, and the stage's check crossed with
+    an independent one in torch on two frames."""
     host, frames, peaks = jf16m_512
     print(f"jungfrau-16M graph batch 512 w={w} eb={eb}", flush=True)
     B = rsz.Batch(frames, peaks, (w, 2, eb, 0))
     B.prepare()
-    B.graph()
+    V = rsz.Verify(B)
+    V.graph()
     first = None
     for rep in range(3):
-        B.replay()
+        V.replay()
         torch.cuda.synchronize()
         assert (B.status.cpu().numpy() == 0).all()
+        bad = V.bad_counts()
+        assert bad == [0] * len(host), [(i, v) for i, v in enumerate(bad) if v][:10]
         sizes = B.sizes.cpu().numpy()
         probe = B.stream(int(np.argmax(sizes)), sizes).clone()
         if first is None:
@@ -291,10 +299,15 @@ def test_jungfrau16m_graph_512_verified_on_device(torch, jf16m_512, w, eb):
         else:
             assert (sizes == first[0]).all()
             assert torch.equal(probe, first[1])
+    print("  512/512 frames verified on the device", flush=True)
     streams = _streams(B, sizes)
     _check_oracle_all(streams, host, synth.JUNGFRAU16M, w, 2, eb)
-    ws = None
-    for i in range(len(host)):
-        y = rsz.decompress(B.stream(i, sizes), ws)
-        _verify_on_device(torch, frames[i], peaks[i], y, w, 2, eb)
+    counts = [p.shape[0] for _, p in host]
+    for i in sorted({0, len(host) - 1, int(np.argmax(counts))}):
+        st, yo = O.decompress(streams[i])
+        assert st == O.OK
+        np.testing.assert_array_equal(V.frames[i].cpu().numpy().view(np.uint32),
+                                      yo.view(np.uint32), err_msg=f"frame {i}")
+    for i in (0, int(np.argmax(counts))):
+        _verify_on_device(torch, frames[i], peaks[i], V.frames[i], w, 2, eb)
     torch.cuda.synchronize()
