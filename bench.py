@@ -72,7 +72,15 @@ def serving_section(args, torch, dev, pool):
                               ws_bytes=args.serve_batch * (12 << 20))
     out["hbm_budget_gb"] = round(args.serve_slots * (limits.out_bytes + limits.ws_bytes) / 1e9, 2)
     batched = serve.GpuExecutor(args.serve_slots, limits, dev)
-    single_lim = serve.SlotLimits(1, 14 << 20, 12 << 20)
+    # one frame per launch: a slot sized for the largest request of the pool,
+    # so that it carries every request the batched slots carry
+    need_out = need_ws = 0
+    for f, p in gpool:
+        for eb in (5.0, 10.0, 20.0):
+            r = serve.Request(0, 0.0, f, p, (17, 2, eb, 0))
+            batched.size_request(r)
+            need_out, need_ws = max(need_out, r.out_cap), max(need_ws, r.ws_bytes)
+    single_lim = serve.SlotLimits(1, need_out, need_ws)
     single = serve.GpuExecutor(1, single_lim, dev)
 
     def requests(rate, n, seed):

@@ -234,7 +234,8 @@ __global__ __launch_bounds__(256) void k_dec_tables(DecBatch db) {
 }
 
 // Four stream words from word index w (0 past the stream's end).
-__device__ __forceinline__ uint4 ld4(const uint32_t *bw, uint64_t nwords, uint64_t w) {
+__device__ __forceinline__ uint4 ld4(const uint32_t *bw_, uint64_t nwords, uint64_t w) {
+  const RSZ_G uint32_t *bw = gm(bw_);
   uint4 r;
   r.x = w < nwords ? bw[w] : 0u;
   r.y = w + 1 < nwords ? bw[w + 1] : 0u;
@@ -304,10 +305,10 @@ __device__ __forceinline__ void put_sym(int32_t *out, uint8_t *out8, uint32_t k,
   const int32_t r = sym ? (int32_t)sym - kRadius : kMark;
   if (out8) {
     const bool small = sym && (uint32_t)(r + 127) < 255u;
-    out8[k] = small ? (uint8_t)(r + 128) : (uint8_t)0;
-    if (!small) out[k] = r;
+    *gm(out8 + k) = small ? (uint8_t)(r + 128) : (uint8_t)0;
+    if (!small) *gm(out + k) = r;
   } else {
-    out[k] = r;
+    *gm(out + k) = r;
   }
 }
 
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
   const int lane = threadIdx.x & 63;
   const uint32_t c = bid * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c >= dp.nchunks || !dec_ok(dp.status)) return;
-  const uint32_t *co = (const uint32_t *)(dp.in + dp.off_chunks);
+  const RSZ_G uint32_t *co = gm((const uint32_t *)(dp.in + dp.off_chunks));
   const uint32_t *bw = dp.bits;   // the stream's bitstream, or the expanded runs
   const uint64_t nwords = (dp.T + 31) / 32;
   const uint64_t S = co[c], E = c + 1 < dp.nchunks ? co[c + 1] : dp.T;
@@ -537,14 +538,14 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
   const bool bytes = panel_in_lds(dp);
   if (!bad) {
     if (bytes) {
-      uint8_t *rc = dp.res8 + g0;
-      for (uint32_t i = 16 * lane; i < nsym; i += 1024) *(uint4 *)(rc + i) = make_uint4(
-          0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
+      RSZ_G uint8_t *rc = gm(dp.res8 + g0);
+      for (uint32_t i = 16 * lane; i < nsym; i += 1024)
+        *(RSZ_G u32x4 *)(rc + i) = u32x4{0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u};
     } else {
-      int32_t *rc = dp.res + g0;
+      RSZ_G int32_t *rc = gm(dp.res + g0);
       for (uint32_t i = 4 * lane; i < nsym; i += 256) {
         if (i + 4 <= nsym) {
-          *(int4 *)(rc + i) = make_int4(0, 0, 0, 0);
+          *(RSZ_G u32x4 *)(rc + i) = u32x4{0u, 0u, 0u, 0u};
         } else {
           for (uint32_t k = i; k < nsym; ++k) rc[k] = 0;
         }
@@ -565,7 +566,7 @@ __global__ __launch_bounds__(256) void k_dec_chunks(DecBatch db) {
   for (int d = 32; d > 0; d >>= 1) zeros += __shfl_xor(zeros, d);
   if (lane == 0) {
     if (bad) corrupt(dp.status);
-    dp.zcount[c] = zeros;
+    *gm(dp.zcount + c) = zeros;
   }
 }
 
@@ -624,12 +625,7 @@ __global__ __launch_bounds__(256) void k_dec_rows(DecBatch db) {
         sum += (uint32_t)v[rr][t];
         x[t] = sum;
       }
-      uint32_t incl = sum;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(incl, d);
-        if (lane >= d) incl += y;
-      }
+      const uint32_t incl = wave_inclusive_sum(sum);
       const uint32_t before = incl - sum;
       int32_t *r = dp.res + (size_t)(row0 + rr) * Wb;
 #pragma unroll
@@ -653,14 +649,9 @@ __global__ __launch_bounds__(256) void k_dec_rows(DecBatch db) {
         bad |= v == kMark;
         x = (uint32_t)v;
       }
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-      }
-      x += carry;
+      x = wave_inclusive_sum(x) + carry;
       if (j < Wb) r[j] = (int32_t)x;
-      carry = __shfl(x, 63);
+      carry = __builtin_amdgcn_readlane(x, 63);
     }
   }
   if (bad) corrupt(dp.status);
@@ -671,14 +662,15 @@ __global__ __launch_bounds__(256) void k_dec_rows(DecBatch db) {
 // rows [I*b, min(I*b + b, H)), columns [J*b, min(J*b + b, W)).  For b = 2 or 4
 // with W a multiple of b a bin's pixels of one row are an aligned float2 /
 // float4 (the frame is 16-byte aligned).
-__device__ __forceinline__ void fill_bin(float *out, uint32_t H, uint32_t W, uint32_t b,
+__device__ __forceinline__ void fill_bin(float *out_, uint32_t H, uint32_t W, uint32_t b,
                                          uint32_t I, uint32_t J, float v) {
+  RSZ_G float *out = gm(out_);
   const uint32_t i0 = I * b, i1 = min(i0 + b, H), j0 = J * b;
   if (b == 2 && W % 2 == 0) {
-    for (uint32_t i = i0; i < i1; ++i) *(float2 *)(out + (size_t)i * W + j0) = make_float2(v, v);
+    for (uint32_t i = i0; i < i1; ++i) *(RSZ_G f32x2 *)(out + (size_t)i * W + j0) = f32x2{v, v};
   } else if (b == 4 && W % 4 == 0) {
     for (uint32_t i = i0; i < i1; ++i)
-      *(float4 *)(out + (size_t)i * W + j0) = make_float4(v, v, v, v);
+      *(RSZ_G f32x4 *)(out + (size_t)i * W + j0) = f32x4{v, v, v, v};
   } else {
     const uint32_t j1 = min(j0 + b, W);
     for (uint32_t i = i0; i < i1; ++i)
@@ -782,7 +774,9 @@ __global__ __launch_bounds__(256) void k_dec_panels(DecBatch db) {
 // row at a time, so the wave's stores of a row are contiguous.
 __global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
   RSZ_DEC_FRAME(16);
-  __shared__ uint32_t s_v[kPanelBins];
+  // s_v[lead + i]: residual i of the panel, lead = the panel's byte offset
+  // in its 16-byte line (the loads below are whole aligned lines)
+  __shared__ __align__(16) uint32_t s_v[kPanelBins + 32];
   __shared__ uint32_t s_part[kPanelThreads];
   __shared__ int s_ok, s_bad;
   const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -795,34 +789,57 @@ __global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
   __syncthreads();
   if (!s_ok) return;
   const uint32_t Hb = dp.Hb, Wb = dp.Wb, n = Hb * Wb;
-  const int32_t *r = dp.res + (size_t)bid * n;
-  const uint8_t *r8 = dp.res8 + (size_t)bid * n;
-  // the panel's code bytes into LDS as residuals, eight loads per thread in
-  // flight; a byte 0 (its residual in res) is marked and filled in a second
-  // pass, so that no load waits on another
+  const RSZ_G int32_t *r = gm(dp.res + (size_t)bid * n);
+  // The panel's code bytes into LDS as residuals: aligned 16-byte loads, all
+  // of a thread's in flight at once (res8 is 256-byte aligned with 64 bytes
+  // to spare past the last bin, so the lines cover the panel and stay in
+  // the buffer).  A byte 0 (its residual in res) is marked and filled in a
+  // second pass, so that no load waits on another.
+  const uint8_t *p8 = dp.res8 + (size_t)bid * n;
+  const uint8_t *a8 = (const uint8_t *)((uintptr_t)p8 & ~(uintptr_t)15);
+  const uint32_t lead = (uint32_t)(p8 - a8), nw = (lead + n + 15) / 16;
+  uint32_t *sv = s_v + lead;
   bool bad = false, esc = false;
-  for (uint32_t i0 = 0; i0 < n; i0 += 8 * kPanelThreads) {
-    uint32_t v[8];
+  for (uint32_t w0 = 0; w0 < nw; w0 += 2 * kPanelThreads) {
+    uint4 v[2];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const uint32_t i = i0 + k * kPanelThreads + t;
-      v[k] = i < n ? r8[i] : 128u;
+    for (int k = 0; k < 2; ++k) {
+      const uint32_t w = w0 + k * kPanelThreads + t;
+      v[k] = w < nw ? ld16(a8 + 16 * (size_t)w) : make_uint4(0x80808080u, 0x80808080u,
+                                                               0x80808080u, 0x80808080u);
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const uint32_t i = i0 + k * kPanelThreads + t;
-      if (i < n) {
-        esc |= v[k] == 0;
-        s_v[i] = v[k] ? (uint32_t)((int32_t)v[k] - 128) : (uint32_t)kMark;
+    for (int k = 0; k < 2; ++k) {
+      const uint32_t w = w0 + k * kPanelThreads + t;
+      if (w < nw) {
+        // bytes of this line inside the panel: [lo, hi)
+        const int32_t lo = max((int32_t)lead - (int32_t)(16 * w), 0);
+        const int32_t hi = min((int32_t)(lead + n) - (int32_t)(16 * w), 16);
+        const uint32_t inr = hi > lo ? ((hi == 16 ? 0xFFFFu : (1u << hi) - 1u) & ~((1u << lo) - 1u))
+                                     : 0u;
+        const uint32_t e[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+        uint32_t zm = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          uint32_t o[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t by = (e[q] >> (8 * j)) & 0xFFu;
+            zm |= (by == 0 ? 1u : 0u) << (4 * q + j);
+            o[j] = by ? (uint32_t)((int32_t)by - 128) : (uint32_t)kMark;
+          }
+          *(uint4 *)(s_v + 16 * w + 4 * q) = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+        esc |= (zm & inr) != 0;
       }
     }
   }
   if (__syncthreads_or(esc)) {
     for (uint32_t i = t; i < n; i += kPanelThreads)
-      if (s_v[i] == (uint32_t)kMark) {
+      if (sv[i] == (uint32_t)kMark) {
         const int32_t x = r[i];
         bad |= x == kMark;
-        s_v[i] = (uint32_t)x;
+        sv[i] = (uint32_t)x;
       }
   }
   if (bad) s_bad = 1;
@@ -836,15 +853,10 @@ __global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
     uint32_t carry = 0;
     for (uint32_t j0 = 0; j0 < Wb; j0 += 64) {
       const uint32_t j = j0 + lane;
-      uint32_t x = j < Wb ? s_v[I * Wb + j] : 0u;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-      }
-      x += carry;
-      if (j < Wb) s_v[I * Wb + j] = x;
-      carry = __shfl(x, 63);
+      uint32_t x = j < Wb ? sv[I * Wb + j] : 0u;
+      x = wave_inclusive_sum(x) + carry;
+      if (j < Wb) sv[I * Wb + j] = x;
+      carry = __builtin_amdgcn_readlane(x, 63);
     }
   }
   __syncthreads();
@@ -855,18 +867,49 @@ __global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
   const uint32_t I0 = min(g * per, Hb), I1 = min(I0 + per, Hb);
   uint32_t part = 0;
   if (g < G)
-    for (uint32_t I = I0; I < I1; ++I) part += s_v[I * Wb + J];
+    for (uint32_t I = I0; I < I1; ++I) part += sv[I * Wb + J];
   s_part[t] = part;
   __syncthreads();
-  if (g >= G) return;
-  uint32_t acc = 0;
-  for (uint32_t h = 0; h < g; ++h) acc += s_part[h * Wb + J];
   float *out = dp.frame + (size_t)bid * dp.H * dp.W;
   const uint32_t H = dp.H, W = dp.W, b = dp.b;
   const double step = dp.step;
-  for (uint32_t I = I0; I < I1; ++I) {
-    acc += s_v[I * Wb + J];
-    fill_bin(out, H, W, b, I, J, (float)((double)(int32_t)acc * step));
+  // Linear output (b = 1, 2 or 4 with rows of whole 16-byte groups and the
+  // frame 16-byte aligned, so the panel is a run of aligned float4): the
+  // bins' values go back into LDS, then the workgroup writes the panel's
+  // pixels in order, one float4 per thread and step, so that every store
+  // of a wave fills whole cache lines (stores by bin leave a line's pieces
+  // to different waves and times).  Otherwise each thread writes its bins'
+  // pixels.
+  const bool lin = (b == 1 || b == 2 || b == 4) && W % 4 == 0 && ((uintptr_t)out & 15) == 0;
+  if (g < G) {
+    uint32_t acc = 0;
+    for (uint32_t h = 0; h < g; ++h) acc += s_part[h * Wb + J];
+    for (uint32_t I = I0; I < I1; ++I) {
+      acc += sv[I * Wb + J];
+      const float v = (float)((double)(int32_t)acc * step);
+      if (lin) sv[I * Wb + J] = __float_as_uint(v);
+      else fill_bin(out, H, W, b, I, J, v);
+    }
+  }
+  if (!lin) return;
+  __syncthreads();
+  const FastDiv fW = fast_div(W);
+  const uint32_t sh = b == 1 ? 0u : (b == 2 ? 1u : 2u), n4 = H * W / 4;
+  RSZ_G f32x4 *o4 = gm((f32x4 *)out);
+  for (uint32_t c = t; c < n4; c += kPanelThreads) {
+    const uint32_t i = fdiv(fW, 4 * c), j = 4 * c - i * W;
+    const uint32_t *rowv = sv + (i >> sh) * Wb + (j >> sh);
+    f32x4 v;
+    if (b == 4) {
+      v.x = v.y = v.z = v.w = __uint_as_float(rowv[0]);
+    } else if (b == 2) {
+      v.x = v.y = __uint_as_float(rowv[0]);
+      v.z = v.w = __uint_as_float(rowv[1]);
+    } else {
+      v = f32x4{__uint_as_float(rowv[0]), __uint_as_float(rowv[1]), __uint_as_float(rowv[2]),
+                __uint_as_float(rowv[3])};
+    }
+    o4[c] = v;
   }
 }
 

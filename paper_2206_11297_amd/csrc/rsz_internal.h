@@ -36,6 +36,41 @@ __host__ __device__ constexpr int group_strips(int b) {
 
 inline __host__ __device__ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// The plans' pointers are generic; the path's buffers are all device (global)
+// memory, and accesses through an address_space(1) pointer compile to global
+// loads and stores.  Generic (flat) ones would also count against the LDS
+// wait counter, so every LDS wait would wait for the HBM accesses in flight
+// too.
+#define RSZ_G __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ RSZ_G T *gm(T *p) {
+  return (RSZ_G T *)p;
+}
+// Plain vector types for such accesses (loads and stores of 8 and 16 bytes).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld16(const void *p) {
+  const u32x4 v = *gm((const u32x4 *)p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// Inclusive prefix sum (wrapping) of x over the 64 lanes of a wave, on DPP
+// lane moves: shifts by 1, 2, 4 and 8 lanes within each row of 16, then
+// lane 15 of a row added into the next row and lane 31 into the upper
+// half.  A lane with no source lane, or outside the rows a move writes,
+// adds 0.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false); // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false); // row_bcast:31
+  return x;
+}
+
 // Division by a run-time constant d (1 <= d < 2^16) through a multiply: with
 // l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, n / d = (hi32(n m) +
 // n) >> l for every n < 2^31 (Granlund and Montgomery, "Division by invariant
@@ -44,7 +79,7 @@ inline __host__ __device__ uint64_t align_up(uint64_t x, uint64_t a) { return (x
 struct FastDiv {
   uint32_t m, l;
 };
-inline FastDiv fast_div(uint32_t d) {
+__host__ __device__ inline FastDiv fast_div(uint32_t d) {
   uint32_t l = 0;
   while ((1ull << l) < d) ++l;
   return FastDiv{(uint32_t)((((1ull << l) - d) << 32) / d + 1), l};
