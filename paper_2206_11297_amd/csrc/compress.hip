@@ -56,7 +56,7 @@ __device__ __forceinline__ uint32_t find_frame(const uint32_t *prefix, uint32_t 
 }
 
 __device__ __forceinline__ int32_t load_status(const FrameState *st) {
-  return __hip_atomic_load(gm(&st->status), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void set_status(FrameState *st, int32_t code) {
@@ -201,8 +201,8 @@ __device__ __forceinline__ void peak_range(const FramePlan &fp, uint32_t p, int6
   k0 = k1 = 0;
   if (lo > hi) return;
   const int64_t band = (int64_t)fp.TH * fp.b;
-  k0 = *gm(fp.bstart + (size_t)p * fp.segs + (uint32_t)(lo / band));
-  k1 = *gm(fp.bstart + (size_t)p * fp.segs + (uint32_t)(hi / band) + 1);
+  k0 = fp.bstart[(size_t)p * fp.segs + (uint32_t)(lo / band)];
+  k1 = fp.bstart[(size_t)p * fp.segs + (uint32_t)(hi / band) + 1];
 }
 
 // ------------------------------------------------------------------ k_roi
@@ -226,8 +226,7 @@ __device__ __forceinline__ void roi_copy(const BatchPlan &bp, uint32_t kg) {
   // unspecified)
   if (fp.off_roi + 4ull * fp.npeaks * fp.w * fp.w > fp.out_cap) return;
   const uint32_t k = kg - bp.peak_prefix[f];
-  const RSZ_G int32_t *pk = gm((const int32_t *)fp.peaks + 3 * k);
-  const int64_t pa = pk[0], r = pk[1], c = pk[2];
+  const int64_t pa = fp.peaks[3 * k], r = fp.peaks[3 * k + 1], c = fp.peaks[3 * k + 2];
   if (pa < 0 || pa >= fp.P) return;
   const uint32_t w = fp.w, ww = w * w, M = 0xFFFFFFFFu / w + 1u;
   const int64_t h = w / 2, H = fp.H, W = fp.W;
@@ -485,7 +484,7 @@ __device__ __forceinline__ void build_mask(const FramePlan &fp, uint32_t p, uint
   for (int i = lane; i < mrows * wpr; i += 64) mask[i] = 0u;
   wave_sync();
   for (uint32_t k = pk0 + lane; k < pk1; k += 64) {
-    const uint32_t rc = *gm(fp.bucket + k);
+    const uint32_t rc = fp.bucket[k];
     const int64_t r = rc >> 16, c = rc & 0xFFFFu;
     const int64_t rlo = max(r - hw, max(R0, (int64_t)0));
     const int64_t rhi = min(r - hw + wwin, min(R0 + mrows, (int64_t)fp.H));
@@ -883,7 +882,7 @@ __device__ __forceinline__ void k_bin_body(BatchPlan bp) {
   const uint32_t f = bp.tile_frame[blockIdx.x];
   const FramePlan &fp = bp.frames[f];
   for (int i = threadIdx.x; i < kNumSym; i += blockDim.x) s_hist[i] = 0u;
-  for (int i = threadIdx.x; i < 65; i += blockDim.x) s_inv[i] = *gm(fp.st->inv + i);
+  for (int i = threadIdx.x; i < 65; i += blockDim.x) s_inv[i] = fp.st->inv[i];
   __syncthreads();
   // wave index as a wave-uniform (scalar) value: everything per tile and
   // per row below stays in scalar registers
@@ -1036,11 +1035,11 @@ __global__ __launch_bounds__(256) void k_lorenzo_dims(BatchPlan bp) {
   for (int i = threadIdx.x; i < kNumSym; i += 256) s_hist[i] = 0u;
   __syncthreads();
   const uint32_t plane = fp.Hb * fp.Wb, nbins = fp.nbins;
-  const RSZ_G u32x4 *__restrict__ c2v = gm((const u32x4 *)fp.codes2);
-  const RSZ_G uint8_t *__restrict__ c2b = gm((const uint8_t *)fp.codes2);
-  const RSZ_G int32_t *__restrict__ rb2 = gm((const int32_t *)fp.rbuf2);
-  RSZ_G u32x4 *__restrict__ cout = gm((u32x4 *)fp.codes);
-  RSZ_G int32_t *__restrict__ rout = gm(fp.rbuf);
+  const uint4 *__restrict__ c2v = (const uint4 *)fp.codes2;
+  const uint8_t *__restrict__ c2b = fp.codes2;
+  const int32_t *__restrict__ rb2 = fp.rbuf2;
+  uint4 *__restrict__ cout = (uint4 *)fp.codes;
+  int32_t *__restrict__ rout = fp.rbuf;
   // the predecessors of 16 aligned bytes start (-plane) mod 16 bytes into an
   // aligned 16-byte group: words q.. of two consecutive groups, shifted by r bytes
   const uint32_t off = (0u - plane) & 15u, qw = off >> 2, rb = off & 3u;
@@ -1052,12 +1051,12 @@ __global__ __launch_bounds__(256) void k_lorenzo_dims(BatchPlan bp) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) ow[k][i] = pw[k][i] = 0u;
     if (g0 < nbins) {
-      const u32x4 o = c2v[g0 >> 4];
+      const uint4 o = c2v[g0 >> 4];
       ow[k][0] = o.x; ow[k][1] = o.y; ow[k][2] = o.z; ow[k][3] = o.w;
       if (g0 >= plane) {
         const uint32_t a = (g0 - plane) & ~15u;   // group holding byte g0 - plane
-        const u32x4 lo = c2v[a >> 4];
-        const u32x4 hi = off ? c2v[(a >> 4) + 1] : u32x4{0u, 0u, 0u, 0u};
+        const uint4 lo = c2v[a >> 4];
+        const uint4 hi = off ? c2v[(a >> 4) + 1] : make_uint4(0u, 0u, 0u, 0u);
         const uint32_t w8[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -1107,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_lorenzo_dims(BatchPlan bp) {
       if (nb == 0) rout[g] = (int32_t)r;
       atomicAdd(&s_hist[code_from_residual((int32_t)r)], 1u);
     }
-    cout[g0 >> 4] = u32x4{outw[0], outw[1], outw[2], outw[3]};
+    cout[g0 >> 4] = make_uint4(outw[0], outw[1], outw[2], outw[3]);
   }
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) c512 += __shfl_xor(c512, d);
@@ -1635,7 +1634,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   // the status, the code lengths and (inside) the zero-map words are loaded
   // together; the status gates only what the wave writes
   const bool ok = load_status(fp.st) == RSZ_OK;
-  const uint4 lv = ld16(fp.st->lens + 16 * lane);
+  const uint4 lv = ((const uint4 *)fp.st->lens)[lane];
   uint8_t *comp = s_comp[wv];
   const ChunkCount cc = count_chunk<SPARSE>(fp, c, lv, s_len4[wv], comp);
   if (!ok) return;   // a frame that failed earlier (k_tail reports it)
@@ -1653,8 +1652,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     nout += __shfl_xor(nout, d);
   }
   if (lane == 0) {
-    *gm(fp.chunk_off + c) = bits;
-    *gm(fp.chunk_oo + c) = nout;
+    fp.chunk_off[c] = bits;
+    fp.chunk_oo[c] = nout;
   }
 }
 
@@ -1805,10 +1804,10 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
   uint32_t *bw = fp.bw;
   const uint64_t bcap = fp.bw_cap;
   for (uint32_t lc = c0 + wv; lc < c1; lc += kWaves) {
-    const uint32_t S0 = *gm(fp.chunk_off + lc);
-    uint32_t oi = *gm(fp.chunk_oo + lc);
+    const uint32_t S0 = fp.chunk_off[lc];
+    uint32_t oi = fp.chunk_oo[lc];
     if (lane == 0 && fp.off_chunks + 4ull * lc + 4 <= cap)
-      *gm((uint32_t *)(o + fp.off_chunks + 4ull * lc)) = S0;
+      *(uint32_t *)(o + fp.off_chunks + 4ull * lc) = S0;
     uint32_t pos = S0 & 31;     // bit position in stg[0]
     uint64_t widx = S0 >> 5;    // stream word of stg[0]
     bool first = (S0 & 31) != 0;
@@ -1818,7 +1817,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
     const uint32_t lc_lane = *gm(fp.lanecnt + (size_t)lc * 64 + lane);
     uint32_t nz_total;
     const uint32_t wr = wave_exclusive_scan32((uint32_t)__builtin_popcountll(mword), nz_total);
-    const uint32_t nbits = (lc + 1 < fp.nchunks ? *gm(fp.chunk_off + lc + 1) : (uint32_t)st->T) - S0;
+    const uint32_t nbits = (lc + 1 < fp.nchunks ? fp.chunk_off[lc + 1] : (uint32_t)st->T) - S0;
     const uint32_t L0 = s_len[kRadius];
     if (s_cw[kRadius] == 0 && L0 && pos + nbits <= 32u * kRoundSyms) {
       // residual 0's codeword is all zeros, so its bins only advance the
@@ -1849,7 +1848,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
       for (uint32_t k = lane; k < nw; k += 64) {
         const uint32_t v = stg[k];
         stg[k] = 0u;
-        if (k == 0 && first) *gm(fp.head + lc) = v;
+        if (k == 0 && first) fp.head[lc] = v;
         else if (widx + k < bcap) *gm(bw + widx + k) = v;
       }
       wave_sync();
@@ -1911,7 +1910,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
         for (uint32_t k = lane; k < nw; k += 64) {
           const uint32_t v = stg[k];
           if (k == 0 && first) {
-            *gm(fp.head + lc) = v;
+            fp.head[lc] = v;
             continue;
           }
           if (widx + k < bcap) *gm(bw + widx + k) = v;
@@ -1961,7 +1960,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
       for (uint32_t k = lane; k < nw; k += 64) {
         const uint32_t v = stg[k];
         if (k == 0 && first) {
-          *gm(fp.head + lc) = v;
+          fp.head[lc] = v;
           continue;
         }
         if (widx + k < bcap) *gm(bw + widx + k) = v;
@@ -1980,7 +1979,7 @@ __global__ __launch_bounds__(256) void k_encode(BatchPlan bp) {
     if (pos) {
       const uint32_t v = stg[0];
       if (lane == 0) {
-        if (first) *gm(fp.head + lc) = v;
+        if (first) fp.head[lc] = v;
         else if (widx < bcap) *gm(bw + widx) = v;
       }
     }
