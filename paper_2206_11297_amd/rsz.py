@@ -181,21 +181,29 @@ def rsz_compress_noalloc(p, d_frame, d_peaks, npeaks, d_out, out_cap, stream):
     return st, nbytes.value
 
 
+def _arr(cls, descs):
+    """A C array of descriptors: `descs` itself when it already is one (the
+    batch classes keep theirs, so a launch marshals nothing), else a copy."""
+    if isinstance(descs, C.Array):
+        return descs
+    return (cls * len(descs))(*descs)
+
+
 def rsz_batch_workspace_bytes(descs):
-    arr = (rsz_frame_desc * len(descs))(*descs)
+    arr = _arr(rsz_frame_desc, descs)
     out = C.c_uint64(0)
     st = lib().rsz_batch_workspace_bytes(len(descs), arr, C.byref(out))
     return st, out.value
 
 
 def rsz_compress_batch(descs, d_out_bytes, d_status, d_ws, ws_bytes, stream):
-    arr = (rsz_frame_desc * len(descs))(*descs)
+    arr = _arr(rsz_frame_desc, descs)
     return lib().rsz_compress_batch(len(descs), arr, d_out_bytes, d_status, d_ws, ws_bytes,
                                     stream)
 
 
 def rsz_batch_prepare(descs, d_out_bytes, d_status, d_ws, ws_bytes, stream):
-    arr = (rsz_frame_desc * len(descs))(*descs)
+    arr = _arr(rsz_frame_desc, descs)
     plan = rsz_batch_plan()
     st = lib().rsz_batch_prepare(len(descs), arr, d_out_bytes, d_status, d_ws, ws_bytes, stream,
                                  C.byref(plan))
@@ -213,14 +221,14 @@ def rsz_batch_graph_create(plan, stream):
 
 
 def rsz_verify_workspace_bytes(plan, descs):
-    arr = (rsz_frame_desc * len(descs))(*descs)
+    arr = _arr(rsz_frame_desc, descs)
     out = C.c_uint64(0)
     st = lib().rsz_verify_workspace_bytes(C.byref(plan), len(descs), arr, C.byref(out))
     return st, out.value
 
 
 def rsz_verify_prepare(plan, descs, frames_out, d_bad, d_ws, ws_bytes, stream):
-    arr = (rsz_frame_desc * len(descs))(*descs)
+    arr = _arr(rsz_frame_desc, descs)
     fo = (C.c_void_p * len(frames_out))(*frames_out)
     vplan = rsz_verify_plan()
     st = lib().rsz_verify_prepare(C.byref(plan), len(descs), arr, fo, d_bad, d_ws, ws_bytes,
@@ -267,7 +275,7 @@ def rsz_decompress(d_in, in_bytes, d_frame, frame_elems, d_ws, ws_bytes, stream)
 
 
 def _decode_descs(descs):
-    arr = (rsz_decode_desc * len(descs))(*descs)
+    arr = _arr(rsz_decode_desc, descs)
     return arr
 
 
@@ -447,6 +455,8 @@ class DecodeBatch:
         self.descs = [rsz_decode_desc(s.data_ptr(), s.numel(), C.addressof(h), f.data_ptr(),
                                       f.numel())
                       for s, h, f in zip(self.streams, self.headers, self.frames)]
+        # kept as a C array: every call passes it as is
+        self.descs = _arr(rsz_decode_desc, self.descs)
         st, wsb = rsz_decompress_batch_workspace_bytes(self.descs)
         if st:
             raise RszError(st, "rsz_decompress_batch_workspace_bytes")
@@ -540,6 +550,8 @@ class Batch:
             d.out = self.out.data_ptr() + self.offsets[i]
             d.out_cap = caps[i]
             self.descs.append(d)
+        # kept as a C array: every launch passes it as is
+        self.descs = _arr(rsz_frame_desc, self.descs)
         st, wsb = rsz_batch_workspace_bytes(self.descs)
         if st:
             raise RszError(st, "rsz_batch_workspace_bytes")
@@ -670,14 +682,14 @@ def peak_params(**kw):
 
 
 def rsz_find_peaks_workspace_bytes(descs):
-    arr = (rsz_peak_desc * len(descs))(*descs)
+    arr = _arr(rsz_peak_desc, descs)
     out = C.c_uint64(0)
     st = lib().rsz_find_peaks_workspace_bytes(len(descs), arr, C.byref(out))
     return st, out.value
 
 
 def rsz_find_peaks_batch(q, descs, d_counts, d_status, d_ws, ws_bytes, stream):
-    arr = (rsz_peak_desc * len(descs))(*descs)
+    arr = _arr(rsz_peak_desc, descs)
     return lib().rsz_find_peaks_batch(C.byref(q), len(descs), arr, d_counts, d_status, d_ws,
                                       ws_bytes, stream)
 
@@ -703,6 +715,8 @@ class PeakBatch:
             d.frame = f.data_ptr()
             d.peaks = self.out[i].data_ptr()
             self.descs.append(d)
+        # kept as a C array: every launch passes it as is
+        self.descs = _arr(rsz_peak_desc, self.descs)
         st, wsb = rsz_find_peaks_workspace_bytes(self.descs)
         if st:
             raise RszError(st, "rsz_find_peaks_workspace_bytes")
