@@ -29,6 +29,8 @@
 //   k_roi_pack, k_run_pack  the coded ROI bits and the run codes.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "rsz_internal.h"
 
 namespace rsz {
@@ -692,95 +694,117 @@ __device__ __forceinline__ void bin_tile(const FramePlan &fp, uint32_t p, uint32
       load_bin<BB, VEC, BG>(px[s], fr, H, W, b, (Irow), jc_, mask, R0, wpr, RSZ_MW(jc_));  \
     }                                                                                       \
   } while (0)
+  // The row loop is compiled for each count of strips it takes (NSR), so
+  // that every strip's loads are unconditional code: with the count a
+  // run-time bound the compiler cannot count the loads in flight and waits
+  // for all of them at the top of each row.
+  auto row_loop = [&](auto nsr_c) __attribute__((always_inline)) {
+    constexpr int NSR = decltype(nsr_c)::value;
 #pragma unroll
-  for (int s = 0; s < NS; ++s)
-    if (s < nsr) RSZ_LOAD(s, I0);
-  for (uint32_t I = I0; I < I1; ++I) {
-    // q left of the group on this row
-    int32_t left = __builtin_amdgcn_readlane(q_left, I - I0 + 1);
-    if (dim == 1 && whole_rows && I > 0) left = lastq;
-    // in-panel pixels of this bin row (vector path: every column is)
-    uint32_t rowbits = 0;
-    if constexpr (VEC) rowbits = (1u << (min((uint32_t)BB, H - I * BB) * BB)) - 1u;
-    {
+    for (int s = 0; s < NS; ++s)
+      if (s < NSR) {
+        RSZ_LOAD(s, I0);
+        // issued in strip order, as the loop issues them (the loop's waits
+        // count on strip 0's loads being the oldest on entry too)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    for (uint32_t I = I0; I < I1; ++I) {
+      // q left of the group on this row
+      int32_t left = __builtin_amdgcn_readlane(q_left, I - I0 + 1);
+      if (dim == 1 && whole_rows && I > 0) left = lastq;
+      // in-panel pixels of this bin row (vector path: every column is)
+      uint32_t rowbits = 0;
+      if constexpr (VEC) rowbits = (1u << (min((uint32_t)BB, H - I * BB) * BB)) - 1u;
+      {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        if (s >= nsr) break;
-        const uint32_t J = J0 + s * 64 + lane;
-        const bool colv = J < Wb;
-        const uint32_t jc = RSZ_JC(s);
-        int32_t qv;
-        if constexpr (VEC) {
-          qv = reduce_vec<BB, BG>(px[s], rowbits, (int)((jc * b) & 31), inv, step, range_err,
-                                  DEBUG, Sd, nd);
-        } else {
-          qv = reduce_bin<BB, BG>(px[s], H, W, b, I, J, step, inv, range_err, Sd, nd,
-                                  (int)((jc * b) & 31), mask, R0, wpr, RSZ_MW(jc));
-        }
-        if (I + 1 < I1) RSZ_LOAD(s, I + 1);
-        const int32_t q = colv ? qv : 0;
-        const int32_t ql = from_left(q, left);
-        left = __builtin_amdgcn_readlane(q, 63);
-        // residual; codes 1..1023 carry r + 512, 0 marks an outlier
-        const int32_t r = dim == 1 ? q - ql : q + ql_up[s] - q_up[s] - ql;
-        const uint32_t code = code_from_residual(r);
-        if (sparse) {
-          // the first bin of a row whose dimension-1 predecessor lies in
-          // another tile (k_lorenzo_dims corrects it) always goes to rbuf
-          const bool forced = dim == 1 && s == 0 && J == 0 && (!whole_rows || I == 0) &&
-                              (p | I) != 0;
-          const uint32_t cb = forced ? 0u : code_byte(r);
-          const bool nz = colv && cb != 128u;
-          const uint64_t m = __ballot(nz);
-          if (nz) {
-            const uint32_t rank =
-                __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            stg->zb[(zcount + rank) & (kZbRing - 1)] = (uint8_t)cb;
-            if (cb == 0) *gm((int32_t *)((char *)(rbuf + (size_t)I * Wb) + J * 4u)) = r;
+        for (int s = 0; s < NS; ++s) {
+          if (s >= NSR) break;
+          const uint32_t J = J0 + s * 64 + lane;
+          const bool colv = J < Wb;
+          const uint32_t jc = RSZ_JC(s);
+          int32_t qv;
+          if constexpr (VEC) {
+            qv = reduce_vec<BB, BG>(px[s], rowbits, (int)((jc * b) & 31), inv, step, range_err,
+                                    DEBUG, Sd, nd);
+          } else {
+            qv = reduce_bin<BB, BG>(px[s], H, W, b, I, J, step, inv, range_err, Sd, nd,
+                                    (int)((jc * b) & 31), mask, R0, wpr, RSZ_MW(jc));
           }
-          // every lane writes the same wave-uniform entry (no branch)
-          const bool here = (uint32_t)lane == (uint32_t)(s & 1) * 32u + (I - I0);
-          zmlo[s >> 1] = here ? (uint32_t)m : zmlo[s >> 1];
-          zmhi[s >> 1] = here ? (uint32_t)(m >> 32) : zmhi[s >> 1];
-          zpv[s >> 1] = here ? zcount : zpv[s >> 1];
-          zcount += (uint32_t)__builtin_popcountll(m);
-          // m holds exactly the lanes whose code is not 512 (a forced bin
-          // with r = 0 is counted through the loop, to the same total)
-          if (dim != 3) wave_histogram_nz(code, m, vmask[s], hist, c512);
-          if (DEBUG && colv) {
+          // the next row's loads are issued on every row (the last row loads
+          // itself again, from cache): a load under a condition leaves the
+          // compiler unable to count what is in flight, and it then waits
+          // for every load at the top of each row
+          RSZ_LOAD(s, min(I + 1, I1 - 1));
+          const int32_t q = colv ? qv : 0;
+          const int32_t ql = from_left(q, left);
+          left = __builtin_amdgcn_readlane(q, 63);
+          // residual; codes 1..1023 carry r + 512, 0 marks an outlier
+          const int32_t r = dim == 1 ? q - ql : q + ql_up[s] - q_up[s] - ql;
+          const uint32_t code = code_from_residual(r);
+          if (sparse) {
+            // the first bin of a row whose dimension-1 predecessor lies in
+            // another tile (k_lorenzo_dims corrects it) always goes to rbuf
+            const bool forced = dim == 1 && s == 0 && J == 0 && (!whole_rows || I == 0) &&
+                                (p | I) != 0;
+            const uint32_t cb = forced ? 0u : code_byte(r);
+            const bool nz = colv && cb != 128u;
+            const uint64_t m = __ballot(nz);
+            if (nz) {
+              const uint32_t rank =
+                  __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+              stg->zb[(zcount + rank) & (kZbRing - 1)] = (uint8_t)cb;
+              if (cb == 0) *gm((int32_t *)((char *)(rbuf + (size_t)I * Wb) + J * 4u)) = r;
+            }
+            // every lane writes the same wave-uniform entry (no branch)
+            const bool here = (uint32_t)lane == (uint32_t)(s & 1) * 32u + (I - I0);
+            zmlo[s >> 1] = here ? (uint32_t)m : zmlo[s >> 1];
+            zmhi[s >> 1] = here ? (uint32_t)(m >> 32) : zmhi[s >> 1];
+            zpv[s >> 1] = here ? zcount : zpv[s >> 1];
+            zcount += (uint32_t)__builtin_popcountll(m);
+            // m holds exactly the lanes whose code is not 512 (a forced bin
+            // with r = 0 is counted through the loop, to the same total)
+            if (dim != 3) wave_histogram_nz(code, m, vmask[s], hist, c512);
+            if (DEBUG && colv) {
+              const size_t g = (size_t)I * Wb + J;
+              if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
+              if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
+              if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
+            }
+          } else if (colv) {
             const size_t g = (size_t)I * Wb + J;
-            if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
-            if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
-            if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
+            const uint32_t cb = code_byte(r);
+            // row pointer (wave-uniform) + 32-bit lane offset
+            *gm(codes + (size_t)I * Wb + J) = (uint8_t)cb;
+            if (cb == 0) *gm((int32_t *)((char *)(rbuf + (size_t)I * Wb) + J * 4u)) = r;
+            if (DEBUG) {
+              if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
+              if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
+              if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
+            }
           }
-        } else if (colv) {
-          const size_t g = (size_t)I * Wb + J;
-          const uint32_t cb = code_byte(r);
-          // row pointer (wave-uniform) + 32-bit lane offset
-          *gm(codes + (size_t)I * Wb + J) = (uint8_t)cb;
-          if (cb == 0) *gm((int32_t *)((char *)(rbuf + (size_t)I * Wb) + J * 4u)) = r;
-          if (DEBUG) {
-            if (fp.dbg_S) fp.dbg_S[gbase + g] = Sd;
-            if (fp.dbg_n) fp.dbg_n[gbase + g] = nd;
-            if (fp.dbg_q) fp.dbg_q[gbase + g] = q;
-          }
+          if (!sparse && dim != 3) wave_histogram(code, vmask[s], hist, c512);
+          if (dim == 1 && s == ns - 1) lastq = __builtin_amdgcn_readlane(q, lastlane);
+          q_up[s] = q;
+          ql_up[s] = ql;
         }
-        if (!sparse && dim != 3) wave_histogram(code, vmask[s], hist, c512);
-        if (dim == 1 && s == ns - 1) lastq = __builtin_amdgcn_readlane(q, lastlane);
-        q_up[s] = q;
-        ql_up[s] = ql;
+      }
+      if (packed) qlast = (uint32_t)lane == I - I0 ? left : qlast;
+      // the row's last q, for k_lorenzo_dims where it cannot be used here
+      if (dim == 1 && last_group && (!whole_rows || I == Hb - 1) && lane == 0)
+        fp.qedge[(size_t)p * Hb + I] = lastq;
+      if (sparse && zcount - zflushed >= kZbFlush) {
+        wave_sync();
+        flush_zb(*stg, fp.zb + (size_t)tix * fp.tile_cap, zflushed, zflushed + kZbFlush);
+        zflushed += kZbFlush;
+        wave_sync();
       }
     }
-    if (packed) qlast = (uint32_t)lane == I - I0 ? left : qlast;
-    // the row's last q, for k_lorenzo_dims where it cannot be used here
-    if (dim == 1 && last_group && (!whole_rows || I == Hb - 1) && lane == 0)
-      fp.qedge[(size_t)p * Hb + I] = lastq;
-    if (sparse && zcount - zflushed >= kZbFlush) {
-      wave_sync();
-      flush_zb(*stg, fp.zb + (size_t)tix * fp.tile_cap, zflushed, zflushed + kZbFlush);
-      zflushed += kZbFlush;
-      wave_sync();
-    }
+  };
+  switch (nsr) {
+    case 1: row_loop(std::integral_constant<int, 1>{}); break;
+    case 2: if constexpr (NS >= 2) row_loop(std::integral_constant<int, 2>{}); break;
+    case 3: if constexpr (NS >= 3) row_loop(std::integral_constant<int, 3>{}); break;
+    default: if constexpr (NS >= 4) row_loop(std::integral_constant<int, 4>{}); break;
   }
   if constexpr (VEC) {
     if (packed) {
@@ -921,12 +945,13 @@ __global__ __launch_bounds__(256) void k_bin(BatchPlan bp) {
   k_bin_body<BB, DEBUG, DIM, false>(bp);
 }
 
-// Batches whose frames all take the vector path: without the scalar path's
-// registers the kernel keeps five waves per SIMD with room to spare, which
-// the compiler uses to keep more loads in flight (measured: six waves with
-// spills, or five without the bound, are both slower).
+// Batches whose frames all take the vector path, without the scalar path's
+// registers.  Four waves per SIMD: with the row loop's loads in strip order
+// the kernel holds its strips' loads and its sums in 128 registers without
+// spilling (five waves spill 23 registers, and measured 0.17 ms slower on
+// the 1000-frame CSPAD batch; six spill more).
 template <int BB, int DIM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_bin_vec(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_bin_vec(
     BatchPlan bp) {
   k_bin_body<BB, false, DIM, true>(bp);
 }
