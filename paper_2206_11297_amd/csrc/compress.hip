@@ -1129,7 +1129,11 @@ __global__ __launch_bounds__(256) void k_lorenzo_dims(BatchPlan bp) {
       const uint32_t nb = code_byte((int32_t)r);
       outw[e >> 2] = (outw[e >> 2] & ~(0xFFu << (8 * (e & 3)))) | (nb << (8 * (e & 3)));
       if (nb == 0) rout[g] = (int32_t)r;
-      atomicAdd(&s_hist[code_from_residual((int32_t)r)], 1u);
+      // residual 0 (most of panel 0's bytes) joins the wave's count: one
+      // LDS atomic per lane on the same word would serialise the wave
+      const uint32_t code = code_from_residual((int32_t)r);
+      if (code == (uint32_t)kRadius) ++c512;
+      else atomicAdd(&s_hist[code], 1u);
     }
     cout[g0 >> 4] = make_uint4(outw[0], outw[1], outw[2], outw[3]);
   }
