@@ -799,7 +799,7 @@ __global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
   const uint8_t *a8 = (const uint8_t *)((uintptr_t)p8 & ~(uintptr_t)15);
   const uint32_t lead = (uint32_t)(p8 - a8), nw = (lead + n + 15) / 16;
   uint32_t *sv = s_v + lead;
-  bool bad = false, esc = false;
+  bool bad = false;
   for (uint32_t w0 = 0; w0 < nw; w0 += 2 * kPanelThreads) {
     uint4 v[2];
 #pragma unroll
@@ -830,17 +830,17 @@ __global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
           }
           *(uint4 *)(s_v + 16 * w + 4 * q) = make_uint4(o[0], o[1], o[2], o[3]);
         }
-        esc |= (zm & inr) != 0;
+        // escapes (byte 0): the residual (or the outlier mark) from res,
+        // by the thread that holds the byte (rare; no other thread reads
+        // these entries before the barrier below)
+        for (uint32_t zb = zm & inr; zb; zb &= zb - 1) {
+          const uint32_t e16 = (uint32_t)__builtin_ctz(zb);
+          const int32_t x = r[16 * w + e16 - lead];
+          bad |= x == kMark;
+          s_v[16 * w + e16] = (uint32_t)x;
+        }
       }
     }
-  }
-  if (__syncthreads_or(esc)) {
-    for (uint32_t i = t; i < n; i += kPanelThreads)
-      if (sv[i] == (uint32_t)kMark) {
-        const int32_t x = r[i];
-        bad |= x == kMark;
-        sv[i] = (uint32_t)x;
-      }
   }
   if (bad) s_bad = 1;
   __syncthreads();
@@ -893,12 +893,9 @@ __global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
   }
   if (!lin) return;
   __syncthreads();
-  const FastDiv fW = fast_div(W);
-  const uint32_t sh = b == 1 ? 0u : (b == 2 ? 1u : 2u), n4 = H * W / 4;
+  const uint32_t sh = b == 1 ? 0u : (b == 2 ? 1u : 2u), W4 = W / 4;
   RSZ_G f32x4 *o4 = gm((f32x4 *)out);
-  for (uint32_t c = t; c < n4; c += kPanelThreads) {
-    const uint32_t i = fdiv(fW, 4 * c), j = 4 * c - i * W;
-    const uint32_t *rowv = sv + (i >> sh) * Wb + (j >> sh);
+  auto pix4 = [&](const uint32_t *rowv) {
     f32x4 v;
     if (b == 4) {
       v.x = v.y = v.z = v.w = __uint_as_float(rowv[0]);
@@ -909,7 +906,28 @@ __global__ __launch_bounds__(1024) void k_dec_panel(DecBatch db) {
       v = f32x4{__uint_as_float(rowv[0]), __uint_as_float(rowv[1]), __uint_as_float(rowv[2]),
                 __uint_as_float(rowv[3])};
     }
-    o4[c] = v;
+    return v;
+  };
+  // A pass covers R whole pixel rows (R a multiple of b), thread t the
+  // float4 (t mod W4) of row t / W4: from pass to pass its LDS bin row and
+  // its output move by fixed steps, with no division per store.
+  uint32_t R = kPanelThreads / W4;
+  R -= R % b;
+  if (R > 0) {
+    const uint32_t r0 = t / W4, c4 = t - r0 * W4;
+    if (r0 < R) {
+      const uint32_t dv = (R >> sh) * Wb;
+      const size_t dO = (size_t)R * W4;
+      const uint32_t *rowv = sv + (r0 >> sh) * Wb + ((4 * c4) >> sh);
+      RSZ_G f32x4 *o = o4 + (size_t)r0 * W4 + c4;
+      for (uint32_t i = r0; i < H; i += R, rowv += dv, o += dO) *o = pix4(rowv);
+    }
+  } else {
+    const FastDiv fW = fast_div(W);
+    for (uint32_t c = t; c < H * W4; c += kPanelThreads) {
+      const uint32_t i = fdiv(fW, 4 * c), j = 4 * c - i * W;
+      o4[c] = pix4(sv + (i >> sh) * Wb + (j >> sh));
+    }
   }
 }
 
