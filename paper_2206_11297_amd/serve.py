@@ -14,6 +14,7 @@ scheduler against a CPU executor.
 """
 import collections
 import dataclasses
+import gc
 import time
 from typing import Callable, List, Optional, Sequence
 
@@ -86,6 +87,18 @@ class Scheduler:
         return batch
 
     def run(self, requests: Sequence[Request], keep_streams=False) -> List[Result]:
+        # Python's cyclic garbage collector stays off while the loop runs: a
+        # full collection over the run's request and result objects takes
+        # tens of milliseconds, which would land on some frame's latency.
+        gc_was_on = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests, keep_streams)
+        finally:
+            if gc_was_on:
+                gc.enable()
+
+    def _run(self, requests: Sequence[Request], keep_streams=False) -> List[Result]:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in reqs:
             self.ex.size_request(r)

@@ -128,3 +128,39 @@ def test_summary_fields():
     res = serve.Scheduler(ex, 2, serve.SlotLimits(8, 1 << 22, 1 << 22), clock=clock).run(reqs)
     s = serve.summarize(res, reqs)
     assert s["ok"] == 20 and s["p99_ms"] >= s["p50_ms"] > 0 and s["gbps"] > 0
+
+
+def test_collector_off_during_run_and_restored():
+    """The loop holds Python's cyclic collector off while it runs and puts
+    it back as it was, also when the executor raises."""
+    import gc
+
+    class Probe(CpuExecutor):
+        def launch(self, slot, batch, now):
+            self.seen = gc.isenabled()
+            return super().launch(slot, batch, now)
+
+    class Failing(CpuExecutor):
+        def launch(self, slot, batch, now):
+            raise RuntimeError("launch failed")
+
+    def run(ex_cls):
+        clock = SimClock()   # the simulated executor counts time from 0
+        ex = ex_cls(clock)
+        serve.Scheduler(ex, 1, serve.SlotLimits(8, 1 << 24, 1 << 24), clock=clock).run(
+            _requests(2, rate=100.0, seed=5))
+        return ex
+
+    assert gc.isenabled()
+    assert run(Probe).seen is False and gc.isenabled()
+    gc.disable()
+    try:
+        run(CpuExecutor)
+        assert not gc.isenabled()   # left off, as the caller had it
+    finally:
+        gc.enable()
+    try:
+        run(Failing)
+    except RuntimeError:
+        pass
+    assert gc.isenabled()
